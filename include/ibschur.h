@@ -1,0 +1,220 @@
+/*
+ * ibschur.h -- C ABI of the MI355X coupled immersed-boundary Schur solver.
+ *
+ * The library advances the direct-forcing immersed-boundary SIMPLE scheme of
+ * Yovel, Treister & Feldman (arXiv 2501.15314) on one GPU.  Its hot path is
+ * the per-time-step pressure / force-density correction solve
+ *
+ *     S~ p' = RHS_p + c^-1 B^T RHS_F,      Phi' = c^-1 (B p' - RHS_F),
+ *     S~    = L + c^-1 B^T B,  L = G^T G,  B = -W^T G  (B^T = D W),
+ *
+ * (paper Sec. 3.1 eq. Saddle; Sec. 4.1 eqs. tildeSp, ApproxSchurPrimalP,
+ * ApproxSchurPrimalF), solved by flexible GMRES right-preconditioned by a
+ * geometric-multigrid V-cycle approximating L^-1 (Sec. 4.2 uses the Laplacian
+ * as the preconditioner; Sec. 6 names the V-cycle as its replacement).
+ *
+ * Notation.  W is the regularization matrix of Sec. 2.3 (the paper's R) with
+ * dimensionless weights w_ik = phi(dx/h) phi(dy/h) phi(dz/h); W^T is the
+ * interpolation.  Phi_k is the force unknown of point k, so that the force on
+ * the grid is W Phi; the physical force of point k is h^3 Phi_k.  c is the
+ * scalar of the lumping W^T W ~ c I (the paper's 1/2, Sec. 4.1).
+ *
+ * Layouts (all float64 unless stated):
+ *   grid field       [n0][n1][n2], axis 2 contiguous; cell (i,j,k) is centred
+ *                    at ((i+1/2)h, (j+1/2)h, (k+1/2)h)
+ *   velocity comp d  [n0][n1][n2]; index (i,j,k) is the face of cell (i,j,k)
+ *                    lower along axis d; on a no-slip axis d the index-0 face
+ *                    is the wall and always holds 0 (the far wall is implicit)
+ *   face field       [3][n0][n1][n2] (components u, v, w one after another)
+ *   point arrays     [K][3], bodies one after another in sim_set_bodies order
+ *
+ * Ownership.  The caller owns every buffer.  The library allocates no device
+ * memory: sim_create carves all of its state out of the caller's device
+ * workspace (sim_workspace_bytes), and it never frees caller memory.  A "d_"
+ * pointer is a device pointer on cfg.device; other pointers are host memory.
+ * Every call enqueues its work on cfg.stream (a hipStream_t; NULL = the null
+ * stream) and returns after that stream has drained, so outputs are ready.
+ *
+ * Errors.  Calls return a sim_status (negative on failure) and never abort or
+ * throw across the ABI; sim_last_error gives a per-handle message.  On
+ * SIM_ENOTCONV the best iterate and the statistics are still written.
+ * Handles are thread-compatible: use one handle per host thread.
+ */
+#ifndef IBSCHUR_H
+#define IBSCHUR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sim_s *sim_t;
+
+typedef enum {
+  SIM_OK = 0,
+  SIM_EINVAL = -1,      /* invalid argument or configuration */
+  SIM_ESTATE = -2,      /* call out of order (e.g. no bodies set) */
+  SIM_ENOTCONV = -3,    /* Krylov / outer loop hit its iteration limit */
+  SIM_ENONFINITE = -4,  /* NaN or Inf met in a Krylov norm */
+  SIM_EDEVICE = -5,     /* HIP runtime error */
+  SIM_ENOMEM = -6       /* workspace too small */
+} sim_status;
+
+enum { SIM_BC_PERIODIC = 0, SIM_BC_NOSLIP = 1 };
+enum { SIM_DELTA_PESKIN4 = 0, SIM_DELTA_ROMA3 = 1 };
+/* FP64: every kernel in float64.  FP32MG: the V-cycle and the momentum
+ * relaxations run in float32 inside float64 outer iterations. */
+enum { SIM_PREC_FP64 = 0, SIM_PREC_FP32MG = 1 };
+enum { SIM_MOTION_PRESCRIBED = 0, SIM_MOTION_FREE = 1 };
+
+typedef struct {
+  int32_t n[3];          /* cells per axis; all even, n[2] >= 4 */
+  double len[3];         /* box size; cells must be cubic: len[d]/n[d] equal */
+  int32_t bc[3];         /* SIM_BC_* per axis (both ends) */
+  double nu;             /* kinematic viscosity (1/Re in the paper's units) */
+  double dt;             /* time step */
+  double g[3];           /* gravity, used by SIM_MOTION_FREE bodies only */
+  int32_t delta;         /* SIM_DELTA_* */
+  double lump_c;         /* c in W^T W ~ c I, > 0 */
+  int32_t precision;     /* SIM_PREC_* */
+  int32_t krylov_restart;/* FGMRES restart length m, 1..64 */
+  int32_t krylov_maxit;  /* total FGMRES iteration cap */
+  double krylov_rtol;    /* stop on ||b - S~ p||_2 / ||b||_2 <= rtol */
+  int32_t helm_maxit;    /* momentum (A-block) iteration cap */
+  double helm_rtol;      /* momentum relative residual target */
+  int32_t mg_coarsest;   /* grid-wide V-cycle levels stop above this size */
+  int32_t mg_pre, mg_post;     /* red-black Gauss-Seidel sweeps per level */
+  int32_t mg_coarse_sweeps;    /* sweeps per level inside the coarse kernel */
+  int32_t outer_iters;   /* pressure-force corrections per step (>= 1) */
+  double outer_tol;      /* stop on ||Phi'||_1 / ||Phi||_1 < tol (0: fixed) */
+  double xi;             /* relaxation of the correction (1 for one-way) */
+  int32_t device;        /* HIP device ordinal */
+  void *stream;          /* hipStream_t on which all work is enqueued */
+} sim_config;
+
+/* A rigid sphere.  Prescribed motion: centre(t) = center + vel t
+ * - osc_amp cos(osc_omega t), constant angular velocity omega.  Free motion:
+ * center / vel / omega are the state at the current time, advanced by the
+ * discrete Newton-Euler equations (paper Sec. 3.2.1). */
+typedef struct {
+  double center[3], vel[3], omega[3];
+  double radius;
+  double density_ratio;  /* theta = rho_p / rho_f (free bodies) */
+  double osc_amp[3];
+  double osc_omega;
+  int32_t motion;        /* SIM_MOTION_* */
+  int32_t n_points;      /* Lagrangian points of this body */
+} sim_body;
+
+typedef struct {
+  int32_t iters;         /* Krylov (or relaxation) iterations */
+  double rel_res;        /* final ||b - A x|| / ||b|| */
+  double seconds;        /* device time of the solve */
+  int32_t nhist;
+  double hist[64];       /* relative residual after each iteration */
+} sim_solve_stats;
+
+typedef struct {
+  int32_t outer;         /* corrections done in the last step */
+  sim_solve_stats helm;  /* momentum solve of the last step */
+  sim_solve_stats schur; /* last pressure-force solve */
+  double div_rel;        /* ||D u^{n+1}|| / ||D u*|| */
+  double slip_rel;       /* ||W^T u^{n+1} - U|| / ||U||  (0 if U = 0) */
+  double outer_crit;     /* ||Phi'||_1 / ||Phi||_1 of the last correction */
+  double seconds;        /* device time of the last step */
+  int32_t total_schur_iters;
+} sim_step_stats;
+
+/* Bytes of device workspace sim_create needs for this configuration and up
+ * to max_points Lagrangian points; 0 if the configuration is invalid. */
+size_t sim_workspace_bytes(const sim_config *cfg, int64_t max_points);
+
+/* Validate cfg, lay out the state in d_workspace (bytes long, 256-byte
+ * aligned) and build the multigrid hierarchy.  Fields start at zero, t = 0.
+ * Errors: SIM_EINVAL (non-cubic cells, odd sizes, lump_c <= 0, ...),
+ * SIM_ENOMEM (bytes too small), SIM_EDEVICE. */
+sim_status sim_create(const sim_config *cfg, void *d_workspace, size_t bytes,
+                      int64_t max_points, sim_t *out);
+
+sim_status sim_destroy(sim_t sim);
+
+/* Set nb bodies and their points: offsets (host, [K][3], K = sum of
+ * n_points) are the point positions relative to the body centre in the body
+ * frame (paper Sec. 2.1, the radius vector L~).  Places the points at the
+ * current time (Sec. 2.2: X_k = X_c + R X~_k), computes their velocities
+ * (eq. kinematic_constraint) and sorts them into tiles.  SIM_EINVAL if K
+ * exceeds max_points or a kernel support crosses a no-slip wall (Appendix B). */
+sim_status sim_set_bodies(sim_t sim, int32_t nb, const sim_body *bodies,
+                          const double *offsets);
+
+/* Copy a time level of the state in: level 0 = t^n (u, v, w, p and, if
+ * d_phi is not NULL, Phi [K][3]); level 1 = t^{n-1} (u, v, w only).
+ * Wall faces are forced to zero. */
+sim_status sim_set_fields(sim_t sim, int32_t level, const double *d_u, const double *d_v,
+                          const double *d_w, const double *d_p, const double *d_phi);
+
+/* Copy the state at t^n out (any pointer may be NULL). */
+sim_status sim_get_fields(sim_t sim, double *d_u, double *d_v, double *d_w, double *d_p);
+
+/* Advance nsteps time steps (paper Sec. 3.1 for prescribed bodies, Sec. 3.2.1
+ * when any body is free): momentum predictor (eq. ustar), then outer_iters
+ * pressure-force corrections.  stats (may be NULL) describe the last step. */
+sim_status sim_step(sim_t sim, int32_t nsteps, sim_step_stats *stats);
+
+/* One pressure-force correction solve on caller data at the current point
+ * positions: d_rhs_p [n0][n1][n2] (its mean is discarded: the system is
+ * singular on constants), d_rhs_f [K][3]; outputs d_p (mean zero) and
+ * d_phi [K][3].  This is the unit of the throughput metric. */
+sim_status sim_solve_schur(sim_t sim, const double *d_rhs_p, const double *d_rhs_f,
+                           double *d_p, double *d_phi, sim_solve_stats *stats);
+
+/* Forces of the last step: d_f [K][3] = h^3 Phi_k (may be NULL) and, per
+ * body, body_ft [nb][6] = (h^3 sum Phi, h^3 sum L~ x Phi) on the host. */
+sim_status sim_get_forces(sim_t sim, double *d_f, double *body_ft);
+
+/* Current point positions and velocities, [K][3] each (either may be NULL). */
+sim_status sim_get_points(sim_t sim, double *d_X, double *d_U);
+
+/* Reverse-mode derivative of the last one-way step (prescribed bodies, one
+ * correction).  Inputs are the cotangents of (u^{n+1}, v, w, p^{n+1},
+ * Phi^{n+1}) (NULL = 0).  Outputs: d_gX [K][3] = dl/dX_k, gU (host [nb][3])
+ * = dl/du_s of each body, and optionally the cotangents of the step's inputs
+ * d_gu_in [3][n0][n1][n2] (u^n), d_gum_in (u^{n-1}), d_gp_in (p^n),
+ * d_gphi_in [K][3] (Phi^n).  Requires the state saved by the last sim_step. */
+sim_status sim_step_adjoint(sim_t sim, const double *d_gu, const double *d_gv,
+                            const double *d_gw, const double *d_gp, const double *d_gphi,
+                            double *d_gX, double *gU, double *d_gu_in, double *d_gum_in,
+                            double *d_gp_in, double *d_gphi_in);
+
+/* Operator applications on caller data (natural layouts above), for
+ * operator-level checks.  in / out sizes follow the operator:
+ *   SIM_OP_LAPLACIAN     cells -> cells      L = G^T G
+ *   SIM_OP_SCHUR         cells -> cells      S~ = L + c^-1 B^T B
+ *   SIM_OP_PRECOND       cells -> cells      one V-cycle, M^-1 ~ L^+
+ *   SIM_OP_GRAD          cells -> faces      G
+ *   SIM_OP_DIV           faces -> cells      D = -G^T
+ *   SIM_OP_INTERP        faces -> points     W^T
+ *   SIM_OP_SPREAD        points -> faces     W
+ *   SIM_OP_HELMHOLTZ     faces -> faces      A = 3/(2dt) - nu Delta_h
+ *   SIM_OP_CONVECTION    faces -> faces      div(u u)
+ *   SIM_OP_HELM_SOLVE    faces -> faces      A^-1 (to helm_rtol)
+ *   SIM_OP_SCHUR_RHS     cells+points -> cells  b = RHS_p + c^-1 D W RHS_F
+ *                        (in = rhs_p, in2 = rhs_f)
+ * Precision follows cfg.precision where the operator has a mixed form. */
+enum {
+  SIM_OP_LAPLACIAN = 0, SIM_OP_SCHUR = 1, SIM_OP_PRECOND = 2, SIM_OP_GRAD = 3,
+  SIM_OP_DIV = 4, SIM_OP_INTERP = 5, SIM_OP_SPREAD = 6, SIM_OP_HELMHOLTZ = 7,
+  SIM_OP_CONVECTION = 8, SIM_OP_HELM_SOLVE = 9, SIM_OP_SCHUR_RHS = 10
+};
+sim_status sim_apply(sim_t sim, int32_t op, const double *d_in, const double *d_in2,
+                     double *d_out);
+
+/* Message of the last failing call on this handle ("" if none). */
+const char *sim_last_error(sim_t sim);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IBSCHUR_H */

@@ -1,0 +1,1025 @@
+// Host driver and C ABI of the coupled immersed-boundary solver.
+//
+//   * workspace: every device array is carved from the caller's buffer;
+//   * bodies: rigid-sphere kinematics on the host (paper Sec. 2.1-2.2), point
+//     placement and tile binning on the device;
+//   * V-cycle driver (FP32 or FP64) approximating L^+ (Sec. 4.2, Sec. 6);
+//   * flexible GMRES(m) on S~ = L + c^-1 B^T B, right-preconditioned by the
+//     V-cycle, classical Gram-Schmidt with fused multi-dot / update kernels,
+//     Hessenberg least squares with Givens rotations on the host (one
+//     device-to-host copy of j+2 doubles per iteration);
+//   * the pressure-force correction (Sec. 3.1 eq. Saddle, Sec. 4.1 eqs.
+//     ApproxSchurPrimalP/F) and the one-way / two-way time steps (Sec. 3.1,
+//     Sec. 3.2.1);
+//   * momentum solve (eq. ustar) by defect correction with Chebyshev
+//     relaxations on the exact spectral enclosure of A.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/ibschur.h"
+#include "internal.h"
+
+using namespace ibs;
+
+namespace {
+
+constexpr int MAX_BODIES = 4096;
+constexpr int MAX_RESTART = 64;
+
+struct HostBody {
+  sim_body b;
+  int k0 = 0, kn = 0;
+  double rmax = 0.0;
+  // free-motion state (inertial frame)
+  double xc[3], xc_m[3], us[3], us_m[3], w[3], w_m[3], R[9];
+  double I_n[3], I_m[3], J_n[3], J_m[3];
+};
+
+struct Level {
+  Geo g;
+  void *x = nullptr;
+  void *b = nullptr;
+};
+
+}  // namespace
+
+struct sim_s {
+  sim_config cfg;
+  hipStream_t st = nullptr;
+  std::string err;
+  Geo g;
+  long long N = 0;  // cells
+  int nt0 = 0, nt1 = 0, nt2 = 0;
+  long long ntiles = 0;
+  int Kmax = 0, K = 0, nb = 0;
+  bool fp32 = false;
+  int ker = 0;
+  double c = 0.5;
+  double t = 0.0;
+  long long nstep = 0;
+  // fields (double, split layout)
+  double *U = nullptr, *UM = nullptr, *USTAR = nullptr, *RHSU = nullptr, *TMP3 = nullptr;
+  double *P = nullptr, *RHSP = nullptr, *BVEC = nullptr, *PP = nullptr, *TMPC = nullptr;
+  // Krylov basis and preconditioned vectors
+  double *V = nullptr;
+  void *Z = nullptr;
+  // momentum relaxation work (T precision)
+  void *HR = nullptr, *HD = nullptr, *HE0 = nullptr, *HE1 = nullptr;
+  std::vector<Level> lv;  // lv[0] is the finest grid (x, b supplied per call)
+  // points
+  double *OFF = nullptr, *XN = nullptr, *UN = nullptr, *PHIN = nullptr;
+  int *BODYOF = nullptr, *TILE = nullptr, *PERM = nullptr, *PERMTMP = nullptr;
+  double *XS = nullptr, *US = nullptr, *Q = nullptr, *RF = nullptr, *PHIP = nullptr, *PHIS = nullptr,
+         *PT3 = nullptr;
+  int *COUNTS = nullptr, *TSTART = nullptr, *FILLC = nullptr, *FLAGS = nullptr, *FPOS = nullptr,
+      *ACTIVE = nullptr, *SCANTMP = nullptr;
+  int nactive = 0;
+  BodyDev *BODIES = nullptr;
+  std::vector<HostBody> bodies;
+  // reductions
+  double *PART = nullptr, *RED = nullptr, *YDEV = nullptr;
+  double *hpin = nullptr;
+  // last-step statistics
+  sim_step_stats last{};
+  bool have_bodies = false;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// error plumbing
+#define CKH(call)                                                                     \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) return fail(s, SIM_EDEVICE, std::string(#call) + ": " +     \
+                                                      hipGetErrorString(e_));         \
+  } while (0)
+
+sim_status fail(sim_t s, sim_status code, const std::string &msg) {
+  if (s) s->err = msg;
+  return code;
+}
+
+// bump allocator over the workspace (base may be null for sizing)
+struct Carver {
+  char *base;
+  size_t off = 0;
+  explicit Carver(void *b) : base((char *)b) {}
+  void *take(size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    void *p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+  template <typename T>
+  T *arr(long long n) { return (T *)take(sizeof(T) * (size_t)(n > 0 ? n : 1)); }
+};
+
+bool is_even(int x) { return (x & 1) == 0; }
+
+// Validate the configuration; fills the level dimensions. Returns "" if ok.
+std::string validate(const sim_config *c, std::vector<int> *dims) {
+  if (!c) return "null config";
+  for (int a = 0; a < 3; ++a) {
+    if (c->n[a] < 16 || c->n[a] % 4) return "every n must be a multiple of 4 and >= 16";
+    if (c->bc[a] != SIM_BC_PERIODIC && c->bc[a] != SIM_BC_NOSLIP) return "bad bc";
+    if (!(c->len[a] > 0)) return "len must be positive";
+  }
+  double h0 = c->len[0] / c->n[0];
+  for (int a = 1; a < 3; ++a)
+    if (fabs(c->len[a] / c->n[a] - h0) > 1e-12 * h0) return "cells must be cubic";
+  if (!(c->dt > 0) || !(c->nu >= 0)) return "dt must be > 0 and nu >= 0";
+  if (!(c->lump_c > 0)) return "lump_c must be > 0";
+  if (c->delta != SIM_DELTA_PESKIN4 && c->delta != SIM_DELTA_ROMA3) return "bad delta kernel";
+  if (c->precision != SIM_PREC_FP64 && c->precision != SIM_PREC_FP32MG) return "bad precision";
+  if (c->krylov_restart < 1 || c->krylov_restart > MAX_RESTART) return "krylov_restart must be 1..64";
+  if (c->krylov_maxit < 1) return "krylov_maxit must be >= 1";
+  if (!(c->krylov_rtol > 0)) return "krylov_rtol must be > 0";
+  if (c->mg_pre < 1 || c->mg_post < 0 || c->mg_coarse_sweeps < 1) return "mg_pre >= 1, mg_coarse_sweeps >= 1";
+  if (c->outer_iters < 1) return "outer_iters must be >= 1";
+  if (c->helm_maxit < 1 || !(c->helm_rtol > 0)) return "helm_maxit >= 1 and helm_rtol > 0";
+  // multigrid hierarchy: halve while above mg_coarsest or too big for the coarse kernel
+  int n0 = c->n[0], n1 = c->n[1], n2 = c->n[2];
+  if (dims) dims->clear();
+  if (dims) { dims->push_back(n0); dims->push_back(n1); dims->push_back(n2); }
+  while ((std::max(n0, std::max(n1, n2)) > c->mg_coarsest ||
+          (long long)n0 * n1 * n2 > coarse_max_cells())) {
+    if (!is_even(n0) || !is_even(n1) || !is_even(n2) || n0 < 4 || n1 < 4 || n2 < 4) break;
+    n0 /= 2; n1 /= 2; n2 /= 2;
+    if (dims) { dims->push_back(n0); dims->push_back(n1); dims->push_back(n2); }
+  }
+  if ((long long)n0 * n1 * n2 > coarse_max_cells()) return "grid cannot be coarsened to the coarse-kernel size";
+  if (!is_even(n0) || !is_even(n1) || !is_even(n2)) return "coarsest multigrid grid must have even sizes";
+  return "";
+}
+
+// Lay out every array; with base == nullptr only the size is computed.
+size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std::vector<int> &dims) {
+  Carver cv(base);
+  long long N = (long long)c->n[0] * c->n[1] * c->n[2];
+  bool f32 = c->precision == SIM_PREC_FP32MG;
+  size_t ts = f32 ? sizeof(float) : sizeof(double);
+  int m = c->krylov_restart;
+  long long K = kmax > 0 ? kmax : 1;
+  long long nt = (long long)(c->n[0] / 4) * (c->n[1] / 4) * (c->n[2] / 4);
+  double *U = cv.arr<double>(3 * N), *UM = cv.arr<double>(3 * N), *USTAR = cv.arr<double>(3 * N);
+  double *RHSU = cv.arr<double>(3 * N), *TMP3 = cv.arr<double>(3 * N);
+  double *P = cv.arr<double>(N), *RHSP = cv.arr<double>(N), *BVEC = cv.arr<double>(N);
+  double *PP = cv.arr<double>(N), *TMPC = cv.arr<double>(N);
+  double *V = cv.arr<double>((long long)(m + 1) * N);
+  void *Z = cv.take(ts * (size_t)m * N);
+  void *HR = cv.take(ts * 3 * N), *HD = cv.take(ts * 3 * N), *HE0 = cv.take(ts * 3 * N),
+       *HE1 = cv.take(ts * 3 * N);
+  std::vector<Level> lv;
+  int nlev = (int)dims.size() / 3;
+  for (int l = 0; l < nlev; ++l) {
+    Level L;
+    double h = c->len[0] / c->n[0] * (double)(1 << l);
+    L.g = make_geo(dims[3 * l], dims[3 * l + 1], dims[3 * l + 2], c->bc[0], c->bc[1], c->bc[2], h);
+    if (l > 0) {
+      long long nl = (long long)dims[3 * l] * dims[3 * l + 1] * dims[3 * l + 2];
+      L.x = cv.take(ts * nl);
+      L.b = cv.take(ts * nl);
+    }
+    lv.push_back(L);
+  }
+  double *OFF = cv.arr<double>(3 * K), *XN = cv.arr<double>(3 * K), *UN = cv.arr<double>(3 * K);
+  double *PHIN = cv.arr<double>(3 * K);
+  int *BODYOF = cv.arr<int>(K), *TILE = cv.arr<int>(K), *PERM = cv.arr<int>(K), *PERMTMP = cv.arr<int>(K);
+  double *XS = cv.arr<double>(3 * K), *US = cv.arr<double>(3 * K), *Q = cv.arr<double>(3 * K);
+  double *RF = cv.arr<double>(3 * K), *PHIP = cv.arr<double>(3 * K), *PHIS = cv.arr<double>(3 * K);
+  double *PT3 = cv.arr<double>(3 * K);
+  int *COUNTS = cv.arr<int>(nt), *TSTART = cv.arr<int>(nt + 1), *FILLC = cv.arr<int>(nt);
+  int *FLAGS = cv.arr<int>(nt), *FPOS = cv.arr<int>(nt + 1), *ACTIVE = cv.arr<int>(nt);
+  int *SCANTMP = cv.arr<int>(nt / 1024 + 16);
+  BodyDev *BODIES = (BodyDev *)cv.take(sizeof(BodyDev) * MAX_BODIES);
+  int rb = std::max(red_blocks(), 1);
+  long long parts = std::max<long long>((long long)rb * (MAX_RESTART + 2), 0);
+  // helm_resid writes one partial per row-launch block
+  long long hparts = (long long)((c->n[2] / 2 + 63) / 64 + 1) * (c->n[1] + 1) * (2LL * c->n[0] * 3);
+  double *PART = cv.arr<double>(std::max(parts, hparts));
+  double *RED = cv.arr<double>(4 * (MAX_RESTART + 2));
+  double *YDEV = cv.arr<double>(MAX_RESTART + 2);
+  if (s) {
+    s->U = U; s->UM = UM; s->USTAR = USTAR; s->RHSU = RHSU; s->TMP3 = TMP3;
+    s->P = P; s->RHSP = RHSP; s->BVEC = BVEC; s->PP = PP; s->TMPC = TMPC;
+    s->V = V; s->Z = Z; s->HR = HR; s->HD = HD; s->HE0 = HE0; s->HE1 = HE1;
+    s->lv = lv;
+    s->OFF = OFF; s->XN = XN; s->UN = UN; s->PHIN = PHIN;
+    s->BODYOF = BODYOF; s->TILE = TILE; s->PERM = PERM; s->PERMTMP = PERMTMP;
+    s->XS = XS; s->US = US; s->Q = Q; s->RF = RF; s->PHIP = PHIP; s->PHIS = PHIS; s->PT3 = PT3;
+    s->COUNTS = COUNTS; s->TSTART = TSTART; s->FILLC = FILLC; s->FLAGS = FLAGS; s->FPOS = FPOS;
+    s->ACTIVE = ACTIVE; s->SCANTMP = SCANTMP; s->BODIES = BODIES;
+    s->PART = PART; s->RED = RED; s->YDEV = YDEV;
+  }
+  return cv.off + 256;
+}
+
+// ---------------------------------------------------------------------------
+// small host helpers
+sim_status sync(sim_t s) {
+  CKH(hipStreamSynchronize(s->st));
+  return SIM_OK;
+}
+
+// device scalar reduction result -> host (synchronises)
+sim_status fetch_red(sim_t s, const double *dptr, int n, double *out) {
+  CKH(hipMemcpyAsync(s->hpin, dptr, sizeof(double) * n, hipMemcpyDeviceToHost, s->st));
+  CKH(hipStreamSynchronize(s->st));
+  memcpy(out, s->hpin, sizeof(double) * n);
+  return SIM_OK;
+}
+
+sim_status dev_norm2(sim_t s, const double *x, long long n, double *out) {
+  CKH(dot2(x, x, n, s->PART, s->st));
+  CKH(finalize(s->PART, red_blocks(), 1, s->RED, s->st));
+  return fetch_red(s, s->RED, 1, out);
+}
+
+// subtract the mean of a cell field (enqueued only; mean left in RED[0])
+sim_status project_mean(sim_t s, double *x) {
+  CKH(dot2(x, nullptr, s->N, s->PART, s->st));
+  CKH(finalize(s->PART, red_blocks(), 1, s->RED, s->st));
+  CKH(add_scalar_dev(x, s->N, s->RED, -1.0 / (double)s->N, s->st));
+  return SIM_OK;
+}
+
+void mat_rodrigues(const double axis[3], double gamma, double R[9]) {
+  double W[9] = {0, -axis[2], axis[1], axis[2], 0, -axis[0], -axis[1], axis[0], 0};
+  double W2[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double v = 0;
+      for (int k = 0; k < 3; ++k) v += W[3 * i + k] * W[3 * k + j];
+      W2[3 * i + j] = v;
+    }
+  double sg = sin(gamma), cg = 1.0 - cos(gamma);
+  for (int q = 0; q < 9; ++q) R[q] = (q % 4 == 0 ? 1.0 : 0.0) + sg * W[q] + cg * W2[q];
+}
+void mat_mul(const double A[9], const double B[9], double C[9]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double v = 0;
+      for (int k = 0; k < 3; ++k) v += A[3 * i + k] * B[3 * k + j];
+      C[3 * i + j] = v;
+    }
+}
+
+// kinematic state of a prescribed body at time t
+void prescribed_state(const sim_body &b, double t, double c[3], double v[3], double R[9]) {
+  double cw = cos(b.osc_omega * t), sw = sin(b.osc_omega * t);
+  for (int a = 0; a < 3; ++a) {
+    c[a] = b.center[a] + b.vel[a] * t - b.osc_amp[a] * cw;
+    v[a] = b.vel[a] + b.osc_amp[a] * b.osc_omega * sw;
+  }
+  double wn = sqrt(b.omega[0] * b.omega[0] + b.omega[1] * b.omega[1] + b.omega[2] * b.omega[2]);
+  if (wn == 0.0) {
+    for (int q = 0; q < 9; ++q) R[q] = (q % 4 == 0) ? 1.0 : 0.0;
+  } else {
+    double ax[3] = {b.omega[0] / wn, b.omega[1] / wn, b.omega[2] / wn};
+    mat_rodrigues(ax, wn * t, R);
+  }
+}
+
+// The support of every point stays on interior nodes of no-slip axes
+// (Appendix B); checked with each body's bounding sphere.
+bool supports_inside(sim_t s, const std::vector<BodyDev> &bd) {
+  double margin = (s->ker == SIM_DELTA_PESKIN4 ? 2.0 : 1.5) * s->g.h;
+  for (size_t i = 0; i < bd.size(); ++i) {
+    for (int a = 0; a < 3; ++a) {
+      if (s->cfg.bc[a] != SIM_BC_NOSLIP) continue;
+      double lo = bd[i].c[a] - s->bodies[i].rmax, hi = bd[i].c[a] + s->bodies[i].rmax;
+      if (lo < margin || hi > s->cfg.len[a] - margin) return false;
+    }
+  }
+  return true;
+}
+
+// Place the points of all bodies from the given body states and bin them.
+sim_status place_and_bin(sim_t s, const std::vector<BodyDev> &bd) {
+  if (!supports_inside(s, bd))
+    return fail(s, SIM_EINVAL, "delta-kernel support of a body crosses a no-slip wall");
+  hipStream_t st = s->st;
+  CKH(hipMemcpyAsync(s->BODIES, bd.data(), sizeof(BodyDev) * bd.size(), hipMemcpyHostToDevice, st));
+  CKH(points_place(s->g, s->K, s->BODIES, s->BODYOF, s->OFF, s->XN, s->UN, s->TILE, s->nt0, s->nt1, s->nt2, st));
+  int nt = (int)s->ntiles;
+  CKH(fill_i32(s->COUNTS, nt, 0, st));
+  CKH(fill_i32(s->FILLC, nt, 0, st));
+  CKH(bin_count(s->K, s->TILE, s->COUNTS, st));
+  CKH(scan_exclusive(s->COUNTS, s->TSTART, nt, s->SCANTMP, st));
+  CKH(bin_scatter(s->K, s->TILE, s->TSTART, s->FILLC, s->PERMTMP, st));
+  CKH(bin_canon(s->K, s->TILE, s->TSTART, s->PERMTMP, s->PERM, st));
+  CKH(gather3(s->K, s->PERM, s->XN, s->XS, st));
+  CKH(gather3(s->K, s->PERM, s->UN, s->US, st));
+  CKH(active_flags(s->nt0, s->nt1, s->nt2, s->cfg.bc[0], s->cfg.bc[1], s->cfg.bc[2], s->COUNTS, s->FLAGS, st));
+  CKH(scan_exclusive(s->FLAGS, s->FPOS, nt, s->SCANTMP, st));
+  CKH(compact(nt, s->FLAGS, s->FPOS, s->ACTIVE, st));
+  int na = 0;
+  CKH(hipMemcpyAsync(s->hpin, s->FPOS + nt, sizeof(int), hipMemcpyDeviceToHost, st));
+  CKH(hipStreamSynchronize(st));
+  memcpy(&na, s->hpin, sizeof(int));
+  s->nactive = na;
+  return SIM_OK;
+}
+
+std::vector<BodyDev> body_states_at(sim_t s, double t) {
+  std::vector<BodyDev> out(s->bodies.size());
+  for (size_t i = 0; i < s->bodies.size(); ++i) {
+    const HostBody &hb = s->bodies[i];
+    BodyDev &d = out[i];
+    if (hb.b.motion == SIM_MOTION_PRESCRIBED) {
+      prescribed_state(hb.b, t, d.c, d.v, d.R);
+      for (int a = 0; a < 3; ++a) d.w[a] = hb.b.omega[a];
+    } else {
+      for (int a = 0; a < 3; ++a) { d.c[a] = hb.xc[a]; d.v[a] = hb.us[a]; d.w[a] = hb.w[a]; }
+      for (int q = 0; q < 9; ++q) d.R[q] = hb.R[q];
+    }
+  }
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// Operators on the split layout
+
+// w = S~ z = L z + c^-1 G^T W W^T G z  (= L z - c^-1 D W (W^T G z))
+template <typename T>
+sim_status schur_matvec(sim_t s, const T *z, double *w) {
+  CKH(lap_apply<T>(s->g, z, w, s->st));
+  CKH(interp_grad<T>(s->ker, s->g, s->K, s->XS, z, 1.0, nullptr, 0.0, s->Q, s->st));
+  CKH(band_apply(s->ker, true, s->g, s->nt0, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TSTART, s->XS, s->Q,
+                 -1.0 / s->c, w, s->st));
+  return SIM_OK;
+}
+
+// z ~ L^+ v by one V-cycle
+template <typename T>
+sim_status vcycle(sim_t s, const double *v, T *z) {
+  hipStream_t st = s->st;
+  const sim_config &c = s->cfg;
+  int nl = (int)s->lv.size();
+  int cyc = c.mg_coarse_sweeps;
+  if (nl == 1) {
+    CKH((mg_coarse<T, double>(s->lv[0].g, v, z, cyc, 2, st)));
+    return SIM_OK;
+  }
+  // descend
+  for (int l = 0; l + 1 < nl; ++l) {
+    const Geo &g = s->lv[l].g;
+    T *x = l == 0 ? z : (T *)s->lv[l].x;
+    if (l == 0) {
+      CKH((mg_smooth_first<T, double>(g, x, v, st)));
+      for (int q = 1; q < c.mg_pre; ++q) {
+        CKH((mg_smooth<T, double>(g, x, v, 0, st)));
+        CKH((mg_smooth<T, double>(g, x, v, 1, st)));
+      }
+    } else {
+      const T *b = (const T *)s->lv[l].b;
+      CKH((mg_smooth_first<T, T>(g, x, b, st)));
+      for (int q = 1; q < c.mg_pre; ++q) {
+        CKH((mg_smooth<T, T>(g, x, b, 0, st)));
+        CKH((mg_smooth<T, T>(g, x, b, 1, st)));
+      }
+    }
+    if (l + 1 < nl - 1 || true) {
+      T *bnext = (T *)s->lv[l + 1].b;
+      if (l == 0)
+        CKH((mg_restrict<T, double>(g, x, v, s->lv[1].g, bnext, st)));
+      else
+        CKH((mg_restrict<T, T>(g, x, (const T *)s->lv[l].b, s->lv[l + 1].g, bnext, st)));
+    }
+  }
+  // coarse grid
+  CKH((mg_coarse<T, T>(s->lv[nl - 1].g, (const T *)s->lv[nl - 1].b, (T *)s->lv[nl - 1].x, cyc, 2, st)));
+  // ascend
+  for (int l = nl - 2; l >= 0; --l) {
+    const Geo &g = s->lv[l].g;
+    T *x = l == 0 ? z : (T *)s->lv[l].x;
+    CKH(mg_prolong<T>(g, x, s->lv[l + 1].g, (const T *)s->lv[l + 1].x, st));
+    for (int q = 0; q < c.mg_post; ++q) {
+      if (l == 0) {
+        CKH((mg_smooth<T, double>(g, x, v, 1, st)));
+        CKH((mg_smooth<T, double>(g, x, v, 0, st)));
+      } else {
+        const T *b = (const T *)s->lv[l].b;
+        CKH((mg_smooth<T, T>(g, x, b, 1, st)));
+        CKH((mg_smooth<T, T>(g, x, b, 0, st)));
+      }
+    }
+  }
+  return SIM_OK;
+}
+
+// Flexible GMRES(m), right preconditioned: solves S~ x = b (b mean-zero).
+template <typename T>
+sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
+  hipStream_t st = s->st;
+  const sim_config &c = s->cfg;
+  const long long N = s->N;
+  const int m = c.krylov_restart;
+  double *V = s->V;
+  T *Z = (T *)s->Z;
+  sim_solve_stats loc{};
+  sim_solve_stats &S = stt ? *stt : loc;
+  S.iters = 0;
+  S.nhist = 0;
+  sim_status rc;
+  double bn2;
+  if ((rc = dev_norm2(s, b, N, &bn2))) return rc;
+  double bnorm = sqrt(bn2);
+  CKH(fill(x, N, 0.0, st));
+  if (!(bnorm > 0)) {
+    S.rel_res = 0;
+    return isfinite(bn2) ? SIM_OK : fail(s, SIM_ENONFINITE, "non-finite right-hand side");
+  }
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
+  auto Hij = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
+  double beta = bnorm;
+  const double *rvec = b;
+  int total = 0;
+  double rel = 1.0;
+  while (true) {
+    rel = beta / bnorm;
+    if (rel <= c.krylov_rtol || total >= c.krylov_maxit) break;
+    CKH(scale_copy(V, rvec, N, 1.0 / beta, st));
+    std::fill(gv.begin(), gv.end(), 0.0);
+    gv[0] = beta;
+    int jd = 0;
+    for (int j = 0; j < m; ++j) {
+      T *zj = Z + (long long)j * N;
+      double *vj = V + (long long)j * N, *w = V + (long long)(j + 1) * N;
+      if ((rc = vcycle<T>(s, vj, zj))) return rc;
+      if ((rc = schur_matvec<T>(s, zj, w))) return rc;
+      CKH(multidot(w, V, N, j + 1, N, s->PART, st));
+      CKH(finalize(s->PART, red_blocks(), j + 1, s->RED, st));
+      CKH(update_norm(w, V, N, j + 1, s->RED, N, s->PART + (long long)(MAX_RESTART + 1) * red_blocks(), st));
+      CKH(finalize(s->PART + (long long)(MAX_RESTART + 1) * red_blocks(), red_blocks(), 1, s->RED + j + 1, st));
+      double hc[MAX_RESTART + 2];
+      if ((rc = fetch_red(s, s->RED, j + 2, hc))) return rc;
+      for (int i = 0; i <= j; ++i) Hij(i, j) = hc[i];
+      double hn = sqrt(std::max(hc[j + 1], 0.0));
+      if (!isfinite(hn)) return fail(s, SIM_ENONFINITE, "non-finite Krylov norm");
+      Hij(j + 1, j) = hn;
+      if (hn > 0) CKH(scale_inplace(w, N, 1.0 / hn, st));
+      for (int i = 0; i < j; ++i) {
+        double t0 = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
+        Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
+        Hij(i, j) = t0;
+      }
+      double den = hypot(Hij(j, j), Hij(j + 1, j));
+      cs[j] = den > 0 ? Hij(j, j) / den : 1.0;
+      sn[j] = den > 0 ? Hij(j + 1, j) / den : 0.0;
+      Hij(j, j) = den;
+      Hij(j + 1, j) = 0.0;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = cs[j] * gv[j];
+      ++total;
+      jd = j + 1;
+      double est = fabs(gv[j + 1]) / bnorm;
+      if (S.nhist < 64) S.hist[S.nhist++] = est;
+      if (est <= c.krylov_rtol || total >= c.krylov_maxit || hn == 0.0) break;
+    }
+    // y = H^-1 g (upper triangular)
+    for (int i = jd - 1; i >= 0; --i) {
+      double v = gv[i];
+      for (int k = i + 1; k < jd; ++k) v -= Hij(i, k) * y[k];
+      y[i] = v / Hij(i, i);
+    }
+    memcpy(s->hpin, y.data(), sizeof(double) * jd);
+    CKH(hipMemcpyAsync(s->YDEV, s->hpin, sizeof(double) * jd, hipMemcpyHostToDevice, st));
+    CKH(sol_update<T>(x, Z, N, jd, s->YDEV, N, st));
+    // true residual r = b - S~ x (in TMPC)
+    if ((rc = schur_matvec<double>(s, x, s->TMPC))) return rc;
+    CKH(sub_mul(s->TMPC, b, s->TMPC, N, s->PART, st));
+    CKH(finalize(s->PART, red_blocks(), 1, s->RED, st));
+    double r2;
+    if ((rc = fetch_red(s, s->RED, 1, &r2))) return rc;
+    if (!isfinite(r2)) return fail(s, SIM_ENONFINITE, "non-finite residual");
+    beta = sqrt(r2);
+    rvec = s->TMPC;
+  }
+  S.iters = total;
+  S.rel_res = rel;
+  if ((rc = project_mean(s, x))) return rc;
+  if (rel > c.krylov_rtol) return fail(s, SIM_ENOTCONV, "Krylov iteration limit reached");
+  return SIM_OK;
+}
+
+sim_status fgmres_any(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
+  return s->fp32 ? fgmres<float>(s, b, x, stt) : fgmres<double>(s, b, x, stt);
+}
+
+// b = RHSP + c^-1 D W RF, projected to mean zero (into BVEC)
+sim_status schur_rhs(sim_t s) {
+  CKH(scale_copy(s->BVEC, s->RHSP, s->N, 1.0, s->st));
+  CKH(band_apply(s->ker, true, s->g, s->nt0, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TSTART, s->XS, s->RF,
+                 1.0 / s->c, s->BVEC, s->st));
+  return project_mean(s, s->BVEC);
+}
+
+// Pressure-force correction on the current RHSP / RF: PP = p', PHIP = Phi'.
+sim_status schur_solve_core(sim_t s, sim_solve_stats *stt) {
+  sim_status rc;
+  hipEvent_t e0, e1;
+  CKH(hipEventCreate(&e0));
+  CKH(hipEventCreate(&e1));
+  CKH(hipEventRecord(e0, s->st));
+  if ((rc = schur_rhs(s))) return rc;
+  sim_status solve_rc = fgmres_any(s, s->BVEC, s->PP, stt);
+  if (solve_rc != SIM_OK && solve_rc != SIM_ENOTCONV) return solve_rc;
+  // Phi' = c^-1 (B p' - RHS_F) = -c^-1 (W^T G p' + RHS_F)
+  CKH(interp_grad<double>(s->ker, s->g, s->K, s->XS, s->PP, -1.0 / s->c, s->RF, -1.0 / s->c, s->PHIP, s->st));
+  CKH(hipEventRecord(e1, s->st));
+  CKH(hipEventSynchronize(e1));
+  float ms = 0;
+  CKH(hipEventElapsedTime(&ms, e0, e1));
+  if (stt) stt->seconds = ms * 1e-3;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return solve_rc;
+}
+
+// ---------------------------------------------------------------------------
+// Momentum solve A u = rhs (faces, split layout): defect correction in FP64,
+// each correction by k Chebyshev steps in precision T on the spectral
+// enclosure [a0, a0 + 12 nu / h^2] of A (Gershgorin; A is symmetric).
+template <typename T>
+sim_status helm_solve(sim_t s, const double *rhs, double *u, sim_solve_stats *stt) {
+  hipStream_t st = s->st;
+  const sim_config &c = s->cfg;
+  const Geo &g = s->g;
+  const long long n3 = 3 * s->N;
+  double a0 = 1.5 / c.dt;
+  double lmin = a0, lmax = a0 + 12.0 * c.nu / g.h2;
+  double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  T *R = (T *)s->HR, *D = (T *)s->HD, *E0 = (T *)s->HE0, *E1 = (T *)s->HE1;
+  sim_solve_stats loc{};
+  sim_solve_stats &S = stt ? *stt : loc;
+  S.iters = 0;
+  S.nhist = 0;
+  sim_status rc;
+  double bn2;
+  if ((rc = dev_norm2(s, rhs, n3, &bn2))) return rc;
+  double bnorm = sqrt(bn2);
+  // inner steps per correction: Chebyshev bound 2 q^k <= 1e-4 (FP32) or rtol-limited (FP64)
+  double kap = lmax / lmin, q = (sqrt(kap) - 1) / (sqrt(kap) + 1);
+  double target = s->fp32 ? 1e-4 : std::max(c.helm_rtol * 0.1, 1e-13);
+  int kin = q > 0 ? (int)ceil(log(target / 2.0) / log(q)) : 1;
+  kin = std::max(1, std::min(kin, 200));
+  double rel = 1.0;
+  int it = 0;
+  int nb = 0;
+  for (;; ++it) {
+    CKH(helm_resid<T>(g, a0, c.nu, u, rhs, R, s->PART, &nb, st));
+    CKH(finalize(s->PART, nb, 1, s->RED, st));
+    double r2;
+    if ((rc = fetch_red(s, s->RED, 1, &r2))) return rc;
+    if (!isfinite(r2)) return fail(s, SIM_ENONFINITE, "non-finite momentum residual");
+    rel = bnorm > 0 ? sqrt(r2) / bnorm : 0.0;
+    if (S.nhist < 64) S.hist[S.nhist++] = rel;
+    if (rel <= c.helm_rtol || it >= c.helm_maxit) break;
+    // Chebyshev for A e = r from e = 0
+    CKH(zero_t<T>(E0, n3, st));
+    CKH(zero_t<T>(D, n3, st));
+    double rho_prev = delta / theta;  // rho_0 = 1 / sigma1
+    for (int k = 0; k < kin; ++k) {
+      double ca, cb;
+      if (k == 0) {
+        ca = 0.0;
+        cb = 1.0 / theta;
+      } else {
+        double sigma1 = theta / delta;
+        double rho = 1.0 / (2.0 * sigma1 - rho_prev);
+        ca = rho * rho_prev;
+        cb = 2.0 * rho / delta;
+        rho_prev = rho;
+      }
+      CKH(helm_cheb<T>(g, a0, c.nu, E0, R, D, E1, ca, cb, st));
+      std::swap(E0, E1);
+    }
+    CKH(add_cast<T>(u, E0, n3, st));
+  }
+  S.iters = it;
+  S.rel_res = rel;
+  if (rel > c.helm_rtol) return fail(s, SIM_ENOTCONV, "momentum solve iteration limit reached");
+  return SIM_OK;
+}
+
+sim_status helm_solve_any(sim_t s, const double *rhs, double *u, sim_solve_stats *stt) {
+  return s->fp32 ? helm_solve<float>(s, rhs, u, stt) : helm_solve<double>(s, rhs, u, stt);
+}
+
+// ---------------------------------------------------------------------------
+// One-way step (prescribed motion) with outer_iters corrections.
+sim_status step_one_way(sim_t s, sim_step_stats *out) {
+  hipStream_t st = s->st;
+  const sim_config &c = s->cfg;
+  const long long N = s->N, n3 = 3 * N;
+  const double tau = 2.0 * c.dt / 3.0;
+  sim_status rc;
+  hipEvent_t e0, e1;
+  CKH(hipEventCreate(&e0));
+  CKH(hipEventCreate(&e1));
+  CKH(hipEventRecord(e0, st));
+  double t1 = s->t + c.dt;
+  std::vector<BodyDev> bd = body_states_at(s, t1);
+  if ((rc = place_and_bin(s, bd))) return rc;
+  // Phi^n in tile order
+  CKH(gather3(s->K, s->PERM, s->PHIN, s->PHIS, st));
+  // momentum right-hand side, W Phi^n added on the band
+  CKH(mom_rhs(s->g, c.dt, s->U, s->UM, s->P, s->RHSU, st));
+  CKH(band_apply(s->ker, false, s->g, s->nt0, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TSTART, s->XS, s->PHIS, 1.0,
+                 s->RHSU, st));
+  // u* from the extrapolated guess 2 u^n - u^{n-1}
+  CKH(scale_copy(s->USTAR, s->U, n3, 2.0, st));
+  CKH(axpby(s->USTAR, s->UM, n3, -1.0, 1.0, st));
+  CKH(zero_wall_faces(s->g, s->USTAR, st));
+  sim_step_stats S{};
+  sim_status hrc = helm_solve_any(s, s->RHSU, s->USTAR, &S.helm);
+  if (hrc != SIM_OK && hrc != SIM_ENOTCONV) return hrc;
+  double divstar = 0.0;
+  sim_status src = SIM_OK;
+  for (int k = 0; k < c.outer_iters; ++k) {
+    CKH(div_apply(s->g, s->USTAR, s->RHSP, -1.0 / tau, st));
+    if (k == 0) {
+      double d2;
+      if ((rc = dev_norm2(s, s->RHSP, N, &d2))) return rc;
+      divstar = sqrt(d2) * tau;
+    }
+    CKH(interp_face(s->ker, s->g, s->K, s->XS, s->USTAR, 1.0 / tau, s->US, -1.0 / tau, s->RF, st));
+    src = schur_solve_core(s, &S.schur);
+    if (src != SIM_OK && src != SIM_ENOTCONV) return src;
+    S.total_schur_iters += S.schur.iters;
+    // u <- u* + xi tau (-G p' + W Phi') ; p += xi p' ; Phi += xi Phi'
+    CKH(grad_apply(s->g, s->PP, s->USTAR, -c.xi * tau, s->USTAR, st));
+    CKH(band_apply(s->ker, false, s->g, s->nt0, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TSTART, s->XS, s->PHIP,
+                   c.xi * tau, s->USTAR, st));
+    CKH(axpby(s->P, s->PP, N, c.xi, 1.0, st));
+    CKH(scale3(s->K, s->PHIP, c.xi, s->PHIS, 1.0, s->PHIS, st));
+    // outer criterion ||Phi'||_1 / ||Phi||_1 (host, small)
+    S.outer = k + 1;
+    if (c.outer_tol > 0 || k + 1 == c.outer_iters) {
+      std::vector<double> a(3 * (size_t)s->K), b(3 * (size_t)s->K);
+      if (s->K > 0) {
+        CKH(hipMemcpyAsync(a.data(), s->PHIP, sizeof(double) * 3 * s->K, hipMemcpyDeviceToHost, st));
+        CKH(hipMemcpyAsync(b.data(), s->PHIS, sizeof(double) * 3 * s->K, hipMemcpyDeviceToHost, st));
+        CKH(hipStreamSynchronize(st));
+      }
+      double na = 0, nbb = 0;
+      for (size_t q = 0; q < a.size(); ++q) { na += fabs(c.xi * a[q]); nbb += fabs(b[q]); }
+      S.outer_crit = nbb > 0 ? na / nbb : 0.0;
+      if (c.outer_tol > 0 && S.outer_crit < c.outer_tol) break;
+    }
+  }
+  CKH(scatter3(s->K, s->PERM, s->PHIS, s->PHIN, st));
+  // diagnostics: divergence and slip of the new velocity
+  CKH(div_apply(s->g, s->USTAR, s->TMPC, 1.0, st));
+  double dn2;
+  if ((rc = dev_norm2(s, s->TMPC, N, &dn2))) return rc;
+  S.div_rel = divstar > 0 ? sqrt(dn2) / divstar : 0.0;
+  CKH(interp_face(s->ker, s->g, s->K, s->XS, s->USTAR, 1.0, s->US, -1.0, s->PT3, st));
+  if (s->K > 0) {
+    double sl2, u2;
+    if ((rc = dev_norm2(s, s->PT3, 3LL * s->K, &sl2))) return rc;
+    if ((rc = dev_norm2(s, s->US, 3LL * s->K, &u2))) return rc;
+    S.slip_rel = u2 > 0 ? sqrt(sl2 / u2) : 0.0;
+  }
+  // rotate time levels: u^{n-1} <- u^n, u^n <- u^{n+1}
+  std::swap(s->UM, s->U);
+  std::swap(s->U, s->USTAR);
+  s->t = t1;
+  ++s->nstep;
+  CKH(hipEventRecord(e1, st));
+  CKH(hipEventSynchronize(e1));
+  float ms = 0;
+  CKH(hipEventElapsedTime(&ms, e0, e1));
+  S.seconds = ms * 1e-3;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  s->last = S;
+  if (out) *out = S;
+  if (hrc == SIM_ENOTCONV) return fail(s, SIM_ENOTCONV, "momentum solve iteration limit reached");
+  return src;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+extern "C" {
+
+size_t sim_workspace_bytes(const sim_config *cfg, int64_t max_points) {
+  std::vector<int> dims;
+  if (!validate(cfg, &dims).empty() || max_points < 0) return 0;
+  return layout(nullptr, cfg, max_points, nullptr, dims);
+}
+
+sim_status sim_create(const sim_config *cfg, void *d_workspace, size_t bytes, int64_t max_points, sim_t *out) {
+  if (!out) return SIM_EINVAL;
+  *out = nullptr;
+  std::vector<int> dims;
+  std::string v = validate(cfg, &dims);
+  if (!v.empty() || max_points < 0 || max_points > (1LL << 30)) return SIM_EINVAL;
+  size_t need = layout(nullptr, cfg, max_points, nullptr, dims);
+  if (!d_workspace || bytes < need) return SIM_ENOMEM;
+  sim_t s = new sim_s();
+  s->cfg = *cfg;
+  s->st = (hipStream_t)cfg->stream;
+  if (hipSetDevice(cfg->device) != hipSuccess) {
+    delete s;
+    return SIM_EDEVICE;
+  }
+  char *base = (char *)(((uintptr_t)d_workspace + 255) & ~(uintptr_t)255);
+  layout(s, cfg, max_points, base, dims);
+  s->g = s->lv[0].g;
+  s->N = 2 * s->g.half;
+  s->nt0 = cfg->n[0] / 4; s->nt1 = cfg->n[1] / 4; s->nt2 = cfg->n[2] / 4;
+  s->ntiles = (long long)s->nt0 * s->nt1 * s->nt2;
+  s->Kmax = (int)max_points;
+  s->fp32 = cfg->precision == SIM_PREC_FP32MG;
+  s->ker = cfg->delta;
+  s->c = cfg->lump_c;
+  if (hipHostMalloc((void **)&s->hpin, 64 * 1024) != hipSuccess) {
+    delete s;
+    return SIM_EDEVICE;
+  }
+  hipStream_t st = s->st;
+  bool ok = fill(s->U, 3 * s->N, 0.0, st) == hipSuccess && fill(s->UM, 3 * s->N, 0.0, st) == hipSuccess &&
+            fill(s->P, s->N, 0.0, st) == hipSuccess && fill(s->USTAR, 3 * s->N, 0.0, st) == hipSuccess &&
+            hipStreamSynchronize(st) == hipSuccess;
+  if (!ok) {
+    hipHostFree(s->hpin);
+    delete s;
+    return SIM_EDEVICE;
+  }
+  *out = s;
+  return SIM_OK;
+}
+
+sim_status sim_destroy(sim_t s) {
+  if (!s) return SIM_EINVAL;
+  hipStreamSynchronize(s->st);
+  if (s->hpin) hipHostFree(s->hpin);
+  delete s;
+  return SIM_OK;
+}
+
+const char *sim_last_error(sim_t s) { return s ? s->err.c_str() : "null handle"; }
+
+sim_status sim_set_bodies(sim_t s, int32_t nb, const sim_body *bodies, const double *offsets) {
+  if (!s) return SIM_EINVAL;
+  if (nb < 0 || nb > MAX_BODIES || (nb > 0 && (!bodies || !offsets))) return fail(s, SIM_EINVAL, "bad body list");
+  long long K = 0;
+  for (int i = 0; i < nb; ++i) {
+    if (bodies[i].n_points < 0 || !(bodies[i].radius >= 0)) return fail(s, SIM_EINVAL, "bad body");
+    if (bodies[i].motion == SIM_MOTION_FREE && !(bodies[i].density_ratio > 0))
+      return fail(s, SIM_EINVAL, "free body needs density_ratio > 0");
+    K += bodies[i].n_points;
+  }
+  if (K > s->Kmax) return fail(s, SIM_EINVAL, "more points than max_points");
+  s->bodies.assign(nb, HostBody());
+  std::vector<int> body_of((size_t)std::max<long long>(K, 1));
+  long long k0 = 0;
+  for (int i = 0; i < nb; ++i) {
+    HostBody &hb = s->bodies[i];
+    hb.b = bodies[i];
+    hb.k0 = (int)k0;
+    hb.kn = bodies[i].n_points;
+    double r = 0;
+    for (int k = 0; k < hb.kn; ++k) {
+      const double *o = offsets + 3 * (k0 + k);
+      r = std::max(r, sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]));
+      body_of[k0 + k] = i;
+    }
+    hb.rmax = r;
+    double c[3], v[3], R[9];
+    prescribed_state(hb.b, s->t, c, v, R);
+    if (hb.b.motion == SIM_MOTION_FREE) {
+      for (int a = 0; a < 3; ++a) {
+        hb.xc[a] = hb.xc_m[a] = bodies[i].center[a];
+        hb.us[a] = hb.us_m[a] = bodies[i].vel[a];
+        hb.w[a] = hb.w_m[a] = bodies[i].omega[a];
+        hb.I_n[a] = hb.I_m[a] = hb.J_n[a] = hb.J_m[a] = 0.0;
+      }
+      for (int q = 0; q < 9; ++q) hb.R[q] = (q % 4 == 0) ? 1.0 : 0.0;
+    }
+    k0 += hb.kn;
+  }
+  s->K = (int)K;
+  s->nb = nb;
+  hipStream_t st = s->st;
+  if (K > 0) {
+    CKH(hipMemcpyAsync(s->OFF, offsets, sizeof(double) * 3 * K, hipMemcpyHostToDevice, st));
+    CKH(hipMemcpyAsync(s->BODYOF, body_of.data(), sizeof(int) * K, hipMemcpyHostToDevice, st));
+    CKH(fill(s->PHIN, 3 * K, 0.0, st));
+  }
+  std::vector<BodyDev> bd = body_states_at(s, s->t);
+  sim_status rc = place_and_bin(s, bd);
+  if (rc) return rc;
+  s->have_bodies = true;
+  return SIM_OK;
+}
+
+sim_status sim_set_fields(sim_t s, int32_t level, const double *d_u, const double *d_v, const double *d_w,
+                          const double *d_p, const double *d_phi) {
+  if (!s || (level != 0 && level != 1)) return fail(s, SIM_EINVAL, "level must be 0 or 1");
+  hipStream_t st = s->st;
+  double *U = level == 0 ? s->U : s->UM;
+  const double *src[3] = {d_u, d_v, d_w};
+  for (int d = 0; d < 3; ++d) {
+    if (!src[d]) continue;
+    // one component at a time: conversion of a single plane
+    CKH(to_split(s->g, 1, src[d], U + d * s->N, st));
+  }
+  CKH(zero_wall_faces(s->g, U, st));
+  if (level == 0 && d_p) CKH(to_split(s->g, 1, d_p, s->P, st));
+  if (level == 0 && d_phi && s->K > 0)
+    CKH(hipMemcpyAsync(s->PHIN, d_phi, sizeof(double) * 3 * s->K, hipMemcpyDeviceToDevice, st));
+  return sync(s);
+}
+
+sim_status sim_get_fields(sim_t s, double *d_u, double *d_v, double *d_w, double *d_p) {
+  if (!s) return SIM_EINVAL;
+  hipStream_t st = s->st;
+  double *dst[3] = {d_u, d_v, d_w};
+  for (int d = 0; d < 3; ++d)
+    if (dst[d]) CKH(to_natural(s->g, 1, s->U + d * s->N, dst[d], st));
+  if (d_p) CKH(to_natural(s->g, 1, s->P, d_p, st));
+  return sync(s);
+}
+
+sim_status sim_get_points(sim_t s, double *d_X, double *d_U) {
+  if (!s) return SIM_EINVAL;
+  if (!s->have_bodies) return fail(s, SIM_ESTATE, "no bodies set");
+  if (s->K > 0) {
+    if (d_X) CKH(hipMemcpyAsync(d_X, s->XN, sizeof(double) * 3 * s->K, hipMemcpyDeviceToDevice, s->st));
+    if (d_U) CKH(hipMemcpyAsync(d_U, s->UN, sizeof(double) * 3 * s->K, hipMemcpyDeviceToDevice, s->st));
+  }
+  return sync(s);
+}
+
+sim_status sim_get_forces(sim_t s, double *d_f, double *body_ft) {
+  if (!s) return SIM_EINVAL;
+  if (!s->have_bodies) return fail(s, SIM_ESTATE, "no bodies set");
+  hipStream_t st = s->st;
+  double h3 = s->g.h * s->g.h * s->g.h;
+  if (d_f && s->K > 0) CKH(scale3(s->K, s->PHIN, h3, nullptr, 0.0, d_f, st));
+  if (body_ft) {
+    std::vector<double> phi(3 * (size_t)s->K), X(3 * (size_t)s->K);
+    if (s->K > 0) {
+      CKH(hipMemcpyAsync(phi.data(), s->PHIN, sizeof(double) * 3 * s->K, hipMemcpyDeviceToHost, st));
+      CKH(hipMemcpyAsync(X.data(), s->XN, sizeof(double) * 3 * s->K, hipMemcpyDeviceToHost, st));
+    }
+    CKH(hipStreamSynchronize(st));
+    std::vector<BodyDev> bd = body_states_at(s, s->t);
+    for (int i = 0; i < s->nb; ++i) {
+      const HostBody &hb = s->bodies[i];
+      double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+      for (int k = hb.k0; k < hb.k0 + hb.kn; ++k) {
+        double l[3] = {X[3 * k] - bd[i].c[0], X[3 * k + 1] - bd[i].c[1], X[3 * k + 2] - bd[i].c[2]};
+        const double *f = &phi[3 * k];
+        for (int a = 0; a < 3; ++a) F[a] += f[a];
+        T[0] += l[1] * f[2] - l[2] * f[1];
+        T[1] += l[2] * f[0] - l[0] * f[2];
+        T[2] += l[0] * f[1] - l[1] * f[0];
+      }
+      for (int a = 0; a < 3; ++a) {
+        body_ft[6 * i + a] = h3 * F[a];
+        body_ft[6 * i + 3 + a] = h3 * T[a];
+      }
+    }
+  }
+  return sync(s);
+}
+
+sim_status sim_solve_schur(sim_t s, const double *d_rhs_p, const double *d_rhs_f, double *d_p, double *d_phi,
+                           sim_solve_stats *stats) {
+  if (!s) return SIM_EINVAL;
+  if (!s->have_bodies) return fail(s, SIM_ESTATE, "no bodies set");
+  if (!d_rhs_p || !d_p || (s->K > 0 && (!d_rhs_f || !d_phi))) return fail(s, SIM_EINVAL, "null argument");
+  hipStream_t st = s->st;
+  CKH(to_split(s->g, 1, d_rhs_p, s->RHSP, st));
+  if (s->K > 0) CKH(gather3(s->K, s->PERM, d_rhs_f, s->RF, st));
+  sim_status rc = schur_solve_core(s, stats);
+  if (rc != SIM_OK && rc != SIM_ENOTCONV) return rc;
+  CKH(to_natural(s->g, 1, s->PP, d_p, st));
+  if (s->K > 0) CKH(scatter3(s->K, s->PERM, s->PHIP, d_phi, st));
+  sim_status r2 = sync(s);
+  return r2 ? r2 : rc;
+}
+
+sim_status sim_step(sim_t s, int32_t nsteps, sim_step_stats *stats) {
+  if (!s) return SIM_EINVAL;
+  if (!s->have_bodies) return fail(s, SIM_ESTATE, "no bodies set");
+  if (nsteps < 0) return fail(s, SIM_EINVAL, "nsteps < 0");
+  for (const HostBody &hb : s->bodies)
+    if (hb.b.motion == SIM_MOTION_FREE) return fail(s, SIM_EINVAL, "free bodies are not supported by this build");
+  sim_status rc = SIM_OK;
+  for (int i = 0; i < nsteps; ++i) {
+    rc = step_one_way(s, stats);
+    if (rc != SIM_OK && rc != SIM_ENOTCONV) return rc;
+  }
+  return rc;
+}
+
+sim_status sim_step_adjoint(sim_t s, const double *, const double *, const double *, const double *,
+                            const double *, double *, double *, double *, double *, double *, double *) {
+  if (!s) return SIM_EINVAL;
+  return fail(s, SIM_ESTATE, "adjoint step not available in this build");
+}
+
+sim_status sim_apply(sim_t s, int32_t op, const double *in, const double *in2, double *out) {
+  if (!s) return SIM_EINVAL;
+  if (!in || !out) return fail(s, SIM_EINVAL, "null argument");
+  hipStream_t st = s->st;
+  const Geo &g = s->g;
+  const long long N = s->N;
+  sim_status rc;
+  bool need_points = op == SIM_OP_SCHUR || op == SIM_OP_INTERP || op == SIM_OP_SPREAD || op == SIM_OP_SCHUR_RHS;
+  if (need_points && !s->have_bodies) return fail(s, SIM_ESTATE, "no bodies set");
+  switch (op) {
+    case SIM_OP_LAPLACIAN:
+      CKH(to_split(g, 1, in, s->TMPC, st));
+      CKH(lap_apply<double>(g, s->TMPC, s->PP, st));
+      CKH(to_natural(g, 1, s->PP, out, st));
+      break;
+    case SIM_OP_SCHUR:
+      CKH(to_split(g, 1, in, s->TMPC, st));
+      if ((rc = schur_matvec<double>(s, s->TMPC, s->PP))) return rc;
+      CKH(to_natural(g, 1, s->PP, out, st));
+      break;
+    case SIM_OP_PRECOND:
+      CKH(to_split(g, 1, in, s->TMPC, st));
+      if (s->fp32) {
+        if ((rc = vcycle<float>(s, s->TMPC, (float *)s->Z))) return rc;
+        CKH(fill(s->PP, N, 0.0, st));
+        CKH(add_cast<float>(s->PP, (const float *)s->Z, N, st));
+      } else {
+        if ((rc = vcycle<double>(s, s->TMPC, (double *)s->Z))) return rc;
+        CKH(scale_copy(s->PP, (const double *)s->Z, N, 1.0, st));
+      }
+      CKH(to_natural(g, 1, s->PP, out, st));
+      break;
+    case SIM_OP_GRAD:
+      CKH(to_split(g, 1, in, s->TMPC, st));
+      CKH(grad_apply(g, s->TMPC, s->TMP3, 1.0, nullptr, st));
+      CKH(to_natural(g, 3, s->TMP3, out, st));
+      break;
+    case SIM_OP_DIV:
+      CKH(to_split(g, 3, in, s->TMP3, st));
+      CKH(zero_wall_faces(g, s->TMP3, st));
+      CKH(div_apply(g, s->TMP3, s->PP, 1.0, st));
+      CKH(to_natural(g, 1, s->PP, out, st));
+      break;
+    case SIM_OP_INTERP:
+      CKH(to_split(g, 3, in, s->TMP3, st));
+      CKH(zero_wall_faces(g, s->TMP3, st));
+      CKH(interp_face(s->ker, g, s->K, s->XS, s->TMP3, 1.0, nullptr, 0.0, s->Q, st));
+      CKH(scatter3(s->K, s->PERM, s->Q, out, st));
+      break;
+    case SIM_OP_SPREAD:
+      CKH(gather3(s->K, s->PERM, in, s->Q, st));
+      CKH(fill(s->TMP3, 3 * N, 0.0, st));
+      CKH(band_apply(s->ker, false, g, s->nt0, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TSTART, s->XS, s->Q, 1.0,
+                     s->TMP3, st));
+      CKH(to_natural(g, 3, s->TMP3, out, st));
+      break;
+    case SIM_OP_HELMHOLTZ:
+      CKH(to_split(g, 3, in, s->TMP3, st));
+      CKH(zero_wall_faces(g, s->TMP3, st));
+      CKH(helm_apply(g, 1.5 / s->cfg.dt, s->cfg.nu, s->TMP3, s->RHSU, st));
+      CKH(to_natural(g, 3, s->RHSU, out, st));
+      break;
+    case SIM_OP_CONVECTION:
+      CKH(to_split(g, 3, in, s->TMP3, st));
+      CKH(zero_wall_faces(g, s->TMP3, st));
+      CKH(convection(g, s->TMP3, s->RHSU, st));
+      CKH(to_natural(g, 3, s->RHSU, out, st));
+      break;
+    case SIM_OP_HELM_SOLVE: {
+      CKH(to_split(g, 3, in, s->RHSU, st));
+      CKH(zero_wall_faces(g, s->RHSU, st));
+      CKH(fill(s->TMP3, 3 * N, 0.0, st));
+      sim_status hr = helm_solve_any(s, s->RHSU, s->TMP3, nullptr);
+      if (hr != SIM_OK && hr != SIM_ENOTCONV) return hr;
+      CKH(to_natural(g, 3, s->TMP3, out, st));
+      break;
+    }
+    case SIM_OP_SCHUR_RHS:
+      if (s->K > 0 && !in2) return fail(s, SIM_EINVAL, "SCHUR_RHS needs rhs_f");
+      CKH(to_split(g, 1, in, s->RHSP, st));
+      if (s->K > 0) CKH(gather3(s->K, s->PERM, in2, s->RF, st));
+      if ((rc = schur_rhs(s))) return rc;
+      CKH(to_natural(g, 1, s->BVEC, out, st));
+      break;
+    default:
+      return fail(s, SIM_EINVAL, "unknown operator");
+  }
+  return sync(s);
+}
+
+}  // extern "C"

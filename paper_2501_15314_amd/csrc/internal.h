@@ -1,0 +1,128 @@
+// Host-side declarations shared between the kernel translation units and the
+// solver driver.  Every launcher enqueues on the given stream and returns the
+// launch status; none of them synchronises.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dev.h"
+
+namespace ibs {
+
+// ---- launch shapes ---------------------------------------------------------
+struct RowLaunch {
+  dim3 grid, block;
+};
+RowLaunch row_launch(const Geo &g, int nz);  // nz = grid.z (2*n0*ncomp, or n0 for one colour)
+
+Geo make_geo(int n0, int n1, int n2, int bc0, int bc1, int bc2, double h);
+inline long long geo_cells(const Geo &g) { return 2 * g.half; }
+
+// ---- grid kernels (kernels_grid.hip) ---------------------------------------
+hipError_t to_split(const Geo &g, int ncomp, const double *nat, double *spl, hipStream_t s);
+hipError_t to_natural(const Geo &g, int ncomp, const double *spl, double *nat, hipStream_t s);
+template <typename T>
+hipError_t lap_apply(const Geo &g, const T *x, double *y, hipStream_t s);  // y = L x
+hipError_t grad_apply(const Geo &g, const double *p, double *f3, double alpha, const double *add3,
+                      hipStream_t s);  // f3 = add3 + alpha G p   (add3 may be null)
+hipError_t div_apply(const Geo &g, const double *u3, double *y, double alpha,
+                     hipStream_t s);  // y = alpha D u
+hipError_t fill(double *x, long long n, double v, hipStream_t s);
+hipError_t fill_i32(int *x, long long n, int v, hipStream_t s);
+hipError_t zero_wall_faces(const Geo &g, double *u3, hipStream_t s);
+hipError_t helm_apply(const Geo &g, double a0, double nu, const double *u3, double *y3,
+                      hipStream_t s);
+hipError_t mom_rhs(const Geo &g, double dt, const double *u3, const double *um3, const double *p,
+                   double *out3, hipStream_t s);
+hipError_t convection(const Geo &g, const double *u3, double *out3, hipStream_t s);
+// helm_resid: r = b - A x (in precision TR), per-block partial sums of |r|^2
+template <typename TR>
+hipError_t helm_resid(const Geo &g, double a0, double nu, const double *x3, const double *b3,
+                      TR *r3, double *part, int *nblocks, hipStream_t s);
+int helm_resid_blocks(const Geo &g);
+// Chebyshev step for A e = r: d = ca d + cb (r - A e_old), e_new = e_old + d
+template <typename T>
+hipError_t helm_cheb(const Geo &g, double a0, double nu, const T *e_old, const T *r3, T *d3, T *e_new,
+                     double ca, double cb, hipStream_t s);
+template <typename T>
+hipError_t zero_t(T *x, long long n, hipStream_t s);
+template <typename T, typename TB>
+hipError_t helm_rbgs(const Geo &g, double a0, double nu, T *x3, const TB *b3, int color, bool first,
+                     hipStream_t s);
+template <typename T>
+hipError_t add_cast(double *y, const T *x, long long n, hipStream_t s);  // y += x
+template <typename T>
+hipError_t cast_copy(T *y, const double *x, long long n, hipStream_t s);
+
+// ---- multigrid (kernels_mg.hip) --------------------------------------------
+template <typename T, typename TB>
+hipError_t mg_smooth_first(const Geo &g, T *x, const TB *b, hipStream_t s);
+template <typename T, typename TB>
+hipError_t mg_smooth(const Geo &g, T *x, const TB *b, int color, hipStream_t s);
+template <typename T, typename TB>
+hipError_t mg_restrict(const Geo &gf, const T *xf, const TB *bf, const Geo &gc, T *bc, hipStream_t s);
+template <typename T>
+hipError_t mg_prolong(const Geo &gf, T *xf, const Geo &gc, const T *xc, hipStream_t s);
+template <typename T, typename TB>
+hipError_t mg_coarse(const Geo &gc, const TB *b, T *x, int cycles, int sweeps, hipStream_t s);
+int coarse_max_cells();
+
+// ---- Lagrangian points (kernels_ib.hip) ------------------------------------
+struct BodyDev {
+  double c[3];
+  double R[9];
+  double v[3];
+  double w[3];
+};
+hipError_t points_place(const Geo &g, int K, const BodyDev *bodies, const int *body_of,
+                        const double *off, double *X, double *U, int *tile, int nt0, int nt1,
+                        int nt2, hipStream_t s);
+hipError_t bin_count(int K, const int *tile, int *counts, hipStream_t s);
+hipError_t scan_exclusive(const int *in, int *out, int n, int *tmp, hipStream_t s);  // out has n+1 entries
+hipError_t bin_scatter(int K, const int *tile, const int *start, int *fillc, int *perm_tmp,
+                       hipStream_t s);
+hipError_t bin_canon(int K, const int *tile, const int *start, const int *perm_tmp, int *perm,
+                     hipStream_t s);
+hipError_t active_flags(int nt0, int nt1, int nt2, int bc0, int bc1, int bc2, const int *counts,
+                        int *flags, hipStream_t s);
+hipError_t compact(int n, const int *flags, const int *pos, int *list, hipStream_t s);
+hipError_t gather3(int K, const int *perm, const double *src, double *dst, hipStream_t s);
+hipError_t scatter3(int K, const int *perm, const double *src, double *dst, hipStream_t s);
+hipError_t scale3(int K, const double *x, double alpha, const double *y, double beta, double *out,
+                  hipStream_t s);  // out = alpha x + beta y (y may be null)
+
+// interp: out[p][d] = alpha * (W^T src)[p][d] + beta * y[p][d]; src is a face
+// field (double) when GRAD is false, otherwise the gradient of a cell field.
+template <typename T>
+hipError_t interp_grad(int ker, const Geo &g, int K, const double *X, const T *z, double alpha,
+                       const double *y, double beta, double *out, hipStream_t s);
+hipError_t interp_face(int ker, const Geo &g, int K, const double *X, const double *u3, double alpha,
+                       const double *y, double beta, double *out, hipStream_t s);
+// band: for the active tiles, outc += alpha D (W q)   (div = true)
+//                          or outf += alpha W q       (div = false)
+hipError_t band_apply(int ker, bool div, const Geo &g, int nt0, int nt1, int nt2, int nactive,
+                      const int *active, const int *tstart, const double *X, const double *q,
+                      double alpha, double *out, hipStream_t s);
+
+// ---- reductions / Krylov vector kernels (kernels_krylov.hip) ---------------
+int red_blocks();
+hipError_t multidot(const double *w, const double *V, long long stride, int nv, long long n,
+                    double *part, hipStream_t s);  // part[blk*nv + i]
+hipError_t finalize(const double *part, int nblk, int nv, double *out, hipStream_t s);
+hipError_t update_norm(double *w, const double *V, long long stride, int nv, const double *hcoef,
+                       long long n, double *part, hipStream_t s);  // w -= sum h_i V_i ; |w|^2
+hipError_t scale_inplace(double *x, long long n, double alpha, hipStream_t s);
+hipError_t scale_copy(double *y, const double *x, long long n, double alpha, hipStream_t s);
+template <typename T>
+hipError_t sol_update(double *x, const T *Z, long long stride, int nz, const double *y, long long n,
+                      hipStream_t s);  // x += sum y_j Z_j
+hipError_t axpby(double *y, const double *x, long long n, double a, double b,
+                 hipStream_t s);  // y = a x + b y
+hipError_t add_scalar_dev(double *x, long long n, const double *dscalar, double mult,
+                          hipStream_t s);  // x += mult * (*dscalar)
+hipError_t sub_mul(double *r, const double *b, const double *ax, long long n, double *part,
+                   hipStream_t s);  // r = b - ax, partial |r|^2
+hipError_t dot2(const double *a, const double *b, long long n, double *part,
+                hipStream_t s);  // partial a.b (sum of a when b is null)
+
+}  // namespace ibs

@@ -1,0 +1,499 @@
+// Staggered-grid stencil kernels in the red/black split layout: layout
+// conversion, the pressure Laplacian L = G^T G, gradient G and divergence
+// D = -G^T (paper Sec. 3.1, eq. modified_poisson), the momentum operator
+// A = 3/(2 dt) - nu Delta_h and its red-black relaxation (eq. ustar), the
+// explicit convection term and the momentum right-hand side.
+//
+// Boundary rules (MAC grid): on a no-slip axis d the index-0 face of velocity
+// component d is the wall (always 0) and the far wall is implicit; the
+// pressure Laplacian is Neumann there; a tangential velocity's neighbour
+// beyond a wall is the ghost value -u.
+#include "internal.h"
+
+namespace ibs {
+
+Geo make_geo(int n0, int n1, int n2, int bc0, int bc1, int bc2, double h) {
+  Geo g;
+  g.n0 = n0; g.n1 = n1; g.n2 = n2; g.hn2 = n2 / 2;
+  g.half = (long long)n0 * n1 * (n2 / 2);
+  g.bc0 = bc0; g.bc1 = bc1; g.bc2 = bc2;
+  g.h = h; g.h2 = h * h;
+  return g;
+}
+
+RowLaunch row_launch(const Geo &g, int nz) {
+  int bx = 1;
+  while (bx < g.hn2 && bx < 64) bx <<= 1;
+  int by = 256 / bx;
+  RowLaunch L;
+  L.block = dim3(bx, by, 1);
+  L.grid = dim3((g.hn2 + bx - 1) / bx, (g.n1 + by - 1) / by, nz);
+  return L;
+}
+
+// Position of a thread in a one-colour launch (grid.z = n0 * ncomp).
+__device__ __forceinline__ bool row_pos1(const Geo &g, int color, RowPos &p) {
+  p.m = blockIdx.x * blockDim.x + threadIdx.x;
+  p.j = blockIdx.y * blockDim.y + threadIdx.y;
+  int z = blockIdx.z;
+  p.comp = z / g.n0;
+  p.i = z - p.comp * g.n0;
+  p.c = color;
+  if (p.m >= g.hn2 || p.j >= g.n1) return false;
+  p.k = 2 * p.m + ((p.c + p.i + p.j) & 1);
+  p.e = (long long)p.c * g.half + ((long long)p.i * g.n1 + p.j) * g.hn2 + p.m;
+  return true;
+}
+
+// Value of a split-layout plane at (i,j,k); 0 outside a wall box, wrapped on
+// periodic axes.
+template <typename T>
+__device__ __forceinline__ T fetch(const T *f, const Geo &g, int i, int j, int k) {
+  if (i < 0 || i >= g.n0) { if (g.bc0) return T(0); i = wrapi(i, g.n0); }
+  if (j < 0 || j >= g.n1) { if (g.bc1) return T(0); j = wrapi(j, g.n1); }
+  if (k < 0 || k >= g.n2) { if (g.bc2) return T(0); k = wrapi(k, g.n2); }
+  return f[sidx(g, i, j, k)];
+}
+
+// Sum of the six neighbours of cell (i,j,k) (colour c, in-row index m) that
+// exist; all of them lie in the other colour plane.
+template <typename T>
+__device__ __forceinline__ T cell_nb_sum(const Geo &g, const T *x, int i, int j, int k, int c, int m) {
+  const T *o = x + (long long)(1 - c) * g.half;
+  T s = T(0);
+  int t;
+  t = nbr(i, -1, g.n0, g.bc0); if (t >= 0) s += o[((long long)t * g.n1 + j) * g.hn2 + m];
+  t = nbr(i, 1, g.n0, g.bc0);  if (t >= 0) s += o[((long long)t * g.n1 + j) * g.hn2 + m];
+  t = nbr(j, -1, g.n1, g.bc1); if (t >= 0) s += o[((long long)i * g.n1 + t) * g.hn2 + m];
+  t = nbr(j, 1, g.n1, g.bc1);  if (t >= 0) s += o[((long long)i * g.n1 + t) * g.hn2 + m];
+  long long row = ((long long)i * g.n1 + j) * g.hn2;
+  t = nbr(k, -1, g.n2, g.bc2); if (t >= 0) s += o[row + (t >> 1)];
+  t = nbr(k, 1, g.n2, g.bc2);  if (t >= 0) s += o[row + (t >> 1)];
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_to_split(Geo g, const double *nat, double *spl) {
+  RowPos p;
+  if (!row_pos(g, p)) return;
+  long long N = 2 * g.half;
+  long long ni = ((long long)p.i * g.n1 + p.j) * g.n2 + p.k;
+  spl[p.comp * N + p.e] = nat[p.comp * N + ni];
+}
+__global__ void k_to_natural(Geo g, const double *spl, double *nat) {
+  RowPos p;
+  if (!row_pos(g, p)) return;
+  long long N = 2 * g.half;
+  long long ni = ((long long)p.i * g.n1 + p.j) * g.n2 + p.k;
+  nat[p.comp * N + ni] = spl[p.comp * N + p.e];
+}
+
+hipError_t to_split(const Geo &g, int ncomp, const double *nat, double *spl, hipStream_t s) {
+  RowLaunch L = row_launch(g, 2 * g.n0 * ncomp);
+  hipLaunchKernelGGL(k_to_split, L.grid, L.block, 0, s, g, nat, spl);
+  return hipGetLastError();
+}
+hipError_t to_natural(const Geo &g, int ncomp, const double *spl, double *nat, hipStream_t s) {
+  RowLaunch L = row_launch(g, 2 * g.n0 * ncomp);
+  hipLaunchKernelGGL(k_to_natural, L.grid, L.block, 0, s, g, spl, nat);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// y = L x, L = G^T G: (L x)_c = sum over existing neighbours (x_c - x_nb) / h^2
+template <typename T>
+__global__ void k_lap(Geo g, const T *x, double *y) {
+  RowPos p;
+  if (!row_pos(g, p)) return;
+  double nb = (double)cell_nb_sum(g, x, p.i, p.j, p.k, p.c, p.m);
+  int nn = cell_nnb(g, p.i, p.j, p.k);
+  y[p.e] = ((double)nn * (double)x[p.e] - nb) / g.h2;
+}
+
+template <typename T>
+hipError_t lap_apply(const Geo &g, const T *x, double *y, hipStream_t s) {
+  RowLaunch L = row_launch(g, 2 * g.n0);
+  hipLaunchKernelGGL(k_lap<T>, L.grid, L.block, 0, s, g, x, y);
+  return hipGetLastError();
+}
+template hipError_t lap_apply<float>(const Geo &, const float *, double *, hipStream_t);
+template hipError_t lap_apply<double>(const Geo &, const double *, double *, hipStream_t);
+
+// f3 = add3 + alpha G p ; (G p)_d(idx) = (p(idx) - p(idx - e_d)) / h, zero on wall faces
+__global__ void k_grad(Geo g, const double *p_, double *f3, double alpha, const double *add3) {
+  RowPos p;
+  if (!row_pos(g, p)) return;
+  long long N = 2 * g.half;
+  int d = p.comp;
+  int bcd = geo_bc(g, d);
+  int xd = d == 0 ? p.i : (d == 1 ? p.j : p.k);
+  double v = 0.0;
+  if (!(bcd && xd == 0)) {
+    int i = p.i - (d == 0), j = p.j - (d == 1), k = p.k - (d == 2);
+    double lo = fetch(p_, g, i, j, k);
+    v = alpha * (p_[p.e] - lo) / g.h;
+    if (add3) v += add3[d * N + p.e];
+  }
+  f3[d * N + p.e] = v;
+}
+hipError_t grad_apply(const Geo &g, const double *p, double *f3, double alpha, const double *add3,
+                      hipStream_t s) {
+  RowLaunch L = row_launch(g, 2 * g.n0 * 3);
+  hipLaunchKernelGGL(k_grad, L.grid, L.block, 0, s, g, p, f3, alpha, add3);
+  return hipGetLastError();
+}
+
+// y = alpha D u ; (D u)_c = sum_d (u_d(c + e_d) - u_d(c)) / h with wall faces = 0
+__global__ void k_div(Geo g, const double *u3, double *y, double alpha) {
+  RowPos p;
+  if (!row_pos(g, p)) return;
+  long long N = 2 * g.half;
+  double acc = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    const double *ud = u3 + d * N;
+    int bcd = geo_bc(g, d);
+    int xd = d == 0 ? p.i : (d == 1 ? p.j : p.k);
+    double lo = (bcd && xd == 0) ? 0.0 : ud[p.e];
+    double hi = fetch(ud, g, p.i + (d == 0), p.j + (d == 1), p.k + (d == 2));
+    acc += hi - lo;
+  }
+  y[p.e] = alpha * acc / g.h;
+}
+hipError_t div_apply(const Geo &g, const double *u3, double *y, double alpha, hipStream_t s) {
+  RowLaunch L = row_launch(g, 2 * g.n0);
+  hipLaunchKernelGGL(k_div, L.grid, L.block, 0, s, g, u3, y, alpha);
+  return hipGetLastError();
+}
+
+__global__ void k_fill(double *x, long long n, double v) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; t < n; t += st) x[t] = v;
+}
+__global__ void k_fill_i32(int *x, long long n, int v) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; t < n; t += st) x[t] = v;
+}
+static int stream_blocks(long long n) {
+  long long b = (n + 255) / 256;
+  return (int)(b < 8192 ? (b < 1 ? 1 : b) : 8192);
+}
+hipError_t fill(double *x, long long n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(stream_blocks(n)), dim3(256), 0, s, x, n, v);
+  return hipGetLastError();
+}
+hipError_t fill_i32(int *x, long long n, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(stream_blocks(n)), dim3(256), 0, s, x, n, v);
+  return hipGetLastError();
+}
+
+__global__ void k_zero_wall(Geo g, double *u3) {
+  RowPos p;
+  if (!row_pos(g, p)) return;
+  int d = p.comp;
+  int xd = d == 0 ? p.i : (d == 1 ? p.j : p.k);
+  if (geo_bc(g, d) && xd == 0) u3[d * 2 * g.half + p.e] = 0.0;
+}
+hipError_t zero_wall_faces(const Geo &g, double *u3, hipStream_t s) {
+  RowLaunch L = row_launch(g, 2 * g.n0 * 3);
+  hipLaunchKernelGGL(k_zero_wall, L.grid, L.block, 0, s, g, u3);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Momentum operator on the component-d face grid.  Per axis a the second
+// difference has diagonal weight 2 (periodic, or normal-to-wall where the
+// wall faces 0 and n hold 0), or 2 plus 1 per missing neighbour for a
+// tangential wall (ghost value -u).  nb = sum of the existing neighbours.
+template <typename T>
+__device__ __forceinline__ void helm_stencil(const Geo &g, const T *ud, int d, int i, int j, int k,
+                                             T &nb, int &diag) {
+  nb = T(0);
+  diag = 0;
+  const int xs[3] = {i, j, k};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int n = geo_n(g, a), bc = geo_bc(g, a);
+#pragma unroll
+    for (int s = -1; s <= 1; s += 2) {
+      int y = xs[a] + s;
+      bool valid;
+      if (!bc) {
+        y = y < 0 ? y + n : (y >= n ? y - n : y);
+        valid = true;
+        diag += 1;
+      } else if (a == d) {
+        valid = (y >= 1) && (y <= n - 1);
+        diag += 1;
+      } else {
+        valid = (y >= 0) && (y <= n - 1);
+        diag += valid ? 1 : 2;
+      }
+      if (valid) {
+        int ii = a == 0 ? y : i, jj = a == 1 ? y : j, kk = a == 2 ? y : k;
+        nb += ud[sidx(g, ii, jj, kk)];
+      }
+    }
+  }
+}
+
+__global__ void k_helm_apply(Geo g, double a0, double nu, const double *u3, double *y3) {
+  RowPos p;
+  if (!row_pos(g, p)) return;
+  long long N = 2 * g.half;
+  int d = p.comp;
+  int xd = d == 0 ? p.i : (d == 1 ? p.j : p.k);
+  double out = 0.0;
+  if (!(geo_bc(g, d) && xd == 0)) {
+    const double *ud = u3 + d * N;
+    double nb;
+    int diag;
+    helm_stencil(g, ud, d, p.i, p.j, p.k, nb, diag);
+    out = (a0 + nu * diag / g.h2) * ud[p.e] - nu / g.h2 * nb;
+  }
+  y3[d * N + p.e] = out;
+}
+hipError_t helm_apply(const Geo &g, double a0, double nu, const double *u3, double *y3, hipStream_t s) {
+  RowLaunch L = row_launch(g, 2 * g.n0 * 3);
+  hipLaunchKernelGGL(k_helm_apply, L.grid, L.block, 0, s, g, a0, nu, u3, y3);
+  return hipGetLastError();
+}
+
+// r = b - A x in precision TR, plus per-block partial sums of |r|^2 (double).
+__device__ __forceinline__ double block_sum_2d(double v, double *sh) {
+  int tid = threadIdx.x + blockDim.x * threadIdx.y;
+  v = wave_sum(v);
+  if ((tid & 63) == 0) sh[tid >> 6] = v;
+  __syncthreads();
+  return ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+template <typename TR>
+__global__ void __launch_bounds__(256) k_helm_resid(Geo g, double a0, double nu, const double *x3, const double *b3,
+                                                    TR *r3, double *part) {
+  __shared__ double sh[4];
+  RowPos p;
+  double out = 0.0;
+  bool ok = row_pos(g, p);
+  long long N = 2 * g.half;
+  if (ok) {
+    int d = p.comp;
+    int xd = d == 0 ? p.i : (d == 1 ? p.j : p.k);
+    if (!(geo_bc(g, d) && xd == 0)) {
+      const double *ud = x3 + d * N;
+      double nb;
+      int diag;
+      helm_stencil(g, ud, d, p.i, p.j, p.k, nb, diag);
+      out = b3[d * N + p.e] - ((a0 + nu * diag / g.h2) * ud[p.e] - nu / g.h2 * nb);
+    }
+    r3[d * N + p.e] = (TR)out;
+  }
+  double t = block_sum_2d(out * out, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0)
+    part[blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z)] = t;
+}
+template <typename TR>
+hipError_t helm_resid(const Geo &g, double a0, double nu, const double *x3, const double *b3, TR *r3,
+                      double *part, int *nblocks, hipStream_t s) {
+  RowLaunch L = row_launch(g, 2 * g.n0 * 3);
+  hipLaunchKernelGGL(k_helm_resid<TR>, L.grid, L.block, 0, s, g, a0, nu, x3, b3, r3, part);
+  *nblocks = (int)(L.grid.x * L.grid.y * L.grid.z);
+  return hipGetLastError();
+}
+template hipError_t helm_resid<float>(const Geo &, double, double, const double *, const double *, float *,
+                                      double *, int *, hipStream_t);
+template hipError_t helm_resid<double>(const Geo &, double, double, const double *, const double *, double *,
+                                       double *, int *, hipStream_t);
+int helm_resid_blocks(const Geo &g) {
+  RowLaunch L = row_launch(g, 2 * g.n0 * 3);
+  return (int)(L.grid.x * L.grid.y * L.grid.z);
+}
+
+// One Chebyshev step for A e = r:  d = ca d + cb (r - A e_old),  e_new = e_old + d.
+template <typename T>
+__global__ void k_helm_cheb(Geo g, T a0, T nuh2, const T *e_old, const T *r3, T *d3, T *e_new, T ca, T cb) {
+  RowPos p;
+  if (!row_pos(g, p)) return;
+  long long N = 2 * g.half;
+  int d = p.comp;
+  int xd = d == 0 ? p.i : (d == 1 ? p.j : p.k);
+  long long q = d * N + p.e;
+  if (geo_bc(g, d) && xd == 0) {
+    d3[q] = T(0);
+    e_new[q] = T(0);
+    return;
+  }
+  T nb;
+  int diag;
+  helm_stencil(g, e_old + d * N, d, p.i, p.j, p.k, nb, diag);
+  T eo = e_old[q];
+  T ae = (a0 + nuh2 * (T)diag) * eo - nuh2 * nb;
+  T dv = ca * d3[q] + cb * (r3[q] - ae);
+  d3[q] = dv;
+  e_new[q] = eo + dv;
+}
+template <typename T>
+hipError_t helm_cheb(const Geo &g, double a0, double nu, const T *e_old, const T *r3, T *d3, T *e_new, double ca,
+                     double cb, hipStream_t s) {
+  RowLaunch L = row_launch(g, 2 * g.n0 * 3);
+  hipLaunchKernelGGL(k_helm_cheb<T>, L.grid, L.block, 0, s, g, (T)a0, (T)(nu / g.h2), e_old, r3, d3, e_new, (T)ca,
+                     (T)cb);
+  return hipGetLastError();
+}
+template hipError_t helm_cheb<float>(const Geo &, double, double, const float *, const float *, float *, float *,
+                                     double, double, hipStream_t);
+template hipError_t helm_cheb<double>(const Geo &, double, double, const double *, const double *, double *,
+                                      double *, double, double, hipStream_t);
+
+template <typename T>
+__global__ void k_fill_t(T *x, long long n) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; t < n; t += st) x[t] = T(0);
+}
+template <typename T>
+hipError_t zero_t(T *x, long long n, hipStream_t s) {
+  long long b = (n + 255) / 256;
+  int nb = (int)(b < 8192 ? (b < 1 ? 1 : b) : 8192);
+  hipLaunchKernelGGL(k_fill_t<T>, dim3(nb), dim3(256), 0, s, x, n);
+  return hipGetLastError();
+}
+template hipError_t zero_t<float>(float *, long long, hipStream_t);
+template hipError_t zero_t<double>(double *, long long, hipStream_t);
+
+// Red-black Gauss-Seidel half sweep for A x = b on the face grids, one colour.
+template <typename T, typename TB>
+__global__ void k_helm_rbgs(Geo g, T a0, T nuh2, T *x3, const TB *b3, int color) {
+  RowPos p;
+  if (!row_pos1(g, color, p)) return;
+  long long N = 2 * g.half;
+  int d = p.comp;
+  int xd = d == 0 ? p.i : (d == 1 ? p.j : p.k);
+  if (geo_bc(g, d) && xd == 0) return;
+  T *ud = x3 + d * N;
+  T nb;
+  int diag;
+  helm_stencil(g, (const T *)ud, d, p.i, p.j, p.k, nb, diag);
+  ud[p.e] = ((T)b3[d * N + p.e] + nuh2 * nb) / (a0 + nuh2 * (T)diag);
+}
+template <typename T, typename TB>
+hipError_t helm_rbgs(const Geo &g, double a0, double nu, T *x3, const TB *b3, int color, bool,
+                     hipStream_t s) {
+  RowLaunch L = row_launch(g, g.n0 * 3);
+  hipLaunchKernelGGL((k_helm_rbgs<T, TB>), L.grid, L.block, 0, s, g, (T)a0, (T)(nu / g.h2), x3, b3,
+                     color);
+  return hipGetLastError();
+}
+template hipError_t helm_rbgs<float, double>(const Geo &, double, double, float *, const double *, int,
+                                             bool, hipStream_t);
+template hipError_t helm_rbgs<double, double>(const Geo &, double, double, double *, const double *,
+                                              int, bool, hipStream_t);
+
+template <typename T>
+__global__ void k_add_cast(double *y, const T *x, long long n) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; t < n; t += st) y[t] += (double)x[t];
+}
+template <typename T>
+hipError_t add_cast(double *y, const T *x, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_cast<T>, dim3(stream_blocks(n)), dim3(256), 0, s, y, x, n);
+  return hipGetLastError();
+}
+template hipError_t add_cast<float>(double *, const float *, long long, hipStream_t);
+template hipError_t add_cast<double>(double *, const double *, long long, hipStream_t);
+
+template <typename T>
+__global__ void k_cast_copy(T *y, const double *x, long long n) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; t < n; t += st) y[t] = (T)x[t];
+}
+template <typename T>
+hipError_t cast_copy(T *y, const double *x, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_cast_copy<T>, dim3(stream_blocks(n)), dim3(256), 0, s, y, x, n);
+  return hipGetLastError();
+}
+template hipError_t cast_copy<float>(float *, const double *, long long, hipStream_t);
+template hipError_t cast_copy<double>(double *, const double *, long long, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Convection div(u u) at a component-d face, divergence form with arithmetic
+// averages; fluxes through no-slip walls vanish.
+__device__ double conv_at(const Geo &g, const double *u3, int d, int i, int j, int k) {
+  long long N = 2 * g.half;
+  const double *ud = u3 + d * N;
+  double acc = 0.0;
+  const int x0[3] = {i, j, k};
+  for (int a = 0; a < 3; ++a) {
+    int ea[3] = {a == 0, a == 1, a == 2};
+    if (a == d) {
+      double u0 = fetch(ud, g, i, j, k);
+      double up = fetch(ud, g, i + ea[0], j + ea[1], k + ea[2]);
+      double um = fetch(ud, g, i - ea[0], j - ea[1], k - ea[2]);
+      double cp = 0.5 * (u0 + up), cm = 0.5 * (um + u0);
+      acc += (cp * cp - cm * cm) / g.h;
+    } else {
+      const double *ua = u3 + a * N;
+      int ed[3] = {d == 0, d == 1, d == 2};
+      int na = geo_n(g, a), bca = geo_bc(g, a);
+      double fp = 0.0, fm = 0.0;
+      if (!(bca && x0[a] == na - 1)) {
+        double udm = 0.5 * (fetch(ud, g, i, j, k) + fetch(ud, g, i + ea[0], j + ea[1], k + ea[2]));
+        double uam = 0.5 * (fetch(ua, g, i + ea[0], j + ea[1], k + ea[2]) +
+                            fetch(ua, g, i + ea[0] - ed[0], j + ea[1] - ed[1], k + ea[2] - ed[2]));
+        fp = udm * uam;
+      }
+      if (!(bca && x0[a] == 0)) {
+        double udm = 0.5 * (fetch(ud, g, i - ea[0], j - ea[1], k - ea[2]) + fetch(ud, g, i, j, k));
+        double uam = 0.5 * (fetch(ua, g, i, j, k) + fetch(ua, g, i - ed[0], j - ed[1], k - ed[2]));
+        fm = udm * uam;
+      }
+      acc += (fp - fm) / g.h;
+    }
+  }
+  return acc;
+}
+
+__global__ void k_convection(Geo g, const double *u3, double *out3) {
+  RowPos p;
+  if (!row_pos(g, p)) return;
+  long long N = 2 * g.half;
+  int d = p.comp;
+  int xd = d == 0 ? p.i : (d == 1 ? p.j : p.k);
+  double v = 0.0;
+  if (!(geo_bc(g, d) && xd == 0)) v = conv_at(g, u3, d, p.i, p.j, p.k);
+  out3[d * N + p.e] = v;
+}
+hipError_t convection(const Geo &g, const double *u3, double *out3, hipStream_t s) {
+  RowLaunch L = row_launch(g, 2 * g.n0 * 3);
+  hipLaunchKernelGGL(k_convection, L.grid, L.block, 0, s, g, u3, out3);
+  return hipGetLastError();
+}
+
+// rhs = (4 u^n - u^{n-1}) / (2 dt) - G p^n - N(u^n)     (eq. ustar; W Phi^n is
+// added afterwards by the band kernel)
+__global__ void k_mom_rhs(Geo g, double dt, const double *u3, const double *um3, const double *p_,
+                          double *out3) {
+  RowPos p;
+  if (!row_pos(g, p)) return;
+  long long N = 2 * g.half;
+  int d = p.comp;
+  int xd = d == 0 ? p.i : (d == 1 ? p.j : p.k);
+  double v = 0.0;
+  if (!(geo_bc(g, d) && xd == 0)) {
+    double lo = fetch(p_, g, p.i - (d == 0), p.j - (d == 1), p.k - (d == 2));
+    double gp = (p_[p.e] - lo) / g.h;
+    v = (4.0 * u3[d * N + p.e] - um3[d * N + p.e]) / (2.0 * dt) - gp -
+        conv_at(g, u3, d, p.i, p.j, p.k);
+  }
+  out3[d * N + p.e] = v;
+}
+hipError_t mom_rhs(const Geo &g, double dt, const double *u3, const double *um3, const double *p,
+                   double *out3, hipStream_t s) {
+  RowLaunch L = row_launch(g, 2 * g.n0 * 3);
+  hipLaunchKernelGGL(k_mom_rhs, L.grid, L.block, 0, s, g, dt, u3, um3, p, out3);
+  return hipGetLastError();
+}
+
+}  // namespace ibs

@@ -1,0 +1,192 @@
+// Vector kernels of the flexible GMRES outer loop: fused multi-dot products
+// (classical Gram-Schmidt), fused orthogonalisation update with the norm of
+// the result, the solution update x += Z y, and small helpers.  All
+// reductions are deterministic: per-thread partials in a fixed grid-stride
+// order, fixed butterfly inside the wavefront, fixed order across the
+// wavefronts of a block, then a second kernel that sums the per-block
+// partials in a fixed order.
+#include "internal.h"
+
+namespace ibs {
+
+constexpr int RED_BLOCKS = 1024;
+constexpr int RED_T = 256;
+constexpr int MD_MAX = 24;  // dot products per multidot pass
+int red_blocks() { return RED_BLOCKS; }
+
+__device__ __forceinline__ double block_reduce(double v, double *sh) {
+  v = wave_sum(v);
+  int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double r = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(RED_T) k_multidot(const double *w, const double *V, long long stride, int nv,
+                                                    long long n, double *part) {
+  double acc[MD_MAX];
+#pragma unroll
+  for (int i = 0; i < MD_MAX; ++i) acc[i] = 0.0;
+  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T) {
+    double wv = w[t];
+#pragma unroll
+    for (int i = 0; i < MD_MAX; ++i)
+      if (i < nv) acc[i] += wv * V[i * stride + t];
+  }
+  __shared__ double sh[4][MD_MAX];
+  int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < MD_MAX; ++i) {
+    if (i < nv) {
+      double v = wave_sum(acc[i]);
+      if (ln == 0) sh[wv][i] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < nv)
+    part[(long long)blockIdx.x * nv + threadIdx.x] =
+        ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
+}
+
+hipError_t multidot(const double *w, const double *V, long long stride, int nv, long long n, double *part,
+                    hipStream_t s) {
+  // part layout: [blk][nv]; chunks of MD_MAX vectors write consecutive column groups
+  for (int c0 = 0; c0 < nv; c0 += MD_MAX) {
+    int nc = nv - c0 < MD_MAX ? nv - c0 : MD_MAX;
+    hipLaunchKernelGGL(k_multidot, dim3(RED_BLOCKS), dim3(RED_T), 0, s, w, V + c0 * stride, stride, nc, n,
+                       part + (long long)c0 * RED_BLOCKS);
+  }
+  return hipGetLastError();
+}
+
+// out[i] = sum_b part[b][i] over nblk blocks (chunked layout of multidot)
+__global__ void __launch_bounds__(RED_T) k_finalize(const double *part, int nblk, int nv, double *out) {
+  int i = blockIdx.x;
+  int c0 = (i / MD_MAX) * MD_MAX;
+  int nc = nv - c0 < MD_MAX ? nv - c0 : MD_MAX;
+  const double *pc = part + (long long)c0 * nblk;
+  int col = i - c0;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += RED_T) v += pc[(long long)b * nc + col];
+  __shared__ double sh[4];
+  v = block_reduce(v, sh);
+  if (threadIdx.x == 0) out[i] = v;
+}
+hipError_t finalize(const double *part, int nblk, int nv, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(nv), dim3(RED_T), 0, s, part, nblk, nv, out);
+  return hipGetLastError();
+}
+
+// w -= sum_i h_i V_i ; partial |w|^2
+__global__ void __launch_bounds__(RED_T) k_update_norm(double *w, const double *V, long long stride, int nv,
+                                                       const double *hcoef, long long n, double *part) {
+  __shared__ double hs[64];
+  __shared__ double sh[4];
+  for (int i = threadIdx.x; i < nv; i += RED_T) hs[i] = hcoef[i];
+  __syncthreads();
+  double acc = 0.0;
+  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T) {
+    double v = w[t];
+    for (int i = 0; i < nv; ++i) v -= hs[i] * V[i * stride + t];
+    w[t] = v;
+    acc += v * v;
+  }
+  acc = block_reduce(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+hipError_t update_norm(double *w, const double *V, long long stride, int nv, const double *hcoef, long long n,
+                       double *part, hipStream_t s) {
+  if (nv > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_update_norm, dim3(RED_BLOCKS), dim3(RED_T), 0, s, w, V, stride, nv, hcoef, n, part);
+  return hipGetLastError();
+}
+
+__global__ void k_scale_copy(double *y, const double *x, long long n, double a) {
+  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T)
+    y[t] = a * x[t];
+}
+hipError_t scale_inplace(double *x, long long n, double alpha, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(RED_BLOCKS * 4), dim3(RED_T), 0, s, x, x, n, alpha);
+  return hipGetLastError();
+}
+hipError_t scale_copy(double *y, const double *x, long long n, double alpha, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(RED_BLOCKS * 4), dim3(RED_T), 0, s, y, x, n, alpha);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_sol_update(double *x, const T *Z, long long stride, int nz, const double *y, long long n) {
+  __shared__ double ys[64];
+  for (int i = threadIdx.x; i < nz; i += RED_T) ys[i] = y[i];
+  __syncthreads();
+  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T) {
+    double v = x[t];
+    for (int j = 0; j < nz; ++j) v += ys[j] * (double)Z[j * stride + t];
+    x[t] = v;
+  }
+}
+template <typename T>
+hipError_t sol_update(double *x, const T *Z, long long stride, int nz, const double *y, long long n,
+                      hipStream_t s) {
+  if (nz > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sol_update<T>, dim3(RED_BLOCKS * 4), dim3(RED_T), 0, s, x, Z, stride, nz, y, n);
+  return hipGetLastError();
+}
+template hipError_t sol_update<float>(double *, const float *, long long, int, const double *, long long,
+                                      hipStream_t);
+template hipError_t sol_update<double>(double *, const double *, long long, int, const double *, long long,
+                                       hipStream_t);
+
+__global__ void k_axpby(double *y, const double *x, long long n, double a, double b) {
+  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T)
+    y[t] = a * x[t] + b * y[t];
+}
+hipError_t axpby(double *y, const double *x, long long n, double a, double b, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3(RED_BLOCKS * 4), dim3(RED_T), 0, s, y, x, n, a, b);
+  return hipGetLastError();
+}
+
+__global__ void k_add_scalar(double *x, long long n, const double *ds, double mult) {
+  double a = mult * ds[0];
+  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T)
+    x[t] += a;
+}
+hipError_t add_scalar_dev(double *x, long long n, const double *dscalar, double mult, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_scalar, dim3(RED_BLOCKS * 4), dim3(RED_T), 0, s, x, n, dscalar, mult);
+  return hipGetLastError();
+}
+
+// r = b - ax ; partial |r|^2
+__global__ void __launch_bounds__(RED_T) k_sub_norm(double *r, const double *b, const double *ax, long long n,
+                                                    double *part) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T) {
+    double v = b[t] - ax[t];
+    r[t] = v;
+    acc += v * v;
+  }
+  acc = block_reduce(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+hipError_t sub_mul(double *r, const double *b, const double *ax, long long n, double *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_norm, dim3(RED_BLOCKS), dim3(RED_T), 0, s, r, b, ax, n, part);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(RED_T) k_dot2(const double *a, const double *b, long long n, double *part) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T)
+    acc += b ? a[t] * b[t] : a[t];
+  acc = block_reduce(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+hipError_t dot2(const double *a, const double *b, long long n, double *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot2, dim3(RED_BLOCKS), dim3(RED_T), 0, s, a, b, n, part);
+  return hipGetLastError();
+}
+
+}  // namespace ibs

@@ -1,0 +1,342 @@
+// Geometric multigrid V-cycle for the pressure Laplacian L = G^T G, used as
+// the preconditioner M^-1 ~ L^+ of the Schur Krylov solve.  The paper applies
+// an exact fast-diagonalisation solve of L once per iteration (Sec. 4.2) and
+// names a multigrid V-cycle as its linear-time replacement (Sec. 6).
+//
+// Cycle: red-black Gauss-Seidel smoothing (pre: red then black, post: black
+// then red, so the cycle is symmetric), residual restricted by averaging the
+// eight children, trilinear cell-centred prolongation, coarse operators
+// rediscretised on 2h, and a single-workgroup kernel that runs V-cycles on
+// the coarsest grids entirely in LDS.  Kernels are templated on the working
+// precision T (float or double) and on the right-hand-side type TB.
+#include "internal.h"
+
+namespace ibs {
+
+__device__ __forceinline__ bool row_pos1m(const Geo &g, int color, RowPos &p) {
+  p.m = blockIdx.x * blockDim.x + threadIdx.x;
+  p.j = blockIdx.y * blockDim.y + threadIdx.y;
+  p.i = blockIdx.z;
+  p.comp = 0;
+  p.c = color;
+  if (p.m >= g.hn2 || p.j >= g.n1) return false;
+  p.k = 2 * p.m + ((p.c + p.i + p.j) & 1);
+  p.e = (long long)p.c * g.half + ((long long)p.i * g.n1 + p.j) * g.hn2 + p.m;
+  return true;
+}
+
+template <typename T>
+__device__ __forceinline__ T nb_sum(const Geo &g, const T *x, int i, int j, int k, int c, int m) {
+  const T *o = x + (long long)(1 - c) * g.half;
+  T s = T(0);
+  int t;
+  t = nbr(i, -1, g.n0, g.bc0); if (t >= 0) s += o[((long long)t * g.n1 + j) * g.hn2 + m];
+  t = nbr(i, 1, g.n0, g.bc0);  if (t >= 0) s += o[((long long)t * g.n1 + j) * g.hn2 + m];
+  t = nbr(j, -1, g.n1, g.bc1); if (t >= 0) s += o[((long long)i * g.n1 + t) * g.hn2 + m];
+  t = nbr(j, 1, g.n1, g.bc1);  if (t >= 0) s += o[((long long)i * g.n1 + t) * g.hn2 + m];
+  long long row = ((long long)i * g.n1 + j) * g.hn2;
+  t = nbr(k, -1, g.n2, g.bc2); if (t >= 0) s += o[row + (t >> 1)];
+  t = nbr(k, 1, g.n2, g.bc2);  if (t >= 0) s += o[row + (t >> 1)];
+  return s;
+}
+
+// First sweep from x = 0: red x = h^2 b / nnb; black uses those red values,
+// which it recomputes from b instead of reading x.
+template <typename T, typename TB>
+__global__ void k_smooth_first(Geo g, T *x, const TB *b) {
+  RowPos p;
+  if (!row_pos(g, p)) return;
+  T h2 = (T)g.h2;
+  int nn = cell_nnb(g, p.i, p.j, p.k);
+  if (p.c == 0) {
+    x[p.e] = h2 * (T)b[p.e] / (T)nn;
+    return;
+  }
+  const TB *o = b;  // red plane
+  T s = T(0);
+  int t;
+#define RED_NB(ii, jj, kk)                                                                  \
+  {                                                                                         \
+    long long q = ((long long)(ii) * g.n1 + (jj)) * g.hn2 + ((kk) >> 1);                   \
+    s += h2 * (T)o[q] / (T)cell_nnb(g, ii, jj, kk);                                         \
+  }
+  t = nbr(p.i, -1, g.n0, g.bc0); if (t >= 0) RED_NB(t, p.j, p.k);
+  t = nbr(p.i, 1, g.n0, g.bc0);  if (t >= 0) RED_NB(t, p.j, p.k);
+  t = nbr(p.j, -1, g.n1, g.bc1); if (t >= 0) RED_NB(p.i, t, p.k);
+  t = nbr(p.j, 1, g.n1, g.bc1);  if (t >= 0) RED_NB(p.i, t, p.k);
+  t = nbr(p.k, -1, g.n2, g.bc2); if (t >= 0) RED_NB(p.i, p.j, t);
+  t = nbr(p.k, 1, g.n2, g.bc2);  if (t >= 0) RED_NB(p.i, p.j, t);
+#undef RED_NB
+  x[p.e] = (h2 * (T)b[p.e] + s) / (T)nn;
+}
+
+template <typename T, typename TB>
+__global__ void k_smooth(Geo g, T *x, const TB *b, int color) {
+  RowPos p;
+  if (!row_pos1m(g, color, p)) return;
+  T s = nb_sum(g, (const T *)x, p.i, p.j, p.k, p.c, p.m);
+  int nn = cell_nnb(g, p.i, p.j, p.k);
+  x[p.e] = ((T)g.h2 * (T)b[p.e] + s) / (T)nn;
+}
+
+// Coarse right-hand side: the average of the fine residual over the eight
+// children.  The last half sweep relaxed the black cells, whose residual is
+// therefore zero; only the four red children contribute.
+template <typename T, typename TB>
+__global__ void k_restrict(Geo gf, const T *xf, const TB *bf, Geo gc, T *bc) {
+  RowPos p;
+  if (!row_pos(gc, p)) return;
+  const int ch[4][3] = {{0, 0, 0}, {0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
+  T acc = T(0);
+  T ih2 = (T)(1.0 / gf.h2);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int i = 2 * p.i + ch[q][0], j = 2 * p.j + ch[q][1], k = 2 * p.k + ch[q][2];
+    int m = k >> 1;
+    long long e = ((long long)i * gf.n1 + j) * gf.hn2 + m;  // red plane
+    T s = nb_sum(gf, xf, i, j, k, 0, m);
+    int nn = cell_nnb(gf, i, j, k);
+    acc += (T)bf[e] - ((T)nn * xf[e] - s) * ih2;
+  }
+  bc[p.e] = acc * (T)0.125;
+}
+
+// x_f += P x_c on the red fine cells only (the following black half sweep
+// overwrites the black cells without reading them).
+template <typename T>
+__global__ void k_prolong(Geo gf, T *xf, Geo gc, const T *xc) {
+  RowPos p;
+  if (!row_pos1m(gf, 0, p)) return;
+  int I[3][2];
+  T w[3][2];
+  const int xs[3] = {p.i, p.j, p.k};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int C = xs[a] >> 1;
+    int s = (xs[a] & 1) ? 1 : -1;
+    int nc = geo_n(gc, a), bc = geo_bc(gc, a);
+    int o = C + s;
+    if (o < 0 || o >= nc) o = bc ? C : (o < 0 ? o + nc : o - nc);
+    I[a][0] = C;
+    I[a][1] = o;
+    w[a][0] = (T)0.75;
+    w[a][1] = (T)0.25;
+  }
+  T acc = T(0);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        acc += w[0][a] * w[1][b] * w[2][c] * xc[sidx(gc, I[0][a], I[1][b], I[2][c])];
+  xf[p.e] += acc;
+}
+
+template <typename T, typename TB>
+hipError_t mg_smooth_first(const Geo &g, T *x, const TB *b, hipStream_t s) {
+  RowLaunch L = row_launch(g, 2 * g.n0);
+  hipLaunchKernelGGL((k_smooth_first<T, TB>), L.grid, L.block, 0, s, g, x, b);
+  return hipGetLastError();
+}
+template <typename T, typename TB>
+hipError_t mg_smooth(const Geo &g, T *x, const TB *b, int color, hipStream_t s) {
+  RowLaunch L = row_launch(g, g.n0);
+  hipLaunchKernelGGL((k_smooth<T, TB>), L.grid, L.block, 0, s, g, x, b, color);
+  return hipGetLastError();
+}
+template <typename T, typename TB>
+hipError_t mg_restrict(const Geo &gf, const T *xf, const TB *bf, const Geo &gc, T *bc, hipStream_t s) {
+  RowLaunch L = row_launch(gc, 2 * gc.n0);
+  hipLaunchKernelGGL((k_restrict<T, TB>), L.grid, L.block, 0, s, gf, xf, bf, gc, bc);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t mg_prolong(const Geo &gf, T *xf, const Geo &gc, const T *xc, hipStream_t s) {
+  RowLaunch L = row_launch(gf, gf.n0);
+  hipLaunchKernelGGL(k_prolong<T>, L.grid, L.block, 0, s, gf, xf, gc, xc);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Coarse-grid kernel: one workgroup, the whole coarse hierarchy in LDS
+// (natural layout).  Projects the right-hand side to mean zero (L is
+// singular on constants), then runs `cycles` V-cycles with `sweeps` red-black
+// sweeps per level and 32 sweeps on the smallest grid.
+constexpr int COARSE_MAX = 4096;                 // cells of the coarse grid
+constexpr int COARSE_CAP = 4096 + 512 + 64 + 8 + 8;
+constexpr int COARSE_THREADS = 1024;
+constexpr int COARSE_MAXLEV = 8;
+int coarse_max_cells() { return COARSE_MAX; }
+
+struct LvlDim { int n0, n1, n2, off; };
+
+template <typename T>
+__device__ void lds_smooth(T *x, const T *b, const LvlDim &d, int bc0, int bc1, int bc2, T h2, int color) {
+  int nc = d.n0 * d.n1 * d.n2;
+  for (int e = threadIdx.x; e < nc; e += COARSE_THREADS) {
+    int k = e % d.n2, r = e / d.n2, j = r % d.n1, i = r / d.n1;
+    if (((i + j + k) & 1) != color) continue;
+    T s = T(0);
+    int nn = 0, t;
+    t = nbr(i, -1, d.n0, bc0); if (t >= 0) { s += x[d.off + (t * d.n1 + j) * d.n2 + k]; ++nn; }
+    t = nbr(i, 1, d.n0, bc0);  if (t >= 0) { s += x[d.off + (t * d.n1 + j) * d.n2 + k]; ++nn; }
+    t = nbr(j, -1, d.n1, bc1); if (t >= 0) { s += x[d.off + (i * d.n1 + t) * d.n2 + k]; ++nn; }
+    t = nbr(j, 1, d.n1, bc1);  if (t >= 0) { s += x[d.off + (i * d.n1 + t) * d.n2 + k]; ++nn; }
+    t = nbr(k, -1, d.n2, bc2); if (t >= 0) { s += x[d.off + (i * d.n1 + j) * d.n2 + t]; ++nn; }
+    t = nbr(k, 1, d.n2, bc2);  if (t >= 0) { s += x[d.off + (i * d.n1 + j) * d.n2 + t]; ++nn; }
+    x[d.off + e] = (h2 * b[d.off + e] + s) / (T)nn;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ T lds_resid(const T *x, const T *b, const LvlDim &d, int bc0, int bc1, int bc2, T ih2, int i, int j,
+                       int k) {
+  T s = T(0);
+  int nn = 0, t;
+  t = nbr(i, -1, d.n0, bc0); if (t >= 0) { s += x[d.off + (t * d.n1 + j) * d.n2 + k]; ++nn; }
+  t = nbr(i, 1, d.n0, bc0);  if (t >= 0) { s += x[d.off + (t * d.n1 + j) * d.n2 + k]; ++nn; }
+  t = nbr(j, -1, d.n1, bc1); if (t >= 0) { s += x[d.off + (i * d.n1 + t) * d.n2 + k]; ++nn; }
+  t = nbr(j, 1, d.n1, bc1);  if (t >= 0) { s += x[d.off + (i * d.n1 + t) * d.n2 + k]; ++nn; }
+  t = nbr(k, -1, d.n2, bc2); if (t >= 0) { s += x[d.off + (i * d.n1 + j) * d.n2 + t]; ++nn; }
+  t = nbr(k, 1, d.n2, bc2);  if (t >= 0) { s += x[d.off + (i * d.n1 + j) * d.n2 + t]; ++nn; }
+  int e = d.off + (i * d.n1 + j) * d.n2 + k;
+  return b[e] - ((T)nn * x[e] - s) * ih2;
+}
+
+template <typename T>
+__device__ double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < COARSE_THREADS / 64; ++q) t += red[q];
+    red[COARSE_THREADS / 64] = t;
+  }
+  __syncthreads();
+  t = red[COARSE_THREADS / 64];
+  __syncthreads();
+  return t;
+}
+
+template <typename T, typename TB>
+__global__ void __launch_bounds__(COARSE_THREADS) k_coarse(Geo g, const TB *bin, T *xout, int cycles, int sweeps) {
+  __shared__ T sx[COARSE_CAP];
+  __shared__ T sb[COARSE_CAP];
+  __shared__ double red[COARSE_THREADS / 64 + 1];
+  LvlDim d[COARSE_MAXLEV];
+  int nl = 1;
+  d[0].n0 = g.n0; d[0].n1 = g.n1; d[0].n2 = g.n2; d[0].off = 0;
+  while (nl < COARSE_MAXLEV) {
+    const LvlDim &q = d[nl - 1];
+    if ((q.n0 & 1) || (q.n1 & 1) || (q.n2 & 1) || q.n0 < 4 || q.n1 < 4 || q.n2 < 4) break;
+    d[nl].n0 = q.n0 / 2; d[nl].n1 = q.n1 / 2; d[nl].n2 = q.n2 / 2;
+    d[nl].off = q.off + q.n0 * q.n1 * q.n2;
+    ++nl;
+  }
+  const int nc0 = g.n0 * g.n1 * g.n2;
+  // load b (split layout -> natural) and project to mean zero
+  double loc = 0.0;
+  for (int e = threadIdx.x; e < nc0; e += COARSE_THREADS) {
+    int k = e % g.n2, r = e / g.n2, j = r % g.n1, i = r / g.n1;
+    T v = (T)bin[sidx(g, i, j, k)];
+    sb[e] = v;
+    sx[e] = T(0);
+    loc += (double)v;
+  }
+  double mean = block_sum<T>(loc, red) / (double)nc0;
+  for (int e = threadIdx.x; e < nc0; e += COARSE_THREADS) sb[e] -= (T)mean;
+  __syncthreads();
+
+  for (int cyc = 0; cyc < cycles; ++cyc) {
+    T h = (T)g.h;
+    for (int l = 0; l + 1 < nl; ++l) {
+      T h2 = h * h;
+      for (int s = 0; s < sweeps; ++s) {
+        lds_smooth(sx, sb, d[l], g.bc0, g.bc1, g.bc2, h2, 0);
+        lds_smooth(sx, sb, d[l], g.bc0, g.bc1, g.bc2, h2, 1);
+      }
+      const LvlDim &f = d[l], &c = d[l + 1];
+      int ncc = c.n0 * c.n1 * c.n2;
+      T ih2 = T(1) / h2;
+      for (int e = threadIdx.x; e < ncc; e += COARSE_THREADS) {
+        int k = e % c.n2, r = e / c.n2, j = r % c.n1, i = r / c.n1;
+        T acc = T(0);
+        for (int q = 0; q < 8; ++q)
+          acc += lds_resid(sx, sb, f, g.bc0, g.bc1, g.bc2, ih2, 2 * i + (q >> 2), 2 * j + ((q >> 1) & 1),
+                           2 * k + (q & 1));
+        sb[c.off + e] = acc * (T)0.125;
+        sx[c.off + e] = T(0);
+      }
+      __syncthreads();
+      h = h * (T)2;
+    }
+    {
+      T h2 = h * h;
+      for (int s = 0; s < 32; ++s) {
+        lds_smooth(sx, sb, d[nl - 1], g.bc0, g.bc1, g.bc2, h2, 0);
+        lds_smooth(sx, sb, d[nl - 1], g.bc0, g.bc1, g.bc2, h2, 1);
+      }
+    }
+    for (int l = nl - 2; l >= 0; --l) {
+      h = h * (T)0.5;
+      const LvlDim &f = d[l], &c = d[l + 1];
+      int ncf = f.n0 * f.n1 * f.n2;
+      for (int e = threadIdx.x; e < ncf; e += COARSE_THREADS) {
+        int k = e % f.n2, r = e / f.n2, j = r % f.n1, i = r / f.n1;
+        const int xs[3] = {i, j, k};
+        const int nn[3] = {c.n0, c.n1, c.n2};
+        const int bcs[3] = {g.bc0, g.bc1, g.bc2};
+        int I[3][2];
+        for (int a = 0; a < 3; ++a) {
+          int C = xs[a] >> 1, s = (xs[a] & 1) ? 1 : -1, o = C + s;
+          if (o < 0 || o >= nn[a]) o = bcs[a] ? C : (o < 0 ? o + nn[a] : o - nn[a]);
+          I[a][0] = C;
+          I[a][1] = o;
+        }
+        T acc = T(0);
+        for (int q = 0; q < 8; ++q) {
+          int qa = q >> 2, qb = (q >> 1) & 1, qc = q & 1;
+          T w = (qa ? (T)0.25 : (T)0.75) * (qb ? (T)0.25 : (T)0.75) * (qc ? (T)0.25 : (T)0.75);
+          acc += w * sx[c.off + (I[0][qa] * c.n1 + I[1][qb]) * c.n2 + I[2][qc]];
+        }
+        sx[f.off + e] += acc;
+      }
+      __syncthreads();
+      T h2 = h * h;
+      for (int s = 0; s < sweeps; ++s) {
+        lds_smooth(sx, sb, d[l], g.bc0, g.bc1, g.bc2, h2, 1);
+        lds_smooth(sx, sb, d[l], g.bc0, g.bc1, g.bc2, h2, 0);
+      }
+    }
+  }
+  for (int e = threadIdx.x; e < nc0; e += COARSE_THREADS) {
+    int k = e % g.n2, r = e / g.n2, j = r % g.n1, i = r / g.n1;
+    xout[sidx(g, i, j, k)] = sx[e];
+  }
+}
+
+template <typename T, typename TB>
+hipError_t mg_coarse(const Geo &gc, const TB *b, T *x, int cycles, int sweeps, hipStream_t s) {
+  if ((long long)gc.n0 * gc.n1 * gc.n2 > COARSE_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_coarse<T, TB>), dim3(1), dim3(COARSE_THREADS), 0, s, gc, b, x, cycles, sweeps);
+  return hipGetLastError();
+}
+
+#define INST(T, TB)                                                                                    \
+  template hipError_t mg_smooth_first<T, TB>(const Geo &, T *, const TB *, hipStream_t);              \
+  template hipError_t mg_smooth<T, TB>(const Geo &, T *, const TB *, int, hipStream_t);               \
+  template hipError_t mg_restrict<T, TB>(const Geo &, const T *, const TB *, const Geo &, T *,         \
+                                         hipStream_t);                                                 \
+  template hipError_t mg_coarse<T, TB>(const Geo &, const TB *, T *, int, int, hipStream_t);
+INST(float, float)
+INST(float, double)
+INST(double, double)
+#undef INST
+template hipError_t mg_prolong<float>(const Geo &, float *, const Geo &, const float *, hipStream_t);
+template hipError_t mg_prolong<double>(const Geo &, double *, const Geo &, const double *, hipStream_t);
+
+}  // namespace ibs

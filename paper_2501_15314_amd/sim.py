@@ -1,0 +1,194 @@
+"""Python front end of libibschur: a thin wrapper that marshals torch device
+tensors and the current HIP stream into the C ABI of include/ibschur.h.
+
+Every computation runs in the HIP library; this module only allocates the
+device workspace and the argument tensors (PyTorch is used for device memory
+and streams) and converts layouts of Python objects into the C structs.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from .workloads import Body, Config, Workload
+
+
+class SimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_lib.STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def make_config(cfg: Config, stream=None) -> _lib.SimConfig:
+    c = _lib.SimConfig()
+    c.n[:] = list(cfg.n)
+    c.len[:] = list(cfg.length)
+    c.bc[:] = list(cfg.bc)
+    c.nu, c.dt = cfg.nu, cfg.dt
+    c.g[:] = list(cfg.g)
+    c.delta, c.lump_c = cfg.delta, cfg.lump_c
+    c.precision, c.krylov_restart, c.krylov_maxit = cfg.precision, cfg.krylov_restart, cfg.krylov_maxit
+    c.krylov_rtol = cfg.krylov_rtol
+    c.helm_maxit, c.helm_rtol = cfg.helm_maxit, cfg.helm_rtol
+    c.mg_coarsest, c.mg_pre, c.mg_post = cfg.mg_coarsest, cfg.mg_pre, cfg.mg_post
+    c.mg_coarse_sweeps = cfg.mg_coarse_sweeps
+    c.outer_iters, c.outer_tol, c.xi = cfg.outer_iters, cfg.outer_tol, cfg.xi
+    c.device = cfg.device
+    c.stream = stream if stream is not None else torch.cuda.current_stream(cfg.device).cuda_stream
+    return c
+
+
+def make_bodies(bodies):
+    arr = (_lib.SimBody * max(1, len(bodies)))()
+    for i, b in enumerate(bodies):
+        sb = arr[i]
+        sb.center[:] = [float(x) for x in b.center]
+        sb.vel[:] = [float(x) for x in b.vel]
+        sb.omega[:] = [float(x) for x in b.omega]
+        sb.radius = float(b.radius)
+        sb.density_ratio = float(b.density_ratio)
+        sb.osc_amp[:] = [float(x) for x in b.osc_amp]
+        sb.osc_omega = float(b.osc_omega)
+        sb.motion = int(b.motion)
+        sb.n_points = int(b.n_points)
+    return arr
+
+
+class Sim:
+    """One solver instance on one GPU (one handle, one stream)."""
+
+    def __init__(self, cfg: Config, max_points: int, device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the IB Schur solver needs a HIP device")
+        self.lib = _lib.load()
+        cfg.device = device
+        self.cfg = cfg
+        self.dev = torch.device("cuda", device)
+        self.stream = torch.cuda.current_stream(self.dev)
+        self.ccfg = make_config(cfg, self.stream.cuda_stream)
+        nbytes = self.lib.sim_workspace_bytes(C.byref(self.ccfg), max_points)
+        if nbytes == 0:
+            raise SimError(_lib.SIM_EINVAL, "invalid configuration")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.dev)
+        h = C.c_void_p()
+        rc = self.lib.sim_create(C.byref(self.ccfg), _ptr(self.workspace), nbytes + 256, max_points,
+                                 C.byref(h))
+        if rc != 0:
+            raise SimError(rc, "sim_create failed")
+        self.h = h
+        self.K = 0
+        self.nb = 0
+        self.n = tuple(cfg.n)
+
+    def _check(self, rc, allow_notconv=False):
+        if rc == 0 or (allow_notconv and rc == _lib.SIM_ENOTCONV):
+            return rc
+        raise SimError(rc, self.lib.sim_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- state ------------------------------------------------------------
+    def set_bodies(self, bodies, offsets):
+        off = np.ascontiguousarray(offsets, dtype=np.float64)
+        arr = make_bodies(bodies)
+        self._check(self.lib.sim_set_bodies(self.h, len(bodies), arr,
+                                            off.ctypes.data_as(C.POINTER(C.c_double))))
+        self.K = int(off.shape[0])
+        self.nb = len(bodies)
+
+    def set_workload(self, w: Workload):
+        self.set_bodies(w.bodies, w.offsets)
+        u0 = torch.as_tensor(w.u0, device=self.dev)
+        self.set_fields(0, u0)
+        self.set_fields(1, u0)
+
+    def _t(self, x):
+        if x is None:
+            return None
+        return torch.as_tensor(x, dtype=torch.float64, device=self.dev).contiguous()
+
+    def set_fields(self, level, u3=None, p=None, phi=None):
+        u3 = self._t(u3)
+        comps = [u3[d] if u3 is not None else None for d in range(3)]
+        p, phi = self._t(p), self._t(phi)
+        self._check(self.lib.sim_set_fields(self.h, level, *[_ptr(c) for c in comps], _ptr(p), _ptr(phi)))
+
+    def get_fields(self):
+        u = torch.empty((3,) + self.n, dtype=torch.float64, device=self.dev)
+        p = torch.empty(self.n, dtype=torch.float64, device=self.dev)
+        self._check(self.lib.sim_get_fields(self.h, _ptr(u[0]), _ptr(u[1]), _ptr(u[2]), _ptr(p)))
+        return u, p
+
+    def get_points(self):
+        X = torch.empty((max(self.K, 1), 3), dtype=torch.float64, device=self.dev)
+        U = torch.empty_like(X)
+        self._check(self.lib.sim_get_points(self.h, _ptr(X), _ptr(U)))
+        return X[:self.K], U[:self.K]
+
+    def get_forces(self):
+        f = torch.empty((max(self.K, 1), 3), dtype=torch.float64, device=self.dev)
+        ft = (C.c_double * (6 * max(self.nb, 1)))()
+        self._check(self.lib.sim_get_forces(self.h, _ptr(f), ft))
+        return f[:self.K], np.array(ft[:6 * self.nb]).reshape(self.nb, 6)
+
+    # -- compute ----------------------------------------------------------
+    def step(self, nsteps=1, allow_notconv=False):
+        st = _lib.StepStats()
+        rc = self._check(self.lib.sim_step(self.h, nsteps, C.byref(st)), allow_notconv)
+        return st, rc
+
+    def solve_schur(self, rhs_p, rhs_f, allow_notconv=False):
+        rp, rf = self._t(rhs_p), self._t(rhs_f)
+        p = torch.empty(self.n, dtype=torch.float64, device=self.dev)
+        phi = torch.empty((max(self.K, 1), 3), dtype=torch.float64, device=self.dev)
+        st = _lib.SolveStats()
+        rc = self._check(self.lib.sim_solve_schur(self.h, _ptr(rp), _ptr(rf), _ptr(p), _ptr(phi),
+                                                  C.byref(st)), allow_notconv)
+        return p, phi[:self.K], st
+
+    def apply(self, op, x, x2=None):
+        opid = _lib.OPS[op]
+        x = self._t(x)
+        x2 = self._t(x2)
+        cells, faces, points = self.n, (3,) + self.n, (max(self.K, 1), 3)
+        out_shape = {"laplacian": cells, "schur": cells, "precond": cells, "grad": faces,
+                     "div": cells, "interp": points, "spread": faces, "helmholtz": faces,
+                     "convection": faces, "helm_solve": faces, "schur_rhs": cells}[op]
+        out = torch.empty(out_shape, dtype=torch.float64, device=self.dev)
+        self._check(self.lib.sim_apply(self.h, opid, _ptr(x), _ptr(x2), _ptr(out)))
+        return out[:self.K] if op == "interp" else out
+
+    def step_adjoint(self, gu=None, gp=None, gphi=None, want_inputs=False):
+        gu = self._t(gu)
+        comps = [gu[d] if gu is not None else None for d in range(3)]
+        gp, gphi = self._t(gp), self._t(gphi)
+        gX = torch.zeros((max(self.K, 1), 3), dtype=torch.float64, device=self.dev)
+        gU = (C.c_double * (3 * max(self.nb, 1)))()
+        outs = [None] * 4
+        if want_inputs:
+            outs = [torch.zeros((3,) + self.n, dtype=torch.float64, device=self.dev),
+                    torch.zeros((3,) + self.n, dtype=torch.float64, device=self.dev),
+                    torch.zeros(self.n, dtype=torch.float64, device=self.dev),
+                    torch.zeros((max(self.K, 1), 3), dtype=torch.float64, device=self.dev)]
+        self._check(self.lib.sim_step_adjoint(self.h, *[_ptr(c) for c in comps], _ptr(gp), _ptr(gphi),
+                                              _ptr(gX), gU, *[_ptr(o) for o in outs]))
+        res = dict(gX=gX[:self.K], gU=np.array(gU[:3 * self.nb]).reshape(self.nb, 3))
+        if want_inputs:
+            res.update(gu=outs[0], gum=outs[1], gp=outs[2], gphi=outs[3][:self.K])
+        return res

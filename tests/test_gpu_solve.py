@@ -1,0 +1,163 @@
+"""Parity of the pressure-force Schur solve (sim_solve_schur) and of one time
+step (sim_step) with the CPU oracle, plus determinism and error paths."""
+import numpy as np
+import pytest
+
+from oracle import bodies as obd
+from oracle import mac as omac
+from oracle import step as ostep
+from paper_2501_15314_amd import workloads as wl
+
+from .conftest import gpu_available
+from .gpu_helpers import mixed_workload, oracle_for, rel, walls_workload
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    from paper_2501_15314_amd.sim import Sim, SimError
+
+
+CASES = {
+    "c1_periodic": lambda: wl.make_c1(n=32, n_points=300),
+    "walls": lambda: walls_workload(32, 260),
+    "mixed": mixed_workload,
+    "c1_48_roma": lambda: _roma(wl.make_c1(n=48, n_points=700)),
+}
+
+
+def _roma(w):
+    w.cfg.delta = wl.DELTA_ROMA3
+    w.cfg.lump_c = wl.lump_constant(wl.DELTA_ROMA3, w.cfg.h, w.n_points, w.bodies[0].radius)
+    return w
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("prec", [wl.PREC_FP64, wl.PREC_FP32MG])
+def test_schur_solve_matches_oracle(case, prec):
+    w = CASES[case]()
+    w.cfg.precision = prec
+    w.cfg.krylov_rtol = 1e-12 if prec == wl.PREC_FP64 else 1e-11
+    print(f"case {case} prec {prec} n={w.cfg.n} K={w.n_points}", flush=True)
+    sim = Sim(w.cfg, w.n_points)
+    sim.set_bodies(w.bodies, w.offsets)
+    g, X, W, S = oracle_for(w)
+    rp, rf = wl.random_schur_rhs(21, g.n, w.n_points)
+    p, phi, st = sim.solve_schur(rp, rf)
+    p_ref, phi_ref, its, _ = S.solve(rp, rf, rtol=1e-13)
+    ep = rel(p.cpu().numpy(), p_ref)
+    ef = rel(phi.cpu().numpy(), phi_ref)
+    print(f"  iters gpu={st.iters} oracle={its} rel_res={st.rel_res:.2e} err p={ep:.2e} phi={ef:.2e}")
+    tol = 1e-10 if prec == wl.PREC_FP64 else 1e-8
+    assert ep < tol and ef < tol
+    assert st.rel_res <= w.cfg.krylov_rtol
+    assert abs(p.cpu().numpy().mean()) < 1e-12 * np.abs(p_ref).max()
+    sim.close()
+
+
+def test_schur_solve_bitwise_repeatable():
+    w = walls_workload(32, 260)
+    w.cfg.precision = wl.PREC_FP32MG
+    w.cfg.krylov_rtol = 1e-10
+    sim = Sim(w.cfg, w.n_points)
+    sim.set_bodies(w.bodies, w.offsets)
+    rp, rf = wl.random_schur_rhs(22, w.cfg.n, w.n_points)
+    p1, f1, _ = sim.solve_schur(rp, rf)
+    p2, f2, _ = sim.solve_schur(rp, rf)
+    assert np.array_equal(p1.cpu().numpy(), p2.cpu().numpy())
+    assert np.array_equal(f1.cpu().numpy(), f2.cpu().numpy())
+    sim.close()
+
+
+def test_notconv_reports_best_iterate():
+    w = wl.make_c1(n=32, n_points=300)
+    w.cfg.krylov_maxit = 1
+    w.cfg.krylov_rtol = 1e-14
+    sim = Sim(w.cfg, w.n_points)
+    sim.set_bodies(w.bodies, w.offsets)
+    rp, rf = wl.random_schur_rhs(23, w.cfg.n, w.n_points)
+    with pytest.raises(SimError) as e:
+        sim.solve_schur(rp, rf)
+    assert "ENOTCONV" in str(e.value)
+    p, phi, st = sim.solve_schur(rp, rf, allow_notconv=True)
+    assert st.iters == 1 and 0 < st.rel_res < 1
+    sim.close()
+
+
+def test_nonfinite_rhs_rejected():
+    w = wl.make_c1(n=32, n_points=300)
+    sim = Sim(w.cfg, w.n_points)
+    sim.set_bodies(w.bodies, w.offsets)
+    rp, rf = wl.random_schur_rhs(24, w.cfg.n, w.n_points)
+    rp[3, 4, 5] = np.nan
+    with pytest.raises(SimError) as e:
+        sim.solve_schur(rp, rf)
+    assert "ENONFINITE" in str(e.value)
+    sim.close()
+
+
+def test_support_crossing_wall_rejected():
+    w = walls_workload(32, 260)
+    w.bodies[0].center = np.array([0.07, 0.5, 0.5])
+    sim = Sim(w.cfg, w.n_points)
+    with pytest.raises(SimError) as e:
+        sim.set_bodies(w.bodies, w.offsets)
+    assert "EINVAL" in str(e.value)
+    sim.close()
+
+
+# ---------------------------------------------------------------------------
+# one-way time step
+
+def _oracle_step(w, state, t1):
+    cfg = w.cfg
+    g, X, W, S = oracle_for(w, t1)
+    U = []
+    for b in w.bodies:
+        v = obd.prescribed_velocity(b.vel, b.osc_amp, b.osc_omega, t1)
+        U.append(np.tile(v, (b.n_points, 1)))
+    U = np.concatenate(U)
+    # rotating bodies: U = v + omega x (R X~)
+    k0 = 0
+    for b in w.bodies:
+        if np.any(b.omega):
+            R = obd.prescribed_rotation(b.omega, t1)
+            lever = w.offsets[k0:k0 + b.n_points] @ R.T
+            U[k0:k0 + b.n_points] = obd.point_velocities(
+                obd.prescribed_velocity(b.vel, b.osc_amp, b.osc_omega, t1), b.omega, lever)
+        k0 += b.n_points
+    return ostep.one_way_step(g, cfg.nu, cfg.dt, state, X, U, cfg.delta, cfg.lump_c, cfg.xi)
+
+
+@pytest.mark.parametrize("case", ["c1_periodic", "walls", "mixed"])
+@pytest.mark.parametrize("prec", [wl.PREC_FP64, wl.PREC_FP32MG])
+def test_one_way_steps_match_oracle(case, prec):
+    w = CASES[case]()
+    cfg = w.cfg
+    cfg.precision = prec
+    cfg.krylov_rtol = 1e-12 if prec == wl.PREC_FP64 else 1e-11
+    cfg.helm_rtol = 1e-12 if prec == wl.PREC_FP64 else 1e-11
+    if case == "walls":
+        rng = np.random.default_rng(5)
+        mask = omac.Grid(cfg.n, cfg.h, cfg.bc).face_dof_mask()
+        w.u0 = rng.standard_normal(w.u0.shape) * 1e-2 * mask
+    print(f"case {case} prec {prec}", flush=True)
+    sim = Sim(cfg, w.n_points)
+    sim.set_workload(w)
+    g = omac.Grid(cfg.n, cfg.h, cfg.bc)
+    mask = g.face_dof_mask()
+    state = ostep.State(w.u0 * mask, w.u0 * mask, np.zeros(g.n), np.zeros((w.n_points, 3)))
+    tol = 1e-9 if prec == wl.PREC_FP64 else 1e-7
+    for n in range(2):
+        st, _ = sim.step(1)
+        t1 = (n + 1) * cfg.dt
+        state, info = _oracle_step(w, state, t1)
+        u, p = sim.get_fields()
+        f, ft = sim.get_forces()
+        eu = rel(u.cpu().numpy(), state.u)
+        ep = rel(p.cpu().numpy() - p.cpu().numpy().mean(), state.p - state.p.mean())
+        ef = rel(f.cpu().numpy(), state.phi * cfg.h ** 3)
+        print(f"  step {n}: helm {st.helm.iters} schur {st.schur.iters} div_rel {st.div_rel:.1e} "
+              f"err u={eu:.2e} p={ep:.2e} phi={ef:.2e}")
+        assert eu < tol and ep < tol and ef < tol
+        assert st.div_rel < 1e-6
+    sim.close()
