@@ -125,6 +125,35 @@ template <int KER> __device__ __forceinline__ int support_start(double x, double
   return KER == KER_PESKIN4 ? (int)floor(s) - 1 : (int)floor(s + 0.5) - 1;
 }
 
+// All weights of a point along one axis from one square root.  With
+// s = x/h - offset (offset 0 for face nodes, 1/2 for centre nodes):
+//   4-point: nodes floor(s)-1 .. floor(s)+2, f = s - floor(s),
+//            q = sqrt(1 + 4f - 4f^2) (the same radicand for all four nodes),
+//            w = ((3-2f-q)/8, (3-2f+q)/8, (1+2f+q)/8, (1+2f-q)/8);
+//   3-point: nodes round(s)-1 .. round(s)+1, f = s - round(s),
+//            q = sqrt(1 - 3f^2), w = ((2-3f-q)/6, (1+q)/3, (2+3f-q)/6, 0).
+template <int KER>
+__device__ __forceinline__ int axis_weights(double x, double inv_h, bool face, double w[4]) {
+  double s = x * inv_h - (face ? 0.0 : 0.5);
+  if (KER == KER_PESKIN4) {
+    double fl = floor(s), f = s - fl;
+    double q = sqrt(fmax(0.0, 1.0 + 4.0 * f - 4.0 * f * f));
+    w[0] = (3.0 - 2.0 * f - q) * 0.125;
+    w[1] = (3.0 - 2.0 * f + q) * 0.125;
+    w[2] = (1.0 + 2.0 * f + q) * 0.125;
+    w[3] = (1.0 + 2.0 * f - q) * 0.125;
+    return (int)fl - 1;
+  } else {
+    double rd = floor(s + 0.5), f = s - rd;
+    double q = sqrt(fmax(0.0, 1.0 - 3.0 * f * f));
+    w[0] = (2.0 - 3.0 * f - q) * (1.0 / 6.0);
+    w[1] = (1.0 + q) * (1.0 / 3.0);
+    w[2] = (2.0 + 3.0 * f - q) * (1.0 / 6.0);
+    w[3] = 0.0;
+    return (int)rd - 1;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Deterministic reductions: fixed butterfly order within a wavefront.
 __device__ __forceinline__ double wave_sum(double v) {

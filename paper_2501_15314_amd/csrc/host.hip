@@ -30,6 +30,7 @@ namespace {
 
 constexpr int MAX_BODIES = 4096;
 constexpr int MAX_RESTART = 64;
+constexpr double FP32_CYCLE_DROP = 1e-6;
 
 struct HostBody {
   sim_body b;
@@ -78,7 +79,13 @@ struct sim_s {
          *PT3 = nullptr;
   int *COUNTS = nullptr, *TSTART = nullptr, *FILLC = nullptr, *FLAGS = nullptr, *FPOS = nullptr,
       *ACTIVE = nullptr, *SCANTMP = nullptr;
+  int *TCOUNT = nullptr, *TLSTART = nullptr, *TFILL = nullptr, *TLTMP = nullptr, *TLIST = nullptr,
+      *SEGOF = nullptr;
+  long long tl_cap = 0;  // capacity of the touch lists
+  int *NZT = nullptr;    // non-empty point tiles
+  int nnz = 0;
   int nactive = 0;
+  int ntouch = 0;
   BodyDev *BODIES = nullptr;
   std::vector<HostBody> bodies;
   // reductions
@@ -197,6 +204,10 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
   int *COUNTS = cv.arr<int>(nt), *TSTART = cv.arr<int>(nt + 1), *FILLC = cv.arr<int>(nt);
   int *FLAGS = cv.arr<int>(nt), *FPOS = cv.arr<int>(nt + 1), *ACTIVE = cv.arr<int>(nt);
   int *SCANTMP = cv.arr<int>(nt / 1024 + 16);
+  long long tl_cap = 27 * K;  // a point touches at most 3 x 3 x 3 tiles
+  int *TCOUNT = cv.arr<int>(nt), *TLSTART = cv.arr<int>(nt + 1), *TFILL = cv.arr<int>(nt);
+  int *TLTMP = cv.arr<int>(tl_cap), *TLIST = cv.arr<int>(tl_cap), *SEGOF = cv.arr<int>(tl_cap);
+  int *NZT = cv.arr<int>(nt);
   BodyDev *BODIES = (BodyDev *)cv.take(sizeof(BodyDev) * MAX_BODIES);
   int rb = std::max(red_blocks(), 1);
   long long parts = std::max<long long>((long long)rb * (MAX_RESTART + 2), 0);
@@ -215,6 +226,8 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
     s->XS = XS; s->US = US; s->Q = Q; s->RF = RF; s->PHIP = PHIP; s->PHIS = PHIS; s->PT3 = PT3;
     s->COUNTS = COUNTS; s->TSTART = TSTART; s->FILLC = FILLC; s->FLAGS = FLAGS; s->FPOS = FPOS;
     s->ACTIVE = ACTIVE; s->SCANTMP = SCANTMP; s->BODIES = BODIES;
+    s->TCOUNT = TCOUNT; s->TLSTART = TLSTART; s->TFILL = TFILL; s->TLTMP = TLTMP; s->TLIST = TLIST;
+    s->SEGOF = SEGOF; s->tl_cap = tl_cap; s->NZT = NZT;
     s->PART = PART; s->RED = RED; s->YDEV = YDEV;
   }
   return cv.off + 256;
@@ -316,13 +329,33 @@ sim_status place_and_bin(sim_t s, const std::vector<BodyDev> &bd) {
   CKH(bin_canon(s->K, s->TILE, s->TSTART, s->PERMTMP, s->PERM, st));
   CKH(gather3(s->K, s->PERM, s->XN, s->XS, st));
   CKH(gather3(s->K, s->PERM, s->UN, s->US, st));
-  CKH(active_flags(s->nt0, s->nt1, s->nt2, s->cfg.bc[0], s->cfg.bc[1], s->cfg.bc[2], s->COUNTS, s->FLAGS, st));
+  // non-empty point tiles (interpolation work list)
+  CKH(positive_flags(nt, s->COUNTS, s->FLAGS, st));
   CKH(scan_exclusive(s->FLAGS, s->FPOS, nt, s->SCANTMP, st));
-  CKH(compact(nt, s->FLAGS, s->FPOS, s->ACTIVE, st));
-  int na = 0;
+  CKH(compact(nt, s->FLAGS, s->FPOS, s->NZT, st));
+  int nz = 0;
   CKH(hipMemcpyAsync(s->hpin, s->FPOS + nt, sizeof(int), hipMemcpyDeviceToHost, st));
   CKH(hipStreamSynchronize(st));
+  memcpy(&nz, s->hpin, sizeof(int));
+  s->nnz = nz;
+  // touch lists of the active tiles (tiles reached by some point's support)
+  CKH(fill_i32(s->TCOUNT, nt, 0, st));
+  CKH(fill_i32(s->TFILL, nt, 0, st));
+  CKH(touch_count(s->ker, s->g, s->K, s->XS, s->nt0, s->nt1, s->nt2, s->TCOUNT, st));
+  CKH(scan_exclusive(s->TCOUNT, s->TLSTART, nt, s->SCANTMP, st));
+  CKH(touch_scatter(s->ker, s->g, s->K, s->XS, s->nt0, s->nt1, s->nt2, s->TLSTART, s->TFILL, s->TLTMP, st));
+  CKH(positive_flags(nt, s->TCOUNT, s->FLAGS, st));
+  CKH(scan_exclusive(s->FLAGS, s->FPOS, nt, s->SCANTMP, st));
+  CKH(compact(nt, s->FLAGS, s->FPOS, s->ACTIVE, st));
+  int na = 0, M = 0;
+  CKH(hipMemcpyAsync(s->hpin, s->FPOS + nt, sizeof(int), hipMemcpyDeviceToHost, st));
+  CKH(hipMemcpyAsync((int *)s->hpin + 1, s->TLSTART + nt, sizeof(int), hipMemcpyDeviceToHost, st));
+  CKH(hipStreamSynchronize(st));
   memcpy(&na, s->hpin, sizeof(int));
+  memcpy(&M, (int *)s->hpin + 1, sizeof(int));
+  if (M > s->tl_cap) return fail(s, SIM_EDEVICE, "touch list overflow");
+  CKH(seg_sort(M, na, s->ACTIVE, s->TLSTART, s->TLTMP, s->SEGOF, s->TLIST, st));
+  s->ntouch = M;
   s->nactive = na;
   return SIM_OK;
 }
@@ -350,8 +383,8 @@ std::vector<BodyDev> body_states_at(sim_t s, double t) {
 template <typename T>
 sim_status schur_matvec(sim_t s, const T *z, double *w) {
   CKH(lap_apply<T>(s->g, z, w, s->st));
-  CKH(interp_grad<T>(s->ker, s->g, s->K, s->XS, z, 1.0, nullptr, 0.0, s->Q, s->st));
-  CKH(band_apply(s->ker, true, s->g, s->nt0, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TSTART, s->XS, s->Q,
+  CKH(interp_grad<T>(s->ker, s->g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, z, 1.0, nullptr, 0.0, s->Q, s->st));
+  CKH(band_apply(s->ker, true, s->g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, s->Q,
                  -1.0 / s->c, w, s->st));
   return SIM_OK;
 }
@@ -364,7 +397,7 @@ sim_status vcycle(sim_t s, const double *v, T *z) {
   int nl = (int)s->lv.size();
   int cyc = c.mg_coarse_sweeps;
   if (nl == 1) {
-    CKH((mg_coarse<T, double>(s->lv[0].g, v, z, cyc, 2, st)));
+    CKH((mg_coarse<T, double>(s->lv[0].g, v, z, cyc, 1, st)));
     return SIM_OK;
   }
   // descend
@@ -385,7 +418,7 @@ sim_status vcycle(sim_t s, const double *v, T *z) {
         CKH((mg_smooth<T, T>(g, x, b, 1, st)));
       }
     }
-    if (l + 1 < nl - 1 || true) {
+    {
       T *bnext = (T *)s->lv[l + 1].b;
       if (l == 0)
         CKH((mg_restrict<T, double>(g, x, v, s->lv[1].g, bnext, st)));
@@ -394,7 +427,7 @@ sim_status vcycle(sim_t s, const double *v, T *z) {
     }
   }
   // coarse grid
-  CKH((mg_coarse<T, T>(s->lv[nl - 1].g, (const T *)s->lv[nl - 1].b, (T *)s->lv[nl - 1].x, cyc, 2, st)));
+  CKH((mg_coarse<T, T>(s->lv[nl - 1].g, (const T *)s->lv[nl - 1].b, (T *)s->lv[nl - 1].x, cyc, 1, st)));
   // ascend
   for (int l = nl - 2; l >= 0; --l) {
     const Geo &g = s->lv[l].g;
@@ -482,6 +515,9 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
       double est = fabs(gv[j + 1]) / bnorm;
       if (S.nhist < 64) S.hist[S.nhist++] = est;
       if (est <= c.krylov_rtol || total >= c.krylov_maxit || hn == 0.0) break;
+      // FP32 preconditioner: restart from the FP64 true residual before the
+      // cycle reaches the float32 accuracy floor of its directions
+      if (s->fp32 && fabs(gv[j + 1]) <= FP32_CYCLE_DROP * beta) break;
     }
     // y = H^-1 g (upper triangular)
     for (int i = jd - 1; i >= 0; --i) {
@@ -516,7 +552,7 @@ sim_status fgmres_any(sim_t s, const double *b, double *x, sim_solve_stats *stt)
 // b = RHSP + c^-1 D W RF, projected to mean zero (into BVEC)
 sim_status schur_rhs(sim_t s) {
   CKH(scale_copy(s->BVEC, s->RHSP, s->N, 1.0, s->st));
-  CKH(band_apply(s->ker, true, s->g, s->nt0, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TSTART, s->XS, s->RF,
+  CKH(band_apply(s->ker, true, s->g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, s->RF,
                  1.0 / s->c, s->BVEC, s->st));
   return project_mean(s, s->BVEC);
 }
@@ -532,7 +568,7 @@ sim_status schur_solve_core(sim_t s, sim_solve_stats *stt) {
   sim_status solve_rc = fgmres_any(s, s->BVEC, s->PP, stt);
   if (solve_rc != SIM_OK && solve_rc != SIM_ENOTCONV) return solve_rc;
   // Phi' = c^-1 (B p' - RHS_F) = -c^-1 (W^T G p' + RHS_F)
-  CKH(interp_grad<double>(s->ker, s->g, s->K, s->XS, s->PP, -1.0 / s->c, s->RF, -1.0 / s->c, s->PHIP, s->st));
+  CKH(interp_grad<double>(s->ker, s->g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, s->PP, -1.0 / s->c, s->RF, -1.0 / s->c, s->PHIP, s->st));
   CKH(hipEventRecord(e1, s->st));
   CKH(hipEventSynchronize(e1));
   float ms = 0;
@@ -632,7 +668,7 @@ sim_status step_one_way(sim_t s, sim_step_stats *out) {
   CKH(gather3(s->K, s->PERM, s->PHIN, s->PHIS, st));
   // momentum right-hand side, W Phi^n added on the band
   CKH(mom_rhs(s->g, c.dt, s->U, s->UM, s->P, s->RHSU, st));
-  CKH(band_apply(s->ker, false, s->g, s->nt0, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TSTART, s->XS, s->PHIS, 1.0,
+  CKH(band_apply(s->ker, false, s->g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, s->PHIS, 1.0,
                  s->RHSU, st));
   // u* from the extrapolated guess 2 u^n - u^{n-1}
   CKH(scale_copy(s->USTAR, s->U, n3, 2.0, st));
@@ -650,13 +686,13 @@ sim_status step_one_way(sim_t s, sim_step_stats *out) {
       if ((rc = dev_norm2(s, s->RHSP, N, &d2))) return rc;
       divstar = sqrt(d2) * tau;
     }
-    CKH(interp_face(s->ker, s->g, s->K, s->XS, s->USTAR, 1.0 / tau, s->US, -1.0 / tau, s->RF, st));
+    CKH(interp_face(s->ker, s->g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, s->USTAR, 1.0 / tau, s->US, -1.0 / tau, s->RF, st));
     src = schur_solve_core(s, &S.schur);
     if (src != SIM_OK && src != SIM_ENOTCONV) return src;
     S.total_schur_iters += S.schur.iters;
     // u <- u* + xi tau (-G p' + W Phi') ; p += xi p' ; Phi += xi Phi'
     CKH(grad_apply(s->g, s->PP, s->USTAR, -c.xi * tau, s->USTAR, st));
-    CKH(band_apply(s->ker, false, s->g, s->nt0, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TSTART, s->XS, s->PHIP,
+    CKH(band_apply(s->ker, false, s->g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, s->PHIP,
                    c.xi * tau, s->USTAR, st));
     CKH(axpby(s->P, s->PP, N, c.xi, 1.0, st));
     CKH(scale3(s->K, s->PHIP, c.xi, s->PHIS, 1.0, s->PHIS, st));
@@ -681,7 +717,7 @@ sim_status step_one_way(sim_t s, sim_step_stats *out) {
   double dn2;
   if ((rc = dev_norm2(s, s->TMPC, N, &dn2))) return rc;
   S.div_rel = divstar > 0 ? sqrt(dn2) / divstar : 0.0;
-  CKH(interp_face(s->ker, s->g, s->K, s->XS, s->USTAR, 1.0, s->US, -1.0, s->PT3, st));
+  CKH(interp_face(s->ker, s->g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, s->USTAR, 1.0, s->US, -1.0, s->PT3, st));
   if (s->K > 0) {
     double sl2, u2;
     if ((rc = dev_norm2(s, s->PT3, 3LL * s->K, &sl2))) return rc;
@@ -978,13 +1014,13 @@ sim_status sim_apply(sim_t s, int32_t op, const double *in, const double *in2, d
     case SIM_OP_INTERP:
       CKH(to_split(g, 3, in, s->TMP3, st));
       CKH(zero_wall_faces(g, s->TMP3, st));
-      CKH(interp_face(s->ker, g, s->K, s->XS, s->TMP3, 1.0, nullptr, 0.0, s->Q, st));
+      CKH(interp_face(s->ker, g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, s->TMP3, 1.0, nullptr, 0.0, s->Q, st));
       CKH(scatter3(s->K, s->PERM, s->Q, out, st));
       break;
     case SIM_OP_SPREAD:
       CKH(gather3(s->K, s->PERM, in, s->Q, st));
       CKH(fill(s->TMP3, 3 * N, 0.0, st));
-      CKH(band_apply(s->ker, false, g, s->nt0, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TSTART, s->XS, s->Q, 1.0,
+      CKH(band_apply(s->ker, false, g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, s->Q, 1.0,
                      s->TMP3, st));
       CKH(to_natural(g, 3, s->TMP3, out, st));
       break;

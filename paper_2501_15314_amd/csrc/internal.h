@@ -83,26 +83,36 @@ hipError_t bin_scatter(int K, const int *tile, const int *start, int *fillc, int
                        hipStream_t s);
 hipError_t bin_canon(int K, const int *tile, const int *start, const int *perm_tmp, int *perm,
                      hipStream_t s);
-hipError_t active_flags(int nt0, int nt1, int nt2, int bc0, int bc1, int bc2, const int *counts,
-                        int *flags, hipStream_t s);
 hipError_t compact(int n, const int *flags, const int *pos, int *list, hipStream_t s);
 hipError_t gather3(int K, const int *perm, const double *src, double *dst, hipStream_t s);
 hipError_t scatter3(int K, const int *perm, const double *src, double *dst, hipStream_t s);
 hipError_t scale3(int K, const double *x, double alpha, const double *y, double beta, double *out,
                   hipStream_t s);  // out = alpha x + beta y (y may be null)
 
-// interp: out[p][d] = alpha * (W^T src)[p][d] + beta * y[p][d]; src is a face
-// field (double) when GRAD is false, otherwise the gradient of a cell field.
+// interp: out[p][d] = alpha * (W^T src)[p][d] + beta * y[p][d] for the points
+// of the ntiles_nz non-empty tiles listed in tiles (points sorted by tile,
+// tstart = tile offsets); src is a face field (interp_face) or the gradient
+// of a cell field (interp_grad).
 template <typename T>
-hipError_t interp_grad(int ker, const Geo &g, int K, const double *X, const T *z, double alpha,
-                       const double *y, double beta, double *out, hipStream_t s);
-hipError_t interp_face(int ker, const Geo &g, int K, const double *X, const double *u3, double alpha,
-                       const double *y, double beta, double *out, hipStream_t s);
-// band: for the active tiles, outc += alpha D (W q)   (div = true)
-//                          or outf += alpha W q       (div = false)
-hipError_t band_apply(int ker, bool div, const Geo &g, int nt0, int nt1, int nt2, int nactive,
-                      const int *active, const int *tstart, const double *X, const double *q,
-                      double alpha, double *out, hipStream_t s);
+hipError_t interp_grad(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, const int *tiles,
+                       const int *tstart, const double *X, const T *z, double alpha, const double *y,
+                       double beta, double *out, hipStream_t s);
+hipError_t interp_face(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, const int *tiles,
+                       const int *tstart, const double *X, const double *u3, double alpha, const double *y,
+                       double beta, double *out, hipStream_t s);
+// touch lists: tiles whose face boxes a point's support meets
+hipError_t touch_count(int ker, const Geo &g, int K, const double *X, int nt0, int nt1, int nt2, int *counts,
+                       hipStream_t s);
+hipError_t touch_scatter(int ker, const Geo &g, int K, const double *X, int nt0, int nt1, int nt2,
+                         const int *start, int *fillc, int *list, hipStream_t s);
+hipError_t seg_sort(int M, int nactive, const int *active, const int *start, const int *tmp, int *seg_of,
+                    int *out, hipStream_t s);
+hipError_t positive_flags(int n, const int *counts, int *flags, hipStream_t s);
+// band: for the active tiles, out += alpha D (W q)   (div = true, cell field)
+//                          or out += alpha W q       (div = false, face field)
+hipError_t band_apply(int ker, bool div, const Geo &g, int nt1, int nt2, int nactive, const int *active,
+                      const int *lstart, const int *list, const double *X, const double *q, double alpha,
+                      double *out, hipStream_t s);
 
 // ---- reductions / Krylov vector kernels (kernels_krylov.hip) ---------------
 int red_blocks();

@@ -150,36 +150,6 @@ hipError_t bin_canon(int K, const int *tile, const int *start, const int *perm_t
   return hipGetLastError();
 }
 
-// A tile is active when it or one of its 26 neighbours holds points: only
-// those tiles can receive spread values.
-__global__ void k_active(int nt0, int nt1, int nt2, int bc0, int bc1, int bc2, const int *counts, int *flags) {
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  long long nt = (long long)nt0 * nt1 * nt2;
-  if (t >= nt) return;
-  int t2 = (int)(t % nt2), r = (int)(t / nt2), t1 = r % nt1, t0 = r / nt1;
-  int f = 0;
-  for (int a = -1; a <= 1 && !f; ++a) {
-    int u0 = nbr(t0, a, nt0, bc0);
-    if (u0 < 0) continue;
-    for (int b = -1; b <= 1 && !f; ++b) {
-      int u1 = nbr(t1, b, nt1, bc1);
-      if (u1 < 0) continue;
-      for (int c = -1; c <= 1; ++c) {
-        int u2 = nbr(t2, c, nt2, bc2);
-        if (u2 < 0) continue;
-        if (counts[((long long)u0 * nt1 + u1) * nt2 + u2] > 0) { f = 1; break; }
-      }
-    }
-  }
-  flags[t] = f;
-}
-hipError_t active_flags(int nt0, int nt1, int nt2, int bc0, int bc1, int bc2, const int *counts, int *flags,
-                        hipStream_t s) {
-  long long nt = (long long)nt0 * nt1 * nt2;
-  hipLaunchKernelGGL(k_active, dim3(nblk(nt, 256)), dim3(256), 0, s, nt0, nt1, nt2, bc0, bc1, bc2, counts,
-                     flags);
-  return hipGetLastError();
-}
 __global__ void k_compact(int n, const int *flags, const int *pos, int *list) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n && flags[t]) list[pos[t]] = t;
@@ -224,184 +194,366 @@ hipError_t scale3(int K, const double *x, double alpha, const double *y, double 
 }
 
 // ---------------------------------------------------------------------------
-// Interpolation.  16 lanes per point (node offsets (a, b) of the x-y
-// support), each summing the z nodes in order; the 16 partial sums are then
-// reduced by a fixed butterfly.  MODE 0: face field u3; MODE 1: G z of a cell
-// field z, (G z)_d(idx) = (z(idx) - z(idx - e_d)) / h.
+// Interpolation, one workgroup per non-empty point tile.  The points of tile
+// T (cells 4T..4T+3 per axis) only reach nodes 4T-2 .. 4T+5 per axis, so the
+// workgroup first stages that 8^3 region of the source in LDS (MODE 0: the
+// three face fields; MODE 1: the cell field, whose face gradients are formed
+// from LDS) together with the 1-D weights of its points (face and centre
+// nodes per axis), then gathers every point's stencil from LDS: 16 lanes per
+// point (node offsets (a, b)), z nodes summed in order, the 16 partial sums
+// reduced by a fixed butterfly.
+constexpr int IREG = 8;   // region width per axis
+constexpr int IPTS = 64;  // points staged per pass
+
 template <int KER, int MODE, typename T>
-__global__ void __launch_bounds__(256) k_interp(Geo g, int K, const double *X, const T *src, double alpha,
-                                                const double *y, double beta, double *out) {
+__global__ void __launch_bounds__(256) k_interp(Geo g, int nt1, int nt2, const int *tiles, const int *tstart,
+                                                const double *X, const T *src, double alpha, const double *y,
+                                                double beta, double *out) {
   constexpr int W = KerWidth<KER>::W;
-  int lane = threadIdx.x & 15;
-  int pnt = blockIdx.x * 16 + (threadIdx.x >> 4);
-  bool active = pnt < K;
-  int ta = lane >> 2, tb = lane & 3;
-  double xp0 = 0, xp1 = 0, xp2 = 0;
-  if (active) { xp0 = X[3 * pnt]; xp1 = X[3 * pnt + 1]; xp2 = X[3 * pnt + 2]; }
-  double ih = 1.0 / g.h;
-  long long N = 2 * g.half;
-  for (int d = 0; d < 3; ++d) {
-    double acc = 0.0;
-    if (active && ta < W && tb < W) {
-      double s0, s1, s2;
-      int i0 = support_start<KER>(xp0, ih, d == 0, s0);
-      int j0 = support_start<KER>(xp1, ih, d == 1, s1);
-      int k0 = support_start<KER>(xp2, ih, d == 2, s2);
-      int i = i0 + ta, j = j0 + tb;
-      bool ok = true;
-      if (g.bc0) ok = ok && i >= 0 && i < g.n0; else i = wrapi(i, g.n0);
-      if (g.bc1) ok = ok && j >= 0 && j < g.n1; else j = wrapi(j, g.n1);
-      double wab = phi<KER>(s0 - (double)(i0 + ta)) * phi<KER>(s1 - (double)(j0 + tb));
-      if (ok) {
-        for (int c = 0; c < W; ++c) {
-          int k = k0 + c;
-          if (g.bc2) { if (k < 0 || k >= g.n2) continue; } else k = wrapi(k, g.n2);
-          double wgt = wab * phi<KER>(s2 - (double)(k0 + c));
-          double v = 0.0;
-          if (MODE == 0) {
-            v = (double)src[d * N + sidx(g, i, j, k)];
-          } else {
-            int im = i - (d == 0), jm = j - (d == 1), km = k - (d == 2);
-            int bcd = geo_bc(g, d), nd = geo_n(g, d);
-            int xm = d == 0 ? im : (d == 1 ? jm : km);
-            bool wall_face = xm < 0 && bcd;  // the wall face carries no gradient
-            if (xm < 0 && !bcd) {
-              if (d == 0) im += nd; else if (d == 1) jm += nd; else km += nd;
+  constexpr int NC = MODE == 0 ? 3 : 1;
+  __shared__ double reg[NC][IREG * IREG * IREG];
+  __shared__ double pw[IPTS][3][2][4];   // [point][axis][face/centre][node]
+  __shared__ int pb[IPTS][3][2];         // local start of the support
+  const int tile = tiles[blockIdx.x];
+  const int T2 = tile % nt2, r = tile / nt2, T1 = r % nt1, T0 = r / nt1;
+  const int o0 = 4 * T0 - 2, o1 = 4 * T1 - 2, o2 = 4 * T2 - 2;  // region origin
+  const long long N = 2 * g.half;
+  for (int e = threadIdx.x; e < NC * IREG * IREG * IREG; e += 256) {
+    int comp = e / (IREG * IREG * IREG), l = e % (IREG * IREG * IREG);
+    int li = l / (IREG * IREG), lj = (l / IREG) % IREG, lk = l % IREG;
+    int i = o0 + li, j = o1 + lj, k = o2 + lk;
+    bool ok = true;
+    if (g.bc0) ok = ok && i >= 0 && i < g.n0; else i = wrapi(i, g.n0);
+    if (g.bc1) ok = ok && j >= 0 && j < g.n1; else j = wrapi(j, g.n1);
+    if (g.bc2) ok = ok && k >= 0 && k < g.n2; else k = wrapi(k, g.n2);
+    reg[comp][l] = ok ? (double)src[comp * N + sidx(g, i, j, k)] : 0.0;
+  }
+  const int s0 = tstart[tile], s1 = tstart[tile + 1];
+  const int lane = threadIdx.x & 15, ta = lane >> 2, tb = lane & 3;
+  const double ih = 1.0 / g.h;
+  const int org[3] = {o0, o1, o2};
+  const int nn[3] = {g.n0, g.n1, g.n2};
+  const int bcs[3] = {g.bc0, g.bc1, g.bc2};
+  for (int c0 = s0; c0 < s1; c0 += IPTS) {
+    const int np = min(IPTS, s1 - c0);
+    __syncthreads();
+    // stage weights: one task per (point, axis, staggering)
+    for (int task = threadIdx.x; task < np * 6; task += 256) {
+      int pt = task / 6, rem = task - 6 * pt, ax = rem >> 1, st = rem & 1;
+      double wv[4];
+      int i0 = axis_weights<KER>(X[3 * (c0 + pt) + ax], ih, st == 0, wv);
+      int l0 = i0 - org[ax];
+      if (!bcs[ax]) l0 = wrapi(l0 + nn[ax] / 2, nn[ax]) - nn[ax] / 2;
+      pb[pt][ax][st] = l0;
+      // a wall face (index 0 along a no-slip axis) carries no gradient: zero its weight
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        pw[pt][ax][st][t] = (MODE == 1 && st == 0 && bcs[ax] && i0 + t == 0) ? 0.0 : wv[t];
+    }
+    __syncthreads();
+    for (int pb0 = 0; pb0 < np; pb0 += 16) {
+      int pt = pb0 + (threadIdx.x >> 4);
+      bool active = pt < np;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double acc = 0.0;
+        if (active && ta < W && tb < W) {
+          const int sx = d == 0 ? 0 : 1, sy = d == 1 ? 0 : 1, sz = d == 2 ? 0 : 1;
+          int li = pb[pt][0][sx] + ta, lj = pb[pt][1][sy] + tb, lk0 = pb[pt][2][sz];
+          double wab = pw[pt][0][sx][ta] * pw[pt][1][sy][tb];
+#pragma unroll
+          for (int c = 0; c < W; ++c) {
+            int lk = lk0 + c;
+            double v = 0.0;
+            bool in = (unsigned)li < IREG && (unsigned)lj < IREG && (unsigned)lk < IREG;
+            if (MODE == 0) {
+              if (in) v = reg[d][(li * IREG + lj) * IREG + lk];
+            } else {
+              int mi = li - (d == 0), mj = lj - (d == 1), mk = lk - (d == 2);
+              bool inm = (unsigned)mi < IREG && (unsigned)mj < IREG && (unsigned)mk < IREG;
+              if (in && inm) v = (reg[0][(li * IREG + lj) * IREG + lk] - reg[0][(mi * IREG + mj) * IREG + mk]) * ih;
             }
-            if (!wall_face)
-              v = ((double)src[sidx(g, i, j, k)] - (double)src[sidx(g, im, jm, km)]) * ih;
+            acc += (wab * pw[pt][2][sz][c]) * v;
           }
-          acc += wgt * v;
+        }
+        acc = sum16(acc);
+        if (active && lane == 0) {
+          long long o = 3LL * (c0 + pt) + d;
+          out[o] = alpha * acc + (y ? beta * y[o] : 0.0);
         }
       }
     }
-    acc = sum16(acc);
-    if (active && lane == 0) out[3 * pnt + d] = alpha * acc + (y ? beta * y[3 * pnt + d] : 0.0);
   }
 }
 
 template <typename T>
-hipError_t interp_grad(int ker, const Geo &g, int K, const double *X, const T *z, double alpha, const double *y,
-                       double beta, double *out, hipStream_t s) {
-  if (K == 0) return hipSuccess;
-  dim3 gr(nblk(K, 16)), bl(256);
+hipError_t interp_grad(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, const int *tiles, const int *tstart,
+                       const double *X, const T *z, double alpha, const double *y, double beta, double *out,
+                       hipStream_t s) {
+  if (ntiles_nz == 0) return hipSuccess;
+  dim3 gr(ntiles_nz), bl(256);
   if (ker == KER_PESKIN4)
-    hipLaunchKernelGGL((k_interp<KER_PESKIN4, 1, T>), gr, bl, 0, s, g, K, X, z, alpha, y, beta, out);
+    hipLaunchKernelGGL((k_interp<KER_PESKIN4, 1, T>), gr, bl, 0, s, g, nt1, nt2, tiles, tstart, X, z, alpha, y,
+                       beta, out);
   else
-    hipLaunchKernelGGL((k_interp<KER_ROMA3, 1, T>), gr, bl, 0, s, g, K, X, z, alpha, y, beta, out);
+    hipLaunchKernelGGL((k_interp<KER_ROMA3, 1, T>), gr, bl, 0, s, g, nt1, nt2, tiles, tstart, X, z, alpha, y,
+                       beta, out);
   return hipGetLastError();
 }
-template hipError_t interp_grad<float>(int, const Geo &, int, const double *, const float *, double,
-                                       const double *, double, double *, hipStream_t);
-template hipError_t interp_grad<double>(int, const Geo &, int, const double *, const double *, double,
-                                        const double *, double, double *, hipStream_t);
+template hipError_t interp_grad<float>(int, const Geo &, int, int, int, const int *, const int *, const double *,
+                                       const float *, double, const double *, double, double *, hipStream_t);
+template hipError_t interp_grad<double>(int, const Geo &, int, int, int, const int *, const int *, const double *,
+                                        const double *, double, const double *, double, double *, hipStream_t);
 
-hipError_t interp_face(int ker, const Geo &g, int K, const double *X, const double *u3, double alpha,
-                       const double *y, double beta, double *out, hipStream_t s) {
-  if (K == 0) return hipSuccess;
-  dim3 gr(nblk(K, 16)), bl(256);
+hipError_t interp_face(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, const int *tiles, const int *tstart,
+                       const double *X, const double *u3, double alpha, const double *y, double beta, double *out,
+                       hipStream_t s) {
+  if (ntiles_nz == 0) return hipSuccess;
+  dim3 gr(ntiles_nz), bl(256);
   if (ker == KER_PESKIN4)
-    hipLaunchKernelGGL((k_interp<KER_PESKIN4, 0, double>), gr, bl, 0, s, g, K, X, u3, alpha, y, beta, out);
+    hipLaunchKernelGGL((k_interp<KER_PESKIN4, 0, double>), gr, bl, 0, s, g, nt1, nt2, tiles, tstart, X, u3, alpha,
+                       y, beta, out);
   else
-    hipLaunchKernelGGL((k_interp<KER_ROMA3, 0, double>), gr, bl, 0, s, g, K, X, u3, alpha, y, beta, out);
+    hipLaunchKernelGGL((k_interp<KER_ROMA3, 0, double>), gr, bl, 0, s, g, nt1, nt2, tiles, tstart, X, u3, alpha, y,
+                       beta, out);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Spreading on one active tile.  Local face box of component d: 4 cells per
-// axis plus the upper face along d (5 x 4 x 4 with the 5 along d).
-template <int KER, bool DIV>
-__global__ void __launch_bounds__(256) k_band(Geo g, int nt0, int nt1, int nt2, const int *active,
-                                              const int *tstart, const double *X, const double *q,
-                                              double alpha, double *out) {
+// Touch lists.  Tile T owns the cells 4T..4T+3 per axis; for velocity
+// component d its face box also holds the upper face 4T+4 along d (needed by
+// the divergence of its last cell).  A point touches T when its support meets
+// that box for some component.  Lists are built once per placement: count,
+// scan, scatter, then sort each list by sorted-point index.
+
+// Range of tiles touched along one axis (union over the components).
+template <int KER>
+__device__ __forceinline__ void touch_range(double x, double ih, int &lo, int &hi) {
   constexpr int W = KerWidth<KER>::W;
-  __shared__ double acc[3][80];
-  int tile = active[blockIdx.x];
-  int T2 = tile % nt2, r = tile / nt2, T1 = r % nt1, T0 = r / nt1;
-  for (int t = threadIdx.x; t < 240; t += blockDim.x) (&acc[0][0])[t] = 0.0;
-  __syncthreads();
-  int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double s;
+  int f0 = support_start<KER>(x, ih, true, s);   // face nodes along this axis
+  int c0 = support_start<KER>(x, ih, false, s);  // centre nodes
+  auto fdiv = [](int a) { return a >= 0 ? a / 4 : -((-a + 3) / 4); };
+  lo = min(fdiv(f0 - 1), fdiv(c0));
+  hi = max(fdiv(f0 + W - 1), fdiv(c0 + W - 1));
+}
+
+template <int KER, int PASS>
+__global__ void k_touch(Geo g, int K, const double *X, int nt0, int nt1, int nt2, int *counts, const int *start,
+                        int *fillc, int *list) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= K) return;
   double ih = 1.0 / g.h;
-  if (wave < 3) {
-    const int d = wave;
-    const int bx = 4 + (d == 0), by = 4 + (d == 1), bz = 4 + (d == 2);
-    const int la = lane >> 4, lb = (lane >> 2) & 3, lc = lane & 3;
-    const bool lane_ok = la < W && lb < W && lc < W;
-    for (int a = -1; a <= 1; ++a) {
-      int u0 = nbr(T0, a, nt0, g.bc0);
-      if (u0 < 0) continue;
-      for (int b = -1; b <= 1; ++b) {
-        int u1 = nbr(T1, b, nt1, g.bc1);
-        if (u1 < 0) continue;
-        for (int c = -1; c <= 1; ++c) {
-          int u2 = nbr(T2, c, nt2, g.bc2);
-          if (u2 < 0) continue;
-          int nt = (u0 * nt1 + u1) * nt2 + u2;
-          int s0 = tstart[nt], s1 = tstart[nt + 1];
-          for (int p = s0; p < s1; ++p) {
-            double x0 = X[3 * p], x1 = X[3 * p + 1], x2 = X[3 * p + 2];
-            double f0, f1, f2;
-            int i0 = support_start<KER>(x0, ih, d == 0, f0);
-            int j0 = support_start<KER>(x1, ih, d == 1, f1);
-            int k0 = support_start<KER>(x2, ih, d == 2, f2);
-            // stencil start relative to the tile origin (minimum image on periodic axes)
-            int li0 = i0 - 4 * T0, lj0 = j0 - 4 * T1, lk0 = k0 - 4 * T2;
-            if (!g.bc0) li0 = wrapi(li0 + g.n0 / 2, g.n0) - g.n0 / 2;
-            if (!g.bc1) lj0 = wrapi(lj0 + g.n1 / 2, g.n1) - g.n1 / 2;
-            if (!g.bc2) lk0 = wrapi(lk0 + g.n2 / 2, g.n2) - g.n2 / 2;
-            if (li0 + W <= 0 || li0 >= bx || lj0 + W <= 0 || lj0 >= by || lk0 + W <= 0 || lk0 >= bz) continue;
-            int li = li0 + la, lj = lj0 + lb, lk = lk0 + lc;
-            if (lane_ok && li >= 0 && li < bx && lj >= 0 && lj < by && lk >= 0 && lk < bz) {
-              double w = phi<KER>(f0 - (double)(i0 + la)) * phi<KER>(f1 - (double)(j0 + lb)) *
-                         phi<KER>(f2 - (double)(k0 + lc));
-              acc[d][(li * by + lj) * bz + lk] += w * q[3 * p + d];
-            }
-          }
+  int lo[3], hi[3];
+  touch_range<KER>(X[3 * s], ih, lo[0], hi[0]);
+  touch_range<KER>(X[3 * s + 1], ih, lo[1], hi[1]);
+  touch_range<KER>(X[3 * s + 2], ih, lo[2], hi[2]);
+  const int nt[3] = {nt0, nt1, nt2};
+  const int bc[3] = {g.bc0, g.bc1, g.bc2};
+  for (int a = 0; a < 3; ++a) {
+    if (bc[a]) { lo[a] = max(lo[a], 0); hi[a] = min(hi[a], nt[a] - 1); }
+  }
+  for (int t0 = lo[0]; t0 <= hi[0]; ++t0)
+    for (int t1 = lo[1]; t1 <= hi[1]; ++t1)
+      for (int t2 = lo[2]; t2 <= hi[2]; ++t2) {
+        int u0 = bc[0] ? t0 : wrapi(t0, nt0), u1 = bc[1] ? t1 : wrapi(t1, nt1), u2 = bc[2] ? t2 : wrapi(t2, nt2);
+        int t = (u0 * nt1 + u1) * nt2 + u2;
+        if (PASS == 0) atomicAdd(&counts[t], 1);
+        else list[start[t] + atomicAdd(&fillc[t], 1)] = s;
+      }
+}
+
+hipError_t touch_count(int ker, const Geo &g, int K, const double *X, int nt0, int nt1, int nt2, int *counts,
+                       hipStream_t s) {
+  if (K == 0) return hipSuccess;
+  if (ker == KER_PESKIN4)
+    hipLaunchKernelGGL((k_touch<KER_PESKIN4, 0>), dim3(nblk(K, 256)), dim3(256), 0, s, g, K, X, nt0, nt1, nt2,
+                       counts, nullptr, nullptr, nullptr);
+  else
+    hipLaunchKernelGGL((k_touch<KER_ROMA3, 0>), dim3(nblk(K, 256)), dim3(256), 0, s, g, K, X, nt0, nt1, nt2,
+                       counts, nullptr, nullptr, nullptr);
+  return hipGetLastError();
+}
+hipError_t touch_scatter(int ker, const Geo &g, int K, const double *X, int nt0, int nt1, int nt2,
+                         const int *start, int *fillc, int *list, hipStream_t s) {
+  if (K == 0) return hipSuccess;
+  if (ker == KER_PESKIN4)
+    hipLaunchKernelGGL((k_touch<KER_PESKIN4, 1>), dim3(nblk(K, 256)), dim3(256), 0, s, g, K, X, nt0, nt1, nt2,
+                       nullptr, start, fillc, list);
+  else
+    hipLaunchKernelGGL((k_touch<KER_ROMA3, 1>), dim3(nblk(K, 256)), dim3(256), 0, s, g, K, X, nt0, nt1, nt2,
+                       nullptr, start, fillc, list);
+  return hipGetLastError();
+}
+
+// Sort every list segment ascending (entries are distinct point indices):
+// the rank of an entry is the number of smaller entries in its segment.
+__global__ void k_seg_sort(int M, const int *seg_of_tmp, const int *start, const int *tmp, int *out) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= M) return;
+  int t = seg_of_tmp[q];
+  int v = tmp[q];
+  int s0 = start[t], s1 = start[t + 1];
+  int r = 0;
+  for (int p = s0; p < s1; ++p) r += tmp[p] < v;
+  out[s0 + r] = v;
+}
+// segment id of every list slot (from the active-tile list and the starts)
+__global__ void k_seg_ids(int nactive, const int *active, const int *start, int *seg_of) {
+  int a = blockIdx.x;
+  if (a >= nactive) return;
+  int t = active[a];
+  for (int p = start[t] + threadIdx.x; p < start[t + 1]; p += blockDim.x) seg_of[p] = t;
+}
+hipError_t seg_sort(int M, int nactive, const int *active, const int *start, const int *tmp, int *seg_of,
+                    int *out, hipStream_t s) {
+  if (M == 0 || nactive == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_seg_ids, dim3(nactive), dim3(64), 0, s, nactive, active, start, seg_of);
+  hipLaunchKernelGGL(k_seg_sort, dim3(nblk(M, 256)), dim3(256), 0, s, M, seg_of, start, tmp, out);
+  return hipGetLastError();
+}
+__global__ void k_positive(int n, const int *counts, int *flags) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) flags[t] = counts[t] > 0;
+}
+hipError_t positive_flags(int n, const int *counts, int *flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_positive, dim3(nblk(n, 256)), dim3(256), 0, s, n, counts, flags);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Spreading on one active tile from its touch list.  The workgroup stages up
+// to BAND_CH listed points at a time in LDS: per component the local start of
+// the support (packed in one word) and the three 1-D weight vectors, the
+// first one multiplied by q.  Each thread owns one face of the tile's face
+// boxes (80 per component) and adds the listed points in list order into a
+// register, so every face value is summed in the same order on every run.
+constexpr int BAND_CH = 128;
+
+__device__ __forceinline__ int pack3(int a, int b, int c) {
+  return ((a + 64) & 255) | (((b + 64) & 255) << 8) | (((c + 64) & 255) << 16);
+}
+
+template <int KER, bool DIV>
+__global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int *active, const int *lstart,
+                                              const int *list, const double *X, const double *q, double alpha,
+                                              double *out) {
+  constexpr int W = KerWidth<KER>::W;
+  __shared__ double wts[BAND_CH][3][3][4];  // [cand][comp][axis][node]
+  __shared__ int base[3][BAND_CH];          // packed local starts per component
+  __shared__ double facev[3][80];
+  const int tile = active[blockIdx.x];
+  const int T2 = tile % nt2, r = tile / nt2, T1 = r % nt1, T0 = r / nt1;
+  const int tid = threadIdx.x;
+  const int s0 = lstart[tile], s1 = lstart[tile + 1];
+  const double ih = 1.0 / g.h;
+  const int org[3] = {4 * T0, 4 * T1, 4 * T2};
+  const int nn[3] = {g.n0, g.n1, g.n2};
+  const int bcs[3] = {g.bc0, g.bc1, g.bc2};
+  // the face owned by this thread: component fd, local indices (fi, fj, fk)
+  const int fd = tid < 80 ? 0 : (tid < 160 ? 1 : 2);
+  const int fl = tid - 80 * fd;
+  const int fby = 4 + (fd == 1), fbz = 4 + (fd == 2);
+  const int fi = fl / (fby * fbz), fj = (fl / fbz) % fby, fk = fl % fbz;
+  const int fpack = pack3(fi, fj, fk);
+  const bool owner = tid < 240;
+  double acc = 0.0;
+  for (int c0 = s0; c0 < s1; c0 += BAND_CH) {
+    const int nc = min(BAND_CH, s1 - c0);
+    __syncthreads();
+    if (tid < nc) {
+      int p = list[c0 + tid];
+      double wf[3][4], wc[3][4];
+      int lf[3], lc[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        int f0 = axis_weights<KER>(X[3 * p + a], ih, true, wf[a]);
+        int e0 = axis_weights<KER>(X[3 * p + a], ih, false, wc[a]);
+        int l0 = f0 - org[a], l1 = e0 - org[a];
+        if (!bcs[a]) {
+          l0 = wrapi(l0 + nn[a] / 2, nn[a]) - nn[a] / 2;
+          l1 = wrapi(l1 + nn[a] / 2, nn[a]) - nn[a] / 2;
+        }
+        lf[a] = l0;
+        lc[a] = l1;
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double qd = q[3 * p + d];
+        base[d][tid] = pack3(d == 0 ? lf[0] : lc[0], d == 1 ? lf[1] : lc[1], d == 2 ? lf[2] : lc[2]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          wts[tid][d][0][t] = (d == 0 ? wf[0][t] : wc[0][t]) * qd;
+          wts[tid][d][1][t] = d == 1 ? wf[1][t] : wc[1][t];
+          wts[tid][d][2][t] = d == 2 ? wf[2][t] : wc[2][t];
         }
       }
     }
+    __syncthreads();
+    if (owner) {
+      // local node offset of this face in the support of candidate c, per axis
+      // (byte lanes of fpack - base, each in [0, W) when the face is covered)
+      int c = 0;
+      for (; c + 4 <= nc; c += 4) {
+        int b0 = base[fd][c], b1 = base[fd][c + 1], b2 = base[fd][c + 2], b3 = base[fd][c + 3];
+        int bb[4] = {b0, b1, b2, b3};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          int la = (fpack & 255) - (bb[u] & 255);
+          int lb = ((fpack >> 8) & 255) - ((bb[u] >> 8) & 255);
+          int lc = ((fpack >> 16) & 255) - ((bb[u] >> 16) & 255);
+          if ((unsigned)la < (unsigned)W && (unsigned)lb < (unsigned)W && (unsigned)lc < (unsigned)W)
+            acc += (wts[c + u][fd][0][la] * wts[c + u][fd][1][lb]) * wts[c + u][fd][2][lc];
+        }
+      }
+      for (; c < nc; ++c) {
+        int bb = base[fd][c];
+        int la = (fpack & 255) - (bb & 255);
+        int lb = ((fpack >> 8) & 255) - ((bb >> 8) & 255);
+        int lc = ((fpack >> 16) & 255) - ((bb >> 16) & 255);
+        if ((unsigned)la < (unsigned)W && (unsigned)lb < (unsigned)W && (unsigned)lc < (unsigned)W)
+          acc += (wts[c][fd][0][la] * wts[c][fd][1][lb]) * wts[c][fd][2][lc];
+      }
+    }
   }
-  __syncthreads();
   long long N = 2 * g.half;
   if (DIV) {
-    if (threadIdx.x < 64) {
-      int ci = threadIdx.x >> 4, cj = (threadIdx.x >> 2) & 3, ck = threadIdx.x & 3;
+    if (owner) facev[fd][fl] = acc;
+    __syncthreads();
+    if (tid < 64) {
+      int ci = tid >> 4, cj = (tid >> 2) & 3, ck = tid & 3;
       double dv = 0.0;
-      // component 0: box 5x4x4
-      dv += acc[0][((ci + 1) * 4 + cj) * 4 + ck] - acc[0][(ci * 4 + cj) * 4 + ck];
-      // component 1: box 4x5x4
-      dv += acc[1][(ci * 5 + cj + 1) * 4 + ck] - acc[1][(ci * 5 + cj) * 4 + ck];
-      // component 2: box 4x4x5
-      dv += acc[2][(ci * 4 + cj) * 5 + ck + 1] - acc[2][(ci * 4 + cj) * 5 + ck];
+      dv += facev[0][((ci + 1) * 4 + cj) * 4 + ck] - facev[0][(ci * 4 + cj) * 4 + ck];
+      dv += facev[1][(ci * 5 + cj + 1) * 4 + ck] - facev[1][(ci * 5 + cj) * 4 + ck];
+      dv += facev[2][(ci * 4 + cj) * 5 + ck + 1] - facev[2][(ci * 4 + cj) * 5 + ck];
       int gi = 4 * T0 + ci, gj = 4 * T1 + cj, gk = 4 * T2 + ck;
       out[sidx(g, gi, gj, gk)] += alpha * dv * ih;
     }
   } else {
-    if (threadIdx.x < 192) {
-      int d = threadIdx.x >> 6, t = threadIdx.x & 63;
-      int ci = t >> 4, cj = (t >> 2) & 3, ck = t & 3;
-      int by = 4 + (d == 1), bz = 4 + (d == 2);
-      int gi = 4 * T0 + ci, gj = 4 * T1 + cj, gk = 4 * T2 + ck;
-      out[d * N + sidx(g, gi, gj, gk)] += alpha * acc[d][(ci * by + cj) * bz + ck];
+    // faces 0..3 along the component's axis belong to this tile
+    bool mine = owner && (fd == 0 ? fi < 4 : (fd == 1 ? fj < 4 : fk < 4));
+    if (mine) {
+      int gi = 4 * T0 + fi, gj = 4 * T1 + fj, gk = 4 * T2 + fk;
+      out[fd * N + sidx(g, gi, gj, gk)] += alpha * acc;
     }
   }
 }
 
-hipError_t band_apply(int ker, bool div, const Geo &g, int nt0, int nt1, int nt2, int nactive, const int *active,
-                      const int *tstart, const double *X, const double *q, double alpha, double *out,
-                      hipStream_t s) {
+hipError_t band_apply(int ker, bool div, const Geo &g, int nt1, int nt2, int nactive, const int *active,
+                      const int *lstart, const int *list, const double *X, const double *q, double alpha,
+                      double *out, hipStream_t s) {
   if (nactive == 0) return hipSuccess;
   dim3 gr(nactive), bl(256);
   if (ker == KER_PESKIN4) {
     if (div)
-      hipLaunchKernelGGL((k_band<KER_PESKIN4, true>), gr, bl, 0, s, g, nt0, nt1, nt2, active, tstart, X, q, alpha, out);
+      hipLaunchKernelGGL((k_band<KER_PESKIN4, true>), gr, bl, 0, s, g, nt1, nt2, active, lstart, list, X, q, alpha, out);
     else
-      hipLaunchKernelGGL((k_band<KER_PESKIN4, false>), gr, bl, 0, s, g, nt0, nt1, nt2, active, tstart, X, q, alpha, out);
+      hipLaunchKernelGGL((k_band<KER_PESKIN4, false>), gr, bl, 0, s, g, nt1, nt2, active, lstart, list, X, q, alpha, out);
   } else {
     if (div)
-      hipLaunchKernelGGL((k_band<KER_ROMA3, true>), gr, bl, 0, s, g, nt0, nt1, nt2, active, tstart, X, q, alpha, out);
+      hipLaunchKernelGGL((k_band<KER_ROMA3, true>), gr, bl, 0, s, g, nt1, nt2, active, lstart, list, X, q, alpha, out);
     else
-      hipLaunchKernelGGL((k_band<KER_ROMA3, false>), gr, bl, 0, s, g, nt0, nt1, nt2, active, tstart, X, q, alpha, out);
+      hipLaunchKernelGGL((k_band<KER_ROMA3, false>), gr, bl, 0, s, g, nt1, nt2, active, lstart, list, X, q, alpha, out);
   }
   return hipGetLastError();
 }

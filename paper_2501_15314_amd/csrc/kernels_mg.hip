@@ -162,45 +162,61 @@ hipError_t mg_prolong(const Geo &gf, T *xf, const Geo &gc, const T *xc, hipStrea
 // Coarse-grid kernel: one workgroup, the whole coarse hierarchy in LDS
 // (natural layout).  Projects the right-hand side to mean zero (L is
 // singular on constants), then runs `cycles` V-cycles with `sweeps` red-black
-// sweeps per level and 32 sweeps on the smallest grid.
+// sweeps per level and `bottom` sweeps on the smallest grid.
 constexpr int COARSE_MAX = 4096;                 // cells of the coarse grid
 constexpr int COARSE_CAP = 4096 + 512 + 64 + 8 + 8;
 constexpr int COARSE_THREADS = 1024;
 constexpr int COARSE_MAXLEV = 8;
 int coarse_max_cells() { return COARSE_MAX; }
 
-struct LvlDim { int n0, n1, n2, off; };
+struct LvlDim { int n0, n1, n2, off, l1, l2, pow2; };
 
-template <typename T>
-__device__ void lds_smooth(T *x, const T *b, const LvlDim &d, int bc0, int bc1, int bc2, T h2, int color) {
-  int nc = d.n0 * d.n1 * d.n2;
-  for (int e = threadIdx.x; e < nc; e += COARSE_THREADS) {
-    int k = e % d.n2, r = e / d.n2, j = r % d.n1, i = r / d.n1;
-    if (((i + j + k) & 1) != color) continue;
-    T s = T(0);
-    int nn = 0, t;
-    t = nbr(i, -1, d.n0, bc0); if (t >= 0) { s += x[d.off + (t * d.n1 + j) * d.n2 + k]; ++nn; }
-    t = nbr(i, 1, d.n0, bc0);  if (t >= 0) { s += x[d.off + (t * d.n1 + j) * d.n2 + k]; ++nn; }
-    t = nbr(j, -1, d.n1, bc1); if (t >= 0) { s += x[d.off + (i * d.n1 + t) * d.n2 + k]; ++nn; }
-    t = nbr(j, 1, d.n1, bc1);  if (t >= 0) { s += x[d.off + (i * d.n1 + t) * d.n2 + k]; ++nn; }
-    t = nbr(k, -1, d.n2, bc2); if (t >= 0) { s += x[d.off + (i * d.n1 + j) * d.n2 + t]; ++nn; }
-    t = nbr(k, 1, d.n2, bc2);  if (t >= 0) { s += x[d.off + (i * d.n1 + j) * d.n2 + t]; ++nn; }
-    x[d.off + e] = (h2 * b[d.off + e] + s) / (T)nn;
+__device__ __forceinline__ void lds_decode(const LvlDim &d, int e, int &i, int &j, int &k) {
+  if (d.pow2) {
+    k = e & (d.n2 - 1);
+    j = (e >> d.l2) & (d.n1 - 1);
+    i = e >> (d.l1 + d.l2);
+  } else {
+    k = e % d.n2;
+    int r = e / d.n2;
+    j = r % d.n1;
+    i = r / d.n1;
   }
-  __syncthreads();
 }
 
 template <typename T>
-__device__ T lds_resid(const T *x, const T *b, const LvlDim &d, int bc0, int bc1, int bc2, T ih2, int i, int j,
-                       int k) {
+__device__ __forceinline__ T lds_nb(const T *x, LvlDim d, int bc0, int bc1, int bc2, int i, int j, int k, int &nn) {
   T s = T(0);
-  int nn = 0, t;
+  int t;
+  nn = 0;
   t = nbr(i, -1, d.n0, bc0); if (t >= 0) { s += x[d.off + (t * d.n1 + j) * d.n2 + k]; ++nn; }
   t = nbr(i, 1, d.n0, bc0);  if (t >= 0) { s += x[d.off + (t * d.n1 + j) * d.n2 + k]; ++nn; }
   t = nbr(j, -1, d.n1, bc1); if (t >= 0) { s += x[d.off + (i * d.n1 + t) * d.n2 + k]; ++nn; }
   t = nbr(j, 1, d.n1, bc1);  if (t >= 0) { s += x[d.off + (i * d.n1 + t) * d.n2 + k]; ++nn; }
   t = nbr(k, -1, d.n2, bc2); if (t >= 0) { s += x[d.off + (i * d.n1 + j) * d.n2 + t]; ++nn; }
   t = nbr(k, 1, d.n2, bc2);  if (t >= 0) { s += x[d.off + (i * d.n1 + j) * d.n2 + t]; ++nn; }
+  return s;
+}
+
+template <typename T>
+__device__ void lds_smooth(T *x, const T *b, LvlDim d, int bc0, int bc1, int bc2, T h2, int color) {
+  int nc = d.n0 * d.n1 * d.n2;
+  for (int e = threadIdx.x; e < nc; e += COARSE_THREADS) {
+    int i, j, k;
+    lds_decode(d, e, i, j, k);
+    if (((i + j + k) & 1) != color) continue;
+    int nn;
+    T s = lds_nb(x, d, bc0, bc1, bc2, i, j, k, nn);
+    x[d.off + e] = (h2 * b[d.off + e] + s) / (T)nn;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ T lds_resid(const T *x, const T *b, LvlDim d, int bc0, int bc1, int bc2, T ih2, int i,
+                                       int j, int k) {
+  int nn;
+  T s = lds_nb(x, d, bc0, bc1, bc2, i, j, k, nn);
   int e = d.off + (i * d.n1 + j) * d.n2 + k;
   return b[e] - ((T)nn * x[e] - s) * ih2;
 }
@@ -222,23 +238,46 @@ __device__ double block_sum(double v, double *red) {
   return t;
 }
 
+__device__ __forceinline__ int coarse_partner(int C, int odd, int nc, int bc) {
+  int o = C + (odd ? 1 : -1);
+  if (o < 0 || o >= nc) o = bc ? C : (o < 0 ? o + nc : o - nc);
+  return o;
+}
+
 template <typename T, typename TB>
-__global__ void __launch_bounds__(COARSE_THREADS) k_coarse(Geo g, const TB *bin, T *xout, int cycles, int sweeps) {
+__global__ void __launch_bounds__(COARSE_THREADS) k_coarse(Geo g, const TB *bin, T *xout, int cycles, int sweeps,
+                                                           int bottom) {
   __shared__ T sx[COARSE_CAP];
   __shared__ T sb[COARSE_CAP];
   __shared__ double red[COARSE_THREADS / 64 + 1];
-  LvlDim d[COARSE_MAXLEV];
-  int nl = 1;
-  d[0].n0 = g.n0; d[0].n1 = g.n1; d[0].n2 = g.n2; d[0].off = 0;
-  while (nl < COARSE_MAXLEV) {
-    const LvlDim &q = d[nl - 1];
-    if ((q.n0 & 1) || (q.n1 & 1) || (q.n2 & 1) || q.n0 < 4 || q.n1 < 4 || q.n2 < 4) break;
-    d[nl].n0 = q.n0 / 2; d[nl].n1 = q.n1 / 2; d[nl].n2 = q.n2 / 2;
-    d[nl].off = q.off + q.n0 * q.n1 * q.n2;
-    ++nl;
+  __shared__ LvlDim dims[COARSE_MAXLEV];
+  __shared__ int s_nl;
+  if (threadIdx.x == 0) {
+    int nl = 1;
+    dims[0].n0 = g.n0; dims[0].n1 = g.n1; dims[0].n2 = g.n2; dims[0].off = 0;
+    while (nl < COARSE_MAXLEV) {
+      LvlDim q = dims[nl - 1];
+      if ((q.n0 & 1) || (q.n1 & 1) || (q.n2 & 1) || q.n0 < 4 || q.n1 < 4 || q.n2 < 4) break;
+      LvlDim nx;
+      nx.n0 = q.n0 / 2; nx.n1 = q.n1 / 2; nx.n2 = q.n2 / 2;
+      nx.off = q.off + q.n0 * q.n1 * q.n2;
+      dims[nl] = nx;
+      ++nl;
+    }
+    for (int l = 0; l < nl; ++l) {
+      LvlDim &q = dims[l];
+      bool p2 = !(q.n0 & (q.n0 - 1)) && !(q.n1 & (q.n1 - 1)) && !(q.n2 & (q.n2 - 1));
+      q.pow2 = p2;
+      q.l1 = 31 - __clz(q.n1);
+      q.l2 = 31 - __clz(q.n2);
+    }
+    s_nl = nl;
   }
+  __syncthreads();
+  const int nl = s_nl;
+  const int bc0 = g.bc0, bc1 = g.bc1, bc2 = g.bc2;
   const int nc0 = g.n0 * g.n1 * g.n2;
-  // load b (split layout -> natural) and project to mean zero
+  // load b (split layout -> natural) and project it to mean zero
   double loc = 0.0;
   for (int e = threadIdx.x; e < nc0; e += COARSE_THREADS) {
     int k = e % g.n2, r = e / g.n2, j = r % g.n1, i = r / g.n1;
@@ -254,20 +293,20 @@ __global__ void __launch_bounds__(COARSE_THREADS) k_coarse(Geo g, const TB *bin,
   for (int cyc = 0; cyc < cycles; ++cyc) {
     T h = (T)g.h;
     for (int l = 0; l + 1 < nl; ++l) {
+      const LvlDim f = dims[l], c = dims[l + 1];
       T h2 = h * h;
       for (int s = 0; s < sweeps; ++s) {
-        lds_smooth(sx, sb, d[l], g.bc0, g.bc1, g.bc2, h2, 0);
-        lds_smooth(sx, sb, d[l], g.bc0, g.bc1, g.bc2, h2, 1);
+        lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 0);
+        lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 1);
       }
-      const LvlDim &f = d[l], &c = d[l + 1];
       int ncc = c.n0 * c.n1 * c.n2;
       T ih2 = T(1) / h2;
       for (int e = threadIdx.x; e < ncc; e += COARSE_THREADS) {
-        int k = e % c.n2, r = e / c.n2, j = r % c.n1, i = r / c.n1;
+        int i, j, k;
+        lds_decode(c, e, i, j, k);
         T acc = T(0);
         for (int q = 0; q < 8; ++q)
-          acc += lds_resid(sx, sb, f, g.bc0, g.bc1, g.bc2, ih2, 2 * i + (q >> 2), 2 * j + ((q >> 1) & 1),
-                           2 * k + (q & 1));
+          acc += lds_resid(sx, sb, f, bc0, bc1, bc2, ih2, 2 * i + (q >> 2), 2 * j + ((q >> 1) & 1), 2 * k + (q & 1));
         sb[c.off + e] = acc * (T)0.125;
         sx[c.off + e] = T(0);
       }
@@ -275,41 +314,40 @@ __global__ void __launch_bounds__(COARSE_THREADS) k_coarse(Geo g, const TB *bin,
       h = h * (T)2;
     }
     {
+      const LvlDim f = dims[nl - 1];
       T h2 = h * h;
-      for (int s = 0; s < 32; ++s) {
-        lds_smooth(sx, sb, d[nl - 1], g.bc0, g.bc1, g.bc2, h2, 0);
-        lds_smooth(sx, sb, d[nl - 1], g.bc0, g.bc1, g.bc2, h2, 1);
+      for (int s = 0; s < bottom; ++s) {
+        lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 0);
+        lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 1);
       }
     }
     for (int l = nl - 2; l >= 0; --l) {
       h = h * (T)0.5;
-      const LvlDim &f = d[l], &c = d[l + 1];
+      const LvlDim f = dims[l], c = dims[l + 1];
       int ncf = f.n0 * f.n1 * f.n2;
       for (int e = threadIdx.x; e < ncf; e += COARSE_THREADS) {
-        int k = e % f.n2, r = e / f.n2, j = r % f.n1, i = r / f.n1;
-        const int xs[3] = {i, j, k};
-        const int nn[3] = {c.n0, c.n1, c.n2};
-        const int bcs[3] = {g.bc0, g.bc1, g.bc2};
-        int I[3][2];
-        for (int a = 0; a < 3; ++a) {
-          int C = xs[a] >> 1, s = (xs[a] & 1) ? 1 : -1, o = C + s;
-          if (o < 0 || o >= nn[a]) o = bcs[a] ? C : (o < 0 ? o + nn[a] : o - nn[a]);
-          I[a][0] = C;
-          I[a][1] = o;
-        }
-        T acc = T(0);
-        for (int q = 0; q < 8; ++q) {
-          int qa = q >> 2, qb = (q >> 1) & 1, qc = q & 1;
-          T w = (qa ? (T)0.25 : (T)0.75) * (qb ? (T)0.25 : (T)0.75) * (qc ? (T)0.25 : (T)0.75);
-          acc += w * sx[c.off + (I[0][qa] * c.n1 + I[1][qb]) * c.n2 + I[2][qc]];
-        }
-        sx[f.off + e] += acc;
+        int i, j, k;
+        lds_decode(f, e, i, j, k);
+        int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
+        int I1 = coarse_partner(I0, i & 1, c.n0, bc0);
+        int J1 = coarse_partner(J0, j & 1, c.n1, bc1);
+        int K1 = coarse_partner(K0, k & 1, c.n2, bc2);
+        const T *xc = sx + c.off;
+#define XC(a, b, cc) xc[((a) * c.n1 + (b)) * c.n2 + (cc)]
+        T v0 = (T)0.75 * XC(I0, J0, K0) + (T)0.25 * XC(I1, J0, K0);
+        T v1 = (T)0.75 * XC(I0, J1, K0) + (T)0.25 * XC(I1, J1, K0);
+        T v2 = (T)0.75 * XC(I0, J0, K1) + (T)0.25 * XC(I1, J0, K1);
+        T v3 = (T)0.75 * XC(I0, J1, K1) + (T)0.25 * XC(I1, J1, K1);
+#undef XC
+        T w0 = (T)0.75 * v0 + (T)0.25 * v1;
+        T w1 = (T)0.75 * v2 + (T)0.25 * v3;
+        sx[f.off + e] += (T)0.75 * w0 + (T)0.25 * w1;
       }
       __syncthreads();
       T h2 = h * h;
       for (int s = 0; s < sweeps; ++s) {
-        lds_smooth(sx, sb, d[l], g.bc0, g.bc1, g.bc2, h2, 1);
-        lds_smooth(sx, sb, d[l], g.bc0, g.bc1, g.bc2, h2, 0);
+        lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 1);
+        lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 0);
       }
     }
   }
@@ -322,7 +360,7 @@ __global__ void __launch_bounds__(COARSE_THREADS) k_coarse(Geo g, const TB *bin,
 template <typename T, typename TB>
 hipError_t mg_coarse(const Geo &gc, const TB *b, T *x, int cycles, int sweeps, hipStream_t s) {
   if ((long long)gc.n0 * gc.n1 * gc.n2 > COARSE_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_coarse<T, TB>), dim3(1), dim3(COARSE_THREADS), 0, s, gc, b, x, cycles, sweeps);
+  hipLaunchKernelGGL((k_coarse<T, TB>), dim3(1), dim3(COARSE_THREADS), 0, s, gc, b, x, cycles, sweeps, 8);
   return hipGetLastError();
 }
 

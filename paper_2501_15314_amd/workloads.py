@@ -60,7 +60,7 @@ class Config:
     mg_coarsest: int = 16
     mg_pre: int = 2
     mg_post: int = 2
-    mg_coarse_sweeps: int = 4
+    mg_coarse_sweeps: int = 1
     outer_iters: int = 1
     outer_tol: float = 0.0
     xi: float = 1.0
