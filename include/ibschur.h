@@ -70,7 +70,7 @@ enum { SIM_PREC_FP64 = 0, SIM_PREC_FP32MG = 1 };
 enum { SIM_MOTION_PRESCRIBED = 0, SIM_MOTION_FREE = 1 };
 
 typedef struct {
-  int32_t n[3];          /* cells per axis; all even, n[2] >= 4 */
+  int32_t n[3];          /* cells per axis; multiples of 4, >= 16 */
   double len[3];         /* box size; cells must be cubic: len[d]/n[d] equal */
   int32_t bc[3];         /* SIM_BC_* per axis (both ends) */
   double nu;             /* kinematic viscosity (1/Re in the paper's units) */
@@ -86,7 +86,7 @@ typedef struct {
   double helm_rtol;      /* momentum relative residual target */
   int32_t mg_coarsest;   /* grid-wide V-cycle levels stop above this size */
   int32_t mg_pre, mg_post;     /* red-black Gauss-Seidel sweeps per level */
-  int32_t mg_coarse_sweeps;    /* sweeps per level inside the coarse kernel */
+  int32_t mg_coarse_sweeps;    /* V-cycles run by the coarse-grid LDS kernel */
   int32_t outer_iters;   /* pressure-force corrections per step (>= 1) */
   double outer_tol;      /* stop on ||Phi'||_1 / ||Phi||_1 < tol (0: fixed) */
   double xi;             /* relaxation of the correction (1 for one-way) */
@@ -210,6 +210,31 @@ enum {
 };
 sim_status sim_apply(sim_t sim, int32_t op, const double *d_in, const double *d_in2,
                      double *d_out);
+
+/* Kernel timing probes (a profiling aid, for throughput / roofline reports).
+ * While a probe is enabled, every launch of its kernel class is bracketed by
+ * HIP events on the launch stream; sim_probe_read returns the number of
+ * probed launches and their summed device time in milliseconds (waiting for
+ * the events) and, if reset != 0, clears them.  Probes are process-wide. */
+enum {
+  SIM_PROBE_SMOOTH_FINE = 0,        /* red-black half sweep, finest level */
+  SIM_PROBE_SMOOTH_FIRST_FINE = 1,  /* first sweep from zero, finest level */
+  SIM_PROBE_RESTRICT_FINE = 2,      /* residual + restriction, finest level */
+  SIM_PROBE_PROLONG_FINE = 3,       /* prolongation + correction, finest level */
+  SIM_PROBE_LAPLACIAN = 4,          /* L z inside the S~ product */
+  SIM_PROBE_SPREAD_DIV = 5,         /* D W q on the active tiles */
+  SIM_PROBE_SPREAD_FACE = 6,        /* W q on the active tiles */
+  SIM_PROBE_INTERP_GRAD = 7,        /* W^T G z */
+  SIM_PROBE_INTERP_FACE = 8,        /* W^T u */
+  SIM_PROBE_MULTIDOT = 9,           /* Gram-Schmidt dot products */
+  SIM_PROBE_UPDATE_NORM = 10,       /* Gram-Schmidt update and norm */
+  SIM_PROBE_COARSE = 11,            /* coarse-grid LDS kernel */
+  SIM_PROBE_HELM_SWEEP = 12,        /* momentum red-black SOR half sweep */
+  SIM_PROBE_HELM_RESID = 13,        /* momentum residual */
+  SIM_PROBE_COUNT = 14
+};
+sim_status sim_probe_enable(sim_t sim, int32_t probe, int32_t on);
+sim_status sim_probe_read(sim_t sim, int32_t probe, int64_t *launches, double *ms, int32_t reset);
 
 /* Message of the last failing call on this handle ("" if none). */
 const char *sim_last_error(sim_t sim);

@@ -11,8 +11,8 @@
 //   * the pressure-force correction (Sec. 3.1 eq. Saddle, Sec. 4.1 eqs.
 //     ApproxSchurPrimalP/F) and the one-way / two-way time steps (Sec. 3.1,
 //     Sec. 3.2.1);
-//   * momentum solve (eq. ustar) by defect correction with Chebyshev
-//     relaxations on the exact spectral enclosure of A.
+//   * momentum solve (eq. ustar) by defect correction with red-black SOR
+//     relaxations at the optimal factor for the constant-coefficient A.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -70,7 +70,7 @@ struct sim_s {
   double *V = nullptr;
   void *Z = nullptr;
   // momentum relaxation work (T precision)
-  void *HR = nullptr, *HD = nullptr, *HE0 = nullptr, *HE1 = nullptr;
+  void *HR = nullptr, *HE0 = nullptr;
   std::vector<Level> lv;  // lv[0] is the finest grid (x, b supplied per call)
   // points
   double *OFF = nullptr, *XN = nullptr, *UN = nullptr, *PHIN = nullptr;
@@ -162,6 +162,10 @@ std::string validate(const sim_config *c, std::vector<int> *dims) {
   }
   if ((long long)n0 * n1 * n2 > coarse_max_cells()) return "grid cannot be coarsened to the coarse-kernel size";
   if (!is_even(n0) || !is_even(n1) || !is_even(n2)) return "coarsest multigrid grid must have even sizes";
+  // the plane-marching kernels handle two in-row values per thread on every grid-wide level
+  if (dims)
+    for (size_t l = 0; l + 3 < dims->size(); l += 3)
+      if ((*dims)[l + 2] % 4) return "axis-2 size of every multigrid level above the coarsest must be a multiple of 4";
   return "";
 }
 
@@ -180,8 +184,7 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
   double *PP = cv.arr<double>(N), *TMPC = cv.arr<double>(N);
   double *V = cv.arr<double>((long long)(m + 1) * N);
   void *Z = cv.take(ts * (size_t)m * N);
-  void *HR = cv.take(ts * 3 * N), *HD = cv.take(ts * 3 * N), *HE0 = cv.take(ts * 3 * N),
-       *HE1 = cv.take(ts * 3 * N);
+  void *HR = cv.take(ts * 3 * N), *HE0 = cv.take(ts * 3 * N);
   std::vector<Level> lv;
   int nlev = (int)dims.size() / 3;
   for (int l = 0; l < nlev; ++l) {
@@ -212,14 +215,15 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
   int rb = std::max(red_blocks(), 1);
   long long parts = std::max<long long>((long long)rb * (MAX_RESTART + 2), 0);
   // helm_resid writes one partial per row-launch block
-  long long hparts = (long long)((c->n[2] / 2 + 63) / 64 + 1) * (c->n[1] + 1) * (2LL * c->n[0] * 3);
+  // the momentum residual writes one partial per plane-march workgroup
+  long long hparts = (long long)(c->n[2] / 4 + 1) * c->n[1] * (c->n[0] / 8 + 1) * 3;
   double *PART = cv.arr<double>(std::max(parts, hparts));
   double *RED = cv.arr<double>(4 * (MAX_RESTART + 2));
   double *YDEV = cv.arr<double>(MAX_RESTART + 2);
   if (s) {
     s->U = U; s->UM = UM; s->USTAR = USTAR; s->RHSU = RHSU; s->TMP3 = TMP3;
     s->P = P; s->RHSP = RHSP; s->BVEC = BVEC; s->PP = PP; s->TMPC = TMPC;
-    s->V = V; s->Z = Z; s->HR = HR; s->HD = HD; s->HE0 = HE0; s->HE1 = HE1;
+    s->V = V; s->Z = Z; s->HR = HR; s->HE0 = HE0;
     s->lv = lv;
     s->OFF = OFF; s->XN = XN; s->UN = UN; s->PHIN = PHIN;
     s->BODYOF = BODYOF; s->TILE = TILE; s->PERM = PERM; s->PERMTMP = PERMTMP;
@@ -382,7 +386,10 @@ std::vector<BodyDev> body_states_at(sim_t s, double t) {
 // w = S~ z = L z + c^-1 G^T W W^T G z  (= L z - c^-1 D W (W^T G z))
 template <typename T>
 sim_status schur_matvec(sim_t s, const T *z, double *w) {
-  CKH(lap_apply<T>(s->g, z, w, s->st));
+  {
+    ProbeScope pr(PR_LAP, s->st);
+    CKH(lap_apply<T>(s->g, z, w, s->st));
+  }
   CKH(interp_grad<T>(s->ker, s->g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, z, 1.0, nullptr, 0.0, s->Q, s->st));
   CKH(band_apply(s->ker, true, s->g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, s->Q,
                  -1.0 / s->c, w, s->st));
@@ -405,10 +412,19 @@ sim_status vcycle(sim_t s, const double *v, T *z) {
     const Geo &g = s->lv[l].g;
     T *x = l == 0 ? z : (T *)s->lv[l].x;
     if (l == 0) {
-      CKH((mg_smooth_first<T, double>(g, x, v, st)));
+      {
+        ProbeScope pr(PR_SMOOTH_FIRST_FINE, st);
+        CKH((mg_smooth_first<T, double>(g, x, v, st)));
+      }
       for (int q = 1; q < c.mg_pre; ++q) {
-        CKH((mg_smooth<T, double>(g, x, v, 0, st)));
-        CKH((mg_smooth<T, double>(g, x, v, 1, st)));
+        {
+          ProbeScope pr(PR_SMOOTH_FINE, st);
+          CKH((mg_smooth<T, double>(g, x, v, 0, st)));
+        }
+        {
+          ProbeScope pr(PR_SMOOTH_FINE, st);
+          CKH((mg_smooth<T, double>(g, x, v, 1, st)));
+        }
       }
     } else {
       const T *b = (const T *)s->lv[l].b;
@@ -420,23 +436,37 @@ sim_status vcycle(sim_t s, const double *v, T *z) {
     }
     {
       T *bnext = (T *)s->lv[l + 1].b;
-      if (l == 0)
+      if (l == 0) {
+        ProbeScope pr(PR_RESTRICT_FINE, st);
         CKH((mg_restrict<T, double>(g, x, v, s->lv[1].g, bnext, st)));
-      else
+      } else
+
         CKH((mg_restrict<T, T>(g, x, (const T *)s->lv[l].b, s->lv[l + 1].g, bnext, st)));
     }
   }
   // coarse grid
-  CKH((mg_coarse<T, T>(s->lv[nl - 1].g, (const T *)s->lv[nl - 1].b, (T *)s->lv[nl - 1].x, cyc, 1, st)));
+  {
+    ProbeScope prc(PR_COARSE, st);
+    CKH((mg_coarse<T, T>(s->lv[nl - 1].g, (const T *)s->lv[nl - 1].b, (T *)s->lv[nl - 1].x, cyc, 1, st)));
+  }
   // ascend
   for (int l = nl - 2; l >= 0; --l) {
     const Geo &g = s->lv[l].g;
     T *x = l == 0 ? z : (T *)s->lv[l].x;
-    CKH(mg_prolong<T>(g, x, s->lv[l + 1].g, (const T *)s->lv[l + 1].x, st));
+    {
+      ProbeScope pr(l == 0 ? PR_PROLONG_FINE : -1, st);
+      CKH(mg_prolong<T>(g, x, s->lv[l + 1].g, (const T *)s->lv[l + 1].x, st));
+    }
     for (int q = 0; q < c.mg_post; ++q) {
       if (l == 0) {
-        CKH((mg_smooth<T, double>(g, x, v, 1, st)));
-        CKH((mg_smooth<T, double>(g, x, v, 0, st)));
+        {
+          ProbeScope pr(PR_SMOOTH_FINE, st);
+          CKH((mg_smooth<T, double>(g, x, v, 1, st)));
+        }
+        {
+          ProbeScope pr(PR_SMOOTH_FINE, st);
+          CKH((mg_smooth<T, double>(g, x, v, 0, st)));
+        }
       } else {
         const T *b = (const T *)s->lv[l].b;
         CKH((mg_smooth<T, T>(g, x, b, 1, st)));
@@ -487,9 +517,15 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
       double *vj = V + (long long)j * N, *w = V + (long long)(j + 1) * N;
       if ((rc = vcycle<T>(s, vj, zj))) return rc;
       if ((rc = schur_matvec<T>(s, zj, w))) return rc;
-      CKH(multidot(w, V, N, j + 1, N, s->PART, st));
+      {
+        ProbeScope pr(PR_MULTIDOT, st);
+        CKH(multidot(w, V, N, j + 1, N, s->PART, st));
+      }
       CKH(finalize(s->PART, red_blocks(), j + 1, s->RED, st));
-      CKH(update_norm(w, V, N, j + 1, s->RED, N, s->PART + (long long)(MAX_RESTART + 1) * red_blocks(), st));
+      {
+        ProbeScope pr(PR_UPDATE_NORM, st);
+        CKH(update_norm(w, V, N, j + 1, s->RED, N, s->PART + (long long)(MAX_RESTART + 1) * red_blocks(), st));
+      }
       CKH(finalize(s->PART + (long long)(MAX_RESTART + 1) * red_blocks(), red_blocks(), 1, s->RED + j + 1, st));
       double hc[MAX_RESTART + 2];
       if ((rc = fetch_red(s, s->RED, j + 2, hc))) return rc;
@@ -581,18 +617,22 @@ sim_status schur_solve_core(sim_t s, sim_solve_stats *stt) {
 
 // ---------------------------------------------------------------------------
 // Momentum solve A u = rhs (faces, split layout): defect correction in FP64,
-// each correction by k Chebyshev steps in precision T on the spectral
-// enclosure [a0, a0 + 12 nu / h^2] of A (Gershgorin; A is symmetric).
+// each correction by red-black SOR sweeps in precision T.  A has a constant
+// interior diagonal a0 + 6 nu/h^2 and red-black ordering makes it consistently
+// ordered, so with rho_J = (6 nu/h^2) / (a0 + 6 nu/h^2) the SOR factor
+// omega = 2 / (1 + sqrt(1 - rho_J^2)) contracts the error by omega - 1 per
+// sweep (boundary rows only add diagonal weight).
 template <typename T>
 sim_status helm_solve(sim_t s, const double *rhs, double *u, sim_solve_stats *stt) {
   hipStream_t st = s->st;
   const sim_config &c = s->cfg;
   const Geo &g = s->g;
   const long long n3 = 3 * s->N;
-  double a0 = 1.5 / c.dt;
-  double lmin = a0, lmax = a0 + 12.0 * c.nu / g.h2;
-  double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
-  T *R = (T *)s->HR, *D = (T *)s->HD, *E0 = (T *)s->HE0, *E1 = (T *)s->HE1;
+  const double a0 = 1.5 / c.dt, nuh2 = c.nu / g.h2;
+  const double rhoJ = 6.0 * nuh2 / (a0 + 6.0 * nuh2);
+  const double omega = 2.0 / (1.0 + sqrt(std::max(0.0, 1.0 - rhoJ * rhoJ)));
+  const double rho = omega - 1.0;
+  T *R = (T *)s->HR, *E = (T *)s->HE0;
   sim_solve_stats loc{};
   sim_solve_stats &S = stt ? *stt : loc;
   S.iters = 0;
@@ -601,16 +641,17 @@ sim_status helm_solve(sim_t s, const double *rhs, double *u, sim_solve_stats *st
   double bn2;
   if ((rc = dev_norm2(s, rhs, n3, &bn2))) return rc;
   double bnorm = sqrt(bn2);
-  // inner steps per correction: Chebyshev bound 2 q^k <= 1e-4 (FP32) or rtol-limited (FP64)
-  double kap = lmax / lmin, q = (sqrt(kap) - 1) / (sqrt(kap) + 1);
-  double target = s->fp32 ? 1e-4 : std::max(c.helm_rtol * 0.1, 1e-13);
-  int kin = q > 0 ? (int)ceil(log(target / 2.0) / log(q)) : 1;
-  kin = std::max(1, std::min(kin, 200));
+  // sweeps per correction: rho^k <= 1e-4 (a safe gain per correction in float32)
+  int kin = rho > 1e-12 ? (int)ceil(log(1e-4) / log(rho)) : 1;
+  kin = std::max(1, std::min(kin, 100));
   double rel = 1.0;
   int it = 0;
   int nb = 0;
   for (;; ++it) {
-    CKH(helm_resid<T>(g, a0, c.nu, u, rhs, R, s->PART, &nb, st));
+    {
+      ProbeScope pr(PR_HELM_RESID, st);
+      CKH(helm_resid<T>(g, a0, c.nu, u, rhs, R, s->PART, &nb, st));
+    }
     CKH(finalize(s->PART, nb, 1, s->RED, st));
     double r2;
     if ((rc = fetch_red(s, s->RED, 1, &r2))) return rc;
@@ -618,26 +659,14 @@ sim_status helm_solve(sim_t s, const double *rhs, double *u, sim_solve_stats *st
     rel = bnorm > 0 ? sqrt(r2) / bnorm : 0.0;
     if (S.nhist < 64) S.hist[S.nhist++] = rel;
     if (rel <= c.helm_rtol || it >= c.helm_maxit) break;
-    // Chebyshev for A e = r from e = 0
-    CKH(zero_t<T>(E0, n3, st));
-    CKH(zero_t<T>(D, n3, st));
-    double rho_prev = delta / theta;  // rho_0 = 1 / sigma1
+    CKH(zero_t<T>(E, n3, st));
     for (int k = 0; k < kin; ++k) {
-      double ca, cb;
-      if (k == 0) {
-        ca = 0.0;
-        cb = 1.0 / theta;
-      } else {
-        double sigma1 = theta / delta;
-        double rho = 1.0 / (2.0 * sigma1 - rho_prev);
-        ca = rho * rho_prev;
-        cb = 2.0 * rho / delta;
-        rho_prev = rho;
+      for (int color = 0; color < 2; ++color) {
+        ProbeScope pr(PR_HELM_SWEEP, st);
+        CKH((helm_sor<T, T>(g, a0, c.nu, omega, E, R, color, st)));
       }
-      CKH(helm_cheb<T>(g, a0, c.nu, E0, R, D, E1, ca, cb, st));
-      std::swap(E0, E1);
     }
-    CKH(add_cast<T>(u, E0, n3, st));
+    CKH(add_cast<T>(u, E, n3, st));
   }
   S.iters = it;
   S.rel_res = rel;
@@ -966,6 +995,24 @@ sim_status sim_step_adjoint(sim_t s, const double *, const double *, const doubl
                             const double *, double *, double *, double *, double *, double *, double *) {
   if (!s) return SIM_EINVAL;
   return fail(s, SIM_ESTATE, "adjoint step not available in this build");
+}
+
+sim_status sim_probe_enable(sim_t s, int32_t probe, int32_t on) {
+  if (!s) return SIM_EINVAL;
+  if (probe < 0 || probe >= PR_COUNT) return fail(s, SIM_EINVAL, "unknown probe");
+  probe_enable(probe, on != 0);
+  return SIM_OK;
+}
+
+sim_status sim_probe_read(sim_t s, int32_t probe, int64_t *launches, double *ms, int32_t reset) {
+  if (!s || !launches || !ms) return SIM_EINVAL;
+  if (probe < 0 || probe >= PR_COUNT) return fail(s, SIM_EINVAL, "unknown probe");
+  long long c = 0;
+  double t = 0.0;
+  CKH(probe_read(probe, &c, &t, reset != 0));
+  *launches = c;
+  *ms = t;
+  return SIM_OK;
 }
 
 sim_status sim_apply(sim_t s, int32_t op, const double *in, const double *in2, double *out) {

@@ -9,6 +9,23 @@
 
 namespace ibs {
 
+// ---- kernel timing probes (probe.hip) --------------------------------------
+enum ProbeId {
+  PR_SMOOTH_FINE = 0, PR_SMOOTH_FIRST_FINE, PR_RESTRICT_FINE, PR_PROLONG_FINE, PR_LAP, PR_BAND_DIV,
+  PR_BAND_FACE, PR_INTERP_GRAD, PR_INTERP_FACE, PR_MULTIDOT, PR_UPDATE_NORM, PR_COARSE, PR_HELM_SWEEP,
+  PR_HELM_RESID, PR_COUNT
+};
+int probe_begin(int id, hipStream_t s);
+void probe_end(int id, int slot, hipStream_t s);
+void probe_enable(int id, bool on);
+hipError_t probe_read(int id, long long *count, double *ms, bool reset);
+struct ProbeScope {
+  int id, slot;
+  hipStream_t s;
+  ProbeScope(int id_, hipStream_t s_) : id(id_), slot(probe_begin(id_, s_)), s(s_) {}
+  ~ProbeScope() { probe_end(id, slot, s); }
+};
+
 // ---- launch shapes ---------------------------------------------------------
 struct RowLaunch {
   dim3 grid, block;
@@ -40,15 +57,12 @@ template <typename TR>
 hipError_t helm_resid(const Geo &g, double a0, double nu, const double *x3, const double *b3,
                       TR *r3, double *part, int *nblocks, hipStream_t s);
 int helm_resid_blocks(const Geo &g);
-// Chebyshev step for A e = r: d = ca d + cb (r - A e_old), e_new = e_old + d
-template <typename T>
-hipError_t helm_cheb(const Geo &g, double a0, double nu, const T *e_old, const T *r3, T *d3, T *e_new,
-                     double ca, double cb, hipStream_t s);
 template <typename T>
 hipError_t zero_t(T *x, long long n, hipStream_t s);
+// red-black SOR half sweep for A e = r on the three face grids (plane march)
 template <typename T, typename TB>
-hipError_t helm_rbgs(const Geo &g, double a0, double nu, T *x3, const TB *b3, int color, bool first,
-                     hipStream_t s);
+hipError_t helm_sor(const Geo &g, double a0, double nu, double omega, T *x3, const TB *b3, int color,
+                    hipStream_t s);
 template <typename T>
 hipError_t add_cast(double *y, const T *x, long long n, hipStream_t s);  // y += x
 template <typename T>

@@ -9,6 +9,7 @@
 // pressure Laplacian is Neumann there; a tangential velocity's neighbour
 // beyond a wall is the ghost value -u.
 #include "internal.h"
+#include "march.h"
 
 namespace ibs {
 
@@ -29,20 +30,6 @@ RowLaunch row_launch(const Geo &g, int nz) {
   L.block = dim3(bx, by, 1);
   L.grid = dim3((g.hn2 + bx - 1) / bx, (g.n1 + by - 1) / by, nz);
   return L;
-}
-
-// Position of a thread in a one-colour launch (grid.z = n0 * ncomp).
-__device__ __forceinline__ bool row_pos1(const Geo &g, int color, RowPos &p) {
-  p.m = blockIdx.x * blockDim.x + threadIdx.x;
-  p.j = blockIdx.y * blockDim.y + threadIdx.y;
-  int z = blockIdx.z;
-  p.comp = z / g.n0;
-  p.i = z - p.comp * g.n0;
-  p.c = color;
-  if (p.m >= g.hn2 || p.j >= g.n1) return false;
-  p.k = 2 * p.m + ((p.c + p.i + p.j) & 1);
-  p.e = (long long)p.c * g.half + ((long long)p.i * g.n1 + p.j) * g.hn2 + p.m;
-  return true;
 }
 
 // Value of a split-layout plane at (i,j,k); 0 outside a wall box, wrapped on
@@ -102,18 +89,9 @@ hipError_t to_natural(const Geo &g, int ncomp, const double *spl, double *nat, h
 // ---------------------------------------------------------------------------
 // y = L x, L = G^T G: (L x)_c = sum over existing neighbours (x_c - x_nb) / h^2
 template <typename T>
-__global__ void k_lap(Geo g, const T *x, double *y) {
-  RowPos p;
-  if (!row_pos(g, p)) return;
-  double nb = (double)cell_nb_sum(g, x, p.i, p.j, p.k, p.c, p.m);
-  int nn = cell_nnb(g, p.i, p.j, p.k);
-  y[p.e] = ((double)nn * (double)x[p.e] - nb) / g.h2;
-}
-
-template <typename T>
 hipError_t lap_apply(const Geo &g, const T *x, double *y, hipStream_t s) {
-  RowLaunch L = row_launch(g, 2 * g.n0);
-  hipLaunchKernelGGL(k_lap<T>, L.grid, L.block, 0, s, g, x, y);
+  MarchShape M = march_shape(g, 1);
+  hipLaunchKernelGGL((k_apply2<T, double, AP_LAP>), M.grid, M.block, 0, s, g, x, nullptr, y, 0.0, 0.0, nullptr);
   return hipGetLastError();
 }
 template hipError_t lap_apply<float>(const Geo &, const float *, double *, hipStream_t);
@@ -260,44 +238,12 @@ hipError_t helm_apply(const Geo &g, double a0, double nu, const double *u3, doub
   return hipGetLastError();
 }
 
-// r = b - A x in precision TR, plus per-block partial sums of |r|^2 (double).
-__device__ __forceinline__ double block_sum_2d(double v, double *sh) {
-  int tid = threadIdx.x + blockDim.x * threadIdx.y;
-  v = wave_sum(v);
-  if ((tid & 63) == 0) sh[tid >> 6] = v;
-  __syncthreads();
-  return ((sh[0] + sh[1]) + sh[2]) + sh[3];
-}
-template <typename TR>
-__global__ void __launch_bounds__(256) k_helm_resid(Geo g, double a0, double nu, const double *x3, const double *b3,
-                                                    TR *r3, double *part) {
-  __shared__ double sh[4];
-  RowPos p;
-  double out = 0.0;
-  bool ok = row_pos(g, p);
-  long long N = 2 * g.half;
-  if (ok) {
-    int d = p.comp;
-    int xd = d == 0 ? p.i : (d == 1 ? p.j : p.k);
-    if (!(geo_bc(g, d) && xd == 0)) {
-      const double *ud = x3 + d * N;
-      double nb;
-      int diag;
-      helm_stencil(g, ud, d, p.i, p.j, p.k, nb, diag);
-      out = b3[d * N + p.e] - ((a0 + nu * diag / g.h2) * ud[p.e] - nu / g.h2 * nb);
-    }
-    r3[d * N + p.e] = (TR)out;
-  }
-  double t = block_sum_2d(out * out, sh);
-  if (threadIdx.x == 0 && threadIdx.y == 0)
-    part[blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z)] = t;
-}
 template <typename TR>
 hipError_t helm_resid(const Geo &g, double a0, double nu, const double *x3, const double *b3, TR *r3,
                       double *part, int *nblocks, hipStream_t s) {
-  RowLaunch L = row_launch(g, 2 * g.n0 * 3);
-  hipLaunchKernelGGL(k_helm_resid<TR>, L.grid, L.block, 0, s, g, a0, nu, x3, b3, r3, part);
-  *nblocks = (int)(L.grid.x * L.grid.y * L.grid.z);
+  MarchShape M = march_shape(g, 3);
+  hipLaunchKernelGGL((k_apply2<double, TR, AP_HRESID>), M.grid, M.block, 0, s, g, x3, b3, r3, a0, nu / g.h2, part);
+  *nblocks = (int)(M.grid.x * M.grid.y * M.grid.z);
   return hipGetLastError();
 }
 template hipError_t helm_resid<float>(const Geo &, double, double, const double *, const double *, float *,
@@ -305,45 +251,23 @@ template hipError_t helm_resid<float>(const Geo &, double, double, const double 
 template hipError_t helm_resid<double>(const Geo &, double, double, const double *, const double *, double *,
                                        double *, int *, hipStream_t);
 int helm_resid_blocks(const Geo &g) {
-  RowLaunch L = row_launch(g, 2 * g.n0 * 3);
-  return (int)(L.grid.x * L.grid.y * L.grid.z);
+  MarchShape M = march_shape(g, 3);
+  return (int)(M.grid.x * M.grid.y * M.grid.z);
 }
 
-// One Chebyshev step for A e = r:  d = ca d + cb (r - A e_old),  e_new = e_old + d.
-template <typename T>
-__global__ void k_helm_cheb(Geo g, T a0, T nuh2, const T *e_old, const T *r3, T *d3, T *e_new, T ca, T cb) {
-  RowPos p;
-  if (!row_pos(g, p)) return;
-  long long N = 2 * g.half;
-  int d = p.comp;
-  int xd = d == 0 ? p.i : (d == 1 ? p.j : p.k);
-  long long q = d * N + p.e;
-  if (geo_bc(g, d) && xd == 0) {
-    d3[q] = T(0);
-    e_new[q] = T(0);
-    return;
-  }
-  T nb;
-  int diag;
-  helm_stencil(g, e_old + d * N, d, p.i, p.j, p.k, nb, diag);
-  T eo = e_old[q];
-  T ae = (a0 + nuh2 * (T)diag) * eo - nuh2 * nb;
-  T dv = ca * d3[q] + cb * (r3[q] - ae);
-  d3[q] = dv;
-  e_new[q] = eo + dv;
-}
-template <typename T>
-hipError_t helm_cheb(const Geo &g, double a0, double nu, const T *e_old, const T *r3, T *d3, T *e_new, double ca,
-                     double cb, hipStream_t s) {
-  RowLaunch L = row_launch(g, 2 * g.n0 * 3);
-  hipLaunchKernelGGL(k_helm_cheb<T>, L.grid, L.block, 0, s, g, (T)a0, (T)(nu / g.h2), e_old, r3, d3, e_new, (T)ca,
-                     (T)cb);
+// Red-black SOR half sweep for A e = r on all three face grids.
+template <typename T, typename TB>
+hipError_t helm_sor(const Geo &g, double a0, double nu, double omega, T *x3, const TB *b3, int color,
+                    hipStream_t s) {
+  MarchShape M = march_shape(g, 3);
+  hipLaunchKernelGGL((k_sweep<T, TB, SW_HELM>), M.grid, M.block, 0, s, g, x3, b3, color, g.h2, a0, nu / g.h2,
+                     omega);
   return hipGetLastError();
 }
-template hipError_t helm_cheb<float>(const Geo &, double, double, const float *, const float *, float *, float *,
-                                     double, double, hipStream_t);
-template hipError_t helm_cheb<double>(const Geo &, double, double, const double *, const double *, double *,
-                                      double *, double, double, hipStream_t);
+template hipError_t helm_sor<float, float>(const Geo &, double, double, double, float *, const float *, int,
+                                           hipStream_t);
+template hipError_t helm_sor<double, double>(const Geo &, double, double, double, double *, const double *, int,
+                                             hipStream_t);
 
 template <typename T>
 __global__ void k_fill_t(T *x, long long n) {
@@ -360,34 +284,6 @@ hipError_t zero_t(T *x, long long n, hipStream_t s) {
 }
 template hipError_t zero_t<float>(float *, long long, hipStream_t);
 template hipError_t zero_t<double>(double *, long long, hipStream_t);
-
-// Red-black Gauss-Seidel half sweep for A x = b on the face grids, one colour.
-template <typename T, typename TB>
-__global__ void k_helm_rbgs(Geo g, T a0, T nuh2, T *x3, const TB *b3, int color) {
-  RowPos p;
-  if (!row_pos1(g, color, p)) return;
-  long long N = 2 * g.half;
-  int d = p.comp;
-  int xd = d == 0 ? p.i : (d == 1 ? p.j : p.k);
-  if (geo_bc(g, d) && xd == 0) return;
-  T *ud = x3 + d * N;
-  T nb;
-  int diag;
-  helm_stencil(g, (const T *)ud, d, p.i, p.j, p.k, nb, diag);
-  ud[p.e] = ((T)b3[d * N + p.e] + nuh2 * nb) / (a0 + nuh2 * (T)diag);
-}
-template <typename T, typename TB>
-hipError_t helm_rbgs(const Geo &g, double a0, double nu, T *x3, const TB *b3, int color, bool,
-                     hipStream_t s) {
-  RowLaunch L = row_launch(g, g.n0 * 3);
-  hipLaunchKernelGGL((k_helm_rbgs<T, TB>), L.grid, L.block, 0, s, g, (T)a0, (T)(nu / g.h2), x3, b3,
-                     color);
-  return hipGetLastError();
-}
-template hipError_t helm_rbgs<float, double>(const Geo &, double, double, float *, const double *, int,
-                                             bool, hipStream_t);
-template hipError_t helm_rbgs<double, double>(const Geo &, double, double, double *, const double *,
-                                              int, bool, hipStream_t);
 
 template <typename T>
 __global__ void k_add_cast(double *y, const T *x, long long n) {

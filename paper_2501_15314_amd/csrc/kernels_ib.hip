@@ -290,6 +290,7 @@ template <typename T>
 hipError_t interp_grad(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, const int *tiles, const int *tstart,
                        const double *X, const T *z, double alpha, const double *y, double beta, double *out,
                        hipStream_t s) {
+  ProbeScope probe_(PR_INTERP_GRAD, s);
   if (ntiles_nz == 0) return hipSuccess;
   dim3 gr(ntiles_nz), bl(256);
   if (ker == KER_PESKIN4)
@@ -308,6 +309,7 @@ template hipError_t interp_grad<double>(int, const Geo &, int, int, int, const i
 hipError_t interp_face(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, const int *tiles, const int *tstart,
                        const double *X, const double *u3, double alpha, const double *y, double beta, double *out,
                        hipStream_t s) {
+  ProbeScope probe_(PR_INTERP_FACE, s);
   if (ntiles_nz == 0) return hipSuccess;
   dim3 gr(ntiles_nz), bl(256);
   if (ker == KER_PESKIN4)
@@ -422,13 +424,20 @@ hipError_t positive_flags(int n, const int *counts, int *flags, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Spreading on one active tile from its touch list.  The workgroup stages up
-// to BAND_CH listed points at a time in LDS: per component the local start of
-// the support (packed in one word) and the three 1-D weight vectors, the
-// first one multiplied by q.  Each thread owns one face of the tile's face
-// boxes (80 per component) and adds the listed points in list order into a
-// register, so every face value is summed in the same order on every run.
-constexpr int BAND_CH = 128;
+// Spreading on one active tile from its touch list.
+//
+// Staging: up to BAND_CH listed points at a time, one task per (point, axis)
+// computing the face- and centre-node weights of that axis (one square root
+// each) and the local start of the support; per component the first weight
+// vector is multiplied by q.
+//
+// Accumulation: lane L < 56 of every wavefront owns one z-column of a face
+// box (component 0: 5 x 4 columns of 4 faces, component 1: 4 x 5 columns of
+// 4 faces, component 2: 4 x 4 columns of 5 faces).  Wavefront w adds the
+// listed points w, w+4, w+8, ... in list order into registers; the four
+// partial sums of a face are added in a fixed order.  Every grid value is
+// therefore summed in the same order on every run.
+constexpr int BAND_CH = 64;
 
 __device__ __forceinline__ int pack3(int a, int b, int c) {
   return ((a + 64) & 255) | (((b + 64) & 255) << 8) | (((c + 64) & 255) << 16);
@@ -440,8 +449,8 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
                                               double *out) {
   constexpr int W = KerWidth<KER>::W;
   __shared__ double wts[BAND_CH][3][3][4];  // [cand][comp][axis][node]
-  __shared__ int base[3][BAND_CH];          // packed local starts per component
-  __shared__ double facev[3][80];
+  __shared__ int base[3][BAND_CH];          // local starts per component, one byte per axis
+  __shared__ double part[4][3][80];         // per-wavefront face sums
   const int tile = active[blockIdx.x];
   const int T2 = tile % nt2, r = tile / nt2, T1 = r % nt1, T0 = r / nt1;
   const int tid = threadIdx.x;
@@ -450,91 +459,97 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
   const int org[3] = {4 * T0, 4 * T1, 4 * T2};
   const int nn[3] = {g.n0, g.n1, g.n2};
   const int bcs[3] = {g.bc0, g.bc1, g.bc2};
-  // the face owned by this thread: component fd, local indices (fi, fj, fk)
-  const int fd = tid < 80 ? 0 : (tid < 160 ? 1 : 2);
-  const int fl = tid - 80 * fd;
-  const int fby = 4 + (fd == 1), fbz = 4 + (fd == 2);
-  const int fi = fl / (fby * fbz), fj = (fl / fbz) % fby, fk = fl % fbz;
-  const int fpack = pack3(fi, fj, fk);
-  const bool owner = tid < 240;
-  double acc = 0.0;
+  // the column owned by this lane: component cd, x-y position (ci, cj), nf faces along z
+  const int wv = tid >> 6, lane = tid & 63;
+  const int cd = lane < 20 ? 0 : (lane < 40 ? 1 : 2);
+  const int cl = lane - 20 * cd;
+  const int cby = cd == 1 ? 5 : 4;               // columns along y in this component's box
+  const int ci = cl / cby, cj = cl % cby;
+  const int nf = cd == 2 ? 5 : 4;
+  const bool owner = lane < 56;
+  const int cpack = pack3(ci, cj, 0);
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int c0 = s0; c0 < s1; c0 += BAND_CH) {
     const int nc = min(BAND_CH, s1 - c0);
     __syncthreads();
-    if (tid < nc) {
-      int p = list[c0 + tid];
-      double wf[3][4], wc[3][4];
-      int lf[3], lc[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        int f0 = axis_weights<KER>(X[3 * p + a], ih, true, wf[a]);
-        int e0 = axis_weights<KER>(X[3 * p + a], ih, false, wc[a]);
-        int l0 = f0 - org[a], l1 = e0 - org[a];
-        if (!bcs[a]) {
-          l0 = wrapi(l0 + nn[a] / 2, nn[a]) - nn[a] / 2;
-          l1 = wrapi(l1 + nn[a] / 2, nn[a]) - nn[a] / 2;
-        }
-        lf[a] = l0;
-        lc[a] = l1;
+    for (int task = tid; task < 3 * nc; task += 256) {
+      const int cand = task / 3, a = task - 3 * cand;
+      const int p = list[c0 + cand];
+      const double xa = X[3 * p + a];
+      double wf[4], wc[4];
+      int f0 = axis_weights<KER>(xa, ih, true, wf);
+      int e0 = axis_weights<KER>(xa, ih, false, wc);
+      int lf = f0 - org[a], lc = e0 - org[a];
+      if (!bcs[a]) {
+        lf = wrapi(lf + nn[a] / 2, nn[a]) - nn[a] / 2;
+        lc = wrapi(lc + nn[a] / 2, nn[a]) - nn[a] / 2;
+      }
+      double qv[3] = {1.0, 1.0, 1.0};
+      if (a == 0) {
+        qv[0] = q[3 * p];
+        qv[1] = q[3 * p + 1];
+        qv[2] = q[3 * p + 2];
       }
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        double qd = q[3 * p + d];
-        base[d][tid] = pack3(d == 0 ? lf[0] : lc[0], d == 1 ? lf[1] : lc[1], d == 2 ? lf[2] : lc[2]);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          wts[tid][d][0][t] = (d == 0 ? wf[0][t] : wc[0][t]) * qd;
-          wts[tid][d][1][t] = d == 1 ? wf[1][t] : wc[1][t];
-          wts[tid][d][2][t] = d == 2 ? wf[2][t] : wc[2][t];
-        }
+        for (int t = 0; t < 4; ++t) wts[cand][d][a][t] = (d == a ? wf[t] : wc[t]) * qv[d];
       }
+      // per component the start along this axis is the face start (d == a) or the centre
+      // start, stored (offset by 64) in byte a of base[d][cand]
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        ((unsigned char *)&base[d][cand])[a] = (unsigned char)(((d == a ? lf : lc) + 64) & 255);
     }
     __syncthreads();
     if (owner) {
-      // local node offset of this face in the support of candidate c, per axis
-      // (byte lanes of fpack - base, each in [0, W) when the face is covered)
-      int c = 0;
-      for (; c + 4 <= nc; c += 4) {
-        int b0 = base[fd][c], b1 = base[fd][c + 1], b2 = base[fd][c + 2], b3 = base[fd][c + 3];
-        int bb[4] = {b0, b1, b2, b3};
+      for (int c = wv; c < nc; c += 4) {
+        const int bb = base[cd][c];
+        const int la = (cpack & 255) - (bb & 255);
+        const int lb = ((cpack >> 8) & 255) - ((bb >> 8) & 255);
+        if ((unsigned)la < (unsigned)W && (unsigned)lb < (unsigned)W) {
+          const double wab = wts[c][cd][0][la] * wts[c][cd][1][lb];
+          const int lk0 = 64 - ((bb >> 16) & 255);  // z node offset of face fk = 0
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          int la = (fpack & 255) - (bb[u] & 255);
-          int lb = ((fpack >> 8) & 255) - ((bb[u] >> 8) & 255);
-          int lc = ((fpack >> 16) & 255) - ((bb[u] >> 16) & 255);
-          if ((unsigned)la < (unsigned)W && (unsigned)lb < (unsigned)W && (unsigned)lc < (unsigned)W)
-            acc += (wts[c + u][fd][0][la] * wts[c + u][fd][1][lb]) * wts[c + u][fd][2][lc];
+          for (int fk = 0; fk < 5; ++fk) {
+            const int lc = lk0 + fk;
+            if (fk < nf && (unsigned)lc < (unsigned)W) acc[fk] += wab * wts[c][cd][2][lc];
+          }
         }
-      }
-      for (; c < nc; ++c) {
-        int bb = base[fd][c];
-        int la = (fpack & 255) - (bb & 255);
-        int lb = ((fpack >> 8) & 255) - ((bb >> 8) & 255);
-        int lc = ((fpack >> 16) & 255) - ((bb >> 16) & 255);
-        if ((unsigned)la < (unsigned)W && (unsigned)lb < (unsigned)W && (unsigned)lc < (unsigned)W)
-          acc += (wts[c][fd][0][la] * wts[c][fd][1][lb]) * wts[c][fd][2][lc];
       }
     }
   }
+  __syncthreads();
+  if (owner) {
+#pragma unroll
+    for (int fk = 0; fk < 5; ++fk) {
+      if (fk < nf) {
+        // face box index: (ci * by + cj) * bz + fk with by = 4 or 5, bz = 4 or 5
+        const int bz = cd == 2 ? 5 : 4;
+        part[wv][cd][(ci * cby + cj) * bz + fk] = acc[fk];
+      }
+    }
+  }
+  __syncthreads();
   long long N = 2 * g.half;
+  auto face = [&](int d, int idx) { return ((part[0][d][idx] + part[1][d][idx]) + part[2][d][idx]) + part[3][d][idx]; };
   if (DIV) {
-    if (owner) facev[fd][fl] = acc;
-    __syncthreads();
     if (tid < 64) {
-      int ci = tid >> 4, cj = (tid >> 2) & 3, ck = tid & 3;
+      int ci2 = tid >> 4, cj2 = (tid >> 2) & 3, ck = tid & 3;
       double dv = 0.0;
-      dv += facev[0][((ci + 1) * 4 + cj) * 4 + ck] - facev[0][(ci * 4 + cj) * 4 + ck];
-      dv += facev[1][(ci * 5 + cj + 1) * 4 + ck] - facev[1][(ci * 5 + cj) * 4 + ck];
-      dv += facev[2][(ci * 4 + cj) * 5 + ck + 1] - facev[2][(ci * 4 + cj) * 5 + ck];
-      int gi = 4 * T0 + ci, gj = 4 * T1 + cj, gk = 4 * T2 + ck;
+      dv += face(0, ((ci2 + 1) * 4 + cj2) * 4 + ck) - face(0, (ci2 * 4 + cj2) * 4 + ck);
+      dv += face(1, (ci2 * 5 + cj2 + 1) * 4 + ck) - face(1, (ci2 * 5 + cj2) * 4 + ck);
+      dv += face(2, (ci2 * 4 + cj2) * 5 + ck + 1) - face(2, (ci2 * 4 + cj2) * 5 + ck);
+      int gi = 4 * T0 + ci2, gj = 4 * T1 + cj2, gk = 4 * T2 + ck;
       out[sidx(g, gi, gj, gk)] += alpha * dv * ih;
     }
   } else {
-    // faces 0..3 along the component's axis belong to this tile
-    bool mine = owner && (fd == 0 ? fi < 4 : (fd == 1 ? fj < 4 : fk < 4));
-    if (mine) {
+    if (tid < 192) {
+      int d = tid >> 6, t = tid & 63;
+      int fi = t >> 4, fj = (t >> 2) & 3, fk = t & 3;
+      int by = 4 + (d == 1), bz = 4 + (d == 2);
       int gi = 4 * T0 + fi, gj = 4 * T1 + fj, gk = 4 * T2 + fk;
-      out[fd * N + sidx(g, gi, gj, gk)] += alpha * acc;
+      out[d * N + sidx(g, gi, gj, gk)] += alpha * face(d, (fi * by + fj) * bz + fk);
     }
   }
 }
@@ -542,6 +557,7 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
 hipError_t band_apply(int ker, bool div, const Geo &g, int nt1, int nt2, int nactive, const int *active,
                       const int *lstart, const int *list, const double *X, const double *q, double alpha,
                       double *out, hipStream_t s) {
+  ProbeScope probe_(div ? PR_BAND_DIV : PR_BAND_FACE, s);
   if (nactive == 0) return hipSuccess;
   dim3 gr(nactive), bl(256);
   if (ker == KER_PESKIN4) {

@@ -10,6 +10,7 @@
 // the coarsest grids entirely in LDS.  Kernels are templated on the working
 // precision T (float or double) and on the right-hand-side type TB.
 #include "internal.h"
+#include "march.h"
 
 namespace ibs {
 
@@ -38,45 +39,6 @@ __device__ __forceinline__ T nb_sum(const Geo &g, const T *x, int i, int j, int 
   t = nbr(k, -1, g.n2, g.bc2); if (t >= 0) s += o[row + (t >> 1)];
   t = nbr(k, 1, g.n2, g.bc2);  if (t >= 0) s += o[row + (t >> 1)];
   return s;
-}
-
-// First sweep from x = 0: red x = h^2 b / nnb; black uses those red values,
-// which it recomputes from b instead of reading x.
-template <typename T, typename TB>
-__global__ void k_smooth_first(Geo g, T *x, const TB *b) {
-  RowPos p;
-  if (!row_pos(g, p)) return;
-  T h2 = (T)g.h2;
-  int nn = cell_nnb(g, p.i, p.j, p.k);
-  if (p.c == 0) {
-    x[p.e] = h2 * (T)b[p.e] / (T)nn;
-    return;
-  }
-  const TB *o = b;  // red plane
-  T s = T(0);
-  int t;
-#define RED_NB(ii, jj, kk)                                                                  \
-  {                                                                                         \
-    long long q = ((long long)(ii) * g.n1 + (jj)) * g.hn2 + ((kk) >> 1);                   \
-    s += h2 * (T)o[q] / (T)cell_nnb(g, ii, jj, kk);                                         \
-  }
-  t = nbr(p.i, -1, g.n0, g.bc0); if (t >= 0) RED_NB(t, p.j, p.k);
-  t = nbr(p.i, 1, g.n0, g.bc0);  if (t >= 0) RED_NB(t, p.j, p.k);
-  t = nbr(p.j, -1, g.n1, g.bc1); if (t >= 0) RED_NB(p.i, t, p.k);
-  t = nbr(p.j, 1, g.n1, g.bc1);  if (t >= 0) RED_NB(p.i, t, p.k);
-  t = nbr(p.k, -1, g.n2, g.bc2); if (t >= 0) RED_NB(p.i, p.j, t);
-  t = nbr(p.k, 1, g.n2, g.bc2);  if (t >= 0) RED_NB(p.i, p.j, t);
-#undef RED_NB
-  x[p.e] = (h2 * (T)b[p.e] + s) / (T)nn;
-}
-
-template <typename T, typename TB>
-__global__ void k_smooth(Geo g, T *x, const TB *b, int color) {
-  RowPos p;
-  if (!row_pos1m(g, color, p)) return;
-  T s = nb_sum(g, (const T *)x, p.i, p.j, p.k, p.c, p.m);
-  int nn = cell_nnb(g, p.i, p.j, p.k);
-  x[p.e] = ((T)g.h2 * (T)b[p.e] + s) / (T)nn;
 }
 
 // Coarse right-hand side: the average of the fine residual over the eight
@@ -135,14 +97,14 @@ __global__ void k_prolong(Geo gf, T *xf, Geo gc, const T *xc) {
 
 template <typename T, typename TB>
 hipError_t mg_smooth_first(const Geo &g, T *x, const TB *b, hipStream_t s) {
-  RowLaunch L = row_launch(g, 2 * g.n0);
-  hipLaunchKernelGGL((k_smooth_first<T, TB>), L.grid, L.block, 0, s, g, x, b);
+  MarchShape M = march_shape(g, 1);
+  hipLaunchKernelGGL((k_sweep<T, TB, SW_FIRST>), M.grid, M.block, 0, s, g, x, b, 1, g.h2, 0.0, 0.0, 1.0);
   return hipGetLastError();
 }
 template <typename T, typename TB>
 hipError_t mg_smooth(const Geo &g, T *x, const TB *b, int color, hipStream_t s) {
-  RowLaunch L = row_launch(g, g.n0);
-  hipLaunchKernelGGL((k_smooth<T, TB>), L.grid, L.block, 0, s, g, x, b, color);
+  MarchShape M = march_shape(g, 1);
+  hipLaunchKernelGGL((k_sweep<T, TB, SW_POISSON>), M.grid, M.block, 0, s, g, x, b, color, g.h2, 0.0, 0.0, 1.0);
   return hipGetLastError();
 }
 template <typename T, typename TB>

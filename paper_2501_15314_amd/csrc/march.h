@@ -1,0 +1,332 @@
+// Plane-marching stencil kernels on the red/black split layout.
+//
+// A workgroup owns a tile of BY rows (axis 1) x 2*BX in-row indices m
+// (axis 2, two per thread, accessed as 2-vectors) and marches over a chunk of
+// MARCH_CH planes along axis 0.  The x-neighbours of a cell come from a
+// register window over three planes, the y- and z-neighbours from an LDS copy
+// of the current plane with a one-cell halo.  BX divides hn2/2 and BY divides
+// n1, so no workgroup is partial and every halo cell is loaded.
+#pragma once
+#include "internal.h"
+
+namespace ibs {
+
+constexpr int MARCH_CH = 8;       // planes per workgroup
+constexpr int MARCH_TILE = 1104;  // >= max (BY+2)(2BX+2) over BX*BY <= 256
+
+struct MarchShape {
+  int bx, by;
+  dim3 grid, block;
+};
+
+inline int pow2_divisor(int n, int cap) {
+  int p = 1;
+  while (p * 2 <= cap && n % (p * 2) == 0) p *= 2;
+  return p;
+}
+
+// ncomp stacks independent component grids along grid.z.
+inline MarchShape march_shape(const Geo &g, int ncomp) {
+  MarchShape s;
+  s.bx = pow2_divisor(g.hn2 / 2, 64);
+  s.by = pow2_divisor(g.n1, 256 / s.bx);
+  s.block = dim3(s.bx, s.by, 1);
+  int nch = (g.n0 + MARCH_CH - 1) / MARCH_CH;
+  s.grid = dim3(g.hn2 / (2 * s.bx), g.n1 / s.by, nch * ncomp);
+  return s;
+}
+
+template <typename T>
+struct V2 {
+  T x, y;
+};
+// 2-vector load of S values converted to R
+template <typename R, typename S>
+__device__ __forceinline__ V2<R> ld2(const S *p) {
+  V2<R> v;
+  if (sizeof(S) == 4) {
+    float2 f = *(const float2 *)p;
+    v.x = (R)f.x;
+    v.y = (R)f.y;
+  } else {
+    double2 f = *(const double2 *)p;
+    v.x = (R)f.x;
+    v.y = (R)f.y;
+  }
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ void st2(T *p, T a, T b) {
+  if (sizeof(T) == 4) {
+    *(float2 *)p = make_float2((float)a, (float)b);
+  } else {
+    *(double2 *)p = make_double2((double)a, (double)b);
+  }
+}
+
+// Coordinate wrap for periodic axes; -1 if outside a wall box.
+__device__ __forceinline__ int mwrap(int i, int n, int bc) {
+  if (i < 0) return bc ? -1 : i + n;
+  if (i >= n) return bc ? -1 : i - n;
+  return i;
+}
+
+// Per-block geometry of a march.
+struct MarchPos {
+  int tx, ty, m0, j, i0, i1, comp;
+};
+__device__ __forceinline__ MarchPos march_pos(const Geo &g) {
+  MarchPos p;
+  p.tx = threadIdx.x;
+  p.ty = threadIdx.y;
+  p.m0 = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
+  p.j = blockIdx.y * blockDim.y + threadIdx.y;
+  int nch = (g.n0 + MARCH_CH - 1) / MARCH_CH;
+  p.comp = blockIdx.z / nch;
+  int ch = blockIdx.z - p.comp * nch;
+  p.i0 = ch * MARCH_CH;
+  p.i1 = min(p.i0 + MARCH_CH, g.n0);
+  return p;
+}
+
+// Load the one-cell halo of the plane tile (rows ty = -1, BY and columns
+// m = -1, 2BX) cooperatively; val(i, j, m) returns the value of a plane at an
+// in-domain position (already wrapped), 0 is stored outside a wall box.
+template <typename T, class F>
+__device__ __forceinline__ void tile_halo(T *tile, const Geo &g, int i, int jbase, int mbase, int BX, int BY,
+                                          F val) {
+  const int W2 = 2 * BX + 2;
+  const int nrow = 2 * (2 * BX), ncol = 2 * BY;
+  const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+  for (int h = tid; h < nrow + ncol; h += blockDim.x * blockDim.y) {
+    int r, cidx;
+    if (h < nrow) {
+      r = h < 2 * BX ? 0 : BY + 1;
+      cidx = 1 + (h % (2 * BX));
+    } else {
+      int q = h - nrow;
+      r = 1 + (q >> 1);
+      cidx = (q & 1) ? 2 * BX + 1 : 0;
+    }
+    int jj = mwrap(jbase + r - 1, g.n1, g.bc1);
+    int mm = mwrap(mbase + cidx - 1, g.hn2, g.bc2);
+    T v = T(0);
+    if (jj >= 0 && mm >= 0 && (unsigned)i < (unsigned)g.n0) v = val(i, jj, mm);
+    tile[r * W2 + cidx] = v;
+  }
+}
+
+}  // namespace ibs
+
+namespace ibs {
+
+// One red-black half sweep of colour `color` on the component grids of x.
+//   SW_POISSON: x_c = (h^2 b_c + sum of neighbours) / (number of neighbours)
+//               (Gauss-Seidel for L = G^T G);
+//   SW_FIRST:   the first pressure sweep from x = 0, colour 1: the colour-0
+//               values h^2 b / nnb are formed on the fly from b (and stored),
+//               then the colour-1 update as above;
+//   SW_HELM:    SOR for A = a0 - nu Delta_h on velocity component `comp`:
+//               x_c += omega ((b_c + nu/h^2 sum) / (a0 + nu/h^2 diag) - x_c),
+//               wall faces untouched.  Neighbours outside a wall box are 0
+//               (normal walls hold 0, tangential ghosts enter the diagonal).
+enum { SW_POISSON = 0, SW_FIRST = 1, SW_HELM = 2 };
+
+template <typename T, typename TB, int MODE>
+__global__ void __launch_bounds__(256) k_sweep(Geo g, T *x, const TB *b, int color, double h2, double a0,
+                                               double nuh2, double omega) {
+  __shared__ T tile[MARCH_TILE];
+  const MarchPos p = march_pos(g);
+  const int BX = blockDim.x, BY = blockDim.y, W2 = 2 * BX + 2;
+  const long long N = 2 * g.half;
+  const int d = p.comp;
+  T *xg = x + d * N;
+  const TB *bg = b + d * N;
+  const int c = color;
+  T *own = xg + (long long)c * g.half;
+  T *oth = xg + (long long)(1 - c) * g.half;
+  const TB *bown = bg + (long long)c * g.half;
+  const TB *both = bg + (long long)(1 - c) * g.half;
+  const int mbase = blockIdx.x * BX * 2, jbase = blockIdx.y * BY;
+  auto row = [&](int i, int jj) { return ((long long)i * g.n1 + jj) * g.hn2; };
+  auto oval = [&](int i, int jj, int mm) -> T {
+    if (MODE == SW_FIRST) {
+      int kk = 2 * mm + ((i + jj) & 1);  // colour-0 cell of row (i, jj) at index mm
+      return (T)h2 * (T)both[row(i, jj) + mm] / (T)cell_nnb(g, i, jj, kk);
+    }
+    return oth[row(i, jj) + mm];
+  };
+  auto owin = [&](int i) -> V2<T> {
+    V2<T> v;
+    v.x = T(0);
+    v.y = T(0);
+    int ii = mwrap(i, g.n0, g.bc0);
+    if (ii < 0) return v;
+    if (MODE == SW_FIRST) {
+      v.x = oval(ii, p.j, p.m0);
+      v.y = oval(ii, p.j, p.m0 + 1);
+      return v;
+    }
+    return ld2<T>(oth + row(ii, p.j) + p.m0);
+  };
+  const T th2 = (T)h2, ta0 = (T)a0, tnu = (T)nuh2, tom = (T)omega;
+  V2<T> prev = owin(p.i0 - 1), cur = owin(p.i0);
+  for (int i = p.i0; i < p.i1; ++i) {
+    V2<T> next = owin(i + 1);
+    tile[(p.ty + 1) * W2 + 2 * p.tx + 1] = cur.x;
+    tile[(p.ty + 1) * W2 + 2 * p.tx + 2] = cur.y;
+    tile_halo(tile, g, i, jbase, mbase, BX, BY, oval);
+    __syncthreads();
+    const long long r = row(i, p.j) + p.m0;
+    V2<T> bb = ld2<T>(bown + r);
+    V2<T> xo;
+    xo.x = T(0);
+    xo.y = T(0);
+    if (MODE == SW_HELM) xo = ld2<T>((const T *)own + r);
+    T out[2];
+    const int s = (c + i + p.j) & 1;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int m = p.m0 + u, k = 2 * m + s, col = 2 * p.tx + 1 + u;
+      const T *trow = tile + (p.ty + 1) * W2;
+      T sum = (u ? prev.y : prev.x) + (u ? next.y : next.x) + tile[p.ty * W2 + col] + tile[(p.ty + 2) * W2 + col] +
+              trow[col - 1 + s] + trow[col + s];
+      T bv = u ? bb.y : bb.x;
+      if (MODE != SW_HELM) {
+        out[u] = (th2 * bv + sum) / (T)cell_nnb(g, i, p.j, k);
+      } else {
+        const int xs[3] = {i, p.j, k};
+        int diag = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          int bca = geo_bc(g, a), na = geo_n(g, a);
+          diag += 2;
+          if (bca && a != d) diag += (xs[a] == 0) + (xs[a] == na - 1);
+        }
+        T xv = u ? xo.y : xo.x;
+        const int xd = d == 0 ? i : (d == 1 ? p.j : k);
+        bool wall = geo_bc(g, d) && xd == 0;
+        T gs = (bv + tnu * sum) / (ta0 + tnu * (T)diag);
+        out[u] = wall ? xv : xv + tom * (gs - xv);
+      }
+    }
+    st2(own + r, out[0], out[1]);
+    if (MODE == SW_FIRST) st2(oth + r, cur.x, cur.y);
+    __syncthreads();
+    prev = cur;
+    cur = next;
+  }
+}
+
+}  // namespace ibs
+
+namespace ibs {
+
+// Operators on both colours at once: every thread owns the four cells of
+// row (i, j) stored at in-row indices m0, m0+1 of both colour planes.
+//   AP_LAP:    y = L x  (x of type T, y double) for the pressure Laplacian;
+//   AP_HRESID: r = b - A x on velocity component `comp` (x, b double; r of
+//              type TR), plus per-block partial sums of r^2 into part.
+enum { AP_LAP = 0, AP_HRESID = 1 };
+
+template <typename T, typename TR, int MODE>
+__global__ void __launch_bounds__(256) k_apply2(Geo g, const T *x, const double *b, TR *out, double a0, double nuh2,
+                                                double *part) {
+  __shared__ T tile[2][MARCH_TILE];
+  __shared__ double red[4];
+  const MarchPos p = march_pos(g);
+  const int BX = blockDim.x, BY = blockDim.y, W2 = 2 * BX + 2;
+  const long long N = 2 * g.half;
+  const int d = p.comp;
+  const T *xg = x + d * N;
+  const double *bg = b ? b + d * N : nullptr;
+  TR *og = out + d * N;
+  const int mbase = blockIdx.x * BX * 2, jbase = blockIdx.y * BY;
+  auto row = [&](int i, int jj) { return ((long long)i * g.n1 + jj) * g.hn2; };
+  auto win = [&](int q, int i) -> V2<T> {
+    V2<T> v;
+    v.x = T(0);
+    v.y = T(0);
+    int ii = mwrap(i, g.n0, g.bc0);
+    if (ii < 0) return v;
+    return ld2<T>(xg + (long long)q * g.half + row(ii, p.j) + p.m0);
+  };
+  V2<T> prv[2], cur[2], nxt[2];
+  prv[0] = win(0, p.i0 - 1);
+  prv[1] = win(1, p.i0 - 1);
+  cur[0] = win(0, p.i0);
+  cur[1] = win(1, p.i0);
+  double acc = 0.0;
+  for (int i = p.i0; i < p.i1; ++i) {
+    nxt[0] = win(0, i + 1);
+    nxt[1] = win(1, i + 1);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      T *tq = tile[q];
+      tq[(p.ty + 1) * W2 + 2 * p.tx + 1] = cur[q].x;
+      tq[(p.ty + 1) * W2 + 2 * p.tx + 2] = cur[q].y;
+      const T *plane = xg + (long long)q * g.half;
+      tile_halo(tq, g, i, jbase, mbase, BX, BY,
+                [&](int ii, int jj, int mm) -> T { return plane[row(ii, jj) + mm]; });
+    }
+    __syncthreads();
+    const long long r = row(i, p.j) + p.m0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const T *to = tile[1 - q];
+      const int s = (q + i + p.j) & 1;
+      V2<double> bb;
+      bb.x = 0.0;
+      bb.y = 0.0;
+      if (MODE == AP_HRESID) bb = ld2<double>(bg + (long long)q * g.half + r);
+      double o[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int m = p.m0 + u, k = 2 * m + s, col = 2 * p.tx + 1 + u;
+        const T *trow = to + (p.ty + 1) * W2;
+        double sum = (double)(u ? prv[1 - q].y : prv[1 - q].x) + (double)(u ? nxt[1 - q].y : nxt[1 - q].x) +
+                     (double)to[p.ty * W2 + col] + (double)to[(p.ty + 2) * W2 + col] + (double)trow[col - 1 + s] +
+                     (double)trow[col + s];
+        double xv = (double)(u ? cur[q].y : cur[q].x);
+        if (MODE == AP_LAP) {
+          o[u] = ((double)cell_nnb(g, i, p.j, k) * xv - sum) / g.h2;
+        } else {
+          const int xs[3] = {i, p.j, k};
+          int diag = 0;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            int bca = geo_bc(g, a), na = geo_n(g, a);
+            diag += 2;
+            if (bca && a != d) diag += (xs[a] == 0) + (xs[a] == na - 1);
+          }
+          const int xd = d == 0 ? i : (d == 1 ? p.j : k);
+          bool wall = geo_bc(g, d) && xd == 0;
+          double rv = (u ? bb.y : bb.x) - ((a0 + nuh2 * diag) * xv - nuh2 * sum);
+          o[u] = wall ? 0.0 : rv;
+          acc += o[u] * o[u];
+        }
+      }
+      st2(og + (long long)q * g.half + r, (TR)o[0], (TR)o[1]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      prv[q] = cur[q];
+      cur[q] = nxt[q];
+    }
+  }
+  if (MODE == AP_HRESID) {
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    acc = wave_sum(acc);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      const int nw = (blockDim.x * blockDim.y + 63) / 64;
+      for (int w = 0; w < nw; ++w) t += red[w];
+      part[blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z)] = t;
+    }
+  }
+}
+
+}  // namespace ibs

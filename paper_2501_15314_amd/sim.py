@@ -174,6 +174,15 @@ class Sim:
         self._check(self.lib.sim_apply(self.h, opid, _ptr(x), _ptr(x2), _ptr(out)))
         return out[:self.K] if op == "interp" else out
 
+    def probe(self, name, on=True):
+        self._check(self.lib.sim_probe_enable(self.h, _lib.PROBES[name], int(on)))
+
+    def probe_read(self, name, reset=True):
+        n = C.c_int64()
+        ms = C.c_double()
+        self._check(self.lib.sim_probe_read(self.h, _lib.PROBES[name], C.byref(n), C.byref(ms), int(reset)))
+        return int(n.value), float(ms.value)
+
     def step_adjoint(self, gu=None, gp=None, gphi=None, want_inputs=False):
         gu = self._t(gu)
         comps = [gu[d] if gu is not None else None for d in range(3)]
