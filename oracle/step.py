@@ -136,9 +136,26 @@ class FreeBody:
                                             for f in dataclasses.fields(self)})
 
 
+def free_body(center, vel, omega, radius, theta, offsets, dt):
+    """A free sphere entering the first step in steady motion: u_s^{-1} = u_s^0,
+    omega^{-1} = omega^0, and the consistent centre X_c^{-1} = X_c^0 - dt u_s^0
+    (so that Step 1's BDF2 prediction advances a steadily moving body by
+    dt u_s); orientation R^0 = I."""
+    c = np.asarray(center, dtype=np.float64)
+    v = np.asarray(vel, dtype=np.float64)
+    w = np.asarray(omega, dtype=np.float64)
+    return FreeBody(radius=float(radius), theta=float(theta),
+                    offsets=np.asarray(offsets, dtype=np.float64), xc=c.copy(), xc_m=c - dt * v,
+                    us=v.copy(), us_m=v.copy(), w=w.copy(), w_m=w.copy(), R=np.eye(3))
+
+
+def domain_length(g: mac.Grid):
+    return tuple(n * g.h for n in g.n)
+
+
 def init_volume_history(g: mac.Grid, u, bodies):
     for b in bodies:
-        I, J = bd.volume_integrals(g, u, b.xc, b.radius)
+        I, J = bd.volume_integrals(g, u, b.xc, b.radius, domain_length(g))
         b.I_n, b.J_n = I, J
         b.I_m, b.J_m = I.copy(), J.copy()
 
@@ -166,16 +183,18 @@ def two_way_step(g: mac.Grid, nu, dt, gvec, state: State, bodies, kernel, c, xi,
     crit_hist, iters = [], []
     us_k = [b.us.copy() for b in bodies]
     w_k = [b.w.copy() for b in bodies]
+    used = [None] * nb
     for k in range(n_outer):
         U = np.empty_like(X)
         for ib, b in enumerate(bodies):
             s0, s1 = starts[ib], starts[ib + 1]
             F = h3 * phi[s0:s1].sum(axis=0)
             T = h3 * np.cross(levers[ib], phi[s0:s1]).sum(axis=0)
-            Ik, Jk = bd.volume_integrals(g, uk, xc1[ib], b.radius)
+            Ik, Jk = bd.volume_integrals(g, uk, xc1[ib], b.radius, domain_length(g))
             us_k[ib], w_k[ib] = bd.newton_euler(b.theta, b.radius, dt, b.us, b.us_m, b.w, b.w_m,
                                                 F, T, Ik, b.I_n, b.I_m, Jk, b.J_n, b.J_m, gvec)
             U[s0:s1] = bd.point_velocities(us_k[ib], w_k[ib], levers[ib])
+            used[ib] = dict(F=F, T=T, I=Ik, J=Jk)
         uk, pp, phip, info = correction(sys, uk, U, dt, xi, schur_rtol)
         p = p + xi * pp
         phi = phi + xi * phip
@@ -192,9 +211,9 @@ def two_way_step(g: mac.Grid, nu, dt, gvec, state: State, bodies, kernel, c, xi,
         nbody.us_m, nbody.us = b.us.copy(), us_k[ib]
         nbody.w_m, nbody.w = b.w.copy(), w_k[ib]
         nbody.R = R1[ib]
-        I1, J1 = bd.volume_integrals(g, uk, xc1[ib], b.radius)
+        I1, J1 = bd.volume_integrals(g, uk, xc1[ib], b.radius, domain_length(g))
         nbody.I_m, nbody.I_n = b.I_n.copy(), I1
         nbody.J_m, nbody.J_n = b.J_n.copy(), J1
         new_bodies.append(nbody)
     new = State(uk, state.u.copy(), p, phi, state.t + dt)
-    return new, new_bodies, dict(crit=crit_hist, iters=iters, X=X, W=W)
+    return new, new_bodies, dict(crit=crit_hist, iters=iters, X=X, W=W, used=used)

@@ -434,3 +434,121 @@ def test_newton_euler_free_fall_limit():
                             np.zeros(3), np.zeros(3), np.zeros(3), (0, 0, -1.0))
     assert np.allclose(us, [0, 0, -2 / 3 * 0.01 * 0.5])
     assert np.allclose(w, 0)
+
+
+# --------------------------------------------------------------------------
+# two-way coupling (Sec. 3.2.1)
+
+def _two_way(n, bc, a, theta, gvec, u0=None, v0=(0, 0, 0), w0=(0, 0, 0), nsteps=1, n_outer=3,
+             xi=0.6, nu=0.002, dt=0.002, center=(0.5, 0.5, 0.5)):
+    g = _grid(n, (bc,) * 3)
+    K = int(round(4 * np.pi * a * a / g.h ** 2))
+    off = wl.fibonacci_offsets(K, a)
+    c = wl.lump_constant(delta.PESKIN4, g.h, K, a)
+    fb = [ostep.free_body(np.array(center, float), np.array(v0, float), np.array(w0, float),
+                          a, theta, off, dt)]
+    u0 = np.zeros((3,) + g.n) if u0 is None else u0
+    st = ostep.State(u0.copy(), u0.copy(), np.zeros(g.n), np.zeros((K, 3)))
+    ostep.init_volume_history(g, st.u, fb)
+    out = []
+    for _ in range(nsteps):
+        new, nbod, info = ostep.two_way_step(g, nu, dt, np.array(gvec, float), st, fb, delta.PESKIN4,
+                                             c, xi, n_outer)
+        out.append((st, fb, new, nbod, info))
+        st, fb = new, nbod
+    return g, out
+
+
+def test_two_way_fluid_momentum_balance():
+    """Periodic box: convection (divergence form), viscosity and the pressure
+    gradient sum to zero over the grid and the delta weights of a point sum to
+    one, so the BDF2 change of the fluid momentum equals the total spread force
+    h^3 sum Phi^{n+1} exactly, whatever the outer iterations did."""
+    n = 16
+    rng = np.random.default_rng(4)
+    u0 = wl.solenoidal_field(rng, (n, n, n), 1.0 / n, 0.05)
+    g, out = _two_way(n, P, 0.25, 1.5, (0, 0, -1.0), u0=u0, v0=(0.02, 0, 0), nsteps=2, n_outer=2)
+    for st, _, new, _, _ in out:
+        h3 = g.h ** 3
+        dm = h3 * (3 * new.u - 4 * st.u + st.um).sum(axis=(1, 2, 3)) / (2 * 0.002)
+        f = h3 * new.phi.sum(axis=0)
+        assert np.allclose(dm, f, rtol=1e-9, atol=1e-12 * np.abs(f).max())
+
+
+def test_two_way_ballistic_heavy_body():
+    """theta -> infinity without gravity: the fluid cannot change the body's
+    motion, so Step 1 must advance the centre by dt u_s and the orientation by
+    the angle dt |omega| about the fixed spin axis."""
+    v0, w0, dt = np.array([0.3, -0.2, 0.1]), np.array([0.0, 0.0, 2.0]), 0.002
+    g, out = _two_way(16, P, 0.25, 1e12, (0, 0, 0), v0=v0, w0=w0, nsteps=3, n_outer=2, dt=dt)
+    c0 = np.array([0.5, 0.5, 0.5])
+    for s, (_, _, _, nb, info) in enumerate(out, start=1):
+        b = nb[0]
+        assert np.allclose(b.us, v0, atol=1e-9) and np.allclose(b.w, w0, atol=1e-9)
+        assert np.allclose(b.xc, c0 + s * dt * v0, atol=1e-12)
+        ang = s * dt * 2.0
+        Rz = np.array([[np.cos(ang), -np.sin(ang), 0], [np.sin(ang), np.cos(ang), 0], [0, 0, 1]])
+        assert np.allclose(b.R, Rz, atol=1e-12)
+        assert np.allclose(info["X"], b.xc + b.offsets @ b.R.T, atol=1e-14)
+
+
+def test_two_way_settling_from_rest():
+    """A sphere released from rest (theta = 2) accelerates along g, slower than
+    free fall (theta - 1)/theta g because the fluid inside and around it must be
+    accelerated too; the inviscid added-mass value is (theta - 1)/(theta + 1/2) g.
+    At 4.8 cells per radius the regularised sphere is effectively larger than a,
+    which adds inertia, so the bracket is loose."""
+    theta, dt = 2.0, 0.002
+    g, out = _two_way(24, W_, 0.2, theta, (0, 0, -1.0), nsteps=1, n_outer=16, dt=dt)
+    b = out[0][3][0]
+    acc = 3 * b.us / (2 * dt)          # BDF2 from rest
+    free = (theta - 1) / theta
+    added = (theta - 1) / (theta + 0.5)
+    assert -free < acc[2] < -0.55 * added
+    assert np.abs(acc[:2]).max() < 1e-3 * abs(acc[2])
+    # the outer iterations contract
+    crit = out[0][4]["crit"]
+    assert crit[-1] < 0.05 * crit[0]
+
+
+def test_two_way_spin_down():
+    """A sphere spinning in fluid at rest (theta = 10): the first step shares its
+    angular momentum with the fluid it must carry (at least the enclosed fluid,
+    moment of inertia I_p / theta relative to the body's), after the start-up
+    transient the surrounding fluid keeps slowing it down, and the spin axis
+    stays put."""
+    theta, w0 = 10.0, np.array([0.0, 0.0, 3.0])
+    g, out = _two_way(16, P, 0.25, theta, (0, 0, 0), w0=w0, nsteps=6, n_outer=4)
+    wz = [o[3][0].w[2] for o in out]
+    # theta I_p w0 = (theta I_p + X I_p) w1 with the carried inertia X I_p, X > 1
+    X = theta * (w0[2] / wz[0] - 1.0)
+    assert 1.0 < X < 4.0
+    assert wz[3] > wz[4] > wz[5] > 0
+    for o in out:
+        assert np.abs(o[3][0].w[:2]).max() < 1e-3 * wz[0]
+
+
+def test_two_way_drag_along():
+    """A body at rest in a uniformly moving periodic fluid is dragged along:
+    0 < u_s < U0 along the flow."""
+    n, U0 = 16, 0.1
+    u0 = np.zeros((3, n, n, n))
+    u0[0] = U0
+    g, out = _two_way(n, P, 0.25, 2.0, (0, 0, 0), u0=u0, nsteps=2, n_outer=4)
+    us = [o[3][0].us for o in out]
+    assert 0 < us[0][0] < us[1][0] < U0
+    assert np.abs(us[1][1:]).max() < 1e-2 * us[1][0]
+
+
+def test_two_way_steady_translation():
+    """Galilean consistency: a sphere moving with a uniform periodic flow stays
+    in it (the BDF2 weights of the enclosed-fluid momentum sum to zero for a
+    steady state); only the small change of the discrete enclosed volume as the
+    sphere crosses cells perturbs it."""
+    n, U0 = 16, 0.1
+    u0 = np.zeros((3, n, n, n))
+    u0[0] = U0
+    g, out = _two_way(n, P, 0.25, 2.0, (0, 0, 0), u0=u0, v0=(U0, 0, 0), nsteps=2, n_outer=3)
+    for _, _, new, nb, _ in out:
+        assert np.abs(nb[0].us - [U0, 0, 0]).max() < 2e-3 * U0
+        assert np.abs(new.u[0] - U0).max() < 2e-2 * U0
