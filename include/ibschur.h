@@ -97,7 +97,12 @@ typedef struct {
 /* A rigid sphere.  Prescribed motion: centre(t) = center + vel t
  * - osc_amp cos(osc_omega t), constant angular velocity omega.  Free motion:
  * center / vel / omega are the state at the current time, advanced by the
- * discrete Newton-Euler equations (paper Sec. 3.2.1). */
+ * discrete Newton-Euler equations (paper Sec. 3.2.1) with the body's volume
+ * V_p = 4/3 pi radius^3 and moment of inertia 2/5 V_p radius^2 in fluid-density
+ * units; the body enters its first step in steady motion (previous velocity
+ * levels equal to the current ones, previous centre = center - dt vel) and
+ * with orientation R = I.  The bodies of one handle are either all prescribed
+ * or all free. */
 typedef struct {
   double center[3], vel[3], omega[3];
   double radius;
@@ -158,9 +163,17 @@ sim_status sim_set_fields(sim_t sim, int32_t level, const double *d_u, const dou
 /* Copy the state at t^n out (any pointer may be NULL). */
 sim_status sim_get_fields(sim_t sim, double *d_u, double *d_v, double *d_w, double *d_p);
 
-/* Advance nsteps time steps (paper Sec. 3.1 for prescribed bodies, Sec. 3.2.1
- * when any body is free): momentum predictor (eq. ustar), then outer_iters
- * pressure-force corrections.  stats (may be NULL) describe the last step. */
+/* Advance nsteps time steps.  Prescribed bodies (paper Sec. 3.1): momentum
+ * predictor (eq. ustar), then outer_iters pressure-force corrections.  Free
+ * bodies (Sec. 3.2.1): Step 1 predicts centres and orientations, Step 2 is the
+ * momentum predictor, Step 3 repeats {per-body force, torque and volume
+ * integrals of the fluid velocity (eq. volume_integrals) -> Newton-Euler on
+ * the host (eqs. bdy_linear_vel_iter, bdy_angular_vel_iter) -> point
+ * velocities -> pressure-force correction relaxed by xi} outer_iters times or
+ * until ||Phi'||_1 / ||Phi||_1 < outer_tol (eq. convergence_criterion).
+ * Errors: SIM_EINVAL if a kernel support would cross a no-slip wall,
+ * SIM_ENONFINITE, SIM_ENOTCONV (the step is still completed).  stats (may be
+ * NULL) describe the last step. */
 sim_status sim_step(sim_t sim, int32_t nsteps, sim_step_stats *stats);
 
 /* One pressure-force correction solve on caller data at the current point
@@ -176,6 +189,13 @@ sim_status sim_get_forces(sim_t sim, double *d_f, double *body_ft);
 
 /* Current point positions and velocities, [K][3] each (either may be NULL). */
 sim_status sim_get_points(sim_t sim, double *d_X, double *d_U);
+
+/* Rigid-body state at the current time, host array [nb][18] in body order:
+ * centre X_c (0..2), velocity u_s (3..5), angular velocity omega in the
+ * inertial frame (6..8), orientation R row-major (9..17; maps body-frame
+ * offsets to inertial ones, Sec. 2.2).  Prescribed bodies report their
+ * prescribed kinematics.  SIM_ESTATE without bodies. */
+sim_status sim_get_body_state(sim_t sim, double *state);
 
 /* Reverse-mode derivative of the last one-way step (prescribed bodies, one
  * correction).  Inputs are the cotangents of (u^{n+1}, v, w, p^{n+1},

@@ -39,6 +39,7 @@ struct HostBody {
   // free-motion state (inertial frame)
   double xc[3], xc_m[3], us[3], us_m[3], w[3], w_m[3], R[9];
   double I_n[3], I_m[3], J_n[3], J_m[3];
+  double xc1[3], R1[9];  // predicted centre and orientation of the step in progress
 };
 
 struct Level {
@@ -88,6 +89,12 @@ struct sim_s {
   int ntouch = 0;
   BodyDev *BODIES = nullptr;
   std::vector<HostBody> bodies;
+  bool any_free = false;
+  // two-way sums: node boxes, per-body results [nb][12], volume-integral partials
+  BodySpan *SPAN = nullptr;
+  double *BSUM = nullptr, *VPART = nullptr;
+  bool vol_init = false;
+  std::vector<BodySpan> hspan;  // host copy (kept alive for the asynchronous upload)
   // reductions
   double *PART = nullptr, *RED = nullptr, *YDEV = nullptr;
   double *hpin = nullptr;
@@ -212,6 +219,9 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
   int *TLTMP = cv.arr<int>(tl_cap), *TLIST = cv.arr<int>(tl_cap), *SEGOF = cv.arr<int>(tl_cap);
   int *NZT = cv.arr<int>(nt);
   BodyDev *BODIES = (BodyDev *)cv.take(sizeof(BodyDev) * MAX_BODIES);
+  BodySpan *SPAN = (BodySpan *)cv.take(sizeof(BodySpan) * MAX_BODIES);
+  double *BSUM = cv.arr<double>(12LL * MAX_BODIES);
+  double *VPART = cv.arr<double>(9LL * VOL_CHUNKS * MAX_BODIES);
   int rb = std::max(red_blocks(), 1);
   long long parts = std::max<long long>((long long)rb * (MAX_RESTART + 2), 0);
   // helm_resid writes one partial per row-launch block
@@ -230,6 +240,7 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
     s->XS = XS; s->US = US; s->Q = Q; s->RF = RF; s->PHIP = PHIP; s->PHIS = PHIS; s->PT3 = PT3;
     s->COUNTS = COUNTS; s->TSTART = TSTART; s->FILLC = FILLC; s->FLAGS = FLAGS; s->FPOS = FPOS;
     s->ACTIVE = ACTIVE; s->SCANTMP = SCANTMP; s->BODIES = BODIES;
+    s->SPAN = SPAN; s->BSUM = BSUM; s->VPART = VPART;
     s->TCOUNT = TCOUNT; s->TLSTART = TLSTART; s->TFILL = TFILL; s->TLTMP = TLTMP; s->TLIST = TLIST;
     s->SEGOF = SEGOF; s->tl_cap = tl_cap; s->NZT = NZT;
     s->PART = PART; s->RED = RED; s->YDEV = YDEV;
@@ -679,92 +690,296 @@ sim_status helm_solve_any(sim_t s, const double *rhs, double *u, sim_solve_stats
 }
 
 // ---------------------------------------------------------------------------
-// One-way step (prescribed motion) with outer_iters corrections.
-sim_status step_one_way(sim_t s, sim_step_stats *out) {
+// One-way (prescribed motion) and two-way (free bodies) time steps.
+
+// Step 2 of both schemes: momentum right-hand side with W Phi^n spread on the
+// band, then u* from the extrapolated guess 2 u^n - u^{n-1}.
+sim_status predictor(sim_t s, sim_step_stats &S, sim_status &hrc) {
   hipStream_t st = s->st;
   const sim_config &c = s->cfg;
-  const long long N = s->N, n3 = 3 * N;
-  const double tau = 2.0 * c.dt / 3.0;
-  sim_status rc;
-  hipEvent_t e0, e1;
-  CKH(hipEventCreate(&e0));
-  CKH(hipEventCreate(&e1));
-  CKH(hipEventRecord(e0, st));
-  double t1 = s->t + c.dt;
-  std::vector<BodyDev> bd = body_states_at(s, t1);
-  if ((rc = place_and_bin(s, bd))) return rc;
-  // Phi^n in tile order
+  const long long n3 = 3 * s->N;
   CKH(gather3(s->K, s->PERM, s->PHIN, s->PHIS, st));
-  // momentum right-hand side, W Phi^n added on the band
   CKH(mom_rhs(s->g, c.dt, s->U, s->UM, s->P, s->RHSU, st));
   CKH(band_apply(s->ker, false, s->g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, s->PHIS, 1.0,
                  s->RHSU, st));
-  // u* from the extrapolated guess 2 u^n - u^{n-1}
   CKH(scale_copy(s->USTAR, s->U, n3, 2.0, st));
   CKH(axpby(s->USTAR, s->UM, n3, -1.0, 1.0, st));
   CKH(zero_wall_faces(s->g, s->USTAR, st));
-  sim_step_stats S{};
-  sim_status hrc = helm_solve_any(s, s->RHSU, s->USTAR, &S.helm);
+  hrc = helm_solve_any(s, s->RHSU, s->USTAR, &S.helm);
   if (hrc != SIM_OK && hrc != SIM_ENOTCONV) return hrc;
-  double divstar = 0.0;
-  sim_status src = SIM_OK;
-  for (int k = 0; k < c.outer_iters; ++k) {
-    CKH(div_apply(s->g, s->USTAR, s->RHSP, -1.0 / tau, st));
-    if (k == 0) {
-      double d2;
-      if ((rc = dev_norm2(s, s->RHSP, N, &d2))) return rc;
-      divstar = sqrt(d2) * tau;
-    }
-    CKH(interp_face(s->ker, s->g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, s->USTAR, 1.0 / tau, s->US, -1.0 / tau, s->RF, st));
-    src = schur_solve_core(s, &S.schur);
-    if (src != SIM_OK && src != SIM_ENOTCONV) return src;
-    S.total_schur_iters += S.schur.iters;
-    // u <- u* + xi tau (-G p' + W Phi') ; p += xi p' ; Phi += xi Phi'
-    CKH(grad_apply(s->g, s->PP, s->USTAR, -c.xi * tau, s->USTAR, st));
-    CKH(band_apply(s->ker, false, s->g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, s->PHIP,
-                   c.xi * tau, s->USTAR, st));
-    CKH(axpby(s->P, s->PP, N, c.xi, 1.0, st));
-    CKH(scale3(s->K, s->PHIP, c.xi, s->PHIS, 1.0, s->PHIS, st));
-    // outer criterion ||Phi'||_1 / ||Phi||_1 (host, small)
-    S.outer = k + 1;
-    if (c.outer_tol > 0 || k + 1 == c.outer_iters) {
-      std::vector<double> a(3 * (size_t)s->K), b(3 * (size_t)s->K);
-      if (s->K > 0) {
-        CKH(hipMemcpyAsync(a.data(), s->PHIP, sizeof(double) * 3 * s->K, hipMemcpyDeviceToHost, st));
-        CKH(hipMemcpyAsync(b.data(), s->PHIS, sizeof(double) * 3 * s->K, hipMemcpyDeviceToHost, st));
-        CKH(hipStreamSynchronize(st));
-      }
-      double na = 0, nbb = 0;
-      for (size_t q = 0; q < a.size(); ++q) { na += fabs(c.xi * a[q]); nbb += fabs(b[q]); }
-      S.outer_crit = nbb > 0 ? na / nbb : 0.0;
-      if (c.outer_tol > 0 && S.outer_crit < c.outer_tol) break;
-    }
+  return SIM_OK;
+}
+
+// One pressure / force correction on u^(k) = USTAR with the point velocities
+// in US: solves eq. Saddle (Sec. 3.1) / eq. pressure_force_iterative_system
+// (Sec. 3.2.1), then u += xi tau (-G p' + W Phi'), p += xi p', Phi += xi Phi'.
+// Sets S.outer_crit = ||Phi'||_1 / ||Phi^(k+1)||_1 (eq. convergence_criterion)
+// when want_crit.
+sim_status correction(sim_t s, int k, bool want_crit, sim_step_stats &S, double &divstar, sim_status &src) {
+  hipStream_t st = s->st;
+  const sim_config &c = s->cfg;
+  const long long N = s->N;
+  const double tau = 2.0 * c.dt / 3.0;
+  sim_status rc;
+  CKH(div_apply(s->g, s->USTAR, s->RHSP, -1.0 / tau, st));
+  if (k == 0) {
+    double d2;
+    if ((rc = dev_norm2(s, s->RHSP, N, &d2))) return rc;
+    divstar = sqrt(d2) * tau;
   }
+  CKH(interp_face(s->ker, s->g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, s->USTAR, 1.0 / tau, s->US,
+                  -1.0 / tau, s->RF, st));
+  src = schur_solve_core(s, &S.schur);
+  if (src != SIM_OK && src != SIM_ENOTCONV) return src;
+  S.total_schur_iters += S.schur.iters;
+  CKH(grad_apply(s->g, s->PP, s->USTAR, -c.xi * tau, s->USTAR, st));
+  CKH(band_apply(s->ker, false, s->g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, s->PHIP,
+                 c.xi * tau, s->USTAR, st));
+  CKH(axpby(s->P, s->PP, N, c.xi, 1.0, st));
+  CKH(scale3(s->K, s->PHIP, c.xi, s->PHIS, 1.0, s->PHIS, st));
+  S.outer = k + 1;
+  if (want_crit) {
+    std::vector<double> a(3 * (size_t)s->K), b(3 * (size_t)s->K);
+    if (s->K > 0) {
+      CKH(hipMemcpyAsync(a.data(), s->PHIP, sizeof(double) * 3 * s->K, hipMemcpyDeviceToHost, st));
+      CKH(hipMemcpyAsync(b.data(), s->PHIS, sizeof(double) * 3 * s->K, hipMemcpyDeviceToHost, st));
+    }
+    CKH(hipStreamSynchronize(st));
+    double na = 0, nbb = 0;
+    for (size_t q = 0; q < a.size(); ++q) { na += fabs(a[q]); nbb += fabs(b[q]); }
+    S.outer_crit = nbb > 0 ? na / nbb : (na > 0 ? INFINITY : 0.0);
+  }
+  return SIM_OK;
+}
+
+// Diagnostics and the rotation of the time levels after the corrections.
+sim_status finish_step(sim_t s, double t1, double divstar, sim_step_stats &S) {
+  hipStream_t st = s->st;
+  const long long N = s->N;
+  sim_status rc;
   CKH(scatter3(s->K, s->PERM, s->PHIS, s->PHIN, st));
-  // diagnostics: divergence and slip of the new velocity
   CKH(div_apply(s->g, s->USTAR, s->TMPC, 1.0, st));
   double dn2;
   if ((rc = dev_norm2(s, s->TMPC, N, &dn2))) return rc;
   S.div_rel = divstar > 0 ? sqrt(dn2) / divstar : 0.0;
-  CKH(interp_face(s->ker, s->g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, s->USTAR, 1.0, s->US, -1.0, s->PT3, st));
+  CKH(interp_face(s->ker, s->g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, s->USTAR, 1.0, s->US, -1.0, s->PT3,
+                  st));
   if (s->K > 0) {
     double sl2, u2;
     if ((rc = dev_norm2(s, s->PT3, 3LL * s->K, &sl2))) return rc;
     if ((rc = dev_norm2(s, s->US, 3LL * s->K, &u2))) return rc;
     S.slip_rel = u2 > 0 ? sqrt(sl2 / u2) : 0.0;
   }
-  // rotate time levels: u^{n-1} <- u^n, u^n <- u^{n+1}
+  // u^{n-1} <- u^n, u^n <- u^{n+1}
   std::swap(s->UM, s->U);
   std::swap(s->U, s->USTAR);
   s->t = t1;
   ++s->nstep;
-  CKH(hipEventRecord(e1, st));
-  CKH(hipEventSynchronize(e1));
-  float ms = 0;
-  CKH(hipEventElapsedTime(&ms, e0, e1));
-  S.seconds = ms * 1e-3;
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  return SIM_OK;
+}
+
+struct StepTimer {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipStream_t st;
+  explicit StepTimer(hipStream_t s) : st(s) {
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return;
+    hipEventRecord(e0, st);
+  }
+  double seconds() {
+    float ms = 0;
+    if (e0 && e1 && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess)
+      hipEventElapsedTime(&ms, e0, e1);
+    return ms * 1e-3;
+  }
+  ~StepTimer() {
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+  }
+};
+
+sim_status step_one_way(sim_t s, sim_step_stats *out) {
+  const sim_config &c = s->cfg;
+  StepTimer timer(s->st);
+  sim_status rc;
+  double t1 = s->t + c.dt;
+  std::vector<BodyDev> bd = body_states_at(s, t1);
+  if ((rc = place_and_bin(s, bd))) return rc;
+  sim_step_stats S{};
+  sim_status hrc = SIM_OK, src = SIM_OK;
+  if ((rc = predictor(s, S, hrc))) return rc;
+  double divstar = 0.0;
+  for (int k = 0; k < c.outer_iters; ++k) {
+    bool want = c.outer_tol > 0 || k + 1 == c.outer_iters;
+    if ((rc = correction(s, k, want, S, divstar, src))) return rc;
+    if (c.outer_tol > 0 && S.outer_crit < c.outer_tol) break;
+  }
+  if ((rc = finish_step(s, t1, divstar, S))) return rc;
+  S.seconds = timer.seconds();
+  s->last = S;
+  if (out) *out = S;
+  if (hrc == SIM_ENOTCONV) return fail(s, SIM_ENOTCONV, "momentum solve iteration limit reached");
+  return src;
+}
+
+// Node box of a sphere for the volume integrals: every velocity node within
+// a + h sqrt(3)/2 of the centre (the only ones with alpha > 0).
+BodySpan body_span(const sim_s *s, const HostBody &hb, const double c[3]) {
+  BodySpan sp{};
+  sp.k0 = hb.k0;
+  sp.kn = hb.kn;
+  sp.radius = hb.b.radius;
+  const double h = s->g.h;
+  for (int a = 0; a < 3; ++a) {
+    sp.c[a] = c[a];
+    const int n = s->cfg.n[a];
+    int lo = (int)floor((c[a] - hb.b.radius) / h) - 2;
+    int hi = (int)floor((c[a] + hb.b.radius) / h) + 3;  // exclusive
+    int dim = hi - lo;
+    if (dim > n) { lo = 0; dim = n; }  // never visit a node twice
+    sp.lo[a] = lo;
+    sp.dim[a] = dim;
+  }
+  return sp;
+}
+
+// Per-body sums on the device -> host: h3 sum Phi, torque (when phi given)
+// and the volume integrals of u at the spans' centres.
+sim_status body_sums(sim_t s, const double *phi_nat, const double *u, std::vector<double> &out) {
+  hipStream_t st = s->st;
+  const int nb = s->nb;
+  const double h3 = s->g.h * s->g.h * s->g.h;
+  if (phi_nat) CKH(body_force_torque(nb, s->BODIES, s->SPAN, s->OFF, phi_nat, h3, s->BSUM, st));
+  CKH(body_volume_integrals(s->g, nb, s->SPAN, u, s->VPART, s->BSUM, st));
+  out.assign(12 * (size_t)nb, 0.0);
+  CKH(hipMemcpyAsync(out.data(), s->BSUM, sizeof(double) * 12 * nb, hipMemcpyDeviceToHost, st));
+  CKH(hipStreamSynchronize(st));
+  for (double v : out)
+    if (!isfinite(v)) return fail(s, SIM_ENONFINITE, "non-finite body force or volume integral");
+  return SIM_OK;
+}
+
+sim_status upload_spans(sim_t s, bool predicted) {
+  CKH(hipStreamSynchronize(s->st));  // the previous upload has been consumed
+  s->hspan.resize(s->nb);
+  for (int i = 0; i < s->nb; ++i) {
+    const HostBody &hb = s->bodies[i];
+    s->hspan[i] = body_span(s, hb, predicted ? hb.xc1 : hb.xc);
+  }
+  CKH(hipMemcpyAsync(s->SPAN, s->hspan.data(), sizeof(BodySpan) * s->nb, hipMemcpyHostToDevice, s->st));
+  return SIM_OK;
+}
+
+// R^{n+1} = R^n R_Delta, R_Delta the rotation by the AB2 angle
+// dt (3/2 |w^n| - 1/2 |w^{n-1}|) about the body-frame axis of w^n (Sec. 2.2).
+void rotation_step(const double R[9], const double w[3], const double wm[3], double dt, double R1[9]) {
+  double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  if (wn == 0.0) {
+    memcpy(R1, R, sizeof(double) * 9);
+    return;
+  }
+  double wmn = sqrt(wm[0] * wm[0] + wm[1] * wm[1] + wm[2] * wm[2]);
+  double gamma = dt * (1.5 * wn - 0.5 * wmn);
+  double e[3] = {w[0] / wn, w[1] / wn, w[2] / wn}, ax[3];
+  for (int i = 0; i < 3; ++i) ax[i] = R[i] * e[0] + R[3 + i] * e[1] + R[6 + i] * e[2];  // R^T e
+  double Rd[9];
+  mat_rodrigues(ax, gamma, Rd);
+  mat_mul(R, Rd, R1);
+}
+
+// Two-way step (Sec. 3.2.1): Step 1 predicts the body positions and
+// orientations; Step 2 is the momentum predictor; Step 3 iterates Newton-Euler
+// on the host (from device sums of the forces and of the volume integrals) and
+// the pressure-force correction with relaxation xi, up to outer_iters times or
+// until ||Phi'||_1 / ||Phi||_1 < outer_tol.
+sim_status step_two_way(sim_t s, sim_step_stats *out) {
+  hipStream_t st = s->st;
+  const sim_config &c = s->cfg;
+  StepTimer timer(st);
+  sim_status rc;
+  const int nb = s->nb;
+  const double dt = c.dt, t1 = s->t + dt;
+  std::vector<double> sums;
+  // volume history at the start: levels n and n-1 both from u^0 at X_c^0
+  if (!s->vol_init) {
+    if ((rc = upload_spans(s, false))) return rc;
+    if ((rc = body_sums(s, nullptr, s->U, sums))) return rc;
+    for (int i = 0; i < nb; ++i) {
+      HostBody &hb = s->bodies[i];
+      for (int a = 0; a < 3; ++a) {
+        hb.I_n[a] = hb.I_m[a] = sums[12 * i + 6 + a];
+        hb.J_n[a] = hb.J_m[a] = sums[12 * i + 9 + a];
+      }
+    }
+    s->vol_init = true;
+  }
+  // Step 1: X_c^{n+1} = (4 X_c^n - X_c^{n-1}) / 3 + (2 dt / 3) u_s^n, R^{n+1}
+  std::vector<BodyDev> bd(nb);
+  for (int i = 0; i < nb; ++i) {
+    HostBody &hb = s->bodies[i];
+    for (int a = 0; a < 3; ++a) hb.xc1[a] = (4.0 * hb.xc[a] - hb.xc_m[a]) / 3.0 + (2.0 * dt / 3.0) * hb.us[a];
+    rotation_step(hb.R, hb.w, hb.w_m, dt, hb.R1);
+    for (int a = 0; a < 3; ++a) { bd[i].c[a] = hb.xc1[a]; bd[i].v[a] = hb.us[a]; bd[i].w[a] = hb.w[a]; }
+    memcpy(bd[i].R, hb.R1, sizeof(double) * 9);
+  }
+  if ((rc = place_and_bin(s, bd))) return rc;
+  if ((rc = upload_spans(s, true))) return rc;
+  // Step 2
+  sim_step_stats S{};
+  sim_status hrc = SIM_OK, src = SIM_OK;
+  if ((rc = predictor(s, S, hrc))) return rc;
+  // Step 3
+  const double tau = 2.0 * dt / 3.0;
+  std::vector<double> us_k(3 * (size_t)nb), w_k(3 * (size_t)nb);
+  double divstar = 0.0;
+  for (int k = 0; k < c.outer_iters; ++k) {
+    // forces of Phi^(n,k) (natural order) and volume integrals of u^(k)
+    CKH(scatter3(s->K, s->PERM, s->PHIS, s->PT3, st));
+    if ((rc = body_sums(s, s->PT3, s->USTAR, sums))) return rc;
+    for (int i = 0; i < nb; ++i) {
+      const HostBody &hb = s->bodies[i];
+      const double a = hb.b.radius, theta = hb.b.density_ratio;
+      const double Vp = 4.0 / 3.0 * M_PI * a * a * a, Ip = 0.4 * Vp * a * a;
+      const double *F = &sums[12 * i], *T = &sums[12 * i + 3], *Ik = &sums[12 * i + 6], *Jk = &sums[12 * i + 9];
+      for (int q = 0; q < 3; ++q) {
+        us_k[3 * i + q] = (4.0 * hb.us[q] - hb.us_m[q]) / 3.0 +
+                          tau / (theta * Vp) *
+                              (-F[q] + (3.0 * Ik[q] - 4.0 * hb.I_n[q] + hb.I_m[q]) / (2.0 * dt) +
+                               (theta - 1.0) * Vp * c.g[q]);
+        w_k[3 * i + q] = (4.0 * hb.w[q] - hb.w_m[q]) / 3.0 +
+                         tau / (theta * Ip) * (-T[q] + (3.0 * Jk[q] - 4.0 * hb.J_n[q] + hb.J_m[q]) / (2.0 * dt));
+      }
+      for (int q = 0; q < 3; ++q) { bd[i].v[q] = us_k[3 * i + q]; bd[i].w[q] = w_k[3 * i + q]; }
+      if (!isfinite(us_k[3 * i] + us_k[3 * i + 1] + us_k[3 * i + 2] + w_k[3 * i] + w_k[3 * i + 1] + w_k[3 * i + 2]))
+        return fail(s, SIM_ENONFINITE, "non-finite body velocity");
+    }
+    // U^(k) = u_s^(k) + omega^(k) x L~ at the predicted points, in tile order
+    CKH(hipMemcpyAsync(s->BODIES, bd.data(), sizeof(BodyDev) * nb, hipMemcpyHostToDevice, st));
+    CKH(points_place(s->g, s->K, s->BODIES, s->BODYOF, s->OFF, s->XN, s->UN, s->TILE, s->nt0, s->nt1, s->nt2, st));
+    CKH(gather3(s->K, s->PERM, s->UN, s->US, st));
+    bool want = c.outer_tol > 0 || k + 1 == c.outer_iters;
+    if ((rc = correction(s, k, want, S, divstar, src))) return rc;
+    if (c.outer_tol > 0 && S.outer_crit < c.outer_tol) break;
+  }
+  // volume integrals of u^{n+1} for the next step's history
+  if ((rc = body_sums(s, nullptr, s->USTAR, sums))) return rc;
+  for (int i = 0; i < nb; ++i) {
+    HostBody &hb = s->bodies[i];
+    for (int q = 0; q < 3; ++q) {
+      hb.xc_m[q] = hb.xc[q];
+      hb.xc[q] = hb.xc1[q];
+      hb.us_m[q] = hb.us[q];
+      hb.us[q] = us_k[3 * i + q];
+      hb.w_m[q] = hb.w[q];
+      hb.w[q] = w_k[3 * i + q];
+      hb.I_m[q] = hb.I_n[q];
+      hb.I_n[q] = sums[12 * i + 6 + q];
+      hb.J_m[q] = hb.J_n[q];
+      hb.J_n[q] = sums[12 * i + 9 + q];
+    }
+    memcpy(hb.R, hb.R1, sizeof(double) * 9);
+  }
+  if ((rc = finish_step(s, t1, divstar, S))) return rc;
+  S.seconds = timer.seconds();
   s->last = S;
   if (out) *out = S;
   if (hrc == SIM_ENOTCONV) return fail(s, SIM_ENOTCONV, "momentum solve iteration limit reached");
@@ -841,8 +1056,12 @@ sim_status sim_set_bodies(sim_t s, int32_t nb, const sim_body *bodies, const dou
   long long K = 0;
   for (int i = 0; i < nb; ++i) {
     if (bodies[i].n_points < 0 || !(bodies[i].radius >= 0)) return fail(s, SIM_EINVAL, "bad body");
-    if (bodies[i].motion == SIM_MOTION_FREE && !(bodies[i].density_ratio > 0))
-      return fail(s, SIM_EINVAL, "free body needs density_ratio > 0");
+    if (bodies[i].motion != SIM_MOTION_PRESCRIBED && bodies[i].motion != SIM_MOTION_FREE)
+      return fail(s, SIM_EINVAL, "bad motion type");
+    if (bodies[i].motion == SIM_MOTION_FREE && !(bodies[i].density_ratio > 0 && bodies[i].radius > 0))
+      return fail(s, SIM_EINVAL, "free body needs density_ratio > 0 and radius > 0");
+    if (bodies[i].motion != bodies[0].motion)
+      return fail(s, SIM_EINVAL, "bodies must be all prescribed or all free");
     K += bodies[i].n_points;
   }
   if (K > s->Kmax) return fail(s, SIM_EINVAL, "more points than max_points");
@@ -864,8 +1083,10 @@ sim_status sim_set_bodies(sim_t s, int32_t nb, const sim_body *bodies, const dou
     double c[3], v[3], R[9];
     prescribed_state(hb.b, s->t, c, v, R);
     if (hb.b.motion == SIM_MOTION_FREE) {
+      // steady motion before the first step: X_c^{-1} = X_c^0 - dt u_s^0
       for (int a = 0; a < 3; ++a) {
-        hb.xc[a] = hb.xc_m[a] = bodies[i].center[a];
+        hb.xc[a] = bodies[i].center[a];
+        hb.xc_m[a] = bodies[i].center[a] - s->cfg.dt * bodies[i].vel[a];
         hb.us[a] = hb.us_m[a] = bodies[i].vel[a];
         hb.w[a] = hb.w_m[a] = bodies[i].omega[a];
         hb.I_n[a] = hb.I_m[a] = hb.J_n[a] = hb.J_m[a] = 0.0;
@@ -876,6 +1097,8 @@ sim_status sim_set_bodies(sim_t s, int32_t nb, const sim_body *bodies, const dou
   }
   s->K = (int)K;
   s->nb = nb;
+  s->any_free = nb > 0 && bodies[0].motion == SIM_MOTION_FREE;
+  s->vol_init = false;
   hipStream_t st = s->st;
   if (K > 0) {
     CKH(hipMemcpyAsync(s->OFF, offsets, sizeof(double) * 3 * K, hipMemcpyHostToDevice, st));
@@ -901,6 +1124,7 @@ sim_status sim_set_fields(sim_t s, int32_t level, const double *d_u, const doubl
     CKH(to_split(s->g, 1, src[d], U + d * s->N, st));
   }
   CKH(zero_wall_faces(s->g, U, st));
+  s->vol_init = false;  // the volume history of free bodies restarts from the new u^n
   if (level == 0 && d_p) CKH(to_split(s->g, 1, d_p, s->P, st));
   if (level == 0 && d_phi && s->K > 0)
     CKH(hipMemcpyAsync(s->PHIN, d_phi, sizeof(double) * 3 * s->K, hipMemcpyDeviceToDevice, st));
@@ -915,6 +1139,23 @@ sim_status sim_get_fields(sim_t s, double *d_u, double *d_v, double *d_w, double
     if (dst[d]) CKH(to_natural(s->g, 1, s->U + d * s->N, dst[d], st));
   if (d_p) CKH(to_natural(s->g, 1, s->P, d_p, st));
   return sync(s);
+}
+
+sim_status sim_get_body_state(sim_t s, double *state) {
+  if (!s) return SIM_EINVAL;
+  if (!s->have_bodies) return fail(s, SIM_ESTATE, "no bodies set");
+  if (!state && s->nb > 0) return fail(s, SIM_EINVAL, "null argument");
+  std::vector<BodyDev> bd = body_states_at(s, s->t);
+  for (int i = 0; i < s->nb; ++i) {
+    double *o = state + 18 * i;
+    for (int a = 0; a < 3; ++a) {
+      o[a] = bd[i].c[a];
+      o[3 + a] = bd[i].v[a];
+      o[6 + a] = bd[i].w[a];
+    }
+    memcpy(o + 9, bd[i].R, sizeof(double) * 9);
+  }
+  return SIM_OK;
 }
 
 sim_status sim_get_points(sim_t s, double *d_X, double *d_U) {
@@ -981,11 +1222,9 @@ sim_status sim_step(sim_t s, int32_t nsteps, sim_step_stats *stats) {
   if (!s) return SIM_EINVAL;
   if (!s->have_bodies) return fail(s, SIM_ESTATE, "no bodies set");
   if (nsteps < 0) return fail(s, SIM_EINVAL, "nsteps < 0");
-  for (const HostBody &hb : s->bodies)
-    if (hb.b.motion == SIM_MOTION_FREE) return fail(s, SIM_EINVAL, "free bodies are not supported by this build");
   sim_status rc = SIM_OK;
   for (int i = 0; i < nsteps; ++i) {
-    rc = step_one_way(s, stats);
+    rc = s->any_free ? step_two_way(s, stats) : step_one_way(s, stats);
     if (rc != SIM_OK && rc != SIM_ENOTCONV) return rc;
   }
   return rc;

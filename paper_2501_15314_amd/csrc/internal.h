@@ -88,6 +88,24 @@ struct BodyDev {
   double v[3];
   double w[3];
 };
+// ---- two-way coupling sums (kernels_body.hip) ------------------------------
+// Per body: its point range in natural order and the node box that holds
+// every velocity node with a non-zero volume fraction (lo may lie outside the
+// grid; periodic axes wrap, no-slip axes clip).
+struct BodySpan {
+  int k0, kn;
+  double c[3];
+  double radius;
+  int lo[3], dim[3];
+};
+constexpr int VOL_CHUNKS = 16;  // workgroups per (body, velocity component)
+// out[12 b + 0..5] = (h^3 sum Phi, h^3 sum L~ x Phi) of body b (phi in natural order)
+hipError_t body_force_torque(int nb, const BodyDev *bodies, const BodySpan *span, const double *off,
+                             const double *phi, double h3, double *out, hipStream_t s);
+// out[12 b + 6..11] = (sum alpha u h^3, sum alpha r x u h^3); part holds
+// nb * 3 * VOL_CHUNKS * 3 doubles
+hipError_t body_volume_integrals(const Geo &g, int nb, const BodySpan *span, const double *u, double *part,
+                                 double *out, hipStream_t s);
 hipError_t points_place(const Geo &g, int K, const BodyDev *bodies, const int *body_of,
                         const double *off, double *X, double *U, int *tile, int nt0, int nt1,
                         int nt2, hipStream_t s);

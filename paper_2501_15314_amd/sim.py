@@ -141,6 +141,13 @@ class Sim:
         self._check(self.lib.sim_get_points(self.h, _ptr(X), _ptr(U)))
         return X[:self.K], U[:self.K]
 
+    def get_body_state(self):
+        """Per body: dict(center, vel, omega, R) at the current time."""
+        buf = (C.c_double * (18 * max(self.nb, 1)))()
+        self._check(self.lib.sim_get_body_state(self.h, buf))
+        a = np.array(buf[:18 * self.nb]).reshape(self.nb, 18)
+        return [dict(center=r[0:3], vel=r[3:6], omega=r[6:9], R=r[9:18].reshape(3, 3)) for r in a]
+
     def get_forces(self):
         f = torch.empty((max(self.K, 1), 3), dtype=torch.float64, device=self.dev)
         ft = (C.c_double * (6 * max(self.nb, 1)))()

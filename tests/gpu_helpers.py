@@ -54,3 +54,42 @@ def mixed_workload(seed=12):
                       n_points=K)]
     off = np.concatenate([wl.fibonacci_offsets(K, radius)] * 2)
     return wl.Workload("mixed_16x24x32", cfg, bodies, off, np.zeros((3,) + n), steps=1, seed=seed)
+
+
+def free_workload(n=32, bc=wl.BC_PERIODIC, seed=21, precision=wl.PREC_FP64, xi=0.6, outer_iters=3):
+    """Two free spheres (a = 0.15, theta 1.5 and 2.5) under gravity, with small
+    random initial velocities and spins in a random solenoidal flow (periodic)
+    or in fluid at rest (no-slip walls)."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    radius = 0.15
+    K = int(round(4 * np.pi * radius ** 2 / h ** 2))
+    cfg = wl.Config(n=(n, n, n), length=(1.0, 1.0, 1.0), bc=(bc,) * 3, nu=0.01, dt=0.002,
+                    delta=wl.DELTA_PESKIN4, lump_c=wl.lump_constant(wl.DELTA_PESKIN4, h, K, radius),
+                    precision=precision, krylov_rtol=1e-12 if precision == wl.PREC_FP64 else 1e-11,
+                    helm_rtol=1e-12 if precision == wl.PREC_FP64 else 1e-11,
+                    outer_iters=outer_iters, outer_tol=0.0, xi=xi)
+    cfg.g = (0.0, 0.0, -1.0)
+    centers = [np.array([0.3, 0.35, 0.6]), np.array([0.68, 0.62, 0.4])]
+    bodies = []
+    for c, theta in zip(centers, (1.5, 2.5)):
+        bodies.append(wl.Body(center=c + rng.uniform(-0.01, 0.01, 3), vel=rng.normal(0, 0.05, 3),
+                              omega=rng.normal(0, 0.5, 3), radius=radius, density_ratio=theta,
+                              motion=wl.MOTION_FREE, n_points=K))
+    off = np.concatenate([wl.fibonacci_offsets(K, radius)] * 2)
+    if bc == wl.BC_PERIODIC:
+        u0 = wl.solenoidal_field(rng, (n, n, n), h, 0.05)
+    else:
+        u0 = np.zeros((3, n, n, n))
+    return wl.Workload(f"free_{n}_{'periodic' if bc == wl.BC_PERIODIC else 'walls'}", cfg, bodies, off,
+                       u0, steps=2, seed=seed)
+
+
+def oracle_free_bodies(w: wl.Workload):
+    from oracle import step as ostep
+    out, k0 = [], 0
+    for b in w.bodies:
+        out.append(ostep.free_body(b.center, b.vel, b.omega, b.radius, b.density_ratio,
+                                   w.offsets[k0:k0 + b.n_points], w.cfg.dt))
+        k0 += b.n_points
+    return out
