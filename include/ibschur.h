@@ -197,12 +197,23 @@ sim_status sim_get_points(sim_t sim, double *d_X, double *d_U);
  * prescribed kinematics.  SIM_ESTATE without bodies. */
 sim_status sim_get_body_state(sim_t sim, double *state);
 
-/* Reverse-mode derivative of the last one-way step (prescribed bodies, one
- * correction).  Inputs are the cotangents of (u^{n+1}, v, w, p^{n+1},
- * Phi^{n+1}) (NULL = 0).  Outputs: d_gX [K][3] = dl/dX_k, gU (host [nb][3])
- * = dl/du_s of each body, and optionally the cotangents of the step's inputs
- * d_gu_in [3][n0][n1][n2] (u^n), d_gum_in (u^{n-1}), d_gp_in (p^n),
- * d_gphi_in [K][3] (Phi^n).  Requires the state saved by the last sim_step. */
+/* Reverse-mode derivative (vector-Jacobian product) of the last time step,
+ * which must be a one-way step (prescribed bodies) with one correction; any
+ * other call that changes the state in between (sim_set_*, sim_solve_schur,
+ * sim_apply, a two-way step) makes this SIM_ESTATE.  The transposed sequence
+ * runs the update, force recovery (eq. ApproxSchurPrimalF), Schur solve (S~ is
+ * symmetric: same FGMRES), right-hand side (eq. ApproxSchurPrimalP) and
+ * momentum solve (A symmetric) backwards, plus the derivatives of W with
+ * respect to the point positions (Sec. 2.3 kernels) and of the convection
+ * term.  Inputs: cotangents of u^{n+1} (d_gu, d_gv, d_gw, natural face
+ * layout), p^{n+1} (d_gp) and Phi^{n+1} (d_gphi, [K][3]); NULL means zero.
+ * Outputs (NULL = not wanted): d_gX [K][3] = dl/dX_k at the step's point
+ * positions; gU (host, [nb][6]) = (dl/du_s, dl/domega) of each body through
+ * the point velocities U_k = u_s + omega x L~_k; the cotangents of the step's
+ * inputs d_gu_in ([3][n0][n1][n2], u^n), d_gum_in (u^{n-1}), d_gp_in (p^n),
+ * d_gphi_in ([K][3], Phi^n).  The state of the step is left unchanged, so the
+ * call may be repeated with other cotangents.  SIM_ENOTCONV if a transposed
+ * solve hit its iteration limit (outputs still written). */
 sim_status sim_step_adjoint(sim_t sim, const double *d_gu, const double *d_gv,
                             const double *d_gw, const double *d_gp, const double *d_gphi,
                             double *d_gX, double *gU, double *d_gu_in, double *d_gum_in,

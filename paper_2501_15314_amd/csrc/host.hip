@@ -95,6 +95,10 @@ struct sim_s {
   double *BSUM = nullptr, *VPART = nullptr;
   bool vol_init = false;
   std::vector<BodySpan> hspan;  // host copy (kept alive for the asynchronous upload)
+  // reverse mode: point cotangent work arrays [5][K][3]; the last step can be
+  // transposed while adj_ready (a one-way step with one correction)
+  double *ADJ = nullptr;
+  bool adj_ready = false;
   // reductions
   double *PART = nullptr, *RED = nullptr, *YDEV = nullptr;
   double *hpin = nullptr;
@@ -211,6 +215,7 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
   double *XS = cv.arr<double>(3 * K), *US = cv.arr<double>(3 * K), *Q = cv.arr<double>(3 * K);
   double *RF = cv.arr<double>(3 * K), *PHIP = cv.arr<double>(3 * K), *PHIS = cv.arr<double>(3 * K);
   double *PT3 = cv.arr<double>(3 * K);
+  double *ADJ = cv.arr<double>(15 * K);
   int *COUNTS = cv.arr<int>(nt), *TSTART = cv.arr<int>(nt + 1), *FILLC = cv.arr<int>(nt);
   int *FLAGS = cv.arr<int>(nt), *FPOS = cv.arr<int>(nt + 1), *ACTIVE = cv.arr<int>(nt);
   int *SCANTMP = cv.arr<int>(nt / 1024 + 16);
@@ -238,6 +243,7 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
     s->OFF = OFF; s->XN = XN; s->UN = UN; s->PHIN = PHIN;
     s->BODYOF = BODYOF; s->TILE = TILE; s->PERM = PERM; s->PERMTMP = PERMTMP;
     s->XS = XS; s->US = US; s->Q = Q; s->RF = RF; s->PHIP = PHIP; s->PHIS = PHIS; s->PT3 = PT3;
+    s->ADJ = ADJ;
     s->COUNTS = COUNTS; s->TSTART = TSTART; s->FILLC = FILLC; s->FLAGS = FLAGS; s->FPOS = FPOS;
     s->ACTIVE = ACTIVE; s->SCANTMP = SCANTMP; s->BODIES = BODIES;
     s->SPAN = SPAN; s->BSUM = BSUM; s->VPART = VPART;
@@ -816,6 +822,7 @@ sim_status step_one_way(sim_t s, sim_step_stats *out) {
   if ((rc = finish_step(s, t1, divstar, S))) return rc;
   S.seconds = timer.seconds();
   s->last = S;
+  s->adj_ready = S.outer == 1;
   if (out) *out = S;
   if (hrc == SIM_ENOTCONV) return fail(s, SIM_ENOTCONV, "momentum solve iteration limit reached");
   return src;
@@ -1098,6 +1105,7 @@ sim_status sim_set_bodies(sim_t s, int32_t nb, const sim_body *bodies, const dou
   s->K = (int)K;
   s->nb = nb;
   s->any_free = nb > 0 && bodies[0].motion == SIM_MOTION_FREE;
+  s->adj_ready = false;
   s->vol_init = false;
   hipStream_t st = s->st;
   if (K > 0) {
@@ -1125,6 +1133,7 @@ sim_status sim_set_fields(sim_t s, int32_t level, const double *d_u, const doubl
   }
   CKH(zero_wall_faces(s->g, U, st));
   s->vol_init = false;  // the volume history of free bodies restarts from the new u^n
+  s->adj_ready = false;
   if (level == 0 && d_p) CKH(to_split(s->g, 1, d_p, s->P, st));
   if (level == 0 && d_phi && s->K > 0)
     CKH(hipMemcpyAsync(s->PHIN, d_phi, sizeof(double) * 3 * s->K, hipMemcpyDeviceToDevice, st));
@@ -1205,6 +1214,7 @@ sim_status sim_get_forces(sim_t s, double *d_f, double *body_ft) {
 sim_status sim_solve_schur(sim_t s, const double *d_rhs_p, const double *d_rhs_f, double *d_p, double *d_phi,
                            sim_solve_stats *stats) {
   if (!s) return SIM_EINVAL;
+  s->adj_ready = false;
   if (!s->have_bodies) return fail(s, SIM_ESTATE, "no bodies set");
   if (!d_rhs_p || !d_p || (s->K > 0 && (!d_rhs_f || !d_phi))) return fail(s, SIM_EINVAL, "null argument");
   hipStream_t st = s->st;
@@ -1220,6 +1230,7 @@ sim_status sim_solve_schur(sim_t s, const double *d_rhs_p, const double *d_rhs_f
 
 sim_status sim_step(sim_t s, int32_t nsteps, sim_step_stats *stats) {
   if (!s) return SIM_EINVAL;
+  s->adj_ready = false;
   if (!s->have_bodies) return fail(s, SIM_ESTATE, "no bodies set");
   if (nsteps < 0) return fail(s, SIM_EINVAL, "nsteps < 0");
   sim_status rc = SIM_OK;
@@ -1230,10 +1241,127 @@ sim_status sim_step(sim_t s, int32_t nsteps, sim_step_stats *stats) {
   return rc;
 }
 
-sim_status sim_step_adjoint(sim_t s, const double *, const double *, const double *, const double *,
-                            const double *, double *, double *, double *, double *, double *, double *) {
+sim_status sim_step_adjoint(sim_t s, const double *d_gu, const double *d_gv, const double *d_gw, const double *d_gp,
+                            const double *d_gphi, double *d_gX, double *gU, double *d_gu_in, double *d_gum_in,
+                            double *d_gp_in, double *d_gphi_in) {
   if (!s) return SIM_EINVAL;
-  return fail(s, SIM_ESTATE, "adjoint step not available in this build");
+  if (!s->have_bodies || !s->adj_ready)
+    return fail(s, SIM_ESTATE, "no recorded one-way step with one correction to transpose");
+  hipStream_t st = s->st;
+  const sim_config &c = s->cfg;
+  const Geo &g = s->g;
+  const long long N = s->N, n3 = 3 * N;
+  const int K = s->K, ker = s->ker;
+  const double tau = 2.0 * c.dt / 3.0, xi = c.xi, ic = 1.0 / s->c;
+  const long long K3 = 3LL * s->Kmax;
+  double *A0 = s->ADJ, *A1 = A0 + K3, *A2 = A1 + K3, *A3 = A2 + K3, *A4 = A3 + K3;
+  double *UB = s->TMP3, *RB = s->RHSU, *F3 = s->USTAR, *PB = s->RHSP, *BB = s->BVEC;
+  sim_status rc;
+  auto band = [&](bool div, const double *q, double alpha, double *out) {
+    return band_apply(ker, div, g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, q, alpha, out,
+                      st);
+  };
+  // cotangents of u^{n+1} (masked), p^{n+1}, Phi^{n+1}
+  CKH(fill(UB, n3, 0.0, st));
+  const double *gin[3] = {d_gu, d_gv, d_gw};
+  for (int d = 0; d < 3; ++d)
+    if (gin[d]) CKH(to_split(g, 1, gin[d], UB + d * N, st));
+  CKH(zero_wall_faces(g, UB, st));
+  CKH(fill(PB, N, 0.0, st));
+  if (d_gp) CKH(to_split(g, 1, d_gp, PB, st));
+  if (K > 0) {
+    if (d_gphi) CKH(gather3(K, s->PERM, d_gphi, A0, st));
+    else CKH(fill(A0, 3LL * K, 0.0, st));
+  }
+  // update u+ = u* + xi tau (-G p' + W Phi'), p+ = p + xi p', Phi+ = Phi + xi Phi':
+  //   pbar' = xi pbar+ - xi tau G^T ubar = xi pbar+ + xi tau D ubar
+  //   Phibar' = xi Phibar+ + xi tau W^T ubar,  Xbar = xi tau d(ubar^T W Phi')
+  CKH(div_apply(g, UB, BB, xi * tau, st));
+  CKH(axpby(PB, BB, N, 1.0, xi, st));
+  CKH(interp_face(ker, g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, UB, xi * tau, A0, xi, A1, st));
+  CKH(fill(A4, 3LL * K, 0.0, st));
+  CKH(interp_dx(ker, g, K, s->XS, UB, s->PHIP, xi * tau, A4, st));
+  // force recovery Phi' = c^-1 (-W^T G p' - RHS_F):
+  //   pbar' += c^-1 D W Phibar',  RHS_F bar = -c^-1 Phibar'
+  CKH(band(true, A1, ic, PB));
+  CKH(scale3(K, A1, -ic, nullptr, 0.0, A2, st));
+  // Schur solve p' = S~^+ b: bbar = S~^+ P pbar' (S~ symmetric)
+  if ((rc = project_mean(s, PB))) return rc;
+  sim_solve_stats sst{};
+  sim_status src = fgmres_any(s, PB, BB, &sst);
+  if (src != SIM_OK && src != SIM_ENOTCONV) return src;
+  // q2 = W^T G bbar;  d S~ and d(RHS) terms:
+  //   Xbar += d((G bbar)^T W Phi') - c^-1 d((G p')^T W (Phibar' + q2))
+  CKH(interp_grad<double>(ker, g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, BB, 1.0, nullptr, 0.0, A3, st));
+  CKH(grad_apply(g, BB, F3, 1.0, nullptr, st));
+  CKH(interp_dx(ker, g, K, s->XS, F3, s->PHIP, 1.0, A4, st));
+  CKH(scale3(K, A1, 1.0, A3, 1.0, A1, st));
+  CKH(grad_apply(g, s->PP, F3, 1.0, nullptr, st));
+  CKH(interp_dx(ker, g, K, s->XS, F3, A1, -ic, A4, st));
+  // b = P(RHS_p + c^-1 D W RHS_F): RHS_p bar = bbar, RHS_F bar += -c^-1 W^T G bbar
+  CKH(scale3(K, A3, -ic, A2, 1.0, A2, st));
+  // RHS_p = -D u*/tau, RHS_F = (W^T u* - U)/tau:
+  //   u*bar = ubar + G bbar / tau + W RHS_F bar / tau,  Ubar = -RHS_F bar / tau
+  CKH(grad_apply(g, BB, UB, 1.0 / tau, UB, st));
+  CKH(band(false, A2, 1.0 / tau, UB));
+  CKH(zero_wall_faces(g, UB, st));
+  CKH(scale3(K, A2, -1.0 / tau, nullptr, 0.0, A3, st));
+  //   Xbar += d(u*^T W RHS_F bar) / tau, u* = u^{n+1} + xi tau (G p' - W Phi')
+  CKH(grad_apply(g, s->PP, F3, xi * tau, s->U, st));
+  CKH(band(false, s->PHIP, -xi * tau, F3));
+  CKH(zero_wall_faces(g, F3, st));
+  CKH(interp_dx(ker, g, K, s->XS, F3, A2, 1.0 / tau, A4, st));
+  // u* = A^-1 rhs (A symmetric): rhs bar = A^-1 u*bar
+  CKH(fill(RB, n3, 0.0, st));
+  sim_solve_stats hst{};
+  sim_status hrc = helm_solve_any(s, UB, RB, &hst);
+  if (hrc != SIM_OK && hrc != SIM_ENOTCONV) return hrc;
+  // rhs = (4u^n - u^{n-1})/(2dt) - G p^n + W Phi^n - N(u^n): Xbar += d(rhsbar^T W Phi^n)
+  CKH(scale3(K, s->PHIP, -xi, s->PHIS, 1.0, A1, st));  // Phi^n = Phi^{n+1} - xi Phi'
+  CKH(interp_dx(ker, g, K, s->XS, RB, A1, 1.0, A4, st));
+  // outputs
+  if (d_gX && K > 0) CKH(scatter3(K, s->PERM, A4, d_gX, st));
+  if (gU && s->nb > 0) {
+    CKH(scatter3(K, s->PERM, A3, s->PT3, st));
+    CKH(hipStreamSynchronize(st));
+    s->hspan.assign(s->nb, BodySpan{});
+    for (int i = 0; i < s->nb; ++i) {
+      s->hspan[i].k0 = s->bodies[i].k0;
+      s->hspan[i].kn = s->bodies[i].kn;
+    }
+    CKH(hipMemcpyAsync(s->SPAN, s->hspan.data(), sizeof(BodySpan) * s->nb, hipMemcpyHostToDevice, st));
+    CKH(body_force_torque(s->nb, s->BODIES, s->SPAN, s->OFF, s->PT3, 1.0, s->BSUM, st));
+    std::vector<double> sums(12 * (size_t)s->nb);
+    CKH(hipMemcpyAsync(sums.data(), s->BSUM, sizeof(double) * 12 * s->nb, hipMemcpyDeviceToHost, st));
+    CKH(hipStreamSynchronize(st));
+    for (int i = 0; i < s->nb; ++i)
+      for (int q = 0; q < 6; ++q) gU[6 * i + q] = sums[12 * i + q];
+  }
+  if (d_gphi_in && K > 0) {
+    CKH(interp_face(ker, g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, RB, 1.0, A0, 1.0, A2, st));
+    CKH(scatter3(K, s->PERM, A2, d_gphi_in, st));
+  }
+  if (d_gp_in) {  // pbar^n = pbar+ - G^T rhsbar = pbar+ + D rhsbar
+    CKH(div_apply(g, RB, s->TMPC, 1.0, st));
+    CKH(fill(PB, N, 0.0, st));
+    if (d_gp) CKH(to_split(g, 1, d_gp, PB, st));
+    CKH(axpby(s->TMPC, PB, N, 1.0, 1.0, st));
+    CKH(to_natural(g, 1, s->TMPC, d_gp_in, st));
+  }
+  if (d_gum_in) {
+    CKH(scale_copy(F3, RB, n3, -1.0 / (2.0 * c.dt), st));
+    for (int d = 0; d < 3; ++d) CKH(to_natural(g, 1, F3 + d * N, d_gum_in + d * N, st));
+  }
+  if (d_gu_in) {  // ubar^n = M (2/dt rhsbar - J_N(u^n)^T rhsbar); u^n is UM after the step
+    CKH(convection_adjoint(g, s->UM, RB, F3, st));
+    CKH(axpby(F3, RB, n3, 2.0 / c.dt, -1.0, st));
+    CKH(zero_wall_faces(g, F3, st));
+    for (int d = 0; d < 3; ++d) CKH(to_natural(g, 1, F3 + d * N, d_gu_in + d * N, st));
+  }
+  if ((rc = sync(s))) return rc;
+  if (src == SIM_ENOTCONV) return fail(s, SIM_ENOTCONV, "adjoint Schur solve iteration limit reached");
+  if (hrc == SIM_ENOTCONV) return fail(s, SIM_ENOTCONV, "adjoint momentum solve iteration limit reached");
+  return SIM_OK;
 }
 
 sim_status sim_probe_enable(sim_t s, int32_t probe, int32_t on) {
@@ -1256,6 +1384,7 @@ sim_status sim_probe_read(sim_t s, int32_t probe, int64_t *launches, double *ms,
 
 sim_status sim_apply(sim_t s, int32_t op, const double *in, const double *in2, double *out) {
   if (!s) return SIM_EINVAL;
+  s->adj_ready = false;
   if (!in || !out) return fail(s, SIM_EINVAL, "null argument");
   hipStream_t st = s->st;
   const Geo &g = s->g;

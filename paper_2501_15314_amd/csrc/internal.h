@@ -154,6 +154,13 @@ hipError_t finalize(const double *part, int nblk, int nv, double *out, hipStream
 hipError_t update_norm(double *w, const double *V, long long stride, int nv, const double *hcoef,
                        long long n, double *part, hipStream_t s);  // w -= sum h_i V_i ; |w|^2
 hipError_t scale_inplace(double *x, long long n, double alpha, hipStream_t s);
+// ---- reverse-mode step (kernels_adj.hip) ------------------------------------
+// out[k][e] += scale * d/dX_{k,e} (a^T W(X) b), a a face field, b [K][3]
+hipError_t interp_dx(int ker, const Geo &g, int K, const double *X, const double *a3, const double *b, double scale,
+                     double *out, hipStream_t s);
+// out3 = J_N(u)^T r (wall faces 0)
+hipError_t convection_adjoint(const Geo &g, const double *u3, const double *r3, double *out3, hipStream_t s);
+
 hipError_t scale_copy(double *y, const double *x, long long n, double alpha, hipStream_t s);
 template <typename T>
 hipError_t sol_update(double *x, const T *Z, long long stride, int nz, const double *y, long long n,

@@ -195,7 +195,7 @@ class Sim:
         comps = [gu[d] if gu is not None else None for d in range(3)]
         gp, gphi = self._t(gp), self._t(gphi)
         gX = torch.zeros((max(self.K, 1), 3), dtype=torch.float64, device=self.dev)
-        gU = (C.c_double * (3 * max(self.nb, 1)))()
+        gU = (C.c_double * (6 * max(self.nb, 1)))()
         outs = [None] * 4
         if want_inputs:
             outs = [torch.zeros((3,) + self.n, dtype=torch.float64, device=self.dev),
@@ -204,7 +204,8 @@ class Sim:
                     torch.zeros((max(self.K, 1), 3), dtype=torch.float64, device=self.dev)]
         self._check(self.lib.sim_step_adjoint(self.h, *[_ptr(c) for c in comps], _ptr(gp), _ptr(gphi),
                                               _ptr(gX), gU, *[_ptr(o) for o in outs]))
-        res = dict(gX=gX[:self.K], gU=np.array(gU[:3 * self.nb]).reshape(self.nb, 3))
+        g6 = np.array(gU[:6 * self.nb]).reshape(self.nb, 6)
+        res = dict(gX=gX[:self.K], gU=g6[:, :3], gW=g6[:, 3:])
         if want_inputs:
             res.update(gu=outs[0], gum=outs[1], gp=outs[2], gphi=outs[3][:self.K])
         return res

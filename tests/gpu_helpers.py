@@ -93,3 +93,18 @@ def oracle_free_bodies(w: wl.Workload):
                                    w.offsets[k0:k0 + b.n_points], w.cfg.dt))
         k0 += b.n_points
     return out
+
+
+def prescribed_points(w: wl.Workload, t: float):
+    """Point positions and velocities of prescribed bodies at time t
+    (X_k = X_c + R X~_k, U_k = u_s + omega x R X~_k)."""
+    Xs, Us, k0 = [], [], 0
+    for b in w.bodies:
+        o = w.offsets[k0:k0 + b.n_points]
+        c = obd.prescribed_center(b.center, b.vel, b.osc_amp, b.osc_omega, t)
+        R = obd.prescribed_rotation(b.omega, t)
+        lever = o @ R.T
+        Xs.append(c[None, :] + lever)
+        Us.append(obd.point_velocities(obd.prescribed_velocity(b.vel, b.osc_amp, b.osc_omega, t), b.omega, lever))
+        k0 += b.n_points
+    return np.concatenate(Xs), np.concatenate(Us)
