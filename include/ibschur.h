@@ -190,6 +190,10 @@ sim_status sim_get_forces(sim_t sim, double *d_f, double *body_ft);
 /* Current point positions and velocities, [K][3] each (either may be NULL). */
 sim_status sim_get_points(sim_t sim, double *d_X, double *d_U);
 
+/* Set the current time t^n (prescribed kinematics are evaluated at t^n and
+ * t^{n+1} = t^n + dt; free-body states are unaffected). */
+sim_status sim_set_time(sim_t sim, double t);
+
 /* Rigid-body state at the current time, host array [nb][18] in body order:
  * centre X_c (0..2), velocity u_s (3..5), angular velocity omega in the
  * inertial frame (6..8), orientation R row-major (9..17; maps body-frame

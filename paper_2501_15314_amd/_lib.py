@@ -22,7 +22,7 @@ OPS = dict(laplacian=0, schur=1, precond=2, grad=3, div=4, interp=5, spread=6, h
 
 EXPORTS = ["sim_workspace_bytes", "sim_create", "sim_destroy", "sim_set_bodies", "sim_set_fields",
            "sim_get_fields", "sim_step", "sim_solve_schur", "sim_get_forces", "sim_get_points",
-           "sim_get_body_state",
+           "sim_get_body_state", "sim_set_time",
            "sim_step_adjoint", "sim_apply", "sim_probe_enable", "sim_probe_read", "sim_last_error"]
 
 PROBES = dict(smooth_fine=0, smooth_first_fine=1, restrict_fine=2, prolong_fine=3, laplacian=4,
@@ -83,6 +83,7 @@ def load(path: str = LIB_PATH):
     lib.sim_get_forces.argtypes = [sim_t, VP, P(D)]
     lib.sim_get_points.argtypes = [sim_t, VP, VP]
     lib.sim_get_body_state.argtypes = [sim_t, P(D)]
+    lib.sim_set_time.argtypes = [sim_t, D]
     lib.sim_step_adjoint.argtypes = [sim_t, VP, VP, VP, VP, VP, VP, P(D), VP, VP, VP, VP]
     lib.sim_apply.argtypes = [sim_t, I32, VP, VP, VP]
     lib.sim_probe_enable.argtypes = [sim_t, I32, I32]

@@ -1150,6 +1150,14 @@ sim_status sim_get_fields(sim_t s, double *d_u, double *d_v, double *d_w, double
   return sync(s);
 }
 
+sim_status sim_set_time(sim_t s, double t) {
+  if (!s) return SIM_EINVAL;
+  if (!isfinite(t)) return fail(s, SIM_EINVAL, "time must be finite");
+  s->t = t;
+  s->adj_ready = false;
+  return SIM_OK;
+}
+
 sim_status sim_get_body_state(sim_t s, double *state) {
   if (!s) return SIM_EINVAL;
   if (!s->have_bodies) return fail(s, SIM_ESTATE, "no bodies set");

@@ -111,6 +111,11 @@ class Sim:
                                             off.ctypes.data_as(C.POINTER(C.c_double))))
         self.K = int(off.shape[0])
         self.nb = len(bodies)
+        self.bodies = list(bodies)
+        self.offsets = off
+
+    def set_time(self, t: float):
+        self._check(self.lib.sim_set_time(self.h, float(t)))
 
     def set_workload(self, w: Workload):
         self.set_bodies(w.bodies, w.offsets)
