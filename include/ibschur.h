@@ -10,8 +10,9 @@
  *
  * (paper Sec. 3.1 eq. Saddle; Sec. 4.1 eqs. tildeSp, ApproxSchurPrimalP,
  * ApproxSchurPrimalF), solved by flexible GMRES right-preconditioned by a
- * geometric-multigrid V-cycle approximating L^-1 (Sec. 4.2 uses the Laplacian
- * as the preconditioner; Sec. 6 names the V-cycle as its replacement).
+ * geometric-multigrid V-cycle approximating L^-1 (Sec. 4.1 uses the Laplacian
+ * as the preconditioner, Sec. 4.2 solves it directly; Sec. 7 names multigrid
+ * as the replacement).
  *
  * Notation.  W is the regularization matrix of Sec. 2.3 (the paper's R) with
  * dimensionless weights w_ik = phi(dx/h) phi(dy/h) phi(dz/h); W^T is the

@@ -1,13 +1,13 @@
 """Staggered (MAC) grid operators, FP64, as explicit sparse matrices.
 
-Paper: Sec. 2.1 (Fig. "cell": velocities on faces, pressure at centres) and
-Sec. 3.1 ("a standard finite volume central-difference discretization ... for
-all the spatial terms"; BDF2 for time).  The paper does not print the stencils;
+Paper: Sec. 2.1 (the discretization cell figure: velocities on faces, pressure
+at centres) and Sec. 3.1 (central finite-volume differences in space, BDF2 in
+time).  The paper does not print the stencils;
 the reading taken here is the classical MAC scheme:
 
   * (G p) on the face of component d at index (i,j,k) = (p[idx] - p[idx-e_d]) / h;
     on a no-slip axis d the index-0 face is the wall, its row of G is zero;
-  * D = -G^T exactly (the symmetry the spectral theorem of Sec. 4.3 needs);
+  * D = -G^T exactly (the symmetry the spectral theorem of Sec. 5 needs);
   * L = G^T G, the positive semi-definite Neumann/periodic Laplacian "-nabla^2"
     of eq. modified_poisson (no Dirichlet point: its null space is the constants);
   * the viscous Laplacian on each velocity component is the 7-point stencil on

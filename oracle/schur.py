@@ -1,7 +1,8 @@
 """The pressure / force-density correction system and its lumped Schur solve.
 
 Paper Sec. 3.1 (eq. Saddle), Sec. 4.1 (eqs. SchurPrimal, tildeSp,
-ApproxSchurPrimalP, ApproxSchurPrimalF), Sec. 4.2 (Laplacian preconditioner).
+ApproxSchurPrimalP, ApproxSchurPrimalF, the Laplacian as preconditioner),
+Sec. 4.2 (its direct solve).
 
 Reading of the signs (the printed saddle matrix is not consistent with the
 printed update and eq. modified_poisson): B^T is taken as the divergence of
@@ -62,7 +63,7 @@ class SchurSystem:
 
     # solves ------------------------------------------------------------------
     def solve(self, rhs_p, rhs_f, rtol=1e-13, restart=30, maxit=400, workers=None):
-        """Krylov solve of S~ p' = b preconditioned by the exact L^+ (Sec. 4.2).
+        """Krylov solve of S~ p' = b preconditioned by the exact L^+ (Sec. 4.1-4.2).
 
         Returns (p', Phi', iterations, residual history)."""
         b = self.rhs(rhs_p, rhs_f)
@@ -86,7 +87,7 @@ class SchurSystem:
 
 def exact_schur_dense(G: np.ndarray, W: np.ndarray):
     """Dense L and the exact primal Schur complement L + B^T C^-1 B with
-    C = W^T W (eq. SchurPrimal), for the spectral checks of Sec. 4.3."""
+    C = W^T W (eq. SchurPrimal), for the spectral checks of Sec. 5."""
     L = G.T @ G
     C = W.T @ W
     B = W.T @ G

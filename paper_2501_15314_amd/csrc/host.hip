@@ -3,7 +3,7 @@
 //   * workspace: every device array is carved from the caller's buffer;
 //   * bodies: rigid-sphere kinematics on the host (paper Sec. 2.1-2.2), point
 //     placement and tile binning on the device;
-//   * V-cycle driver (FP32 or FP64) approximating L^+ (Sec. 4.2, Sec. 6);
+//   * V-cycle driver (FP32 or FP64) approximating L^+ (Sec. 4.1-4.2, Sec. 7);
 //   * flexible GMRES(m) on S~ = L + c^-1 B^T B, right-preconditioned by the
 //     V-cycle, classical Gram-Schmidt with fused multi-dot / update kernels,
 //     Hessenberg least squares with Givens rotations on the host (one

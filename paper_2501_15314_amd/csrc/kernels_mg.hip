@@ -1,7 +1,7 @@
 // Geometric multigrid V-cycle for the pressure Laplacian L = G^T G, used as
 // the preconditioner M^-1 ~ L^+ of the Schur Krylov solve.  The paper applies
 // an exact fast-diagonalisation solve of L once per iteration (Sec. 4.2) and
-// names a multigrid V-cycle as its linear-time replacement (Sec. 6).
+// names a multigrid V-cycle as its linear-time replacement (Sec. 7).
 //
 // Cycle: red-black Gauss-Seidel smoothing (pre: red then black, post: black
 // then red, so the cycle is symmetric), residual restricted by averaging the

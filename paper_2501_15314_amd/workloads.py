@@ -8,7 +8,7 @@ no delta kernels, no Krylov or multigrid code), so both the HIP path and the
 CPU reference consume exactly the same arrays.
 
 The workloads stand in for the paper's own sphere-in-box experiments
-(Sec. 5.1, oscillating sphere; Sec. 5.1.2, porous sphere arrays; Sec. 5.1.3,
+(Sec. 6.1.1, oscillating sphere; Sec. 6.1.2, porous sphere arrays; Sec. 6.1.3,
 sedimentation): no dataset is involved.
 
 Array layout conventions (identical on both sides):
@@ -108,7 +108,7 @@ def fibonacci_offsets(n_points: int, radius: float) -> np.ndarray:
 
     z_q = 1 - (2q+1)/N, rho_q = sqrt(1 - z_q^2), azimuth q*pi*(3 - sqrt 5).
     Every point carries the same share of the surface area, as the paper's
-    equal-area partition does (Sec. 5.1.1)."""
+    equal-area partition does (Sec. 6.1.1)."""
     q = np.arange(n_points, dtype=np.float64)
     z = 1.0 - (2.0 * q + 1.0) / n_points
     rho = np.sqrt(np.maximum(0.0, 1.0 - z * z))
@@ -269,7 +269,7 @@ def scaled(make, n: int, **kw) -> Workload:
 
 def body_positions_at(w: Workload, t: float) -> np.ndarray:
     """Centres of prescribed bodies at time t (constant velocity plus the
-    paper's oscillation law x_c = x_0 - A cos(omega t), Sec. 5.1.1)."""
+    paper's oscillation law x_c = x_0 - A cos(omega t), Sec. 6.1.1)."""
     out = []
     for b in w.bodies:
         out.append(b.center + b.vel * t - b.osc_amp * math.cos(b.osc_omega * t))
@@ -279,7 +279,7 @@ def body_positions_at(w: Workload, t: float) -> np.ndarray:
 def random_schur_rhs(seed: int, n, n_points: int):
     """Random right-hand side for a pressure-force solve: rhs_p ~ N(0,1) with its
     mean removed, rhs_f ~ N(0,1) per point and component (the paper's
-    random-RHS experiment, Sec. 5.2)."""
+    random-RHS experiment, Sec. 6.2)."""
     rng = np.random.default_rng(seed)
     rp = rng.standard_normal(tuple(n))
     rp -= rp.mean()

@@ -329,7 +329,7 @@ def test_schur_krylov_vs_direct(bc):
 
 def test_spectral_theorem_bounds():
     """spec(L^-1 (L + B^T C^-1 B)) in [1, 2] on the mean-zero subspace
-    (theorem of Sec. 4.3), and the lumped operator is bounded by
+    (theorem of Sec. 5), and the lumped operator is bounded by
     1 + lambda_max(C)/c."""
     g, X, Wm, c = _small_system(8, (P, P, P), 40, delta.ROMA3)
     G = mac.gradient(g).toarray()
@@ -374,7 +374,7 @@ def test_one_way_step_divergence_free_and_slip():
 
 
 def test_iteration_count_flat_under_refinement():
-    """Spectral equivalence (Sec. 4.3, Sec. 5.2): with the exact Laplacian as
+    """Spectral equivalence (Sec. 5, Sec. 6.2): with the exact Laplacian as
     preconditioner the Krylov count does not grow with resolution."""
     counts = []
     for n in (16, 32, 48):
