@@ -52,6 +52,15 @@ def kernel_bytes(name, N, T, K, nactive, nnz):
     }.get(name)
 
 
+def sources_digest(srcs):
+    """sha256 over the concatenated bytes of the given repository files."""
+    h = hashlib.sha256()
+    for src in srcs:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def traffic_record(kernel):
     """Counter-measured HBM bytes per launch from profiles/, if they were
     taken on the current kernel source (matching source hash)."""
@@ -67,9 +76,8 @@ def traffic_record(kernel):
         rec[k.strip()] = v.strip()
     if rec.get("kernel") != kernel:
         return None
-    src = rec.get("source", "")
-    digest = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest() if src else ""
-    if digest != rec.get("source_sha256"):
+    srcs = [x.strip() for x in rec.get("source", "").split(",") if x.strip()]
+    if not srcs or rec.get("source_sha256") != sources_digest(srcs):
         return None
     try:
         return float(rec["bytes_per_launch"])
@@ -135,6 +143,9 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form solve rate")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy three times (the reference "
+                         "kernel for scaling HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the solver runs on a single MI355X); "
@@ -143,6 +154,15 @@ def main():
 
     import numpy as np
     import torch
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}), flush=True)
+        return
     from paper_2501_15314_amd import _lib
     from paper_2501_15314_amd import workloads as wl
     from paper_2501_15314_amd.sim import Sim
