@@ -49,6 +49,8 @@ def kernel_bytes(name, N, T, K, nactive, nnz):
         # SOR half sweep on the three face grids: other colour e, own colour r and e read, own e written
         "helm_sweep": 3 * N * (T / 2 + T / 2 + T / 2 + T / 2),
         "helm_resid": 3 * N * (16 + T),
+        # momentum right-hand side: u^n, u^{n-1} (3 components each) and p read, rhs written
+        "mom_rhs": N * (7 * 8 + 3 * 8),
     }.get(name)
 
 

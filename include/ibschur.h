@@ -267,7 +267,9 @@ enum {
   SIM_PROBE_COARSE = 11,            /* coarse-grid LDS kernel */
   SIM_PROBE_HELM_SWEEP = 12,        /* momentum red-black SOR half sweep */
   SIM_PROBE_HELM_RESID = 13,        /* momentum residual */
-  SIM_PROBE_COUNT = 14
+  SIM_PROBE_VCYCLE = 14,            /* one whole V-cycle (all levels) */
+  SIM_PROBE_MOM_RHS = 15,           /* momentum right-hand side with convection */
+  SIM_PROBE_COUNT = 16
 };
 sim_status sim_probe_enable(sim_t sim, int32_t probe, int32_t on);
 sim_status sim_probe_read(sim_t sim, int32_t probe, int64_t *launches, double *ms, int32_t reset);

@@ -67,8 +67,8 @@ struct sim_s {
   // fields (double, split layout)
   double *U = nullptr, *UM = nullptr, *USTAR = nullptr, *RHSU = nullptr, *TMP3 = nullptr;
   double *P = nullptr, *RHSP = nullptr, *BVEC = nullptr, *PP = nullptr, *TMPC = nullptr;
-  // Krylov basis and preconditioned vectors
-  double *V = nullptr;
+  // Krylov basis and preconditioned vectors (float32 in the FP32-MG form)
+  void *V = nullptr;
   void *Z = nullptr;
   // momentum relaxation work (T precision)
   void *HR = nullptr, *HE0 = nullptr;
@@ -193,7 +193,7 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
   double *RHSU = cv.arr<double>(3 * N), *TMP3 = cv.arr<double>(3 * N);
   double *P = cv.arr<double>(N), *RHSP = cv.arr<double>(N), *BVEC = cv.arr<double>(N);
   double *PP = cv.arr<double>(N), *TMPC = cv.arr<double>(N);
-  double *V = cv.arr<double>((long long)(m + 1) * N);
+  void *V = cv.take(ts * (size_t)(m + 1) * N);
   void *Z = cv.take(ts * (size_t)m * N);
   void *HR = cv.take(ts * 3 * N), *HE0 = cv.take(ts * 3 * N);
   std::vector<Level> lv;
@@ -231,7 +231,7 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
   long long parts = std::max<long long>((long long)rb * (MAX_RESTART + 2), 0);
   // helm_resid writes one partial per row-launch block
   // the momentum residual writes one partial per plane-march workgroup
-  long long hparts = (long long)(c->n[2] / 4 + 1) * c->n[1] * (c->n[0] / 8 + 1) * 3;
+  long long hparts = helm_resid_blocks(lv[0].g);
   double *PART = cv.arr<double>(std::max(parts, hparts));
   double *RED = cv.arr<double>(4 * (MAX_RESTART + 2));
   double *YDEV = cv.arr<double>(MAX_RESTART + 2);
@@ -413,15 +413,17 @@ sim_status schur_matvec(sim_t s, const T *z, double *w) {
   return SIM_OK;
 }
 
-// z ~ L^+ v by one V-cycle
-template <typename T>
-sim_status vcycle(sim_t s, const double *v, T *z) {
+// z ~ L^+ v by one V-cycle (v in precision TV: float64, or float32 for the
+// FP32-MG basis)
+template <typename T, typename TV>
+sim_status vcycle(sim_t s, const TV *v, T *z) {
+  ProbeScope whole(PR_VCYCLE, s->st);
   hipStream_t st = s->st;
   const sim_config &c = s->cfg;
   int nl = (int)s->lv.size();
   int cyc = c.mg_coarse_sweeps;
   if (nl == 1) {
-    CKH((mg_coarse<T, double>(s->lv[0].g, v, z, cyc, 1, st)));
+    CKH((mg_coarse<T, TV>(s->lv[0].g, v, z, cyc, 1, st)));
     return SIM_OK;
   }
   // descend
@@ -431,16 +433,16 @@ sim_status vcycle(sim_t s, const double *v, T *z) {
     if (l == 0) {
       {
         ProbeScope pr(PR_SMOOTH_FIRST_FINE, st);
-        CKH((mg_smooth_first<T, double>(g, x, v, st)));
+        CKH((mg_smooth_first<T, TV>(g, x, v, st)));
       }
       for (int q = 1; q < c.mg_pre; ++q) {
         {
           ProbeScope pr(PR_SMOOTH_FINE, st);
-          CKH((mg_smooth<T, double>(g, x, v, 0, st)));
+          CKH((mg_smooth<T, TV>(g, x, v, 0, st)));
         }
         {
           ProbeScope pr(PR_SMOOTH_FINE, st);
-          CKH((mg_smooth<T, double>(g, x, v, 1, st)));
+          CKH((mg_smooth<T, TV>(g, x, v, 1, st)));
         }
       }
     } else {
@@ -455,7 +457,7 @@ sim_status vcycle(sim_t s, const double *v, T *z) {
       T *bnext = (T *)s->lv[l + 1].b;
       if (l == 0) {
         ProbeScope pr(PR_RESTRICT_FINE, st);
-        CKH((mg_restrict<T, double>(g, x, v, s->lv[1].g, bnext, st)));
+        CKH((mg_restrict<T, TV>(g, x, v, s->lv[1].g, bnext, st)));
       } else
 
         CKH((mg_restrict<T, T>(g, x, (const T *)s->lv[l].b, s->lv[l + 1].g, bnext, st)));
@@ -478,11 +480,11 @@ sim_status vcycle(sim_t s, const double *v, T *z) {
       if (l == 0) {
         {
           ProbeScope pr(PR_SMOOTH_FINE, st);
-          CKH((mg_smooth<T, double>(g, x, v, 1, st)));
+          CKH((mg_smooth<T, TV>(g, x, v, 1, st)));
         }
         {
           ProbeScope pr(PR_SMOOTH_FINE, st);
-          CKH((mg_smooth<T, double>(g, x, v, 0, st)));
+          CKH((mg_smooth<T, TV>(g, x, v, 0, st)));
         }
       } else {
         const T *b = (const T *)s->lv[l].b;
@@ -495,14 +497,19 @@ sim_status vcycle(sim_t s, const double *v, T *z) {
 }
 
 // Flexible GMRES(m), right preconditioned: solves S~ x = b (b mean-zero).
+// T: precision of the preconditioned vectors Z and of the V-cycle; the basis
+// V has the same precision (a float32 basis in the FP32-MG form: each cycle
+// only has to gain FP32_CYCLE_DROP before the float64 true residual restarts
+// it).  w = S~ z_j is formed and orthogonalised in float64.
 template <typename T>
 sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
   hipStream_t st = s->st;
   const sim_config &c = s->cfg;
   const long long N = s->N;
   const int m = c.krylov_restart;
-  double *V = s->V;
+  T *V = (T *)s->V;
   T *Z = (T *)s->Z;
+  const bool sep_w = sizeof(T) != sizeof(double);  // orthogonalise in a float64 buffer
   sim_solve_stats loc{};
   sim_solve_stats &S = stt ? *stt : loc;
   S.iters = 0;
@@ -525,23 +532,24 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
   while (true) {
     rel = beta / bnorm;
     if (rel <= c.krylov_rtol || total >= c.krylov_maxit) break;
-    CKH(scale_copy(V, rvec, N, 1.0 / beta, st));
+    CKH(scale_cast<T>(V, rvec, N, 1.0 / beta, st));
     std::fill(gv.begin(), gv.end(), 0.0);
     gv[0] = beta;
     int jd = 0;
     for (int j = 0; j < m; ++j) {
       T *zj = Z + (long long)j * N;
-      double *vj = V + (long long)j * N, *w = V + (long long)(j + 1) * N;
-      if ((rc = vcycle<T>(s, vj, zj))) return rc;
+      T *vj = V + (long long)j * N, *vnext = V + (long long)(j + 1) * N;
+      double *w = sep_w ? s->TMPC : (double *)vnext;
+      if ((rc = vcycle<T, T>(s, vj, zj))) return rc;
       if ((rc = schur_matvec<T>(s, zj, w))) return rc;
       {
         ProbeScope pr(PR_MULTIDOT, st);
-        CKH(multidot(w, V, N, j + 1, N, s->PART, st));
+        CKH(multidot<T>(w, V, N, j + 1, N, s->PART, st));
       }
       CKH(finalize(s->PART, red_blocks(), j + 1, s->RED, st));
       {
         ProbeScope pr(PR_UPDATE_NORM, st);
-        CKH(update_norm(w, V, N, j + 1, s->RED, N, s->PART + (long long)(MAX_RESTART + 1) * red_blocks(), st));
+        CKH(update_norm<T>(w, V, N, j + 1, s->RED, N, s->PART + (long long)(MAX_RESTART + 1) * red_blocks(), st));
       }
       CKH(finalize(s->PART + (long long)(MAX_RESTART + 1) * red_blocks(), red_blocks(), 1, s->RED + j + 1, st));
       double hc[MAX_RESTART + 2];
@@ -550,7 +558,7 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
       double hn = sqrt(std::max(hc[j + 1], 0.0));
       if (!isfinite(hn)) return fail(s, SIM_ENONFINITE, "non-finite Krylov norm");
       Hij(j + 1, j) = hn;
-      if (hn > 0) CKH(scale_inplace(w, N, 1.0 / hn, st));
+      if (hn > 0) CKH(scale_cast<T>(vnext, w, N, 1.0 / hn, st));
       for (int i = 0; i < j; ++i) {
         double t0 = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
         Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
@@ -705,7 +713,10 @@ sim_status predictor(sim_t s, sim_step_stats &S, sim_status &hrc) {
   const sim_config &c = s->cfg;
   const long long n3 = 3 * s->N;
   CKH(gather3(s->K, s->PERM, s->PHIN, s->PHIS, st));
-  CKH(mom_rhs(s->g, c.dt, s->U, s->UM, s->P, s->RHSU, st));
+  {
+    ProbeScope pr(PR_MOM_RHS, st);
+    CKH(mom_rhs(s->g, c.dt, s->U, s->UM, s->P, s->RHSU, st));
+  }
   CKH(band_apply(s->ker, false, s->g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, s->PHIS, 1.0,
                  s->RHSU, st));
   CKH(scale_copy(s->USTAR, s->U, n3, 2.0, st));
@@ -1414,11 +1425,11 @@ sim_status sim_apply(sim_t s, int32_t op, const double *in, const double *in2, d
     case SIM_OP_PRECOND:
       CKH(to_split(g, 1, in, s->TMPC, st));
       if (s->fp32) {
-        if ((rc = vcycle<float>(s, s->TMPC, (float *)s->Z))) return rc;
+        if ((rc = vcycle<float, double>(s, s->TMPC, (float *)s->Z))) return rc;
         CKH(fill(s->PP, N, 0.0, st));
         CKH(add_cast<float>(s->PP, (const float *)s->Z, N, st));
       } else {
-        if ((rc = vcycle<double>(s, s->TMPC, (double *)s->Z))) return rc;
+        if ((rc = vcycle<double, double>(s, s->TMPC, (double *)s->Z))) return rc;
         CKH(scale_copy(s->PP, (const double *)s->Z, N, 1.0, st));
       }
       CKH(to_natural(g, 1, s->PP, out, st));

@@ -13,7 +13,7 @@ namespace ibs {
 enum ProbeId {
   PR_SMOOTH_FINE = 0, PR_SMOOTH_FIRST_FINE, PR_RESTRICT_FINE, PR_PROLONG_FINE, PR_LAP, PR_BAND_DIV,
   PR_BAND_FACE, PR_INTERP_GRAD, PR_INTERP_FACE, PR_MULTIDOT, PR_UPDATE_NORM, PR_COARSE, PR_HELM_SWEEP,
-  PR_HELM_RESID, PR_COUNT
+  PR_HELM_RESID, PR_VCYCLE, PR_MOM_RHS, PR_COUNT
 };
 int probe_begin(int id, hipStream_t s);
 void probe_end(int id, int slot, hipStream_t s);
@@ -148,11 +148,16 @@ hipError_t band_apply(int ker, bool div, const Geo &g, int nt1, int nt2, int nac
 
 // ---- reductions / Krylov vector kernels (kernels_krylov.hip) ---------------
 int red_blocks();
-hipError_t multidot(const double *w, const double *V, long long stride, int nv, long long n,
+// basis V of type TV (float32 in the FP32-MG form, float64 otherwise); n, stride even
+template <typename TV>
+hipError_t multidot(const double *w, const TV *V, long long stride, int nv, long long n,
                     double *part, hipStream_t s);  // part[blk*nv + i]
 hipError_t finalize(const double *part, int nblk, int nv, double *out, hipStream_t s);
-hipError_t update_norm(double *w, const double *V, long long stride, int nv, const double *hcoef,
-                       long long n, double *part, hipStream_t s);  // w -= sum h_i V_i ; |w|^2
+template <typename TV>
+hipError_t update_norm(double *w, const TV *V, long long stride, int nv, const double *hcoef,
+                       long long n, double *part, hipStream_t s);
+template <typename TV>
+hipError_t scale_cast(TV *y, const double *x, long long n, double alpha, hipStream_t s);  // y = alpha x  // w -= sum h_i V_i ; |w|^2
 hipError_t scale_inplace(double *x, long long n, double alpha, hipStream_t s);
 // ---- reverse-mode step (kernels_adj.hip) ------------------------------------
 // out[k][e] += scale * d/dX_{k,e} (a^T W(X) b), a a face field, b [K][3]

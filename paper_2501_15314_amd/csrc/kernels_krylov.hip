@@ -24,16 +24,38 @@ __device__ __forceinline__ double block_reduce(double v, double *sh) {
   return r;
 }
 
-__global__ void __launch_bounds__(RED_T) k_multidot(const double *w, const double *V, long long stride, int nv,
+// Two consecutive entries per thread per grid-stride step (n is even: every
+// vector here is a whole split-layout grid array); the basis V may be stored
+// in float32 (the FP32-MG form) or float64, products accumulate in float64.
+template <typename TV>
+__device__ __forceinline__ void ld_pair(const TV *p, double &a, double &b) {
+  if (sizeof(TV) == 4) {
+    float2 f = *(const float2 *)p;
+    a = f.x;
+    b = f.y;
+  } else {
+    double2 f = *(const double2 *)p;
+    a = f.x;
+    b = f.y;
+  }
+}
+
+template <typename TV>
+__global__ void __launch_bounds__(RED_T) k_multidot(const double *w, const TV *V, long long stride, int nv,
                                                     long long n, double *part) {
   double acc[MD_MAX];
 #pragma unroll
   for (int i = 0; i < MD_MAX; ++i) acc[i] = 0.0;
-  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T) {
-    double wv = w[t];
+  const long long n2 = n >> 1;
+  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n2; t += (long long)gridDim.x * RED_T) {
+    const double2 wv = *(const double2 *)(w + 2 * t);
 #pragma unroll
     for (int i = 0; i < MD_MAX; ++i)
-      if (i < nv) acc[i] += wv * V[i * stride + t];
+      if (i < nv) {
+        double a, b;
+        ld_pair(V + i * stride + 2 * t, a, b);
+        acc[i] += wv.x * a + wv.y * b;
+      }
   }
   __shared__ double sh[4][MD_MAX];
   int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
@@ -50,16 +72,22 @@ __global__ void __launch_bounds__(RED_T) k_multidot(const double *w, const doubl
         ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
 }
 
-hipError_t multidot(const double *w, const double *V, long long stride, int nv, long long n, double *part,
+template <typename TV>
+hipError_t multidot(const double *w, const TV *V, long long stride, int nv, long long n, double *part,
                     hipStream_t s) {
+  if ((n & 1) || (stride & 1)) return hipErrorInvalidValue;
   // part layout: [blk][nv]; chunks of MD_MAX vectors write consecutive column groups
   for (int c0 = 0; c0 < nv; c0 += MD_MAX) {
     int nc = nv - c0 < MD_MAX ? nv - c0 : MD_MAX;
-    hipLaunchKernelGGL(k_multidot, dim3(RED_BLOCKS), dim3(RED_T), 0, s, w, V + c0 * stride, stride, nc, n,
+    hipLaunchKernelGGL(k_multidot<TV>, dim3(RED_BLOCKS), dim3(RED_T), 0, s, w, V + c0 * stride, stride, nc, n,
                        part + (long long)c0 * RED_BLOCKS);
   }
   return hipGetLastError();
 }
+template hipError_t multidot<float>(const double *, const float *, long long, int, long long, double *,
+                                    hipStream_t);
+template hipError_t multidot<double>(const double *, const double *, long long, int, long long, double *,
+                                     hipStream_t);
 
 // out[i] = sum_b part[b][i] over nblk blocks (chunked layout of multidot)
 __global__ void __launch_bounds__(RED_T) k_finalize(const double *part, int nblk, int nv, double *out) {
@@ -80,28 +108,54 @@ hipError_t finalize(const double *part, int nblk, int nv, double *out, hipStream
 }
 
 // w -= sum_i h_i V_i ; partial |w|^2
-__global__ void __launch_bounds__(RED_T) k_update_norm(double *w, const double *V, long long stride, int nv,
+template <typename TV>
+__global__ void __launch_bounds__(RED_T) k_update_norm(double *w, const TV *V, long long stride, int nv,
                                                        const double *hcoef, long long n, double *part) {
   __shared__ double hs[64];
   __shared__ double sh[4];
   for (int i = threadIdx.x; i < nv; i += RED_T) hs[i] = hcoef[i];
   __syncthreads();
   double acc = 0.0;
-  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T) {
-    double v = w[t];
-    for (int i = 0; i < nv; ++i) v -= hs[i] * V[i * stride + t];
-    w[t] = v;
-    acc += v * v;
+  const long long n2 = n >> 1;
+  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n2; t += (long long)gridDim.x * RED_T) {
+    double2 v = *(double2 *)(w + 2 * t);
+    for (int i = 0; i < nv; ++i) {
+      double a, b;
+      ld_pair(V + i * stride + 2 * t, a, b);
+      v.x -= hs[i] * a;
+      v.y -= hs[i] * b;
+    }
+    *(double2 *)(w + 2 * t) = v;
+    acc += v.x * v.x + v.y * v.y;
   }
   acc = block_reduce(acc, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
-hipError_t update_norm(double *w, const double *V, long long stride, int nv, const double *hcoef, long long n,
+template <typename TV>
+hipError_t update_norm(double *w, const TV *V, long long stride, int nv, const double *hcoef, long long n,
                        double *part, hipStream_t s) {
-  if (nv > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_update_norm, dim3(RED_BLOCKS), dim3(RED_T), 0, s, w, V, stride, nv, hcoef, n, part);
+  if (nv > 64 || (n & 1) || (stride & 1)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_update_norm<TV>, dim3(RED_BLOCKS), dim3(RED_T), 0, s, w, V, stride, nv, hcoef, n, part);
   return hipGetLastError();
 }
+template hipError_t update_norm<float>(double *, const float *, long long, int, const double *, long long,
+                                       double *, hipStream_t);
+template hipError_t update_norm<double>(double *, const double *, long long, int, const double *, long long,
+                                        double *, hipStream_t);
+
+// y = (TV)(a x): a basis vector from a float64 residual or orthogonalised vector
+template <typename TV>
+__global__ void k_scale_cast(TV *y, const double *x, long long n, double a) {
+  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T)
+    y[t] = (TV)(a * x[t]);
+}
+template <typename TV>
+hipError_t scale_cast(TV *y, const double *x, long long n, double alpha, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_cast<TV>, dim3(RED_BLOCKS * 4), dim3(RED_T), 0, s, y, x, n, alpha);
+  return hipGetLastError();
+}
+template hipError_t scale_cast<float>(float *, const double *, long long, double, hipStream_t);
+template hipError_t scale_cast<double>(double *, const double *, long long, double, hipStream_t);
 
 __global__ void k_scale_copy(double *y, const double *x, long long n, double a) {
   for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T)

@@ -2,7 +2,7 @@
 //
 // A workgroup owns a tile of BY rows (axis 1) x 2*BX in-row indices m
 // (axis 2, two per thread, accessed as 2-vectors) and marches over a chunk of
-// MARCH_CH planes along axis 0.  The x-neighbours of a cell come from a
+// planes along axis 0 (march_chunk).  The x-neighbours of a cell come from a
 // register window over three planes, the y- and z-neighbours from an LDS copy
 // of the current plane with a one-cell halo.  BX divides hn2/2 and BY divides
 // n1, so no workgroup is partial and every halo cell is loaded.
@@ -11,18 +11,32 @@
 
 namespace ibs {
 
-constexpr int MARCH_CH = 8;       // planes per workgroup
+constexpr int MARCH_CH = 8;       // most planes per workgroup
 constexpr int MARCH_TILE = 1104;  // >= max (BY+2)(2BX+2) over BX*BY <= 256
+constexpr int MARCH_MIN_BLOCKS = 2048;
 
 struct MarchShape {
   int bx, by;
   dim3 grid, block;
 };
 
-inline int pow2_divisor(int n, int cap) {
+__host__ __device__ inline int pow2_divisor(int n, int cap) {
   int p = 1;
   while (p * 2 <= cap && n % (p * 2) == 0) p *= 2;
   return p;
+}
+
+// Planes per workgroup: MARCH_CH on large grids (long register-window
+// chains, few halo re-reads), halved until the grid has MARCH_MIN_BLOCKS
+// workgroups on coarse multigrid levels, where latency rather than bytes
+// bounds a sweep.
+__host__ __device__ inline int march_chunk(const Geo &g) {
+  const int bx = pow2_divisor(g.hn2 / 2, 64);
+  const int by = pow2_divisor(g.n1, 256 / bx);
+  const long long xy = (long long)(g.hn2 / (2 * bx)) * (g.n1 / by);
+  int ch = MARCH_CH;
+  while (ch > 1 && xy * ((g.n0 + ch - 1) / ch) < MARCH_MIN_BLOCKS) ch >>= 1;
+  return ch;
 }
 
 // ncomp stacks independent component grids along grid.z.
@@ -31,7 +45,8 @@ inline MarchShape march_shape(const Geo &g, int ncomp) {
   s.bx = pow2_divisor(g.hn2 / 2, 64);
   s.by = pow2_divisor(g.n1, 256 / s.bx);
   s.block = dim3(s.bx, s.by, 1);
-  int nch = (g.n0 + MARCH_CH - 1) / MARCH_CH;
+  const int ch = march_chunk(g);
+  int nch = (g.n0 + ch - 1) / ch;
   s.grid = dim3(g.hn2 / (2 * s.bx), g.n1 / s.by, nch * ncomp);
   return s;
 }
@@ -81,11 +96,12 @@ __device__ __forceinline__ MarchPos march_pos(const Geo &g) {
   p.ty = threadIdx.y;
   p.m0 = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
   p.j = blockIdx.y * blockDim.y + threadIdx.y;
-  int nch = (g.n0 + MARCH_CH - 1) / MARCH_CH;
+  const int len = march_chunk(g);
+  int nch = (g.n0 + len - 1) / len;
   p.comp = blockIdx.z / nch;
   int ch = blockIdx.z - p.comp * nch;
-  p.i0 = ch * MARCH_CH;
-  p.i1 = min(p.i0 + MARCH_CH, g.n0);
+  p.i0 = ch * len;
+  p.i1 = min(p.i0 + len, g.n0);
   return p;
 }
 
