@@ -368,27 +368,93 @@ hipError_t convection(const Geo &g, const double *u3, double *out3, hipStream_t 
 }
 
 // rhs = (4 u^n - u^{n-1}) / (2 dt) - G p^n - N(u^n)     (eq. ustar; W Phi^n is
-// added afterwards by the band kernel)
-__global__ void k_mom_rhs(Geo g, double dt, const double *u3, const double *um3, const double *p_,
-                          double *out3) {
-  RowPos p;
-  if (!row_pos(g, p)) return;
-  long long N = 2 * g.half;
-  int d = p.comp;
-  int xd = d == 0 ? p.i : (d == 1 ? p.j : p.k);
-  double v = 0.0;
-  if (!(geo_bc(g, d) && xd == 0)) {
-    double lo = fetch(p_, g, p.i - (d == 0), p.j - (d == 1), p.k - (d == 2));
-    double gp = (p_[p.e] - lo) / g.h;
-    v = (4.0 * u3[d * N + p.e] - um3[d * N + p.e]) / (2.0 * dt) - gp -
-        conv_at(g, u3, d, p.i, p.j, p.k);
+// added afterwards by the band kernel).
+//
+// Tiled: a workgroup stages the three velocity components of a
+// (MR_TX+2) x (MR_TY+2) x (MR_TZ+2) natural-order box (the tile and a one-cell
+// halo: every value the divergence-form convection of a face needs) in LDS,
+// then each thread marches over the MR_TX planes of its (y, z) column and
+// writes the three components.  Tiles are handed out XCD-major (consecutive
+// tiles of the grid go to the same XCD), so the halos shared by neighbouring
+// tiles are fetched from HBM once per XCD L2.
+constexpr int MR_TX = 4, MR_TY = 8, MR_TZ = 32;
+constexpr int MR_RX = MR_TX + 2, MR_RY = MR_TY + 2, MR_RZ = MR_TZ + 2;
+constexpr int MR_REG = MR_RX * MR_RY * MR_RZ;
+
+__global__ void __launch_bounds__(MR_TY * MR_TZ) k_mom_rhs(Geo g, double dt, const double *u3, const double *um3,
+                                                           const double *p_, double *out3, int ntz, int nty,
+                                                           int ntiles) {
+  __shared__ double su[3][MR_REG];
+  const long long N = 2 * g.half;
+  // XCD-major tile order: block b runs on XCD b % 8
+  const int b = blockIdx.x;
+  const int per = ntiles / 8;
+  const int tile = (ntiles % 8 == 0) ? (b % 8) * per + b / 8 : b;
+  const int tz = tile % ntz, r0 = tile / ntz, ty = r0 % nty, tx = r0 / nty;
+  const int i0 = tx * MR_TX, j0 = ty * MR_TY, k0 = tz * MR_TZ;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < MR_REG; q += MR_TY * MR_TZ) {
+    const int zk = q % MR_RZ, rr = q / MR_RZ, yj = rr % MR_RY, xi = rr / MR_RY;
+    int gi = i0 - 1 + xi, gj = j0 - 1 + yj, gk = k0 - 1 + zk;
+    bool in = true;
+    if (gi < 0 || gi >= g.n0) { if (g.bc0) in = false; else gi = wrapi(gi, g.n0); }
+    if (gj < 0 || gj >= g.n1) { if (g.bc1) in = false; else gj = wrapi(gj, g.n1); }
+    if (gk < 0 || gk >= g.n2) { if (g.bc2) in = false; else gk = wrapi(gk, g.n2); }
+    const long long e = in ? sidx(g, gi, gj, gk) : 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) su[c][q] = in ? u3[c * N + e] : 0.0;
   }
-  out3[d * N + p.e] = v;
+  __syncthreads();
+  const int cj = tid / MR_TZ, ck = tid % MR_TZ;
+  const int j = j0 + cj, k = k0 + ck;
+  if (j >= g.n1 || k >= g.n2) return;
+  const double ih = 1.0 / g.h;
+  for (int ci = 0; ci < MR_TX; ++ci) {
+    const int i = i0 + ci;
+    if (i >= g.n0) break;
+    const int x0[3] = {i, j, k};
+    const long long e = sidx(g, i, j, k);
+    // LDS value of component c at offset (dx, dy, dz) from this cell
+    auto U = [&](int c, int dx, int dy, int dz) -> double {
+      return su[c][((ci + 1 + dx) * MR_RY + (cj + 1 + dy)) * MR_RZ + (ck + 1 + dz)];
+    };
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double v = 0.0;
+      if (!(geo_bc(g, d) && x0[d] == 0)) {
+        const int ed0 = d == 0, ed1 = d == 1, ed2 = d == 2;
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int ea0 = a == 0, ea1 = a == 1, ea2 = a == 2;
+          if (a == d) {
+            const double u0 = U(d, 0, 0, 0);
+            const double cp = 0.5 * (u0 + U(d, ea0, ea1, ea2)), cm = 0.5 * (U(d, -ea0, -ea1, -ea2) + u0);
+            acc += (cp * cp - cm * cm) * ih;
+          } else {
+            const int na = geo_n(g, a), bca = geo_bc(g, a);
+            double fp = 0.0, fm = 0.0;
+            if (!(bca && x0[a] == na - 1))
+              fp = 0.5 * (U(d, 0, 0, 0) + U(d, ea0, ea1, ea2)) * 0.5 *
+                   (U(a, ea0, ea1, ea2) + U(a, ea0 - ed0, ea1 - ed1, ea2 - ed2));
+            if (!(bca && x0[a] == 0))
+              fm = 0.5 * (U(d, -ea0, -ea1, -ea2) + U(d, 0, 0, 0)) * 0.5 * (U(a, 0, 0, 0) + U(a, -ed0, -ed1, -ed2));
+            acc += (fp - fm) * ih;
+          }
+        }
+        const double lo = fetch(p_, g, i - ed0, j - ed1, k - ed2);
+        const double gp = (p_[e] - lo) * ih;
+        v = (4.0 * U(d, 0, 0, 0) - um3[d * N + e]) / (2.0 * dt) - gp - acc;
+      }
+      out3[d * N + e] = v;
+    }
+  }
 }
 hipError_t mom_rhs(const Geo &g, double dt, const double *u3, const double *um3, const double *p,
                    double *out3, hipStream_t s) {
-  RowLaunch L = row_launch(g, 2 * g.n0 * 3);
-  hipLaunchKernelGGL(k_mom_rhs, L.grid, L.block, 0, s, g, dt, u3, um3, p, out3);
+  const int ntx = (g.n0 + MR_TX - 1) / MR_TX, nty = (g.n1 + MR_TY - 1) / MR_TY, ntz = (g.n2 + MR_TZ - 1) / MR_TZ;
+  const int ntiles = ntx * nty * ntz;
+  hipLaunchKernelGGL(k_mom_rhs, dim3(ntiles), dim3(MR_TY * MR_TZ), 0, s, g, dt, u3, um3, p, out3, ntz, nty, ntiles);
   return hipGetLastError();
 }
 
