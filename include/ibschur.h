@@ -87,7 +87,9 @@ typedef struct {
   double helm_rtol;      /* momentum relative residual target */
   int32_t mg_coarsest;   /* grid-wide V-cycle levels stop above this size */
   int32_t mg_pre, mg_post;     /* red-black Gauss-Seidel sweeps per level */
-  int32_t mg_coarse_sweeps;    /* V-cycles run by the coarse-grid LDS kernel */
+  int32_t mg_coarse_sweeps;    /* coarsest grid: 0 = exact solve by fast diagonalisation
+                                  (<= 32 cells per axis), k >= 1 = k V-cycles of the
+                                  LDS-resident coarse kernel */
   int32_t outer_iters;   /* pressure-force corrections per step (>= 1) */
   double outer_tol;      /* stop on ||Phi'||_1 / ||Phi||_1 < tol (0: fixed) */
   double xi;             /* relaxation of the correction (1 for one-way) */

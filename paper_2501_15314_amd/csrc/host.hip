@@ -101,6 +101,7 @@ struct sim_s {
   bool adj_ready = false;
   // reductions
   double *PART = nullptr, *RED = nullptr, *YDEV = nullptr;
+  double *COARSEFD = nullptr;  // eigen-decomposition of the coarsest grid (exact coarse solve)
   double *hpin = nullptr;
   // last-step statistics
   sim_step_stats last{};
@@ -158,7 +159,7 @@ std::string validate(const sim_config *c, std::vector<int> *dims) {
   if (c->krylov_restart < 1 || c->krylov_restart > MAX_RESTART) return "krylov_restart must be 1..64";
   if (c->krylov_maxit < 1) return "krylov_maxit must be >= 1";
   if (!(c->krylov_rtol > 0)) return "krylov_rtol must be > 0";
-  if (c->mg_pre < 1 || c->mg_post < 0 || c->mg_coarse_sweeps < 1) return "mg_pre >= 1, mg_coarse_sweeps >= 1";
+  if (c->mg_pre < 1 || c->mg_post < 0 || c->mg_coarse_sweeps < 0) return "mg_pre >= 1, mg_coarse_sweeps >= 0";
   if (c->outer_iters < 1) return "outer_iters must be >= 1";
   if (c->helm_maxit < 1 || !(c->helm_rtol > 0)) return "helm_maxit >= 1 and helm_rtol > 0";
   // multigrid hierarchy: halve while above mg_coarsest or too big for the coarse kernel
@@ -173,6 +174,8 @@ std::string validate(const sim_config *c, std::vector<int> *dims) {
   }
   if ((long long)n0 * n1 * n2 > coarse_max_cells()) return "grid cannot be coarsened to the coarse-kernel size";
   if (!is_even(n0) || !is_even(n1) || !is_even(n2)) return "coarsest multigrid grid must have even sizes";
+  if (c->mg_coarse_sweeps == 0 && (n0 > COARSE_FD_MAXN || n1 > COARSE_FD_MAXN || n2 > COARSE_FD_MAXN))
+    return "the exact coarse solve needs at most 32 cells per axis on the coarsest grid";
   // the plane-marching kernels handle two in-row values per thread on every grid-wide level
   if (dims)
     for (size_t l = 0; l + 3 < dims->size(); l += 3)
@@ -235,6 +238,8 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
   double *PART = cv.arr<double>(std::max(parts, hparts));
   double *RED = cv.arr<double>(4 * (MAX_RESTART + 2));
   double *YDEV = cv.arr<double>(MAX_RESTART + 2);
+  const int cdims[3] = {dims[dims.size() - 3], dims[dims.size() - 2], dims[dims.size() - 1]};
+  double *COARSEFD = cv.arr<double>(coarse_fd_size(cdims));
   if (s) {
     s->U = U; s->UM = UM; s->USTAR = USTAR; s->RHSU = RHSU; s->TMP3 = TMP3;
     s->P = P; s->RHSP = RHSP; s->BVEC = BVEC; s->PP = PP; s->TMPC = TMPC;
@@ -250,6 +255,7 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
     s->TCOUNT = TCOUNT; s->TLSTART = TLSTART; s->TFILL = TFILL; s->TLTMP = TLTMP; s->TLIST = TLIST;
     s->SEGOF = SEGOF; s->tl_cap = tl_cap; s->NZT = NZT;
     s->PART = PART; s->RED = RED; s->YDEV = YDEV;
+    s->COARSEFD = COARSEFD;
   }
   return cv.off + 256;
 }
@@ -423,7 +429,8 @@ sim_status vcycle(sim_t s, const TV *v, T *z) {
   int nl = (int)s->lv.size();
   int cyc = c.mg_coarse_sweeps;
   if (nl == 1) {
-    CKH((mg_coarse<T, TV>(s->lv[0].g, v, z, cyc, 1, st)));
+    if (cyc == 0) CKH((mg_coarse_fd<T, TV>(s->lv[0].g, v, z, s->COARSEFD, st)));
+    else CKH((mg_coarse<T, TV>(s->lv[0].g, v, z, cyc, 1, st)));
     return SIM_OK;
   }
   // descend
@@ -466,7 +473,10 @@ sim_status vcycle(sim_t s, const TV *v, T *z) {
   // coarse grid
   {
     ProbeScope prc(PR_COARSE, st);
-    CKH((mg_coarse<T, T>(s->lv[nl - 1].g, (const T *)s->lv[nl - 1].b, (T *)s->lv[nl - 1].x, cyc, 1, st)));
+    if (cyc == 0)
+      CKH((mg_coarse_fd<T, T>(s->lv[nl - 1].g, (const T *)s->lv[nl - 1].b, (T *)s->lv[nl - 1].x, s->COARSEFD, st)));
+    else
+      CKH((mg_coarse<T, T>(s->lv[nl - 1].g, (const T *)s->lv[nl - 1].b, (T *)s->lv[nl - 1].x, cyc, 1, st)));
   }
   // ascend
   for (int l = nl - 2; l >= 0; --l) {
@@ -1044,6 +1054,18 @@ sim_status sim_create(const sim_config *cfg, void *d_workspace, size_t bytes, in
   if (hipHostMalloc((void **)&s->hpin, 64 * 1024) != hipSuccess) {
     delete s;
     return SIM_EDEVICE;
+  }
+  {
+    const Geo &gcoarse = s->lv.back().g;
+    const int cn[3] = {gcoarse.n0, gcoarse.n1, gcoarse.n2};
+    const int cbc[3] = {cfg->bc[0], cfg->bc[1], cfg->bc[2]};
+    std::vector<double> fd((size_t)coarse_fd_size(cn));
+    coarse_fd_build(cn, cbc, gcoarse.h, fd.data());
+    if (hipMemcpy(s->COARSEFD, fd.data(), sizeof(double) * fd.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      hipHostFree(s->hpin);
+      delete s;
+      return SIM_EDEVICE;
+    }
   }
   hipStream_t st = s->st;
   bool ok = fill(s->U, 3 * s->N, 0.0, st) == hipSuccess && fill(s->UM, 3 * s->N, 0.0, st) == hipSuccess &&

@@ -80,6 +80,12 @@ hipError_t mg_prolong(const Geo &gf, T *xf, const Geo &gc, const T *xc, hipStrea
 template <typename T, typename TB>
 hipError_t mg_coarse(const Geo &gc, const TB *b, T *x, int cycles, int sweeps, hipStream_t s);
 int coarse_max_cells();
+// exact coarse solve by fast diagonalisation; fd from coarse_fd_build (device copy)
+template <typename T, typename TB>
+hipError_t mg_coarse_fd(const Geo &gc, const TB *b, T *x, const double *fd, hipStream_t s);
+int coarse_fd_size(const int n[3]);  // doubles
+void coarse_fd_build(const int n[3], const int bc[3], double h, double *out);
+constexpr int COARSE_FD_MAXN = 32;
 
 // ---- Lagrangian points (kernels_ib.hip) ------------------------------------
 struct BodyDev {

@@ -160,18 +160,52 @@ __device__ __forceinline__ T lds_nb(const T *x, LvlDim d, int bc0, int bc1, int 
   return s;
 }
 
+// 1 / (number of neighbours) for 0..6 neighbours
 template <typename T>
-__device__ void lds_smooth(T *x, const T *b, LvlDim d, int bc0, int bc1, int bc2, T h2, int color) {
-  int nc = d.n0 * d.n1 * d.n2;
-  for (int e = threadIdx.x; e < nc; e += COARSE_THREADS) {
-    int i, j, k;
-    lds_decode(d, e, i, j, k);
-    if (((i + j + k) & 1) != color) continue;
+__device__ __forceinline__ T inv_nn(int nn) {
+  return nn == 6 ? T(1) / T(6) : nn == 5 ? T(1) / T(5) : nn == 4 ? T(0.25) : nn == 3 ? T(1) / T(3) : T(1) / T(nn);
+}
+
+// Sync of the threads that take part in a coarse-kernel phase: the whole
+// workgroup, or only wavefront 0 for levels small enough for one wavefront
+// (its LDS operations complete in program order, so a compiler-level fence
+// between phases suffices).
+__device__ __forceinline__ void phase_sync(bool one_wave) {
+  if (one_wave) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  } else {
+    __syncthreads();
+  }
+}
+
+// One red-black half sweep over the cells of colour `color` only (the
+// in-row index of a colour-c cell of row (i, j) is k = 2 kh + ((i+j+c) & 1);
+// every level has an even n2).
+template <typename T>
+__device__ void lds_smooth(T *x, const T *b, LvlDim d, int bc0, int bc1, int bc2, T h2, int color, int nthr) {
+  const int hn2 = d.n2 >> 1;
+  const int nc = d.n0 * d.n1 * hn2;
+  for (int e = threadIdx.x; e < nc; e += nthr) {
+    int kh, r, i, j;
+    if (d.pow2) {
+      kh = e & (hn2 - 1);
+      r = e >> (d.l2 - 1);
+      j = r & (d.n1 - 1);
+      i = r >> d.l1;
+    } else {
+      kh = e % hn2;
+      r = e / hn2;
+      j = r % d.n1;
+      i = r / d.n1;
+    }
+    const int k = 2 * kh + ((i + j + color) & 1);
     int nn;
     T s = lds_nb(x, d, bc0, bc1, bc2, i, j, k, nn);
-    x[d.off + e] = (h2 * b[d.off + e] + s) / (T)nn;
+    const int q = d.off + (i * d.n1 + j) * d.n2 + k;
+    x[q] = (h2 * b[q] + s) * inv_nn<T>(nn);
   }
-  __syncthreads();
 }
 
 template <typename T>
@@ -252,66 +286,90 @@ __global__ void __launch_bounds__(COARSE_THREADS) k_coarse(Geo g, const TB *bin,
   for (int e = threadIdx.x; e < nc0; e += COARSE_THREADS) sb[e] -= (T)mean;
   __syncthreads();
 
+  // levels of at most 2 x 64 cells run on wavefront 0 alone
+  auto small = [&](const LvlDim &q) { return q.n0 * q.n1 * q.n2 <= 128; };
   for (int cyc = 0; cyc < cycles; ++cyc) {
     T h = (T)g.h;
     for (int l = 0; l + 1 < nl; ++l) {
       const LvlDim f = dims[l], c = dims[l + 1];
-      T h2 = h * h;
-      for (int s = 0; s < sweeps; ++s) {
-        lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 0);
-        lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 1);
+      const bool one = small(f);
+      const int nthr = one ? 64 : COARSE_THREADS;
+      if (!one || threadIdx.x < 64) {
+        T h2 = h * h;
+        for (int s = 0; s < sweeps; ++s) {
+          lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 0, nthr);
+          phase_sync(one);
+          lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 1, nthr);
+          phase_sync(one);
+        }
+        int ncc = c.n0 * c.n1 * c.n2;
+        T ih2 = T(1) / h2;
+        for (int e = threadIdx.x; e < ncc; e += nthr) {
+          int i, j, k;
+          lds_decode(c, e, i, j, k);
+          T acc = T(0);
+          for (int q = 0; q < 8; ++q)
+            acc += lds_resid(sx, sb, f, bc0, bc1, bc2, ih2, 2 * i + (q >> 2), 2 * j + ((q >> 1) & 1), 2 * k + (q & 1));
+          sb[c.off + e] = acc * (T)0.125;
+          sx[c.off + e] = T(0);
+        }
       }
-      int ncc = c.n0 * c.n1 * c.n2;
-      T ih2 = T(1) / h2;
-      for (int e = threadIdx.x; e < ncc; e += COARSE_THREADS) {
-        int i, j, k;
-        lds_decode(c, e, i, j, k);
-        T acc = T(0);
-        for (int q = 0; q < 8; ++q)
-          acc += lds_resid(sx, sb, f, bc0, bc1, bc2, ih2, 2 * i + (q >> 2), 2 * j + ((q >> 1) & 1), 2 * k + (q & 1));
-        sb[c.off + e] = acc * (T)0.125;
-        sx[c.off + e] = T(0);
-      }
-      __syncthreads();
+      if (one) phase_sync(true);
+      else __syncthreads();
       h = h * (T)2;
     }
     {
       const LvlDim f = dims[nl - 1];
-      T h2 = h * h;
-      for (int s = 0; s < bottom; ++s) {
-        lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 0);
-        lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 1);
+      const bool one = small(f);
+      const int nthr = one ? 64 : COARSE_THREADS;
+      if (!one || threadIdx.x < 64) {
+        T h2 = h * h;
+        for (int s = 0; s < bottom; ++s) {
+          lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 0, nthr);
+          phase_sync(one);
+          lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 1, nthr);
+          phase_sync(one);
+        }
       }
     }
     for (int l = nl - 2; l >= 0; --l) {
       h = h * (T)0.5;
       const LvlDim f = dims[l], c = dims[l + 1];
-      int ncf = f.n0 * f.n1 * f.n2;
-      for (int e = threadIdx.x; e < ncf; e += COARSE_THREADS) {
-        int i, j, k;
-        lds_decode(f, e, i, j, k);
-        int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
-        int I1 = coarse_partner(I0, i & 1, c.n0, bc0);
-        int J1 = coarse_partner(J0, j & 1, c.n1, bc1);
-        int K1 = coarse_partner(K0, k & 1, c.n2, bc2);
-        const T *xc = sx + c.off;
+      const bool one = small(f);
+      const int nthr = one ? 64 : COARSE_THREADS;
+      // the coarse level was written by all threads (large) or wavefront 0
+      if (!small(c) || !one) __syncthreads();
+      if (!one || threadIdx.x < 64) {
+        int ncf = f.n0 * f.n1 * f.n2;
+        for (int e = threadIdx.x; e < ncf; e += nthr) {
+          int i, j, k;
+          lds_decode(f, e, i, j, k);
+          int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
+          int I1 = coarse_partner(I0, i & 1, c.n0, bc0);
+          int J1 = coarse_partner(J0, j & 1, c.n1, bc1);
+          int K1 = coarse_partner(K0, k & 1, c.n2, bc2);
+          const T *xc = sx + c.off;
 #define XC(a, b, cc) xc[((a) * c.n1 + (b)) * c.n2 + (cc)]
-        T v0 = (T)0.75 * XC(I0, J0, K0) + (T)0.25 * XC(I1, J0, K0);
-        T v1 = (T)0.75 * XC(I0, J1, K0) + (T)0.25 * XC(I1, J1, K0);
-        T v2 = (T)0.75 * XC(I0, J0, K1) + (T)0.25 * XC(I1, J0, K1);
-        T v3 = (T)0.75 * XC(I0, J1, K1) + (T)0.25 * XC(I1, J1, K1);
+          T v0 = (T)0.75 * XC(I0, J0, K0) + (T)0.25 * XC(I1, J0, K0);
+          T v1 = (T)0.75 * XC(I0, J1, K0) + (T)0.25 * XC(I1, J1, K0);
+          T v2 = (T)0.75 * XC(I0, J0, K1) + (T)0.25 * XC(I1, J0, K1);
+          T v3 = (T)0.75 * XC(I0, J1, K1) + (T)0.25 * XC(I1, J1, K1);
 #undef XC
-        T w0 = (T)0.75 * v0 + (T)0.25 * v1;
-        T w1 = (T)0.75 * v2 + (T)0.25 * v3;
-        sx[f.off + e] += (T)0.75 * w0 + (T)0.25 * w1;
-      }
-      __syncthreads();
-      T h2 = h * h;
-      for (int s = 0; s < sweeps; ++s) {
-        lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 1);
-        lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 0);
+          T w0 = (T)0.75 * v0 + (T)0.25 * v1;
+          T w1 = (T)0.75 * v2 + (T)0.25 * v3;
+          sx[f.off + e] += (T)0.75 * w0 + (T)0.25 * w1;
+        }
+        phase_sync(one);
+        T h2 = h * h;
+        for (int s = 0; s < sweeps; ++s) {
+          lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 1, nthr);
+          phase_sync(one);
+          lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 0, nthr);
+          phase_sync(one);
+        }
       }
     }
+    __syncthreads();
   }
   for (int e = threadIdx.x; e < nc0; e += COARSE_THREADS) {
     int k = e % g.n2, r = e / g.n2, j = r % g.n1, i = r / g.n1;
@@ -326,12 +384,143 @@ hipError_t mg_coarse(const Geo &gc, const TB *b, T *x, int cycles, int sweeps, h
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Exact coarse-grid solve by fast diagonalisation (the direct method of
+// Sec. 4.2, here on the coarsest multigrid grid): the rediscretised
+// Laplacian of a box with a per-axis boundary type is a Kronecker sum
+// L = L0 (+) L1 (+) L2 of 1-D operators with known orthonormal eigenvectors
+// Q_a and eigenvalues lam_a, so
+//     x = (Q0 x Q1 x Q2) diag(1 / (lam0_i + lam1_j + lam2_k)) (Q0 x Q1 x Q2)^T b,
+// the constant mode (all eigenvalues zero) dropped (the pseudo-inverse).
+// One workgroup keeps the grid in LDS and applies the six 1-D transforms.
+constexpr int FD_MAXN = 32;
+constexpr int FD_CELLS = 4096;
+constexpr int FD_THREADS = 1024;
+
+template <typename T, typename TB>
+__global__ void __launch_bounds__(FD_THREADS) k_coarse_fd(Geo g, const TB *bin, T *xout, const double *fd) {
+  __shared__ T bufA[FD_CELLS];
+  __shared__ T bufB[FD_CELLS];
+  __shared__ T Q[3][FD_MAXN * FD_MAXN];
+  __shared__ T lam[3][FD_MAXN];
+  const int n[3] = {g.n0, g.n1, g.n2};
+  const int nc = g.n0 * g.n1 * g.n2;
+  const int tid = threadIdx.x;
+  {
+    const double *p = fd;
+    for (int a = 0; a < 3; ++a) {
+      for (int q = tid; q < n[a] * n[a]; q += FD_THREADS) Q[a][q] = (T)p[q];
+      p += n[a] * n[a];
+    }
+    for (int a = 0; a < 3; ++a) {
+      for (int q = tid; q < n[a]; q += FD_THREADS) lam[a][q] = (T)p[q];
+      p += n[a];
+    }
+  }
+  for (int e = tid; e < nc; e += FD_THREADS) {
+    int k = e % g.n2, r = e / g.n2, j = r % g.n1, i = r / g.n1;
+    bufA[e] = (T)bin[sidx(g, i, j, k)];
+  }
+  __syncthreads();
+  // one 1-D transform along axis a: out[.., m, ..] = sum_t M[t][m] in[.., t, ..]
+  // (forward, coefficients) or sum_t M[m][t] in[.., t, ..] (backward)
+  auto pass = [&](const T *in, T *out, int a, bool fwd) {
+    const int na = n[a];
+    const int stride = a == 2 ? 1 : (a == 1 ? g.n2 : g.n1 * g.n2);
+    const T *M = Q[a];
+    for (int e = tid; e < nc; e += FD_THREADS) {
+      const int ia = (e / stride) % na;
+      const int base = e - ia * stride;
+      T acc = T(0);
+      for (int t = 0; t < na; ++t) acc += (fwd ? M[t * na + ia] : M[ia * na + t]) * in[base + t * stride];
+      out[e] = acc;
+    }
+    __syncthreads();
+  };
+  pass(bufA, bufB, 2, true);
+  pass(bufB, bufA, 1, true);
+  pass(bufA, bufB, 0, true);
+  for (int e = tid; e < nc; e += FD_THREADS) {
+    int k = e % g.n2, r = e / g.n2, j = r % g.n1, i = r / g.n1;
+    T d = lam[0][i] + lam[1][j] + lam[2][k];
+    bufB[e] = d > T(0) ? bufB[e] / d : T(0);
+  }
+  __syncthreads();
+  pass(bufB, bufA, 0, false);
+  pass(bufA, bufB, 1, false);
+  pass(bufB, bufA, 2, false);
+  for (int e = tid; e < nc; e += FD_THREADS) {
+    int k = e % g.n2, r = e / g.n2, j = r % g.n1, i = r / g.n1;
+    xout[sidx(g, i, j, k)] = bufA[e];
+  }
+}
+
+template <typename T, typename TB>
+hipError_t mg_coarse_fd(const Geo &gc, const TB *b, T *x, const double *fd, hipStream_t s) {
+  if ((long long)gc.n0 * gc.n1 * gc.n2 > FD_CELLS || gc.n0 > FD_MAXN || gc.n1 > FD_MAXN || gc.n2 > FD_MAXN)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_coarse_fd<T, TB>), dim3(1), dim3(FD_THREADS), 0, s, gc, b, x, fd);
+  return hipGetLastError();
+}
+
+// Packed eigen-decompositions of the three 1-D Laplacians of a coarse grid
+// (host): Q0 (n0 x n0), Q1, Q2 row-major with the eigenvectors as columns,
+// then lam0, lam1, lam2.  No-slip axes: cell-centred Neumann operator,
+// eigenvectors cos(pi k (i + 1/2) / n), eigenvalues (4/h^2) sin^2(pi k / 2n).
+// Periodic axes: the constant, cos / sin(2 pi k i / n) pairs and, for even n,
+// (-1)^i, eigenvalues (4/h^2) sin^2(pi k / n).
+int coarse_fd_size(const int n[3]) { return n[0] * n[0] + n[1] * n[1] + n[2] * n[2] + n[0] + n[1] + n[2]; }
+void coarse_fd_build(const int n[3], const int bc[3], double h, double *out) {
+  const double pi = 3.14159265358979323846;
+  double *q = out;
+  double *l = out + n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
+  for (int a = 0; a < 3; ++a) {
+    const int na = n[a];
+    const double c = 4.0 / (h * h);
+    for (int col = 0; col < na; ++col) {
+      double lamv;
+      for (int i = 0; i < na; ++i) {
+        double v;
+        if (bc[a]) {
+          const double nrm = col == 0 ? sqrt((double)na) : sqrt(0.5 * na);
+          v = cos(pi * col * (i + 0.5) / na) / nrm;
+        } else if (col == 0) {
+          v = 1.0 / sqrt((double)na);
+        } else if ((na % 2 == 0) && col == na - 1) {
+          v = ((i & 1) ? -1.0 : 1.0) / sqrt((double)na);
+        } else {
+          const int k = (col + 1) / 2;  // columns 1, 2 -> k = 1 (cos, sin), 3, 4 -> k = 2 ...
+          const double th = 2.0 * pi * k * i / na;
+          v = ((col & 1) ? cos(th) : sin(th)) / sqrt(0.5 * na);
+        }
+        q[i * na + col] = v;
+      }
+      if (bc[a]) {
+        const double sn = sin(pi * col / (2.0 * na));
+        lamv = c * sn * sn;
+      } else if (col == 0) {
+        lamv = 0.0;
+      } else if ((na % 2 == 0) && col == na - 1) {
+        lamv = c;
+      } else {
+        const int k = (col + 1) / 2;
+        const double sn = sin(pi * k / na);
+        lamv = c * sn * sn;
+      }
+      l[col] = lamv;
+    }
+    q += na * na;
+    l += na;
+  }
+}
+
 #define INST(T, TB)                                                                                    \
   template hipError_t mg_smooth_first<T, TB>(const Geo &, T *, const TB *, hipStream_t);              \
   template hipError_t mg_smooth<T, TB>(const Geo &, T *, const TB *, int, hipStream_t);               \
   template hipError_t mg_restrict<T, TB>(const Geo &, const T *, const TB *, const Geo &, T *,         \
                                          hipStream_t);                                                 \
-  template hipError_t mg_coarse<T, TB>(const Geo &, const TB *, T *, int, int, hipStream_t);
+  template hipError_t mg_coarse<T, TB>(const Geo &, const TB *, T *, int, int, hipStream_t);                   \
+  template hipError_t mg_coarse_fd<T, TB>(const Geo &, const TB *, T *, const double *, hipStream_t);
 INST(float, float)
 INST(float, double)
 INST(double, double)

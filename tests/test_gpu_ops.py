@@ -121,3 +121,24 @@ def test_vcycle_fp32_contracts():
     r = b - (L @ z.ravel()).reshape(g.n)
     assert np.linalg.norm(r) / np.linalg.norm(b) < 0.25
     sim.close()
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 1), (1, 0, 0), (0, 1, 1)])
+@pytest.mark.parametrize("prec", [wl.PREC_FP64, wl.PREC_FP32MG])
+def test_exact_coarse_solve_is_pseudo_inverse(bc, prec):
+    """A 16^3 grid is its own coarsest grid: the preconditioner is then the
+    fast-diagonalisation solve alone and must equal L^+ (the oracle's
+    FFT/DCT pseudo-inverse) to the working precision."""
+    from oracle import poisson as opoisson
+    n = 16
+    cfg = wl.Config(n=(n, n, n), length=(1.0, 1.0, 1.0), bc=bc, precision=prec, mg_coarsest=16,
+                    mg_coarse_sweeps=0)
+    sim = Sim(cfg, 1)
+    g = omac.Grid(cfg.n, cfg.h, cfg.bc)
+    b = _rand(12, g.n)
+    z = sim.apply("precond", b).cpu().numpy()
+    ref = opoisson.solve_laplacian(g, b)
+    err = rel(z - z.mean(), ref)
+    print(f"bc {bc} prec {prec}: rel err {err:.2e}", flush=True)
+    assert err < (1e-12 if prec == wl.PREC_FP64 else 1e-5)
+    sim.close()
