@@ -102,6 +102,7 @@ struct sim_s {
   // reductions
   double *PART = nullptr, *RED = nullptr, *YDEV = nullptr;
   double *COARSEFD = nullptr;  // eigen-decomposition of the coarsest grid (exact coarse solve)
+  double *SIG2 = nullptr;      // squared scales of the unnormalised Krylov basis
   double *hpin = nullptr;
   // last-step statistics
   sim_step_stats last{};
@@ -238,6 +239,7 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
   double *PART = cv.arr<double>(std::max(parts, hparts));
   double *RED = cv.arr<double>(4 * (MAX_RESTART + 2));
   double *YDEV = cv.arr<double>(MAX_RESTART + 2);
+  double *SIG2 = cv.arr<double>(MAX_RESTART + 2);
   const int cdims[3] = {dims[dims.size() - 3], dims[dims.size() - 2], dims[dims.size() - 1]};
   double *COARSEFD = cv.arr<double>(coarse_fd_size(cdims));
   if (s) {
@@ -256,6 +258,7 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
     s->SEGOF = SEGOF; s->tl_cap = tl_cap; s->NZT = NZT;
     s->PART = PART; s->RED = RED; s->YDEV = YDEV;
     s->COARSEFD = COARSEFD;
+    s->SIG2 = SIG2;
   }
   return cv.off + 256;
 }
@@ -520,6 +523,7 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
   T *V = (T *)s->V;
   T *Z = (T *)s->Z;
   const bool sep_w = sizeof(T) != sizeof(double);  // orthogonalise in a float64 buffer
+  constexpr int SIG_STAGE = 4096;                    // pinned staging slots of sig^2
   sim_solve_stats loc{};
   sim_solve_stats &S = stt ? *stt : loc;
   S.iters = 0;
@@ -533,7 +537,7 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
     S.rel_res = 0;
     return isfinite(bn2) ? SIM_OK : fail(s, SIM_ENONFINITE, "non-finite right-hand side");
   }
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), sig(m + 1);
   auto Hij = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
   double beta = bnorm;
   const double *rvec = b;
@@ -543,6 +547,9 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
     rel = beta / bnorm;
     if (rel <= c.krylov_rtol || total >= c.krylov_maxit) break;
     CKH(scale_cast<T>(V, rvec, N, 1.0 / beta, st));
+    sig[0] = 1.0;
+    s->hpin[SIG_STAGE] = 1.0;
+    CKH(hipMemcpyAsync(s->SIG2, s->hpin + SIG_STAGE, sizeof(double), hipMemcpyHostToDevice, st));
     std::fill(gv.begin(), gv.end(), 0.0);
     gv[0] = beta;
     int jd = 0;
@@ -552,6 +559,10 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
       double *w = sep_w ? s->TMPC : (double *)vnext;
       if ((rc = vcycle<T, T>(s, vj, zj))) return rc;
       if ((rc = schur_matvec<T>(s, zj, w))) return rc;
+      // classical Gram-Schmidt on the unnormalised basis (v_i = sig_i V'_i):
+      // g_i = <w', V'_i>, V'_{j+1} = w' - sum_i sig_i^2 g_i V'_i and its norm
+      // in one pass; with w' = S~ z'_j = S~ z_j / sig_j the Hessenberg column
+      // is h_ij = sig_j sig_i g_i, h_{j+1,j} = sig_j |V'_{j+1}|.
       {
         ProbeScope pr(PR_MULTIDOT, st);
         CKH(multidot<T>(w, V, N, j + 1, N, s->PART, st));
@@ -559,16 +570,22 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
       CKH(finalize(s->PART, red_blocks(), j + 1, s->RED, st));
       {
         ProbeScope pr(PR_UPDATE_NORM, st);
-        CKH(update_norm<T>(w, V, N, j + 1, s->RED, N, s->PART + (long long)(MAX_RESTART + 1) * red_blocks(), st));
+        CKH(update_cast_norm<T>(vnext, w, V, N, j + 1, s->RED, s->SIG2, N,
+                                s->PART + (long long)(MAX_RESTART + 1) * red_blocks(), st));
       }
       CKH(finalize(s->PART + (long long)(MAX_RESTART + 1) * red_blocks(), red_blocks(), 1, s->RED + j + 1, st));
       double hc[MAX_RESTART + 2];
       if ((rc = fetch_red(s, s->RED, j + 2, hc))) return rc;
-      for (int i = 0; i <= j; ++i) Hij(i, j) = hc[i];
-      double hn = sqrt(std::max(hc[j + 1], 0.0));
-      if (!isfinite(hn)) return fail(s, SIM_ENONFINITE, "non-finite Krylov norm");
+      const double nrm = sqrt(std::max(hc[j + 1], 0.0));
+      if (!isfinite(nrm)) return fail(s, SIM_ENONFINITE, "non-finite Krylov norm");
+      for (int i = 0; i <= j; ++i) Hij(i, j) = sig[j] * sig[i] * hc[i];
+      const double hn = sig[j] * nrm;
       Hij(j + 1, j) = hn;
-      if (hn > 0) CKH(scale_cast<T>(vnext, w, N, 1.0 / hn, st));
+      if (nrm > 0) {
+        sig[j + 1] = 1.0 / nrm;
+        s->hpin[SIG_STAGE + j + 1] = sig[j + 1] * sig[j + 1];
+        CKH(hipMemcpyAsync(s->SIG2 + j + 1, s->hpin + SIG_STAGE + j + 1, sizeof(double), hipMemcpyHostToDevice, st));
+      }
       for (int i = 0; i < j; ++i) {
         double t0 = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
         Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
@@ -596,7 +613,7 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
       for (int k = i + 1; k < jd; ++k) v -= Hij(i, k) * y[k];
       y[i] = v / Hij(i, i);
     }
-    memcpy(s->hpin, y.data(), sizeof(double) * jd);
+    for (int i = 0; i < jd; ++i) s->hpin[i] = y[i] * sig[i];  // z_i = sig_i z'_i
     CKH(hipMemcpyAsync(s->YDEV, s->hpin, sizeof(double) * jd, hipMemcpyHostToDevice, st));
     CKH(sol_update<T>(x, Z, N, jd, s->YDEV, N, st));
     // true residual r = b - S~ x (in TMPC)

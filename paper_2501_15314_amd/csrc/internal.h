@@ -163,7 +163,11 @@ template <typename TV>
 hipError_t update_norm(double *w, const TV *V, long long stride, int nv, const double *hcoef,
                        long long n, double *part, hipStream_t s);
 template <typename TV>
-hipError_t scale_cast(TV *y, const double *x, long long n, double alpha, hipStream_t s);  // y = alpha x  // w -= sum h_i V_i ; |w|^2
+hipError_t scale_cast(TV *y, const double *x, long long n, double alpha, hipStream_t s);  // y = alpha x
+// vout = (TV)(w - sum_i sig2_i g_i V_i), partial |vout|^2 per block (g, sig2 on the device)
+template <typename TV>
+hipError_t update_cast_norm(TV *vout, const double *w, const TV *V, long long stride, int nv, const double *g,
+                            const double *sig2, long long n, double *part, hipStream_t s);  // w -= sum h_i V_i ; |w|^2
 hipError_t scale_inplace(double *x, long long n, double alpha, hipStream_t s);
 // ---- reverse-mode step (kernels_adj.hip) ------------------------------------
 // out[k][e] += scale * d/dX_{k,e} (a^T W(X) b), a a face field, b [K][3]

@@ -84,6 +84,51 @@ hipError_t multidot(const double *w, const TV *V, long long stride, int nv, long
   }
   return hipGetLastError();
 }
+
+// vout = (TV)(w - sum_i sig2_i g_i V_i) and partial |vout|^2 (vout may alias
+// w when TV is double): the next unnormalised basis vector in one pass
+template <typename TV>
+__global__ void __launch_bounds__(RED_T) k_update_cast_norm(TV *vout, const double *w, const TV *V, long long stride,
+                                                            int nv, const double *g, const double *sig2, long long n,
+                                                            double *part) {
+  __shared__ double hs[64];
+  __shared__ double sh[4];
+  for (int i = threadIdx.x; i < nv; i += RED_T) hs[i] = sig2[i] * g[i];
+  __syncthreads();
+  double acc = 0.0;
+  const long long n2 = n >> 1;
+  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n2; t += (long long)gridDim.x * RED_T) {
+    double2 v = *(const double2 *)(w + 2 * t);
+    for (int i = 0; i < nv; ++i) {
+      double a, b;
+      ld_pair(V + i * stride + 2 * t, a, b);
+      v.x -= hs[i] * a;
+      v.y -= hs[i] * b;
+    }
+    if (sizeof(TV) == 4) {
+      const float2 f = make_float2((float)v.x, (float)v.y);
+      *(float2 *)(vout + 2 * t) = f;
+      acc += (double)f.x * (double)f.x + (double)f.y * (double)f.y;
+    } else {
+      *(double2 *)(vout + 2 * t) = v;
+      acc += v.x * v.x + v.y * v.y;
+    }
+  }
+  acc = block_reduce(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+template <typename TV>
+hipError_t update_cast_norm(TV *vout, const double *w, const TV *V, long long stride, int nv, const double *g,
+                            const double *sig2, long long n, double *part, hipStream_t s) {
+  if (nv > 64 || (n & 1) || (stride & 1)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_update_cast_norm<TV>, dim3(RED_BLOCKS), dim3(RED_T), 0, s, vout, w, V, stride, nv, g, sig2, n,
+                     part);
+  return hipGetLastError();
+}
+template hipError_t update_cast_norm<float>(float *, const double *, const float *, long long, int, const double *,
+                                            const double *, long long, double *, hipStream_t);
+template hipError_t update_cast_norm<double>(double *, const double *, const double *, long long, int,
+                                             const double *, const double *, long long, double *, hipStream_t);
 template hipError_t multidot<float>(const double *, const float *, long long, int, long long, double *,
                                     hipStream_t);
 template hipError_t multidot<double>(const double *, const double *, long long, int, long long, double *,

@@ -67,7 +67,7 @@ def test_unrolled_gradient_matches_finite_differences():
     coords += [("om0", (b, a)) for b, a in [(0, 2), (1, 0), (0, 0), (1, 1)]]
     coords += [("phi0", (int(k), int(a))) for k, a in zip(rng.integers(0, w.n_points, 4), rng.integers(0, 3, 4))]
     assert len(coords) == 20
-    eps = dict(c0=2e-6, v0=1e-5, om0=1e-5, phi0=1e-3)
+    eps = dict(c0=2e-6, v0=1e-5, om0=1e-5, phi0=2e-2)
     worst = 0.0
     with torch.no_grad():
         for name, idx in coords:
