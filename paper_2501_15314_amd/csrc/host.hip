@@ -102,8 +102,8 @@ struct sim_s {
   // reductions
   double *PART = nullptr, *RED = nullptr, *YDEV = nullptr;
   double *COARSEFD = nullptr;  // eigen-decomposition of the coarsest grid (exact coarse solve)
-  double *SIG2 = nullptr;      // squared scales of the unnormalised Krylov basis
   double *hpin = nullptr;
+  double *hpin_dev = nullptr;  // device address of hpin
   // last-step statistics
   sim_step_stats last{};
   bool have_bodies = false;
@@ -239,7 +239,6 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
   double *PART = cv.arr<double>(std::max(parts, hparts));
   double *RED = cv.arr<double>(4 * (MAX_RESTART + 2));
   double *YDEV = cv.arr<double>(MAX_RESTART + 2);
-  double *SIG2 = cv.arr<double>(MAX_RESTART + 2);
   const int cdims[3] = {dims[dims.size() - 3], dims[dims.size() - 2], dims[dims.size() - 1]};
   double *COARSEFD = cv.arr<double>(coarse_fd_size(cdims));
   if (s) {
@@ -258,7 +257,6 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
     s->SEGOF = SEGOF; s->tl_cap = tl_cap; s->NZT = NZT;
     s->PART = PART; s->RED = RED; s->YDEV = YDEV;
     s->COARSEFD = COARSEFD;
-    s->SIG2 = SIG2;
   }
   return cv.off + 256;
 }
@@ -270,18 +268,19 @@ sim_status sync(sim_t s) {
   return SIM_OK;
 }
 
-// device scalar reduction result -> host (synchronises)
-sim_status fetch_red(sim_t s, const double *dptr, int n, double *out) {
-  CKH(hipMemcpyAsync(s->hpin, dptr, sizeof(double) * n, hipMemcpyDeviceToHost, s->st));
+// values that finalize mirrored into the pinned buffer at offset 0 -> host
+// (synchronises)
+sim_status read_mirror(sim_t s, int n, double *out) {
   CKH(hipStreamSynchronize(s->st));
   memcpy(out, s->hpin, sizeof(double) * n);
   return SIM_OK;
 }
 
+
 sim_status dev_norm2(sim_t s, const double *x, long long n, double *out) {
   CKH(dot2(x, x, n, s->PART, s->st));
-  CKH(finalize(s->PART, red_blocks(), 1, s->RED, s->st));
-  return fetch_red(s, s->RED, 1, out);
+  CKH(finalize(s->PART, red_blocks(), 1, s->RED, s->st, s->hpin_dev));
+  return read_mirror(s, 1, out);
 }
 
 // subtract the mean of a cell field (enqueued only; mean left in RED[0])
@@ -523,7 +522,6 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
   T *V = (T *)s->V;
   T *Z = (T *)s->Z;
   const bool sep_w = sizeof(T) != sizeof(double);  // orthogonalise in a float64 buffer
-  constexpr int SIG_STAGE = 4096;                    // pinned staging slots of sig^2
   sim_solve_stats loc{};
   sim_solve_stats &S = stt ? *stt : loc;
   S.iters = 0;
@@ -538,6 +536,7 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
     return isfinite(bn2) ? SIM_OK : fail(s, SIM_ENONFINITE, "non-finite right-hand side");
   }
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), sig(m + 1);
+  Coef64 sig2{};  // sig_i^2, passed by value to the update kernel
   auto Hij = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
   double beta = bnorm;
   const double *rvec = b;
@@ -548,8 +547,7 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
     if (rel <= c.krylov_rtol || total >= c.krylov_maxit) break;
     CKH(scale_cast<T>(V, rvec, N, 1.0 / beta, st));
     sig[0] = 1.0;
-    s->hpin[SIG_STAGE] = 1.0;
-    CKH(hipMemcpyAsync(s->SIG2, s->hpin + SIG_STAGE, sizeof(double), hipMemcpyHostToDevice, st));
+    sig2.v[0] = 1.0;
     std::fill(gv.begin(), gv.end(), 0.0);
     gv[0] = beta;
     int jd = 0;
@@ -567,15 +565,16 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
         ProbeScope pr(PR_MULTIDOT, st);
         CKH(multidot<T>(w, V, N, j + 1, N, s->PART, st));
       }
-      CKH(finalize(s->PART, red_blocks(), j + 1, s->RED, st));
+      CKH(finalize(s->PART, red_blocks(), j + 1, s->RED, st, s->hpin_dev));
       {
         ProbeScope pr(PR_UPDATE_NORM, st);
-        CKH(update_cast_norm<T>(vnext, w, V, N, j + 1, s->RED, s->SIG2, N,
+        CKH(update_cast_norm<T>(vnext, w, V, N, j + 1, s->RED, sig2, N,
                                 s->PART + (long long)(MAX_RESTART + 1) * red_blocks(), st));
       }
-      CKH(finalize(s->PART + (long long)(MAX_RESTART + 1) * red_blocks(), red_blocks(), 1, s->RED + j + 1, st));
+      CKH(finalize(s->PART + (long long)(MAX_RESTART + 1) * red_blocks(), red_blocks(), 1, s->RED + j + 1, st,
+                   s->hpin_dev + j + 1));
       double hc[MAX_RESTART + 2];
-      if ((rc = fetch_red(s, s->RED, j + 2, hc))) return rc;
+      if ((rc = read_mirror(s, j + 2, hc))) return rc;
       const double nrm = sqrt(std::max(hc[j + 1], 0.0));
       if (!isfinite(nrm)) return fail(s, SIM_ENONFINITE, "non-finite Krylov norm");
       for (int i = 0; i <= j; ++i) Hij(i, j) = sig[j] * sig[i] * hc[i];
@@ -583,8 +582,7 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
       Hij(j + 1, j) = hn;
       if (nrm > 0) {
         sig[j + 1] = 1.0 / nrm;
-        s->hpin[SIG_STAGE + j + 1] = sig[j + 1] * sig[j + 1];
-        CKH(hipMemcpyAsync(s->SIG2 + j + 1, s->hpin + SIG_STAGE + j + 1, sizeof(double), hipMemcpyHostToDevice, st));
+        sig2.v[j + 1] = sig[j + 1] * sig[j + 1];
       }
       for (int i = 0; i < j; ++i) {
         double t0 = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
@@ -613,15 +611,15 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
       for (int k = i + 1; k < jd; ++k) v -= Hij(i, k) * y[k];
       y[i] = v / Hij(i, i);
     }
-    for (int i = 0; i < jd; ++i) s->hpin[i] = y[i] * sig[i];  // z_i = sig_i z'_i
-    CKH(hipMemcpyAsync(s->YDEV, s->hpin, sizeof(double) * jd, hipMemcpyHostToDevice, st));
-    CKH(sol_update<T>(x, Z, N, jd, s->YDEV, N, st));
+    Coef64 yc{};
+    for (int i = 0; i < jd; ++i) yc.v[i] = y[i] * sig[i];  // z_i = sig_i z'_i
+    CKH(sol_update<T>(x, Z, N, jd, yc, N, st));
     // true residual r = b - S~ x (in TMPC)
     if ((rc = schur_matvec<double>(s, x, s->TMPC))) return rc;
     CKH(sub_mul(s->TMPC, b, s->TMPC, N, s->PART, st));
-    CKH(finalize(s->PART, red_blocks(), 1, s->RED, st));
+    CKH(finalize(s->PART, red_blocks(), 1, s->RED, st, s->hpin_dev));
     double r2;
-    if ((rc = fetch_red(s, s->RED, 1, &r2))) return rc;
+    if ((rc = read_mirror(s, 1, &r2))) return rc;
     if (!isfinite(r2)) return fail(s, SIM_ENONFINITE, "non-finite residual");
     beta = sqrt(r2);
     rvec = s->TMPC;
@@ -704,9 +702,9 @@ sim_status helm_solve(sim_t s, const double *rhs, double *u, sim_solve_stats *st
       ProbeScope pr(PR_HELM_RESID, st);
       CKH(helm_resid<T>(g, a0, c.nu, u, rhs, R, s->PART, &nb, st));
     }
-    CKH(finalize(s->PART, nb, 1, s->RED, st));
+    CKH(finalize(s->PART, nb, 1, s->RED, st, s->hpin_dev));
     double r2;
-    if ((rc = fetch_red(s, s->RED, 1, &r2))) return rc;
+    if ((rc = read_mirror(s, 1, &r2))) return rc;
     if (!isfinite(r2)) return fail(s, SIM_ENONFINITE, "non-finite momentum residual");
     rel = bnorm > 0 ? sqrt(r2) / bnorm : 0.0;
     if (S.nhist < 64) S.hist[S.nhist++] = rel;
@@ -738,17 +736,13 @@ sim_status helm_solve_any(sim_t s, const double *rhs, double *u, sim_solve_stats
 sim_status predictor(sim_t s, sim_step_stats &S, sim_status &hrc) {
   hipStream_t st = s->st;
   const sim_config &c = s->cfg;
-  const long long n3 = 3 * s->N;
   CKH(gather3(s->K, s->PERM, s->PHIN, s->PHIS, st));
   {
     ProbeScope pr(PR_MOM_RHS, st);
-    CKH(mom_rhs(s->g, c.dt, s->U, s->UM, s->P, s->RHSU, st));
+    CKH(mom_rhs(s->g, c.dt, s->U, s->UM, s->P, s->RHSU, s->USTAR, st));
   }
   CKH(band_apply(s->ker, false, s->g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, s->PHIS, 1.0,
                  s->RHSU, st));
-  CKH(scale_copy(s->USTAR, s->U, n3, 2.0, st));
-  CKH(axpby(s->USTAR, s->UM, n3, -1.0, 1.0, st));
-  CKH(zero_wall_faces(s->g, s->USTAR, st));
   hrc = helm_solve_any(s, s->RHSU, s->USTAR, &S.helm);
   if (hrc != SIM_OK && hrc != SIM_ENOTCONV) return hrc;
   return SIM_OK;
@@ -1069,6 +1063,11 @@ sim_status sim_create(const sim_config *cfg, void *d_workspace, size_t bytes, in
   s->ker = cfg->delta;
   s->c = cfg->lump_c;
   if (hipHostMalloc((void **)&s->hpin, 64 * 1024) != hipSuccess) {
+    delete s;
+    return SIM_EDEVICE;
+  }
+  if (hipHostGetDevicePointer((void **)&s->hpin_dev, s->hpin, 0) != hipSuccess) {
+    hipHostFree(s->hpin);
     delete s;
     return SIM_EDEVICE;
   }

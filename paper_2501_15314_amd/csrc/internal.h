@@ -50,7 +50,7 @@ hipError_t zero_wall_faces(const Geo &g, double *u3, hipStream_t s);
 hipError_t helm_apply(const Geo &g, double a0, double nu, const double *u3, double *y3,
                       hipStream_t s);
 hipError_t mom_rhs(const Geo &g, double dt, const double *u3, const double *um3, const double *p,
-                   double *out3, hipStream_t s);
+                   double *out3, double *guess3, hipStream_t s);  // guess3 (may be null) = 2u - um
 hipError_t convection(const Geo &g, const double *u3, double *out3, hipStream_t s);
 // helm_resid: r = b - A x (in precision TR), per-block partial sums of |r|^2
 template <typename TR>
@@ -158,16 +158,21 @@ int red_blocks();
 template <typename TV>
 hipError_t multidot(const double *w, const TV *V, long long stride, int nv, long long n,
                     double *part, hipStream_t s);  // part[blk*nv + i]
-hipError_t finalize(const double *part, int nblk, int nv, double *out, hipStream_t s);
+hipError_t finalize(const double *part, int nblk, int nv, double *out, hipStream_t s,
+                    double *host = nullptr);  // host: optional pinned mirror of out
 template <typename TV>
 hipError_t update_norm(double *w, const TV *V, long long stride, int nv, const double *hcoef,
                        long long n, double *part, hipStream_t s);
 template <typename TV>
 hipError_t scale_cast(TV *y, const double *x, long long n, double alpha, hipStream_t s);  // y = alpha x
-// vout = (TV)(w - sum_i sig2_i g_i V_i), partial |vout|^2 per block (g, sig2 on the device)
+// up to 64 coefficients passed by value to a kernel
+struct Coef64 {
+  double v[64];
+};
+// vout = (TV)(w - sum_i sig2_i g_i V_i), partial |vout|^2 per block (g on the device)
 template <typename TV>
 hipError_t update_cast_norm(TV *vout, const double *w, const TV *V, long long stride, int nv, const double *g,
-                            const double *sig2, long long n, double *part, hipStream_t s);  // w -= sum h_i V_i ; |w|^2
+                            const Coef64 &sig2, long long n, double *part, hipStream_t s);  // w -= sum h_i V_i ; |w|^2
 hipError_t scale_inplace(double *x, long long n, double alpha, hipStream_t s);
 // ---- reverse-mode step (kernels_adj.hip) ------------------------------------
 // out[k][e] += scale * d/dX_{k,e} (a^T W(X) b), a a face field, b [K][3]
@@ -178,8 +183,8 @@ hipError_t convection_adjoint(const Geo &g, const double *u3, const double *r3, 
 
 hipError_t scale_copy(double *y, const double *x, long long n, double alpha, hipStream_t s);
 template <typename T>
-hipError_t sol_update(double *x, const T *Z, long long stride, int nz, const double *y, long long n,
-                      hipStream_t s);  // x += sum y_j Z_j
+hipError_t sol_update(double *x, const T *Z, long long stride, int nz, const Coef64 &y, long long n,
+                      hipStream_t s);  // x += sum y_j Z_j  // x += sum y_j Z_j
 hipError_t axpby(double *y, const double *x, long long n, double a, double b,
                  hipStream_t s);  // y = a x + b y
 hipError_t add_scalar_dev(double *x, long long n, const double *dscalar, double mult,

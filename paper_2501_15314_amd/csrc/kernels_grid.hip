@@ -368,7 +368,8 @@ hipError_t convection(const Geo &g, const double *u3, double *out3, hipStream_t 
 }
 
 // rhs = (4 u^n - u^{n-1}) / (2 dt) - G p^n - N(u^n)     (eq. ustar; W Phi^n is
-// added afterwards by the band kernel).
+// added afterwards by the band kernel), and optionally the extrapolated
+// initial guess 2 u^n - u^{n-1} of the momentum solve (0 on wall faces).
 //
 // Tiled: a workgroup stages the three velocity components of a
 // (MR_TX+2) x (MR_TY+2) x (MR_TZ+2) natural-order box (the tile and a one-cell
@@ -382,8 +383,8 @@ constexpr int MR_RX = MR_TX + 2, MR_RY = MR_TY + 2, MR_RZ = MR_TZ + 2;
 constexpr int MR_REG = MR_RX * MR_RY * MR_RZ;
 
 __global__ void __launch_bounds__(MR_TY * MR_TZ) k_mom_rhs(Geo g, double dt, const double *u3, const double *um3,
-                                                           const double *p_, double *out3, int ntz, int nty,
-                                                           int ntiles) {
+                                                           const double *p_, double *out3, double *guess3, int ntz,
+                                                           int nty, int ntiles) {
   __shared__ double su[3][MR_REG];
   const long long N = 2 * g.half;
   // XCD-major tile order: block b runs on XCD b % 8
@@ -420,7 +421,7 @@ __global__ void __launch_bounds__(MR_TY * MR_TZ) k_mom_rhs(Geo g, double dt, con
     };
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      double v = 0.0;
+      double v = 0.0, gv = 0.0;
       if (!(geo_bc(g, d) && x0[d] == 0)) {
         const int ed0 = d == 0, ed1 = d == 1, ed2 = d == 2;
         double acc = 0.0;
@@ -444,17 +445,21 @@ __global__ void __launch_bounds__(MR_TY * MR_TZ) k_mom_rhs(Geo g, double dt, con
         }
         const double lo = fetch(p_, g, i - ed0, j - ed1, k - ed2);
         const double gp = (p_[e] - lo) * ih;
-        v = (4.0 * U(d, 0, 0, 0) - um3[d * N + e]) / (2.0 * dt) - gp - acc;
+        const double umv = um3[d * N + e];
+        v = (4.0 * U(d, 0, 0, 0) - umv) / (2.0 * dt) - gp - acc;
+        gv = 2.0 * U(d, 0, 0, 0) - umv;
       }
       out3[d * N + e] = v;
+      if (guess3) guess3[d * N + e] = gv;
     }
   }
 }
 hipError_t mom_rhs(const Geo &g, double dt, const double *u3, const double *um3, const double *p,
-                   double *out3, hipStream_t s) {
+                   double *out3, double *guess3, hipStream_t s) {
   const int ntx = (g.n0 + MR_TX - 1) / MR_TX, nty = (g.n1 + MR_TY - 1) / MR_TY, ntz = (g.n2 + MR_TZ - 1) / MR_TZ;
   const int ntiles = ntx * nty * ntz;
-  hipLaunchKernelGGL(k_mom_rhs, dim3(ntiles), dim3(MR_TY * MR_TZ), 0, s, g, dt, u3, um3, p, out3, ntz, nty, ntiles);
+  hipLaunchKernelGGL(k_mom_rhs, dim3(ntiles), dim3(MR_TY * MR_TZ), 0, s, g, dt, u3, um3, p, out3, guess3, ntz, nty,
+                     ntiles);
   return hipGetLastError();
 }
 

@@ -89,11 +89,11 @@ hipError_t multidot(const double *w, const TV *V, long long stride, int nv, long
 // w when TV is double): the next unnormalised basis vector in one pass
 template <typename TV>
 __global__ void __launch_bounds__(RED_T) k_update_cast_norm(TV *vout, const double *w, const TV *V, long long stride,
-                                                            int nv, const double *g, const double *sig2, long long n,
+                                                            int nv, const double *g, Coef64 sig2, long long n,
                                                             double *part) {
   __shared__ double hs[64];
   __shared__ double sh[4];
-  for (int i = threadIdx.x; i < nv; i += RED_T) hs[i] = sig2[i] * g[i];
+  for (int i = threadIdx.x; i < nv; i += RED_T) hs[i] = sig2.v[i] * g[i];
   __syncthreads();
   double acc = 0.0;
   const long long n2 = n >> 1;
@@ -119,23 +119,26 @@ __global__ void __launch_bounds__(RED_T) k_update_cast_norm(TV *vout, const doub
 }
 template <typename TV>
 hipError_t update_cast_norm(TV *vout, const double *w, const TV *V, long long stride, int nv, const double *g,
-                            const double *sig2, long long n, double *part, hipStream_t s) {
+                            const Coef64 &sig2, long long n, double *part, hipStream_t s) {
   if (nv > 64 || (n & 1) || (stride & 1)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_update_cast_norm<TV>, dim3(RED_BLOCKS), dim3(RED_T), 0, s, vout, w, V, stride, nv, g, sig2, n,
                      part);
   return hipGetLastError();
 }
 template hipError_t update_cast_norm<float>(float *, const double *, const float *, long long, int, const double *,
-                                            const double *, long long, double *, hipStream_t);
+                                            const Coef64 &, long long, double *, hipStream_t);
 template hipError_t update_cast_norm<double>(double *, const double *, const double *, long long, int,
-                                             const double *, const double *, long long, double *, hipStream_t);
+                                             const double *, const Coef64 &, long long, double *, hipStream_t);
 template hipError_t multidot<float>(const double *, const float *, long long, int, long long, double *,
                                     hipStream_t);
 template hipError_t multidot<double>(const double *, const double *, long long, int, long long, double *,
                                      hipStream_t);
 
-// out[i] = sum_b part[b][i] over nblk blocks (chunked layout of multidot)
-__global__ void __launch_bounds__(RED_T) k_finalize(const double *part, int nblk, int nv, double *out) {
+// out[i] = sum_b part[b][i] over nblk blocks (chunked layout of multidot);
+// with host != null the sums are also written to that pinned host buffer
+// (read by the host after the stream is synchronised, no separate copy)
+__global__ void __launch_bounds__(RED_T) k_finalize(const double *part, int nblk, int nv, double *out,
+                                                    double *host) {
   int i = blockIdx.x;
   int c0 = (i / MD_MAX) * MD_MAX;
   int nc = nv - c0 < MD_MAX ? nv - c0 : MD_MAX;
@@ -145,10 +148,16 @@ __global__ void __launch_bounds__(RED_T) k_finalize(const double *part, int nblk
   for (int b = threadIdx.x; b < nblk; b += RED_T) v += pc[(long long)b * nc + col];
   __shared__ double sh[4];
   v = block_reduce(v, sh);
-  if (threadIdx.x == 0) out[i] = v;
+  if (threadIdx.x == 0) {
+    out[i] = v;
+    if (host) {
+      host[i] = v;
+      __threadfence_system();
+    }
+  }
 }
-hipError_t finalize(const double *part, int nblk, int nv, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(nv), dim3(RED_T), 0, s, part, nblk, nv, out);
+hipError_t finalize(const double *part, int nblk, int nv, double *out, hipStream_t s, double *host) {
+  hipLaunchKernelGGL(k_finalize, dim3(nv), dim3(RED_T), 0, s, part, nblk, nv, out, host);
   return hipGetLastError();
 }
 
@@ -216,9 +225,9 @@ hipError_t scale_copy(double *y, const double *x, long long n, double alpha, hip
 }
 
 template <typename T>
-__global__ void k_sol_update(double *x, const T *Z, long long stride, int nz, const double *y, long long n) {
+__global__ void k_sol_update(double *x, const T *Z, long long stride, int nz, Coef64 y, long long n) {
   __shared__ double ys[64];
-  for (int i = threadIdx.x; i < nz; i += RED_T) ys[i] = y[i];
+  for (int i = threadIdx.x; i < nz; i += RED_T) ys[i] = y.v[i];
   __syncthreads();
   for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T) {
     double v = x[t];
@@ -227,15 +236,15 @@ __global__ void k_sol_update(double *x, const T *Z, long long stride, int nz, co
   }
 }
 template <typename T>
-hipError_t sol_update(double *x, const T *Z, long long stride, int nz, const double *y, long long n,
+hipError_t sol_update(double *x, const T *Z, long long stride, int nz, const Coef64 &y, long long n,
                       hipStream_t s) {
   if (nz > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_sol_update<T>, dim3(RED_BLOCKS * 4), dim3(RED_T), 0, s, x, Z, stride, nz, y, n);
   return hipGetLastError();
 }
-template hipError_t sol_update<float>(double *, const float *, long long, int, const double *, long long,
+template hipError_t sol_update<float>(double *, const float *, long long, int, const Coef64 &, long long,
                                       hipStream_t);
-template hipError_t sol_update<double>(double *, const double *, long long, int, const double *, long long,
+template hipError_t sol_update<double>(double *, const double *, long long, int, const Coef64 &, long long,
                                        hipStream_t);
 
 __global__ void k_axpby(double *y, const double *x, long long n, double a, double b) {
