@@ -69,6 +69,11 @@ enum { SIM_DELTA_PESKIN4 = 0, SIM_DELTA_ROMA3 = 1 };
  * relaxations run in float32 inside float64 outer iterations. */
 enum { SIM_PREC_FP64 = 0, SIM_PREC_FP32MG = 1 };
 enum { SIM_MOTION_PRESCRIBED = 0, SIM_MOTION_FREE = 1 };
+/* VCYCLE: one geometric-multigrid V-cycle approximating L^+ (mg_* fields).
+ * FASTDIAG: L^+ by fast diagonalisation of the whole grid (the direct method
+ * of paper Sec. 4.2): six batched eigenbasis transforms on the matrix cores
+ * with bfloat16 operands and float32 accumulation. */
+enum { SIM_PRECOND_VCYCLE = 0, SIM_PRECOND_FASTDIAG = 1 };
 
 typedef struct {
   int32_t n[3];          /* cells per axis; multiples of 4, >= 16 */
@@ -90,6 +95,7 @@ typedef struct {
   int32_t mg_coarse_sweeps;    /* coarsest grid: 0 = exact solve by fast diagonalisation
                                   (<= 32 cells per axis), k >= 1 = k V-cycles of the
                                   LDS-resident coarse kernel */
+  int32_t precond;       /* SIM_PRECOND_*: preconditioner of the Schur Krylov solve */
   int32_t outer_iters;   /* pressure-force corrections per step (>= 1) */
   double outer_tol;      /* stop on ||Phi'||_1 / ||Phi||_1 < tol (0: fixed) */
   double xi;             /* relaxation of the correction (1 for one-way) */

@@ -102,6 +102,12 @@ struct sim_s {
   // reductions
   double *PART = nullptr, *RED = nullptr, *YDEV = nullptr;
   double *COARSEFD = nullptr;  // eigen-decomposition of the coarsest grid (exact coarse solve)
+  // whole-grid fast-diagonalisation preconditioner: eigenbases (float) and two
+  // bfloat16 scratch grids
+  bool fastdiag = false;
+  bool coarse_mfma = false;  // exact coarse solve on the matrix cores
+  unsigned char *FDQ = nullptr;  // packed eigenbases (fd_blob_pack)
+  unsigned short *FDW1 = nullptr, *FDW2 = nullptr;
   double *hpin = nullptr;
   double *hpin_dev = nullptr;  // device address of hpin
   // last-step statistics
@@ -161,22 +167,30 @@ std::string validate(const sim_config *c, std::vector<int> *dims) {
   if (c->krylov_maxit < 1) return "krylov_maxit must be >= 1";
   if (!(c->krylov_rtol > 0)) return "krylov_rtol must be > 0";
   if (c->mg_pre < 1 || c->mg_post < 0 || c->mg_coarse_sweeps < 0) return "mg_pre >= 1, mg_coarse_sweeps >= 0";
+  if (c->precond != SIM_PRECOND_VCYCLE && c->precond != SIM_PRECOND_FASTDIAG) return "bad precond";
   if (c->outer_iters < 1) return "outer_iters must be >= 1";
   if (c->helm_maxit < 1 || !(c->helm_rtol > 0)) return "helm_maxit >= 1 and helm_rtol > 0";
   // multigrid hierarchy: halve while above mg_coarsest or too big for the coarse kernel
   int n0 = c->n[0], n1 = c->n[1], n2 = c->n[2];
   if (dims) dims->clear();
   if (dims) { dims->push_back(n0); dims->push_back(n1); dims->push_back(n2); }
+  // exact coarse solves (mg_coarse_sweeps = 0) take any coarsest grid: small
+  // ones in one LDS workgroup, larger ones on the matrix cores
+  const bool exact = c->mg_coarse_sweeps == 0;
   while ((std::max(n0, std::max(n1, n2)) > c->mg_coarsest ||
-          (long long)n0 * n1 * n2 > coarse_max_cells())) {
+          (!exact && (long long)n0 * n1 * n2 > coarse_max_cells()))) {
     if (!is_even(n0) || !is_even(n1) || !is_even(n2) || n0 < 4 || n1 < 4 || n2 < 4) break;
     n0 /= 2; n1 /= 2; n2 /= 2;
     if (dims) { dims->push_back(n0); dims->push_back(n1); dims->push_back(n2); }
   }
-  if ((long long)n0 * n1 * n2 > coarse_max_cells()) return "grid cannot be coarsened to the coarse-kernel size";
-  if (!is_even(n0) || !is_even(n1) || !is_even(n2)) return "coarsest multigrid grid must have even sizes";
-  if (c->mg_coarse_sweeps == 0 && (n0 > COARSE_FD_MAXN || n1 > COARSE_FD_MAXN || n2 > COARSE_FD_MAXN))
-    return "the exact coarse solve needs at most 32 cells per axis on the coarsest grid";
+  if (!exact && (long long)n0 * n1 * n2 > coarse_max_cells()) return "grid cannot be coarsened to the coarse-kernel size";
+  if (!exact && (!is_even(n0) || !is_even(n1) || !is_even(n2))) return "coarsest multigrid grid must have even sizes";
+  // the matrix-core fast diagonalisation takes sizes that are multiples of 4, up to 512
+  auto mfma_fd_ok = [](int a, int b, int d) { return a % 4 == 0 && b % 4 == 0 && d % 4 == 0 && a <= 512 && b <= 512 && d <= 512; };
+  if (c->precond == SIM_PRECOND_FASTDIAG && !mfma_fd_ok(c->n[0], c->n[1], c->n[2]))
+    return "the fast-diagonalisation preconditioner takes axis sizes up to 512";
+  if (exact && c->precond == SIM_PRECOND_VCYCLE && !coarse_lds_fits(n0, n1, n2) && !mfma_fd_ok(n0, n1, n2))
+    return "an exact coarse solve above 32 per axis needs coarsest sizes that are multiples of 4, up to 512";
   // the plane-marching kernels handle two in-row values per thread on every grid-wide level
   if (dims)
     for (size_t l = 0; l + 3 < dims->size(); l += 3)
@@ -241,6 +255,15 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
   double *YDEV = cv.arr<double>(MAX_RESTART + 2);
   const int cdims[3] = {dims[dims.size() - 3], dims[dims.size() - 2], dims[dims.size() - 1]};
   double *COARSEFD = cv.arr<double>(coarse_fd_size(cdims));
+  // matrix-core fast diagonalisation: of the whole grid (FASTDIAG
+  // preconditioner) or of a coarsest grid too large for the LDS solver
+  const bool fdg = c->precond == SIM_PRECOND_FASTDIAG;
+  const bool fdc = !fdg && c->mg_coarse_sweeps == 0 && !coarse_lds_fits(cdims[0], cdims[1], cdims[2]);
+  const int *fdn = fdg ? c->n : cdims;
+  const long long fdcells = (long long)fdn[0] * fdn[1] * fdn[2];
+  unsigned char *FDQ = (fdg || fdc) ? cv.arr<unsigned char>((long long)fd_blob_bytes(fdn)) : nullptr;
+  unsigned short *FDW1 = (fdg || fdc) ? cv.arr<unsigned short>(fdcells) : nullptr;
+  unsigned short *FDW2 = (fdg || fdc) ? cv.arr<unsigned short>(fdcells) : nullptr;
   if (s) {
     s->U = U; s->UM = UM; s->USTAR = USTAR; s->RHSU = RHSU; s->TMP3 = TMP3;
     s->P = P; s->RHSP = RHSP; s->BVEC = BVEC; s->PP = PP; s->TMPC = TMPC;
@@ -257,6 +280,9 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
     s->SEGOF = SEGOF; s->tl_cap = tl_cap; s->NZT = NZT;
     s->PART = PART; s->RED = RED; s->YDEV = YDEV;
     s->COARSEFD = COARSEFD;
+    s->fastdiag = fdg;
+    s->coarse_mfma = fdc;
+    s->FDQ = FDQ; s->FDW1 = FDW1; s->FDW2 = FDW2;
   }
   return cv.off + 256;
 }
@@ -431,7 +457,8 @@ sim_status vcycle(sim_t s, const TV *v, T *z) {
   int nl = (int)s->lv.size();
   int cyc = c.mg_coarse_sweeps;
   if (nl == 1) {
-    if (cyc == 0) CKH((mg_coarse_fd<T, TV>(s->lv[0].g, v, z, s->COARSEFD, st)));
+    if (cyc == 0 && s->coarse_mfma) CKH((fd_precond<TV, T>(s->lv[0].g, v, z, s->FDW1, s->FDW2, s->FDQ, 1.0f, st)));
+    else if (cyc == 0) CKH((mg_coarse_fd<T, TV>(s->lv[0].g, v, z, s->COARSEFD, st)));
     else CKH((mg_coarse<T, TV>(s->lv[0].g, v, z, cyc, 1, st)));
     return SIM_OK;
   }
@@ -475,7 +502,10 @@ sim_status vcycle(sim_t s, const TV *v, T *z) {
   // coarse grid
   {
     ProbeScope prc(PR_COARSE, st);
-    if (cyc == 0)
+    if (cyc == 0 && s->coarse_mfma)
+      CKH((fd_precond<T, T>(s->lv[nl - 1].g, (const T *)s->lv[nl - 1].b, (T *)s->lv[nl - 1].x, s->FDW1, s->FDW2,
+                            s->FDQ, 1.0f, st)));
+    else if (cyc == 0)
       CKH((mg_coarse_fd<T, T>(s->lv[nl - 1].g, (const T *)s->lv[nl - 1].b, (T *)s->lv[nl - 1].x, s->COARSEFD, st)));
     else
       CKH((mg_coarse<T, T>(s->lv[nl - 1].g, (const T *)s->lv[nl - 1].b, (T *)s->lv[nl - 1].x, cyc, 1, st)));
@@ -555,7 +585,12 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
       T *zj = Z + (long long)j * N;
       T *vj = V + (long long)j * N, *vnext = V + (long long)(j + 1) * N;
       double *w = sep_w ? s->TMPC : (double *)vnext;
-      if ((rc = vcycle<T, T>(s, vj, zj))) return rc;
+      if (s->fastdiag) {
+        ProbeScope pr(PR_VCYCLE, st);
+        CKH((fd_precond<T, T>(s->g, vj, zj, s->FDW1, s->FDW2, s->FDQ, (float)sig[j], st)));
+      } else if ((rc = vcycle<T, T>(s, vj, zj))) {
+        return rc;
+      }
       if ((rc = schur_matvec<T>(s, zj, w))) return rc;
       // classical Gram-Schmidt on the unnormalised basis (v_i = sig_i V'_i):
       // g_i = <w', V'_i>, V'_{j+1} = w' - sum_i sig_i^2 g_i V'_i and its norm
@@ -1082,6 +1117,19 @@ sim_status sim_create(const sim_config *cfg, void *d_workspace, size_t bytes, in
       delete s;
       return SIM_EDEVICE;
     }
+    if (s->fastdiag || s->coarse_mfma) {
+      const Geo &gq = s->fastdiag ? s->lv[0].g : gcoarse;
+      const int fn[3] = {gq.n0, gq.n1, gq.n2};
+      std::vector<double> qd((size_t)coarse_fd_size(fn));
+      coarse_fd_build(fn, cbc, gq.h, qd.data());
+      std::vector<unsigned char> blob(fd_blob_bytes(fn));
+      fd_blob_pack(fn, qd.data(), blob.data());
+      if (hipMemcpy(s->FDQ, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        hipHostFree(s->hpin);
+        delete s;
+        return SIM_EDEVICE;
+      }
+    }
   }
   hipStream_t st = s->st;
   bool ok = fill(s->U, 3 * s->N, 0.0, st) == hipSuccess && fill(s->UM, 3 * s->N, 0.0, st) == hipSuccess &&
@@ -1462,7 +1510,9 @@ sim_status sim_apply(sim_t s, int32_t op, const double *in, const double *in2, d
       break;
     case SIM_OP_PRECOND:
       CKH(to_split(g, 1, in, s->TMPC, st));
-      if (s->fp32) {
+      if (s->fastdiag) {
+        CKH((fd_precond<double, double>(g, s->TMPC, s->PP, s->FDW1, s->FDW2, s->FDQ, 1.0f, st)));
+      } else if (s->fp32) {
         if ((rc = vcycle<float, double>(s, s->TMPC, (float *)s->Z))) return rc;
         CKH(fill(s->PP, N, 0.0, st));
         CKH(add_cast<float>(s->PP, (const float *)s->Z, N, st));

@@ -84,8 +84,21 @@ int coarse_max_cells();
 template <typename T, typename TB>
 hipError_t mg_coarse_fd(const Geo &gc, const TB *b, T *x, const double *fd, hipStream_t s);
 int coarse_fd_size(const int n[3]);  // doubles
+// z = L^+ v on a grid by fast diagonalisation (bfloat16 matrix-core
+// transforms); w1, w2: bfloat16 scratch grids; blob: eigenbases packed by
+// fd_blob_pack from coarse_fd_build's output (device copy)
+template <typename TI, typename T>
+hipError_t fd_precond(const Geo &g, const TI *v, T *z, unsigned short *w1, unsigned short *w2, const void *blob,
+                      float vscale, hipStream_t s);
+size_t fd_blob_bytes(const int n[3]);
+void fd_blob_pack(const int n[3], const double *qd, unsigned char *out);
+
 void coarse_fd_build(const int n[3], const int bc[3], double h, double *out);
 constexpr int COARSE_FD_MAXN = 32;
+// whether the single-workgroup exact coarse solver takes this grid
+inline bool coarse_lds_fits(int n0, int n1, int n2) {
+  return n0 <= COARSE_FD_MAXN && n1 <= COARSE_FD_MAXN && n2 <= COARSE_FD_MAXN && n0 * n1 * n2 <= 4096;
+}
 
 // ---- Lagrangian points (kernels_ib.hip) ------------------------------------
 struct BodyDev {

@@ -39,6 +39,7 @@ def make_config(cfg: Config, stream=None) -> _lib.SimConfig:
     c.helm_maxit, c.helm_rtol = cfg.helm_maxit, cfg.helm_rtol
     c.mg_coarsest, c.mg_pre, c.mg_post = cfg.mg_coarsest, cfg.mg_pre, cfg.mg_post
     c.mg_coarse_sweeps = cfg.mg_coarse_sweeps
+    c.precond = cfg.precond
     c.outer_iters, c.outer_tol, c.xi = cfg.outer_iters, cfg.outer_tol, cfg.xi
     c.device = cfg.device
     c.stream = stream if stream is not None else torch.cuda.current_stream(cfg.device).cuda_stream

@@ -142,3 +142,41 @@ def test_exact_coarse_solve_is_pseudo_inverse(bc, prec):
     print(f"bc {bc} prec {prec}: rel err {err:.2e}", flush=True)
     assert err < (1e-12 if prec == wl.PREC_FP64 else 1e-5)
     sim.close()
+
+
+@pytest.mark.parametrize("case", ["c1_periodic", "walls", "mixed"])
+def test_fastdiag_preconditioner_is_pseudo_inverse(case):
+    """The whole-grid fast-diagonalisation preconditioner approximates L^+ to
+    the bfloat16 rounding of its six transforms."""
+    from oracle import poisson as opoisson
+    w = _cases()[case]()
+    w.cfg.precond = wl.PRECOND_FASTDIAG
+    sim = Sim(w.cfg, w.n_points)
+    g = omac.Grid(w.cfg.n, w.cfg.h, w.cfg.bc)
+    b = _rand(13, g.n)
+    z = sim.apply("precond", b).cpu().numpy()
+    ref = opoisson.solve_laplacian(g, b)
+    err = rel(z - z.mean(), ref)
+    print(f"{case}: fast-diagonalisation rel err {err:.2e}", flush=True)
+    assert err < 2e-2
+    sim.close()
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 1), (1, 0, 1)])
+def test_exact_coarse_solve_on_matrix_cores(bc):
+    """A 32^3 coarsest grid is too large for the single-workgroup solver, so
+    the exact coarse solve runs the bfloat16 matrix-core fast diagonalisation:
+    it must equal L^+ to that rounding."""
+    from oracle import poisson as opoisson
+    n = 32
+    cfg = wl.Config(n=(n, n, n), length=(1.0, 1.0, 1.0), bc=bc, precision=wl.PREC_FP32MG, mg_coarsest=32,
+                    mg_coarse_sweeps=0)
+    sim = Sim(cfg, 1)
+    g = omac.Grid(cfg.n, cfg.h, cfg.bc)
+    b = _rand(14, g.n)
+    z = sim.apply("precond", b).cpu().numpy()
+    ref = opoisson.solve_laplacian(g, b)
+    err = rel(z - z.mean(), ref)
+    print(f"bc {bc}: matrix-core coarse solve rel err {err:.2e}", flush=True)
+    assert err < 2e-2
+    sim.close()

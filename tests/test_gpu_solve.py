@@ -33,11 +33,13 @@ def _roma(w):
 
 @pytest.mark.parametrize("case", list(CASES))
 @pytest.mark.parametrize("prec", [wl.PREC_FP64, wl.PREC_FP32MG])
-def test_schur_solve_matches_oracle(case, prec):
+@pytest.mark.parametrize("precond", [wl.PRECOND_VCYCLE, wl.PRECOND_FASTDIAG])
+def test_schur_solve_matches_oracle(case, prec, precond):
     w = CASES[case]()
     w.cfg.precision = prec
+    w.cfg.precond = precond
     w.cfg.krylov_rtol = 1e-12 if prec == wl.PREC_FP64 else 1e-11
-    print(f"case {case} prec {prec} n={w.cfg.n} K={w.n_points}", flush=True)
+    print(f"case {case} prec {prec} precond {precond} n={w.cfg.n} K={w.n_points}", flush=True)
     sim = Sim(w.cfg, w.n_points)
     sim.set_bodies(w.bodies, w.offsets)
     g, X, W, S = oracle_for(w)
