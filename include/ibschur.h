@@ -72,7 +72,8 @@ enum { SIM_MOTION_PRESCRIBED = 0, SIM_MOTION_FREE = 1 };
 /* VCYCLE: one geometric-multigrid V-cycle approximating L^+ (mg_* fields).
  * FASTDIAG: L^+ by fast diagonalisation of the whole grid (the direct method
  * of paper Sec. 4.2): six batched eigenbasis transforms on the matrix cores
- * with bfloat16 operands and float32 accumulation. */
+ * with bfloat16 operands and float32 accumulation; every n[d] a multiple of
+ * 8, at most 512 (else sim_create returns SIM_EINVAL). */
 enum { SIM_PRECOND_VCYCLE = 0, SIM_PRECOND_FASTDIAG = 1 };
 
 typedef struct {
@@ -93,8 +94,10 @@ typedef struct {
   int32_t mg_coarsest;   /* grid-wide V-cycle levels stop above this size */
   int32_t mg_pre, mg_post;     /* red-black Gauss-Seidel sweeps per level */
   int32_t mg_coarse_sweeps;    /* coarsest grid: 0 = exact solve by fast diagonalisation
-                                  (<= 32 cells per axis), k >= 1 = k V-cycles of the
-                                  LDS-resident coarse kernel */
+                                  (one LDS workgroup up to 32 cells per axis and 4096
+                                  cells; above that on the matrix cores in bfloat16,
+                                  sizes multiples of 8, <= 512), k >= 1 = k V-cycles
+                                  of the LDS-resident coarse kernel */
   int32_t precond;       /* SIM_PRECOND_*: preconditioner of the Schur Krylov solve */
   int32_t outer_iters;   /* pressure-force corrections per step (>= 1) */
   double outer_tol;      /* stop on ||Phi'||_1 / ||Phi||_1 < tol (0: fixed) */

@@ -185,12 +185,12 @@ std::string validate(const sim_config *c, std::vector<int> *dims) {
   }
   if (!exact && (long long)n0 * n1 * n2 > coarse_max_cells()) return "grid cannot be coarsened to the coarse-kernel size";
   if (!exact && (!is_even(n0) || !is_even(n1) || !is_even(n2))) return "coarsest multigrid grid must have even sizes";
-  // the matrix-core fast diagonalisation takes sizes that are multiples of 4, up to 512
-  auto mfma_fd_ok = [](int a, int b, int d) { return a % 4 == 0 && b % 4 == 0 && d % 4 == 0 && a <= 512 && b <= 512 && d <= 512; };
+  // the matrix-core fast diagonalisation takes sizes that are multiples of 8, up to 512
+  auto mfma_fd_ok = [](int a, int b, int d) { return a % 8 == 0 && b % 8 == 0 && d % 8 == 0 && a <= 512 && b <= 512 && d <= 512; };
   if (c->precond == SIM_PRECOND_FASTDIAG && !mfma_fd_ok(c->n[0], c->n[1], c->n[2]))
-    return "the fast-diagonalisation preconditioner takes axis sizes up to 512";
+    return "the fast-diagonalisation preconditioner takes axis sizes that are multiples of 8, up to 512";
   if (exact && c->precond == SIM_PRECOND_VCYCLE && !coarse_lds_fits(n0, n1, n2) && !mfma_fd_ok(n0, n1, n2))
-    return "an exact coarse solve above 32 per axis needs coarsest sizes that are multiples of 4, up to 512";
+    return "an exact coarse solve above the single-workgroup size needs coarsest sizes that are multiples of 8, up to 512";
   // the plane-marching kernels handle two in-row values per thread on every grid-wide level
   if (dims)
     for (size_t l = 0; l + 3 < dims->size(); l += 3)

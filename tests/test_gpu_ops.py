@@ -180,3 +180,21 @@ def test_exact_coarse_solve_on_matrix_cores(bc):
     print(f"bc {bc}: matrix-core coarse solve rel err {err:.2e}", flush=True)
     assert err < 2e-2
     sim.close()
+
+
+@pytest.mark.parametrize("n,bc", [((16, 24, 272), (0, 1, 1)), ((264, 16, 48), (1, 0, 1))])
+def test_fastdiag_long_axis(n, bc):
+    """Axes longer than 256 take the eight-tile-per-wavefront variant of the
+    transform kernel; sizes not a multiple of 16 or 64 exercise the padding."""
+    from oracle import poisson as opoisson
+    cfg = wl.Config(n=n, length=tuple(x / 64.0 for x in n), bc=bc, precision=wl.PREC_FP32MG,
+                    precond=wl.PRECOND_FASTDIAG)
+    sim = Sim(cfg, 1)
+    g = omac.Grid(cfg.n, cfg.h, cfg.bc)
+    b = _rand(15, g.n)
+    z = sim.apply("precond", b).cpu().numpy()
+    ref = opoisson.solve_laplacian(g, b)
+    err = rel(z - z.mean(), ref)
+    print(f"n {n} bc {bc}: fast-diagonalisation rel err {err:.2e}", flush=True)
+    assert err < 2e-2
+    sim.close()
