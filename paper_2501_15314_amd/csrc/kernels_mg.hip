@@ -43,56 +43,154 @@ __device__ __forceinline__ T nb_sum(const Geo &g, const T *x, int i, int j, int 
 
 // Coarse right-hand side: the average of the fine residual over the eight
 // children.  The last half sweep relaxed the black cells, whose residual is
-// therefore zero; only the four red children contribute.
+// therefore zero; only the four red children contribute: in fine planes 2I
+// and 2I+1, rows 2J and 2J+1, each at in-row index K of the red plane.
+//
+// Plane march over the fine grid like the sweeps (register window of black
+// planes along axis 0, LDS tile of the current black plane): a thread forms
+// the residuals of its two red cells (in-row m0, m0+1 = coarse K, K+1),
+// sums them over the plane pair, and the pair of rows is combined through
+// LDS; the even-row thread writes the two coarse values (one per colour).
+// The chunk of planes per workgroup is even, so a pair never splits.
+__host__ __device__ inline int restrict_chunk(const Geo &gf) { return march_chunk(gf) < 2 ? 2 : march_chunk(gf); }
+
 template <typename T, typename TB>
-__global__ void k_restrict(Geo gf, const T *xf, const TB *bf, Geo gc, T *bc) {
-  RowPos p;
-  if (!row_pos(gc, p)) return;
-  const int ch[4][3] = {{0, 0, 0}, {0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
-  T acc = T(0);
-  T ih2 = (T)(1.0 / gf.h2);
+__global__ void __launch_bounds__(256) k_restrict(Geo gf, const T *xf, const TB *bf, Geo gc, T *bc) {
+  __shared__ T tile[MARCH_TILE];
+  __shared__ T pair[256][2];
+  const int BX = blockDim.x, BY = blockDim.y, W2 = 2 * BX + 2;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + BX * ty;
+  const int m0 = 2 * (blockIdx.x * BX + tx), j = blockIdx.y * BY + ty;
+  const int len = restrict_chunk(gf);
+  const int i0 = blockIdx.z * len, i1 = min(i0 + len, gf.n0);
+  const T *red = xf, *blk = xf + gf.half;
+  const int mbase = blockIdx.x * BX * 2, jbase = blockIdx.y * BY;
+  auto row = [&](int i, int jj) { return ((long long)i * gf.n1 + jj) * gf.hn2; };
+  auto bval = [&](int i, int jj, int mm) -> T { return blk[row(i, jj) + mm]; };
+  auto bwin = [&](int i) -> V2<T> {
+    V2<T> v;
+    v.x = T(0);
+    v.y = T(0);
+    const int ii = mwrap(i, gf.n0, gf.bc0);
+    if (ii < 0) return v;
+    return ld2<T>(blk + row(ii, j) + m0);
+  };
+  const T ih2 = (T)(1.0 / gf.h2);
+  T acc[2] = {T(0), T(0)};
+  V2<T> prev = bwin(i0 - 1), cur = bwin(i0);
+  for (int i = i0; i < i1; ++i) {
+    V2<T> next = bwin(i + 1);
+    tile[(ty + 1) * W2 + 2 * tx + 1] = cur.x;
+    tile[(ty + 1) * W2 + 2 * tx + 2] = cur.y;
+    tile_halo(tile, gf, i, jbase, mbase, BX, BY, bval);
+    __syncthreads();
+    const long long r = row(i, j) + m0;
+    const V2<T> xr = ld2<T>(red + r);
+    const V2<T> br = ld2<T>(bf + r);
+    const int s = (i + j) & 1;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int i = 2 * p.i + ch[q][0], j = 2 * p.j + ch[q][1], k = 2 * p.k + ch[q][2];
-    int m = k >> 1;
-    long long e = ((long long)i * gf.n1 + j) * gf.hn2 + m;  // red plane
-    T s = nb_sum(gf, xf, i, j, k, 0, m);
-    int nn = cell_nnb(gf, i, j, k);
-    acc += (T)bf[e] - ((T)nn * xf[e] - s) * ih2;
+    for (int u = 0; u < 2; ++u) {
+      const int k = 2 * (m0 + u) + s, col = 2 * tx + 1 + u;
+      const T *trow = tile + (ty + 1) * W2;
+      const T sum = (u ? prev.y : prev.x) + (u ? next.y : next.x) + tile[ty * W2 + col] + tile[(ty + 2) * W2 + col] +
+                    trow[col - 1 + s] + trow[col + s];
+      const T xv = u ? xr.y : xr.x, bv = u ? br.y : br.x;
+      acc[u] += bv - ((T)cell_nnb(gf, i, j, k) * xv - sum) * ih2;
+    }
+    if (i & 1) {
+      // plane pair done: add the partner row and write the coarse values
+      pair[tid][0] = acc[0];
+      pair[tid][1] = acc[1];
+    }
+    __syncthreads();
+    if ((i & 1) && !(ty & 1)) {
+      const T v0 = (acc[0] + pair[tid + BX][0]) * (T)0.125;
+      const T v1 = (acc[1] + pair[tid + BX][1]) * (T)0.125;
+      const int I = i >> 1, J = j >> 1, K = m0;  // K even: colour of (I, J, K) is (I + J) & 1
+      const long long cr = ((long long)I * gc.n1 + J) * gc.hn2 + (K >> 1);
+      const int c0 = (I + J) & 1;
+      bc[(long long)c0 * gc.half + cr] = v0;
+      bc[(long long)(1 - c0) * gc.half + cr] = v1;
+    }
+    if (i & 1) {
+      acc[0] = T(0);
+      acc[1] = T(0);
+    }
+    prev = cur;
+    cur = next;
   }
-  bc[p.e] = acc * (T)0.125;
 }
 
 // x_f += P x_c on the red fine cells only (the following black half sweep
-// overwrites the black cells without reading them).
+// overwrites the black cells without reading them).  P is trilinear
+// cell-centred interpolation: per axis weight 3/4 on the parent and 1/4 on
+// the parent's neighbour on the child's side (past a wall the parent itself,
+// periodic axes wrap).
+//
+// Plane march over the fine grid: a thread owns the red cells at in-row
+// m0, m0+1 of fine row (i, j).  Along axis 0 the two coarse planes in use,
+// (i-1)>>1 and (i+1)>>1, are held in registers (each coarse plane is read
+// once per march); per plane the thread keeps its two coarse rows (parent and
+// neighbour along axis 1) at the four coarse K = m0-1 .. m0+2 that both
+// parities of the fine row need.
 template <typename T>
-__global__ void k_prolong(Geo gf, T *xf, Geo gc, const T *xc) {
-  RowPos p;
-  if (!row_pos1m(gf, 0, p)) return;
-  int I[3][2];
-  T w[3][2];
-  const int xs[3] = {p.i, p.j, p.k};
+__global__ void __launch_bounds__(256) k_prolong(Geo gf, T *xf, Geo gc, const T *xc) {
+  const int BX = blockDim.x, BY = blockDim.y;
+  const int m0 = 2 * (blockIdx.x * BX + threadIdx.x), j = blockIdx.y * BY + threadIdx.y;
+  const int len = march_chunk(gf);
+  const int i0 = blockIdx.z * len, i1 = min(i0 + len, gf.n0);
+  auto side = [](int C, int o, int n, int bc) { return (o < 0 || o >= n) ? (bc ? C : (o < 0 ? o + n : o - n)) : o; };
+  const int J = j >> 1, Jo = side(J, J + ((j & 1) ? 1 : -1), gc.n1, gc.bc1);
+  int Kq[4];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    int C = xs[a] >> 1;
-    int s = (xs[a] & 1) ? 1 : -1;
-    int nc = geo_n(gc, a), bc = geo_bc(gc, a);
-    int o = C + s;
-    if (o < 0 || o >= nc) o = bc ? C : (o < 0 ? o + nc : o - nc);
-    I[a][0] = C;
-    I[a][1] = o;
-    w[a][0] = (T)0.75;
-    w[a][1] = (T)0.25;
+  for (int q = 0; q < 4; ++q) {
+    const int K = m0 - 1 + q;
+    Kq[q] = (K < 0) ? (gc.bc2 ? 0 : gc.n2 - 1) : (K >= gc.n2 ? (gc.bc2 ? gc.n2 - 1 : 0) : K);
   }
-  T acc = T(0);
+  // coarse plane P: values at rows J, Jo and K = Kq[0..3]
+  auto load_plane = [&](int P, T v[2][4]) {
+    const int rows[2] = {J, Jo};
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+      for (int q = 0; q < 4; ++q) v[r][q] = xc[sidx(gc, P, rows[r], Kq[q])];
+  };
+  auto wrapP = [&](int P) { return side(P < 0 ? 0 : gc.n0 - 1, P, gc.n0, gc.bc0); };
+  int lo = (i0 - 1) >> 1;
+  T vlo[2][4], vhi[2][4];
+  load_plane(wrapP(lo), vlo);
+  load_plane(wrapP(lo + 1), vhi);
+  for (int i = i0; i < i1; ++i) {
+    if (((i - 1) >> 1) != lo) {
+      ++lo;
 #pragma unroll
-      for (int c = 0; c < 2; ++c)
-        acc += w[0][a] * w[1][b] * w[2][c] * xc[sidx(gc, I[0][a], I[1][b], I[2][c])];
-  xf[p.e] += acc;
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) vlo[r][q] = vhi[r][q];
+      load_plane(wrapP(lo + 1), vhi);
+    }
+    // parent plane i>>1 is lo for odd i, hi for even i
+    const T wlo = (i & 1) ? (T)0.75 : (T)0.25, whi = (T)1 - wlo;
+    const int s = (i + j) & 1;  // fine red cells k = 2 (m0 + u) + s
+    T out[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      // parent K = m0 + u (slot u + 1), neighbour K - 1 (slot u) or K + 1 (slot u + 2)
+      const int qc = u + 1, qo = s ? u + 2 : u;
+      T acc = T(0);
+#pragma unroll
+      for (int pl = 0; pl < 2; ++pl) {
+        const T(*v)[4] = pl ? vhi : vlo;
+        const T zJ = (T)0.75 * v[0][qc] + (T)0.25 * v[0][qo];
+        const T zO = (T)0.75 * v[1][qc] + (T)0.25 * v[1][qo];
+        acc += (pl ? whi : wlo) * ((T)0.75 * zJ + (T)0.25 * zO);
+      }
+      out[u] = acc;
+    }
+    T *p = xf + ((long long)i * gf.n1 + j) * gf.hn2 + m0;
+    const V2<T> x = ld2<T>(p);
+    st2(p, x.x + out[0], x.y + out[1]);
+  }
 }
 
 template <typename T, typename TB>
@@ -109,14 +207,18 @@ hipError_t mg_smooth(const Geo &g, T *x, const TB *b, int color, hipStream_t s) 
 }
 template <typename T, typename TB>
 hipError_t mg_restrict(const Geo &gf, const T *xf, const TB *bf, const Geo &gc, T *bc, hipStream_t s) {
-  RowLaunch L = row_launch(gc, 2 * gc.n0);
-  hipLaunchKernelGGL((k_restrict<T, TB>), L.grid, L.block, 0, s, gf, xf, bf, gc, bc);
+  MarchShape M = march_shape(gf, 1);
+  const int len = restrict_chunk(gf);
+  M.grid.z = (gf.n0 + len - 1) / len;
+  // pairs of planes and rows stay inside one workgroup
+  if (gf.n0 % 2 || M.block.y % 2 || len % 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_restrict<T, TB>), M.grid, M.block, 0, s, gf, xf, bf, gc, bc);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t mg_prolong(const Geo &gf, T *xf, const Geo &gc, const T *xc, hipStream_t s) {
-  RowLaunch L = row_launch(gf, gf.n0);
-  hipLaunchKernelGGL(k_prolong<T>, L.grid, L.block, 0, s, gf, xf, gc, xc);
+  MarchShape M = march_shape(gf, 1);
+  hipLaunchKernelGGL(k_prolong<T>, M.grid, M.block, 0, s, gf, xf, gc, xc);
   return hipGetLastError();
 }
 
