@@ -75,6 +75,14 @@ enum { SIM_MOTION_PRESCRIBED = 0, SIM_MOTION_FREE = 1 };
  * with bfloat16 operands and float32 accumulation; every n[d] a multiple of
  * 8, at most 512 (else sim_create returns SIM_EINVAL). */
 enum { SIM_PRECOND_VCYCLE = 0, SIM_PRECOND_FASTDIAG = 1 };
+/* FGMRES: flexible GMRES(krylov_restart) with classical Gram-Schmidt.
+ * BICGSTAB: right-preconditioned BiCGStab (the Krylov method the paper pairs
+ * with the Laplacian preconditioner, Sec. 4.2): two preconditioner and two
+ * operator applications per iteration, vectors in float64 in both
+ * precisions, the preconditioner in the precision of `precision`;
+ * krylov_maxit counts iterations.  The reported rel_res is the true residual
+ * ||b - S~ p|| / ||b|| at exit. */
+enum { SIM_KRYLOV_FGMRES = 0, SIM_KRYLOV_BICGSTAB = 1 };
 
 typedef struct {
   int32_t n[3];          /* cells per axis; multiples of 4, >= 16 */
@@ -99,6 +107,7 @@ typedef struct {
                                   sizes multiples of 8, <= 512), k >= 1 = k V-cycles
                                   of the LDS-resident coarse kernel */
   int32_t precond;       /* SIM_PRECOND_*: preconditioner of the Schur Krylov solve */
+  int32_t krylov;        /* SIM_KRYLOV_*: Krylov method of the Schur solve */
   int32_t outer_iters;   /* pressure-force corrections per step (>= 1) */
   double outer_tol;      /* stop on ||Phi'||_1 / ||Phi||_1 < tol (0: fixed) */
   double xi;             /* relaxation of the correction (1 for one-way) */

@@ -66,3 +66,45 @@ def gmres(matvec, b, precond=None, rtol=1e-13, restart=30, maxit=500, x0=None):
     r = b - matvec(x)
     hist.append(np.linalg.norm(r) / bnorm)
     return x, it, hist
+
+
+def bicgstab(matvec, b, precond=None, rtol=1e-13, maxit=500, x0=None):
+    """Right-preconditioned BiCGStab (van der Vorst, 1992), the Krylov method
+    the paper pairs with the Laplacian preconditioner (Sec. 4.2, Sec. 6.2).
+    One iteration applies the preconditioner and the operator twice.  The
+    recursive residual is used for the stopping test; the returned history
+    ends with the true residual.  Returns (x, iterations, history)."""
+    M = precond if precond is not None else (lambda v: v)
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        return x, 0, [0.0]
+    r = b - matvec(x)
+    rhat = r.copy()
+    p = np.zeros_like(b)
+    v = np.zeros_like(b)
+    rho_old = alpha = omega = 1.0
+    hist = [np.linalg.norm(r) / bnorm]
+    it = 0
+    while hist[-1] > rtol and it < maxit:
+        rho = np.vdot(rhat, r)
+        beta = (rho / rho_old) * (alpha / omega) if it > 0 else 0.0
+        p = r + beta * (p - omega * v)
+        phat = M(p)
+        v = matvec(phat)
+        alpha = rho / np.vdot(rhat, v)
+        s = r - alpha * v
+        it += 1
+        if np.linalg.norm(s) / bnorm <= rtol:
+            x = x + alpha * phat
+            hist.append(np.linalg.norm(s) / bnorm)
+            break
+        shat = M(s)
+        t = matvec(shat)
+        omega = np.vdot(t, s) / np.vdot(t, t)
+        x = x + alpha * phat + omega * shat
+        r = s - omega * t
+        rho_old = rho
+        hist.append(np.linalg.norm(r) / bnorm)
+    hist.append(np.linalg.norm(b - matvec(x)) / bnorm)
+    return x, it, hist

@@ -62,14 +62,18 @@ class SchurSystem:
         return (self.B(p) - rhs_f) / self.c
 
     # solves ------------------------------------------------------------------
-    def solve(self, rhs_p, rhs_f, rtol=1e-13, restart=30, maxit=400, workers=None):
-        """Krylov solve of S~ p' = b preconditioned by the exact L^+ (Sec. 4.1-4.2).
+    def solve(self, rhs_p, rhs_f, rtol=1e-13, restart=30, maxit=400, workers=None, method="gmres"):
+        """Krylov solve of S~ p' = b preconditioned by the exact L^+ (Sec. 4.1-4.2),
+        by restarted GMRES or by BiCGStab (method="bicgstab").
 
         Returns (p', Phi', iterations, residual history)."""
         b = self.rhs(rhs_p, rhs_f)
         pre = lambda v: poisson.solve_laplacian(self.g, v, workers)
-        p, its, hist = krylov.gmres(self.matvec, b, precond=pre, rtol=rtol,
-                                    restart=restart, maxit=maxit)
+        if method == "bicgstab":
+            p, its, hist = krylov.bicgstab(self.matvec, b, precond=pre, rtol=rtol, maxit=maxit)
+        else:
+            p, its, hist = krylov.gmres(self.matvec, b, precond=pre, rtol=rtol,
+                                        restart=restart, maxit=maxit)
         p = p - p.mean()
         return p, self.force(p, rhs_f), its, hist
 

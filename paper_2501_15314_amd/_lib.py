@@ -37,7 +37,7 @@ class SimConfig(C.Structure):
                 ("precision", C.c_int32), ("krylov_restart", C.c_int32), ("krylov_maxit", C.c_int32),
                 ("krylov_rtol", C.c_double), ("helm_maxit", C.c_int32), ("helm_rtol", C.c_double),
                 ("mg_coarsest", C.c_int32), ("mg_pre", C.c_int32), ("mg_post", C.c_int32),
-                ("mg_coarse_sweeps", C.c_int32), ("precond", C.c_int32),
+                ("mg_coarse_sweeps", C.c_int32), ("precond", C.c_int32), ("krylov", C.c_int32),
                 ("outer_iters", C.c_int32), ("outer_tol", C.c_double),
                 ("xi", C.c_double), ("device", C.c_int32), ("stream", C.c_void_p)]
 

@@ -107,6 +107,7 @@ struct sim_s {
   bool fastdiag = false;
   bool coarse_mfma = false;  // exact coarse solve on the matrix cores
   unsigned char *FDQ = nullptr;  // packed eigenbases (fd_blob_pack)
+  double *BCG = nullptr;  // BiCGStab vectors r, r^, p, v, s, t (float64)
   unsigned short *FDW1 = nullptr, *FDW2 = nullptr;
   double *hpin = nullptr;
   double *hpin_dev = nullptr;  // device address of hpin
@@ -168,6 +169,7 @@ std::string validate(const sim_config *c, std::vector<int> *dims) {
   if (!(c->krylov_rtol > 0)) return "krylov_rtol must be > 0";
   if (c->mg_pre < 1 || c->mg_post < 0 || c->mg_coarse_sweeps < 0) return "mg_pre >= 1, mg_coarse_sweeps >= 0";
   if (c->precond != SIM_PRECOND_VCYCLE && c->precond != SIM_PRECOND_FASTDIAG) return "bad precond";
+  if (c->krylov != SIM_KRYLOV_FGMRES && c->krylov != SIM_KRYLOV_BICGSTAB) return "bad krylov method";
   if (c->outer_iters < 1) return "outer_iters must be >= 1";
   if (c->helm_maxit < 1 || !(c->helm_rtol > 0)) return "helm_maxit >= 1 and helm_rtol > 0";
   // multigrid hierarchy: halve while above mg_coarsest or too big for the coarse kernel
@@ -212,7 +214,8 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
   double *P = cv.arr<double>(N), *RHSP = cv.arr<double>(N), *BVEC = cv.arr<double>(N);
   double *PP = cv.arr<double>(N), *TMPC = cv.arr<double>(N);
   void *V = cv.take(ts * (size_t)(m + 1) * N);
-  void *Z = cv.take(ts * (size_t)m * N);
+  void *Z = cv.take(ts * (size_t)std::max(m, 2) * N);  // BiCGStab keeps p^, s^ in Z[0], Z[1]
+  double *BCG = c->krylov == SIM_KRYLOV_BICGSTAB ? cv.arr<double>(6 * N) : nullptr;
   void *HR = cv.take(ts * 3 * N), *HE0 = cv.take(ts * 3 * N);
   std::vector<Level> lv;
   int nlev = (int)dims.size() / 3;
@@ -267,7 +270,7 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
   if (s) {
     s->U = U; s->UM = UM; s->USTAR = USTAR; s->RHSU = RHSU; s->TMP3 = TMP3;
     s->P = P; s->RHSP = RHSP; s->BVEC = BVEC; s->PP = PP; s->TMPC = TMPC;
-    s->V = V; s->Z = Z; s->HR = HR; s->HE0 = HE0;
+    s->V = V; s->Z = Z; s->HR = HR; s->HE0 = HE0; s->BCG = BCG;
     s->lv = lv;
     s->OFF = OFF; s->XN = XN; s->UN = UN; s->PHIN = PHIN;
     s->BODYOF = BODYOF; s->TILE = TILE; s->PERM = PERM; s->PERMTMP = PERMTMP;
@@ -666,7 +669,136 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
   return SIM_OK;
 }
 
+// Right-preconditioned BiCGStab (van der Vorst) on S~ x = b: vectors and
+// recurrences in float64, the preconditioner (V-cycle or fast
+// diagonalisation) in precision T.  Three host synchronisations per
+// iteration: (r^, v); |s|, (t, s), (t, t); |r|, (r, r^).  The loop restarts
+// from the float64 true residual when the recursive one meets the tolerance
+// (or on a breakdown), so the reported residual is the true one.
+template <typename T>
+sim_status bicgstab(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
+  hipStream_t st = s->st;
+  const sim_config &c = s->cfg;
+  const long long N = s->N;
+  double *R = s->BCG, *RH = R + N, *P = RH + N, *Vv = P + N, *Sv = Vv + N, *Tv = Sv + N;
+  T *PH = (T *)s->Z, *SH = PH + N;
+  sim_solve_stats loc{};
+  sim_solve_stats &S = stt ? *stt : loc;
+  S.iters = 0;
+  S.nhist = 0;
+  sim_status rc;
+  auto precond = [&](const double *in, T *out) -> sim_status {
+    if (s->fastdiag) {
+      ProbeScope pr(PR_VCYCLE, st);
+      CKH((fd_precond<double, T>(s->g, in, out, s->FDW1, s->FDW2, s->FDQ, 1.0f, st)));
+      return SIM_OK;
+    }
+    return vcycle<T, double>(s, in, out);
+  };
+  auto reduce = [&](int nv, double *out) -> sim_status {
+    CKH(finalize(s->PART, red_blocks(), nv, s->RED, st, s->hpin_dev));
+    return read_mirror(s, nv, out);
+  };
+  double bn2;
+  if ((rc = dev_norm2(s, b, N, &bn2))) return rc;
+  const double bnorm = sqrt(bn2);
+  CKH(fill(x, N, 0.0, st));
+  if (!(bnorm > 0)) {
+    S.rel_res = 0;
+    return isfinite(bn2) ? SIM_OK : fail(s, SIM_ENONFINITE, "non-finite right-hand side");
+  }
+  const int rb = red_blocks();
+  int total = 0;
+  double rel = 1.0;
+  double r2 = bn2;
+  CKH(scale_copy(R, b, N, 1.0, st));  // x = 0: r = b
+  while (true) {
+    // (re)start: r^ = r
+    CKH(scale_copy(RH, R, N, 1.0, st));
+    double rho = r2, rho_old = 1.0, alpha = 1.0, omega = 1.0;
+    int since = 0;
+    bool breakdown = false;
+    while (sqrt(r2) / bnorm > c.krylov_rtol && total < c.krylov_maxit) {
+      // p = r + beta (p - omega v); p = r on the first iteration
+      if (since == 0) {
+        CKH(scale_copy(P, R, N, 1.0, st));
+      } else {
+        const double beta = (rho / rho_old) * (alpha / omega);
+        CKH(lincomb(P, R, 1.0, P, beta, Vv, -beta * omega, nullptr, 0, N, nullptr, st));
+      }
+      if ((rc = precond(P, PH))) return rc;
+      if ((rc = schur_matvec<T>(s, PH, Vv))) return rc;
+      CKH(dot2(RH, Vv, N, s->PART, st));
+      double rv;
+      if ((rc = reduce(1, &rv))) return rc;
+      if (!isfinite(rv)) return fail(s, SIM_ENONFINITE, "non-finite Krylov product");
+      if (rv == 0.0) {
+        breakdown = true;
+        break;
+      }
+      alpha = rho / rv;
+      // s = r - alpha v with |s|^2; then (t, s), (t, t) for t = S~ M^-1 s
+      CKH(lincomb(Sv, R, 1.0, Vv, -alpha, nullptr, 0.0, nullptr, 1, N, s->PART, st));
+      if ((rc = precond(Sv, SH))) return rc;
+      if ((rc = schur_matvec<T>(s, SH, Tv))) return rc;
+      CKH(dots2(Tv, Sv, Tv, N, s->PART + 2LL * rb, st));
+      CKH(finalize(s->PART, rb, 2, s->RED, st, s->hpin_dev));
+      CKH(finalize(s->PART + 2LL * rb, rb, 2, s->RED + 2, st, s->hpin_dev + 2));
+      double q[4];
+      if ((rc = read_mirror(s, 4, q))) return rc;
+      const double ss = q[0], ts = q[2], tt = q[3];
+      if (!isfinite(ss) || !isfinite(ts) || !isfinite(tt)) return fail(s, SIM_ENONFINITE, "non-finite Krylov norm");
+      ++total;
+      ++since;
+      if (sqrt(ss) / bnorm <= c.krylov_rtol || !(tt > 0.0)) {
+        // converged (or t = 0) at the half step: x += alpha p^, r = s
+        Coef64 y1{};
+        y1.v[0] = alpha;
+        CKH(sol_update<T>(x, PH, N, 1, y1, N, st));
+        CKH(scale_copy(R, Sv, N, 1.0, st));
+        r2 = ss;
+        if (S.nhist < 64) S.hist[S.nhist++] = sqrt(r2) / bnorm;
+        breakdown = !(tt > 0.0) && sqrt(ss) / bnorm > c.krylov_rtol;
+        break;
+      }
+      omega = ts / tt;
+      // x += alpha p^ + omega s^ (p^, s^ adjacent in Z); r = s - omega t with |r|^2, (r, r^)
+      Coef64 y2{};
+      y2.v[0] = alpha;
+      y2.v[1] = omega;
+      CKH(sol_update<T>(x, PH, N, 2, y2, N, st));
+      CKH(lincomb(R, Sv, 1.0, Tv, -omega, nullptr, 0.0, RH, 2, N, s->PART, st));
+      double rr[2];
+      if ((rc = reduce(2, rr))) return rc;
+      if (!isfinite(rr[0]) || !isfinite(rr[1])) return fail(s, SIM_ENONFINITE, "non-finite Krylov norm");
+      r2 = rr[0];
+      rho_old = rho;
+      rho = rr[1];
+      if (S.nhist < 64) S.hist[S.nhist++] = sqrt(r2) / bnorm;
+      if (omega == 0.0 || rho == 0.0) {
+        breakdown = true;
+        break;
+      }
+    }
+    // the true residual decides; a drifted recursion or a breakdown restarts
+    if ((rc = schur_matvec<double>(s, x, s->TMPC))) return rc;
+    CKH(sub_mul(R, b, s->TMPC, N, s->PART, st));
+    if ((rc = reduce(1, &r2))) return rc;
+    if (!isfinite(r2)) return fail(s, SIM_ENONFINITE, "non-finite residual");
+    rel = sqrt(r2) / bnorm;
+    if (rel <= c.krylov_rtol || total >= c.krylov_maxit) break;
+    if (breakdown && since == 0) break;  // no progress since the last restart
+  }
+  S.iters = total;
+  S.rel_res = rel;
+  if ((rc = project_mean(s, x))) return rc;
+  if (rel > c.krylov_rtol) return fail(s, SIM_ENOTCONV, "Krylov iteration limit reached or breakdown");
+  return SIM_OK;
+}
+
 sim_status fgmres_any(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
+  if (s->cfg.krylov == SIM_KRYLOV_BICGSTAB)
+    return s->fp32 ? bicgstab<float>(s, b, x, stt) : bicgstab<double>(s, b, x, stt);
   return s->fp32 ? fgmres<float>(s, b, x, stt) : fgmres<double>(s, b, x, stt);
 }
 

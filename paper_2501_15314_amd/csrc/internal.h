@@ -205,6 +205,9 @@ hipError_t add_scalar_dev(double *x, long long n, const double *dscalar, double 
 hipError_t sub_mul(double *r, const double *b, const double *ax, long long n, double *part,
                    hipStream_t s);  // r = b - ax, partial |r|^2
 hipError_t dot2(const double *a, const double *b, long long n, double *part,
-                hipStream_t s);  // partial a.b (sum of a when b is null)
+                hipStream_t s);
+hipError_t lincomb(double *y, const double *a, double ca, const double *b, double cb, const double *c, double cc,
+                   const double *d, int nd, long long n, double *part, hipStream_t s);
+hipError_t dots2(const double *a, const double *b0, const double *b1, long long n, double *part, hipStream_t s);  // partial a.b (sum of a when b is null)
 
 }  // namespace ibs

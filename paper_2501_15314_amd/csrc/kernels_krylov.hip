@@ -297,4 +297,55 @@ hipError_t dot2(const double *a, const double *b, long long n, double *part, hip
   return hipGetLastError();
 }
 
+// BiCGStab vector updates: y = ca a + cb b (+ cc c), with per-block partial
+// sums of y.y (nd >= 1) and y.d (nd = 2), two per block in part.  y may
+// alias a, b or c (elementwise).
+__global__ void __launch_bounds__(RED_T) k_lincomb(double *y, const double *a, double ca, const double *b, double cb,
+                                                   const double *c, double cc, const double *d, int nd, long long n,
+                                                   double *part) {
+  __shared__ double sh[4];
+  double s0 = 0.0, s1 = 0.0;
+  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T) {
+    double v = ca * a[t] + cb * b[t];
+    if (c) v += cc * c[t];
+    y[t] = v;
+    s0 += v * v;
+    if (nd == 2) s1 += v * d[t];
+  }
+  if (nd == 0) return;
+  s0 = block_reduce(s0, sh);
+  s1 = block_reduce(s1, sh);
+  if (threadIdx.x == 0) {
+    part[2LL * blockIdx.x] = s0;
+    part[2LL * blockIdx.x + 1] = s1;
+  }
+}
+hipError_t lincomb(double *y, const double *a, double ca, const double *b, double cb, const double *c, double cc,
+                   const double *d, int nd, long long n, double *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_lincomb, dim3(RED_BLOCKS), dim3(RED_T), 0, s, y, a, ca, b, cb, c, cc, d, nd, n, part);
+  return hipGetLastError();
+}
+
+// a.b0 and a.b1, two partial sums per block in part
+__global__ void __launch_bounds__(RED_T) k_dots2(const double *a, const double *b0, const double *b1, long long n,
+                                                 double *part) {
+  __shared__ double sh[4];
+  double s0 = 0.0, s1 = 0.0;
+  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T) {
+    const double av = a[t];
+    s0 += av * b0[t];
+    s1 += av * b1[t];
+  }
+  s0 = block_reduce(s0, sh);
+  s1 = block_reduce(s1, sh);
+  if (threadIdx.x == 0) {
+    part[2LL * blockIdx.x] = s0;
+    part[2LL * blockIdx.x + 1] = s1;
+  }
+}
+hipError_t dots2(const double *a, const double *b0, const double *b1, long long n, double *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_dots2, dim3(RED_BLOCKS), dim3(RED_T), 0, s, a, b0, b1, n, part);
+  return hipGetLastError();
+}
+
 }  // namespace ibs

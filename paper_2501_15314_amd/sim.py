@@ -40,6 +40,7 @@ def make_config(cfg: Config, stream=None) -> _lib.SimConfig:
     c.mg_coarsest, c.mg_pre, c.mg_post = cfg.mg_coarsest, cfg.mg_pre, cfg.mg_post
     c.mg_coarse_sweeps = cfg.mg_coarse_sweeps
     c.precond = cfg.precond
+    c.krylov = cfg.krylov
     c.outer_iters, c.outer_tol, c.xi = cfg.outer_iters, cfg.outer_tol, cfg.xi
     c.device = cfg.device
     c.stream = stream if stream is not None else torch.cuda.current_stream(cfg.device).cuda_stream

@@ -37,6 +37,8 @@ MOTION_PRESCRIBED = 0
 MOTION_FREE = 1
 PRECOND_VCYCLE = 0
 PRECOND_FASTDIAG = 1
+KRYLOV_FGMRES = 0
+KRYLOV_BICGSTAB = 1
 
 # Sum over integer shifts j of phi(r - j)^2 for the two kernels (independent of
 # r for both).  Used only to size the scalar lumping constant of C = W^T W.
@@ -67,6 +69,7 @@ class Config:
     mg_post: int = 1
     mg_coarse_sweeps: int = 0
     precond: int = 0            # PRECOND_VCYCLE or PRECOND_FASTDIAG
+    krylov: int = 0             # KRYLOV_FGMRES or KRYLOV_BICGSTAB
     outer_iters: int = 1
     outer_tol: float = 0.0
     xi: float = 1.0

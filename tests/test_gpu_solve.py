@@ -56,6 +56,33 @@ def test_schur_solve_matches_oracle(case, prec, precond):
     sim.close()
 
 
+@pytest.mark.parametrize("case", ["c1_periodic", "walls", "mixed"])
+@pytest.mark.parametrize("prec", [wl.PREC_FP64, wl.PREC_FP32MG])
+@pytest.mark.parametrize("precond", [wl.PRECOND_VCYCLE, wl.PRECOND_FASTDIAG])
+def test_schur_bicgstab_matches_oracle(case, prec, precond):
+    """BiCGStab (the paper's Krylov method) reaches the same unique mean-zero
+    solution as the oracle's BiCGStab with the exact L^+."""
+    w = CASES[case]()
+    w.cfg.precision = prec
+    w.cfg.precond = precond
+    w.cfg.krylov = wl.KRYLOV_BICGSTAB
+    w.cfg.krylov_rtol = 1e-12 if prec == wl.PREC_FP64 else 1e-11
+    print(f"case {case} prec {prec} precond {precond} bicgstab n={w.cfg.n} K={w.n_points}", flush=True)
+    sim = Sim(w.cfg, w.n_points)
+    sim.set_bodies(w.bodies, w.offsets)
+    g, X, W, S = oracle_for(w)
+    rp, rf = wl.random_schur_rhs(24, g.n, w.n_points)
+    p, phi, st = sim.solve_schur(rp, rf)
+    p_ref, phi_ref, its, _ = S.solve(rp, rf, rtol=1e-13, method="bicgstab")
+    ep = rel(p.cpu().numpy(), p_ref)
+    ef = rel(phi.cpu().numpy(), phi_ref)
+    print(f"  iters gpu={st.iters} oracle={its} rel_res={st.rel_res:.2e} err p={ep:.2e} phi={ef:.2e}")
+    tol = 1e-10 if prec == wl.PREC_FP64 else 1e-8
+    assert ep < tol and ef < tol
+    assert st.rel_res <= w.cfg.krylov_rtol
+    sim.close()
+
+
 def test_schur_solve_bitwise_repeatable():
     w = walls_workload(32, 260)
     w.cfg.precision = wl.PREC_FP32MG

@@ -327,6 +327,43 @@ def test_schur_krylov_vs_direct(bc):
     assert np.abs(r1).max() < 1e-9 * np.abs(rp).max()
 
 
+@pytest.mark.parametrize("bc", [(P, P, P), (W_, P, W_)])
+def test_schur_bicgstab_vs_direct(bc):
+    """BiCGStab with the exact L^+ (the paper's pairing, Sec. 4.2) reaches the
+    LU solution; with a spectrum of L^+ S~ inside [1, 2] it needs only a few
+    iterations (two operator applications each)."""
+    g, X, Wm, c = _small_system(16, bc, 200)
+    S = schur.SchurSystem(g, Wm, c)
+    rp, rf = wl.random_schur_rhs(11, g.n, X.shape[0])
+    p1, f1, its, hist = S.solve(rp, rf, rtol=1e-12, method="bicgstab")
+    p2, f2 = S.solve_direct(rp, rf)
+    assert np.linalg.norm(p1 - p2) / np.linalg.norm(p2) < 1e-10
+    assert np.linalg.norm(f1 - f2) / np.linalg.norm(f2) < 1e-10
+    assert hist[-1] < 1e-11
+    assert its <= 12
+
+
+def test_bicgstab_closed_forms():
+    """A = a I converges in one iteration to b / a; on a diagonal SPD matrix
+    with k distinct eigenvalues the iterates reach the solution, and the result
+    matches scipy's BiCGStab."""
+    from oracle import krylov
+    import scipy.sparse.linalg as spla
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(50)
+    x, its, _ = krylov.bicgstab(lambda v: 2.5 * v, b, rtol=1e-14)
+    assert its == 1 and np.abs(x - b / 2.5).max() < 1e-15
+    d = np.repeat([1.0, 3.0, 7.0], [20, 20, 10])
+    x, its, hist = krylov.bicgstab(lambda v: d * v, b, rtol=1e-13)
+    assert np.abs(x - b / d).max() < 1e-11 and its <= 4
+    A = np.diag(d) + 0.1 * np.diag(np.ones(49), 1)
+    x, its, hist = krylov.bicgstab(lambda v: A @ v, b, rtol=1e-13, maxit=200)
+    xs, info = spla.bicgstab(A, b, rtol=1e-13, maxiter=200)
+    assert info == 0
+    assert np.abs(x - np.linalg.solve(A, b)).max() < 1e-10
+    assert np.abs(xs - np.linalg.solve(A, b)).max() < 1e-9
+
+
 def test_spectral_theorem_bounds():
     """spec(L^-1 (L + B^T C^-1 B)) in [1, 2] on the mean-zero subspace
     (theorem of Sec. 5), and the lumped operator is bounded by
