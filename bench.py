@@ -145,6 +145,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form solve rate")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the solver variants (fast-diagonalisation preconditioner, BiCGStab)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the reference "
                          "kernel for scaling HBM byte counters) and exit")
@@ -225,11 +227,25 @@ def main():
     torch.cuda.empty_cache()
     N = int(np.prod(cfg.n))
     T = 4
-    forms = [("fp32mg", wl.PREC_FP32MG)] + ([] if args.no_fp64 else [("fp64", wl.PREC_FP64)])
-    for form, prec in forms:
+    # the two forms of the metric (FGMRES + V-cycle), then the solver variants:
+    # the paper's own preconditioner (fast diagonalisation of L) and Krylov
+    # method (BiCGStab)
+    forms = [("fp32mg", wl.PREC_FP32MG, wl.PRECOND_VCYCLE, wl.KRYLOV_FGMRES)]
+    if not args.no_fp64:
+        forms.append(("fp64", wl.PREC_FP64, wl.PRECOND_VCYCLE, wl.KRYLOV_FGMRES))
+    if not args.no_variants:
+        for tag, prec in [("fp32mg", wl.PREC_FP32MG), ("fp64", wl.PREC_FP64)]:
+            if prec == wl.PREC_FP64 and args.no_fp64:
+                continue
+            forms += [(f"{tag}_fgmres_fastdiag", prec, wl.PRECOND_FASTDIAG, wl.KRYLOV_FGMRES),
+                      (f"{tag}_bicgstab_vcycle", prec, wl.PRECOND_VCYCLE, wl.KRYLOV_BICGSTAB),
+                      (f"{tag}_bicgstab_fastdiag", prec, wl.PRECOND_FASTDIAG, wl.KRYLOV_BICGSTAB)]
+    for form, prec, precond, krylov in forms:
         # a fresh solver with the bodies at t = 0, the geometry the oracle check uses
         cf = wl.make_c3(n=n, points_per_sphere=int(round(18000 * (n / 256) ** 2))).cfg
         cf.precision = prec
+        cf.precond = precond
+        cf.krylov = krylov
         cf.krylov_rtol = 1e-8
         s2 = Sim(cf, w.n_points)
         s2.set_bodies(w.bodies, w.offsets)
@@ -297,7 +313,12 @@ def main():
                               "cell_updates_per_s": round(N * solve_its[form] / solve_s[form], 1),
                               "oracle_rel_residual": (resid or {}).get(form),
                               "oracle_force_rel_err": (fres or {}).get(form)}
-                       for form in solve_s},
+                       for form in solve_s if form in ("fp32mg", "fp64")},
+        "schur_variants": {form: {"solves_per_s": round(1.0 / solve_s[form], 2), "ms": round(1e3 * solve_s[form], 3),
+                                  "iters": solve_its[form],
+                                  "oracle_rel_residual": (resid or {}).get(form),
+                                  "oracle_force_rel_err": (fres or {}).get(form)}
+                           for form in solve_s if form not in ("fp32mg", "fp64")},
         "roofline": roof,
         "kernels": kinfo,
         "cpu_baseline": cpu,
