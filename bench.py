@@ -32,12 +32,14 @@ def kernel_bytes(name, N, T, K, nactive, nnz):
     """Algorithmic (compulsory) bytes of one launch: every operand read once,
     every result written once.  N cells, T bytes per V-cycle value, K points."""
     return {
-        # RB-GS half sweep on the finest grid: other colour x, own colour rhs (f64), own colour x
-        "smooth_fine": N * (T / 2 + 8 / 2 + T / 2),
-        # first sweep from zero: rhs (f64) read, both colours of x written
-        "smooth_first_fine": N * (8 + T),
-        # red residual + 8-child restriction: x, red rhs (f64), coarse rhs
-        "restrict_fine": N * (T + 4 + T / 8),
+        # The finest-level right-hand side is the Krylov basis vector, stored
+        # in the V-cycle precision T in both forms.
+        # RB-GS half sweep on the finest grid: other colour x, own colour rhs, own colour x
+        "smooth_fine": N * (T / 2 + T / 2 + T / 2),
+        # first sweep from zero: rhs read, both colours of x written
+        "smooth_first_fine": N * (T + T),
+        # red residual + 8-child restriction: black x, red x, red rhs, coarse rhs
+        "restrict_fine": N * (T / 2 + T / 2 + T / 2 + T / 8),
         # trilinear correction of the red cells: red x read/written, coarse x
         "prolong_fine": N * (T + T / 8),
         # L z inside S~ z: z read, w (f64) written

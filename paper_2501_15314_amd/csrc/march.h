@@ -132,6 +132,70 @@ __device__ __forceinline__ void tile_halo(T *tile, const Geo &g, int i, int jbas
   }
 }
 
+// The same halo in two halves, so that the loads of the next plane can be
+// issued before the current plane is computed: halo_fetch reads up to
+// HALO_REG values per thread into registers, halo_put stores them (and loads
+// any remainder of very thin tiles directly).
+constexpr int HALO_REG = 2;
+template <typename T>
+struct Halo {
+  T v[HALO_REG];
+};
+__device__ __forceinline__ void halo_slot(int h, int BX, int BY, int &r, int &cidx) {
+  const int nrow = 2 * (2 * BX);
+  if (h < nrow) {
+    r = h < 2 * BX ? 0 : BY + 1;
+    cidx = 1 + (h % (2 * BX));
+  } else {
+    const int q = h - nrow;
+    r = 1 + (q >> 1);
+    cidx = (q & 1) ? 2 * BX + 1 : 0;
+  }
+}
+template <typename T, class F>
+__device__ __forceinline__ Halo<T> halo_fetch(const Geo &g, int i, int jbase, int mbase, int BX, int BY, F val) {
+  Halo<T> hv;
+  const int total = 2 * (2 * BX) + 2 * BY, nthr = BX * BY;
+  const int tid = threadIdx.x + BX * threadIdx.y;
+#pragma unroll
+  for (int q = 0; q < HALO_REG; ++q) {
+    hv.v[q] = T(0);
+    const int h = tid + q * nthr;
+    if (h < total) {
+      int r, cidx;
+      halo_slot(h, BX, BY, r, cidx);
+      const int jj = mwrap(jbase + r - 1, g.n1, g.bc1);
+      const int mm = mwrap(mbase + cidx - 1, g.hn2, g.bc2);
+      if (jj >= 0 && mm >= 0 && (unsigned)i < (unsigned)g.n0) hv.v[q] = val(i, jj, mm);
+    }
+  }
+  return hv;
+}
+template <typename T, class F>
+__device__ __forceinline__ void halo_put(T *tile, const Halo<T> &hv, const Geo &g, int i, int jbase, int mbase,
+                                         int BX, int BY, F val) {
+  const int total = 2 * (2 * BX) + 2 * BY, nthr = BX * BY, W2 = 2 * BX + 2;
+  const int tid = threadIdx.x + BX * threadIdx.y;
+#pragma unroll
+  for (int q = 0; q < HALO_REG; ++q) {
+    const int h = tid + q * nthr;
+    if (h < total) {
+      int r, cidx;
+      halo_slot(h, BX, BY, r, cidx);
+      tile[r * W2 + cidx] = hv.v[q];
+    }
+  }
+  for (int h = tid + HALO_REG * nthr; h < total; h += nthr) {
+    int r, cidx;
+    halo_slot(h, BX, BY, r, cidx);
+    const int jj = mwrap(jbase + r - 1, g.n1, g.bc1);
+    const int mm = mwrap(mbase + cidx - 1, g.hn2, g.bc2);
+    T v = T(0);
+    if (jj >= 0 && mm >= 0 && (unsigned)i < (unsigned)g.n0) v = val(i, jj, mm);
+    tile[r * W2 + cidx] = v;
+  }
+}
+
 }  // namespace ibs
 
 namespace ibs {
@@ -186,19 +250,33 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, T *x, const TB *b, int col
     return ld2<T>(oth + row(ii, p.j) + p.m0);
   };
   const T th2 = (T)h2, ta0 = (T)a0, tnu = (T)nuh2, tom = (T)omega;
-  V2<T> prev = owin(p.i0 - 1), cur = owin(p.i0);
-  for (int i = p.i0; i < p.i1; ++i) {
-    V2<T> next = owin(i + 1);
-    tile[(p.ty + 1) * W2 + 2 * p.tx + 1] = cur.x;
-    tile[(p.ty + 1) * W2 + 2 * p.tx + 2] = cur.y;
-    tile_halo(tile, g, i, jbase, mbase, BX, BY, oval);
-    __syncthreads();
+  // software pipeline: the window plane i+2, the halo and the own-colour
+  // operands of plane i+1 are loaded while plane i is computed
+  auto own_ops = [&](int i, V2<T> &bb, V2<T> &xo) {
     const long long r = row(i, p.j) + p.m0;
-    V2<T> bb = ld2<T>(bown + r);
-    V2<T> xo;
+    bb = ld2<T>(bown + r);
     xo.x = T(0);
     xo.y = T(0);
     if (MODE == SW_HELM) xo = ld2<T>((const T *)own + r);
+  };
+  V2<T> prev = owin(p.i0 - 1), cur = owin(p.i0), next = owin(p.i0 + 1);
+  Halo<T> hcur = halo_fetch<T>(g, p.i0, jbase, mbase, BX, BY, oval);
+  V2<T> bb, xo;
+  own_ops(p.i0, bb, xo);
+  for (int i = p.i0; i < p.i1; ++i) {
+    const bool more = i + 1 < p.i1;
+    V2<T> nn = more ? owin(i + 2) : next;
+    Halo<T> hnext = hcur;
+    V2<T> bbn = bb, xon = xo;
+    if (more) {
+      hnext = halo_fetch<T>(g, i + 1, jbase, mbase, BX, BY, oval);
+      own_ops(i + 1, bbn, xon);
+    }
+    tile[(p.ty + 1) * W2 + 2 * p.tx + 1] = cur.x;
+    tile[(p.ty + 1) * W2 + 2 * p.tx + 2] = cur.y;
+    halo_put(tile, hcur, g, i, jbase, mbase, BX, BY, oval);
+    __syncthreads();
+    const long long r = row(i, p.j) + p.m0;
     T out[2];
     const int s = (c + i + p.j) & 1;
 #pragma unroll
@@ -231,6 +309,10 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, T *x, const TB *b, int col
     __syncthreads();
     prev = cur;
     cur = next;
+    next = nn;
+    hcur = hnext;
+    bb = bbn;
+    xo = xon;
   }
 }
 
