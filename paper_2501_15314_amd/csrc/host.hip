@@ -413,6 +413,9 @@ sim_status place_and_bin(sim_t s, const std::vector<BodyDev> &bd) {
   memcpy(&M, (int *)s->hpin + 1, sizeof(int));
   if (M > s->tl_cap) return fail(s, SIM_EDEVICE, "touch list overflow");
   CKH(seg_sort(M, na, s->ACTIVE, s->TLSTART, s->TLTMP, s->SEGOF, s->TLIST, st));
+  // longest touch lists first (FLAGS, no longer needed, takes the old order)
+  CKH(order_active(na, s->ACTIVE, s->TLSTART, s->FLAGS, st));
+  std::swap(s->ACTIVE, s->FLAGS);
   s->ntouch = M;
   s->nactive = na;
   return SIM_OK;

@@ -158,6 +158,7 @@ hipError_t touch_scatter(int ker, const Geo &g, int K, const double *X, int nt0,
                          const int *start, int *fillc, int *list, hipStream_t s);
 hipError_t seg_sort(int M, int nactive, const int *active, const int *start, const int *tmp, int *seg_of,
                     int *out, hipStream_t s);
+hipError_t order_active(int n, const int *active, const int *lstart, int *out, hipStream_t s);
 hipError_t positive_flags(int n, const int *counts, int *flags, hipStream_t s);
 // band: for the active tiles, out += alpha D (W q)   (div = true, cell field)
 //                          or out += alpha W q       (div = false, face field)

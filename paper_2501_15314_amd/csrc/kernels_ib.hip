@@ -414,6 +414,38 @@ hipError_t seg_sort(int M, int nactive, const int *active, const int *start, con
   hipLaunchKernelGGL(k_seg_sort, dim3(nblk(M, 256)), dim3(256), 0, s, M, seg_of, start, tmp, out);
   return hipGetLastError();
 }
+// Active tiles in order of decreasing touch-list length (one workgroup,
+// bucket sort on min(length, 1023)): the spreading workgroups with the most
+// work start first, which shortens the tail of the launch.  Each tile's
+// result does not depend on the order, which within a bucket is arbitrary.
+constexpr int ORD_T = 1024, ORD_B = 1024;
+__global__ void __launch_bounds__(ORD_T) k_order_active(int n, const int *active, const int *lstart, int *out) {
+  __shared__ int cnt[ORD_B], base[ORD_B];
+  const int t = threadIdx.x;
+  cnt[t] = 0;
+  __syncthreads();
+  auto key = [&](int i) {
+    const int a = active[i];
+    return ORD_B - 1 - min(lstart[a + 1] - lstart[a], ORD_B - 1);
+  };
+  for (int i = t; i < n; i += ORD_T) atomicAdd(&cnt[key(i)], 1);
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int b = 0; b < ORD_B; ++b) {
+      base[b] = acc;
+      acc += cnt[b];
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < n; i += ORD_T) out[atomicAdd(&base[key(i)], 1)] = active[i];
+}
+hipError_t order_active(int n, const int *active, const int *lstart, int *out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_order_active, dim3(1), dim3(ORD_T), 0, s, n, active, lstart, out);
+  return hipGetLastError();
+}
+
 __global__ void k_positive(int n, const int *counts, int *flags) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) flags[t] = counts[t] > 0;
@@ -428,29 +460,33 @@ hipError_t positive_flags(int n, const int *counts, int *flags, hipStream_t s) {
 //
 // Staging: up to BAND_CH listed points at a time, one task per (point, axis)
 // computing the face- and centre-node weights of that axis (one square root
-// each) and the local start of the support; per component the first weight
-// vector is multiplied by q.
+// each) and laying them out over the tile's own positions along the axis
+// (5 face / 4 centre positions per component, zero outside the point's
+// support; the x weights of component d carry q_d).
 //
 // Accumulation: lane L < 56 of every wavefront owns one z-column of a face
 // box (component 0: 5 x 4 columns of 4 faces, component 1: 4 x 5 columns of
 // 4 faces, component 2: 4 x 4 columns of 5 faces).  Wavefront w adds the
-// listed points w, w+4, w+8, ... in list order into registers; the four
-// partial sums of a face are added in a fixed order.  Every grid value is
-// therefore summed in the same order on every run.
+// listed points w, w+4, w+8, ... in list order into registers, with no
+// branch: w_x[ci] w_y[cj] times the five z weights of its column (zeros add
+// nothing).  The four partial sums of a face are added in a fixed order.
+// Every grid value is therefore summed in the same order on every run.
 constexpr int BAND_CH = 64;
-
-__device__ __forceinline__ int pack3(int a, int b, int c) {
-  return ((a + 64) & 255) | (((b + 64) & 255) << 8) | (((c + 64) & 255) << 16);
-}
+// doubles per point: x[comp][5], y[comp][5], z[comp][5].  The point stride
+// is odd in 8-byte units, so staging writes of consecutive points spread
+// over the LDS banks, and the three components' 5-double blocks of one axis
+// fall on distinct banks for the accumulation reads.
+constexpr int BAND_WS = 45;
 
 template <int KER, bool DIV>
 __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int *active, const int *lstart,
                                               const int *list, const double *X, const double *q, double alpha,
                                               double *out) {
-  constexpr int W = KerWidth<KER>::W;
-  __shared__ double wts[BAND_CH][3][3][4];  // [cand][comp][axis][node]
-  __shared__ int base[3][BAND_CH];          // local starts per component, one byte per axis
-  __shared__ double part[4][3][80];         // per-wavefront face sums
+  // [cand][axis a * 15 + comp * 5 + position]; after the last chunk the same
+  // LDS holds the per-wavefront face sums part[4][3][80]
+  static_assert(4 * 3 * 80 <= BAND_CH * BAND_WS, "face sums must fit the weight buffer");
+  __shared__ double wts[BAND_CH][BAND_WS];
+  double(*part)[3][80] = reinterpret_cast<double(*)[3][80]>(&wts[0][0]);
   const int tile = active[blockIdx.x];
   const int T2 = tile % nt2, r = tile / nt2, T1 = r % nt1, T0 = r / nt1;
   const int tid = threadIdx.x;
@@ -463,11 +499,10 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
   const int wv = tid >> 6, lane = tid & 63;
   const int cd = lane < 20 ? 0 : (lane < 40 ? 1 : 2);
   const int cl = lane - 20 * cd;
-  const int cby = cd == 1 ? 5 : 4;               // columns along y in this component's box
-  const int ci = cl / cby, cj = cl % cby;
+  const int cby = cd == 1 ? 5 : 4;  // columns along y in this component's box
+  const int ci = min(cl / cby, 4), cj = cl % cby;
   const int nf = cd == 2 ? 5 : 4;
   const bool owner = lane < 56;
-  const int cpack = pack3(ci, cj, 0);
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int c0 = s0; c0 < s1; c0 += BAND_CH) {
     const int nc = min(BAND_CH, s1 - c0);
@@ -484,38 +519,32 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
         lf = wrapi(lf + nn[a] / 2, nn[a]) - nn[a] / 2;
         lc = wrapi(lc + nn[a] / 2, nn[a]) - nn[a] / 2;
       }
-      double qv[3] = {1.0, 1.0, 1.0};
-      if (a == 0) {
-        qv[0] = q[3 * p];
-        qv[1] = q[3 * p + 1];
-        qv[2] = q[3 * p + 2];
-      }
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
+        const double qd = a == 0 ? q[3 * p + d] : 1.0;
+        const int l0 = d == a ? lf : lc;
+        const double *w = d == a ? wf : wc;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) wts[cand][d][a][t] = (d == a ? wf[t] : wc[t]) * qv[d];
+        for (int t = 0; t < 5; ++t) {
+          const int idx = t - l0;
+          // position t exists for the faces of axis d (5) and the cells of the others (4)
+          // select chain (no dynamic index into w, no branch)
+          double v = idx == 0 ? w[0] : 0.0;
+          v = idx == 1 ? w[1] : v;
+          v = idx == 2 ? w[2] : v;
+          v = idx == 3 ? w[3] : v;
+          v *= (t < 4 || d == a) ? qd : 0.0;
+          wts[cand][15 * a + 5 * d + t] = v;
+        }
       }
-      // per component the start along this axis is the face start (d == a) or the centre
-      // start, stored (offset by 64) in byte a of base[d][cand]
-#pragma unroll
-      for (int d = 0; d < 3; ++d)
-        ((unsigned char *)&base[d][cand])[a] = (unsigned char)(((d == a ? lf : lc) + 64) & 255);
     }
     __syncthreads();
     if (owner) {
       for (int c = wv; c < nc; c += 4) {
-        const int bb = base[cd][c];
-        const int la = (cpack & 255) - (bb & 255);
-        const int lb = ((cpack >> 8) & 255) - ((bb >> 8) & 255);
-        if ((unsigned)la < (unsigned)W && (unsigned)lb < (unsigned)W) {
-          const double wab = wts[c][cd][0][la] * wts[c][cd][1][lb];
-          const int lk0 = 64 - ((bb >> 16) & 255);  // z node offset of face fk = 0
+        const double *W = wts[c] + 5 * cd;
+        const double wab = W[ci] * W[15 + cj];
 #pragma unroll
-          for (int fk = 0; fk < 5; ++fk) {
-            const int lc = lk0 + fk;
-            if (fk < nf && (unsigned)lc < (unsigned)W) acc[fk] += wab * wts[c][cd][2][lc];
-          }
-        }
+        for (int fk = 0; fk < 5; ++fk) acc[fk] += wab * W[30 + fk];
       }
     }
   }
