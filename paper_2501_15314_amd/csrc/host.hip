@@ -390,12 +390,14 @@ sim_status place_and_bin(sim_t s, const std::vector<BodyDev> &bd) {
   // non-empty point tiles (interpolation work list)
   CKH(positive_flags(nt, s->COUNTS, s->FLAGS, st));
   CKH(scan_exclusive(s->FLAGS, s->FPOS, nt, s->SCANTMP, st));
-  CKH(compact(nt, s->FLAGS, s->FPOS, s->NZT, st));
+  CKH(compact(nt, s->FLAGS, s->FPOS, s->ACTIVE, st));
   int nz = 0;
   CKH(hipMemcpyAsync(s->hpin, s->FPOS + nt, sizeof(int), hipMemcpyDeviceToHost, st));
   CKH(hipStreamSynchronize(st));
   memcpy(&nz, s->hpin, sizeof(int));
   s->nnz = nz;
+  // fullest point tiles first (ACTIVE, rebuilt below, is the scratch here)
+  CKH(order_active(nz, s->ACTIVE, s->TSTART, s->NZT, st));
   // touch lists of the active tiles (tiles reached by some point's support)
   CKH(fill_i32(s->TCOUNT, nt, 0, st));
   CKH(fill_i32(s->TFILL, nt, 0, st));
