@@ -949,14 +949,15 @@ sim_status correction(sim_t s, int k, bool want_crit, sim_step_stats &S, double 
   CKH(scale3(s->K, s->PHIP, c.xi, s->PHIS, 1.0, s->PHIS, st));
   S.outer = k + 1;
   if (want_crit) {
-    std::vector<double> a(3 * (size_t)s->K), b(3 * (size_t)s->K);
+    // ||Phi'||_1 and ||Phi||_1 on the device
+    double l1[2] = {0.0, 0.0};
     if (s->K > 0) {
-      CKH(hipMemcpyAsync(a.data(), s->PHIP, sizeof(double) * 3 * s->K, hipMemcpyDeviceToHost, st));
-      CKH(hipMemcpyAsync(b.data(), s->PHIS, sizeof(double) * 3 * s->K, hipMemcpyDeviceToHost, st));
+      CKH(abs_sums(s->PHIP, s->PHIS, 3LL * s->K, s->PART, st));
+      CKH(finalize(s->PART, red_blocks(), 2, s->RED, st, s->hpin_dev));
+      sim_status rc2 = read_mirror(s, 2, l1);
+      if (rc2) return rc2;
     }
-    CKH(hipStreamSynchronize(st));
-    double na = 0, nbb = 0;
-    for (size_t q = 0; q < a.size(); ++q) { na += fabs(a[q]); nbb += fabs(b[q]); }
+    const double na = l1[0], nbb = l1[1];
     S.outer_crit = nbb > 0 ? na / nbb : (na > 0 ? INFINITY : 0.0);
   }
   return SIM_OK;
@@ -969,17 +970,17 @@ sim_status finish_step(sim_t s, double t1, double divstar, sim_step_stats &S) {
   sim_status rc;
   CKH(scatter3(s->K, s->PERM, s->PHIS, s->PHIN, st));
   CKH(div_apply(s->g, s->USTAR, s->TMPC, 1.0, st));
-  double dn2;
-  if ((rc = dev_norm2(s, s->TMPC, N, &dn2))) return rc;
-  S.div_rel = divstar > 0 ? sqrt(dn2) / divstar : 0.0;
-  CKH(interp_face(s->ker, s->g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, s->USTAR, 1.0, s->US, -1.0, s->PT3,
-                  st));
-  if (s->K > 0) {
-    double sl2, u2;
-    if ((rc = dev_norm2(s, s->PT3, 3LL * s->K, &sl2))) return rc;
-    if ((rc = dev_norm2(s, s->US, 3LL * s->K, &u2))) return rc;
-    S.slip_rel = u2 > 0 ? sqrt(sl2 / u2) : 0.0;
-  }
+  if (s->K > 0)
+    CKH(interp_face(s->ker, s->g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, s->USTAR, 1.0, s->US, -1.0,
+                    s->PT3, st));
+  // |D u|^2, |slip|^2, |U|^2 in one reduction
+  double q3[3];
+  CKH(sumsq3(s->TMPC, N, s->K > 0 ? s->PT3 : nullptr, 3LL * s->K, s->K > 0 ? s->US : nullptr, 3LL * s->K, s->PART,
+             st));
+  CKH(finalize(s->PART, red_blocks(), 3, s->RED, st, s->hpin_dev));
+  if ((rc = read_mirror(s, 3, q3))) return rc;
+  S.div_rel = divstar > 0 ? sqrt(q3[0]) / divstar : 0.0;
+  if (s->K > 0) S.slip_rel = q3[2] > 0 ? sqrt(q3[1] / q3[2]) : 0.0;
   // u^{n-1} <- u^n, u^n <- u^{n+1}
   std::swap(s->UM, s->U);
   std::swap(s->U, s->USTAR);

@@ -209,6 +209,9 @@ hipError_t dot2(const double *a, const double *b, long long n, double *part,
                 hipStream_t s);
 hipError_t lincomb(double *y, const double *a, double ca, const double *b, double cb, const double *c, double cc,
                    const double *d, int nd, long long n, double *part, hipStream_t s);
-hipError_t dots2(const double *a, const double *b0, const double *b1, long long n, double *part, hipStream_t s);  // partial a.b (sum of a when b is null)
+hipError_t dots2(const double *a, const double *b0, const double *b1, long long n, double *part, hipStream_t s);
+hipError_t abs_sums(const double *a, const double *b, long long n, double *part, hipStream_t s);
+hipError_t sumsq3(const double *a, long long na, const double *b, long long nb, const double *c, long long nc,
+                  double *part, hipStream_t s);  // partial a.b (sum of a when b is null)
 
 }  // namespace ibs

@@ -348,4 +348,48 @@ hipError_t dots2(const double *a, const double *b0, const double *b1, long long 
   return hipGetLastError();
 }
 
+// Step diagnostics in one pass each: sum |a| and sum |b| (two per block), and
+// the sums of squares of up to three vectors of different lengths (three per
+// block; a null vector contributes 0).
+__global__ void __launch_bounds__(RED_T) k_abs_sums(const double *a, const double *b, long long n, double *part) {
+  __shared__ double sh[4];
+  double s0 = 0.0, s1 = 0.0;
+  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T) {
+    s0 += fabs(a[t]);
+    s1 += fabs(b[t]);
+  }
+  s0 = block_reduce(s0, sh);
+  s1 = block_reduce(s1, sh);
+  if (threadIdx.x == 0) {
+    part[2LL * blockIdx.x] = s0;
+    part[2LL * blockIdx.x + 1] = s1;
+  }
+}
+hipError_t abs_sums(const double *a, const double *b, long long n, double *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_abs_sums, dim3(RED_BLOCKS), dim3(RED_T), 0, s, a, b, n, part);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(RED_T) k_sumsq3(const double *a, long long na, const double *b, long long nb,
+                                                  const double *c, long long nc, double *part) {
+  __shared__ double sh[4];
+  double s[3] = {0.0, 0.0, 0.0};
+  const double *v[3] = {a, b, c};
+  const long long nn[3] = {a ? na : 0, b ? nb : 0, c ? nc : 0};
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+    for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < nn[q]; t += (long long)gridDim.x * RED_T)
+      s[q] += v[q][t] * v[q][t];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const double r = block_reduce(s[q], sh);
+    if (threadIdx.x == 0) part[3LL * blockIdx.x + q] = r;
+  }
+}
+hipError_t sumsq3(const double *a, long long na, const double *b, long long nb, const double *c, long long nc,
+                  double *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_sumsq3, dim3(RED_BLOCKS), dim3(RED_T), 0, s, a, na, b, nb, c, nc, part);
+  return hipGetLastError();
+}
+
 }  // namespace ibs
