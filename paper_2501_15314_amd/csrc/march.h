@@ -349,23 +349,53 @@ __global__ void __launch_bounds__(256) k_apply2(Geo g, const T *x, const double 
     if (ii < 0) return v;
     return ld2<T>(xg + (long long)q * g.half + row(ii, p.j) + p.m0);
   };
+  // software pipeline as in the sweeps: the window plane i+2, both halos and
+  // the right-hand side of plane i+1 are loaded while plane i is computed
+  auto plane_val = [&](int q) {
+    const T *plane = xg + (long long)q * g.half;
+    return [=](int ii, int jj, int mm) -> T { return plane[((long long)ii * g.n1 + jj) * g.hn2 + mm]; };
+  };
+  auto rhs = [&](int i, V2<double> *bb) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      bb[q].x = 0.0;
+      bb[q].y = 0.0;
+      if (MODE == AP_HRESID) bb[q] = ld2<double>(bg + (long long)q * g.half + row(i, p.j) + p.m0);
+    }
+  };
   V2<T> prv[2], cur[2], nxt[2];
-  prv[0] = win(0, p.i0 - 1);
-  prv[1] = win(1, p.i0 - 1);
-  cur[0] = win(0, p.i0);
-  cur[1] = win(1, p.i0);
+  Halo<T> hcur[2];
+  V2<double> bbc[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    prv[q] = win(q, p.i0 - 1);
+    cur[q] = win(q, p.i0);
+    nxt[q] = win(q, p.i0 + 1);
+    hcur[q] = halo_fetch<T>(g, p.i0, jbase, mbase, BX, BY, plane_val(q));
+  }
+  rhs(p.i0, bbc);
   double acc = 0.0;
   for (int i = p.i0; i < p.i1; ++i) {
-    nxt[0] = win(0, i + 1);
-    nxt[1] = win(1, i + 1);
+    const bool more = i + 1 < p.i1;
+    V2<T> nn[2];
+    Halo<T> hnext[2];
+    V2<double> bbn[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      nn[q] = more ? win(q, i + 2) : nxt[q];
+      hnext[q] = more ? halo_fetch<T>(g, i + 1, jbase, mbase, BX, BY, plane_val(q)) : hcur[q];
+    }
+    if (more) rhs(i + 1, bbn);
+    else {
+      bbn[0] = bbc[0];
+      bbn[1] = bbc[1];
+    }
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       T *tq = tile[q];
       tq[(p.ty + 1) * W2 + 2 * p.tx + 1] = cur[q].x;
       tq[(p.ty + 1) * W2 + 2 * p.tx + 2] = cur[q].y;
-      const T *plane = xg + (long long)q * g.half;
-      tile_halo(tq, g, i, jbase, mbase, BX, BY,
-                [&](int ii, int jj, int mm) -> T { return plane[row(ii, jj) + mm]; });
+      halo_put(tq, hcur[q], g, i, jbase, mbase, BX, BY, plane_val(q));
     }
     __syncthreads();
     const long long r = row(i, p.j) + p.m0;
@@ -373,10 +403,7 @@ __global__ void __launch_bounds__(256) k_apply2(Geo g, const T *x, const double 
     for (int q = 0; q < 2; ++q) {
       const T *to = tile[1 - q];
       const int s = (q + i + p.j) & 1;
-      V2<double> bb;
-      bb.x = 0.0;
-      bb.y = 0.0;
-      if (MODE == AP_HRESID) bb = ld2<double>(bg + (long long)q * g.half + r);
+      const V2<double> bb = bbc[q];
       double o[2];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
@@ -411,6 +438,9 @@ __global__ void __launch_bounds__(256) k_apply2(Geo g, const T *x, const double 
     for (int q = 0; q < 2; ++q) {
       prv[q] = cur[q];
       cur[q] = nxt[q];
+      nxt[q] = nn[q];
+      hcur[q] = hnext[q];
+      bbc[q] = bbn[q];
     }
   }
   if (MODE == AP_HRESID) {
