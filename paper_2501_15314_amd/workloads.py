@@ -259,6 +259,50 @@ def make_c5(seed: int = 5, n: int = 384, points_per_sphere: int = 18000,
                     seed=seed)
 
 
+# Porous sphere of diameter D modelled by solid sub-spheres packed inside it
+# (Sec. 6.1.2): sub-sphere radius r D and centres in units of D / 10, from the
+# paper's table of the 7- and 14-sub-sphere configurations.
+POROUS_CONFIGS = {
+    7: (0.193, [(1.1140, -1.9296, -2.1126), (-2.2281, 0.0, -2.1126), (1.1140, 1.9296, -2.1126),
+                (-1.5009, -2.5997, 0.64522), (3.0019, 0.0, 0.64522), (-1.5009, 2.5997, 0.64522),
+                (0.0, 0.0, 3.0704)]),
+    14: (0.161, [(0.0, -2.287, -2.4917), (-2.2875, 0.0, -2.4917), (2.2875, 0.0, -2.4917), (0.0, 2.2875, -2.4917),
+                 (-2.3820, -2.3820, -0.30478), (2.3820, -2.3820, -0.30478), (-2.3820, 2.3820, -0.30478),
+                 (2.3820, 2.3820, -0.30478), (0.0, 0.0, 0.0), (0.0, -2.8412, 1.8355), (-2.8412, 0.0, 1.8355),
+                 (2.8412, 0.0, 1.8355), (0.0, 2.8412, 1.8355), (0.0, 0.0, 3.3825)]),
+}
+
+
+def make_porous(n_sub: int = 7, cells_per_d: int = 32, re: float = 100.0, amp: float = 1.0,
+                precision: int = PREC_FP64) -> Workload:
+    """Oscillating porous sphere (Sec. 6.1.2, the oscillation law of Sec. 6.1.1):
+    bounding sphere of diameter D = 1 at the centre of a 4D x 4D x 6D no-slip
+    box, n_sub rigid sub-spheres of radius r D - h/2 at the tabulated centres,
+    all moving with z(t) = -A cos(t / A) (u_z = sin(t / A), U_max = 1), nu =
+    1/Re, Roma 3-point kernel, markers at spacing ~h, time step at CFL 0.1.
+    The grid is (4, 4, 6) x cells_per_d (multiples of 8 so that every
+    multigrid level keeps the plane-march layout)."""
+    r, centres = POROUS_CONFIGS[n_sub]
+    n = (4 * cells_per_d, 4 * cells_per_d, 6 * cells_per_d)
+    h = 1.0 / cells_per_d
+    radius = r - 0.5 * h
+    n_points = max(8, int(round(4.0 * math.pi * radius * radius / (h * h))))
+    box_centre = np.array([2.0, 2.0, 3.0])
+    cfg = Config(n=n, length=(4.0, 4.0, 6.0), bc=(BC_NOSLIP,) * 3, nu=1.0 / re, dt=0.1 * h,
+                 delta=DELTA_ROMA3, lump_c=lump_constant(DELTA_ROMA3, h, n_points, radius),
+                 precision=precision, krylov_rtol=1e-8)
+    bodies = []
+    for c in centres:
+        # centre(t) = centre - A cos(t / A) e_z: the stroke z in [-A, A] about
+        # the box centre, starting at its lowest point
+        bodies.append(Body(center=box_centre + 0.1 * np.array(c), vel=np.zeros(3),
+                           omega=np.zeros(3), radius=radius, n_points=n_points,
+                           osc_amp=np.array([0.0, 0.0, amp]), osc_omega=1.0 / amp))
+    offsets = np.concatenate([fibonacci_offsets(n_points, radius) for _ in centres])
+    u0 = np.zeros((3,) + n)
+    return Workload(f"porous{n_sub}_{n[0]}x{n[1]}x{n[2]}", cfg, bodies, offsets, u0, steps=1, seed=0)
+
+
 def scaled(make, n: int, **kw) -> Workload:
     """The same geometry on an n^3 grid with the marker count scaled as h^-2."""
     w0 = make()
