@@ -863,9 +863,16 @@ sim_status helm_solve(sim_t s, const double *rhs, double *u, sim_solve_stats *st
   double bn2;
   if ((rc = dev_norm2(s, rhs, n3, &bn2))) return rc;
   double bnorm = sqrt(bn2);
-  // sweeps per correction: rho^k <= 1e-4 (a safe gain per correction in float32)
-  int kin = rho > 1e-12 ? (int)ceil(log(1e-4) / log(rho)) : 1;
-  kin = std::max(1, std::min(kin, 100));
+  // sweeps per correction: enough for rho^k to reach the remaining factor
+  // to helm_rtol (half of it, for margin), but no more than a safe gain for
+  // the correction's precision (1e-4 in float32; 1e-10 in float64, where one
+  // correction usually suffices)
+  const double floor_gain = sizeof(T) == 4 ? 1e-4 : 1e-10;
+  auto sweeps_for = [&](double rel_now) {
+    const double gain = std::min(1.0, std::max(0.5 * c.helm_rtol / std::max(rel_now, 1e-300), floor_gain));
+    int k = rho > 1e-12 ? (int)ceil(log(gain) / log(rho)) : 1;
+    return std::max(1, std::min(k, 100));
+  };
   double rel = 1.0;
   int it = 0;
   int nb = 0;
@@ -882,6 +889,7 @@ sim_status helm_solve(sim_t s, const double *rhs, double *u, sim_solve_stats *st
     if (S.nhist < 64) S.hist[S.nhist++] = rel;
     if (rel <= c.helm_rtol || it >= c.helm_maxit) break;
     CKH(zero_t<T>(E, n3, st));
+    const int kin = sweeps_for(rel);
     for (int k = 0; k < kin; ++k) {
       for (int color = 0; color < 2; ++color) {
         ProbeScope pr(PR_HELM_SWEEP, st);
