@@ -157,17 +157,30 @@ __global__ void __launch_bounds__(256) k_prolong(Geo gf, T *xf, Geo gc, const T 
   };
   auto wrapP = [&](int P) { return side(P < 0 ? 0 : gc.n0 - 1, P, gc.n0, gc.bc0); };
   int lo = (i0 - 1) >> 1;
-  T vlo[2][4], vhi[2][4];
+  T vlo[2][4], vhi[2][4], vpre[2][4];
   load_plane(wrapP(lo), vlo);
   load_plane(wrapP(lo + 1), vhi);
+  auto xrow = [&](int i) { return xf + ((long long)i * gf.n1 + j) * gf.hn2 + m0; };
+  V2<T> xcur = ld2<T>(xrow(i0));
   for (int i = i0; i < i1; ++i) {
     if (((i - 1) >> 1) != lo) {
+      // the window moves up one coarse plane (prefetched one fine plane ago)
       ++lo;
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) vlo[r][q] = vhi[r][q];
-      load_plane(wrapP(lo + 1), vhi);
+        for (int q = 0; q < 4; ++q) {
+          vlo[r][q] = vhi[r][q];
+          vhi[r][q] = vpre[r][q];
+        }
+    }
+    // software pipeline: the next fine row and, when the window will move at
+    // plane i+1, its new coarse plane
+    const bool more = i + 1 < i1;
+    V2<T> xnext = xcur;
+    if (more) {
+      xnext = ld2<T>(xrow(i + 1));
+      if ((i >> 1) != lo) load_plane(wrapP(lo + 2), vpre);
     }
     // parent plane i>>1 is lo for odd i, hi for even i
     const T wlo = (i & 1) ? (T)0.75 : (T)0.25, whi = (T)1 - wlo;
@@ -187,9 +200,8 @@ __global__ void __launch_bounds__(256) k_prolong(Geo gf, T *xf, Geo gc, const T 
       }
       out[u] = acc;
     }
-    T *p = xf + ((long long)i * gf.n1 + j) * gf.hn2 + m0;
-    const V2<T> x = ld2<T>(p);
-    st2(p, x.x + out[0], x.y + out[1]);
+    st2(xrow(i), xcur.x + out[0], xcur.y + out[1]);
+    xcur = xnext;
   }
 }
 
