@@ -124,6 +124,38 @@ def test_nonfinite_rhs_rejected():
     sim.close()
 
 
+@pytest.mark.parametrize("field,value", [("precond", 7), ("krylov", 5), ("n", (20, 20, 20))])
+def test_bad_solver_options_rejected(field, value):
+    """Unknown preconditioner or Krylov codes, and a fast-diagonalisation grid
+    whose sizes are not multiples of 8 (one multigrid level, so that only that
+    rule applies), are refused at creation."""
+    w = wl.make_c1(n=32, n_points=300)
+    cfg = w.cfg
+    if field == "n":
+        cfg.n, cfg.length, cfg.precond, cfg.mg_coarsest = value, (1.0, 1.0, 1.0), wl.PRECOND_FASTDIAG, 32
+    else:
+        setattr(cfg, field, value)
+    with pytest.raises(SimError) as e:
+        Sim(cfg, w.n_points)
+    assert "EINVAL" in str(e.value)
+
+
+def test_bicgstab_notconv_reports_best_iterate():
+    w = wl.make_c1(n=32, n_points=300)
+    w.cfg.krylov = wl.KRYLOV_BICGSTAB
+    w.cfg.krylov_maxit = 1
+    w.cfg.krylov_rtol = 1e-14
+    sim = Sim(w.cfg, w.n_points)
+    sim.set_bodies(w.bodies, w.offsets)
+    rp, rf = wl.random_schur_rhs(25, w.cfg.n, w.n_points)
+    with pytest.raises(SimError) as e:
+        sim.solve_schur(rp, rf)
+    assert "ENOTCONV" in str(e.value)
+    p, phi, st = sim.solve_schur(rp, rf, allow_notconv=True)
+    assert st.iters == 1 and 0 < st.rel_res < 1
+    sim.close()
+
+
 def test_support_crossing_wall_rejected():
     w = walls_workload(32, 260)
     w.bodies[0].center = np.array([0.07, 0.5, 0.5])
