@@ -257,12 +257,16 @@ sim_status sim_step_adjoint(sim_t sim, const double *d_gu, const double *d_gv,
  *   SIM_OP_CONVECTION    faces -> faces      div(u u)
  *   SIM_OP_HELM_SOLVE    faces -> faces      A^-1 (to helm_rtol)
  *   SIM_OP_SCHUR_RHS     cells+points -> cells  b = RHS_p + c^-1 D W RHS_F
+ *   SIM_OP_SCHUR_EXACT   cells -> cells      S_p = L + B^T (W^T W)^-1 B, the primal Schur
+ *                        complement before lumping (paper Sec. 4.1; the operator of the
+ *                        spectral theorem of Sec. 5), (W^T W)^-1 by conjugate gradients
+ *                        on the device to 1e-13 (SIM_ENOTCONV if that fails)
  *                        (in = rhs_p, in2 = rhs_f)
  * Precision follows cfg.precision where the operator has a mixed form. */
 enum {
   SIM_OP_LAPLACIAN = 0, SIM_OP_SCHUR = 1, SIM_OP_PRECOND = 2, SIM_OP_GRAD = 3,
   SIM_OP_DIV = 4, SIM_OP_INTERP = 5, SIM_OP_SPREAD = 6, SIM_OP_HELMHOLTZ = 7,
-  SIM_OP_CONVECTION = 8, SIM_OP_HELM_SOLVE = 9, SIM_OP_SCHUR_RHS = 10
+  SIM_OP_CONVECTION = 8, SIM_OP_HELM_SOLVE = 9, SIM_OP_SCHUR_RHS = 10, SIM_OP_SCHUR_EXACT = 11
 };
 sim_status sim_apply(sim_t sim, int32_t op, const double *d_in, const double *d_in2,
                      double *d_out);

@@ -18,7 +18,7 @@ STATUS_NAMES = {0: "SIM_OK", -1: "SIM_EINVAL", -2: "SIM_ESTATE", -3: "SIM_ENOTCO
                 -4: "SIM_ENONFINITE", -5: "SIM_EDEVICE", -6: "SIM_ENOMEM"}
 
 OPS = dict(laplacian=0, schur=1, precond=2, grad=3, div=4, interp=5, spread=6, helmholtz=7,
-           convection=8, helm_solve=9, schur_rhs=10)
+           convection=8, helm_solve=9, schur_rhs=10, schur_exact=11)
 
 EXPORTS = ["sim_workspace_bytes", "sim_create", "sim_destroy", "sim_set_bodies", "sim_set_fields",
            "sim_get_fields", "sim_step", "sim_solve_schur", "sim_get_forces", "sim_get_points",

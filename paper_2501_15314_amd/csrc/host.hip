@@ -1633,6 +1633,65 @@ sim_status sim_probe_read(sim_t s, int32_t probe, int64_t *launches, double *ms,
   return SIM_OK;
 }
 
+// w = S_p z = L z + B^T C^-1 B z with the unlumped C = W^T W (the primal
+// Schur complement of Sec. 4.1 before the lumping C ~ c I; B = -W^T G,
+// B^T = D W).  C^-1 by conjugate gradients on the Lagrangian vectors in
+// float64 to a relative residual of 1e-13, started from the lumped guess
+// B z / c; each C product is a spread into a cleared face field followed by
+// an interpolation.  An operator-level tool (the spectral checks of Sec. 5),
+// not part of the time step.
+sim_status exact_schur_matvec(sim_t s, const double *z, double *w, int *cg_iters) {
+  hipStream_t st = s->st;
+  const Geo &g = s->g;
+  const long long N = s->N, n3 = 3LL * s->K;
+  sim_status rc;
+  CKH(lap_apply<double>(g, z, w, st));
+  if (cg_iters) *cg_iters = 0;
+  if (s->K == 0) return SIM_OK;
+  double *q = s->ADJ, *y = q + n3, *r = y + n3, *pv = r + n3, *ap = pv + n3;
+  auto dot = [&](const double *a, const double *b, double *out) -> sim_status {
+    CKH(dot2(a, b, n3, s->PART, st));
+    CKH(finalize(s->PART, red_blocks(), 1, s->RED, st, s->hpin_dev));
+    return read_mirror(s, 1, out);
+  };
+  auto applyC = [&](const double *v, double *out) -> sim_status {
+    CKH(fill(s->TMP3, 3 * N, 0.0, st));
+    CKH(band_apply(s->ker, false, g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, v, 1.0,
+                   s->TMP3, st));
+    CKH(interp_face(s->ker, g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, s->TMP3, 1.0, nullptr, 0.0, out,
+                    st));
+    return SIM_OK;
+  };
+  // q = B z
+  CKH(interp_grad<double>(s->ker, g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, z, -1.0, nullptr, 0.0, q, st));
+  CKH(scale3(s->K, q, 1.0 / s->c, nullptr, 0.0, y, st));
+  if ((rc = applyC(y, ap))) return rc;
+  CKH(scale3(s->K, q, 1.0, ap, -1.0, r, st));
+  CKH(scale3(s->K, r, 1.0, nullptr, 0.0, pv, st));
+  double q2, rr;
+  if ((rc = dot(q, q, &q2)) || (rc = dot(r, r, &rr))) return rc;
+  if (!isfinite(q2) || !isfinite(rr)) return fail(s, SIM_ENONFINITE, "non-finite Lagrangian vector");
+  int it = 0;
+  for (; it < 500 && rr > 1e-26 * q2; ++it) {
+    if ((rc = applyC(pv, ap))) return rc;
+    double pap;
+    if ((rc = dot(pv, ap, &pap))) return rc;
+    if (!(pap > 0)) return fail(s, SIM_ENONFINITE, "W^T W is not positive definite on this point set");
+    const double alpha = rr / pap;
+    CKH(scale3(s->K, y, 1.0, pv, alpha, y, st));
+    CKH(scale3(s->K, r, 1.0, ap, -alpha, r, st));
+    double rr2;
+    if ((rc = dot(r, r, &rr2))) return rc;
+    CKH(scale3(s->K, r, 1.0, pv, rr2 / rr, pv, st));
+    rr = rr2;
+  }
+  if (cg_iters) *cg_iters = it;
+  if (rr > 1e-26 * q2) return fail(s, SIM_ENOTCONV, "inner conjugate gradients on W^T W did not converge");
+  // w += B^T y = D W y
+  CKH(band_apply(s->ker, true, g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, y, 1.0, w, st));
+  return SIM_OK;
+}
+
 sim_status sim_apply(sim_t s, int32_t op, const double *in, const double *in2, double *out) {
   if (!s) return SIM_EINVAL;
   s->adj_ready = false;
@@ -1641,7 +1700,8 @@ sim_status sim_apply(sim_t s, int32_t op, const double *in, const double *in2, d
   const Geo &g = s->g;
   const long long N = s->N;
   sim_status rc;
-  bool need_points = op == SIM_OP_SCHUR || op == SIM_OP_INTERP || op == SIM_OP_SPREAD || op == SIM_OP_SCHUR_RHS;
+  bool need_points = op == SIM_OP_SCHUR || op == SIM_OP_INTERP || op == SIM_OP_SPREAD || op == SIM_OP_SCHUR_RHS ||
+                     op == SIM_OP_SCHUR_EXACT;
   if (need_points && !s->have_bodies) return fail(s, SIM_ESTATE, "no bodies set");
   switch (op) {
     case SIM_OP_LAPLACIAN:
@@ -1713,6 +1773,11 @@ sim_status sim_apply(sim_t s, int32_t op, const double *in, const double *in2, d
       CKH(to_natural(g, 3, s->TMP3, out, st));
       break;
     }
+    case SIM_OP_SCHUR_EXACT:
+      CKH(to_split(g, 1, in, s->TMPC, st));
+      if ((rc = exact_schur_matvec(s, s->TMPC, s->PP, nullptr))) return rc;
+      CKH(to_natural(g, 1, s->PP, out, st));
+      break;
     case SIM_OP_SCHUR_RHS:
       if (s->K > 0 && !in2) return fail(s, SIM_EINVAL, "SCHUR_RHS needs rhs_f");
       CKH(to_split(g, 1, in, s->RHSP, st));

@@ -183,7 +183,7 @@ class Sim:
         cells, faces, points = self.n, (3,) + self.n, (max(self.K, 1), 3)
         out_shape = {"laplacian": cells, "schur": cells, "precond": cells, "grad": faces,
                      "div": cells, "interp": points, "spread": faces, "helmholtz": faces,
-                     "convection": faces, "helm_solve": faces, "schur_rhs": cells}[op]
+                     "convection": faces, "helm_solve": faces, "schur_rhs": cells, "schur_exact": cells}[op]
         out = torch.empty(out_shape, dtype=torch.float64, device=self.dev)
         self._check(self.lib.sim_apply(self.h, opid, _ptr(x), _ptr(x2), _ptr(out)))
         return out[:self.K] if op == "interp" else out
