@@ -27,15 +27,15 @@ import scipy.sparse as sp
 
 from . import delta, mac
 from . import step as ostep
-from .mac import NOSLIP
+from .mac import is_wall
 
 
 def _shift(g: mac.Grid, a: int, s: int) -> sp.csr_matrix:
-    """(S f)(x) = f(x + s e_a); zero outside a no-slip box, wrapped otherwise."""
+    """(S f)(x) = f(x + s e_a); zero outside a wall box, wrapped otherwise."""
     ii = [x.ravel() for x in g.idx()]
     jj = [x.copy() for x in ii]
     jj[a] = ii[a] + s
-    if g.bc[a] == NOSLIP:
+    if is_wall(g.bc[a]):
         ok = (jj[a] >= 0) & (jj[a] < g.n[a])
     else:
         jj[a] %= g.n[a]
@@ -49,7 +49,7 @@ def convection_jacobian(g: mac.Grid, u: np.ndarray) -> sp.csr_matrix:
     """dN/du at u (3N x 3N) for the flux form of mac.convection:
     N_d = sum_a (F_ad(x) - F_ad(x - e_a)) / h with F_dd = C^2, C the cell mean
     of u_d, and F_ad = E1 E2 (a != d), E1 = mean of u_d across the edge,
-    E2 = mean of u_a along d at the edge; fluxes through no-slip walls are 0."""
+    E2 = mean of u_a along d at the edge; fluxes through walls are 0."""
     N, h = g.N, g.h
     mask = g.face_dof_mask().reshape(3, N).astype(np.float64)
     uu = (u.reshape(3, N) * mask)
@@ -71,7 +71,7 @@ def convection_jacobian(g: mac.Grid, u: np.ndarray) -> sp.csr_matrix:
                 E1, E2 = E1op @ uu[d], E2op @ uu[a]
                 zp = np.ones(N)
                 zm = np.ones(N)
-                if g.bc[a] == NOSLIP:
+                if is_wall(g.bc[a]):
                     zp[idx[a] == g.n[a] - 1] = 0.0
                     zm[idx[a] == 0] = 0.0
                 Zp, Zm = sp.diags(zp), sp.diags(zm)

@@ -11,7 +11,7 @@ Kernels (1-D, argument in cell widths):
   * PESKIN4: the standard 4-point kernel (support 2 cells); the paper prints
     only the 3-point one, the 4-point formula is Peskin's (Acta Numerica 2002).
 
-Periodic axes wrap with the minimum image; on a no-slip axis the support of a
+Periodic axes wrap with the minimum image; on a wall axis (either kind) the support of a
 point must stay inside the domain (Appendix B), otherwise ValueError.
 """
 from __future__ import annotations
@@ -19,7 +19,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from .mac import NOSLIP, PERIODIC, Grid
+from .mac import PERIODIC, Grid
 
 PESKIN4 = 0
 ROMA3 = 1
@@ -103,17 +103,17 @@ def _stencil(g: Grid, X: np.ndarray, d: int, kernel: int):
 
 
 def check_support(g: Grid, X: np.ndarray, kernel: int):
-    """Appendix B: near a no-slip wall the whole support must lie on interior
-    nodes; raise ValueError otherwise."""
+    """Appendix B: near a wall (either kind) the whole support must lie on
+    interior nodes; raise ValueError otherwise."""
     for d in range(3):
         idx, _ = _stencil(g, X, d, kernel)
         for a in range(3):
-            if g.bc[a] != NOSLIP:
+            if g.bc[a] == PERIODIC:
                 continue
             lo = 1 if a == d else 0
             hi = g.n[a] - 1
             if (idx[:, a, :] < lo).any() or (idx[:, a, :] > hi).any():
-                raise ValueError("delta support of a Lagrangian point crosses a no-slip wall")
+                raise ValueError("delta support of a Lagrangian point crosses a wall")
 
 
 def regularization_matrix(g: Grid, X: np.ndarray, kernel: int = PESKIN4,

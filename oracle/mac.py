@@ -6,13 +6,18 @@ time).  The paper does not print the stencils;
 the reading taken here is the classical MAC scheme:
 
   * (G p) on the face of component d at index (i,j,k) = (p[idx] - p[idx-e_d]) / h;
-    on a no-slip axis d the index-0 face is the wall, its row of G is zero;
+    on a wall axis d the index-0 face is the wall, its row of G is zero;
   * D = -G^T exactly (the symmetry the spectral theorem of Sec. 5 needs);
   * L = G^T G, the positive semi-definite Neumann/periodic Laplacian "-nabla^2"
     of eq. modified_poisson (no Dirichlet point: its null space is the constants);
   * the viscous Laplacian on each velocity component is the 7-point stencil on
-    that component's face grid; a tangential wall neighbour is the ghost value
-    -u (wall half a cell away), a normal wall neighbour is the wall face, 0;
+    that component's face grid; a normal wall neighbour is the wall face, 0;
+    a tangential wall neighbour is a ghost half a cell beyond the wall: -u on
+    a no-slip wall (zero tangential velocity at the wall), +u on a free-slip
+    wall (zero normal derivative of the tangential velocity, the box
+    condition of the sedimentation runs of Sec. 6.1.3);
+  * both wall kinds carry zero normal velocity, so G, D, L and the
+    convective fluxes through the wall are the same for both;
   * the convection term (u . grad u) of eq. ustar is taken in divergence form
     div(u u) with arithmetic averaging to the control-volume faces.
 
@@ -25,6 +30,12 @@ import scipy.sparse as sp
 
 PERIODIC = 0
 NOSLIP = 1
+FREESLIP = 2
+
+
+def is_wall(b: int) -> bool:
+    """Either wall kind: the box ends on this axis, normal velocity zero."""
+    return b != PERIODIC
 
 
 class Grid:
@@ -41,11 +52,11 @@ class Grid:
         return (i * self.n[1] + j) * self.n[2] + k
 
     def face_dof_mask(self):
-        """(3, n0, n1, n2) bool: False on wall faces (index 0 of a no-slip axis d
+        """(3, n0, n1, n2) bool: False on wall faces (index 0 of a wall axis d
         for component d), which are not unknowns and always hold zero."""
         m = np.ones((3,) + self.n, dtype=bool)
         for d in range(3):
-            if self.bc[d] == NOSLIP:
+            if is_wall(self.bc[d]):
                 sl = [d, slice(None), slice(None), slice(None)]
                 sl[1 + d] = 0
                 m[tuple(sl)] = False
@@ -71,7 +82,7 @@ def gradient(g: Grid) -> sp.csr_matrix:
     rows, cols, vals = [], [], []
     for d in range(3):
         lo, valid = _shift(ii, d, -1, g.n, g.bc)
-        if g.bc[d] == NOSLIP:
+        if is_wall(g.bc[d]):
             valid = valid & (ii[d] > 0)
         r = d * g.N + g.lin(*ii)
         rows += [r[valid], r[valid]]
@@ -116,11 +127,15 @@ def viscous_laplacian(g: Grid) -> sp.csr_matrix:
                     ok = (nbi >= 1) & (nbi <= g.n[a] - 1)
                     diag -= h2
                 else:
-                    # tangential: outside the box the ghost value is -u (wall at the
-                    # cell boundary), which adds -1/h^2 to the diagonal
+                    # tangential: outside the box the ghost value is -u on a
+                    # no-slip wall (adds -1/h^2 to the diagonal) and +u on a
+                    # free-slip wall (cancels the -1/h^2 of the centre)
                     ok = valid
                     diag -= h2
-                    diag[~valid] -= h2
+                    if g.bc[a] == FREESLIP:
+                        diag[~valid] += h2
+                    else:
+                        diag[~valid] -= h2
                 ok = ok & dof & mask[d][g.lin(*nb)]
                 rows.append(base + lin[ok])
                 cols.append(base + g.lin(*nb)[ok])
@@ -142,8 +157,8 @@ def helmholtz(g: Grid, nu: float, dt: float) -> sp.csr_matrix:
 
 def convection(g: Grid, u: np.ndarray) -> np.ndarray:
     """N(u) = div(u u) at the faces, central, arithmetic averages (reading of
-    Sec. 3.1: explicit at t^n).  u: (3, n0, n1, n2).  Fluxes through no-slip
-    walls vanish (normal velocity zero there, tangential ghost = -u)."""
+    Sec. 3.1: explicit at t^n).  u: (3, n0, n1, n2).  Fluxes through walls
+    of either kind vanish (normal velocity zero there)."""
     n, h, bc = g.n, g.h, g.bc
     out = np.zeros_like(u)
     mask = g.face_dof_mask()
@@ -152,7 +167,7 @@ def convection(g: Grid, u: np.ndarray) -> np.ndarray:
     def sh(f, a, s):
         """f(idx + s e_a), zero outside a wall box."""
         r = np.roll(f, -s, axis=a)
-        if bc[a] == NOSLIP:
+        if is_wall(bc[a]):
             sl = [slice(None)] * 3
             if s > 0:
                 sl[a] = slice(n[a] - s, n[a])
@@ -177,10 +192,10 @@ def convection(g: Grid, u: np.ndarray) -> np.ndarray:
                 ud_e = 0.5 * (ud + sh(ud, a, 1))
                 ua_e = 0.5 * (sh(ua, a, 1) + sh(sh(ua, a, 1), d, -1))
                 fp = ud_e * ua_e
-                if bc[a] == NOSLIP:
+                if is_wall(bc[a]):
                     fp = np.where(idx[a] == n[a] - 1, 0.0, fp)
                 fm = sh(fp, a, -1)
-                if bc[a] == NOSLIP:
+                if is_wall(bc[a]):
                     fm = np.where(idx[a] == 0, 0.0, fm)
                 acc += (fp - fm) / h
         out[d] = acc
@@ -195,7 +210,7 @@ def grad_stencil(g: Grid, p: np.ndarray) -> np.ndarray:
     out = np.empty((3,) + g.n)
     for d in range(3):
         gd = (p - np.roll(p, 1, axis=d)) / g.h
-        if g.bc[d] == NOSLIP:
+        if is_wall(g.bc[d]):
             sl = [slice(None)] * 3
             sl[d] = 0
             gd[tuple(sl)] = 0.0
@@ -207,12 +222,12 @@ def div_stencil(g: Grid, u: np.ndarray) -> np.ndarray:
     out = np.zeros(g.n)
     for d in range(3):
         ud = u[d].copy()
-        if g.bc[d] == NOSLIP:
+        if is_wall(g.bc[d]):
             sl = [slice(None)] * 3
             sl[d] = 0
             ud[tuple(sl)] = 0.0
         up = np.roll(ud, -1, axis=d)
-        if g.bc[d] == NOSLIP:
+        if is_wall(g.bc[d]):
             sl = [slice(None)] * 3
             sl[d] = g.n[d] - 1
             up[tuple(sl)] = 0.0

@@ -4,7 +4,7 @@ Sec. 4.2 factorises L once with the direct method of Lynch et al.: L is a sum
 of Kronecker products of 1-D second-difference matrices, each diagonalised by
 its own eigenbasis.  On a uniform grid those eigenbases are known in closed
 form: the discrete Fourier basis on a periodic axis and the DCT-II basis on a
-Neumann axis (the pressure axis between two no-slip walls).  The 1-D
+Neumann axis (the pressure axis between two walls of either kind).  The 1-D
 eigenvalues are (4/h^2) sin^2(pi k / n) and (4/h^2) sin^2(pi k / (2n)).
 
 The zero eigenvalue (constants) is mapped to zero: the result is the

@@ -12,10 +12,10 @@ from oracle import mac
 from oracle import step as ostep
 from paper_2501_15314_amd import workloads as wl
 
-P, W_ = mac.PERIODIC, mac.NOSLIP
+P, W_, F_ = mac.PERIODIC, mac.NOSLIP, mac.FREESLIP
 
 
-@pytest.mark.parametrize("bc", [(P, P, P), (W_, W_, W_), (W_, P, P), (P, W_, W_)])
+@pytest.mark.parametrize("bc", [(P, P, P), (W_, W_, W_), (W_, P, P), (P, W_, W_), (F_, F_, W_)])
 def test_convection_jacobian_polarization(bc):
     """N is quadratic with N(0) = 0, so J(u) v = N(u + v) - N(u) - N(v)."""
     g = mac.Grid((6, 8, 10), 0.125, bc)

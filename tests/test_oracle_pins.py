@@ -14,7 +14,7 @@ from oracle import delta, mac, poisson, schur
 from oracle import step as ostep
 from paper_2501_15314_amd import workloads as wl
 
-P, W_ = mac.PERIODIC, mac.NOSLIP
+P, W_, F_ = mac.PERIODIC, mac.NOSLIP, mac.FREESLIP
 
 
 def _grid(n, bc, L=1.0):
@@ -32,7 +32,8 @@ def _basis_1d(n, bc, k):
     return np.cos(np.pi * k * (i + 0.5) / n)        # DCT-II
 
 
-@pytest.mark.parametrize("bc", [(P, P, P), (W_, W_, W_), (P, W_, P), (W_, P, W_)])
+@pytest.mark.parametrize("bc", [(P, P, P), (W_, W_, W_), (P, W_, P), (W_, P, W_), (F_, F_, F_),
+                                (P, F_, W_)])
 def test_laplacian_symbol(bc):
     g = _grid((6, 8, 10), bc)
     L = mac.laplacian(g)
@@ -53,12 +54,15 @@ def test_lap_symbol_closed_form_values():
     assert np.allclose(e, [0.0, 2.0])
 
 
-@pytest.mark.parametrize("bc", [(P, P, P), (W_, W_, W_), (W_, P, W_)])
+@pytest.mark.parametrize("bc", [(P, P, P), (W_, W_, W_), (W_, P, W_), (F_, F_, F_), (F_, P, W_),
+                                (W_, F_, F_)])
 def test_momentum_operator_symbol(bc):
     """A = 3/(2dt) - nu Delta_h on each face grid.  Eigenvectors per axis:
     periodic Fourier; tangential no-slip (ghost = -u): DST-II with eigenvalue
-    (4/h^2) sin^2(pi (k+1)/(2n)); normal no-slip (Dirichlet on faces 0, n):
-    DST-I on faces 1..n-1 with eigenvalue (4/h^2) sin^2(pi k/(2n))."""
+    (4/h^2) sin^2(pi (k+1)/(2n)); tangential free-slip (ghost = +u): DCT-II
+    with eigenvalue (4/h^2) sin^2(pi k/(2n)), k = 0 included (a uniform
+    tangential flow is not damped); normal wall of either kind (Dirichlet on
+    faces 0, n): DST-I on faces 1..n-1 with eigenvalue (4/h^2) sin^2(pi k/(2n))."""
     g = _grid((6, 8, 6), bc)
     nu, dt = 0.03, 0.01
     A = mac.helmholtz(g, nu, dt)
@@ -77,6 +81,10 @@ def test_momentum_operator_symbol(bc):
                     k = rng.integers(1, n)
                     vecs.append(np.sin(np.pi * k * i / n))
                     lam += 4 / g.h ** 2 * np.sin(np.pi * k / (2 * n)) ** 2
+                elif bc[a] == F_:
+                    k = rng.integers(0, n) if _ else 0
+                    vecs.append(np.cos(np.pi * k * (i + 0.5) / n))
+                    lam += 4 / g.h ** 2 * np.sin(np.pi * k / (2 * n)) ** 2
                 else:
                     k = rng.integers(0, n)
                     vecs.append(np.sin(np.pi * (k + 1) * (i + 0.5) / n))
@@ -91,7 +99,7 @@ def test_momentum_operator_symbol(bc):
 # --------------------------------------------------------------------------
 # P2 / P16: G, D, L consistency and a second formulation
 
-@pytest.mark.parametrize("bc", [(P, P, P), (W_, W_, W_), (P, W_, W_)])
+@pytest.mark.parametrize("bc", [(P, P, P), (W_, W_, W_), (P, W_, W_), (F_, P, W_), (F_, F_, F_)])
 def test_sparse_vs_stencil(bc):
     g = _grid((5, 6, 8), bc)
     rng = np.random.default_rng(2)
@@ -254,8 +262,9 @@ def test_interpolation_consistency_and_adjoint():
     assert abs(lhs - rhs) < 1e-14 * abs(lhs) * 100
 
 
-def test_support_crossing_wall_rejected():
-    g = _grid(16, (W_, W_, W_))
+@pytest.mark.parametrize("bc", [(W_, W_, W_), (F_, P, P)])
+def test_support_crossing_wall_rejected(bc):
+    g = _grid(16, bc)
     with pytest.raises(ValueError):
         delta.regularization_matrix(g, np.array([[0.05, 0.5, 0.5]]), delta.PESKIN4)
     delta.regularization_matrix(g, np.array([[0.2, 0.5, 0.5]]), delta.PESKIN4)
