@@ -24,8 +24,9 @@
  *   grid field       [n0][n1][n2], axis 2 contiguous; cell (i,j,k) is centred
  *                    at ((i+1/2)h, (j+1/2)h, (k+1/2)h)
  *   velocity comp d  [n0][n1][n2]; index (i,j,k) is the face of cell (i,j,k)
- *                    lower along axis d; on a no-slip axis d the index-0 face
- *                    is the wall and always holds 0 (the far wall is implicit)
+ *                    lower along axis d; on a wall axis d (either kind) the
+ *                    index-0 face is the wall and always holds 0 (the far
+ *                    wall is implicit)
  *   face field       [3][n0][n1][n2] (components u, v, w one after another)
  *   point arrays     [K][3], bodies one after another in sim_set_bodies order
  *
@@ -63,7 +64,12 @@ typedef enum {
   SIM_ENOMEM = -6       /* workspace too small */
 } sim_status;
 
-enum { SIM_BC_PERIODIC = 0, SIM_BC_NOSLIP = 1 };
+/* Boundary condition per axis.  Both wall kinds hold zero normal velocity
+ * and give the pressure Laplacian a Neumann end.  NOSLIP: zero tangential
+ * velocity at the wall (ghost value -u half a cell beyond it).  FREESLIP:
+ * zero normal derivative of the tangential velocity (ghost value +u), the
+ * box condition of the sedimentation runs of Sec. 6.1.3. */
+enum { SIM_BC_PERIODIC = 0, SIM_BC_NOSLIP = 1, SIM_BC_FREESLIP = 2 };
 enum { SIM_DELTA_PESKIN4 = 0, SIM_DELTA_ROMA3 = 1 };
 /* FP64: every kernel in float64.  FP32MG: the V-cycle and the momentum
  * relaxations run in float32 inside float64 outer iterations. */
@@ -73,7 +79,8 @@ enum { SIM_MOTION_PRESCRIBED = 0, SIM_MOTION_FREE = 1 };
  * FASTDIAG: L^+ by fast diagonalisation of the whole grid (the direct method
  * of paper Sec. 4.2): six batched eigenbasis transforms on the matrix cores
  * with bfloat16 operands and float32 accumulation; every n[d] a multiple of
- * 8, at most 512 (else sim_create returns SIM_EINVAL). */
+ * 8, at most 512 (else sim_create returns SIM_EINVAL).  It builds no
+ * multigrid hierarchy, so the mg_* fields and their size rules do not apply. */
 enum { SIM_PRECOND_VCYCLE = 0, SIM_PRECOND_FASTDIAG = 1 };
 /* FGMRES: flexible GMRES(krylov_restart) with classical Gram-Schmidt.
  * BICGSTAB: right-preconditioned BiCGStab (the Krylov method the paper pairs
@@ -171,7 +178,7 @@ sim_status sim_destroy(sim_t sim);
  * frame (paper Sec. 2.1, the radius vector L~).  Places the points at the
  * current time (Sec. 2.2: X_k = X_c + R X~_k), computes their velocities
  * (eq. kinematic_constraint) and sorts them into tiles.  SIM_EINVAL if K
- * exceeds max_points or a kernel support crosses a no-slip wall (Appendix B). */
+ * exceeds max_points or a kernel support crosses a wall (Appendix B). */
 sim_status sim_set_bodies(sim_t sim, int32_t nb, const sim_body *bodies,
                           const double *offsets);
 
@@ -192,7 +199,7 @@ sim_status sim_get_fields(sim_t sim, double *d_u, double *d_v, double *d_w, doub
  * the host (eqs. bdy_linear_vel_iter, bdy_angular_vel_iter) -> point
  * velocities -> pressure-force correction relaxed by xi} outer_iters times or
  * until ||Phi'||_1 / ||Phi||_1 < outer_tol (eq. convergence_criterion).
- * Errors: SIM_EINVAL if a kernel support would cross a no-slip wall,
+ * Errors: SIM_EINVAL if a kernel support would cross a wall,
  * SIM_ENONFINITE, SIM_ENOTCONV (the step is still completed).  stats (may be
  * NULL) describe the last step. */
 sim_status sim_step(sim_t sim, int32_t nsteps, sim_step_stats *stats);

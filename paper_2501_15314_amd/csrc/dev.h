@@ -20,12 +20,19 @@ namespace ibs {
 struct Geo {
   int n0, n1, n2, hn2;
   long long half;   // n0*n1*hn2
-  int bc0, bc1, bc2;  // 0 periodic, 1 no-slip (Neumann for cell fields)
+  int bc0, bc1, bc2;  // 0 periodic, 1 no-slip wall, 2 free-slip wall (Neumann for cell fields)
   double h, h2;     // cell width and its square
 };
 
 __host__ __device__ inline int geo_n(const Geo &g, int a) { return a == 0 ? g.n0 : (a == 1 ? g.n1 : g.n2); }
 __host__ __device__ inline int geo_bc(const Geo &g, int a) { return a == 0 ? g.bc0 : (a == 1 ? g.bc1 : g.bc2); }
+
+// Change of the viscous 7-point diagonal (in units of 1/h^2, on top of the
+// centre's 2 per axis) for each missing tangential neighbour beyond a wall:
+// the ghost value is -u on a no-slip wall (+1) and +u on a free-slip wall
+// (-1).  Both wall kinds hold zero normal velocity, so every other operator
+// only asks whether an axis is a wall (bc != 0).
+__host__ __device__ inline int wall_ghost_diag(int bc) { return bc == 1 ? 1 : -1; }
 
 __device__ __forceinline__ long long sidx(const Geo &g, int i, int j, int k) {
   return (long long)((i + j + k) & 1) * g.half + ((long long)i * g.n1 + j) * g.hn2 + (k >> 1);

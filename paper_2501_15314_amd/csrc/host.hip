@@ -154,7 +154,8 @@ std::string validate(const sim_config *c, std::vector<int> *dims) {
   if (!c) return "null config";
   for (int a = 0; a < 3; ++a) {
     if (c->n[a] < 16 || c->n[a] % 4) return "every n must be a multiple of 4 and >= 16";
-    if (c->bc[a] != SIM_BC_PERIODIC && c->bc[a] != SIM_BC_NOSLIP) return "bad bc";
+    if (c->bc[a] != SIM_BC_PERIODIC && c->bc[a] != SIM_BC_NOSLIP && c->bc[a] != SIM_BC_FREESLIP)
+      return "bad bc";
     if (!(c->len[a] > 0)) return "len must be positive";
   }
   double h0 = c->len[0] / c->n[0];
@@ -172,15 +173,18 @@ std::string validate(const sim_config *c, std::vector<int> *dims) {
   if (c->krylov != SIM_KRYLOV_FGMRES && c->krylov != SIM_KRYLOV_BICGSTAB) return "bad krylov method";
   if (c->outer_iters < 1) return "outer_iters must be >= 1";
   if (c->helm_maxit < 1 || !(c->helm_rtol > 0)) return "helm_maxit >= 1 and helm_rtol > 0";
-  // multigrid hierarchy: halve while above mg_coarsest or too big for the coarse kernel
+  // multigrid hierarchy: halve while above mg_coarsest or too big for the
+  // coarse kernel.  The fast-diagonalisation preconditioner never runs a
+  // V-cycle, so it keeps the fine level only and takes no multigrid limits.
   int n0 = c->n[0], n1 = c->n[1], n2 = c->n[2];
   if (dims) dims->clear();
   if (dims) { dims->push_back(n0); dims->push_back(n1); dims->push_back(n2); }
   // exact coarse solves (mg_coarse_sweeps = 0) take any coarsest grid: small
   // ones in one LDS workgroup, larger ones on the matrix cores
-  const bool exact = c->mg_coarse_sweeps == 0;
-  while ((std::max(n0, std::max(n1, n2)) > c->mg_coarsest ||
-          (!exact && (long long)n0 * n1 * n2 > coarse_max_cells()))) {
+  const bool fdg = c->precond == SIM_PRECOND_FASTDIAG;
+  const bool exact = fdg || c->mg_coarse_sweeps == 0;
+  while (!fdg && (std::max(n0, std::max(n1, n2)) > c->mg_coarsest ||
+                  (!exact && (long long)n0 * n1 * n2 > coarse_max_cells()))) {
     if (!is_even(n0) || !is_even(n1) || !is_even(n2) || n0 < 4 || n1 < 4 || n2 < 4) break;
     n0 /= 2; n1 /= 2; n2 /= 2;
     if (dims) { dims->push_back(n0); dims->push_back(n1); dims->push_back(n2); }
@@ -357,13 +361,13 @@ void prescribed_state(const sim_body &b, double t, double c[3], double v[3], dou
   }
 }
 
-// The support of every point stays on interior nodes of no-slip axes
-// (Appendix B); checked with each body's bounding sphere.
+// The support of every point stays on interior nodes of wall axes of either
+// kind (Appendix B); checked with each body's bounding sphere.
 bool supports_inside(sim_t s, const std::vector<BodyDev> &bd) {
   double margin = (s->ker == SIM_DELTA_PESKIN4 ? 2.0 : 1.5) * s->g.h;
   for (size_t i = 0; i < bd.size(); ++i) {
     for (int a = 0; a < 3; ++a) {
-      if (s->cfg.bc[a] != SIM_BC_NOSLIP) continue;
+      if (s->cfg.bc[a] == SIM_BC_PERIODIC) continue;
       double lo = bd[i].c[a] - s->bodies[i].rmax, hi = bd[i].c[a] + s->bodies[i].rmax;
       if (lo < margin || hi > s->cfg.len[a] - margin) return false;
     }
@@ -374,7 +378,7 @@ bool supports_inside(sim_t s, const std::vector<BodyDev> &bd) {
 // Place the points of all bodies from the given body states and bin them.
 sim_status place_and_bin(sim_t s, const std::vector<BodyDev> &bd) {
   if (!supports_inside(s, bd))
-    return fail(s, SIM_EINVAL, "delta-kernel support of a body crosses a no-slip wall");
+    return fail(s, SIM_EINVAL, "delta-kernel support of a body crosses a wall");
   hipStream_t st = s->st;
   CKH(hipMemcpyAsync(s->BODIES, bd.data(), sizeof(BodyDev) * bd.size(), hipMemcpyHostToDevice, st));
   CKH(points_place(s->g, s->K, s->BODIES, s->BODYOF, s->OFF, s->XN, s->UN, s->TILE, s->nt0, s->nt1, s->nt2, st));
@@ -843,7 +847,9 @@ sim_status schur_solve_core(sim_t s, sim_solve_stats *stt) {
 // interior diagonal a0 + 6 nu/h^2 and red-black ordering makes it consistently
 // ordered, so with rho_J = (6 nu/h^2) / (a0 + 6 nu/h^2) the SOR factor
 // omega = 2 / (1 + sqrt(1 - rho_J^2)) contracts the error by omega - 1 per
-// sweep (boundary rows only add diagonal weight).
+// sweep (boundary rows have no larger Jacobi row ratio: a no-slip ghost adds
+// diagonal weight, a free-slip ghost removes an off-diagonal together with
+// its share of the diagonal, so rho_J still bounds the Jacobi spectrum).
 template <typename T>
 sim_status helm_solve(sim_t s, const double *rhs, double *u, sim_solve_stats *stt) {
   hipStream_t st = s->st;

@@ -110,7 +110,7 @@ struct BodyDev {
 // ---- two-way coupling sums (kernels_body.hip) ------------------------------
 // Per body: its point range in natural order and the node box that holds
 // every velocity node with a non-zero volume fraction (lo may lie outside the
-// grid; periodic axes wrap, no-slip axes clip).
+// grid; periodic axes wrap, wall axes clip).
 struct BodySpan {
   int k0, kn;
   double c[3];

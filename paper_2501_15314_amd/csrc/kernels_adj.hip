@@ -4,7 +4,7 @@
 //       out_{k,e} += scale sum_d b_{k,d} sum_i a_d(x_i) dw_ik/dX_{k,e},
 //     dw/dX_e = phi'(r_e)/h phi(r_f) phi(r_g) (Sec. 2.3 weights, r in cells);
 //   * convection_adjoint: J_N(u)^T r for the flux form of N(u) = div(u u)
-//     (arithmetic averages, no flux through no-slip walls), written as a
+//     (arithmetic averages, no flux through walls of either kind), written as a
 //     gather: after summation by parts r^T N = sum over flux points of
 //     F(x) psi(x), psi the difference of r across the flux point, and each
 //     face collects dF/du psi from the flux points whose averages contain it.
@@ -75,7 +75,7 @@ __global__ void k_interp_dx(Geo g, int K, const double *X, const double *a3, con
   for (int e = 0; e < 3; ++e) out[3 * k + e] += scale * ge[e];
 }
 
-// F_{a,d}(x) is zero through a no-slip wall: x_a = n_a - 1 on a no-slip axis a.
+// F_{a,d}(x) is zero through a wall: x_a = n_a - 1 on a wall axis a.
 __device__ __forceinline__ bool flux_open(const Geo &g, int a, const int x[3]) {
   return !(geo_bc(g, a) && x[a] == geo_n(g, a) - 1);
 }

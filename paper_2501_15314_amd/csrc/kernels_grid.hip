@@ -4,10 +4,11 @@
 // A = 3/(2 dt) - nu Delta_h and its red-black relaxation (eq. ustar), the
 // explicit convection term and the momentum right-hand side.
 //
-// Boundary rules (MAC grid): on a no-slip axis d the index-0 face of velocity
+// Boundary rules (MAC grid): on a wall axis d the index-0 face of velocity
 // component d is the wall (always 0) and the far wall is implicit; the
 // pressure Laplacian is Neumann there; a tangential velocity's neighbour
-// beyond a wall is the ghost value -u.
+// beyond a wall is the ghost value -u on a no-slip wall and +u on a
+// free-slip wall.
 #include "internal.h"
 #include "march.h"
 
@@ -182,8 +183,9 @@ hipError_t zero_wall_faces(const Geo &g, double *u3, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Momentum operator on the component-d face grid.  Per axis a the second
 // difference has diagonal weight 2 (periodic, or normal-to-wall where the
-// wall faces 0 and n hold 0), or 2 plus 1 per missing neighbour for a
-// tangential wall (ghost value -u).  nb = sum of the existing neighbours.
+// wall faces 0 and n hold 0); for a tangential wall each missing neighbour
+// adds 1 (no-slip, ghost value -u) or removes 1 (free-slip, ghost value +u).
+// nb = sum of the existing neighbours.
 template <typename T>
 __device__ __forceinline__ void helm_stencil(const Geo &g, const T *ud, int d, int i, int j, int k,
                                              T &nb, int &diag) {
@@ -206,7 +208,7 @@ __device__ __forceinline__ void helm_stencil(const Geo &g, const T *ud, int d, i
         diag += 1;
       } else {
         valid = (y >= 0) && (y <= n - 1);
-        diag += valid ? 1 : 2;
+        diag += valid ? 1 : 1 + wall_ghost_diag(bc);
       }
       if (valid) {
         int ii = a == 0 ? y : i, jj = a == 1 ? y : j, kk = a == 2 ? y : k;
@@ -315,7 +317,7 @@ template hipError_t cast_copy<double>(double *, const double *, long long, hipSt
 
 // ---------------------------------------------------------------------------
 // Convection div(u u) at a component-d face, divergence form with arithmetic
-// averages; fluxes through no-slip walls vanish.
+// averages; fluxes through walls (either kind) vanish.
 __device__ double conv_at(const Geo &g, const double *u3, int d, int i, int j, int k) {
   long long N = 2 * g.half;
   const double *ud = u3 + d * N;

@@ -245,7 +245,7 @@ __global__ void __launch_bounds__(256) k_interp(Geo g, int nt1, int nt2, const i
       int l0 = i0 - org[ax];
       if (!bcs[ax]) l0 = wrapi(l0 + nn[ax] / 2, nn[ax]) - nn[ax] / 2;
       pb[pt][ax][st] = l0;
-      // a wall face (index 0 along a no-slip axis) carries no gradient: zero its weight
+      // a wall face (index 0 along a wall axis) carries no gradient: zero its weight
 #pragma unroll
       for (int t = 0; t < 4; ++t)
         pw[pt][ax][st][t] = (MODE == 1 && st == 0 && bcs[ax] && i0 + t == 0) ? 0.0 : wv[t];

@@ -209,7 +209,8 @@ namespace ibs {
 //   SW_HELM:    SOR for A = a0 - nu Delta_h on velocity component `comp`:
 //               x_c += omega ((b_c + nu/h^2 sum) / (a0 + nu/h^2 diag) - x_c),
 //               wall faces untouched.  Neighbours outside a wall box are 0
-//               (normal walls hold 0, tangential ghosts enter the diagonal).
+//               (normal walls hold 0, tangential ghosts enter the diagonal:
+//               -u on a no-slip wall, +u on a free-slip wall).
 enum { SW_POISSON = 0, SW_FIRST = 1, SW_HELM = 2 };
 
 template <typename T, typename TB, int MODE>
@@ -295,7 +296,7 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, T *x, const TB *b, int col
         for (int a = 0; a < 3; ++a) {
           int bca = geo_bc(g, a), na = geo_n(g, a);
           diag += 2;
-          if (bca && a != d) diag += (xs[a] == 0) + (xs[a] == na - 1);
+          if (bca && a != d) diag += wall_ghost_diag(bca) * ((xs[a] == 0) + (xs[a] == na - 1));
         }
         T xv = u ? xo.y : xo.x;
         const int xd = d == 0 ? i : (d == 1 ? p.j : k);
@@ -422,7 +423,7 @@ __global__ void __launch_bounds__(256) k_apply2(Geo g, const T *x, const double 
           for (int a = 0; a < 3; ++a) {
             int bca = geo_bc(g, a), na = geo_n(g, a);
             diag += 2;
-            if (bca && a != d) diag += (xs[a] == 0) + (xs[a] == na - 1);
+            if (bca && a != d) diag += wall_ghost_diag(bca) * ((xs[a] == 0) + (xs[a] == na - 1));
           }
           const int xd = d == 0 ? i : (d == 1 ? p.j : k);
           bool wall = geo_bc(g, d) && xd == 0;

@@ -34,6 +34,16 @@ def walls_workload(n=32, pts=260, seed=3):
     return wl.make_c3(seed=seed, n=n, points_per_sphere=pts)
 
 
+def freeslip_workload(n=32, pts=260, seed=3):
+    """The wall-bounded spheres of walls_workload in a box with free-slip
+    walls normal to x and y and no-slip walls normal to z, so that both
+    ghost rules of the viscous stencil meet in one grid."""
+    w = walls_workload(n, pts, seed)
+    w.cfg.bc = (wl.BC_FREESLIP, wl.BC_FREESLIP, wl.BC_NOSLIP)
+    w.name = w.name.replace("noslip", "freeslip_xy_noslip_z")
+    return w
+
+
 def mixed_workload(seed=12):
     """Non-cubic grid (16 x 24 x 32 cells of width 1/32), no-slip along x only,
     two spheres."""
@@ -81,8 +91,8 @@ def free_workload(n=32, bc=wl.BC_PERIODIC, seed=21, precision=wl.PREC_FP64, xi=0
         u0 = wl.solenoidal_field(rng, (n, n, n), h, 0.05)
     else:
         u0 = np.zeros((3, n, n, n))
-    return wl.Workload(f"free_{n}_{'periodic' if bc == wl.BC_PERIODIC else 'walls'}", cfg, bodies, off,
-                       u0, steps=2, seed=seed)
+    kind = {wl.BC_PERIODIC: "periodic", wl.BC_NOSLIP: "walls", wl.BC_FREESLIP: "freeslip"}[bc]
+    return wl.Workload(f"free_{n}_{kind}", cfg, bodies, off, u0, steps=2, seed=seed)
 
 
 def oracle_free_bodies(w: wl.Workload):

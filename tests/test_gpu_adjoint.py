@@ -10,7 +10,7 @@ from oracle import step as ostep
 from paper_2501_15314_amd import workloads as wl
 
 from .conftest import gpu_available
-from .gpu_helpers import prescribed_points, rel, walls_workload
+from .gpu_helpers import freeslip_workload, prescribed_points, rel, walls_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -24,7 +24,7 @@ def _case(name, prec):
     if name == "c4_32":
         w = wl.scaled(wl.make_c4, 32)
     else:
-        w = walls_workload(32, 200)
+        w = walls_workload(32, 200) if name == "walls" else freeslip_workload(32, 200)
         w.bodies = w.bodies[:3]
         w.offsets = w.offsets[:600]
         w.bodies[1].omega = np.array([0.0, 1.5, -0.5])
@@ -55,7 +55,7 @@ def _gpu(w, state, ybar):
     return sim, res
 
 
-@pytest.mark.parametrize("name", ["c4_32", "walls"])
+@pytest.mark.parametrize("name", ["c4_32", "walls", "freeslip"])
 @pytest.mark.parametrize("prec", [wl.PREC_FP64, wl.PREC_FP32MG])
 def test_step_adjoint_matches_oracle(name, prec):
     w, g, state, ybar = _case(name, prec)

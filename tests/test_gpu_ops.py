@@ -7,7 +7,7 @@ from oracle import mac as omac
 from paper_2501_15314_amd import workloads as wl
 
 from .conftest import gpu_available
-from .gpu_helpers import mixed_workload, oracle_for, rel, walls_workload
+from .gpu_helpers import freeslip_workload, mixed_workload, oracle_for, rel, walls_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -20,10 +20,11 @@ def _cases():
         "c1_periodic": lambda: wl.make_c1(n=32, n_points=300),
         "walls": lambda: walls_workload(32, 260),
         "mixed": mixed_workload,
+        "freeslip": freeslip_workload,
     }
 
 
-@pytest.fixture(scope="module", params=["c1_periodic", "walls", "mixed"])
+@pytest.fixture(scope="module", params=["c1_periodic", "walls", "mixed", "freeslip"])
 def setup(request):
     w = _cases()[request.param]()
     w.cfg.precision = wl.PREC_FP64

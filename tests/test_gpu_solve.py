@@ -9,7 +9,7 @@ from oracle import step as ostep
 from paper_2501_15314_amd import workloads as wl
 
 from .conftest import gpu_available
-from .gpu_helpers import mixed_workload, oracle_for, rel, walls_workload
+from .gpu_helpers import freeslip_workload, mixed_workload, oracle_for, rel, walls_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -22,6 +22,7 @@ CASES = {
     "walls": lambda: walls_workload(32, 260),
     "mixed": mixed_workload,
     "c1_48_roma": lambda: _roma(wl.make_c1(n=48, n_points=700)),
+    "freeslip": freeslip_workload,
 }
 
 
@@ -156,8 +157,10 @@ def test_bicgstab_notconv_reports_best_iterate():
     sim.close()
 
 
-def test_support_crossing_wall_rejected():
+@pytest.mark.parametrize("bc", [wl.BC_NOSLIP, wl.BC_FREESLIP])
+def test_support_crossing_wall_rejected(bc):
     w = walls_workload(32, 260)
+    w.cfg.bc = (bc,) * 3
     w.bodies[0].center = np.array([0.07, 0.5, 0.5])
     sim = Sim(w.cfg, w.n_points)
     with pytest.raises(SimError) as e:
@@ -189,7 +192,7 @@ def _oracle_step(w, state, t1):
     return ostep.one_way_step(g, cfg.nu, cfg.dt, state, X, U, cfg.delta, cfg.lump_c, cfg.xi)
 
 
-@pytest.mark.parametrize("case", ["c1_periodic", "walls", "mixed"])
+@pytest.mark.parametrize("case", ["c1_periodic", "walls", "mixed", "freeslip"])
 @pytest.mark.parametrize("prec", [wl.PREC_FP64, wl.PREC_FP32MG])
 def test_one_way_steps_match_oracle(case, prec):
     w = CASES[case]()
@@ -197,7 +200,7 @@ def test_one_way_steps_match_oracle(case, prec):
     cfg.precision = prec
     cfg.krylov_rtol = 1e-12 if prec == wl.PREC_FP64 else 1e-11
     cfg.helm_rtol = 1e-12 if prec == wl.PREC_FP64 else 1e-11
-    if case == "walls":
+    if case in ("walls", "freeslip"):
         rng = np.random.default_rng(5)
         mask = omac.Grid(cfg.n, cfg.h, cfg.bc).face_dof_mask()
         w.u0 = rng.standard_normal(w.u0.shape) * 1e-2 * mask

@@ -25,7 +25,7 @@ def _body_err(gpu_state, bodies):
     return e
 
 
-@pytest.mark.parametrize("bc", [wl.BC_PERIODIC, wl.BC_NOSLIP])
+@pytest.mark.parametrize("bc", [wl.BC_PERIODIC, wl.BC_NOSLIP, wl.BC_FREESLIP])
 @pytest.mark.parametrize("prec", [wl.PREC_FP64, wl.PREC_FP32MG])
 def test_two_way_steps_match_oracle(bc, prec):
     w = free_workload(32, bc, precision=prec)
