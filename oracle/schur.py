@@ -97,3 +97,32 @@ def exact_schur_dense(G: np.ndarray, W: np.ndarray):
     B = W.T @ G
     Sp = L + B.T @ np.linalg.solve(C, B)
     return L, Sp, C
+
+
+def preconditioned_spectrum(sys: SchurSystem, exact: bool, workers=None):
+    """Eigenvalues of L^+ S on mean-zero pressures, the quantity bounded by
+    the theorem of Sec. 5 and measured in Sec. 6.2: S = S~ = L + c^-1 B^T B
+    (exact = False) or S_p = L + B^T C^-1 B with C = W^T W (exact = True).
+
+    L^+ S = I + L^+ B^T M B with M = I/c or C^-1, and a product of two
+    matrices has the same nonzero eigenvalues in either order, so apart from
+    the eigenvalue 1 (on the mean-zero vectors that B annihilates) the
+    spectrum is 1 + eig(M K) with the 3K x 3K matrix K = B L^+ B^T, formed
+    column by column with the exact Poisson solve.  Returns those 3K values,
+    ascending (the remaining eigenvalues are all 1)."""
+    g = sys.g
+    m = sys.W.shape[1]
+    K = np.empty((m, m))
+    for i in range(m):
+        e = np.zeros(m)
+        e[i] = 1.0
+        z = poisson.solve_laplacian(g, sys.BT(e.reshape(-1, 3)), workers)
+        K[:, i] = sys.B(z).ravel()
+    K = 0.5 * (K + K.T)
+    if exact:
+        import scipy.linalg as sla
+        C = (sys.W.T @ sys.W).toarray()
+        ev = sla.eigh(K, C, eigvals_only=True)
+    else:
+        ev = np.linalg.eigvalsh(K) / sys.c
+    return 1.0 + np.sort(ev)

@@ -396,6 +396,29 @@ def test_spectral_theorem_bounds():
 # --------------------------------------------------------------------------
 # P9 / P10: one-way step properties, flat iteration counts
 
+@pytest.mark.parametrize("bc", [(P, P, P), (W_, F_, W_)])
+def test_preconditioned_spectrum_matches_dense(bc):
+    """The reduced 3K x 3K form of spec(L^+ S) equals the dense spectrum of
+    the mean-zero pencil: 1 with multiplicity N - 1 - 3K and the 3K reduced
+    values, for the lumped and for the exact primal Schur complement."""
+    g, X, Wm, c = _small_system(8, bc, 30, delta.ROMA3)
+    sysm = schur.SchurSystem(g, Wm, c)
+    G = mac.gradient(g).toarray()
+    Wd = Wm.toarray()
+    L, Sp, C = schur.exact_schur_dense(G, Wd)
+    N = g.N
+    Q, _ = np.linalg.qr(np.eye(N)[:, 1:] - 1.0 / N)
+    Lq = Q.T @ L @ Q
+    for exact, S in ((True, Sp), (False, L + G.T @ Wd @ Wd.T @ G / c)):
+        dense = np.sort(np.linalg.eigvals(np.linalg.solve(Lq, Q.T @ S @ Q)).real)
+        red = schur.preconditioned_spectrum(sysm, exact)
+        m = red.size
+        assert np.allclose(dense[-m:], red, rtol=0, atol=1e-9)
+        assert np.allclose(dense[:-m], 1.0, rtol=0, atol=1e-9)
+        if exact:
+            assert red.min() > 1 - 1e-9 and red.max() < 2 + 1e-9
+
+
 def test_one_way_step_divergence_free_and_slip():
     w = wl.make_c1(n=16, n_points=80)
     cfg = w.cfg
