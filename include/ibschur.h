@@ -267,7 +267,7 @@ sim_status sim_step_adjoint(sim_t sim, const double *d_gu, const double *d_gv,
  *   SIM_OP_SCHUR_EXACT   cells -> cells      S_p = L + B^T (W^T W)^-1 B, the primal Schur
  *                        complement before lumping (paper Sec. 4.1; the operator of the
  *                        spectral theorem of Sec. 5), (W^T W)^-1 by conjugate gradients
- *                        on the device to 1e-13 (SIM_ENOTCONV if that fails)
+ *                        on the device to 1e-13 within 2000 iterations (else SIM_ENOTCONV)
  *                        (in = rhs_p, in2 = rhs_f)
  * Precision follows cfg.precision where the operator has a mixed form. */
 enum {
@@ -277,6 +277,32 @@ enum {
 };
 sim_status sim_apply(sim_t sim, int32_t op, const double *d_in, const double *d_in2,
                      double *d_out);
+
+/* Spectrum of the Laplacian-preconditioned Schur operator L^+ S on mean-free
+ * pressures for the current point set: S = S~ = L + c^-1 B^T B (exact = 0,
+ * the lumped operator the Krylov solve inverts, Sec. 4.1) or the primal
+ * Schur complement S_p = L + B^T (W^T W)^-1 B (exact != 0, as in
+ * SIM_OP_SCHUR_EXACT).  The theorem of Sec. 5 bounds spec(L^+ S_p) by
+ * [1, 2]; Sec. 6.2 measures the extremes for both operators.
+ * Method: Lanczos on the pencil (S, L) in the L inner product, `steps`
+ * steps (1..1024) from the start vector d_v0 ([n0][n1][n2] on the device,
+ * not modified; its mean is removed).  Each step applies S once and solves
+ * L w = S v by flexible conjugate gradients preconditioned with the
+ * configured preconditioner to relative residual lap_rtol (0 < lap_rtol < 1).
+ * Outputs (host, any may be NULL): alpha[steps] and beta[steps], the
+ * tridiagonal Lanczos matrix T (beta[0] = L-norm of the mean-free start
+ * vector, beta[j] couples rows j-1 and j); *steps_done, the order of T (less
+ * than steps if an invariant subspace was found); *lmin, *lmax, the extreme
+ * eigenvalues of T, which lie inside the extremes of spec(L^+ S) and
+ * approach them as the step count grows.
+ * Uses the solver's work fields only (the state u, p, Phi is kept) and
+ * invalidates the record of sim_step_adjoint.  Errors: SIM_ESTATE without
+ * bodies; SIM_EINVAL for bad arguments or a start vector without mean-free
+ * part; SIM_ENOTCONV if an inner solve (the Laplacian, or W^T W for the
+ * exact operator) misses its tolerance; SIM_ENONFINITE. */
+sim_status sim_schur_spectrum(sim_t sim, int32_t exact, const double *d_v0, int32_t steps,
+                              double lap_rtol, double *alpha, double *beta, int32_t *steps_done,
+                              double *lmin, double *lmax);
 
 /* Kernel timing probes (a profiling aid, for throughput / roofline reports).
  * While a probe is enabled, every launch of its kernel class is bracketed by

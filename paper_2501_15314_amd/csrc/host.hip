@@ -1678,7 +1678,7 @@ sim_status exact_schur_matvec(sim_t s, const double *z, double *w, int *cg_iters
   if ((rc = dot(q, q, &q2)) || (rc = dot(r, r, &rr))) return rc;
   if (!isfinite(q2) || !isfinite(rr)) return fail(s, SIM_ENONFINITE, "non-finite Lagrangian vector");
   int it = 0;
-  for (; it < 500 && rr > 1e-26 * q2; ++it) {
+  for (; it < 2000 && rr > 1e-26 * q2; ++it) {
     if ((rc = applyC(pv, ap))) return rc;
     double pap;
     if ((rc = dot(pv, ap, &pap))) return rc;
@@ -1696,6 +1696,124 @@ sim_status exact_schur_matvec(sim_t s, const double *z, double *w, int *cg_iters
   // w += B^T y = D W y
   CKH(band_apply(s->ker, true, g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, y, 1.0, w, st));
   return SIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Spectrum of the Laplacian-preconditioned Schur operator L^+ S (the theorem
+// of Sec. 5 bounds it by [1, 2] for the primal Schur complement; Sec. 6.2
+// measures it for S_p and for the lumped S~).  Lanczos on the pencil (S, L)
+// in the L inner product over mean-free pressures; each step applies S once
+// and solves L w = S v.  An operator-level tool, not part of the time step.
+
+// x = L^+ b for a mean-free cell field b (split layout) by flexible
+// preconditioned conjugate gradients (Polak-Ribiere beta, so that the float32
+// V-cycle or the bfloat16 fast diagonalisation may serve as preconditioner)
+// to ||b - L x|| <= rtol ||b||; x is returned mean-free.  sc: five cell
+// fields of scratch.
+sim_status lap_solve(sim_t s, const double *b, double *x, double rtol, int maxit, double *const sc[5], int *iters) {
+  hipStream_t st = s->st;
+  const Geo &g = s->g;
+  const long long N = s->N;
+  sim_status rc;
+  double *r = sc[0], *zo = sc[1], *zn = sc[2], *p = sc[3], *q = sc[4];
+  auto dot = [&](const double *a, const double *c, double *out) -> sim_status {
+    CKH(dot2(a, c, N, s->PART, st));
+    CKH(finalize(s->PART, red_blocks(), 1, s->RED, st, s->hpin_dev));
+    return read_mirror(s, 1, out);
+  };
+  auto precond = [&](const double *in, double *out) -> sim_status {
+    if (s->fastdiag) {
+      CKH((fd_precond<double, double>(g, in, out, s->FDW1, s->FDW2, s->FDQ, 1.0f, st)));
+    } else if (s->fp32) {
+      if ((rc = vcycle<float, double>(s, in, (float *)s->Z))) return rc;
+      CKH(fill(out, N, 0.0, st));
+      CKH(add_cast<float>(out, (const float *)s->Z, N, st));
+    } else {
+      if ((rc = vcycle<double, double>(s, in, (double *)s->Z))) return rc;
+      CKH(scale_copy(out, (const double *)s->Z, N, 1.0, st));
+    }
+    return project_mean(s, out);
+  };
+  *iters = 0;
+  CKH(fill(x, N, 0.0, st));
+  double bb;
+  if ((rc = dot(b, b, &bb))) return rc;
+  if (!isfinite(bb)) return fail(s, SIM_ENONFINITE, "non-finite right-hand side of the Laplacian solve");
+  if (bb == 0.0) return SIM_OK;
+  // the residual stays mean-free: its constant part (rounding) is outside the
+  // range of L and would stall the stopping test
+  CKH(scale_copy(r, b, N, 1.0, st));
+  if ((rc = project_mean(s, r))) return rc;
+  if ((rc = precond(r, zo))) return rc;
+  CKH(scale_copy(p, zo, N, 1.0, st));
+  double rz, rr = bb;
+  if ((rc = dot(r, zo, &rz))) return rc;
+  const double stop = rtol * rtol * bb;
+  int it = 0;
+  while (it < maxit && rr > stop) {
+    CKH(lap_apply<double>(g, p, q, st));
+    double pq;
+    if ((rc = dot(p, q, &pq))) return rc;
+    if (!(pq > 0.0) || !(rz > 0.0)) {
+      char msg[160];
+      snprintf(msg, sizeof msg, "Laplacian solve broke down (iteration %d: p.Lp = %.3e, r.z = %.3e, |b|^2 = %.3e)",
+               it, pq, rz, bb);
+      return fail(s, SIM_ENONFINITE, msg);
+    }
+    const double alpha = rz / pq;
+    CKH(axpby(x, p, N, alpha, 1.0, st));   // x += alpha p
+    CKH(axpby(r, q, N, -alpha, 1.0, st));  // r -= alpha q
+    if ((rc = project_mean(s, r))) return rc;
+    ++it;
+    if ((rc = dot(r, r, &rr))) return rc;
+    if (rr <= stop) break;
+    if ((rc = precond(r, zn))) return rc;
+    double d2[2];
+    CKH(dots2(r, zn, zo, N, s->PART, st));
+    CKH(finalize(s->PART, red_blocks(), 2, s->RED, st, s->hpin_dev));
+    if ((rc = read_mirror(s, 2, d2))) return rc;
+    const double beta = (d2[0] - d2[1]) / rz;
+    rz = d2[0];
+    CKH(axpby(p, zn, N, 1.0, beta, st));  // p = zn + beta p
+    std::swap(zo, zn);
+  }
+  if ((rc = project_mean(s, x))) return rc;
+  *iters = it;
+  if (!isfinite(rr)) return fail(s, SIM_ENONFINITE, "non-finite residual in the Laplacian solve");
+  if (rr > stop) return fail(s, SIM_ENOTCONV, "Laplacian solve did not reach its tolerance");
+  return SIM_OK;
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix with
+// diagonal a[0..m) and off-diagonal b[1..m) (Sturm sequence of the LDL^T
+// pivots).
+int sturm_below(const double *a, const double *b, int m, double x) {
+  int cnt = 0;
+  double q = a[0] - x;
+  if (q < 0.0) ++cnt;
+  for (int i = 1; i < m; ++i) {
+    const double piv = q != 0.0 ? q : 1e-300;
+    q = a[i] - x - b[i] * b[i] / piv;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// Eigenvalue number idx (0-based, ascending) of the tridiagonal matrix by
+// bisection between its Gershgorin bounds.
+double tridiag_eig(const double *a, const double *b, int m, int idx) {
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? fabs(b[i]) : 0.0) + (i + 1 < m ? fabs(b[i + 1]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  for (int k = 0; k < 200 && hi - lo > 1e-15 * std::max(fabs(lo), fabs(hi)); ++k) {
+    const double mid = 0.5 * (lo + hi);
+    if (sturm_below(a, b, m, mid) > idx) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
 }
 
 sim_status sim_apply(sim_t s, int32_t op, const double *in, const double *in2, double *out) {
@@ -1794,6 +1912,78 @@ sim_status sim_apply(sim_t s, int32_t op, const double *in, const double *in2, d
     default:
       return fail(s, SIM_EINVAL, "unknown operator");
   }
+  return sync(s);
+}
+
+sim_status sim_schur_spectrum(sim_t s, int32_t exact, const double *v0, int32_t steps, double lap_rtol,
+                              double *alpha, double *beta, int32_t *steps_done, double *lmin, double *lmax) {
+  if (!s) return SIM_EINVAL;
+  s->adj_ready = false;
+  if (!v0) return fail(s, SIM_EINVAL, "null start vector");
+  if (steps < 1 || steps > 1024) return fail(s, SIM_EINVAL, "steps must be 1..1024");
+  if (!(lap_rtol > 0.0 && lap_rtol < 1.0)) return fail(s, SIM_EINVAL, "lap_rtol must lie in (0, 1)");
+  if (!s->have_bodies) return fail(s, SIM_ESTATE, "no bodies set");
+  hipStream_t st = s->st;
+  const Geo &g = s->g;
+  const long long N = s->N;
+  sim_status rc;
+  // scratch: the momentum work fields and the cell work fields (no state)
+  double *vp = s->USTAR, *v = s->USTAR + N, *w = s->USTAR + 2 * N, *sv = s->RHSU, *lw = s->RHSU + N;
+  double *const sc[5] = {s->RHSU + 2 * N, s->BVEC, s->RHSP, s->TMPC, s->PP};
+  auto dot = [&](const double *a, const double *c, double *out) -> sim_status {
+    CKH(dot2(a, c, N, s->PART, st));
+    CKH(finalize(s->PART, red_blocks(), 1, s->RED, st, s->hpin_dev));
+    return read_mirror(s, 1, out);
+  };
+  std::vector<double> A(steps, 0.0), Bt(steps + 1, 0.0);
+  CKH(to_split(g, 1, v0, v, st));
+  if ((rc = project_mean(s, v))) return rc;
+  CKH(lap_apply<double>(g, v, lw, st));
+  double b0;
+  if ((rc = dot(v, lw, &b0))) return rc;
+  if (!isfinite(b0)) return fail(s, SIM_ENONFINITE, "non-finite start vector");
+  if (!(b0 > 0.0)) return fail(s, SIM_EINVAL, "start vector has no mean-free part");
+  CKH(scale_inplace(v, N, 1.0 / sqrt(b0), st));
+  CKH(fill(vp, N, 0.0, st));
+  Bt[0] = sqrt(b0);
+  int m = 0;
+  double bj = 0.0;
+  for (int j = 0; j < steps; ++j) {
+    if (exact) {
+      int cg;
+      if ((rc = exact_schur_matvec(s, v, sv, &cg))) return rc;
+    } else if ((rc = schur_matvec<double>(s, v, sv))) {
+      return rc;
+    }
+    double a;
+    if ((rc = dot(v, sv, &a))) return rc;
+    int its;
+    if ((rc = lap_solve(s, sv, w, lap_rtol, 1000, sc, &its))) return rc;
+    // w = L^+ S v - a v - b_j v_prev, kept mean-free: the constant mode has
+    // zero L-norm, so rounding in it would grow by 1/beta every step
+    CKH(lincomb(w, w, 1.0, v, -a, vp, -bj, nullptr, 0, N, nullptr, st));
+    if ((rc = project_mean(s, w))) return rc;
+    CKH(lap_apply<double>(g, w, lw, st));
+    double bn2;
+    if ((rc = dot(w, lw, &bn2))) return rc;
+    if (!isfinite(a) || !isfinite(bn2)) return fail(s, SIM_ENONFINITE, "non-finite Lanczos coefficient");
+    A[j] = a;
+    m = j + 1;
+    // an invariant subspace has been found: T holds exact eigenvalues
+    if (!(bn2 > 1e-28 * a * a)) break;
+    bj = sqrt(bn2);
+    Bt[j + 1] = bj;
+    double *t = vp;
+    vp = v;
+    v = w;
+    w = t;
+    CKH(scale_inplace(v, N, 1.0 / bj, st));
+  }
+  if (alpha) memcpy(alpha, A.data(), sizeof(double) * m);
+  if (beta) memcpy(beta, Bt.data(), sizeof(double) * m);
+  if (steps_done) *steps_done = m;
+  if (lmin) *lmin = tridiag_eig(A.data(), Bt.data(), m, 0);
+  if (lmax) *lmax = tridiag_eig(A.data(), Bt.data(), m, m - 1);
   return sync(s);
 }
 

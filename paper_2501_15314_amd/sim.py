@@ -188,6 +188,21 @@ class Sim:
         self._check(self.lib.sim_apply(self.h, opid, _ptr(x), _ptr(x2), _ptr(out)))
         return out[:self.K] if op == "interp" else out
 
+    def schur_spectrum(self, v0, exact=False, steps=60, lap_rtol=1e-12):
+        """Lanczos estimate of spec(L^+ S) (S = S~, or S_p if exact): dict with
+        the tridiagonal coefficients alpha, beta, its order and the extreme
+        Ritz values lmin, lmax."""
+        v = self._t(v0)
+        a = (C.c_double * steps)()
+        b = (C.c_double * steps)()
+        m = C.c_int32()
+        lo, hi = C.c_double(), C.c_double()
+        self._check(self.lib.sim_schur_spectrum(self.h, int(bool(exact)), _ptr(v), int(steps), float(lap_rtol),
+                                                a, b, C.byref(m), C.byref(lo), C.byref(hi)))
+        k = int(m.value)
+        return dict(alpha=np.array(a[:k]), beta=np.array(b[:k]), steps=k, lmin=float(lo.value),
+                    lmax=float(hi.value))
+
     def probe(self, name, on=True):
         self._check(self.lib.sim_probe_enable(self.h, _lib.PROBES[name], int(on)))
 
