@@ -314,7 +314,8 @@ SEDIMENTATION_CASES = {
 
 
 def make_sedimentation(case: str = "re11", cells_per_d: int = 16,
-                       precision: int = PREC_FP32MG) -> Workload:
+                       precision: int = PREC_FP32MG, spacing_ratio: float = 1.0,
+                       lump_c: Optional[float] = None) -> Workload:
     """Free sphere of diameter D = 1 released from rest on the vertical centre
     line at height 8.5 D of a 10D x 10D x 15D box with free-slip walls on all
     faces (Sec. 6.1.3).  Units D = 1 and |g| = 1, so that the terminal velocity
@@ -327,14 +328,18 @@ def make_sedimentation(case: str = "re11", cells_per_d: int = 16,
     modes that the grid barely sees).  The grid is
     (10, 10, 15) x cells_per_d; cells_per_d a multiple of 8 keeps every axis
     a multiple of 8 for the fast-diagonalisation preconditioner, which the
-    workload uses (the 15 D axis does not halve to the multigrid coarse size)."""
+    workload uses (the 15 D axis does not halve to the multigrid coarse size).
+    spacing_ratio = h / h_L sets the marker spacing h_L (the sweep of
+    Appendix A: markers ~ 4 pi a^2 / h_L^2); lump_c overrides the lumping
+    constant, which otherwise is rescaled by the marker density."""
     theta, re, fr = SEDIMENTATION_CASES[case]
     n = (10 * cells_per_d, 10 * cells_per_d, 15 * cells_per_d)
     h = 1.0 / cells_per_d
     radius = 0.5 - 0.5 * h
-    n_points = int(round(4.0 * math.pi * radius * radius / (h * h)))
+    n_points = int(round(4.0 * math.pi * radius * radius * (spacing_ratio / h) ** 2))
+    c = lump_constant(DELTA_ROMA3, h, n_points, radius) if lump_c is None else float(lump_c)
     cfg = Config(n=n, length=(10.0, 10.0, 15.0), bc=(BC_FREESLIP,) * 3, nu=fr / re, dt=0.1 * h,
-                 delta=DELTA_ROMA3, lump_c=lump_constant(DELTA_ROMA3, h, n_points, radius),
+                 delta=DELTA_ROMA3, lump_c=c,
                  precision=precision, krylov_rtol=1e-8, precond=PRECOND_FASTDIAG,
                  outer_iters=3, outer_tol=1e-3, xi=0.6)
     cfg.g = (0.0, 0.0, -1.0)
