@@ -116,6 +116,35 @@ def volume_fraction(g: Grid, d: int, center, radius, length=(1.0, 1.0, 1.0)):
     return np.where(den > 0.0, num / np.where(den > 0, den, 1.0), 0.0)
 
 
+def volume_fraction_grad(g: Grid, d: int, center, radius, length=(1.0, 1.0, 1.0)):
+    """Derivative of volume_fraction with respect to the sphere centre,
+    (3, n0, n1, n2): with s_i = |c_i - X_c| - a at the 8 corners c_i,
+    d s_i / d X_c = -(c_i - X_c) / |c_i - X_c|, and alpha = num / den with
+    num = sum(-s_i, s_i < 0), den = sum |s_i| (piecewise smooth; the branch of
+    each s_i is taken at its value)."""
+    pos = face_positions(g, d)
+    r = _rel(g, pos, np.asarray(center), length)
+    num = np.zeros(g.n)
+    den = np.zeros(g.n)
+    dnum = np.zeros((3,) + g.n)
+    dden = np.zeros((3,) + g.n)
+    for sx in (-0.5, 0.5):
+        for sy in (-0.5, 0.5):
+            for sz in (-0.5, 0.5):
+                c = np.stack([r[0] + sx * g.h, r[1] + sy * g.h, r[2] + sz * g.h])
+                dist = np.sqrt((c * c).sum(axis=0))
+                s = dist - radius
+                ds = -c / np.where(dist > 0, dist, 1.0)
+                inside = s < 0.0
+                num += np.where(inside, -s, 0.0)
+                den += np.abs(s)
+                dnum -= np.where(inside, ds, 0.0)
+                dden += np.sign(s) * ds
+    ok = den > 0.0
+    safe = np.where(ok, den, 1.0)
+    return np.where(ok, (dnum * safe - num * dden) / (safe * safe), 0.0)
+
+
 def volume_integrals(g: Grid, u, center, radius, length=(1.0, 1.0, 1.0)):
     """(sum alpha u h^3, sum alpha r x u h^3) for one sphere (eq. volume_integrals)."""
     h3 = g.h ** 3

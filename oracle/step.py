@@ -184,6 +184,8 @@ def two_way_step(g: mac.Grid, nu, dt, gvec, state: State, bodies, kernel, c, xi,
     us_k = [b.us.copy() for b in bodies]
     w_k = [b.w.copy() for b in bodies]
     used = [None] * nb
+    # per-pass record for the reverse-mode step (no arithmetic of its own)
+    rec = dict(u=[], phi=[], pp=[], phip=[], rhs_f=[], U=[], us=[], w=[], u0=uk.copy())
     for k in range(n_outer):
         U = np.empty_like(X)
         for ib, b in enumerate(bodies):
@@ -195,7 +197,15 @@ def two_way_step(g: mac.Grid, nu, dt, gvec, state: State, bodies, kernel, c, xi,
                                                 F, T, Ik, b.I_n, b.I_m, Jk, b.J_n, b.J_m, gvec)
             U[s0:s1] = bd.point_velocities(us_k[ib], w_k[ib], levers[ib])
             used[ib] = dict(F=F, T=T, I=Ik, J=Jk)
+        rec["u"].append(uk.copy())
+        rec["phi"].append(phi.copy())
+        rec["U"].append(U.copy())
+        rec["us"].append([v.copy() for v in us_k])
+        rec["w"].append([v.copy() for v in w_k])
         uk, pp, phip, info = correction(sys, uk, U, dt, xi, schur_rtol)
+        rec["pp"].append(pp)
+        rec["phip"].append(phip)
+        rec["rhs_f"].append(info["rhs_f"])
         p = p + xi * pp
         phi = phi + xi * phip
         iters.append(info["iters"])
@@ -216,4 +226,5 @@ def two_way_step(g: mac.Grid, nu, dt, gvec, state: State, bodies, kernel, c, xi,
         nbody.J_m, nbody.J_n = b.J_n.copy(), J1
         new_bodies.append(nbody)
     new = State(uk, state.u.copy(), p, phi, state.t + dt)
-    return new, new_bodies, dict(crit=crit_hist, iters=iters, X=X, W=W, used=used)
+    return new, new_bodies, dict(crit=crit_hist, iters=iters, X=X, W=W, used=used, sys=sys,
+                                 xc1=xc1, R1=R1, levers=levers, starts=starts, rec=rec)

@@ -136,3 +136,87 @@ def test_step_vjp_positions_central_difference(case):
         fd = (fp - fm) / (2 * eps)
         an = float(np.vdot(grads["X"], Xd))
         assert abs(fd - an) < 1e-5 * abs(an), (fd, an)
+
+
+# --------------------------------------------------------------------------
+# two-way step (fixed number of outer passes)
+
+def _two_way_setup(bc, seed=11):
+    rng = np.random.default_rng(seed)
+    n, a, theta = 16, 0.17, (1.6, 2.4)
+    g = mac.Grid((n, n, n), 1.0 / n, (bc,) * 3)
+    K = int(round(4 * np.pi * a * a / g.h ** 2))
+    off = wl.fibonacci_offsets(K, a)
+    c = wl.lump_constant(wl.DELTA_PESKIN4, g.h, K, a)
+    dt = 0.004
+    fb = []
+    for cen, th in zip(((0.38, 0.38, 0.6), (0.64, 0.62, 0.4)), theta):
+        b = ostep.free_body(np.array(cen) + rng.uniform(-0.01, 0.01, 3), rng.normal(0, 0.1, 3),
+                            rng.normal(0, 1.0, 3), a, th, off, dt)
+        b.xc_m = b.xc - dt * b.us + rng.normal(0, 1e-4, 3)
+        b.us_m = b.us + rng.normal(0, 0.01, 3)
+        b.w_m = b.w + rng.normal(0, 0.1, 3)
+        fb.append(b)
+    mask = g.face_dof_mask()
+    u0 = rng.standard_normal((3,) + g.n) * 0.05 * mask
+    st = ostep.State(u0, u0 + 0.01 * rng.standard_normal(u0.shape) * mask, rng.standard_normal(g.n),
+                     0.2 * rng.standard_normal((2 * K, 3)))
+    ostep.init_volume_history(g, st.u, fb)
+    for b in fb:
+        b.I_m = b.I_m + rng.normal(0, 1e-4, 3)
+        b.J_m = b.J_m + rng.normal(0, 1e-5, 3)
+    return g, st, fb, c, dt
+
+
+_BODY_IN = ("xc", "xc_m", "us", "us_m", "w", "w_m", "I_n", "I_m", "J_n", "J_m")
+
+
+@pytest.mark.parametrize("bc", [P, W_, F_])
+def test_two_way_step_vjp_central_differences(bc):
+    """<ybar, (step(x + e d) - step(x - e d)) / 2e> = <J^T ybar, d> along a
+    random direction of every input group, fluid and body."""
+    g, st, fb, c, dt = _two_way_setup(bc)
+    nu, xi, n_outer, gvec = 0.01, 0.6, 3, np.array([0.0, 0.0, -1.0])
+    rng = np.random.default_rng(5)
+    mask = g.face_dof_mask()
+    K = st.phi.shape[0]
+    gu = rng.standard_normal((3,) + g.n) * mask
+    gp = rng.standard_normal(g.n)
+    gphi = rng.standard_normal((K, 3))
+    gbod = [dict(xc=rng.standard_normal(3), us=rng.standard_normal(3), w=rng.standard_normal(3),
+                 I=rng.standard_normal(3), J=rng.standard_normal(3)) for _ in fb]
+    grads, _, _, _ = oadj.two_way_step_vjp(g, nu, dt, gvec, st, fb, wl.DELTA_PESKIN4, c, xi, n_outer,
+                                           gu, gp, gphi, gbod)
+
+    def ell(s, bodies):
+        new, nb, _ = ostep.two_way_step(g, nu, dt, gvec, s, bodies, wl.DELTA_PESKIN4, c, xi, n_outer,
+                                        0.0, 1e-13, 1e-14)
+        v = float(np.vdot(gu, new.u) + np.vdot(gp, new.p) + np.vdot(gphi, new.phi))
+        for b, y in zip(nb, gbod):
+            v += float(y["xc"] @ b.xc + y["us"] @ b.us + y["w"] @ b.w + y["I"] @ b.I_n + y["J"] @ b.J_n)
+        return v
+
+    groups = {"u": 1e-4, "um": 1e-4, "p": 1e-4, "phi": 1e-4}
+    groups.update({f"b{i}.{k}": 1e-6 for i in range(len(fb)) for k in _BODY_IN})
+    for name, eps in groups.items():
+        if name.startswith("b"):
+            i, key = int(name[1]), name[3:]
+            d = rng.standard_normal(3)
+            d *= {"I_n": 1e-3, "I_m": 1e-3, "J_n": 1e-4, "J_m": 1e-4}.get(key, 1.0)
+            an = float(grads["bodies"][i][key] @ d)
+
+            def shifted(sgn):
+                bs = [b.copy() for b in fb]
+                setattr(bs[i], key, getattr(bs[i], key) + sgn * eps * d)
+                return ell(st, bs)
+        else:
+            shape = {"u": st.u.shape, "um": st.u.shape, "p": g.n, "phi": st.phi.shape}[name]
+            d = rng.standard_normal(shape) * (mask if name in ("u", "um") else 1.0)
+            an = float(np.vdot(grads[name], d))
+
+            def shifted(sgn):
+                s2 = st.copy()
+                setattr(s2, name, getattr(st, name) + sgn * eps * d)
+                return ell(s2, [b.copy() for b in fb])
+        fd = (shifted(1.0) - shifted(-1.0)) / (2 * eps)
+        assert abs(fd - an) < 2e-6 * max(abs(an), abs(fd), 1e-3), (name, fd, an)
