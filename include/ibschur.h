@@ -118,6 +118,9 @@ typedef struct {
   int32_t outer_iters;   /* pressure-force corrections per step (>= 1) */
   double outer_tol;      /* stop on ||Phi'||_1 / ||Phi||_1 < tol (0: fixed) */
   double xi;             /* relaxation of the correction (1 for one-way) */
+  int32_t record_two_way;/* != 0: a two-way step keeps, per outer pass, what
+                            sim_step_adjoint_two_way needs (outer_iters x (4 cell
+                            fields + 3 point vectors) of workspace) */
   int32_t device;        /* HIP device ordinal */
   void *stream;          /* hipStream_t on which all work is enqueued */
 } sim_config;
@@ -250,6 +253,27 @@ sim_status sim_step_adjoint(sim_t sim, const double *d_gu, const double *d_gv,
                             const double *d_gw, const double *d_gp, const double *d_gphi,
                             double *d_gX, double *gU, double *d_gu_in, double *d_gum_in,
                             double *d_gp_in, double *d_gphi_in);
+
+/* Reverse mode of the last two-way step (free bodies, Sec. 3.2.1): the
+ * vector-Jacobian product of the step with its fixed number of outer passes.
+ * Needs cfg.record_two_way != 0, cfg.outer_tol = 0 and a sim_step that ran
+ * exactly one two-way step since the last state change (else SIM_ESTATE).
+ * Output cotangents: d_gu, d_gv, d_gw, d_gp ([n0][n1][n2], device), d_gphi
+ * ([K][3], device) for u^{n+1}, p^{n+1}, Phi^{n+1}; gbody_out (host,
+ * [nb][15]) for each body's X_c^{n+1}, u_s^{n+1}, omega^{n+1} and the volume
+ * integrals sum alpha u h^3, sum alpha r x u h^3 of u^{n+1} at X_c^{n+1}
+ * (the next step's history).  Any may be NULL (zero).
+ * Input cotangents (any may be NULL): d_gu_in, d_gum_in ([3][n0][n1][n2]) of
+ * u^n, u^{n-1}; d_gp_in of p^n; d_gphi_in ([K][3]) of Phi^n; gbody_in (host,
+ * [nb][30]) of each body's X_c^n, X_c^{n-1}, u_s^n, u_s^{n-1}, omega^n,
+ * omega^{n-1} and of the volume-integral history I^n, I^{n-1}, J^n, J^{n-1}.
+ * The orientation R^n is held fixed.  The transposed Schur and momentum solves
+ * use the step's solvers and tolerances; SIM_ENOTCONV if one misses it (the
+ * result is still written). */
+sim_status sim_step_adjoint_two_way(sim_t sim, const double *d_gu, const double *d_gv,
+                                    const double *d_gw, const double *d_gp, const double *d_gphi,
+                                    const double *gbody_out, double *d_gu_in, double *d_gum_in,
+                                    double *d_gp_in, double *d_gphi_in, double *gbody_in);
 
 /* Operator applications on caller data (natural layouts above), for
  * operator-level checks.  in / out sizes follow the operator:

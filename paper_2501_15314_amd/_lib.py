@@ -23,7 +23,7 @@ OPS = dict(laplacian=0, schur=1, precond=2, grad=3, div=4, interp=5, spread=6, h
 EXPORTS = ["sim_workspace_bytes", "sim_create", "sim_destroy", "sim_set_bodies", "sim_set_fields",
            "sim_get_fields", "sim_step", "sim_solve_schur", "sim_get_forces", "sim_get_points",
            "sim_get_body_state", "sim_set_time",
-           "sim_step_adjoint", "sim_apply", "sim_schur_spectrum", "sim_probe_enable", "sim_probe_read", "sim_last_error"]
+           "sim_step_adjoint", "sim_step_adjoint_two_way", "sim_apply", "sim_schur_spectrum", "sim_probe_enable", "sim_probe_read", "sim_last_error"]
 
 PROBES = dict(smooth_fine=0, smooth_first_fine=1, restrict_fine=2, prolong_fine=3, laplacian=4,
               spread_div=5, spread_face=6, interp_grad=7, interp_face=8, multidot=9,
@@ -39,7 +39,8 @@ class SimConfig(C.Structure):
                 ("mg_coarsest", C.c_int32), ("mg_pre", C.c_int32), ("mg_post", C.c_int32),
                 ("mg_coarse_sweeps", C.c_int32), ("precond", C.c_int32), ("krylov", C.c_int32),
                 ("outer_iters", C.c_int32), ("outer_tol", C.c_double),
-                ("xi", C.c_double), ("device", C.c_int32), ("stream", C.c_void_p)]
+                ("xi", C.c_double), ("record_two_way", C.c_int32), ("device", C.c_int32),
+                ("stream", C.c_void_p)]
 
 
 class SimBody(C.Structure):
@@ -87,6 +88,7 @@ def load(path: str = LIB_PATH):
     lib.sim_set_time.argtypes = [sim_t, D]
     lib.sim_step_adjoint.argtypes = [sim_t, VP, VP, VP, VP, VP, VP, P(D), VP, VP, VP, VP]
     lib.sim_apply.argtypes = [sim_t, I32, VP, VP, VP]
+    lib.sim_step_adjoint_two_way.argtypes = [sim_t, VP, VP, VP, VP, VP, P(D), VP, VP, VP, VP, P(D)]
     lib.sim_schur_spectrum.argtypes = [sim_t, I32, VP, I32, D, P(D), P(D), P(I32), P(D), P(D)]
     lib.sim_probe_enable.argtypes = [sim_t, I32, I32]
     lib.sim_probe_read.argtypes = [sim_t, I32, P(I64), P(D), I32]

@@ -99,6 +99,16 @@ struct sim_s {
   // transposed while adj_ready (a one-way step with one correction)
   double *ADJ = nullptr;
   bool adj_ready = false;
+  // reverse mode of a two-way step (cfg.record_two_way): per outer pass k the
+  // velocity u^k before the correction, p'_k, and in tile order Phi^(k),
+  // Phi'_k and RHS_F; the pass count, the body velocities of every pass
+  // (6 per body and pass) and the body state before the step (18 per body);
+  // ADJ2 holds natural-order point work and the per-body coefficients.
+  double *REC_U = nullptr, *REC_PP = nullptr, *REC_PHI = nullptr, *REC_PHIP = nullptr, *REC_RF = nullptr;
+  double *ADJ2 = nullptr;
+  int rec_passes = 0;
+  bool adj2_ready = false;
+  std::vector<double> rec_body, rec_pre;
   // reductions
   double *PART = nullptr, *RED = nullptr, *YDEV = nullptr;
   double *COARSEFD = nullptr;  // eigen-decomposition of the coarsest grid (exact coarse solve)
@@ -241,6 +251,13 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
   double *RF = cv.arr<double>(3 * K), *PHIP = cv.arr<double>(3 * K), *PHIS = cv.arr<double>(3 * K);
   double *PT3 = cv.arr<double>(3 * K);
   double *ADJ = cv.arr<double>(15 * K);
+  const long long npass = c->record_two_way ? c->outer_iters : 0;
+  double *REC_U = npass ? cv.arr<double>(npass * 3 * N) : nullptr;
+  double *REC_PP = npass ? cv.arr<double>(npass * N) : nullptr;
+  double *REC_PHI = npass ? cv.arr<double>(npass * 3 * K) : nullptr;
+  double *REC_PHIP = npass ? cv.arr<double>(npass * 3 * K) : nullptr;
+  double *REC_RF = npass ? cv.arr<double>(npass * 3 * K) : nullptr;
+  double *ADJ2 = npass ? cv.arr<double>(15 * K + 9 * MAX_BODIES + 9 * VOL_CHUNKS) : nullptr;
   int *COUNTS = cv.arr<int>(nt), *TSTART = cv.arr<int>(nt + 1), *FILLC = cv.arr<int>(nt);
   int *FLAGS = cv.arr<int>(nt), *FPOS = cv.arr<int>(nt + 1), *ACTIVE = cv.arr<int>(nt);
   int *SCANTMP = cv.arr<int>(nt / 1024 + 16);
@@ -280,6 +297,8 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
     s->BODYOF = BODYOF; s->TILE = TILE; s->PERM = PERM; s->PERMTMP = PERMTMP;
     s->XS = XS; s->US = US; s->Q = Q; s->RF = RF; s->PHIP = PHIP; s->PHIS = PHIS; s->PT3 = PT3;
     s->ADJ = ADJ;
+    s->REC_U = REC_U; s->REC_PP = REC_PP; s->REC_PHI = REC_PHI; s->REC_PHIP = REC_PHIP; s->REC_RF = REC_RF;
+    s->ADJ2 = ADJ2;
     s->COUNTS = COUNTS; s->TSTART = TSTART; s->FILLC = FILLC; s->FLAGS = FLAGS; s->FPOS = FPOS;
     s->ACTIVE = ACTIVE; s->SCANTMP = SCANTMP; s->BODIES = BODIES;
     s->SPAN = SPAN; s->BSUM = BSUM; s->VPART = VPART;
@@ -1138,6 +1157,25 @@ sim_status step_two_way(sim_t s, sim_step_stats *out) {
     }
     s->vol_init = true;
   }
+  // record for the reverse-mode step: the body state before the step
+  const bool rec = c.record_two_way && s->REC_U;
+  const long long N = s->N, K3 = 3LL * s->Kmax;
+  if (rec) {
+    s->rec_pre.assign(18 * (size_t)nb, 0.0);
+    s->rec_body.assign(6 * (size_t)nb * c.outer_iters, 0.0);
+    for (int i = 0; i < nb; ++i) {
+      const HostBody &hb = s->bodies[i];
+      double *q = &s->rec_pre[18 * i];
+      for (int a = 0; a < 3; ++a) {
+        q[a] = hb.xc[a];
+        q[3 + a] = hb.xc_m[a];
+        q[6 + a] = hb.us[a];
+        q[9 + a] = hb.us_m[a];
+        q[12 + a] = hb.w[a];
+        q[15 + a] = hb.w_m[a];
+      }
+    }
+  }
   // Step 1: X_c^{n+1} = (4 X_c^n - X_c^{n-1}) / 3 + (2 dt / 3) u_s^n, R^{n+1}
   std::vector<BodyDev> bd(nb);
   for (int i = 0; i < nb; ++i) {
@@ -1183,7 +1221,24 @@ sim_status step_two_way(sim_t s, sim_step_stats *out) {
     CKH(points_place(s->g, s->K, s->BODIES, s->BODYOF, s->OFF, s->XN, s->UN, s->TILE, s->nt0, s->nt1, s->nt2, st));
     CKH(gather3(s->K, s->PERM, s->UN, s->US, st));
     bool want = c.outer_tol > 0 || k + 1 == c.outer_iters;
+    if (rec) {
+      CKH(hipMemcpyAsync(s->REC_U + k * 3 * N, s->USTAR, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, st));
+      if (s->K > 0)
+        CKH(hipMemcpyAsync(s->REC_PHI + k * K3, s->PHIS, sizeof(double) * 3 * s->K, hipMemcpyDeviceToDevice, st));
+      for (int i = 0; i < nb; ++i)
+        for (int q = 0; q < 3; ++q) {
+          s->rec_body[6 * ((size_t)k * nb + i) + q] = us_k[3 * i + q];
+          s->rec_body[6 * ((size_t)k * nb + i) + 3 + q] = w_k[3 * i + q];
+        }
+    }
     if ((rc = correction(s, k, want, S, divstar, src))) return rc;
+    if (rec) {
+      CKH(hipMemcpyAsync(s->REC_PP + k * N, s->PP, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+      if (s->K > 0) {
+        CKH(hipMemcpyAsync(s->REC_PHIP + k * K3, s->PHIP, sizeof(double) * 3 * s->K, hipMemcpyDeviceToDevice, st));
+        CKH(hipMemcpyAsync(s->REC_RF + k * K3, s->RF, sizeof(double) * 3 * s->K, hipMemcpyDeviceToDevice, st));
+      }
+    }
     if (c.outer_tol > 0 && S.outer_crit < c.outer_tol) break;
   }
   // volume integrals of u^{n+1} for the next step's history
@@ -1207,6 +1262,9 @@ sim_status step_two_way(sim_t s, sim_step_stats *out) {
   if ((rc = finish_step(s, t1, divstar, S))) return rc;
   S.seconds = timer.seconds();
   s->last = S;
+  // the reverse mode needs the fixed pass count (no early stop on outer_tol)
+  s->rec_passes = S.outer;
+  s->adj2_ready = rec && c.outer_tol == 0.0 && S.outer == c.outer_iters;
   if (out) *out = S;
   if (hrc == SIM_ENOTCONV) return fail(s, SIM_ENOTCONV, "momentum solve iteration limit reached");
   return src;
@@ -1355,6 +1413,7 @@ sim_status sim_set_bodies(sim_t s, int32_t nb, const sim_body *bodies, const dou
   s->nb = nb;
   s->any_free = nb > 0 && bodies[0].motion == SIM_MOTION_FREE;
   s->adj_ready = false;
+  s->adj2_ready = false;
   s->vol_init = false;
   hipStream_t st = s->st;
   if (K > 0) {
@@ -1383,6 +1442,7 @@ sim_status sim_set_fields(sim_t s, int32_t level, const double *d_u, const doubl
   CKH(zero_wall_faces(s->g, U, st));
   s->vol_init = false;  // the volume history of free bodies restarts from the new u^n
   s->adj_ready = false;
+  s->adj2_ready = false;
   if (level == 0 && d_p) CKH(to_split(s->g, 1, d_p, s->P, st));
   if (level == 0 && d_phi && s->K > 0)
     CKH(hipMemcpyAsync(s->PHIN, d_phi, sizeof(double) * 3 * s->K, hipMemcpyDeviceToDevice, st));
@@ -1404,6 +1464,7 @@ sim_status sim_set_time(sim_t s, double t) {
   if (!isfinite(t)) return fail(s, SIM_EINVAL, "time must be finite");
   s->t = t;
   s->adj_ready = false;
+  s->adj2_ready = false;
   return SIM_OK;
 }
 
@@ -1472,6 +1533,7 @@ sim_status sim_solve_schur(sim_t s, const double *d_rhs_p, const double *d_rhs_f
                            sim_solve_stats *stats) {
   if (!s) return SIM_EINVAL;
   s->adj_ready = false;
+  s->adj2_ready = false;
   if (!s->have_bodies) return fail(s, SIM_ESTATE, "no bodies set");
   if (!d_rhs_p || !d_p || (s->K > 0 && (!d_rhs_f || !d_phi))) return fail(s, SIM_EINVAL, "null argument");
   hipStream_t st = s->st;
@@ -1488,6 +1550,7 @@ sim_status sim_solve_schur(sim_t s, const double *d_rhs_p, const double *d_rhs_f
 sim_status sim_step(sim_t s, int32_t nsteps, sim_step_stats *stats) {
   if (!s) return SIM_EINVAL;
   s->adj_ready = false;
+  s->adj2_ready = false;
   if (!s->have_bodies) return fail(s, SIM_ESTATE, "no bodies set");
   if (nsteps < 0) return fail(s, SIM_EINVAL, "nsteps < 0");
   sim_status rc = SIM_OK;
@@ -1615,6 +1678,238 @@ sim_status sim_step_adjoint(sim_t s, const double *d_gu, const double *d_gv, con
     CKH(zero_wall_faces(g, F3, st));
     for (int d = 0; d < 3; ++d) CKH(to_natural(g, 1, F3 + d * N, d_gu_in + d * N, st));
   }
+  if ((rc = sync(s))) return rc;
+  if (src == SIM_ENOTCONV) return fail(s, SIM_ENOTCONV, "adjoint Schur solve iteration limit reached");
+  if (hrc == SIM_ENOTCONV) return fail(s, SIM_ENOTCONV, "adjoint momentum solve iteration limit reached");
+  return SIM_OK;
+}
+
+// Reverse mode of the last two-way step (Sec. 3.2.1 with a fixed number of
+// outer passes): the passes in reverse order, each the transposed correction
+// (as in sim_step_adjoint, with u^k and U^k of the pass), then U^k = u_s^k +
+// w^k x L~, Newton-Euler, the force / torque sums of Phi^(k) and the volume
+// integrals of u^k; then the momentum predictor, the points
+// X = X_c^{n+1} + L~, L~ = R^{n+1} X~, and Step 1 (X_c^{n+1} by BDF2 and
+// R^{n+1} = exp([psi]) R^n with psi = gamma w^n / |w^n|; the cotangent of
+// psi is J_l(psi)^T times the rotation cotangent sum L~ x Lbar).
+sim_status sim_step_adjoint_two_way(sim_t s, const double *d_gu, const double *d_gv, const double *d_gw,
+                                    const double *d_gp, const double *d_gphi, const double *gbody_out,
+                                    double *d_gu_in, double *d_gum_in, double *d_gp_in, double *d_gphi_in,
+                                    double *gbody_in) {
+  if (!s) return SIM_EINVAL;
+  if (!s->have_bodies || !s->adj2_ready)
+    return fail(s, SIM_ESTATE, "no recorded two-way step (record_two_way, outer_tol = 0) to transpose");
+  hipStream_t st = s->st;
+  const sim_config &c = s->cfg;
+  const Geo &g = s->g;
+  const long long N = s->N, n3 = 3 * N;
+  const int K = s->K, ker = s->ker, nb = s->nb, npass = s->rec_passes;
+  const double dt = c.dt, tau = 2.0 * dt / 3.0, xi = c.xi, ic = 1.0 / s->c, h3 = g.h * g.h * g.h;
+  const long long K3 = 3LL * s->Kmax;
+  double *A0 = s->ADJ, *A1 = A0 + K3, *A2 = A1 + K3, *A3 = A2 + K3, *A4 = A3 + K3;
+  double *PBN = s->ADJ2, *LBN = PBN + K3, *UBN = LBN + K3, *XBN = UBN + K3, *PHN = XBN + K3;
+  double *COEF = PHN + K3, *VP = COEF + 9 * MAX_BODIES;
+  double *UB = s->TMP3, *RB = s->RHSU, *F3 = s->USTAR, *PB = s->RHSP, *PPB = s->PP, *BB = s->BVEC;
+  sim_status rc;
+  auto band = [&](bool div, const double *q, double alpha, double *out) {
+    return band_apply(ker, div, g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, q, alpha, out,
+                      st);
+  };
+  // per-body sums of a natural-order point vector: (sum v, sum L~ x v)
+  std::vector<double> sums(12 * (size_t)nb);
+  auto body_sums_of = [&](const double *v) -> sim_status {
+    CKH(body_force_torque(nb, s->BODIES, s->SPAN, s->OFF, v, 1.0, s->BSUM, st));
+    CKH(hipMemcpyAsync(sums.data(), s->BSUM, sizeof(double) * 12 * nb, hipMemcpyDeviceToHost, st));
+    CKH(hipStreamSynchronize(st));
+    return SIM_OK;
+  };
+  // transposed volume integrals of u at X_c^{n+1}: ubar += ..., centre cotangents into xc1b
+  std::vector<double> xc1b(3 * (size_t)nb, 0.0), vp(9 * VOL_CHUNKS);
+  auto vol_adj = [&](const double *u, int i, const double ib[3], const double jb[3]) -> sim_status {
+    CKH(body_volume_adjoint(g, s->hspan[i], ib, jb, u, UB, VP, st));
+    CKH(hipMemcpyAsync(vp.data(), VP, sizeof(double) * vp.size(), hipMemcpyDeviceToHost, st));
+    CKH(hipStreamSynchronize(st));
+    for (int t = 0; t < 3 * VOL_CHUNKS; ++t)
+      for (int q = 0; q < 3; ++q) xc1b[3 * i + q] += vp[3 * t + q];
+    return SIM_OK;
+  };
+  if ((rc = upload_spans(s, false))) return rc;  // node boxes at X_c^{n+1}
+  // output cotangents
+  CKH(fill(UB, n3, 0.0, st));
+  const double *gin[3] = {d_gu, d_gv, d_gw};
+  for (int d = 0; d < 3; ++d)
+    if (gin[d]) CKH(to_split(g, 1, gin[d], UB + d * N, st));
+  CKH(zero_wall_faces(g, UB, st));
+  CKH(fill(PB, N, 0.0, st));
+  if (d_gp) CKH(to_split(g, 1, d_gp, PB, st));
+  if (K > 0) {
+    if (d_gphi) CKH(scale_copy(PBN, d_gphi, 3LL * K, 1.0, st));
+    else CKH(fill(PBN, 3LL * K, 0.0, st));
+    CKH(fill(LBN, 3LL * K, 0.0, st));
+    CKH(fill(A4, 3LL * K, 0.0, st));
+  }
+  // per-body output cotangents (xc, us, w, I, J of the step's result) and input accumulators
+  std::vector<double> gout(15 * (size_t)nb, 0.0), gin_b(30 * (size_t)nb, 0.0);
+  if (gbody_out) std::copy(gbody_out, gbody_out + 15 * nb, gout.begin());
+  for (int i = 0; i < nb; ++i)
+    for (int q = 0; q < 3; ++q) xc1b[3 * i + q] = gout[15 * i + q];
+  for (int i = 0; i < nb; ++i) {
+    const double *ib = &gout[15 * i + 9], *jb = &gout[15 * i + 12];
+    if (ib[0] != 0.0 || ib[1] != 0.0 || ib[2] != 0.0 || jb[0] != 0.0 || jb[1] != 0.0 || jb[2] != 0.0)
+      if ((rc = vol_adj(s->U, i, ib, jb))) return rc;
+  }
+  CKH(zero_wall_faces(g, UB, st));
+  sim_status src = SIM_OK;
+  std::vector<double> coef(9 * (size_t)nb);
+  for (int k = npass - 1; k >= 0; --k) {
+    const double *uk = s->REC_U + k * n3, *ppk = s->REC_PP + k * N;
+    const double *phik = s->REC_PHI + k * K3, *phipk = s->REC_PHIP + k * K3, *rfk = s->REC_RF + k * K3;
+    if (K > 0) CKH(gather3(K, s->PERM, PBN, A0, st));
+    // u^{k+1} = u^k + xi tau (-G p' + W Phi'), p += xi p', Phi += xi Phi'
+    CKH(div_apply(g, UB, PPB, xi * tau, st));
+    CKH(axpby(PPB, PB, N, xi, 1.0, st));
+    CKH(interp_face(ker, g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, UB, xi * tau, A0, xi, A1, st));
+    CKH(interp_dx(ker, g, K, s->XS, UB, phipk, xi * tau, A4, st));
+    // Phi' = c^-1 (-W^T G p' - RHS_F)
+    CKH(band(true, A1, ic, PPB));
+    CKH(scale3(K, A1, -ic, nullptr, 0.0, A2, st));
+    // p' = S~^+ b
+    if ((rc = project_mean(s, PPB))) return rc;
+    sim_solve_stats sst{};
+    sim_status r1 = fgmres_any(s, PPB, BB, &sst);
+    if (r1 != SIM_OK && r1 != SIM_ENOTCONV) return r1;
+    if (r1 == SIM_ENOTCONV) src = r1;
+    CKH(interp_grad<double>(ker, g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, BB, 1.0, nullptr, 0.0, A3, st));
+    CKH(grad_apply(g, BB, F3, 1.0, nullptr, st));
+    CKH(interp_dx(ker, g, K, s->XS, F3, phipk, 1.0, A4, st));
+    CKH(scale3(K, A1, 1.0, A3, 1.0, A1, st));
+    CKH(grad_apply(g, ppk, F3, 1.0, nullptr, st));
+    CKH(interp_dx(ker, g, K, s->XS, F3, A1, -ic, A4, st));
+    CKH(scale3(K, A3, -ic, A2, 1.0, A2, st));
+    // RHS_p = -D u^k / tau, RHS_F = (W^T u^k - U^k) / tau
+    CKH(grad_apply(g, BB, UB, 1.0 / tau, UB, st));
+    CKH(band(false, A2, 1.0 / tau, UB));
+    CKH(zero_wall_faces(g, UB, st));
+    CKH(scale3(K, A2, -1.0 / tau, nullptr, 0.0, A3, st));
+    CKH(interp_dx(ker, g, K, s->XS, uk, A2, 1.0 / tau, A4, st));
+    // U^k = u_s^k + w^k x L~: per-body sums of Ubar; Newton-Euler transposed on the host
+    if (K > 0) CKH(scatter3(K, s->PERM, A3, UBN, st));
+    if ((rc = body_sums_of(UBN))) return rc;
+    for (int i = 0; i < nb; ++i) {
+      const HostBody &hb = s->bodies[i];
+      const double a = hb.b.radius, theta = hb.b.density_ratio;
+      const double Vp = 4.0 / 3.0 * M_PI * a * a * a, Ip = 0.4 * Vp * a * a;
+      const double cu = tau / (theta * Vp), cw = tau / (theta * Ip);
+      double usb[3], wb[3], Fb[3], Tb[3], Ikb[3], Jkb[3];
+      double *o = &gin_b[30 * i];
+      for (int q = 0; q < 3; ++q) {
+        usb[q] = sums[12 * i + q] + (k == npass - 1 ? gout[15 * i + 3 + q] : 0.0);
+        wb[q] = sums[12 * i + 3 + q] + (k == npass - 1 ? gout[15 * i + 6 + q] : 0.0);
+        o[6 + q] += 4.0 / 3.0 * usb[q];     // us
+        o[9 + q] -= usb[q] / 3.0;           // us_m
+        o[12 + q] += 4.0 / 3.0 * wb[q];     // w
+        o[15 + q] -= wb[q] / 3.0;           // w_m
+        Fb[q] = -cu * usb[q];
+        Tb[q] = -cw * wb[q];
+        Ikb[q] = cu * 1.5 / dt * usb[q];
+        Jkb[q] = cw * 1.5 / dt * wb[q];
+        o[18 + q] -= cu * 2.0 / dt * usb[q];  // I_n
+        o[21 + q] += cu * 0.5 / dt * usb[q];  // I_m
+        o[24 + q] -= cw * 2.0 / dt * wb[q];   // J_n
+        o[27 + q] += cw * 0.5 / dt * wb[q];   // J_m
+        coef[9 * i + q] = Fb[q];
+        coef[9 * i + 3 + q] = Tb[q];
+        coef[9 * i + 6 + q] = s->rec_body[6 * ((size_t)k * nb + i) + 3 + q];
+      }
+      if ((rc = vol_adj(uk, i, Ikb, Jkb))) return rc;
+    }
+    CKH(zero_wall_faces(g, UB, st));
+    if (K > 0) {
+      CKH(hipMemcpyAsync(COEF, coef.data(), sizeof(double) * 9 * nb, hipMemcpyHostToDevice, st));
+      CKH(scatter3(K, s->PERM, phik, PHN, st));
+      CKH(point_adjoint(K, s->BODYOF, s->OFF, s->BODIES, COEF, h3, PHN, UBN, PBN, LBN, st));
+      CKH(hipStreamSynchronize(st));  // coef is reused by the next pass
+    }
+  }
+  // predictor: rhs bar = A^-1 u^0 bar
+  CKH(fill(RB, n3, 0.0, st));
+  sim_solve_stats hst{};
+  sim_status hrc = helm_solve_any(s, UB, RB, &hst);
+  if (hrc != SIM_OK && hrc != SIM_ENOTCONV) return hrc;
+  CKH(interp_dx(ker, g, K, s->XS, RB, s->REC_PHI, 1.0, A4, st));  // Phi^n = Phi^(0)
+  if (d_gphi_in && K > 0) {
+    CKH(gather3(K, s->PERM, PBN, A0, st));
+    CKH(interp_face(ker, g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, RB, 1.0, A0, 1.0, A2, st));
+    CKH(scatter3(K, s->PERM, A2, d_gphi_in, st));
+  }
+  if (d_gp_in) {
+    CKH(div_apply(g, RB, s->TMPC, 1.0, st));
+    CKH(axpby(s->TMPC, PB, N, 1.0, 1.0, st));
+    CKH(to_natural(g, 1, s->TMPC, d_gp_in, st));
+  }
+  if (d_gum_in) {
+    CKH(scale_copy(F3, RB, n3, -1.0 / (2.0 * dt), st));
+    for (int d = 0; d < 3; ++d) CKH(to_natural(g, 1, F3 + d * N, d_gum_in + d * N, st));
+  }
+  if (d_gu_in) {
+    CKH(convection_adjoint(g, s->UM, RB, F3, st));
+    CKH(axpby(F3, RB, n3, 2.0 / dt, -1.0, st));
+    CKH(zero_wall_faces(g, F3, st));
+    for (int d = 0; d < 3; ++d) CKH(to_natural(g, 1, F3 + d * N, d_gu_in + d * N, st));
+  }
+  // points: X = X_c^{n+1} + L~ -> sum Xbar per body; rotation cotangent sum L~ x (Lbar + Xbar)
+  if (K > 0) {
+    CKH(scatter3(K, s->PERM, A4, XBN, st));
+    if ((rc = body_sums_of(XBN))) return rc;
+    for (int i = 0; i < nb; ++i)
+      for (int q = 0; q < 3; ++q) xc1b[3 * i + q] += sums[12 * i + q];
+    CKH(axpby(LBN, XBN, 3LL * K, 1.0, 1.0, st));
+    if ((rc = body_sums_of(LBN))) return rc;
+  } else {
+    std::fill(sums.begin(), sums.end(), 0.0);
+  }
+  for (int i = 0; i < nb; ++i) {
+    const double *pre = &s->rec_pre[18 * i];
+    const double *w = pre + 12, *wm = pre + 15;
+    double *o = &gin_b[30 * i];
+    const double phib[3] = {sums[12 * i + 3], sums[12 * i + 4], sums[12 * i + 5]};
+    const double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    if (wn > 0.0) {
+      const double wmn = sqrt(wm[0] * wm[0] + wm[1] * wm[1] + wm[2] * wm[2]);
+      const double gam = dt * (1.5 * wn - 0.5 * wmn);
+      const double e[3] = {w[0] / wn, w[1] / wn, w[2] / wn};
+      const double psi[3] = {gam * e[0], gam * e[1], gam * e[2]};
+      // J_l(psi) = I + (1 - cos th)/th^2 [psi] + (th - sin th)/th^3 [psi]^2; psib = J_l^T phib
+      const double th = fabs(gam);
+      double c1, c2;
+      if (th < 1e-8) {
+        c1 = 0.5;
+        c2 = 1.0 / 6.0;
+      } else {
+        c1 = (1.0 - cos(th)) / (th * th);
+        c2 = (th - sin(th)) / (th * th * th);
+      }
+      // [psi]^T v = -psi x v, ([psi]^2)^T = [psi]^2: psi x (psi x v)
+      const double pxv[3] = {psi[1] * phib[2] - psi[2] * phib[1], psi[2] * phib[0] - psi[0] * phib[2],
+                             psi[0] * phib[1] - psi[1] * phib[0]};
+      const double ppv[3] = {psi[1] * pxv[2] - psi[2] * pxv[1], psi[2] * pxv[0] - psi[0] * pxv[2],
+                             psi[0] * pxv[1] - psi[1] * pxv[0]};
+      double psib[3];
+      for (int q = 0; q < 3; ++q) psib[q] = phib[q] - c1 * pxv[q] + c2 * ppv[q];
+      // d psi / d w = 1.5 dt e e^T + gam (I - e e^T) / |w|;  d psi / d w_m = -0.5 dt e e_m^T
+      const double ep = e[0] * psib[0] + e[1] * psib[1] + e[2] * psib[2];
+      for (int q = 0; q < 3; ++q) o[12 + q] += 1.5 * dt * e[q] * ep + gam / wn * (psib[q] - e[q] * ep);
+      if (wmn > 0.0)
+        for (int q = 0; q < 3; ++q) o[15 + q] += -0.5 * dt * (wm[q] / wmn) * ep;
+    }
+    // X_c^{n+1} = (4 X_c^n - X_c^{n-1}) / 3 + tau u_s^n
+    for (int q = 0; q < 3; ++q) {
+      o[q] += 4.0 / 3.0 * xc1b[3 * i + q];
+      o[3 + q] -= xc1b[3 * i + q] / 3.0;
+      o[6 + q] += tau * xc1b[3 * i + q];
+    }
+  }
+  if (gbody_in) std::copy(gin_b.begin(), gin_b.end(), gbody_in);
   if ((rc = sync(s))) return rc;
   if (src == SIM_ENOTCONV) return fail(s, SIM_ENOTCONV, "adjoint Schur solve iteration limit reached");
   if (hrc == SIM_ENOTCONV) return fail(s, SIM_ENOTCONV, "adjoint momentum solve iteration limit reached");
@@ -1819,6 +2114,7 @@ double tridiag_eig(const double *a, const double *b, int m, int idx) {
 sim_status sim_apply(sim_t s, int32_t op, const double *in, const double *in2, double *out) {
   if (!s) return SIM_EINVAL;
   s->adj_ready = false;
+  s->adj2_ready = false;
   if (!in || !out) return fail(s, SIM_EINVAL, "null argument");
   hipStream_t st = s->st;
   const Geo &g = s->g;
@@ -1919,6 +2215,7 @@ sim_status sim_schur_spectrum(sim_t s, int32_t exact, const double *v0, int32_t 
                               double *alpha, double *beta, int32_t *steps_done, double *lmin, double *lmax) {
   if (!s) return SIM_EINVAL;
   s->adj_ready = false;
+  s->adj2_ready = false;
   if (!v0) return fail(s, SIM_EINVAL, "null start vector");
   if (steps < 1 || steps > 1024) return fail(s, SIM_EINVAL, "steps must be 1..1024");
   if (!(lap_rtol > 0.0 && lap_rtol < 1.0)) return fail(s, SIM_EINVAL, "lap_rtol must lie in (0, 1)");

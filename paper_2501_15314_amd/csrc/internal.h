@@ -118,6 +118,16 @@ struct BodySpan {
   int lo[3], dim[3];
 };
 constexpr int VOL_CHUNKS = 16;  // workgroups per (body, velocity component)
+// Reverse mode of the volume integrals of one body: ubar += alpha h^3 (ib + jb x r)
+// on the body's node box and part[(d * VOL_CHUNKS + chunk) * 3 + q] the partial
+// centre cotangents (summed on the host)
+hipError_t body_volume_adjoint(const Geo &g, const BodySpan &span, const double ib[3], const double jb[3],
+                               const double *u, double *ubar, double *part, hipStream_t s);
+// Per-point transposes of the force / torque sums and of U = u_s + w x L~
+// (natural order; coef[9 b ..] = (Fbar, Tbar, w) of body b)
+hipError_t point_adjoint(int K, const int *bodyof, const double *off, const BodyDev *bodies, const double *coef,
+                         double h3, const double *phi, const double *ubar, double *phibar, double *lbar,
+                         hipStream_t s);
 // out[12 b + 0..5] = (h^3 sum Phi, h^3 sum L~ x Phi) of body b (phi in natural order)
 hipError_t body_force_torque(int nb, const BodyDev *bodies, const BodySpan *span, const double *off,
                              const double *phi, double h3, double *out, hipStream_t s);

@@ -42,6 +42,7 @@ def make_config(cfg: Config, stream=None) -> _lib.SimConfig:
     c.precond = cfg.precond
     c.krylov = cfg.krylov
     c.outer_iters, c.outer_tol, c.xi = cfg.outer_iters, cfg.outer_tol, cfg.xi
+    c.record_two_way = cfg.record_two_way
     c.device = cfg.device
     c.stream = stream if stream is not None else torch.cuda.current_stream(cfg.device).cuda_stream
     return c
@@ -211,6 +212,32 @@ class Sim:
         ms = C.c_double()
         self._check(self.lib.sim_probe_read(self.h, _lib.PROBES[name], C.byref(n), C.byref(ms), int(reset)))
         return int(n.value), float(ms.value)
+
+    BODY_OUT = ("xc", "us", "w", "I", "J")
+    BODY_IN = ("xc", "xc_m", "us", "us_m", "w", "w_m", "I_n", "I_m", "J_n", "J_m")
+
+    def step_adjoint_two_way(self, gu=None, gp=None, gphi=None, gbodies=None):
+        """Reverse mode of the last two-way step.  gbodies: per body a dict with
+        any of xc, us, w, I, J (cotangents of the step's body outputs).
+        Returns dict(gu, gum, gp, gphi, bodies=[dict(xc, xc_m, us, ...)])."""
+        gu = self._t(gu)
+        comps = [gu[d] if gu is not None else None for d in range(3)]
+        gp, gphi = self._t(gp), self._t(gphi)
+        gout = (C.c_double * (15 * max(self.nb, 1)))()
+        for i, gb in enumerate(gbodies or []):
+            for j, key in enumerate(self.BODY_OUT):
+                if gb.get(key) is not None:
+                    gout[15 * i + 3 * j:15 * i + 3 * j + 3] = [float(x) for x in gb[key]]
+        gin = (C.c_double * (30 * max(self.nb, 1)))()
+        outs = [torch.zeros((3,) + self.n, dtype=torch.float64, device=self.dev),
+                torch.zeros((3,) + self.n, dtype=torch.float64, device=self.dev),
+                torch.zeros(self.n, dtype=torch.float64, device=self.dev),
+                torch.zeros((max(self.K, 1), 3), dtype=torch.float64, device=self.dev)]
+        self._check(self.lib.sim_step_adjoint_two_way(self.h, *[_ptr(c) for c in comps], _ptr(gp), _ptr(gphi),
+                                                      gout, *[_ptr(o) for o in outs], gin))
+        g30 = np.array(gin[:30 * self.nb]).reshape(self.nb, 10, 3)
+        bodies = [{k: g30[i, j].copy() for j, k in enumerate(self.BODY_IN)} for i in range(self.nb)]
+        return dict(gu=outs[0], gum=outs[1], gp=outs[2], gphi=outs[3][:self.K], bodies=bodies)
 
     def step_adjoint(self, gu=None, gp=None, gphi=None, want_inputs=False):
         gu = self._t(gu)

@@ -74,6 +74,7 @@ class Config:
     outer_iters: int = 1
     outer_tol: float = 0.0
     xi: float = 1.0
+    record_two_way: int = 0     # keep the outer passes for the reverse-mode two-way step
     device: int = 0
 
     @property
