@@ -149,6 +149,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form solve rate")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the solver variants (fast-diagonalisation preconditioner, BiCGStab)")
+    ap.add_argument("--no-two-way", action="store_true",
+                    help="skip the two-way (free body) step timings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the reference "
                          "kernel for scaling HBM byte counters) and exit")
@@ -256,6 +258,35 @@ def main():
         del s2
         torch.cuda.empty_cache()
 
+    # two-way steps (free bodies, three outer passes): the 27 settling spheres
+    # at 384^3 and the single settling sphere in its free-slip box
+    two_way = {}
+    if not args.no_two_way:
+        for tag, make in (("c5_384cube_27free", lambda: wl.make_c5()),
+                          ("sedimentation_160x160x240_freeslip", lambda: wl.make_sedimentation("re11", 16))):
+            wt = make()
+            wt.cfg.outer_tol = 0.0
+            print(f"[bench] two-way {tag} n={wt.cfg.n} K={wt.n_points}", file=sys.stderr, flush=True)
+            st2 = Sim(wt.cfg, wt.n_points)
+            st2.set_workload(wt)
+            st2.step(1, allow_notconv=True)
+            its2 = []
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            nts = 3
+            for _ in range(nts):
+                sst, _ = st2.step(1, allow_notconv=True)
+                its2.append(sst.total_schur_iters)
+            torch.cuda.synchronize()
+            two_way[tag] = {"ms_per_step": round(1e3 * (time.perf_counter() - a) / nts, 2),
+                            "outer_passes": int(sst.outer), "schur_iters_per_step": float(np.mean(its2)),
+                            "grid": list(wt.cfg.n), "points": wt.n_points, "bodies": len(wt.bodies),
+                            "form": "fp32mg" if wt.cfg.precision == wl.PREC_FP32MG else "fp64",
+                            "precond": "vcycle" if wt.cfg.precond == wl.PRECOND_VCYCLE else "fastdiag"}
+            st2.close()
+            del st2, wt
+            torch.cuda.empty_cache()
+
     # tile counts for the band / interpolation byte model (same geometry as the host code)
     X = body_points(w)
     cells = np.floor(X / cfg.h).astype(int)
@@ -321,6 +352,7 @@ def main():
                                   "oracle_rel_residual": (resid or {}).get(form),
                                   "oracle_force_rel_err": (fres or {}).get(form)}
                            for form in solve_s if form not in ("fp32mg", "fp64")},
+        "two_way_steps": two_way,
         "roofline": roof,
         "kernels": kinfo,
         "cpu_baseline": cpu,
