@@ -72,3 +72,64 @@ def test_two_way_adjoint_needs_a_recorded_step():
     with pytest.raises(SimError, match="ESTATE"):
         sim.step_adjoint_two_way()
     sim.close()
+
+
+def test_two_way_adjoint_dot_product_full_size():
+    """The 27 settling spheres at 384^3 (486 000 points), three outer passes:
+    with the body state fixed the two-way step is affine in (u^{n-1}, p^n,
+    Phi^n), so <ybar, step(x + xdot) - step(x)> must equal <J^T ybar, xdot>
+    for each of them (ybar on the fluid outputs and on the bodies' X_c, u_s,
+    omega)."""
+    import torch
+    w = wl.make_c5()
+    cfg = w.cfg
+    cfg.precision = wl.PREC_FP64
+    cfg.krylov_rtol = 1e-12
+    cfg.helm_rtol = 1e-12
+    cfg.outer_tol = 0.0
+    cfg.record_two_way = 1
+    dev = torch.device("cuda", 0)
+    gen = torch.Generator(device=dev).manual_seed(7)
+    n = cfg.n
+    K = w.n_points
+    print(f"two-way adjoint dot product n={n} K={K} bodies={len(w.bodies)}", flush=True)
+
+    def rnd(*shape, scale=1.0):
+        return torch.randn(*shape, generator=gen, device=dev, dtype=torch.float64) * scale
+
+    u0, um, p0, phi0 = rnd(3, *n, scale=0.02), rnd(3, *n, scale=0.02), rnd(*n), rnd(K, 3, scale=0.2)
+    ybar = (rnd(3, *n), rnd(*n), rnd(K, 3))
+    rng = np.random.default_rng(8)
+    gbod = [dict(xc=rng.standard_normal(3), us=rng.standard_normal(3), w=rng.standard_normal(3))
+            for _ in w.bodies]
+
+    def run(du=None, dp=None, dphi=None):
+        s = Sim(cfg, K)
+        s.set_bodies(w.bodies, w.offsets)
+        s.set_fields(0, u0, p0 + (dp if dp is not None else 0), phi0 + (dphi if dphi is not None else 0))
+        s.set_fields(1, um + (du if du is not None else 0))
+        s.step(1)
+        u, p = s.get_fields()
+        f, _ = s.get_forces()
+        bs = s.get_body_state()
+        return s, (u, p, f / cfg.h ** 3, bs)
+
+    def pairing(out, base):
+        v = sum(float((a - b).mul(y).sum()) for a, b, y in zip(out[:3], base[:3], ybar))
+        for bo, bb, y in zip(out[3], base[3], gbod):
+            v += float(y["xc"] @ (bo["center"] - bb["center"]) + y["us"] @ (bo["vel"] - bb["vel"])
+                       + y["w"] @ (bo["omega"] - bb["omega"]))
+        return v
+
+    base_sim, base = run()
+    res = base_sim.step_adjoint_two_way(*ybar, gbodies=gbod)
+    base_sim.close()
+    dirs = dict(um=rnd(3, *n), p=rnd(*n), phi=rnd(K, 3))
+    for name, xd in dirs.items():
+        s2, out = run(du=xd if name == "um" else None, dp=xd if name == "p" else None,
+                      dphi=xd if name == "phi" else None)
+        s2.close()
+        lhs = pairing(out, base)
+        rhs = float((res[dict(um="gum", p="gp", phi="gphi")[name]] * xd).sum())
+        print(f"  {name}: <ybar, J xdot> = {lhs:.12e}  <J^T ybar, xdot> = {rhs:.12e}", flush=True)
+        assert abs(lhs - rhs) < 1e-8 * (abs(lhs) + abs(rhs))
