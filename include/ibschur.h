@@ -163,8 +163,14 @@ typedef struct {
   int32_t total_schur_iters;
 } sim_step_stats;
 
+/* Check a configuration on the host (no device work): SIM_OK, or SIM_EINVAL
+ * with the first rule it breaks written to msg (NUL-terminated, truncated to
+ * msg_len bytes; msg may be NULL).  max_points must lie in 0..2^30. */
+sim_status sim_config_check(const sim_config *cfg, int64_t max_points, char *msg, int32_t msg_len);
+
 /* Bytes of device workspace sim_create needs for this configuration and up
- * to max_points Lagrangian points; 0 if the configuration is invalid. */
+ * to max_points Lagrangian points; 0 if the configuration is invalid (see
+ * sim_config_check for the reason). */
 size_t sim_workspace_bytes(const sim_config *cfg, int64_t max_points);
 
 /* Validate cfg, lay out the state in d_workspace (bytes long, 256-byte

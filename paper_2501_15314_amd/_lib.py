@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "SIM_OK", -1: "SIM_EINVAL", -2: "SIM_ESTATE", -3: "SIM_ENOTCO
 OPS = dict(laplacian=0, schur=1, precond=2, grad=3, div=4, interp=5, spread=6, helmholtz=7,
            convection=8, helm_solve=9, schur_rhs=10, schur_exact=11)
 
-EXPORTS = ["sim_workspace_bytes", "sim_create", "sim_destroy", "sim_set_bodies", "sim_set_fields",
+EXPORTS = ["sim_config_check", "sim_workspace_bytes", "sim_create", "sim_destroy", "sim_set_bodies", "sim_set_fields",
            "sim_get_fields", "sim_step", "sim_solve_schur", "sim_get_forces", "sim_get_points",
            "sim_get_body_state", "sim_set_time",
            "sim_step_adjoint", "sim_step_adjoint_two_way", "sim_apply", "sim_schur_spectrum", "sim_probe_enable", "sim_probe_read", "sim_last_error"]
@@ -73,6 +73,7 @@ def load(path: str = LIB_PATH):
     lib = C.CDLL(path)
     P, D, I32, I64, VP = C.POINTER, C.c_double, C.c_int32, C.c_int64, C.c_void_p
     sim_t = C.c_void_p
+    lib.sim_config_check.argtypes = [P(SimConfig), I64, C.c_char_p, I32]
     lib.sim_workspace_bytes.argtypes = [P(SimConfig), I64]
     lib.sim_workspace_bytes.restype = C.c_size_t
     lib.sim_create.argtypes = [P(SimConfig), VP, C.c_size_t, I64, P(sim_t)]

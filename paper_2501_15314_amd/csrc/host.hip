@@ -1276,9 +1276,21 @@ sim_status step_two_way(sim_t s, sim_step_stats *out) {
 // C ABI
 extern "C" {
 
+sim_status sim_config_check(const sim_config *cfg, int64_t max_points, char *msg, int32_t msg_len) {
+  std::vector<int> dims;
+  std::string v = validate(cfg, &dims);
+  if (v.empty() && (max_points < 0 || max_points > (1LL << 30))) v = "max_points must be 0..2^30";
+  if (msg && msg_len > 0) {
+    const size_t n = std::min(v.size(), (size_t)msg_len - 1);
+    memcpy(msg, v.data(), n);
+    msg[n] = '\0';
+  }
+  return v.empty() ? SIM_OK : SIM_EINVAL;
+}
+
 size_t sim_workspace_bytes(const sim_config *cfg, int64_t max_points) {
   std::vector<int> dims;
-  if (!validate(cfg, &dims).empty() || max_points < 0) return 0;
+  if (!validate(cfg, &dims).empty() || max_points < 0 || max_points > (1LL << 30)) return 0;
   return layout(nullptr, cfg, max_points, nullptr, dims);
 }
 

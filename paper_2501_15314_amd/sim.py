@@ -26,6 +26,15 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
 
 
+def config_check(cfg: Config, max_points: int = 0) -> str:
+    """The first rule of the C ABI's configuration check that cfg breaks, or
+    "" (host-only: needs the built library but no GPU)."""
+    lib = _lib.load()
+    msg = C.create_string_buffer(256)
+    lib.sim_config_check(C.byref(make_config(cfg, 0)), max_points, msg, 256)
+    return msg.value.decode()
+
+
 def make_config(cfg: Config, stream=None) -> _lib.SimConfig:
     c = _lib.SimConfig()
     c.n[:] = list(cfg.n)
@@ -76,6 +85,9 @@ class Sim:
         self.dev = torch.device("cuda", device)
         self.stream = torch.cuda.current_stream(self.dev)
         self.ccfg = make_config(cfg, self.stream.cuda_stream)
+        msg = C.create_string_buffer(256)
+        if self.lib.sim_config_check(C.byref(self.ccfg), max_points, msg, 256) != 0:
+            raise SimError(_lib.SIM_EINVAL, f"invalid configuration: {msg.value.decode()}")
         nbytes = self.lib.sim_workspace_bytes(C.byref(self.ccfg), max_points)
         if nbytes == 0:
             raise SimError(_lib.SIM_EINVAL, "invalid configuration")

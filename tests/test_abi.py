@@ -90,3 +90,33 @@ def test_workspace_bytes_validation():
     # 256^3 FP32-MG form with FGMRES(20) fits easily in one GPU's 288 GB
     w3 = _cfg(n=(256, 256, 256), precision=wl.PREC_FP32MG)
     assert 4e9 < lib.sim_workspace_bytes(C.byref(w3), 144000) < 16e9
+
+
+def test_config_check_names_the_broken_rule():
+    """sim_config_check runs on the host: the rules of the configuration,
+    each reported by name, without a GPU."""
+    import copy
+
+    from paper_2501_15314_amd import workloads as wl
+    from paper_2501_15314_amd.sim import config_check
+
+    good = wl.make_c1(n=32, n_points=300).cfg
+    assert config_check(good, 300) == ""
+    cases = [
+        (dict(n=(30, 32, 32)), "multiple of 4"),
+        (dict(bc=(3, 0, 0)), "bad bc"),
+        (dict(length=(1.0, 1.0, 2.0)), "cubic"),
+        (dict(dt=0.0), "dt"),
+        (dict(lump_c=0.0), "lump_c"),
+        (dict(krylov_restart=65), "krylov_restart"),
+        (dict(precond=wl.PRECOND_FASTDIAG, n=(36, 36, 36), length=(1.0, 1.0, 1.0)), "multiples of 8"),
+        (dict(krylov=7), "krylov"),
+        (dict(outer_iters=0), "outer_iters"),
+    ]
+    for change, words in cases:
+        cfg = copy.deepcopy(good)
+        for k, v in change.items():
+            setattr(cfg, k, v)
+        msg = config_check(cfg, 300)
+        assert words in msg, (change, msg)
+    assert "max_points" in config_check(good, -1)
