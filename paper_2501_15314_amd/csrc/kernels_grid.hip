@@ -373,95 +373,165 @@ hipError_t convection(const Geo &g, const double *u3, double *out3, hipStream_t 
 // added afterwards by the band kernel), and optionally the extrapolated
 // initial guess 2 u^n - u^{n-1} of the momentum solve (0 on wall faces).
 //
-// Tiled: a workgroup stages the three velocity components of a
-// (MR_TX+2) x (MR_TY+2) x (MR_TZ+2) natural-order box (the tile and a one-cell
-// halo: every value the divergence-form convection of a face needs) in LDS,
-// then each thread marches over the MR_TX planes of its (y, z) column and
-// writes the three components.  Tiles are handed out XCD-major (consecutive
-// tiles of the grid go to the same XCD), so the halos shared by neighbouring
-// tiles are fetched from HBM once per XCD L2.
-constexpr int MR_TX = 4, MR_TY = 8, MR_TZ = 32;
-constexpr int MR_RX = MR_TX + 2, MR_RY = MR_TY + 2, MR_RZ = MR_TZ + 2;
-constexpr int MR_REG = MR_RX * MR_RY * MR_RZ;
+// Plane march along axis 0: a workgroup owns MQ_BY rows (axis 1) x MQ_BK
+// cells (axis 2, natural order) and a chunk of MQ_CH planes.  LDS holds a
+// ring of three planes (i-1, i, i+1) of the three velocity components with a
+// one-cell halo in axes 1 and 2 (every value the divergence-form convection
+// of a face needs), and the current plane of p with its lower halo; plane
+// i+2 is fetched into registers while plane i is computed.  Each thread
+// computes two neighbouring cells of a row, whose split-layout addresses lie
+// in the two colour planes at the same in-row index, so the stores of a wave
+// are two contiguous runs.  Tiles are handed out XCD-major (consecutive tiles
+// go to the same XCD), so halos shared by neighbouring tiles come from its L2.
+constexpr int MQ_BY = 8, MQ_BK = 64, MQ_CH = 16, MQ_T = 256;
+constexpr int MQ_RY = MQ_BY + 2, MQ_RK = MQ_BK + 2, MQ_PL = MQ_RY * MQ_RK;  // 660 cells per plane
+constexpr int MQ_PY = MQ_BY + 1, MQ_PK = MQ_BK + 1, MQ_PP = MQ_PY * MQ_PK;  // p: lower halo only
+constexpr int MQ_NU = (MQ_PL + MQ_T - 1) / MQ_T;                            // plane loads per thread
+constexpr int MQ_NP = (MQ_PP + MQ_T - 1) / MQ_T;
 
-__global__ void __launch_bounds__(MR_TY * MR_TZ) k_mom_rhs(Geo g, double dt, const double *u3, const double *um3,
-                                                           const double *p_, double *out3, double *guess3, int ntz,
-                                                           int nty, int ntiles) {
-  __shared__ double su[3][MR_REG];
+// Split-layout index of a (possibly outside) cell, or -1 outside a wall box.
+__device__ __forceinline__ long long mq_index(const Geo &g, int i, int j, int k) {
+  if (i < 0 || i >= g.n0) { if (g.bc0) return -1; i = wrapi(i, g.n0); }
+  if (j < 0 || j >= g.n1) { if (g.bc1) return -1; j = wrapi(j, g.n1); }
+  if (k < 0 || k >= g.n2) { if (g.bc2) return -1; k = wrapi(k, g.n2); }
+  return sidx(g, i, j, k);
+}
+
+__global__ void __launch_bounds__(MQ_T) k_mom_rhs(Geo g, double dt, const double *u3, const double *um3,
+                                                  const double *p_, double *out3, double *guess3, int ntk, int ntj,
+                                                  int ntiles) {
+  __shared__ double su[3][3][MQ_PL];  // [ring slot][component][cell]
+  __shared__ double sp[MQ_PP];
   const long long N = 2 * g.half;
-  // XCD-major tile order: block b runs on XCD b % 8
   const int b = blockIdx.x;
   const int per = ntiles / 8;
   const int tile = (ntiles % 8 == 0) ? (b % 8) * per + b / 8 : b;
-  const int tz = tile % ntz, r0 = tile / ntz, ty = r0 % nty, tx = r0 / nty;
-  const int i0 = tx * MR_TX, j0 = ty * MR_TY, k0 = tz * MR_TZ;
+  const int tk = tile % ntk, r0 = tile / ntk, tj = r0 % ntj, tc = r0 / ntj;
+  const int j0 = tj * MQ_BY, k0 = tk * MQ_BK, i0 = tc * MQ_CH;
+  const int i1 = min(i0 + MQ_CH, g.n0);
   const int tid = threadIdx.x;
-  for (int q = tid; q < MR_REG; q += MR_TY * MR_TZ) {
-    const int zk = q % MR_RZ, rr = q / MR_RZ, yj = rr % MR_RY, xi = rr / MR_RY;
-    int gi = i0 - 1 + xi, gj = j0 - 1 + yj, gk = k0 - 1 + zk;
-    bool in = true;
-    if (gi < 0 || gi >= g.n0) { if (g.bc0) in = false; else gi = wrapi(gi, g.n0); }
-    if (gj < 0 || gj >= g.n1) { if (g.bc1) in = false; else gj = wrapi(gj, g.n1); }
-    if (gk < 0 || gk >= g.n2) { if (g.bc2) in = false; else gk = wrapi(gk, g.n2); }
-    const long long e = in ? sidx(g, gi, gj, gk) : 0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) su[c][q] = in ? u3[c * N + e] : 0.0;
-  }
-  __syncthreads();
-  const int cj = tid / MR_TZ, ck = tid % MR_TZ;
+  const int cj = tid / (MQ_BK / 2), ck = 2 * (tid % (MQ_BK / 2));
   const int j = j0 + cj, k = k0 + ck;
-  if (j >= g.n1 || k >= g.n2) return;
-  const double ih = 1.0 / g.h;
-  for (int ci = 0; ci < MR_TX; ++ci) {
-    const int i = i0 + ci;
-    if (i >= g.n0) break;
-    const int x0[3] = {i, j, k};
-    const long long e = sidx(g, i, j, k);
-    // LDS value of component c at offset (dx, dy, dz) from this cell
-    auto U = [&](int c, int dx, int dy, int dz) -> double {
-      return su[c][((ci + 1 + dx) * MR_RY + (cj + 1 + dy)) * MR_RZ + (ck + 1 + dz)];
-    };
+  const bool act = j < g.n1 && k < g.n2;  // n2 is even, so k + 1 < n2 too
+  const double ih = 1.0 / g.h, i2dt = 1.0 / (2.0 * dt);
+  // plane loads: register staging of plane `pl` of the velocity components
+  double ru[MQ_NU][3];
+  auto fetch_u = [&](int pl) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      double v = 0.0, gv = 0.0;
-      if (!(geo_bc(g, d) && x0[d] == 0)) {
-        const int ed0 = d == 0, ed1 = d == 1, ed2 = d == 2;
-        double acc = 0.0;
+    for (int t = 0; t < MQ_NU; ++t) {
+      const int q = tid + t * MQ_T;
+      const int yy = q / MQ_RK, kk = q - yy * MQ_RK;
+      const long long e = q < MQ_PL ? mq_index(g, pl, j0 - 1 + yy, k0 - 1 + kk) : -1;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const int ea0 = a == 0, ea1 = a == 1, ea2 = a == 2;
-          if (a == d) {
+      for (int c = 0; c < 3; ++c) ru[t][c] = e >= 0 ? u3[c * N + e] : 0.0;
+    }
+  };
+  auto store_u = [&](int slot) {
+#pragma unroll
+    for (int t = 0; t < MQ_NU; ++t) {
+      const int q = tid + t * MQ_T;
+      if (q < MQ_PL)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) su[slot][c][q] = ru[t][c];
+    }
+  };
+  double rp[MQ_NP];
+  auto fetch_p = [&](int pl) {
+#pragma unroll
+    for (int t = 0; t < MQ_NP; ++t) {
+      const int q = tid + t * MQ_T;
+      const int yy = q / MQ_PK, kk = q - yy * MQ_PK;
+      const long long e = q < MQ_PP ? mq_index(g, pl, j0 - 1 + yy, k0 - 1 + kk) : -1;
+      rp[t] = e >= 0 ? p_[e] : 0.0;
+    }
+  };
+  auto store_p = [&]() {
+#pragma unroll
+    for (int t = 0; t < MQ_NP; ++t) {
+      const int q = tid + t * MQ_T;
+      if (q < MQ_PP) sp[q] = rp[t];
+    }
+  };
+  // the ring starts with planes i0 - 1 and i0; p of plane i0 - 1 at the own cells
+  double pprev[2] = {0.0, 0.0};
+  if (act) {
+    const long long e0 = mq_index(g, i0 - 1, j, k), e1 = mq_index(g, i0 - 1, j, k + 1);
+    pprev[0] = e0 >= 0 ? p_[e0] : 0.0;
+    pprev[1] = e1 >= 0 ? p_[e1] : 0.0;
+  }
+  fetch_u(i0 - 1);
+  store_u((i0 + 2) % 3);
+  fetch_u(i0);
+  store_u(i0 % 3);
+  fetch_u(i0 + 1);
+  fetch_p(i0);
+  for (int i = i0; i < i1; ++i) {
+    const int sm = (i + 2) % 3, s0 = i % 3, s1 = (i + 1) % 3;
+    __syncthreads();  // the previous plane's readers are done with slot s1 and sp
+    store_u(s1);
+    store_p();
+    __syncthreads();
+    if (i + 1 < i1) {
+      fetch_u(i + 2);  // in flight while this plane is computed
+      fetch_p(i + 1);
+    }
+    if (act) {
+      const int x0[2][3] = {{i, j, k}, {i, j, k + 1}};
+#pragma unroll
+      for (int h2 = 0; h2 < 2; ++h2) {
+        const int cy = cj + 1, cz = ck + 1 + h2;
+        // component c at offset (dx, dy, dz) from this cell
+        auto U = [&](int c, int dx, int dy, int dz) -> double {
+          const int sl = dx < 0 ? sm : (dx > 0 ? s1 : s0);
+          return su[sl][c][(cy + dy) * MQ_RK + cz + dz];
+        };
+        const double pv = sp[(cj + 1) * MQ_PK + ck + 1 + h2];
+        const double plo[3] = {pprev[h2], sp[cj * MQ_PK + ck + 1 + h2], sp[(cj + 1) * MQ_PK + ck + h2]};
+        const long long e = sidx(g, x0[h2][0], x0[h2][1], x0[h2][2]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          double v = 0.0, gv = 0.0;
+          if (!(geo_bc(g, d) && x0[h2][d] == 0)) {
+            const int ed0 = d == 0, ed1 = d == 1, ed2 = d == 2;
+            double acc = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              const int ea0 = a == 0, ea1 = a == 1, ea2 = a == 2;
+              if (a == d) {
+                const double u0 = U(d, 0, 0, 0);
+                const double cp = 0.5 * (u0 + U(d, ea0, ea1, ea2)), cm = 0.5 * (U(d, -ea0, -ea1, -ea2) + u0);
+                acc += (cp * cp - cm * cm) * ih;
+              } else {
+                const int na = geo_n(g, a), bca = geo_bc(g, a);
+                double fp = 0.0, fm = 0.0;
+                if (!(bca && x0[h2][a] == na - 1))
+                  fp = 0.5 * (U(d, 0, 0, 0) + U(d, ea0, ea1, ea2)) * 0.5 *
+                       (U(a, ea0, ea1, ea2) + U(a, ea0 - ed0, ea1 - ed1, ea2 - ed2));
+                if (!(bca && x0[h2][a] == 0))
+                  fm = 0.5 * (U(d, -ea0, -ea1, -ea2) + U(d, 0, 0, 0)) * 0.5 * (U(a, 0, 0, 0) + U(a, -ed0, -ed1, -ed2));
+                acc += (fp - fm) * ih;
+              }
+            }
+            const double gp = (pv - plo[d]) * ih;
+            const double umv = um3[d * N + e];
             const double u0 = U(d, 0, 0, 0);
-            const double cp = 0.5 * (u0 + U(d, ea0, ea1, ea2)), cm = 0.5 * (U(d, -ea0, -ea1, -ea2) + u0);
-            acc += (cp * cp - cm * cm) * ih;
-          } else {
-            const int na = geo_n(g, a), bca = geo_bc(g, a);
-            double fp = 0.0, fm = 0.0;
-            if (!(bca && x0[a] == na - 1))
-              fp = 0.5 * (U(d, 0, 0, 0) + U(d, ea0, ea1, ea2)) * 0.5 *
-                   (U(a, ea0, ea1, ea2) + U(a, ea0 - ed0, ea1 - ed1, ea2 - ed2));
-            if (!(bca && x0[a] == 0))
-              fm = 0.5 * (U(d, -ea0, -ea1, -ea2) + U(d, 0, 0, 0)) * 0.5 * (U(a, 0, 0, 0) + U(a, -ed0, -ed1, -ed2));
-            acc += (fp - fm) * ih;
+            v = (4.0 * u0 - umv) * i2dt - gp - acc;
+            gv = 2.0 * u0 - umv;
           }
+          out3[d * N + e] = v;
+          if (guess3) guess3[d * N + e] = gv;
         }
-        const double lo = fetch(p_, g, i - ed0, j - ed1, k - ed2);
-        const double gp = (p_[e] - lo) * ih;
-        const double umv = um3[d * N + e];
-        v = (4.0 * U(d, 0, 0, 0) - umv) / (2.0 * dt) - gp - acc;
-        gv = 2.0 * U(d, 0, 0, 0) - umv;
+        pprev[h2] = pv;
       }
-      out3[d * N + e] = v;
-      if (guess3) guess3[d * N + e] = gv;
     }
   }
 }
 hipError_t mom_rhs(const Geo &g, double dt, const double *u3, const double *um3, const double *p,
                    double *out3, double *guess3, hipStream_t s) {
-  const int ntx = (g.n0 + MR_TX - 1) / MR_TX, nty = (g.n1 + MR_TY - 1) / MR_TY, ntz = (g.n2 + MR_TZ - 1) / MR_TZ;
-  const int ntiles = ntx * nty * ntz;
-  hipLaunchKernelGGL(k_mom_rhs, dim3(ntiles), dim3(MR_TY * MR_TZ), 0, s, g, dt, u3, um3, p, out3, guess3, ntz, nty,
-                     ntiles);
+  const int ntj = (g.n1 + MQ_BY - 1) / MQ_BY, ntk = (g.n2 + MQ_BK - 1) / MQ_BK;
+  const int nch = (g.n0 + MQ_CH - 1) / MQ_CH;
+  const int ntiles = ntj * ntk * nch;
+  hipLaunchKernelGGL(k_mom_rhs, dim3(ntiles), dim3(MQ_T), 0, s, g, dt, u3, um3, p, out3, guess3, ntk, ntj, ntiles);
   return hipGetLastError();
 }
 
