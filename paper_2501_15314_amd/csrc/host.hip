@@ -80,8 +80,7 @@ struct sim_s {
          *PT3 = nullptr;
   int *COUNTS = nullptr, *TSTART = nullptr, *FILLC = nullptr, *FLAGS = nullptr, *FPOS = nullptr,
       *ACTIVE = nullptr, *SCANTMP = nullptr;
-  int *TCOUNT = nullptr, *TLSTART = nullptr, *TFILL = nullptr, *TLTMP = nullptr, *TLIST = nullptr,
-      *SEGOF = nullptr;
+  int *TCOUNT = nullptr, *TLSTART = nullptr, *TLIST = nullptr;
   long long tl_cap = 0;  // capacity of the touch lists
   int *NZT = nullptr;    // non-empty point tiles
   int nnz = 0;
@@ -262,8 +261,7 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
   int *FLAGS = cv.arr<int>(nt), *FPOS = cv.arr<int>(nt + 1), *ACTIVE = cv.arr<int>(nt);
   int *SCANTMP = cv.arr<int>(nt / 1024 + 16);
   long long tl_cap = 27 * K;  // a point touches at most 3 x 3 x 3 tiles
-  int *TCOUNT = cv.arr<int>(nt), *TLSTART = cv.arr<int>(nt + 1), *TFILL = cv.arr<int>(nt);
-  int *TLTMP = cv.arr<int>(tl_cap), *TLIST = cv.arr<int>(tl_cap), *SEGOF = cv.arr<int>(tl_cap);
+  int *TCOUNT = cv.arr<int>(nt), *TLSTART = cv.arr<int>(nt + 1), *TLIST = cv.arr<int>(tl_cap);
   int *NZT = cv.arr<int>(nt);
   BodyDev *BODIES = (BodyDev *)cv.take(sizeof(BodyDev) * MAX_BODIES);
   BodySpan *SPAN = (BodySpan *)cv.take(sizeof(BodySpan) * MAX_BODIES);
@@ -302,8 +300,8 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
     s->COUNTS = COUNTS; s->TSTART = TSTART; s->FILLC = FILLC; s->FLAGS = FLAGS; s->FPOS = FPOS;
     s->ACTIVE = ACTIVE; s->SCANTMP = SCANTMP; s->BODIES = BODIES;
     s->SPAN = SPAN; s->BSUM = BSUM; s->VPART = VPART;
-    s->TCOUNT = TCOUNT; s->TLSTART = TLSTART; s->TFILL = TFILL; s->TLTMP = TLTMP; s->TLIST = TLIST;
-    s->SEGOF = SEGOF; s->tl_cap = tl_cap; s->NZT = NZT;
+    s->TCOUNT = TCOUNT; s->TLSTART = TLSTART; s->TLIST = TLIST;
+    s->tl_cap = tl_cap; s->NZT = NZT;
     s->PART = PART; s->RED = RED; s->YDEV = YDEV;
     s->COARSEFD = COARSEFD;
     s->fastdiag = fdg;
@@ -421,12 +419,18 @@ sim_status place_and_bin(sim_t s, const std::vector<BodyDev> &bd) {
   s->nnz = nz;
   // fullest point tiles first (ACTIVE, rebuilt below, is the scratch here)
   CKH(order_active(nz, s->ACTIVE, s->TSTART, s->NZT, st));
-  // touch lists of the active tiles (tiles reached by some point's support)
+  // touch lists of the active tiles (tiles reached by some point's support),
+  // counted and filled tile by tile in a fixed order; only the tiles within
+  // one tile of a non-empty point tile can be reached (candidates, compacted
+  // into ACTIVE; their number stays on the device)
+  CKH(fill_i32(s->FLAGS, nt, 0, st));
+  CKH(mark_near(s->g, s->nt0, s->nt1, s->nt2, nz, s->NZT, s->FLAGS, st));
+  CKH(scan_exclusive(s->FLAGS, s->FPOS, nt, s->SCANTMP, st));
+  CKH(compact(nt, s->FLAGS, s->FPOS, s->ACTIVE, st));
   CKH(fill_i32(s->TCOUNT, nt, 0, st));
-  CKH(fill_i32(s->TFILL, nt, 0, st));
-  CKH(touch_count(s->ker, s->g, s->K, s->XS, s->nt0, s->nt1, s->nt2, s->TCOUNT, st));
+  CKH(touch_tiles(s->ker, s->g, s->nt0, s->nt1, s->nt2, (int)std::min<long long>(nt, 27LL * nz), s->FPOS + nt,
+                  s->ACTIVE, s->TSTART, s->XS, s->TCOUNT, nullptr, nullptr, st));
   CKH(scan_exclusive(s->TCOUNT, s->TLSTART, nt, s->SCANTMP, st));
-  CKH(touch_scatter(s->ker, s->g, s->K, s->XS, s->nt0, s->nt1, s->nt2, s->TLSTART, s->TFILL, s->TLTMP, st));
   CKH(positive_flags(nt, s->TCOUNT, s->FLAGS, st));
   CKH(scan_exclusive(s->FLAGS, s->FPOS, nt, s->SCANTMP, st));
   CKH(compact(nt, s->FLAGS, s->FPOS, s->ACTIVE, st));
@@ -437,7 +441,8 @@ sim_status place_and_bin(sim_t s, const std::vector<BodyDev> &bd) {
   memcpy(&na, s->hpin, sizeof(int));
   memcpy(&M, (int *)s->hpin + 1, sizeof(int));
   if (M > s->tl_cap) return fail(s, SIM_EDEVICE, "touch list overflow");
-  CKH(seg_sort(M, na, s->ACTIVE, s->TLSTART, s->TLTMP, s->SEGOF, s->TLIST, st));
+  CKH(touch_tiles(s->ker, s->g, s->nt0, s->nt1, s->nt2, na, nullptr, s->ACTIVE, s->TSTART, s->XS, nullptr,
+                  s->TLSTART, s->TLIST, st));
   // longest touch lists first (FLAGS, no longer needed, takes the old order)
   CKH(order_active(na, s->ACTIVE, s->TLSTART, s->FLAGS, st));
   std::swap(s->ACTIVE, s->FLAGS);

@@ -161,13 +161,14 @@ hipError_t interp_grad(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, c
 hipError_t interp_face(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, const int *tiles,
                        const int *tstart, const double *X, const double *u3, double alpha, const double *y,
                        double beta, double *out, hipStream_t s);
-// touch lists: tiles whose face boxes a point's support meets
-hipError_t touch_count(int ker, const Geo &g, int K, const double *X, int nt0, int nt1, int nt2, int *counts,
-                       hipStream_t s);
-hipError_t touch_scatter(int ker, const Geo &g, int K, const double *X, int nt0, int nt1, int nt2,
-                         const int *start, int *fillc, int *list, hipStream_t s);
-hipError_t seg_sort(int M, int nactive, const int *active, const int *start, const int *tmp, int *seg_of,
-                    int *out, hipStream_t s);
+// Touch lists (the tiles whose face boxes a point's support meets), tile by tile (no atomics, fixed order): with list == nullptr the
+// counts of the listed tiles (tiles == nullptr: tiles 0..ntl-1), else their
+// lists at lstart; ntl bounds the launch, *ntl_dev (if given) is the count
+hipError_t touch_tiles(int ker, const Geo &g, int nt0, int nt1, int nt2, int ntl, const int *ntl_dev,
+                       const int *tiles, const int *tstart, const double *X, int *counts, const int *lstart,
+                       int *list, hipStream_t s);
+// flags[t] = 1 for the tiles within one tile of the n tiles nz[0..n)
+hipError_t mark_near(const Geo &g, int nt0, int nt1, int nt2, int n, const int *nz, int *flags, hipStream_t s);
 hipError_t order_active(int n, const int *active, const int *lstart, int *out, hipStream_t s);
 hipError_t positive_flags(int n, const int *counts, int *flags, hipStream_t s);
 // band: for the active tiles, out += alpha D (W q)   (div = true, cell field)

@@ -325,8 +325,8 @@ hipError_t interp_face(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, c
 // Touch lists.  Tile T owns the cells 4T..4T+3 per axis; for velocity
 // component d its face box also holds the upper face 4T+4 along d (needed by
 // the divergence of its last cell).  A point touches T when its support meets
-// that box for some component.  Lists are built once per placement: count,
-// scan, scatter, then sort each list by sorted-point index.
+// that box for some component.  Lists are built once per placement: count
+// per tile, scan, then fill per tile.
 
 // Range of tiles touched along one axis (union over the components).
 template <int KER>
@@ -340,80 +340,126 @@ __device__ __forceinline__ void touch_range(double x, double ih, int &lo, int &h
   hi = max(fdiv(f0 + W - 1), fdiv(c0 + W - 1));
 }
 
+// Touch lists built tile by tile, without atomics: the 64 lanes of a
+// wavefront walk the points of the neighbouring point tiles of tile t (home
+// tiles within one tile along each axis, wrapped on periodic axes; a point's
+// support never reaches further) in a fixed order (neighbour offsets in
+// lexicographic order, sorted points within a tile) and keep those whose
+// support touches t.  PASS 0 writes the count of every tile; PASS 1 writes the
+// lists of the active tiles by ordered wavefront compaction, so every list
+// has the same order on every run.
 template <int KER, int PASS>
-__global__ void k_touch(Geo g, int K, const double *X, int nt0, int nt1, int nt2, int *counts, const int *start,
-                        int *fillc, int *list) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= K) return;
-  double ih = 1.0 / g.h;
-  int lo[3], hi[3];
-  touch_range<KER>(X[3 * s], ih, lo[0], hi[0]);
-  touch_range<KER>(X[3 * s + 1], ih, lo[1], hi[1]);
-  touch_range<KER>(X[3 * s + 2], ih, lo[2], hi[2]);
-  const int nt[3] = {nt0, nt1, nt2};
-  const int bc[3] = {g.bc0, g.bc1, g.bc2};
+__global__ void __launch_bounds__(256) k_touch_tile(Geo g, int nt0, int nt1, int nt2, int ntl, const int *ntl_dev,
+                                                    const int *tiles, const int *tstart, const double *X,
+                                                    int *counts, const int *lstart, int *list) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = blockIdx.x * 4 + wave;
+  if (w >= ntl || (ntl_dev && w >= *ntl_dev)) return;
+  const int t = tiles ? tiles[w] : w;
+  const int nt[3] = {nt0, nt1, nt2}, bc[3] = {g.bc0, g.bc1, g.bc2};
+  const int tc[3] = {t / (nt1 * nt2), (t / nt2) % nt1, t % nt2};
+  int nb[3][3], nn[3];
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
-    if (bc[a]) { lo[a] = max(lo[a], 0); hi[a] = min(hi[a], nt[a] - 1); }
-  }
-  for (int t0 = lo[0]; t0 <= hi[0]; ++t0)
-    for (int t1 = lo[1]; t1 <= hi[1]; ++t1)
-      for (int t2 = lo[2]; t2 <= hi[2]; ++t2) {
-        int u0 = bc[0] ? t0 : wrapi(t0, nt0), u1 = bc[1] ? t1 : wrapi(t1, nt1), u2 = bc[2] ? t2 : wrapi(t2, nt2);
-        int t = (u0 * nt1 + u1) * nt2 + u2;
-        if (PASS == 0) atomicAdd(&counts[t], 1);
-        else list[start[t] + atomicAdd(&fillc[t], 1)] = s;
+    nn[a] = 0;
+    for (int sft = -1; sft <= 1; ++sft) {
+      int v = tc[a] + sft;
+      if (v < 0 || v >= nt[a]) {
+        if (bc[a]) continue;
+        v = wrapi(v, nt[a]);
       }
+      bool dup = false;
+      for (int q = 0; q < nn[a]; ++q) dup = dup || nb[a][q] == v;
+      if (!dup) nb[a][nn[a]++] = v;
+    }
+  }
+  const double ih = 1.0 / g.h;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const int base = PASS ? lstart[t] : 0;
+  int cnt = 0;
+  for (int q0 = 0; q0 < nn[0]; ++q0)
+    for (int q1 = 0; q1 < nn[1]; ++q1)
+      for (int q2 = 0; q2 < nn[2]; ++q2) {
+        const int n = (nb[0][q0] * nt1 + nb[1][q1]) * nt2 + nb[2][q2];
+        const int p0 = tstart[n], p1 = tstart[n + 1];
+        for (int pb = p0; pb < p1; pb += 64) {
+          const int p = pb + lane;
+          bool hit = false;
+          if (p < p1) {
+            hit = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              int lo, hi;
+              touch_range<KER>(X[3 * p + a], ih, lo, hi);
+              bool in = false;
+              for (int v = lo; v <= hi; ++v) {
+                int u = v;
+                if (u < 0 || u >= nt[a]) {
+                  if (bc[a]) continue;
+                  u = wrapi(u, nt[a]);
+                }
+                in = in || u == tc[a];
+              }
+              hit = hit && in;
+            }
+          }
+          const unsigned long long m = __ballot(hit);
+          if (PASS == 1 && hit) list[base + cnt + __popcll(m & below)] = p;
+          cnt += __popcll(m);
+        }
+      }
+  if (PASS == 0 && lane == 0) counts[t] = cnt;
 }
 
-hipError_t touch_count(int ker, const Geo &g, int K, const double *X, int nt0, int nt1, int nt2, int *counts,
-                       hipStream_t s) {
-  if (K == 0) return hipSuccess;
-  if (ker == KER_PESKIN4)
-    hipLaunchKernelGGL((k_touch<KER_PESKIN4, 0>), dim3(nblk(K, 256)), dim3(256), 0, s, g, K, X, nt0, nt1, nt2,
-                       counts, nullptr, nullptr, nullptr);
-  else
-    hipLaunchKernelGGL((k_touch<KER_ROMA3, 0>), dim3(nblk(K, 256)), dim3(256), 0, s, g, K, X, nt0, nt1, nt2,
-                       counts, nullptr, nullptr, nullptr);
-  return hipGetLastError();
-}
-hipError_t touch_scatter(int ker, const Geo &g, int K, const double *X, int nt0, int nt1, int nt2,
-                         const int *start, int *fillc, int *list, hipStream_t s) {
-  if (K == 0) return hipSuccess;
-  if (ker == KER_PESKIN4)
-    hipLaunchKernelGGL((k_touch<KER_PESKIN4, 1>), dim3(nblk(K, 256)), dim3(256), 0, s, g, K, X, nt0, nt1, nt2,
-                       nullptr, start, fillc, list);
-  else
-    hipLaunchKernelGGL((k_touch<KER_ROMA3, 1>), dim3(nblk(K, 256)), dim3(256), 0, s, g, K, X, nt0, nt1, nt2,
-                       nullptr, start, fillc, list);
+hipError_t touch_tiles(int ker, const Geo &g, int nt0, int nt1, int nt2, int ntl, const int *ntl_dev,
+                       const int *tiles, const int *tstart, const double *X, int *counts, const int *lstart,
+                       int *list, hipStream_t s) {
+  if (ntl == 0) return hipSuccess;
+  const dim3 gr((ntl + 3) / 4), bl(256);
+  if (list == nullptr) {
+    if (ker == KER_PESKIN4)
+      hipLaunchKernelGGL((k_touch_tile<KER_PESKIN4, 0>), gr, bl, 0, s, g, nt0, nt1, nt2, ntl, ntl_dev, tiles,
+                         tstart, X, counts, lstart, list);
+    else
+      hipLaunchKernelGGL((k_touch_tile<KER_ROMA3, 0>), gr, bl, 0, s, g, nt0, nt1, nt2, ntl, ntl_dev, tiles, tstart,
+                         X, counts, lstart, list);
+  } else {
+    if (ker == KER_PESKIN4)
+      hipLaunchKernelGGL((k_touch_tile<KER_PESKIN4, 1>), gr, bl, 0, s, g, nt0, nt1, nt2, ntl, ntl_dev, tiles,
+                         tstart, X, counts, lstart, list);
+    else
+      hipLaunchKernelGGL((k_touch_tile<KER_ROMA3, 1>), gr, bl, 0, s, g, nt0, nt1, nt2, ntl, ntl_dev, tiles, tstart,
+                         X, counts, lstart, list);
+  }
   return hipGetLastError();
 }
 
-// Sort every list segment ascending (entries are distinct point indices):
-// the rank of an entry is the number of smaller entries in its segment.
-__global__ void k_seg_sort(int M, const int *seg_of_tmp, const int *start, const int *tmp, int *out) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= M) return;
-  int t = seg_of_tmp[q];
-  int v = tmp[q];
-  int s0 = start[t], s1 = start[t + 1];
-  int r = 0;
-  for (int p = s0; p < s1; ++p) r += tmp[p] < v;
-  out[s0 + r] = v;
+// Flag the tiles within one tile (per axis, wrapped on periodic axes) of the
+// n non-empty point tiles: the only tiles a point's support can reach.  Every
+// writer stores the same value 1.
+__global__ void k_mark_near(Geo g, int nt0, int nt1, int nt2, int n, const int *nz, int *flags) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= 27 * n) return;
+  const int t = nz[q / 27], o = q % 27;
+  const int nt[3] = {nt0, nt1, nt2}, bc[3] = {g.bc0, g.bc1, g.bc2};
+  const int tc[3] = {t / (nt1 * nt2), (t / nt2) % nt1, t % nt2};
+  const int off[3] = {o / 9 - 1, (o / 3) % 3 - 1, o % 3 - 1};
+  int v[3];
+  for (int a = 0; a < 3; ++a) {
+    v[a] = tc[a] + off[a];
+    if (v[a] < 0 || v[a] >= nt[a]) {
+      if (bc[a]) return;
+      v[a] = wrapi(v[a], nt[a]);
+    }
+  }
+  flags[(v[0] * nt1 + v[1]) * nt2 + v[2]] = 1;
 }
-// segment id of every list slot (from the active-tile list and the starts)
-__global__ void k_seg_ids(int nactive, const int *active, const int *start, int *seg_of) {
-  int a = blockIdx.x;
-  if (a >= nactive) return;
-  int t = active[a];
-  for (int p = start[t] + threadIdx.x; p < start[t + 1]; p += blockDim.x) seg_of[p] = t;
-}
-hipError_t seg_sort(int M, int nactive, const int *active, const int *start, const int *tmp, int *seg_of,
-                    int *out, hipStream_t s) {
-  if (M == 0 || nactive == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_seg_ids, dim3(nactive), dim3(64), 0, s, nactive, active, start, seg_of);
-  hipLaunchKernelGGL(k_seg_sort, dim3(nblk(M, 256)), dim3(256), 0, s, M, seg_of, start, tmp, out);
+hipError_t mark_near(const Geo &g, int nt0, int nt1, int nt2, int n, const int *nz, int *flags, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mark_near, dim3(nblk(27LL * n, 256)), dim3(256), 0, s, g, nt0, nt1, nt2, n, nz, flags);
   return hipGetLastError();
 }
+
 // Active tiles in order of decreasing touch-list length (one workgroup,
 // bucket sort on min(length, 1023)): the spreading workgroups with the most
 // work start first, which shortens the tail of the launch.  Each tile's
