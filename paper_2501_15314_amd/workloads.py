@@ -320,7 +320,10 @@ def make_sedimentation(case: str = "re11", cells_per_d: int = 16,
     """Free sphere of diameter D = 1 released from rest on the vertical centre
     line at height 8.5 D of a 10D x 10D x 15D box with free-slip walls on all
     faces (Sec. 6.1.3).  Units D = 1 and |g| = 1, so that the terminal velocity
-    is Fr and nu = Fr / Re_p.  Marker sphere radius D/2 - h/2, spacing ~h,
+    is Fr and nu = Fr / Re_p.  Markers on a sphere of radius D/2 - h/2 (the
+    regularised force layer reaches about half a cell outside the markers),
+    spacing ~h; the body itself (mass, buoyancy and the volume integrals of
+    Newton-Euler) keeps its physical radius D/2;
     Roma 3-point kernel, time step at CFL 0.1 for a unit velocity, relaxation
     0.6 (the paper's value for the smallest density ratios), outer loop until
     the relative l1 change of the force density drops below 1e-3 (the paper's
@@ -344,7 +347,7 @@ def make_sedimentation(case: str = "re11", cells_per_d: int = 16,
                  precision=precision, krylov_rtol=1e-8, precond=PRECOND_FASTDIAG,
                  outer_iters=3, outer_tol=1e-3, xi=0.6)
     cfg.g = (0.0, 0.0, -1.0)
-    body = Body(center=np.array([5.0, 5.0, 8.5]), vel=np.zeros(3), omega=np.zeros(3), radius=radius,
+    body = Body(center=np.array([5.0, 5.0, 8.5]), vel=np.zeros(3), omega=np.zeros(3), radius=0.5,
                 density_ratio=theta, motion=MOTION_FREE, n_points=n_points)
     u0 = np.zeros((3,) + n)
     return Workload(f"sedimentation_{case}_{n[0]}x{n[1]}x{n[2]}_freeslip", cfg, [body],
