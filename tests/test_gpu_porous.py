@@ -72,3 +72,63 @@ def test_porous_steps():
     print(f"porous 14: total external force z {ft[:, 2].sum():.4e}", flush=True)
     assert ft[:, 2].sum() > 0
     sim.close()
+
+
+def _max_drag(w, periods=1.5):
+    """Largest |C_D| = 8 f_D,z / pi over the last half period of the
+    oscillation z = -A cos(t / A) (U_max = 1, D = 1), with the drag from the
+    force balance of Sec. 6.1.1 for bodies filled with fluid moving rigidly:
+    f_D = V du_c/dt - (sum of the IB forces)."""
+    import math
+    cfg = w.cfg
+    sim = Sim(cfg, w.n_points)
+    sim.set_workload(w)
+    A = 1.0 / w.bodies[0].osc_omega
+    # the markers sit half a cell inside each body's physical radius
+    vol = sum(4.0 / 3.0 * math.pi * (b.radius + 0.5 * cfg.h) ** 3 for b in w.bodies)
+    T = 2.0 * math.pi * A
+    nsteps = int(round(periods * T / cfg.dt))
+    best = 0.0
+    for s in range(nsteps):
+        sim.step(1)
+        t = (s + 1) * cfg.dt
+        if t > (periods - 0.5) * T:
+            _, ft = sim.get_forces()
+            fd = vol * math.cos(t / A) / A - ft[:, 2].sum()
+            best = max(best, abs(8.0 * fd / math.pi))
+    sim.close()
+    return best
+
+
+def test_porous_drag_trends():
+    """The trends the paper reads off its porous-array drag histories
+    (Sec. 6.1.2): the drag coefficient falls as Re grows, the 14-sub-sphere
+    array drags more than the 7-sub-sphere one at every Re, and the denser
+    array approaches the solid sphere.  64 x 64 x 96 (D/h = 16), 1.5
+    periods of the A/D = 1 oscillation."""
+    cd = {}
+    for n_sub in (7, 14):
+        for re in (100.0, 200.0, 300.0):
+            w = wl.make_porous(n_sub, 16, re=re, precision=wl.PREC_FP32MG)
+            w.cfg.helm_rtol = 1e-8
+            cd[(n_sub, re)] = _max_drag(w)
+    # the solid sphere: one body of diameter D in the same box and motion
+    w = wl.make_porous(7, 16, re=100.0, precision=wl.PREC_FP32MG)
+    h = w.cfg.h
+    r = 0.5 - 0.5 * h
+    k = int(round(4.0 * np.pi * r * r / (h * h)))
+    b = w.bodies[0]
+    b.center = np.array([2.0, 2.0, 3.0])
+    b.radius, b.n_points = r, k
+    w.bodies = [b]
+    w.offsets = wl.fibonacci_offsets(k, r)
+    w.cfg.lump_c = wl.lump_constant(wl.DELTA_ROMA3, h, k, r)
+    w.cfg.helm_rtol = 1e-8
+    solid = _max_drag(w)
+    print("max |C_D|: " + ", ".join(f"{n}/{re:.0f}: {v:.3f}" for (n, re), v in sorted(cd.items()))
+          + f", solid/100: {solid:.3f}", flush=True)
+    for n_sub in (7, 14):
+        assert cd[(n_sub, 100.0)] > cd[(n_sub, 200.0)] > cd[(n_sub, 300.0)]
+    for re in (100.0, 200.0, 300.0):
+        assert cd[(14, re)] > cd[(7, re)]
+    assert solid > cd[(14, 100.0)]
