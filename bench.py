@@ -53,6 +53,8 @@ def kernel_bytes(name, N, T, K, nactive, nnz):
         "spread_div": K * 48 + nactive * 64 * 16,
         # SOR half sweep on the three face grids: other colour e, own colour r and e read, own e written
         "helm_sweep": 3 * N * (T / 2 + T / 2 + T / 2 + T / 2),
+        # first SOR sweep from zero: r read, both colours of e written
+        "helm_first": 3 * N * (T + T),
         "helm_resid": 3 * N * (16 + T),
         # momentum right-hand side: u^n, u^{n-1} (3 components each) and p read, rhs written
         "mom_rhs": N * (7 * 8 + 3 * 8),

@@ -356,7 +356,8 @@ enum {
   SIM_PROBE_HELM_RESID = 13,        /* momentum residual */
   SIM_PROBE_VCYCLE = 14,            /* one whole V-cycle (all levels) */
   SIM_PROBE_MOM_RHS = 15,           /* momentum right-hand side with convection */
-  SIM_PROBE_COUNT = 16
+  SIM_PROBE_HELM_FIRST = 16,        /* momentum SOR sweep from zero (both colours) */
+  SIM_PROBE_COUNT = 17
 };
 sim_status sim_probe_enable(sim_t sim, int32_t probe, int32_t on);
 sim_status sim_probe_read(sim_t sim, int32_t probe, int64_t *launches, double *ms, int32_t reset);

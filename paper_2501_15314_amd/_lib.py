@@ -27,7 +27,8 @@ EXPORTS = ["sim_config_check", "sim_workspace_bytes", "sim_create", "sim_destroy
 
 PROBES = dict(smooth_fine=0, smooth_first_fine=1, restrict_fine=2, prolong_fine=3, laplacian=4,
               spread_div=5, spread_face=6, interp_grad=7, interp_face=8, multidot=9,
-              update_norm=10, coarse=11, helm_sweep=12, helm_resid=13, vcycle=14, mom_rhs=15)
+              update_norm=10, coarse=11, helm_sweep=12, helm_resid=13, vcycle=14, mom_rhs=15,
+              helm_first=16)
 
 
 class SimConfig(C.Structure):

@@ -918,9 +918,12 @@ sim_status helm_solve(sim_t s, const double *rhs, double *u, sim_solve_stats *st
     rel = bnorm > 0 ? sqrt(r2) / bnorm : 0.0;
     if (S.nhist < 64) S.hist[S.nhist++] = rel;
     if (rel <= c.helm_rtol || it >= c.helm_maxit) break;
-    CKH(zero_t<T>(E, n3, st));
     const int kin = sweeps_for(rel);
-    for (int k = 0; k < kin; ++k) {
+    {
+      ProbeScope pr(PR_HELM_FIRST, st);
+      CKH((helm_sor_first<T>(g, a0, c.nu, omega, E, R, st)));
+    }
+    for (int k = 1; k < kin; ++k) {
       for (int color = 0; color < 2; ++color) {
         ProbeScope pr(PR_HELM_SWEEP, st);
         CKH((helm_sor<T, T>(g, a0, c.nu, omega, E, R, color, st)));

@@ -13,7 +13,7 @@ namespace ibs {
 enum ProbeId {
   PR_SMOOTH_FINE = 0, PR_SMOOTH_FIRST_FINE, PR_RESTRICT_FINE, PR_PROLONG_FINE, PR_LAP, PR_BAND_DIV,
   PR_BAND_FACE, PR_INTERP_GRAD, PR_INTERP_FACE, PR_MULTIDOT, PR_UPDATE_NORM, PR_COARSE, PR_HELM_SWEEP,
-  PR_HELM_RESID, PR_VCYCLE, PR_MOM_RHS, PR_COUNT
+  PR_HELM_RESID, PR_VCYCLE, PR_MOM_RHS, PR_HELM_FIRST, PR_COUNT
 };
 int probe_begin(int id, hipStream_t s);
 void probe_end(int id, int slot, hipStream_t s);
@@ -63,6 +63,8 @@ hipError_t zero_t(T *x, long long n, hipStream_t s);
 template <typename T, typename TB>
 hipError_t helm_sor(const Geo &g, double a0, double nu, double omega, T *x3, const TB *b3, int color,
                     hipStream_t s);
+template <typename T>
+hipError_t helm_sor_first(const Geo &g, double a0, double nu, double omega, T *x3, const T *b3, hipStream_t s);
 template <typename T>
 hipError_t add_cast(double *y, const T *x, long long n, hipStream_t s);  // y += x
 template <typename T>

@@ -271,6 +271,18 @@ template hipError_t helm_sor<float, float>(const Geo &, double, double, double, 
 template hipError_t helm_sor<double, double>(const Geo &, double, double, double, double *, const double *, int,
                                              hipStream_t);
 
+// The first SOR sweep of a correction solve A e = r from e = 0 (both colours
+// written, so e need not be cleared beforehand).
+template <typename T>
+hipError_t helm_sor_first(const Geo &g, double a0, double nu, double omega, T *x3, const T *b3, hipStream_t s) {
+  MarchShape M = march_shape(g, 3);
+  hipLaunchKernelGGL((k_sweep<T, T, SW_HFIRST>), M.grid, M.block, 0, s, g, x3, b3, 1, g.h2, a0, nu / g.h2, omega);
+  return hipGetLastError();
+}
+template hipError_t helm_sor_first<float>(const Geo &, double, double, double, float *, const float *, hipStream_t);
+template hipError_t helm_sor_first<double>(const Geo &, double, double, double, double *, const double *,
+                                           hipStream_t);
+
 template <typename T>
 __global__ void k_fill_t(T *x, long long n) {
   long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;

@@ -195,6 +195,34 @@ __device__ __forceinline__ void halo_put(T *tile, const Halo<T> &hv, const Geo &
     tile[r * W2 + cidx] = v;
   }
 }
+// halo_put for halos fetched as raw operands: the register part stores
+// xf(i, jj, mm, raw) (0 outside a wall box), the remainder val(i, jj, mm).
+template <typename T, class F, class X>
+__device__ __forceinline__ void halo_put_xf(T *tile, const Halo<T> &hv, const Geo &g, int i, int jbase, int mbase,
+                                            int BX, int BY, F val, X xf) {
+  const int total = 2 * (2 * BX) + 2 * BY, nthr = BX * BY, W2 = 2 * BX + 2;
+  const int tid = threadIdx.x + BX * threadIdx.y;
+#pragma unroll
+  for (int q = 0; q < HALO_REG; ++q) {
+    const int h = tid + q * nthr;
+    if (h < total) {
+      int r, cidx;
+      halo_slot(h, BX, BY, r, cidx);
+      const int jj = mwrap(jbase + r - 1, g.n1, g.bc1);
+      const int mm = mwrap(mbase + cidx - 1, g.hn2, g.bc2);
+      tile[r * W2 + cidx] = (jj >= 0 && mm >= 0 && (unsigned)i < (unsigned)g.n0) ? xf(i, jj, mm, hv.v[q]) : T(0);
+    }
+  }
+  for (int h = tid + HALO_REG * nthr; h < total; h += nthr) {
+    int r, cidx;
+    halo_slot(h, BX, BY, r, cidx);
+    const int jj = mwrap(jbase + r - 1, g.n1, g.bc1);
+    const int mm = mwrap(mbase + cidx - 1, g.hn2, g.bc2);
+    T v = T(0);
+    if (jj >= 0 && mm >= 0 && (unsigned)i < (unsigned)g.n0) v = val(i, jj, mm);
+    tile[r * W2 + cidx] = v;
+  }
+}
 
 }  // namespace ibs
 
@@ -211,7 +239,11 @@ namespace ibs {
 //               wall faces untouched.  Neighbours outside a wall box are 0
 //               (normal walls hold 0, tangential ghosts enter the diagonal:
 //               -u on a no-slip wall, +u on a free-slip wall).
-enum { SW_POISSON = 0, SW_FIRST = 1, SW_HELM = 2 };
+//   SW_HFIRST:  the first SOR sweep of SW_HELM from x = 0, colour 1: the
+//               colour-0 values omega b / (a0 + nu/h^2 diag) are formed on
+//               the fly from b (and stored), then the colour-1 update; one
+//               pass replaces clearing x and two half sweeps.
+enum { SW_POISSON = 0, SW_FIRST = 1, SW_HELM = 2, SW_HFIRST = 3 };
 
 template <typename T, typename TB, int MODE>
 __global__ void __launch_bounds__(256) k_sweep(Geo g, T *x, const TB *b, int color, double h2, double a0,
@@ -230,88 +262,189 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, T *x, const TB *b, int col
   const TB *both = bg + (long long)(1 - c) * g.half;
   const int mbase = blockIdx.x * BX * 2, jbase = blockIdx.y * BY;
   auto row = [&](int i, int jj) { return ((long long)i * g.n1 + jj) * g.hn2; };
-  auto oval = [&](int i, int jj, int mm) -> T {
-    if (MODE == SW_FIRST) {
-      int kk = 2 * mm + ((i + jj) & 1);  // colour-0 cell of row (i, jj) at index mm
-      return (T)h2 * (T)both[row(i, jj) + mm] / (T)cell_nnb(g, i, jj, kk);
+  const long long P = (long long)g.n1 * g.hn2;  // one plane of one colour
+  const int rw = p.j * g.hn2 + p.m0;            // this thread's two cells within a plane
+  const T th2 = (T)h2, ta0 = (T)a0, tnu = (T)nuh2, tom = (T)omega;
+  constexpr bool FIRSTM = MODE == SW_FIRST || MODE == SW_HFIRST;
+  constexpr bool HELMM = MODE == SW_HELM || MODE == SW_HFIRST;
+  // momentum stencil at face (i, jj, kk) of component d: the diagonal count
+  // (2 per axis plus the tangential wall ghosts) and whether it is a wall face
+  auto helm_cell = [&](int i, int jj, int kk, bool &wall) -> int {
+    const int xs[3] = {i, jj, kk};
+    int diag = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      int bca = geo_bc(g, a), na = geo_n(g, a);
+      diag += 2;
+      if (bca && a != d) diag += wall_ghost_diag(bca) * ((xs[a] == 0) + (xs[a] == na - 1));
     }
+    const int xd = d == 0 ? i : (d == 1 ? jj : kk);
+    wall = geo_bc(g, d) && xd == 0;
+    return diag;
+  };
+  // In the first-sweep modes the other-colour operand is formed from the
+  // right-hand side: the loads of the next plane fetch it raw, oxf turns it
+  // into the colour-0 value once the current plane has been computed.
+  auto oxf = [&](int i, int jj, int mm, T bv) -> T {
+    const int kk = 2 * mm + ((i + jj) & 1);  // colour-0 cell of row (i, jj) at index mm
+    if (MODE == SW_FIRST) return th2 * bv / (T)cell_nnb(g, i, jj, kk);
+    bool wall;
+    const int dg = helm_cell(i, jj, kk, wall);
+    return wall ? T(0) : tom * (bv / (ta0 + tnu * (T)dg));
+  };
+  auto oval = [&](int i, int jj, int mm) -> T {
+    if (FIRSTM) return oxf(i, jj, mm, (T)both[row(i, jj) + mm]);
     return oth[row(i, jj) + mm];
   };
-  auto owin = [&](int i) -> V2<T> {
+  // other-colour operand of plane ii (in the domain) at in-plane offset o
+  auto oget = [&](int ii, int o) -> T {
+    if (FIRSTM) return (T)both[ii * P + o];
+    return oth[ii * P + o];
+  };
+  auto owin_ld = [&](int i) -> V2<T> {
     V2<T> v;
     v.x = T(0);
     v.y = T(0);
     int ii = mwrap(i, g.n0, g.bc0);
     if (ii < 0) return v;
-    if (MODE == SW_FIRST) {
-      v.x = oval(ii, p.j, p.m0);
-      v.y = oval(ii, p.j, p.m0 + 1);
-      return v;
-    }
-    return ld2<T>(oth + row(ii, p.j) + p.m0);
+    if (FIRSTM) return ld2<T>(both + ii * P + rw);
+    return ld2<T>(oth + ii * P + rw);
   };
-  const T th2 = (T)h2, ta0 = (T)a0, tnu = (T)nuh2, tom = (T)omega;
+  auto owin_xf = [&](int i, V2<T> v) -> V2<T> {
+    if (!FIRSTM) return v;
+    int ii = mwrap(i, g.n0, g.bc0);
+    if (ii < 0) return v;  // zeros from owin_ld
+    v.x = oxf(ii, p.j, p.m0, v.x);
+    v.y = oxf(ii, p.j, p.m0 + 1, v.y);
+    return v;
+  };
+  // Plane-invariant halo slots of this thread (HALO_REG of them): LDS slot
+  // (-1: none), in-plane offset (-1: outside a wall box) and row / in-row
+  // index; thin tiles load the rest of their halo directly.
+  const int htotal = 2 * (2 * BX) + 2 * BY, nthr = BX * BY, tid = p.tx + BX * p.ty;
+  int hslot[HALO_REG], hoff[HALO_REG], hj[HALO_REG], hm[HALO_REG];
+#pragma unroll
+  for (int q = 0; q < HALO_REG; ++q) {
+    const int h = tid + q * nthr;
+    hslot[q] = -1;
+    hoff[q] = -1;
+    hj[q] = 0;
+    hm[q] = 0;
+    if (h < htotal) {
+      int r, cidx;
+      halo_slot(h, BX, BY, r, cidx);
+      hslot[q] = r * W2 + cidx;
+      const int jj = mwrap(jbase + r - 1, g.n1, g.bc1);
+      const int mm = mwrap(mbase + cidx - 1, g.hn2, g.bc2);
+      if (jj >= 0 && mm >= 0) {
+        hoff[q] = jj * g.hn2 + mm;
+        hj[q] = jj;
+        hm[q] = mm;
+      }
+    }
+  }
+  const bool hrem = htotal > HALO_REG * nthr;
+  auto hfetch = [&](int i, T *hv) {
+#pragma unroll
+    for (int q = 0; q < HALO_REG; ++q) hv[q] = hoff[q] >= 0 ? oget(i, hoff[q]) : T(0);
+  };
+  auto hput = [&](int i, const T *hv) {
+#pragma unroll
+    for (int q = 0; q < HALO_REG; ++q)
+      if (hslot[q] >= 0) tile[hslot[q]] = (FIRSTM && hoff[q] >= 0) ? oxf(i, hj[q], hm[q], hv[q]) : hv[q];
+    if (hrem) {
+      for (int h = tid + HALO_REG * nthr; h < htotal; h += nthr) {
+        int r, cidx;
+        halo_slot(h, BX, BY, r, cidx);
+        const int jj = mwrap(jbase + r - 1, g.n1, g.bc1);
+        const int mm = mwrap(mbase + cidx - 1, g.hn2, g.bc2);
+        tile[r * W2 + cidx] = (jj >= 0 && mm >= 0) ? oval(i, jj, mm) : T(0);
+      }
+    }
+  };
+  // Diagonal of the two cells, axes 1 and 2 (fixed along the march) for
+  // either parity s of the cells' column index k = 2 m + s; axis 0 is added
+  // per plane.  Poisson: the number of missing neighbours; momentum: the
+  // stencil diagonal count and the wall-face flag.
+  int djk[2][2];
+  bool wjk[2][2];
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int k = 2 * (p.m0 + u) + sp;
+      if (HELMM) {
+        int dg = 4;
+        if (g.bc1 && d != 1) dg += wall_ghost_diag(g.bc1) * ((p.j == 0) + (p.j == g.n1 - 1));
+        if (g.bc2 && d != 2) dg += wall_ghost_diag(g.bc2) * ((k == 0) + (k == g.n2 - 1));
+        djk[sp][u] = dg;
+        wjk[sp][u] = d == 1 ? (g.bc1 && p.j == 0) : (d == 2 ? (g.bc2 && k == 0) : false);
+      } else {
+        djk[sp][u] = (g.bc1 ? (p.j == 0) + (p.j == g.n1 - 1) : 0) + (g.bc2 ? (k == 0) + (k == g.n2 - 1) : 0);
+        wjk[sp][u] = false;
+      }
+    }
+  V2<T> prev = owin_xf(p.i0 - 1, owin_ld(p.i0 - 1)), cur = owin_xf(p.i0, owin_ld(p.i0)),
+        next = owin_xf(p.i0 + 1, owin_ld(p.i0 + 1));
+  T hcur[HALO_REG], hnext[HALO_REG];
+  hfetch(p.i0, hcur);
   // software pipeline: the window plane i+2, the halo and the own-colour
   // operands of plane i+1 are loaded while plane i is computed
   auto own_ops = [&](int i, V2<T> &bb, V2<T> &xo) {
-    const long long r = row(i, p.j) + p.m0;
+    const long long r = i * P + rw;
     bb = ld2<T>(bown + r);
     xo.x = T(0);
     xo.y = T(0);
     if (MODE == SW_HELM) xo = ld2<T>((const T *)own + r);
   };
-  V2<T> prev = owin(p.i0 - 1), cur = owin(p.i0), next = owin(p.i0 + 1);
-  Halo<T> hcur = halo_fetch<T>(g, p.i0, jbase, mbase, BX, BY, oval);
   V2<T> bb, xo;
   own_ops(p.i0, bb, xo);
   for (int i = p.i0; i < p.i1; ++i) {
     const bool more = i + 1 < p.i1;
-    V2<T> nn = more ? owin(i + 2) : next;
-    Halo<T> hnext = hcur;
+    V2<T> nn = more ? owin_ld(i + 2) : next;
     V2<T> bbn = bb, xon = xo;
+#pragma unroll
+    for (int q = 0; q < HALO_REG; ++q) hnext[q] = hcur[q];
     if (more) {
-      hnext = halo_fetch<T>(g, i + 1, jbase, mbase, BX, BY, oval);
+      hfetch(i + 1, hnext);
       own_ops(i + 1, bbn, xon);
     }
     tile[(p.ty + 1) * W2 + 2 * p.tx + 1] = cur.x;
     tile[(p.ty + 1) * W2 + 2 * p.tx + 2] = cur.y;
-    halo_put(tile, hcur, g, i, jbase, mbase, BX, BY, oval);
+    hput(i, hcur);
     __syncthreads();
-    const long long r = row(i, p.j) + p.m0;
     T out[2];
     const int s = (c + i + p.j) & 1;
+    // axis-0 part of the diagonal
+    const bool ie = i == 0, il = i == g.n0 - 1;
+    const int di = HELMM ? 2 + ((g.bc0 && d != 0) ? wall_ghost_diag(g.bc0) * (ie + il) : 0)
+                         : (g.bc0 ? ie + il : 0);
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int m = p.m0 + u, k = 2 * m + s, col = 2 * p.tx + 1 + u;
+      const int col = 2 * p.tx + 1 + u;
       const T *trow = tile + (p.ty + 1) * W2;
       T sum = (u ? prev.y : prev.x) + (u ? next.y : next.x) + tile[p.ty * W2 + col] + tile[(p.ty + 2) * W2 + col] +
               trow[col - 1 + s] + trow[col + s];
       T bv = u ? bb.y : bb.x;
-      if (MODE != SW_HELM) {
-        out[u] = (th2 * bv + sum) / (T)cell_nnb(g, i, p.j, k);
+      if (!HELMM) {
+        out[u] = (th2 * bv + sum) / (T)(6 - di - djk[s][u]);
       } else {
-        const int xs[3] = {i, p.j, k};
-        int diag = 0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          int bca = geo_bc(g, a), na = geo_n(g, a);
-          diag += 2;
-          if (bca && a != d) diag += wall_ghost_diag(bca) * ((xs[a] == 0) + (xs[a] == na - 1));
-        }
-        T xv = u ? xo.y : xo.x;
-        const int xd = d == 0 ? i : (d == 1 ? p.j : k);
-        bool wall = geo_bc(g, d) && xd == 0;
+        const int diag = di + djk[s][u];
+        const bool wall = d == 0 ? (g.bc0 && ie) : wjk[s][u];
+        T xv = u ? xo.y : xo.x;  // 0 in SW_HFIRST
         T gs = (bv + tnu * sum) / (ta0 + tnu * (T)diag);
         out[u] = wall ? xv : xv + tom * (gs - xv);
       }
     }
+    const long long r = i * P + rw;
     st2(own + r, out[0], out[1]);
-    if (MODE == SW_FIRST) st2(oth + r, cur.x, cur.y);
+    if (FIRSTM) st2(oth + r, cur.x, cur.y);
     __syncthreads();
     prev = cur;
     cur = next;
-    next = nn;
-    hcur = hnext;
+    next = more ? owin_xf(i + 2, nn) : nn;
+#pragma unroll
+    for (int q = 0; q < HALO_REG; ++q) hcur[q] = hnext[q];
     bb = bbn;
     xo = xon;
   }
