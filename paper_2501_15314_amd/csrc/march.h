@@ -86,20 +86,50 @@ __device__ __forceinline__ int mwrap(int i, int n, int bc) {
   return i;
 }
 
+// Tile coordinates of this workgroup.  The dispatcher deals consecutive
+// workgroups round-robin to the 8 XCDs; with `xcd` set, each XCD walks all
+// row tiles of one plane chunk (grid.z) in turn while the other XCDs take the
+// seven chunks beside it, so the tiles that share halo rows run on one XCD at
+// the same time and those re-reads hit its L2.  Measured, this pays on the
+// three-component momentum grids and costs time on the single-component
+// multigrid levels, which keep the plain order.
+struct MarchBlock {
+  int x, y, z;
+};
+__device__ __forceinline__ MarchBlock march_block(bool xcd) {
+  const unsigned gx = gridDim.x, gxy = gx * gridDim.y;
+  MarchBlock mb;
+  if (xcd && gridDim.z % 8 == 0) {
+    const unsigned b = blockIdx.x + gx * (blockIdx.y + gridDim.y * blockIdx.z);
+    const unsigned slot = b / 8, rem = slot % gxy;
+    mb.x = rem % gx;
+    mb.y = rem / gx;
+    mb.z = (slot / gxy) * 8 + b % 8;
+  } else {
+    mb.x = blockIdx.x;
+    mb.y = blockIdx.y;
+    mb.z = blockIdx.z;
+  }
+  return mb;
+}
+
 // Per-block geometry of a march.
 struct MarchPos {
-  int tx, ty, m0, j, i0, i1, comp;
+  int tx, ty, m0, j, i0, i1, comp, mbase, jbase;
 };
-__device__ __forceinline__ MarchPos march_pos(const Geo &g) {
+__device__ __forceinline__ MarchPos march_pos(const Geo &g, bool xcd) {
   MarchPos p;
+  const MarchBlock mb = march_block(xcd);
   p.tx = threadIdx.x;
   p.ty = threadIdx.y;
-  p.m0 = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
-  p.j = blockIdx.y * blockDim.y + threadIdx.y;
+  p.mbase = mb.x * blockDim.x * 2;
+  p.jbase = mb.y * blockDim.y;
+  p.m0 = p.mbase + 2 * threadIdx.x;
+  p.j = p.jbase + threadIdx.y;
   const int len = march_chunk(g);
   int nch = (g.n0 + len - 1) / len;
-  p.comp = blockIdx.z / nch;
-  int ch = blockIdx.z - p.comp * nch;
+  p.comp = mb.z / nch;
+  int ch = mb.z - p.comp * nch;
   p.i0 = ch * len;
   p.i1 = min(p.i0 + len, g.n0);
   return p;
@@ -249,7 +279,7 @@ template <typename T, typename TB, int MODE>
 __global__ void __launch_bounds__(256) k_sweep(Geo g, T *x, const TB *b, int color, double h2, double a0,
                                                double nuh2, double omega) {
   __shared__ T tile[MARCH_TILE];
-  const MarchPos p = march_pos(g);
+  const MarchPos p = march_pos(g, MODE == SW_HELM || MODE == SW_HFIRST);
   const int BX = blockDim.x, BY = blockDim.y, W2 = 2 * BX + 2;
   const long long N = 2 * g.half;
   const int d = p.comp;
@@ -260,7 +290,7 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, T *x, const TB *b, int col
   T *oth = xg + (long long)(1 - c) * g.half;
   const TB *bown = bg + (long long)c * g.half;
   const TB *both = bg + (long long)(1 - c) * g.half;
-  const int mbase = blockIdx.x * BX * 2, jbase = blockIdx.y * BY;
+  const int mbase = p.mbase, jbase = p.jbase;
   auto row = [&](int i, int jj) { return ((long long)i * g.n1 + jj) * g.hn2; };
   const long long P = (long long)g.n1 * g.hn2;  // one plane of one colour
   const int rw = p.j * g.hn2 + p.m0;            // this thread's two cells within a plane
@@ -466,14 +496,14 @@ __global__ void __launch_bounds__(256) k_apply2(Geo g, const T *x, const double 
                                                 double *part) {
   __shared__ T tile[2][MARCH_TILE];
   __shared__ double red[4];
-  const MarchPos p = march_pos(g);
+  const MarchPos p = march_pos(g, MODE == AP_HRESID);
   const int BX = blockDim.x, BY = blockDim.y, W2 = 2 * BX + 2;
   const long long N = 2 * g.half;
   const int d = p.comp;
   const T *xg = x + d * N;
   const double *bg = b ? b + d * N : nullptr;
   TR *og = out + d * N;
-  const int mbase = blockIdx.x * BX * 2, jbase = blockIdx.y * BY;
+  const int mbase = p.mbase, jbase = p.jbase;
   auto row = [&](int i, int jj) { return ((long long)i * g.n1 + jj) * g.hn2; };
   auto win = [&](int q, int i) -> V2<T> {
     V2<T> v;
