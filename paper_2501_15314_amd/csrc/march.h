@@ -258,6 +258,84 @@ __device__ __forceinline__ void halo_put_xf(T *tile, const Halo<T> &hv, const Ge
 
 namespace ibs {
 
+// Plane-invariant halo slots of a thread (HALO_REG of them): LDS slot (-1:
+// none), in-plane offset (-1: outside a wall box), row and in-row index.
+// Thin tiles (more halo cells than HALO_REG per thread) load the rest of
+// their halo directly.
+struct HaloSlots {
+  int slot[HALO_REG], off[HALO_REG], jj[HALO_REG], mm[HALO_REG];
+  int total, nthr, tid;
+  bool rem;
+};
+__device__ __forceinline__ HaloSlots halo_slots(const Geo &g, int jbase, int mbase, int BX, int BY) {
+  HaloSlots hs;
+  const int W2 = 2 * BX + 2;
+  hs.total = 2 * (2 * BX) + 2 * BY;
+  hs.nthr = BX * BY;
+  hs.tid = threadIdx.x + BX * threadIdx.y;
+  hs.rem = hs.total > HALO_REG * hs.nthr;
+#pragma unroll
+  for (int q = 0; q < HALO_REG; ++q) {
+    const int h = hs.tid + q * hs.nthr;
+    hs.slot[q] = -1;
+    hs.off[q] = -1;
+    hs.jj[q] = 0;
+    hs.mm[q] = 0;
+    if (h < hs.total) {
+      int r, cidx;
+      halo_slot(h, BX, BY, r, cidx);
+      hs.slot[q] = r * W2 + cidx;
+      const int jj = mwrap(jbase + r - 1, g.n1, g.bc1);
+      const int mm = mwrap(mbase + cidx - 1, g.hn2, g.bc2);
+      if (jj >= 0 && mm >= 0) {
+        hs.off[q] = jj * g.hn2 + mm;
+        hs.jj[q] = jj;
+        hs.mm[q] = mm;
+      }
+    }
+  }
+  return hs;
+}
+
+// Stencil diagonal of a thread's two cells k = 2 (m0 + u) + s of row j, split
+// into the part of axes 1 and 2 (fixed along a march along axis 0, tabulated
+// for both parities s) and the part of axis 0 (per plane).  Pressure
+// Laplacian: the number of missing neighbours (the cell has 6 - di - djk);
+// momentum operator on component d: the 7-point diagonal count in units of
+// 1/h^2 (di + djk) with the tangential wall ghosts, and the wall-face flag.
+struct DiagJK {
+  int d[2][2];
+  bool w[2][2];
+  // entries for parity s and (compile-time) cell u, selected without a
+  // dynamic index so that the table stays in registers
+  __device__ __forceinline__ int dg(int s, int u) const { return s ? d[1][u] : d[0][u]; }
+  __device__ __forceinline__ bool wl(int s, int u) const { return s ? w[1][u] : w[0][u]; }
+};
+__device__ __forceinline__ DiagJK diag_jk(const Geo &g, int j, int m0, bool helm, int d) {
+  DiagJK r;
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int k = 2 * (m0 + u) + sp;
+      if (helm) {
+        int dg = 4;
+        if (g.bc1 && d != 1) dg += wall_ghost_diag(g.bc1) * ((j == 0) + (j == g.n1 - 1));
+        if (g.bc2 && d != 2) dg += wall_ghost_diag(g.bc2) * ((k == 0) + (k == g.n2 - 1));
+        r.d[sp][u] = dg;
+        r.w[sp][u] = d == 1 ? (g.bc1 && j == 0) : (d == 2 ? (g.bc2 && k == 0) : false);
+      } else {
+        r.d[sp][u] = (g.bc1 ? (j == 0) + (j == g.n1 - 1) : 0) + (g.bc2 ? (k == 0) + (k == g.n2 - 1) : 0);
+        r.w[sp][u] = false;
+      }
+    }
+  return r;
+}
+__device__ __forceinline__ int diag_i(const Geo &g, int i, bool helm, int d) {
+  const int e = (i == 0) + (i == g.n0 - 1);
+  return helm ? 2 + ((g.bc0 && d != 0) ? wall_ghost_diag(g.bc0) * e : 0) : (g.bc0 ? e : 0);
+}
+
 // One red-black half sweep of colour `color` on the component grids of x.
 //   SW_POISSON: x_c = (h^2 b_c + sum of neighbours) / (number of neighbours)
 //               (Gauss-Seidel for L = G^T G);
@@ -348,42 +426,17 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, T *x, const TB *b, int col
     v.y = oxf(ii, p.j, p.m0 + 1, v.y);
     return v;
   };
-  // Plane-invariant halo slots of this thread (HALO_REG of them): LDS slot
-  // (-1: none), in-plane offset (-1: outside a wall box) and row / in-row
-  // index; thin tiles load the rest of their halo directly.
-  const int htotal = 2 * (2 * BX) + 2 * BY, nthr = BX * BY, tid = p.tx + BX * p.ty;
-  int hslot[HALO_REG], hoff[HALO_REG], hj[HALO_REG], hm[HALO_REG];
-#pragma unroll
-  for (int q = 0; q < HALO_REG; ++q) {
-    const int h = tid + q * nthr;
-    hslot[q] = -1;
-    hoff[q] = -1;
-    hj[q] = 0;
-    hm[q] = 0;
-    if (h < htotal) {
-      int r, cidx;
-      halo_slot(h, BX, BY, r, cidx);
-      hslot[q] = r * W2 + cidx;
-      const int jj = mwrap(jbase + r - 1, g.n1, g.bc1);
-      const int mm = mwrap(mbase + cidx - 1, g.hn2, g.bc2);
-      if (jj >= 0 && mm >= 0) {
-        hoff[q] = jj * g.hn2 + mm;
-        hj[q] = jj;
-        hm[q] = mm;
-      }
-    }
-  }
-  const bool hrem = htotal > HALO_REG * nthr;
+  const HaloSlots hs = halo_slots(g, jbase, mbase, BX, BY);
   auto hfetch = [&](int i, T *hv) {
 #pragma unroll
-    for (int q = 0; q < HALO_REG; ++q) hv[q] = hoff[q] >= 0 ? oget(i, hoff[q]) : T(0);
+    for (int q = 0; q < HALO_REG; ++q) hv[q] = hs.off[q] >= 0 ? oget(i, hs.off[q]) : T(0);
   };
   auto hput = [&](int i, const T *hv) {
 #pragma unroll
     for (int q = 0; q < HALO_REG; ++q)
-      if (hslot[q] >= 0) tile[hslot[q]] = (FIRSTM && hoff[q] >= 0) ? oxf(i, hj[q], hm[q], hv[q]) : hv[q];
-    if (hrem) {
-      for (int h = tid + HALO_REG * nthr; h < htotal; h += nthr) {
+      if (hs.slot[q] >= 0) tile[hs.slot[q]] = (FIRSTM && hs.off[q] >= 0) ? oxf(i, hs.jj[q], hs.mm[q], hv[q]) : hv[q];
+    if (hs.rem) {
+      for (int h = hs.tid + HALO_REG * hs.nthr; h < hs.total; h += hs.nthr) {
         int r, cidx;
         halo_slot(h, BX, BY, r, cidx);
         const int jj = mwrap(jbase + r - 1, g.n1, g.bc1);
@@ -392,28 +445,7 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, T *x, const TB *b, int col
       }
     }
   };
-  // Diagonal of the two cells, axes 1 and 2 (fixed along the march) for
-  // either parity s of the cells' column index k = 2 m + s; axis 0 is added
-  // per plane.  Poisson: the number of missing neighbours; momentum: the
-  // stencil diagonal count and the wall-face flag.
-  int djk[2][2];
-  bool wjk[2][2];
-#pragma unroll
-  for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int k = 2 * (p.m0 + u) + sp;
-      if (HELMM) {
-        int dg = 4;
-        if (g.bc1 && d != 1) dg += wall_ghost_diag(g.bc1) * ((p.j == 0) + (p.j == g.n1 - 1));
-        if (g.bc2 && d != 2) dg += wall_ghost_diag(g.bc2) * ((k == 0) + (k == g.n2 - 1));
-        djk[sp][u] = dg;
-        wjk[sp][u] = d == 1 ? (g.bc1 && p.j == 0) : (d == 2 ? (g.bc2 && k == 0) : false);
-      } else {
-        djk[sp][u] = (g.bc1 ? (p.j == 0) + (p.j == g.n1 - 1) : 0) + (g.bc2 ? (k == 0) + (k == g.n2 - 1) : 0);
-        wjk[sp][u] = false;
-      }
-    }
+  const DiagJK djk = diag_jk(g, p.j, p.m0, HELMM, d);
   V2<T> prev = owin_xf(p.i0 - 1, owin_ld(p.i0 - 1)), cur = owin_xf(p.i0, owin_ld(p.i0)),
         next = owin_xf(p.i0 + 1, owin_ld(p.i0 + 1));
   T hcur[HALO_REG], hnext[HALO_REG];
@@ -445,10 +477,7 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, T *x, const TB *b, int col
     __syncthreads();
     T out[2];
     const int s = (c + i + p.j) & 1;
-    // axis-0 part of the diagonal
-    const bool ie = i == 0, il = i == g.n0 - 1;
-    const int di = HELMM ? 2 + ((g.bc0 && d != 0) ? wall_ghost_diag(g.bc0) * (ie + il) : 0)
-                         : (g.bc0 ? ie + il : 0);
+    const int di = diag_i(g, i, HELMM, d);
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int col = 2 * p.tx + 1 + u;
@@ -457,10 +486,10 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, T *x, const TB *b, int col
               trow[col - 1 + s] + trow[col + s];
       T bv = u ? bb.y : bb.x;
       if (!HELMM) {
-        out[u] = (th2 * bv + sum) / (T)(6 - di - djk[s][u]);
+        out[u] = (th2 * bv + sum) / (T)(6 - di - djk.dg(s, u));
       } else {
-        const int diag = di + djk[s][u];
-        const bool wall = d == 0 ? (g.bc0 && ie) : wjk[s][u];
+        const int diag = di + djk.dg(s, u);
+        const bool wall = d == 0 ? (g.bc0 && i == 0) : djk.wl(s, u);
         T xv = u ? xo.y : xo.x;  // 0 in SW_HFIRST
         T gs = (bv + tnu * sum) / (ta0 + tnu * (T)diag);
         out[u] = wall ? xv : xv + tom * (gs - xv);
@@ -504,14 +533,16 @@ __global__ void __launch_bounds__(256) k_apply2(Geo g, const T *x, const double 
   const double *bg = b ? b + d * N : nullptr;
   TR *og = out + d * N;
   const int mbase = p.mbase, jbase = p.jbase;
-  auto row = [&](int i, int jj) { return ((long long)i * g.n1 + jj) * g.hn2; };
+  const long long P = (long long)g.n1 * g.hn2;  // one plane of one colour
+  const int rw = p.j * g.hn2 + p.m0;            // this thread's cells within a plane
+  constexpr bool HELMM = MODE == AP_HRESID;
   auto win = [&](int q, int i) -> V2<T> {
     V2<T> v;
     v.x = T(0);
     v.y = T(0);
     int ii = mwrap(i, g.n0, g.bc0);
     if (ii < 0) return v;
-    return ld2<T>(xg + (long long)q * g.half + row(ii, p.j) + p.m0);
+    return ld2<T>(xg + (long long)q * g.half + ii * P + rw);
   };
   // software pipeline as in the sweeps: the window plane i+2, both halos and
   // the right-hand side of plane i+1 are loaded while plane i is computed
@@ -519,35 +550,63 @@ __global__ void __launch_bounds__(256) k_apply2(Geo g, const T *x, const double 
     const T *plane = xg + (long long)q * g.half;
     return [=](int ii, int jj, int mm) -> T { return plane[((long long)ii * g.n1 + jj) * g.hn2 + mm]; };
   };
+  const HaloSlots hs = halo_slots(g, jbase, mbase, BX, BY);
+  auto hfetch = [&](int q, int i, T *hv) {
+    const T *plane = xg + (long long)q * g.half + i * P;
+#pragma unroll
+    for (int e = 0; e < HALO_REG; ++e) hv[e] = hs.off[e] >= 0 ? plane[hs.off[e]] : T(0);
+  };
+  auto hput = [&](int q, int i, const T *hv) {
+    T *tq = tile[q];
+#pragma unroll
+    for (int e = 0; e < HALO_REG; ++e)
+      if (hs.slot[e] >= 0) tq[hs.slot[e]] = hv[e];
+    if (hs.rem) {
+      auto val = plane_val(q);
+      for (int h = hs.tid + HALO_REG * hs.nthr; h < hs.total; h += hs.nthr) {
+        int r, cidx;
+        halo_slot(h, BX, BY, r, cidx);
+        const int jj = mwrap(jbase + r - 1, g.n1, g.bc1);
+        const int mm = mwrap(mbase + cidx - 1, g.hn2, g.bc2);
+        tq[r * W2 + cidx] = (jj >= 0 && mm >= 0) ? val(i, jj, mm) : T(0);
+      }
+    }
+  };
   auto rhs = [&](int i, V2<double> *bb) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       bb[q].x = 0.0;
       bb[q].y = 0.0;
-      if (MODE == AP_HRESID) bb[q] = ld2<double>(bg + (long long)q * g.half + row(i, p.j) + p.m0);
+      if (MODE == AP_HRESID) bb[q] = ld2<double>(bg + (long long)q * g.half + i * P + rw);
     }
   };
+  const DiagJK djk = diag_jk(g, p.j, p.m0, HELMM, d);
   V2<T> prv[2], cur[2], nxt[2];
-  Halo<T> hcur[2];
+  T hcur[2][HALO_REG];
   V2<double> bbc[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     prv[q] = win(q, p.i0 - 1);
     cur[q] = win(q, p.i0);
     nxt[q] = win(q, p.i0 + 1);
-    hcur[q] = halo_fetch<T>(g, p.i0, jbase, mbase, BX, BY, plane_val(q));
+    hfetch(q, p.i0, hcur[q]);
   }
   rhs(p.i0, bbc);
   double acc = 0.0;
   for (int i = p.i0; i < p.i1; ++i) {
     const bool more = i + 1 < p.i1;
     V2<T> nn[2];
-    Halo<T> hnext[2];
+    T hnext[2][HALO_REG];
     V2<double> bbn[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       nn[q] = more ? win(q, i + 2) : nxt[q];
-      hnext[q] = more ? halo_fetch<T>(g, i + 1, jbase, mbase, BX, BY, plane_val(q)) : hcur[q];
+      if (more) {
+        hfetch(q, i + 1, hnext[q]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < HALO_REG; ++e) hnext[q][e] = hcur[q][e];
+      }
     }
     if (more) rhs(i + 1, bbn);
     else {
@@ -559,10 +618,11 @@ __global__ void __launch_bounds__(256) k_apply2(Geo g, const T *x, const double 
       T *tq = tile[q];
       tq[(p.ty + 1) * W2 + 2 * p.tx + 1] = cur[q].x;
       tq[(p.ty + 1) * W2 + 2 * p.tx + 2] = cur[q].y;
-      halo_put(tq, hcur[q], g, i, jbase, mbase, BX, BY, plane_val(q));
+      hput(q, i, hcur[q]);
     }
     __syncthreads();
-    const long long r = row(i, p.j) + p.m0;
+    const long long r = i * P + rw;
+    const int di = diag_i(g, i, HELMM, d);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const T *to = tile[1 - q];
@@ -571,25 +631,17 @@ __global__ void __launch_bounds__(256) k_apply2(Geo g, const T *x, const double 
       double o[2];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int m = p.m0 + u, k = 2 * m + s, col = 2 * p.tx + 1 + u;
+        const int col = 2 * p.tx + 1 + u;
         const T *trow = to + (p.ty + 1) * W2;
         double sum = (double)(u ? prv[1 - q].y : prv[1 - q].x) + (double)(u ? nxt[1 - q].y : nxt[1 - q].x) +
                      (double)to[p.ty * W2 + col] + (double)to[(p.ty + 2) * W2 + col] + (double)trow[col - 1 + s] +
                      (double)trow[col + s];
         double xv = (double)(u ? cur[q].y : cur[q].x);
         if (MODE == AP_LAP) {
-          o[u] = ((double)cell_nnb(g, i, p.j, k) * xv - sum) / g.h2;
+          o[u] = ((double)(6 - di - djk.dg(s, u)) * xv - sum) / g.h2;
         } else {
-          const int xs[3] = {i, p.j, k};
-          int diag = 0;
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            int bca = geo_bc(g, a), na = geo_n(g, a);
-            diag += 2;
-            if (bca && a != d) diag += wall_ghost_diag(bca) * ((xs[a] == 0) + (xs[a] == na - 1));
-          }
-          const int xd = d == 0 ? i : (d == 1 ? p.j : k);
-          bool wall = geo_bc(g, d) && xd == 0;
+          const int diag = di + djk.dg(s, u);
+          const bool wall = d == 0 ? (g.bc0 && i == 0) : djk.wl(s, u);
           double rv = (u ? bb.y : bb.x) - ((a0 + nuh2 * diag) * xv - nuh2 * sum);
           o[u] = wall ? 0.0 : rv;
           acc += o[u] * o[u];
@@ -603,7 +655,8 @@ __global__ void __launch_bounds__(256) k_apply2(Geo g, const T *x, const double 
       prv[q] = cur[q];
       cur[q] = nxt[q];
       nxt[q] = nn[q];
-      hcur[q] = hnext[q];
+#pragma unroll
+      for (int e = 0; e < HALO_REG; ++e) hcur[q][e] = hnext[q][e];
       bbc[q] = bbn[q];
     }
   }
