@@ -510,13 +510,16 @@ hipError_t positive_flags(int n, const int *counts, int *flags, hipStream_t s) {
 // (5 face / 4 centre positions per component, zero outside the point's
 // support; the x weights of component d carry q_d).
 //
-// Accumulation: lane L < 56 of every wavefront owns one z-column of a face
-// box (component 0: 5 x 4 columns of 4 faces, component 1: 4 x 5 columns of
-// 4 faces, component 2: 4 x 4 columns of 5 faces).  Wavefront w adds the
-// listed points w, w+4, w+8, ... in list order into registers, with no
-// branch: w_x[ci] w_y[cj] times the five z weights of its column (zeros add
-// nothing).  The four partial sums of a face are added in a fixed order.
-// Every grid value is therefore summed in the same order on every run.
+// Accumulation: lane l < 30 of every half-wavefront owns two neighbouring
+// z-columns (same x, consecutive y) of a face box (component 0: 5 x 4
+// columns of 4 faces, component 1: 4 x 5 columns of 4 faces, component 2:
+// 4 x 4 columns of 5 faces).  Half-wavefront h (0..7) adds the listed points
+// h, h+8, h+16, ... in list order into registers, with no branch:
+// w_x[ci] w_y[cj] times the five z weights of the column (zeros add
+// nothing); the x and z weights serve both columns, so a lane reads 8 LDS
+// values per point for 10 products.  The eight partial sums of a face are
+// added in a fixed order, so every grid value is summed in the same order
+// on every run.
 constexpr int BAND_CH = 64;
 // doubles per point: x[comp][5], y[comp][5], z[comp][5].  The point stride
 // is odd in 8-byte units, so staging writes of consecutive points spread
@@ -529,8 +532,8 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
                                               const int *list, const double *X, const double *q, double alpha,
                                               double *out) {
   // [cand][axis a * 15 + comp * 5 + position]; after the last chunk the same
-  // LDS holds the per-wavefront face sums part[4][3][80]
-  static_assert(4 * 3 * 80 <= BAND_CH * BAND_WS, "face sums must fit the weight buffer");
+  // LDS holds the per-half-wavefront face sums part[8][3][80]
+  static_assert(8 * 3 * 80 <= BAND_CH * BAND_WS, "face sums must fit the weight buffer");
   __shared__ double wts[BAND_CH][BAND_WS];
   double(*part)[3][80] = reinterpret_cast<double(*)[3][80]>(&wts[0][0]);
   const int tile = active[blockIdx.x];
@@ -541,15 +544,21 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
   const int org[3] = {4 * T0, 4 * T1, 4 * T2};
   const int nn[3] = {g.n0, g.n1, g.n2};
   const int bcs[3] = {g.bc0, g.bc1, g.bc2};
-  // the column owned by this lane: component cd, x-y position (ci, cj), nf faces along z
-  const int wv = tid >> 6, lane = tid & 63;
-  const int cd = lane < 20 ? 0 : (lane < 40 ? 1 : 2);
-  const int cl = lane - 20 * cd;
-  const int cby = cd == 1 ? 5 : 4;  // columns along y in this component's box
-  const int ci = min(cl / cby, 4), cj = cl % cby;
+  // Accumulation: each half-wavefront takes every 8th listed point; lane hl
+  // of a half owns, for component cd, the x position ci and the two y
+  // positions cj0, cj0 + 1 (the second absent at the odd end of a 5-wide box)
+  // of a pair of face columns, nf faces along z: 30 of the 32 lanes, 4 LDS
+  // reads per (point, tile) pair and lane instead of 7 with one column each.
+  const int wv = tid >> 6, lane = tid & 63, half = lane >> 5, hl = lane & 31;
+  const int cd = hl < 10 ? 0 : (hl < 22 ? 1 : 2);
+  const int cl = hl - (cd == 0 ? 0 : (cd == 1 ? 10 : 22));
+  const int npair = cd == 1 ? 3 : 2;  // column pairs along y
+  const int cby = cd == 1 ? 5 : 4;    // columns along y in this component's box
+  const int ci = min(cl / npair, 4), cj0 = 2 * (cl % npair);
+  const bool has1 = cj0 + 1 < cby;
   const int nf = cd == 2 ? 5 : 4;
-  const bool owner = lane < 56;
-  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const bool owner = hl < 30;
+  double acc0[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, acc1[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int c0 = s0; c0 < s1; c0 += BAND_CH) {
     const int nc = min(BAND_CH, s1 - c0);
     __syncthreads();
@@ -586,28 +595,40 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
     }
     __syncthreads();
     if (owner) {
-      for (int c = wv; c < nc; c += 4) {
+      for (int c = 2 * wv + half; c < nc; c += 8) {
         const double *W = wts[c] + 5 * cd;
-        const double wab = W[ci] * W[15 + cj];
+        const double wx = W[ci];
+        const double wab0 = wx * W[15 + cj0];
+        const double wab1 = has1 ? wx * W[16 + cj0] : 0.0;
 #pragma unroll
-        for (int fk = 0; fk < 5; ++fk) acc[fk] += wab * W[30 + fk];
+        for (int fk = 0; fk < 5; ++fk) {
+          const double wz = W[30 + fk];
+          acc0[fk] += wab0 * wz;
+          acc1[fk] += wab1 * wz;
+        }
       }
     }
   }
   __syncthreads();
   if (owner) {
+    // face box index: (ci * by + cj) * bz + fk with by = 4 or 5, bz = 4 or 5
+    const int bz = cd == 2 ? 5 : 4, slot = 2 * wv + half;
 #pragma unroll
     for (int fk = 0; fk < 5; ++fk) {
       if (fk < nf) {
-        // face box index: (ci * by + cj) * bz + fk with by = 4 or 5, bz = 4 or 5
-        const int bz = cd == 2 ? 5 : 4;
-        part[wv][cd][(ci * cby + cj) * bz + fk] = acc[fk];
+        part[slot][cd][(ci * cby + cj0) * bz + fk] = acc0[fk];
+        if (has1) part[slot][cd][(ci * cby + cj0 + 1) * bz + fk] = acc1[fk];
       }
     }
   }
   __syncthreads();
   long long N = 2 * g.half;
-  auto face = [&](int d, int idx) { return ((part[0][d][idx] + part[1][d][idx]) + part[2][d][idx]) + part[3][d][idx]; };
+  auto face = [&](int d, int idx) {
+    double f = part[0][d][idx];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) f += part[q][d][idx];
+    return f;
+  };
   if (DIV) {
     if (tid < 64) {
       int ci2 = tid >> 4, cj2 = (tid >> 2) & 3, ck = tid & 3;
