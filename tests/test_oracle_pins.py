@@ -442,6 +442,51 @@ def test_one_way_step_divergence_free_and_slip():
     assert slip1 < 0.7 * slip0
 
 
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_one_way_steps_advect_a_transverse_wave_downstream(axis):
+    """Sign and placement of the convection term in the momentum predictor
+    (Sec. 3.1, eq. ustar: the material derivative du/dt + u.grad u on the
+    left, so N(u^n) enters the right-hand side with a minus sign).
+
+    A uniform stream U0 along `axis` carries a small transverse wave
+    v = eps sin(2 pi x_axis / L) whose velocity points along the next axis;
+    the field is divergence-free, p stays constant and no body is present.
+    The exact solution of the continuous equations is the wave moved
+    downstream by U0 t and damped by exp(-nu k^2 t).  After k steps the
+    oracle's wave must have moved +U0 k dt (to the O(h^2) phase error of
+    central differences and the O(dt) of the explicit term) and kept
+    the viscous amplitude; with the sign of N flipped it moves upstream."""
+    n = [8, 8, 8]
+    n[axis] = 32
+    h = 1.0 / 32
+    g = mac.Grid(tuple(n), h, (P, P, P))
+    U0, eps, nu, dt, k = 1.0, 1e-3, 0.01, 0.002, 25
+    tr = (axis + 1) % 3
+    x = (np.arange(32) + 0.5) * h          # transverse component sits at cell centres along `axis`
+    shape = [1, 1, 1]
+    shape[axis] = 32
+    u = np.zeros((3,) + g.n)
+    u[axis] = U0
+    u[tr] = eps * np.sin(2 * np.pi * x).reshape(shape)
+    st = ostep.State(u.copy(), u.copy(), np.zeros(g.n), np.zeros((0, 3)))
+    none = np.zeros((0, 3))
+    for _ in range(k):
+        st, _ = ostep.one_way_step(g, nu, dt, st, none, none, delta.PESKIN4, 0.375)
+    line = [0, 0, 0]
+    line[axis] = slice(None)
+    v = st.u[tr][tuple(line)]
+    a = 2.0 / 32 * np.sum(v * np.sin(2 * np.pi * x))
+    b = 2.0 / 32 * np.sum(v * np.cos(2 * np.pi * x))
+    shift = np.arctan2(-b, a) / (2 * np.pi)  # v = A sin(2 pi (x - shift))
+    amp = np.hypot(a, b) / eps
+    assert abs(shift - U0 * k * dt) < 0.05 * U0 * k * dt, shift
+    assert abs(amp - np.exp(-nu * (2 * np.pi) ** 2 * k * dt)) < 0.01, amp
+    # the stream itself is untouched and no other component appears
+    assert np.abs(st.u[axis] - U0).max() < 1e-12
+    assert np.abs(st.u[3 - axis - tr]).max() < 1e-12
+    assert np.ptp(st.p) < 1e-10
+
+
 def test_iteration_count_flat_under_refinement():
     """Spectral equivalence (Sec. 5, Sec. 6.2): with the exact Laplacian as
     preconditioner the Krylov count does not grow with resolution."""
