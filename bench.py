@@ -1,27 +1,31 @@
 #!/usr/bin/env python3
-"""Throughput benchmark of the coupled IB pressure-force solve on one MI355X.
+"""Throughput benchmark of the coupled IB pressure-force Schur solve on one MI355X.
 
-Workload: 256^3 staggered grid with no-slip walls, eight spheres of radius
-0.06 with random constant velocities and 18,000 Lagrangian points each
-(144,000 points), nu = 0.005, dt = 0.002 (seeded, synthetic).  A timed step
-is one full time step of the one-way scheme (point placement and binning,
-momentum right-hand side, momentum solve, pressure-force Schur solve, force
-recovery, velocity / pressure / force update), in the FP32-preconditioned
-form; every step performs exactly one Schur solve, so steps/s = Schur
-solves/s.
+Unit of work (one timed step): one sim_solve_schur -- the lumped Schur solve
+S~ p' = b (FGMRES right-preconditioned by one V-cycle per iteration) plus
+the force recovery Phi' (paper Sec. 4.1) -- in the FP32-preconditioned form,
+on the right-hand side of the first time step of the 256^3 workload: a
+no-slip box, eight spheres of radius 0.06 with seeded constant velocities
+and 18,000 Lagrangian points each (144,000 points), nu = 0.005, dt = 0.002,
+fluid at rest.  From rest the momentum predictor gives u* = 0, so the
+first step's system is RHS_p = -D u*/tau = 0 and RHS_F = (W^T u* - U)/tau =
+-U/tau with the points at t = dt.  Inputs are resident in HBM before the
+timed region; value = Schur solves per second at rtol 1e-8.
 
-Printed: one JSON line with the throughput, the isolated Schur-solve rates of
-the FP32-preconditioned and FP64 forms, the roofline of the dominant kernel
-(HIP events around its launches inside the timed region) and the CPU oracle
-baseline on a bounded sample of the same solve.  The per-kernel table comes
-from an untimed instrumented pass of three steps (HIP events around every
-kernel class, about 1 ms per step of event overhead); that pass also names
-the dominant kernel, the only one probed while the timed steps run.
+Printed: one JSON line with the solve rate of the FP32-MG form (value) and
+of the FP64 form, both forms' relative L2 error against the FP64 CPU
+oracle's own solution of the same 256^3 system (GMRES to 1e-13 with its
+exact L^+), the roofline of the dominant kernel of the solve (HIP events and
+algorithmic bytes of every launch of that kernel inside the timed region),
+the whole preconditioner application as an aggregate, the per-kernel table
+of an untimed instrumented pass, solver variants, whole time steps of the
+workloads at 128^3, 256^3 and 384^3, and the CPU oracle baseline rows.
 """
 import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -29,36 +33,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+SINGLE_KERNEL_CLASSES = ("smooth", "smooth_first", "restrict", "prolong", "coarse", "laplacian",
+                         "spread_div", "interp_grad", "multidot", "update_norm")
 
 
-def kernel_bytes(name, N, T, K, nactive, nnz):
-    """Algorithmic (compulsory) bytes of one launch: every operand read once,
-    every result written once.  N cells, T bytes per V-cycle value, K points."""
-    return {
-        # The finest-level right-hand side is the Krylov basis vector, stored
-        # in the V-cycle precision T in both forms.
-        # RB-GS half sweep on the finest grid: other colour x, own colour rhs, own colour x
-        "smooth_fine": N * (T / 2 + T / 2 + T / 2),
-        # first sweep from zero: rhs read, both colours of x written
-        "smooth_first_fine": N * (T + T),
-        # red residual + 8-child restriction: black x, red x, red rhs, coarse rhs
-        "restrict_fine": N * (T / 2 + T / 2 + T / 2 + T / 8),
-        # trilinear correction of the red cells: red x read/written, coarse x
-        "prolong_fine": N * (T + T / 8),
-        # L z inside S~ z: z read, w (f64) written
-        "laplacian": N * (T + 8),
-        # W^T G z: 8^3 region per non-empty tile + positions / results
-        "interp_grad": nnz * 512 * T + K * 48,
-        # D W q on the active tiles: positions and q, read-modify-write of w
-        "spread_div": K * 48 + nactive * 64 * 16,
-        # SOR half sweep on the three face grids: other colour e, own colour r and e read, own e written
-        "helm_sweep": 3 * N * (T / 2 + T / 2 + T / 2 + T / 2),
-        # first SOR sweep from zero: r read, both colours of e written
-        "helm_first": 3 * N * (T + T),
-        "helm_resid": 3 * N * (16 + T),
-        # momentum right-hand side: u^n, u^{n-1} (3 components each) and p read, rhs written
-        "mom_rhs": N * (7 * 8 + 3 * 8),
-    }.get(name)
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def sources_digest(srcs):
@@ -94,8 +74,33 @@ def traffic_record(kernel):
         return None
 
 
-def body_points(w):
-    """Lagrangian point positions at t = 0 (constant-velocity bodies, no rotation)."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def first_step(w):
+    """The workload with its bodies moved to their positions at t = dt, and
+    the first step's Schur right-hand side (RHS_p = 0, RHS_F = -U / tau)."""
+    import copy
+    import numpy as np
+    w1 = copy.deepcopy(w)
+    dt = w.cfg.dt
+    for b in w1.bodies:
+        b.center = b.center + b.vel * dt - b.osc_amp * np.cos(b.osc_omega * dt)
+        b.osc_amp = np.zeros(3)
+        assert not np.any(b.omega), "the benchmark bodies do not rotate"
+    U = np.concatenate([np.tile(b.vel, (b.n_points, 1)) for b in w.bodies])
+    tau = 2.0 * dt / 3.0
+    return w1, np.zeros(w.cfg.n), -U / tau
+
+
+def oracle_points(w):
     import numpy as np
     out, k0 = [], 0
     for b in w.bodies:
@@ -104,58 +109,56 @@ def body_points(w):
     return np.concatenate(out)
 
 
-def cpu_baseline(w, gpu_p, gpu_phi, rp, rf, gpu_iters, budget_iters=3):
-    """FP64 oracle on the same 256^3 system: the Krylov solve is timed for a
-    bounded number of iterations and scaled to the iteration count a full
-    solve at rtol 1e-8 needs; the oracle's own operator also gives the true
-    residual of the GPU solution."""
-    import numpy as np
+def oracle_solve(w, rp, rf, workers, rtol=1e-13):
+    """The FP64 oracle's own Schur solve (sparse S~, GMRES preconditioned by
+    the exact L^+ by FFT/DCT): returns (p', Phi', iterations, seconds of
+    the solve, seconds of the operator assembly)."""
     import scipy.fft
-    from oracle import delta, krylov, mac, poisson, schur
-
-    workers = len(os.sched_getaffinity(0))
-    t0 = time.perf_counter()
+    from oracle import delta, mac, schur
     cfg = w.cfg
+    t0 = time.perf_counter()
     g = mac.Grid(cfg.n, cfg.h, cfg.bc)
-    X = body_points(w)
-    S = schur.SchurSystem(g, delta.regularization_matrix(g, X, cfg.delta), cfg.lump_c)
-    setup = time.perf_counter() - t0
-    b = S.rhs(rp, rf)
+    S = schur.SchurSystem(g, delta.regularization_matrix(g, oracle_points(w), cfg.delta), cfg.lump_c)
+    t1 = time.perf_counter()
     with scipy.fft.set_workers(workers):
-        pre = lambda v: poisson.solve_laplacian(g, v, workers)
-        t1 = time.perf_counter()
-        _, its, _ = krylov.gmres(S.matvec, b, precond=pre, rtol=1e-30, restart=budget_iters,
-                                 maxit=budget_iters)
-        t_iter = (time.perf_counter() - t1) / max(its, 1)
-    n_full = gpu_iters
-    t_solve = t_iter * n_full
-    out = {"value": 1.0 / t_solve, "unit": "Schur solves/s", "cores": workers, "kind": "oracle",
-           "sample": f"FP64 NumPy/SciPy oracle on the same 256^3 system: {its} right-preconditioned "
-                     f"GMRES iterations (exact fast-diagonalisation L^+, sparse S~) timed, "
-                     f"{t_iter:.2f} s/iteration, scaled to the {n_full} iterations of a 1e-8 solve; "
-                     f"operator assembly ({setup:.1f} s) excluded"}
-    res = {}
-    for form, p in gpu_p.items():
-        r = b - S.matvec(p)
-        res[form] = float(np.linalg.norm(r) / np.linalg.norm(b))
-    f_ref = {form: S.force(gpu_p[form], rf) for form in gpu_p}
-    fres = {form: float(np.linalg.norm(gpu_phi[form] - f_ref[form]) / np.linalg.norm(f_ref[form]))
-            for form in gpu_p}
-    return out, res, fres
+        p, phi, its, _ = S.solve(rp, rf, rtol=rtol, workers=workers)
+    t2 = time.perf_counter()
+    return p, phi, its, t2 - t1, t1 - t0
+
+
+def cpu_rows(make_first, workers_all):
+    """Full oracle Schur solves of the first-step system at 32^3 and 128^3,
+    on one core and on all cores."""
+    rows = []
+    for n in (32, 128):
+        w1, rp, rf = make_first(n)
+        for workers in (1, workers_all):
+            p, phi, its, ts, ta = oracle_solve(w1, rp, rf, workers)
+            rows.append({"grid": n, "cores": workers, "iters_to_1e-13": its, "solve_s": round(ts, 3),
+                         "assembly_s": round(ta, 3), "solves_per_s": round(1.0 / ts, 4)})
+            log(f"oracle {n}^3 on {workers} core(s): {its} iterations, {ts:.2f} s")
+    return rows
+
+
+def rel(a, b):
+    import numpy as np
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20, help="timed Schur solves")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle (errors and baseline)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form solve rate")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the solver variants (fast-diagonalisation preconditioner, BiCGStab)")
-    ap.add_argument("--no-two-way", action="store_true",
-                    help="skip the two-way (free body) step timings")
+    ap.add_argument("--no-steps", action="store_true",
+                    help="skip the whole-time-step timings (128^3, 256^3, 384^3 two-way)")
+    ap.add_argument("--c5-steps", type=int, default=100, help="timed two-way steps at 384^3")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the reference "
                          "kernel for scaling HBM byte counters) and exit")
@@ -181,164 +184,194 @@ def main():
     from paper_2501_15314_amd.sim import Sim
 
     n = args.n
-    w = wl.make_c3(n=n, points_per_sphere=int(round(18000 * (n / 256) ** 2)))
-    cfg = w.cfg
-    cfg.precision = wl.PREC_FP32MG
-    cfg.krylov_rtol = 1e-8
-    cfg.helm_rtol = 1e-8
-    print(f"[bench] workload {w.name} n={n} K={w.n_points} steps={args.steps} warmup={args.warmup}",
-          file=sys.stderr, flush=True)
-    sim = Sim(cfg, w.n_points)
-    sim.set_workload(w)
+    pps = int(round(18000 * (n / 256) ** 2))
+
+    def make_first(nn):
+        return first_step(wl.make_c3(n=nn, points_per_sphere=int(round(18000 * (nn / 256) ** 2))))
+
+    w1, rp, rf = make_first(n)
+    K = w1.n_points
+    N = int(np.prod(w1.cfg.n))
+    rpt = torch.as_tensor(rp, device="cuda")
+    rft = torch.as_tensor(rf, device="cuda")
+
+    def make_sim(prec, precond=wl.PRECOND_VCYCLE, krylov=wl.KRYLOV_FGMRES, rtol=1e-8):
+        cfg = wl.make_c3(n=n, points_per_sphere=pps).cfg
+        cfg.precision, cfg.precond, cfg.krylov, cfg.krylov_rtol = prec, precond, krylov, rtol
+        s = Sim(cfg, K)
+        s.set_bodies(w1.bodies, w1.offsets)
+        return s
+
+    log(f"workload c3 first-step system n={n} K={K} steps={args.steps} warmup={args.warmup}")
+    sim = make_sim(wl.PREC_FP32MG)
     for _ in range(args.warmup):
-        sim.step(1)
-    N = int(np.prod(cfg.n))
-    T = 4
-    # tile counts for the band / interpolation byte model (same geometry as the host code)
-    X = body_points(w)
-    cells = np.floor(X / cfg.h).astype(int)
-    nnz = len({tuple(c) for c in (cells // 4)})
-    # instrumented pass (untimed): HIP-event probes around every kernel class
-    # give the per-kernel table and the dominant kernel; the events cost about
-    # a millisecond per step, so the timed steps below probe that kernel only
+        sim.solve_schur(rpt, rft)
+    # untimed instrumented pass: every kernel class probed (HIP events and
+    # algorithmic bytes of every launch) over three solves
     probes = list(_lib.PROBES)
     for p in probes:
         sim.probe(p, True)
         sim.probe_read(p, reset=True)
     for _ in range(3):
-        sim.step(1)
+        sim.solve_schur(rpt, rft)
     kern = {}
     for p in probes:
-        cnt, ms = sim.probe_read(p, reset=True)
+        cnt, ms, nb = sim.probe_read(p, reset=True)
         sim.probe(p, False)
         if cnt:
-            kern[p] = (cnt, ms)
-    dom, dom_t = None, -1.0
-    for name, (cnt, ms) in kern.items():
-        if name != "spread_div" and kernel_bytes(name, N, T, w.n_points, 0, nnz) and ms > dom_t:
-            dom, dom_t = name, ms
-    if dom:
-        sim.probe(dom, True)
-        sim.probe_read(dom, reset=True)
-    iters, helm_iters = [], []
+            kern[p] = (cnt, ms, nb)
+    singles = {k: v for k, v in kern.items() if k in SINGLE_KERNEL_CLASSES}
+    dom = max(singles, key=lambda k: singles[k][1]) if singles else None
+    for p in ([dom] if dom else []) + ["vcycle"]:
+        sim.probe(p, True)
+        sim.probe_read(p, reset=True)
+    # timed region: K solves, the dominant kernel's and the preconditioner's
+    # launches bracketed by events on the solver's stream
+    its = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        st, _ = sim.step(1)
-        iters.append(st.schur.iters)
-        helm_iters.append(st.helm.iters)
+        p32, phi32, st = sim.solve_schur(rpt, rft)
+        its.append(st.iters)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    dom_timed = None
-    if dom:
-        dom_timed = sim.probe_read(dom, reset=True)
-        sim.probe(dom, False)
-    print(f"[bench] {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
-
-    # isolated Schur solves (the metric's unit) on a random right-hand side
-    rp, rf = wl.random_schur_rhs(31, cfg.n, w.n_points)
-    rpt = torch.as_tensor(rp, device="cuda")
-    rft = torch.as_tensor(rf, device="cuda")
-
-    def solve_rate(s):
-        s.solve_schur(rpt, rft)
-        times, its = [], []
-        for _ in range(3):
-            torch.cuda.synchronize()
-            a = time.perf_counter()
-            p, phi, st = s.solve_schur(rpt, rft)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - a)
-            its.append(st.iters)
-        return p.cpu().numpy(), phi.cpu().numpy(), min(times), its[-1]
-
-    gp, gphi, solve_s, solve_its = {}, {}, {}, {}
+    dom_timed = sim.probe_read(dom, reset=True) if dom else None
+    vc_timed = sim.probe_read("vcycle", reset=True)
+    for p in ([dom] if dom else []) + ["vcycle"]:
+        sim.probe(p, False)
+    res32 = st.rel_res
+    p32, phi32 = p32.cpu().numpy(), phi32.cpu().numpy()
     sim.close()
     del sim
     torch.cuda.empty_cache()
-    # the two forms of the metric (FGMRES + V-cycle), then the solver variants:
-    # the paper's own preconditioner (fast diagonalisation of L) and Krylov
-    # method (BiCGStab)
-    forms = [("fp32mg", wl.PREC_FP32MG, wl.PRECOND_VCYCLE, wl.KRYLOV_FGMRES)]
-    if not args.no_fp64:
-        forms.append(("fp64", wl.PREC_FP64, wl.PRECOND_VCYCLE, wl.KRYLOV_FGMRES))
+    log(f"{args.steps} FP32-MG solves in {elapsed:.3f} s ({its[-1]} iterations each)")
+
+    def solve_rate(s, reps=5):
+        s.solve_schur(rpt, rft)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            p, phi, st2 = s.solve_schur(rpt, rft)
+        torch.cuda.synchronize()
+        return p.cpu().numpy(), phi.cpu().numpy(), (time.perf_counter() - a) / reps, st2
+
+    forms = {}
+    gp, gphi = {"fp32mg": p32, }, {"fp32mg": phi32}
+    forms["fp32mg"] = {"solves_per_s": round(args.steps / elapsed, 2), "ms": round(1e3 * elapsed / args.steps, 3),
+                       "iters": its[-1], "rel_res": res32,
+                       "cell_updates_per_s": round(N * its[-1] * args.steps / elapsed, 1)}
+    variants = [("fp64", wl.PREC_FP64, wl.PRECOND_VCYCLE, wl.KRYLOV_FGMRES)] if not args.no_fp64 else []
     if not args.no_variants:
-        for tag, prec in [("fp32mg", wl.PREC_FP32MG), ("fp64", wl.PREC_FP64)]:
-            if prec == wl.PREC_FP64 and args.no_fp64:
-                continue
-            forms += [(f"{tag}_fgmres_fastdiag", prec, wl.PRECOND_FASTDIAG, wl.KRYLOV_FGMRES),
-                      (f"{tag}_bicgstab_vcycle", prec, wl.PRECOND_VCYCLE, wl.KRYLOV_BICGSTAB),
-                      (f"{tag}_bicgstab_fastdiag", prec, wl.PRECOND_FASTDIAG, wl.KRYLOV_BICGSTAB)]
-    for form, prec, precond, krylov in forms:
-        # a fresh solver with the bodies at t = 0, the geometry the oracle check uses
-        cf = wl.make_c3(n=n, points_per_sphere=int(round(18000 * (n / 256) ** 2))).cfg
-        cf.precision = prec
-        cf.precond = precond
-        cf.krylov = krylov
-        cf.krylov_rtol = 1e-8
-        s2 = Sim(cf, w.n_points)
-        s2.set_bodies(w.bodies, w.offsets)
-        gp[form], gphi[form], solve_s[form], solve_its[form] = solve_rate(s2)
+        variants += [("fp32mg_fgmres_fastdiag", wl.PREC_FP32MG, wl.PRECOND_FASTDIAG, wl.KRYLOV_FGMRES),
+                     ("fp32mg_bicgstab_vcycle", wl.PREC_FP32MG, wl.PRECOND_VCYCLE, wl.KRYLOV_BICGSTAB),
+                     ("fp64_bicgstab_vcycle", wl.PREC_FP64, wl.PRECOND_VCYCLE, wl.KRYLOV_BICGSTAB),
+                     ("fp64_bicgstab_fastdiag", wl.PREC_FP64, wl.PRECOND_FASTDIAG, wl.KRYLOV_BICGSTAB)]
+    for form, prec, precond, krylov in variants:
+        s2 = make_sim(prec, precond, krylov)
+        gp[form], gphi[form], tsol, st2 = solve_rate(s2)
+        forms[form] = {"solves_per_s": round(1.0 / tsol, 2), "ms": round(1e3 * tsol, 3), "iters": st2.iters,
+                       "rel_res": st2.rel_res, "cell_updates_per_s": round(N * st2.iters / tsol, 1)}
+        log(f"{form}: {1e3 * tsol:.2f} ms, {st2.iters} iterations")
         s2.close()
         del s2
         torch.cuda.empty_cache()
 
-    # two-way steps (free bodies, three outer passes): the 27 settling spheres
-    # at 384^3 and the single settling sphere in its free-slip box
-    two_way = {}
-    if not args.no_two_way:
-        for tag, make in (("c5_384cube_27free", lambda: wl.make_c5()),
-                          ("sedimentation_160x160x240_freeslip", lambda: wl.make_sedimentation("re11", 16))):
-            wt = make()
-            wt.cfg.outer_tol = 0.0
-            print(f"[bench] two-way {tag} n={wt.cfg.n} K={wt.n_points}", file=sys.stderr, flush=True)
-            st2 = Sim(wt.cfg, wt.n_points)
-            st2.set_workload(wt)
-            st2.step(1, allow_notconv=True)
-            its2 = []
-            torch.cuda.synchronize()
-            a = time.perf_counter()
-            nts = 3
-            for _ in range(nts):
-                sst, _ = st2.step(1, allow_notconv=True)
-                its2.append(sst.total_schur_iters)
-            torch.cuda.synchronize()
-            two_way[tag] = {"ms_per_step": round(1e3 * (time.perf_counter() - a) / nts, 2),
-                            "outer_passes": int(sst.outer), "schur_iters_per_step": float(np.mean(its2)),
-                            "grid": list(wt.cfg.n), "points": wt.n_points, "bodies": len(wt.bodies),
-                            "form": "fp32mg" if wt.cfg.precision == wl.PREC_FP32MG else "fp64",
-                            "precond": "vcycle" if wt.cfg.precond == wl.PRECOND_VCYCLE else "fastdiag"}
-            st2.close()
-            del st2, wt
-            torch.cuda.empty_cache()
+    # random right-hand side (the paper's random-RHS experiment, Sec. 6.2)
+    rrp, rrf = wl.random_schur_rhs(31, w1.cfg.n, K)
+    rand_rhs = {}
+    for form, prec in (("fp32mg", wl.PREC_FP32MG), ("fp64", wl.PREC_FP64)):
+        if form == "fp64" and args.no_fp64:
+            continue
+        s2 = make_sim(prec)
+        a, b = torch.as_tensor(rrp, device="cuda"), torch.as_tensor(rrf, device="cuda")
+        s2.solve_schur(a, b)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, _, st2 = s2.solve_schur(a, b)
+        torch.cuda.synchronize()
+        rand_rhs[form] = {"ms": round(1e3 * (time.perf_counter() - t), 3), "iters": st2.iters}
+        s2.close()
+        del s2
+        torch.cuda.empty_cache()
 
-    nactive = None
+    # whole time steps: the 256^3 workload (one-way, both forms), the
+    # oscillating sphere at 128^3 (50 steps, FP64 then FP32-MG) and the 27
+    # settling spheres at 384^3 (two-way, three outer passes, FP32-MG)
+    steps = {}
+    if not args.no_steps:
+        for tag, make, nsteps, forms_ in (("c3_256cube_8spheres", lambda: wl.make_c3(n=n, points_per_sphere=pps), 10,
+                                           (wl.PREC_FP32MG, wl.PREC_FP64)),
+                                          ("c2_128cube_oscillating_sphere", wl.make_c2, 50,
+                                           (wl.PREC_FP64, wl.PREC_FP32MG)),
+                                          ("c5_384cube_27free_spheres", wl.make_c5, args.c5_steps,
+                                           (wl.PREC_FP32MG,))):
+            for prec in forms_:
+                wt = make()
+                wt.cfg.precision = prec
+                if tag.startswith("c5"):
+                    wt.cfg.outer_tol = 0.0      # every step runs all three passes
+                fname = "fp32mg" if prec == wl.PREC_FP32MG else "fp64"
+                log(f"time steps {tag} {fname} n={wt.cfg.n} K={wt.n_points}")
+                st3 = Sim(wt.cfg, wt.n_points)
+                st3.set_workload(wt)
+                st3.step(1, allow_notconv=True)
+                schur_its = []
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                for _ in range(nsteps):
+                    sst, _ = st3.step(1, allow_notconv=True)
+                    schur_its.append(sst.total_schur_iters)
+                torch.cuda.synchronize()
+                steps[f"{tag}_{fname}"] = {"ms_per_step": round(1e3 * (time.perf_counter() - a) / nsteps, 3),
+                                           "steps": nsteps, "schur_iters_per_step": float(np.mean(schur_its)),
+                                           "outer_passes": int(sst.outer), "grid": list(wt.cfg.n),
+                                           "points": wt.n_points, "bodies": len(wt.bodies)}
+                st3.close()
+                del st3, wt
+                torch.cuda.empty_cache()
+
+    # kernel table of the instrumented pass
     kinfo = {}
-    for name, (cnt, ms) in kern.items():
+    for name, (cnt, ms, nb) in kern.items():
         avg_us = 1e3 * ms / cnt
-        nb = kernel_bytes(name, N, T, w.n_points, nactive or 0, nnz)
-        if name == "spread_div":
-            nb = None  # depends on the active-tile count, reported as time only
-        gbs = (nb / (avg_us * 1e-6) / 1e9) if nb else None
+        gbs = nb / (ms * 1e-3) / 1e9 if nb > 0 else None
         kinfo[name] = {"launches": cnt, "avg_us": round(avg_us, 2), "total_ms": round(ms, 3),
-                       "alg_GBs": round(gbs, 1) if gbs else None}
+                       "alg_bytes_per_launch": round(nb / cnt), "alg_GBs": round(gbs, 1) if gbs else None,
+                       "frac": round(gbs / HBM_PEAK_GBS, 4) if gbs else None}
     roof = None
     if dom and dom_timed and dom_timed[0]:
-        cnt, ms = dom_timed
+        cnt, ms, nb = dom_timed
         avg_s = ms * 1e-3 / cnt
-        nb = kernel_bytes(dom, N, T, w.n_points, 0, nnz)
-        ach = nb / avg_s / 1e9
-        traffic = traffic_record(dom)
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "alg_bytes_per_launch": nb, "avg_launch_us": round(avg_s * 1e6, 2),
-                "launches": cnt}
+        ach = nb / (ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_record(dom),
+                "alg_bytes_per_launch": round(nb / cnt), "avg_launch_us": round(avg_s * 1e6, 2), "launches": cnt}
+    vagg = None
+    if vc_timed and vc_timed[0]:
+        cnt, ms, nb = vc_timed
+        vagg = {"launches": cnt, "avg_us": round(1e3 * ms / cnt, 2), "alg_bytes_per_application": round(nb / cnt),
+                "achieved_GBs": round(nb / (ms * 1e-3) / 1e9, 1),
+                "frac": round(nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
-    cpu = None
-    resid = fres = None
+    cpu, errors = None, {}
     if not args.no_cpu:
-        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        cpu, resid, fres = cpu_baseline(w, gp, gphi, rp, rf, solve_its["fp32mg"])
+        workers = len(os.sched_getaffinity(0))
+        log(f"CPU oracle: the same {n}^3 system on {workers} cores")
+        pref, phiref, oits, ts, ta = oracle_solve(w1, rp, rf, workers)
+        log(f"oracle {n}^3: {oits} iterations, {ts:.1f} s (assembly {ta:.1f} s)")
+        pm = pref - pref.mean()
+        for form in gp:
+            q = gp[form] - gp[form].mean()
+            errors[form] = {"p_rel_err": rel(q, pm), "phi_rel_err": rel(gphi[form], phiref)}
+        rows = cpu_rows(make_first, workers)
+        cpu = {"value": round(1.0 / ts, 5), "unit": "Schur solves/s", "cores": workers, "kind": "oracle",
+               "cpu": cpu_model(),
+               "sample": f"one full FP64 NumPy/SciPy oracle solve of the same {n}^3 first-step system "
+                         f"(sparse S~, GMRES to 1e-13 preconditioned by the exact L^+ by FFT/DCT: "
+                         f"{oits} iterations, {ts:.1f} s; operator assembly {ta:.1f} s excluded); baseline only",
+               "rows": rows}
+        for form, e in errors.items():
+            forms[form].update(e)
 
     value = args.steps / elapsed
     line = {
@@ -354,24 +387,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f64+f32mg",
         "data": "synthetic",
-        "config": {"workload": w.name, "grid": list(cfg.n), "bc": "no-slip walls", "bodies": len(w.bodies),
-                   "points": w.n_points, "form": "fp32mg", "krylov": "fgmres(20)",
-                   "krylov_rtol": cfg.krylov_rtol, "helm_rtol": cfg.helm_rtol, "nu": cfg.nu, "dt": cfg.dt},
-        "schur_iters_per_step": float(np.mean(iters)),
-        "helm_iters_per_step": float(np.mean(helm_iters)),
-        "schur_only": {form: {"solves_per_s": round(1.0 / solve_s[form], 2), "ms": round(1e3 * solve_s[form], 3),
-                              "iters": solve_its[form],
-                              "cell_updates_per_s": round(N * solve_its[form] / solve_s[form], 1),
-                              "oracle_rel_residual": (resid or {}).get(form),
-                              "oracle_force_rel_err": (fres or {}).get(form)}
-                       for form in solve_s if form in ("fp32mg", "fp64")},
-        "schur_variants": {form: {"solves_per_s": round(1.0 / solve_s[form], 2), "ms": round(1e3 * solve_s[form], 3),
-                                  "iters": solve_its[form],
-                                  "oracle_rel_residual": (resid or {}).get(form),
-                                  "oracle_force_rel_err": (fres or {}).get(form)}
-                           for form in solve_s if form not in ("fp32mg", "fp64")},
-        "two_way_steps": two_way,
+        "config": {"workload": f"c3 first-step Schur system, {n}^3 no-slip box, 8 spheres, {K} points",
+                   "grid": list(w1.cfg.n), "bodies": len(w1.bodies), "points": K, "form": "fp32mg",
+                   "krylov": "fgmres(20)", "precond": "vcycle", "krylov_rtol": 1e-8, "nu": w1.cfg.nu,
+                   "dt": w1.cfg.dt},
+        "solves": forms,
+        "random_rhs": rand_rhs,
+        "time_steps": steps,
         "roofline": roof,
+        "precond_aggregate": vagg,
         "kernels": kinfo,
         "cpu_baseline": cpu,
     }

@@ -81,7 +81,12 @@ enum { SIM_MOTION_PRESCRIBED = 0, SIM_MOTION_FREE = 1 };
  * with bfloat16 operands and float32 accumulation; every n[d] a multiple of
  * 8, at most 512 (else sim_create returns SIM_EINVAL).  It builds no
  * multigrid hierarchy, so the mg_* fields and their size rules do not apply. */
-enum { SIM_PRECOND_VCYCLE = 0, SIM_PRECOND_FASTDIAG = 1 };
+/* FASTDIAG_EXACT: the same L^+ exactly, with the eigenbasis transforms in
+ * float64 (six dense mode products on the vector units, 12 n N flops per
+ * application): the paper's exact direct solve for its solver variant
+ * (BiCGStab to 1e-12, Sec. 4.2 and Sec. 6.2).  Needs precision FP64 (else
+ * SIM_EINVAL); any axis sizes; no multigrid hierarchy. */
+enum { SIM_PRECOND_VCYCLE = 0, SIM_PRECOND_FASTDIAG = 1, SIM_PRECOND_FASTDIAG_EXACT = 2 };
 /* FGMRES: flexible GMRES(krylov_restart) with classical Gram-Schmidt.
  * BICGSTAB: right-preconditioned BiCGStab (the Krylov method the paper pairs
  * with the Laplacian preconditioner, Sec. 4.2): two preconditioner and two
@@ -335,15 +340,20 @@ sim_status sim_schur_spectrum(sim_t sim, int32_t exact, const double *d_v0, int3
                               double *lmin, double *lmax);
 
 /* Kernel timing probes (a profiling aid, for throughput / roofline reports).
- * While a probe is enabled, every launch of its kernel class is bracketed by
- * HIP events on the launch stream; sim_probe_read returns the number of
- * probed launches and their summed device time in milliseconds (waiting for
- * the events) and, if reset != 0, clears them.  Probes are process-wide. */
+ * While a probe is enabled on a handle, every launch of its kernel class made
+ * by that handle is bracketed by HIP events on the launch stream and
+ * records its algorithmic bytes (every operand read once, every result
+ * written once, from the launch's sizes; the models are stated where the
+ * kernels are launched).  sim_probe_read returns the number of probed
+ * launches, their summed device time in milliseconds (waiting for the
+ * events) and, if bytes is not NULL, their summed algorithmic bytes; with
+ * reset != 0 it clears them.  Probe state belongs to the handle.  The
+ * multigrid classes cover every level. */
 enum {
-  SIM_PROBE_SMOOTH_FINE = 0,        /* red-black half sweep, finest level */
-  SIM_PROBE_SMOOTH_FIRST_FINE = 1,  /* first sweep from zero, finest level */
-  SIM_PROBE_RESTRICT_FINE = 2,      /* residual + restriction, finest level */
-  SIM_PROBE_PROLONG_FINE = 3,       /* prolongation + correction, finest level */
+  SIM_PROBE_SMOOTH = 0,             /* red-black Gauss-Seidel half sweep, all levels */
+  SIM_PROBE_SMOOTH_FIRST = 1,       /* first sweep from zero, all levels */
+  SIM_PROBE_RESTRICT = 2,           /* residual + restriction, all levels */
+  SIM_PROBE_PROLONG = 3,            /* prolongation + correction, all levels */
   SIM_PROBE_LAPLACIAN = 4,          /* L z inside the S~ product */
   SIM_PROBE_SPREAD_DIV = 5,         /* D W q on the active tiles */
   SIM_PROBE_SPREAD_FACE = 6,        /* W q on the active tiles */
@@ -351,16 +361,17 @@ enum {
   SIM_PROBE_INTERP_FACE = 8,        /* W^T u */
   SIM_PROBE_MULTIDOT = 9,           /* Gram-Schmidt dot products */
   SIM_PROBE_UPDATE_NORM = 10,       /* Gram-Schmidt update and norm */
-  SIM_PROBE_COARSE = 11,            /* coarse-grid LDS kernel */
+  SIM_PROBE_COARSE = 11,            /* coarsest-grid solve */
   SIM_PROBE_HELM_SWEEP = 12,        /* momentum red-black SOR half sweep */
   SIM_PROBE_HELM_RESID = 13,        /* momentum residual */
-  SIM_PROBE_VCYCLE = 14,            /* one whole V-cycle (all levels) */
+  SIM_PROBE_VCYCLE = 14,            /* one whole preconditioner application (all its kernels) */
   SIM_PROBE_MOM_RHS = 15,           /* momentum right-hand side with convection */
   SIM_PROBE_HELM_FIRST = 16,        /* momentum SOR sweep from zero (both colours) */
   SIM_PROBE_COUNT = 17
 };
 sim_status sim_probe_enable(sim_t sim, int32_t probe, int32_t on);
-sim_status sim_probe_read(sim_t sim, int32_t probe, int64_t *launches, double *ms, int32_t reset);
+sim_status sim_probe_read(sim_t sim, int32_t probe, int64_t *launches, double *ms, double *bytes,
+                          int32_t reset);
 
 /* Message of the last failing call on this handle ("" if none). */
 const char *sim_last_error(sim_t sim);

@@ -21,11 +21,12 @@ OPS = dict(laplacian=0, schur=1, precond=2, grad=3, div=4, interp=5, spread=6, h
            convection=8, helm_solve=9, schur_rhs=10, schur_exact=11)
 
 EXPORTS = ["sim_config_check", "sim_workspace_bytes", "sim_create", "sim_destroy", "sim_set_bodies", "sim_set_fields",
-           "sim_get_fields", "sim_step", "sim_solve_schur", "sim_get_forces", "sim_get_points",
+           "sim_get_fields", "sim_step", "sim_solve_schur", "sim_get_forces",
+           "sim_get_points",
            "sim_get_body_state", "sim_set_time",
            "sim_step_adjoint", "sim_step_adjoint_two_way", "sim_apply", "sim_schur_spectrum", "sim_probe_enable", "sim_probe_read", "sim_last_error"]
 
-PROBES = dict(smooth_fine=0, smooth_first_fine=1, restrict_fine=2, prolong_fine=3, laplacian=4,
+PROBES = dict(smooth=0, smooth_first=1, restrict=2, prolong=3, laplacian=4,
               spread_div=5, spread_face=6, interp_grad=7, interp_face=8, multidot=9,
               update_norm=10, coarse=11, helm_sweep=12, helm_resid=13, vcycle=14, mom_rhs=15,
               helm_first=16)
@@ -93,7 +94,7 @@ def load(path: str = LIB_PATH):
     lib.sim_step_adjoint_two_way.argtypes = [sim_t, VP, VP, VP, VP, VP, P(D), VP, VP, VP, VP, P(D)]
     lib.sim_schur_spectrum.argtypes = [sim_t, I32, VP, I32, D, P(D), P(D), P(I32), P(D), P(D)]
     lib.sim_probe_enable.argtypes = [sim_t, I32, I32]
-    lib.sim_probe_read.argtypes = [sim_t, I32, P(I64), P(D), I32]
+    lib.sim_probe_read.argtypes = [sim_t, I32, P(I64), P(D), P(D), I32]
     lib.sim_last_error.argtypes = [sim_t]
     lib.sim_last_error.restype = C.c_char_p
     for name in EXPORTS:

@@ -1,13 +1,15 @@
 """torch.autograd form of the one-way time step (argument marshalling only).
 
-ib_step(sim, u, um, p, phi, centers, vels, omegas) advances one step of the
-scheme of Sec. 3.1 with one pressure-force correction and returns
+ib_step(sim, u, um, p, phi, centers, vels, omegas, offsets=None) advances one
+step of the scheme of Sec. 3.1 with one pressure-force correction and returns
 (u^{n+1}, p^{n+1}, Phi^{n+1}).  The bodies are rigid spheres whose points sit
-at X_k = centers_b + X~_k (the offsets given to sim.set_bodies, taken as the
-orientation of the step) and move with U_k = vels_b + omegas_b x X~_k, all at
-t^{n+1}.  Gradients flow to every argument: u^n, u^{n-1}, p^n, Phi^n through
-the transposed step, centers through dl/dX_k summed over each body's points,
-vels and omegas through dl/dU_k.
+at X_k = centers_b + X~_k (X~_k: `offsets`, [K][3], or the offsets given to
+sim.set_bodies, taken as the orientation of the step) and move with
+U_k = vels_b + omegas_b x X~_k, all at t^{n+1}.  Gradients flow to every
+argument: u^n, u^{n-1}, p^n, Phi^n through the transposed step, centers
+through dl/dX_k summed over each body's points, the offsets through dl/dX_k
+itself (with zero angular velocities: the lever-arm term of omegas x X~_k is
+not formed), vels and omegas through dl/dU_k.
 
 The backward pass recomputes its step from the saved inputs before running
 sim_step_adjoint (checkpointing: the handle's state may have moved on), so
@@ -22,7 +24,7 @@ import torch
 from .workloads import MOTION_PRESCRIBED, Body
 
 
-def _place(sim, centers, vels, omegas):
+def _place(sim, centers, vels, omegas, offsets=None):
     """Prescribed bodies whose kinematics at t^{n+1} = 0 are the given ones."""
     bodies = []
     c = centers.detach().cpu().numpy()
@@ -35,11 +37,12 @@ def _place(sim, centers, vels, omegas):
     # with t^n = -dt the step places the points at t^{n+1} = 0, where the
     # prescribed centre is `center` and the orientation is the identity
     sim.set_time(-sim.cfg.dt)
-    sim.set_bodies(bodies, sim.offsets)
+    off = sim.offsets if offsets is None else offsets.detach().cpu().numpy()
+    sim.set_bodies(bodies, off)
 
 
-def _forward(sim, u, um, p, phi, centers, vels, omegas):
-    _place(sim, centers, vels, omegas)
+def _forward(sim, u, um, p, phi, centers, vels, omegas, offsets=None):
+    _place(sim, centers, vels, omegas, offsets)
     sim.set_fields(0, u, p, phi)
     sim.set_fields(1, um)
     st, rc = sim.step(1)
@@ -50,19 +53,22 @@ def _forward(sim, u, um, p, phi, centers, vels, omegas):
 
 class IBStep(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, sim, u, um, p, phi, centers, vels, omegas):
+    def forward(ctx, sim, u, um, p, phi, centers, vels, omegas, offsets):
         if sim.cfg.outer_iters != 1:
             raise ValueError("the differentiable step takes one correction (outer_iters = 1)")
-        out = _forward(sim, u, um, p, phi, centers, vels, omegas)
+        if offsets is not None and offsets.requires_grad and bool(torch.any(omegas != 0)):
+            raise ValueError("gradients with respect to the offsets need zero angular velocities")
+        out = _forward(sim, u, um, p, phi, centers, vels, omegas, offsets)
         ctx.sim = sim
-        ctx.save_for_backward(u, um, p, phi, centers, vels, omegas)
+        ctx.has_off = offsets is not None
+        ctx.save_for_backward(u, um, p, phi, centers, vels, omegas, offsets)
         return out
 
     @staticmethod
     def backward(ctx, gu, gp, gphi):
         sim = ctx.sim
-        u, um, p, phi, centers, vels, omegas = ctx.saved_tensors
-        _forward(sim, u, um, p, phi, centers, vels, omegas)
+        u, um, p, phi, centers, vels, omegas, offsets = ctx.saved_tensors
+        _forward(sim, u, um, p, phi, centers, vels, omegas, offsets if ctx.has_off else None)
         r = sim.step_adjoint(gu, gp, gphi, want_inputs=True)
         gX = r["gX"]
         gc = torch.stack([gX[b0:b0 + b.n_points].sum(dim=0) for b0, b in
@@ -70,8 +76,9 @@ class IBStep(torch.autograd.Function):
         dev = centers.device
         gv = torch.as_tensor(r["gU"], dtype=torch.float64, device=dev)
         gw = torch.as_tensor(r["gW"], dtype=torch.float64, device=dev)
-        return None, r["gu"], r["gum"], r["gp"], r["gphi"], gc.to(dev), gv, gw
+        goff = gX.to(dev) if ctx.has_off else None
+        return None, r["gu"], r["gum"], r["gp"], r["gphi"], gc.to(dev), gv, gw, goff
 
 
-def ib_step(sim, u, um, p, phi, centers, vels, omegas):
-    return IBStep.apply(sim, u, um, p, phi, centers, vels, omegas)
+def ib_step(sim, u, um, p, phi, centers, vels, omegas, offsets=None):
+    return IBStep.apply(sim, u, um, p, phi, centers, vels, omegas, offsets)

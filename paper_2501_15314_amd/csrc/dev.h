@@ -17,10 +17,16 @@
 
 namespace ibs {
 
+// Plane-marching kernels shorten their chunks of planes until a grid has at
+// least this many workgroups (coarse multigrid levels); 0 keeps full chunks
+// on every grid.
+constexpr int MARCH_MIN_BLOCKS_DEFAULT = 2048;
+
 struct Geo {
   int n0, n1, n2, hn2;
   long long half;   // n0*n1*hn2
   int bc0, bc1, bc2;  // 0 periodic, 1 no-slip wall, 2 free-slip wall (Neumann for cell fields)
+  int march_min_blocks;  // see MARCH_MIN_BLOCKS_DEFAULT
   double h, h2;     // cell width and its square
 };
 

@@ -15,10 +15,12 @@
 //     relaxations at the optimal factor for the constant-coefficient A.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/ibschur.h"
@@ -30,6 +32,7 @@ namespace {
 
 constexpr int MAX_BODIES = 4096;
 constexpr int MAX_RESTART = 64;
+static_assert(KCOEF_MAX >= MAX_RESTART + 1, "FGMRES writes sig_{j+1}^2 for j < MAX_RESTART");
 constexpr double FP32_CYCLE_DROP = 1e-6;
 
 struct HostBody {
@@ -82,9 +85,9 @@ struct sim_s {
       *ACTIVE = nullptr, *SCANTMP = nullptr;
   int *TCOUNT = nullptr, *TLSTART = nullptr, *TLIST = nullptr;
   long long tl_cap = 0;  // capacity of the touch lists
-  int *NZT = nullptr;    // non-empty point tiles
-  int nnz = 0;
-  int nactive = 0;
+  int *NZT = nullptr;    // non-empty point tiles in launch order (-1: hole)
+  int nnz = 0;           // launch count of NZT
+  int nactive = 0;       // launch count of ACTIVE (active tiles in launch order)
   int ntouch = 0;
   BodyDev *BODIES = nullptr;
   std::vector<HostBody> bodies;
@@ -109,17 +112,25 @@ struct sim_s {
   bool adj2_ready = false;
   std::vector<double> rec_body, rec_pre;
   // reductions
-  double *PART = nullptr, *RED = nullptr, *YDEV = nullptr;
+  double *PART = nullptr, *RED = nullptr;
   double *COARSEFD = nullptr;  // eigen-decomposition of the coarsest grid (exact coarse solve)
   // whole-grid fast-diagonalisation preconditioner: eigenbases (float) and two
   // bfloat16 scratch grids
   bool fastdiag = false;
+  bool fdx = false;                // exact float64 fast diagonalisation (preconditioner)
+  double *FDXQ = nullptr;          // its eigenbases and eigenvalues (fdx_blob_pack)
+  double *FDX1 = nullptr, *FDX2 = nullptr;  // two natural-layout float64 work grids
   bool coarse_mfma = false;  // exact coarse solve on the matrix cores
   unsigned char *FDQ = nullptr;  // packed eigenbases (fd_blob_pack)
   double *BCG = nullptr;  // BiCGStab vectors r, r^, p, v, s, t (float64)
   unsigned short *FDW1 = nullptr, *FDW2 = nullptr;
   double *hpin = nullptr;
   double *hpin_dev = nullptr;  // device address of hpin
+  // kernel timing probes of this handle; the timing events of a Schur solve
+  ProbeState *probes = nullptr;
+  hipEvent_t ev_solve[2] = {nullptr, nullptr};
+  // multigrid level sizes (3 per level, finest first)
+  std::vector<int> dims;
   // last-step statistics
   sim_step_stats last{};
   bool have_bodies = false;
@@ -158,6 +169,15 @@ struct Carver {
 
 bool is_even(int x) { return (x & 1) == 0; }
 
+// IBSCHUR_MARCH_FULL_CHUNKS=1 in the environment at sim_create: every grid,
+// however small, runs the plane-marching kernels with their full chunk of
+// planes per workgroup, the launch shape of the large grids (so that small
+// test problems exercise the same register-window code paths).
+int march_min_blocks_setting() {
+  const char *e = getenv("IBSCHUR_MARCH_FULL_CHUNKS");
+  return (e && e[0] == '1' && e[1] == '\0') ? 0 : MARCH_MIN_BLOCKS_DEFAULT;
+}
+
 // Validate the configuration; fills the level dimensions. Returns "" if ok.
 std::string validate(const sim_config *c, std::vector<int> *dims) {
   if (!c) return "null config";
@@ -178,7 +198,11 @@ std::string validate(const sim_config *c, std::vector<int> *dims) {
   if (c->krylov_maxit < 1) return "krylov_maxit must be >= 1";
   if (!(c->krylov_rtol > 0)) return "krylov_rtol must be > 0";
   if (c->mg_pre < 1 || c->mg_post < 0 || c->mg_coarse_sweeps < 0) return "mg_pre >= 1, mg_coarse_sweeps >= 0";
-  if (c->precond != SIM_PRECOND_VCYCLE && c->precond != SIM_PRECOND_FASTDIAG) return "bad precond";
+  if (c->precond != SIM_PRECOND_VCYCLE && c->precond != SIM_PRECOND_FASTDIAG &&
+      c->precond != SIM_PRECOND_FASTDIAG_EXACT)
+    return "bad precond";
+  if (c->precond == SIM_PRECOND_FASTDIAG_EXACT && c->precision != SIM_PREC_FP64)
+    return "the exact fast-diagonalisation preconditioner runs in float64: precision must be FP64";
   if (c->krylov != SIM_KRYLOV_FGMRES && c->krylov != SIM_KRYLOV_BICGSTAB) return "bad krylov method";
   if (c->outer_iters < 1) return "outer_iters must be >= 1";
   if (c->helm_maxit < 1 || !(c->helm_rtol > 0)) return "helm_maxit >= 1 and helm_rtol > 0";
@@ -190,7 +214,7 @@ std::string validate(const sim_config *c, std::vector<int> *dims) {
   if (dims) { dims->push_back(n0); dims->push_back(n1); dims->push_back(n2); }
   // exact coarse solves (mg_coarse_sweeps = 0) take any coarsest grid: small
   // ones in one LDS workgroup, larger ones on the matrix cores
-  const bool fdg = c->precond == SIM_PRECOND_FASTDIAG;
+  const bool fdg = c->precond == SIM_PRECOND_FASTDIAG || c->precond == SIM_PRECOND_FASTDIAG_EXACT;
   const bool exact = fdg || c->mg_coarse_sweeps == 0;
   while (!fdg && (std::max(n0, std::max(n1, n2)) > c->mg_coarsest ||
                   (!exact && (long long)n0 * n1 * n2 > coarse_max_cells()))) {
@@ -213,22 +237,107 @@ std::string validate(const sim_config *c, std::vector<int> *dims) {
   return "";
 }
 
+// The arrays a pressure-force Schur solve works in besides the handle's
+// state (points, tiles, touch lists, eigenbases): staged right-hand sides,
+// the Krylov basis and preconditioned vectors, BiCGStab vectors, the
+// multigrid levels below the finest, the point work vector of S~, the
+// fast-diagonalisation work grids and the reduction partials.
+struct SolveScratch {
+  double *RHSP = nullptr, *BVEC = nullptr, *PP = nullptr, *TMPC = nullptr, *BCG = nullptr;
+  void *V = nullptr, *Z = nullptr;
+  static constexpr int MAX_LEVELS = 24;
+  int nlv = 0;                       // levels below the finest
+  void *lvx[MAX_LEVELS] = {}, *lvb[MAX_LEVELS] = {};
+  double *Q = nullptr, *RF = nullptr, *PHIP = nullptr, *PART = nullptr, *RED = nullptr;
+  unsigned short *FDW1 = nullptr, *FDW2 = nullptr;
+  double *FDX1 = nullptr, *FDX2 = nullptr;
+};
+
+void put_solve_scratch(sim_s *s, const SolveScratch &q) {
+  s->RHSP = q.RHSP; s->BVEC = q.BVEC; s->PP = q.PP; s->TMPC = q.TMPC; s->BCG = q.BCG;
+  s->V = q.V; s->Z = q.Z;
+  for (int l = 0; l < q.nlv; ++l) {
+    s->lv[l + 1].x = q.lvx[l];
+    s->lv[l + 1].b = q.lvb[l];
+  }
+  s->Q = q.Q; s->RF = q.RF; s->PHIP = q.PHIP; s->PART = q.PART; s->RED = q.RED;
+  s->FDW1 = q.FDW1; s->FDW2 = q.FDW2;
+  s->FDX1 = q.FDX1; s->FDX2 = q.FDX2;
+}
+
+SolveScratch get_solve_scratch(const sim_s *s) {
+  SolveScratch q;
+  q.RHSP = s->RHSP; q.BVEC = s->BVEC; q.PP = s->PP; q.TMPC = s->TMPC; q.BCG = s->BCG;
+  q.V = s->V; q.Z = s->Z;
+  for (size_t l = 1; l < s->lv.size() && q.nlv < SolveScratch::MAX_LEVELS; ++l) {
+    q.lvx[q.nlv] = s->lv[l].x;
+    q.lvb[q.nlv] = s->lv[l].b;
+    ++q.nlv;
+  }
+  q.Q = s->Q; q.RF = s->RF; q.PHIP = s->PHIP; q.PART = s->PART; q.RED = s->RED;
+  q.FDW1 = s->FDW1; q.FDW2 = s->FDW2;
+  q.FDX1 = s->FDX1; q.FDX2 = s->FDX2;
+  return q;
+}
+
+// Whether the configuration runs a fast diagonalisation on the matrix cores
+// (whole-grid preconditioner, or a coarsest grid too large for the LDS solver).
+void fd_flags(const sim_config *c, const std::vector<int> &dims, bool &fdg, bool &fdc, int fdn[3]) {
+  const int cdims[3] = {dims[dims.size() - 3], dims[dims.size() - 2], dims[dims.size() - 1]};
+  fdg = c->precond == SIM_PRECOND_FASTDIAG;
+  fdc = !fdg && c->precond == SIM_PRECOND_VCYCLE && c->mg_coarse_sweeps == 0 &&
+        !coarse_lds_fits(cdims[0], cdims[1], cdims[2]);
+  for (int a = 0; a < 3; ++a) fdn[a] = fdg ? c->n[a] : cdims[a];
+}
+
+SolveScratch carve_solve(Carver &cv, const sim_config *c, long long K, long long hparts,
+                         const std::vector<int> &dims) {
+  SolveScratch q;
+  const long long N = (long long)c->n[0] * c->n[1] * c->n[2];
+  const size_t ts = c->precision == SIM_PREC_FP32MG ? sizeof(float) : sizeof(double);
+  const int m = c->krylov_restart;
+  q.RHSP = cv.arr<double>(N);
+  q.BVEC = cv.arr<double>(N);
+  q.PP = cv.arr<double>(N);
+  q.TMPC = cv.arr<double>(N);
+  q.V = cv.take(ts * (size_t)(m + 1) * N);
+  q.Z = cv.take(ts * (size_t)std::max(m, 2) * N);  // BiCGStab keeps p^, s^ in Z[0], Z[1]
+  q.BCG = c->krylov == SIM_KRYLOV_BICGSTAB ? cv.arr<double>(6 * N) : nullptr;
+  for (size_t l = 3; l < dims.size() && q.nlv < SolveScratch::MAX_LEVELS; l += 3) {
+    const long long nl = (long long)dims[l] * dims[l + 1] * dims[l + 2];
+    q.lvx[q.nlv] = cv.take(ts * nl);
+    q.lvb[q.nlv] = cv.take(ts * nl);
+    ++q.nlv;
+  }
+  q.Q = cv.arr<double>(3 * K);
+  q.RF = cv.arr<double>(3 * K);
+  q.PHIP = cv.arr<double>(3 * K);
+  const int rb = std::max(red_blocks(), 1);
+  q.PART = cv.arr<double>(std::max((long long)rb * (MAX_RESTART + 2), hparts));
+  q.RED = cv.arr<double>(4 * (MAX_RESTART + 2));
+  bool fdg, fdc;
+  int fdn[3];
+  fd_flags(c, dims, fdg, fdc, fdn);
+  const long long fdcells = (long long)fdn[0] * fdn[1] * fdn[2];
+  q.FDW1 = (fdg || fdc) ? cv.arr<unsigned short>(fdcells) : nullptr;
+  q.FDW2 = (fdg || fdc) ? cv.arr<unsigned short>(fdcells) : nullptr;
+  const bool fdx = c->precond == SIM_PRECOND_FASTDIAG_EXACT;
+  q.FDX1 = fdx ? cv.arr<double>(N) : nullptr;
+  q.FDX2 = fdx ? cv.arr<double>(N) : nullptr;
+  return q;
+}
+
 // Lay out every array; with base == nullptr only the size is computed.
 size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std::vector<int> &dims) {
   Carver cv(base);
   long long N = (long long)c->n[0] * c->n[1] * c->n[2];
   bool f32 = c->precision == SIM_PREC_FP32MG;
   size_t ts = f32 ? sizeof(float) : sizeof(double);
-  int m = c->krylov_restart;
   long long K = kmax > 0 ? kmax : 1;
   long long nt = (long long)(c->n[0] / 4) * (c->n[1] / 4) * (c->n[2] / 4);
   double *U = cv.arr<double>(3 * N), *UM = cv.arr<double>(3 * N), *USTAR = cv.arr<double>(3 * N);
   double *RHSU = cv.arr<double>(3 * N), *TMP3 = cv.arr<double>(3 * N);
-  double *P = cv.arr<double>(N), *RHSP = cv.arr<double>(N), *BVEC = cv.arr<double>(N);
-  double *PP = cv.arr<double>(N), *TMPC = cv.arr<double>(N);
-  void *V = cv.take(ts * (size_t)(m + 1) * N);
-  void *Z = cv.take(ts * (size_t)std::max(m, 2) * N);  // BiCGStab keeps p^, s^ in Z[0], Z[1]
-  double *BCG = c->krylov == SIM_KRYLOV_BICGSTAB ? cv.arr<double>(6 * N) : nullptr;
+  double *P = cv.arr<double>(N);
   void *HR = cv.take(ts * 3 * N), *HE0 = cv.take(ts * 3 * N);
   std::vector<Level> lv;
   int nlev = (int)dims.size() / 3;
@@ -236,18 +345,17 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
     Level L;
     double h = c->len[0] / c->n[0] * (double)(1 << l);
     L.g = make_geo(dims[3 * l], dims[3 * l + 1], dims[3 * l + 2], c->bc[0], c->bc[1], c->bc[2], h);
-    if (l > 0) {
-      long long nl = (long long)dims[3 * l] * dims[3 * l + 1] * dims[3 * l + 2];
-      L.x = cv.take(ts * nl);
-      L.b = cv.take(ts * nl);
-    }
+    L.g.march_min_blocks = march_min_blocks_setting();
     lv.push_back(L);
   }
+  // the momentum residual writes one partial per plane-march workgroup
+  const long long hparts = helm_resid_blocks(lv[0].g);
+  SolveScratch sq = carve_solve(cv, c, K, hparts, dims);
   double *OFF = cv.arr<double>(3 * K), *XN = cv.arr<double>(3 * K), *UN = cv.arr<double>(3 * K);
   double *PHIN = cv.arr<double>(3 * K);
   int *BODYOF = cv.arr<int>(K), *TILE = cv.arr<int>(K), *PERM = cv.arr<int>(K), *PERMTMP = cv.arr<int>(K);
-  double *XS = cv.arr<double>(3 * K), *US = cv.arr<double>(3 * K), *Q = cv.arr<double>(3 * K);
-  double *RF = cv.arr<double>(3 * K), *PHIP = cv.arr<double>(3 * K), *PHIS = cv.arr<double>(3 * K);
+  double *XS = cv.arr<double>(3 * K), *US = cv.arr<double>(3 * K);
+  double *PHIS = cv.arr<double>(3 * K);
   double *PT3 = cv.arr<double>(3 * K);
   double *ADJ = cv.arr<double>(15 * K);
   const long long npass = c->record_two_way ? c->outer_iters : 0;
@@ -258,42 +366,34 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
   double *REC_RF = npass ? cv.arr<double>(npass * 3 * K) : nullptr;
   double *ADJ2 = npass ? cv.arr<double>(15 * K + 9 * MAX_BODIES + 9 * VOL_CHUNKS) : nullptr;
   int *COUNTS = cv.arr<int>(nt), *TSTART = cv.arr<int>(nt + 1), *FILLC = cv.arr<int>(nt);
-  int *FLAGS = cv.arr<int>(nt), *FPOS = cv.arr<int>(nt + 1), *ACTIVE = cv.arr<int>(nt);
+  // FLAGS and ACTIVE swap roles and take launch orders with holes (nt + 8)
+  int *FLAGS = cv.arr<int>(nt + 8), *FPOS = cv.arr<int>(nt + 1), *ACTIVE = cv.arr<int>(nt + 8);
   int *SCANTMP = cv.arr<int>(nt / 1024 + 16);
   long long tl_cap = 27 * K;  // a point touches at most 3 x 3 x 3 tiles
   int *TCOUNT = cv.arr<int>(nt), *TLSTART = cv.arr<int>(nt + 1), *TLIST = cv.arr<int>(tl_cap);
-  int *NZT = cv.arr<int>(nt);
+  int *NZT = cv.arr<int>(nt + 8);
   BodyDev *BODIES = (BodyDev *)cv.take(sizeof(BodyDev) * MAX_BODIES);
   BodySpan *SPAN = (BodySpan *)cv.take(sizeof(BodySpan) * MAX_BODIES);
   double *BSUM = cv.arr<double>(12LL * MAX_BODIES);
   double *VPART = cv.arr<double>(9LL * VOL_CHUNKS * MAX_BODIES);
-  int rb = std::max(red_blocks(), 1);
-  long long parts = std::max<long long>((long long)rb * (MAX_RESTART + 2), 0);
-  // helm_resid writes one partial per row-launch block
-  // the momentum residual writes one partial per plane-march workgroup
-  long long hparts = helm_resid_blocks(lv[0].g);
-  double *PART = cv.arr<double>(std::max(parts, hparts));
-  double *RED = cv.arr<double>(4 * (MAX_RESTART + 2));
-  double *YDEV = cv.arr<double>(MAX_RESTART + 2);
   const int cdims[3] = {dims[dims.size() - 3], dims[dims.size() - 2], dims[dims.size() - 1]};
   double *COARSEFD = cv.arr<double>(coarse_fd_size(cdims));
   // matrix-core fast diagonalisation: of the whole grid (FASTDIAG
   // preconditioner) or of a coarsest grid too large for the LDS solver
-  const bool fdg = c->precond == SIM_PRECOND_FASTDIAG;
-  const bool fdc = !fdg && c->mg_coarse_sweeps == 0 && !coarse_lds_fits(cdims[0], cdims[1], cdims[2]);
-  const int *fdn = fdg ? c->n : cdims;
-  const long long fdcells = (long long)fdn[0] * fdn[1] * fdn[2];
+  bool fdg, fdc;
+  int fdn[3];
+  fd_flags(c, dims, fdg, fdc, fdn);
   unsigned char *FDQ = (fdg || fdc) ? cv.arr<unsigned char>((long long)fd_blob_bytes(fdn)) : nullptr;
-  unsigned short *FDW1 = (fdg || fdc) ? cv.arr<unsigned short>(fdcells) : nullptr;
-  unsigned short *FDW2 = (fdg || fdc) ? cv.arr<unsigned short>(fdcells) : nullptr;
+  const bool fdx = c->precond == SIM_PRECOND_FASTDIAG_EXACT;
+  double *FDXQ = fdx ? cv.arr<double>((long long)fdx_blob_doubles(c->n)) : nullptr;
   if (s) {
     s->U = U; s->UM = UM; s->USTAR = USTAR; s->RHSU = RHSU; s->TMP3 = TMP3;
-    s->P = P; s->RHSP = RHSP; s->BVEC = BVEC; s->PP = PP; s->TMPC = TMPC;
-    s->V = V; s->Z = Z; s->HR = HR; s->HE0 = HE0; s->BCG = BCG;
+    s->P = P; s->HR = HR; s->HE0 = HE0;
     s->lv = lv;
+    put_solve_scratch(s, sq);
     s->OFF = OFF; s->XN = XN; s->UN = UN; s->PHIN = PHIN;
     s->BODYOF = BODYOF; s->TILE = TILE; s->PERM = PERM; s->PERMTMP = PERMTMP;
-    s->XS = XS; s->US = US; s->Q = Q; s->RF = RF; s->PHIP = PHIP; s->PHIS = PHIS; s->PT3 = PT3;
+    s->XS = XS; s->US = US; s->PHIS = PHIS; s->PT3 = PT3;
     s->ADJ = ADJ;
     s->REC_U = REC_U; s->REC_PP = REC_PP; s->REC_PHI = REC_PHI; s->REC_PHIP = REC_PHIP; s->REC_RF = REC_RF;
     s->ADJ2 = ADJ2;
@@ -302,11 +402,12 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
     s->SPAN = SPAN; s->BSUM = BSUM; s->VPART = VPART;
     s->TCOUNT = TCOUNT; s->TLSTART = TLSTART; s->TLIST = TLIST;
     s->tl_cap = tl_cap; s->NZT = NZT;
-    s->PART = PART; s->RED = RED; s->YDEV = YDEV;
     s->COARSEFD = COARSEFD;
     s->fastdiag = fdg;
     s->coarse_mfma = fdc;
-    s->FDQ = FDQ; s->FDW1 = FDW1; s->FDW2 = FDW2;
+    s->FDQ = FDQ;
+    s->fdx = fdx;
+    s->FDXQ = FDXQ;
   }
   return cv.off + 256;
 }
@@ -416,15 +517,15 @@ sim_status place_and_bin(sim_t s, const std::vector<BodyDev> &bd) {
   CKH(hipMemcpyAsync(s->hpin, s->FPOS + nt, sizeof(int), hipMemcpyDeviceToHost, st));
   CKH(hipStreamSynchronize(st));
   memcpy(&nz, s->hpin, sizeof(int));
-  s->nnz = nz;
-  // fullest point tiles first (ACTIVE, rebuilt below, is the scratch here)
+  s->nnz = order_launch_count(nz);  // launch count of NZT (holes included)
+  // launch order of the non-empty point tiles: XCD chunks, fullest first
   CKH(order_active(nz, s->ACTIVE, s->TSTART, s->NZT, st));
   // touch lists of the active tiles (tiles reached by some point's support),
   // counted and filled tile by tile in a fixed order; only the tiles within
   // one tile of a non-empty point tile can be reached (candidates, compacted
   // into ACTIVE; their number stays on the device)
   CKH(fill_i32(s->FLAGS, nt, 0, st));
-  CKH(mark_near(s->g, s->nt0, s->nt1, s->nt2, nz, s->NZT, s->FLAGS, st));
+  CKH(mark_near(s->g, s->nt0, s->nt1, s->nt2, nz, s->ACTIVE, s->FLAGS, st));
   CKH(scan_exclusive(s->FLAGS, s->FPOS, nt, s->SCANTMP, st));
   CKH(compact(nt, s->FLAGS, s->FPOS, s->ACTIVE, st));
   CKH(fill_i32(s->TCOUNT, nt, 0, st));
@@ -443,11 +544,13 @@ sim_status place_and_bin(sim_t s, const std::vector<BodyDev> &bd) {
   if (M > s->tl_cap) return fail(s, SIM_EDEVICE, "touch list overflow");
   CKH(touch_tiles(s->ker, s->g, s->nt0, s->nt1, s->nt2, na, nullptr, s->ACTIVE, s->TSTART, s->XS, nullptr,
                   s->TLSTART, s->TLIST, st));
-  // longest touch lists first (FLAGS, no longer needed, takes the old order)
+  // launch order of the active tiles: XCD chunks, longest touch lists first
+  // (FLAGS, no longer needed, takes the order)
   CKH(order_active(na, s->ACTIVE, s->TLSTART, s->FLAGS, st));
   std::swap(s->ACTIVE, s->FLAGS);
   s->ntouch = M;
-  s->nactive = na;
+  s->nactive = order_launch_count(na);  // launch count of ACTIVE (holes included)
+  probe_set_points(s->probes, s->K, na);
   return SIM_OK;
 }
 
@@ -470,11 +573,23 @@ std::vector<BodyDev> body_states_at(sim_t s, double t) {
 // ---------------------------------------------------------------------------
 // Operators on the split layout
 
+// Algorithmic bytes of one whole-grid fast-diagonalisation solve: the input
+// (ti bytes per cell) read and bfloat16 lines written, three bfloat16 passes
+// (y forward, x forward + scale + back, y back), bfloat16 lines read and the
+// output (to bytes per cell) written.
+double fd_bytes(const sim_s *s, size_t ti, size_t to) { return (double)s->N * (ti + 2 + 3 * 4 + 2 + to); }
+
+// Algorithmic bytes of one exact float64 fast-diagonalisation solve: the
+// split-layout input read and written in natural order, six mode products
+// each reading and writing the grid, the natural-order result read and
+// written in split order (16 passes of 8 bytes per cell).
+double fdx_bytes(const sim_s *s) { return (double)s->N * 16 * 8; }
+
 // w = S~ z = L z + c^-1 G^T W W^T G z  (= L z - c^-1 D W (W^T G z))
 template <typename T>
 sim_status schur_matvec(sim_t s, const T *z, double *w) {
   {
-    ProbeScope pr(PR_LAP, s->st);
+    ProbeScope pr(PR_LAP, s->st, (double)s->N * (sizeof(T) + sizeof(double)));  // z read, w written
     CKH(lap_apply<T>(s->g, z, w, s->st));
   }
   CKH(interp_grad<T>(s->ker, s->g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, z, 1.0, nullptr, 0.0, s->Q, s->st));
@@ -484,92 +599,102 @@ sim_status schur_matvec(sim_t s, const T *z, double *w) {
 }
 
 // z ~ L^+ v by one V-cycle (v in precision TV: float64, or float32 for the
-// FP32-MG basis)
+// FP32-MG basis).  Every kernel launch is probed with its algorithmic bytes
+// (each operand read once, each result written once; T-typed values of the
+// level, the finest level's right-hand side in TV).
 template <typename T, typename TV>
 sim_status vcycle(sim_t s, const TV *v, T *z) {
-  ProbeScope whole(PR_VCYCLE, s->st);
   hipStream_t st = s->st;
   const sim_config &c = s->cfg;
-  int nl = (int)s->lv.size();
-  int cyc = c.mg_coarse_sweeps;
-  if (nl == 1) {
-    if (cyc == 0 && s->coarse_mfma) CKH((fd_precond<TV, T>(s->lv[0].g, v, z, s->FDW1, s->FDW2, s->FDQ, 1.0f, st)));
-    else if (cyc == 0) CKH((mg_coarse_fd<T, TV>(s->lv[0].g, v, z, s->COARSEFD, st)));
-    else CKH((mg_coarse<T, TV>(s->lv[0].g, v, z, cyc, 1, st)));
+  const int nl = (int)s->lv.size();
+  const int cyc = c.mg_coarse_sweeps;
+  const double t = sizeof(T);
+  auto cells = [&](int l) { return (double)geo_cells(s->lv[l].g); };
+  auto tb = [&](int l) { return l == 0 ? (double)sizeof(TV) : t; };  // right-hand-side bytes of level l
+  auto coarse_bytes = [&](int l) { return cells(l) * (tb(l) + t); };  // b read, x written
+  auto first_bytes = [&](int l, bool store_red) { return cells(l) * (tb(l) + (store_red ? t : 0.5 * t)); };
+  auto half_bytes = [&](int l) { return cells(l) * (0.5 * t + 0.5 * tb(l) + 0.5 * t); };
+  auto restrict_bytes = [&](int l) { return cells(l) * (t + 0.5 * tb(l)) + cells(l + 1) * t; };
+  auto prolong_bytes = [&](int l) { return cells(l) * t + cells(l + 1) * t; };
+  // the last two levels run in one LDS workgroup when they fit (an exact
+  // coarse solve below a fine level of at most 4096 cells); grid-wide levels
+  // run above level lsub
+  const bool sub = nl >= 2 && cyc == 0 && !s->coarse_mfma && subcycle_fits(s->lv[nl - 2].g, s->lv[nl - 1].g);
+  const int lsub = sub ? nl - 2 : nl - 1;
+  // the whole cycle: the sum of the per-launch models below
+  ProbeScope whole(PR_VCYCLE, st, [&] {
+    double b = nl == 1 ? coarse_bytes(0) : coarse_bytes(lsub);
+    for (int l = 0; l < lsub; ++l)
+      b += first_bytes(l, c.mg_pre == 1) + 2.0 * (c.mg_pre - 1) * half_bytes(l) + restrict_bytes(l) +
+           prolong_bytes(l) + 2.0 * c.mg_post * half_bytes(l);
+    return b;
+  }());
+  auto coarse_solve = [&](const Geo &g, auto *b, T *x) -> sim_status {
+    using TBc = std::remove_const_t<std::remove_pointer_t<decltype(b)>>;
+    ProbeScope pr(PR_COARSE, st, (double)geo_cells(g) * (sizeof(TBc) + t));
+    if (cyc == 0 && s->coarse_mfma) CKH((fd_precond<TBc, T>(g, b, x, s->FDW1, s->FDW2, s->FDQ, 1.0f, st)));
+    else if (cyc == 0) CKH((mg_coarse_fd<T, TBc>(g, b, x, s->COARSEFD, st)));
+    else CKH((mg_coarse<T, TBc>(g, b, x, cyc, 1, st)));
     return SIM_OK;
-  }
-  // descend
-  for (int l = 0; l + 1 < nl; ++l) {
+  };
+  if (nl == 1) return coarse_solve(s->lv[0].g, v, z);
+  auto subcycle = [&](auto *b, T *x) -> sim_status {
+    using TBs = std::remove_const_t<std::remove_pointer_t<decltype(b)>>;
+    const Geo &gf = s->lv[nl - 2].g;
+    ProbeScope pr(PR_COARSE, st, (double)geo_cells(gf) * (sizeof(TBs) + t));
+    CKH((mg_subcycle<T, TBs>(gf, s->lv[nl - 1].g, b, x, s->COARSEFD, c.mg_pre, c.mg_post, st)));
+    return SIM_OK;
+  };
+  if (sub && lsub == 0) return subcycle(v, z);
+  // descend: pre-smoothing red then black, the first sweep from zero (which
+  // stores the red values only when no further half sweep overwrites them)
+  const bool store_red = c.mg_pre == 1;
+  for (int l = 0; l < lsub; ++l) {
     const Geo &g = s->lv[l].g;
     T *x = l == 0 ? z : (T *)s->lv[l].x;
-    if (l == 0) {
+    auto pre = [&](auto *b) -> sim_status {
+      using TBl = std::remove_const_t<std::remove_pointer_t<decltype(b)>>;
       {
-        ProbeScope pr(PR_SMOOTH_FIRST_FINE, st);
-        CKH((mg_smooth_first<T, TV>(g, x, v, st)));
+        ProbeScope pr(PR_SMOOTH_FIRST, st, first_bytes(l, store_red));
+        CKH((mg_smooth_first<T, TBl>(g, x, b, store_red, st)));
       }
-      for (int q = 1; q < c.mg_pre; ++q) {
-        {
-          ProbeScope pr(PR_SMOOTH_FINE, st);
-          CKH((mg_smooth<T, TV>(g, x, v, 0, st)));
+      for (int q = 1; q < c.mg_pre; ++q)
+        for (int color = 0; color < 2; ++color) {
+          ProbeScope pr(PR_SMOOTH, st, half_bytes(l));
+          CKH((mg_smooth<T, TBl>(g, x, b, color, st)));
         }
-        {
-          ProbeScope pr(PR_SMOOTH_FINE, st);
-          CKH((mg_smooth<T, TV>(g, x, v, 1, st)));
-        }
-      }
-    } else {
-      const T *b = (const T *)s->lv[l].b;
-      CKH((mg_smooth_first<T, T>(g, x, b, st)));
-      for (int q = 1; q < c.mg_pre; ++q) {
-        CKH((mg_smooth<T, T>(g, x, b, 0, st)));
-        CKH((mg_smooth<T, T>(g, x, b, 1, st)));
-      }
-    }
-    {
       T *bnext = (T *)s->lv[l + 1].b;
-      if (l == 0) {
-        ProbeScope pr(PR_RESTRICT_FINE, st);
-        CKH((mg_restrict<T, TV>(g, x, v, s->lv[1].g, bnext, st)));
-      } else
-
-        CKH((mg_restrict<T, T>(g, x, (const T *)s->lv[l].b, s->lv[l + 1].g, bnext, st)));
-    }
+      ProbeScope pr(PR_RESTRICT, st, restrict_bytes(l));
+      CKH((mg_restrict<T, TBl>(g, x, b, s->lv[l + 1].g, bnext, st)));
+      return SIM_OK;
+    };
+    sim_status rc = l == 0 ? pre(v) : pre((const T *)s->lv[l].b);
+    if (rc) return rc;
   }
-  // coarse grid
   {
-    ProbeScope prc(PR_COARSE, st);
-    if (cyc == 0 && s->coarse_mfma)
-      CKH((fd_precond<T, T>(s->lv[nl - 1].g, (const T *)s->lv[nl - 1].b, (T *)s->lv[nl - 1].x, s->FDW1, s->FDW2,
-                            s->FDQ, 1.0f, st)));
-    else if (cyc == 0)
-      CKH((mg_coarse_fd<T, T>(s->lv[nl - 1].g, (const T *)s->lv[nl - 1].b, (T *)s->lv[nl - 1].x, s->COARSEFD, st)));
-    else
-      CKH((mg_coarse<T, T>(s->lv[nl - 1].g, (const T *)s->lv[nl - 1].b, (T *)s->lv[nl - 1].x, cyc, 1, st)));
+    sim_status rc = sub ? subcycle((const T *)s->lv[lsub].b, (T *)s->lv[lsub].x)
+                        : coarse_solve(s->lv[nl - 1].g, (const T *)s->lv[nl - 1].b, (T *)s->lv[nl - 1].x);
+    if (rc) return rc;
   }
-  // ascend
-  for (int l = nl - 2; l >= 0; --l) {
+  // ascend: prolongation onto the red cells, post-smoothing black then red
+  for (int l = lsub - 1; l >= 0; --l) {
     const Geo &g = s->lv[l].g;
     T *x = l == 0 ? z : (T *)s->lv[l].x;
     {
-      ProbeScope pr(l == 0 ? PR_PROLONG_FINE : -1, st);
+      ProbeScope pr(PR_PROLONG, st, prolong_bytes(l));
       CKH(mg_prolong<T>(g, x, s->lv[l + 1].g, (const T *)s->lv[l + 1].x, st));
     }
-    for (int q = 0; q < c.mg_post; ++q) {
-      if (l == 0) {
-        {
-          ProbeScope pr(PR_SMOOTH_FINE, st);
-          CKH((mg_smooth<T, TV>(g, x, v, 1, st)));
+    auto post = [&](auto *b) -> sim_status {
+      using TBl = std::remove_const_t<std::remove_pointer_t<decltype(b)>>;
+      for (int q = 0; q < c.mg_post; ++q)
+        for (int color = 1; color >= 0; --color) {
+          ProbeScope pr(PR_SMOOTH, st, half_bytes(l));
+          CKH((mg_smooth<T, TBl>(g, x, b, color, st)));
         }
-        {
-          ProbeScope pr(PR_SMOOTH_FINE, st);
-          CKH((mg_smooth<T, TV>(g, x, v, 0, st)));
-        }
-      } else {
-        const T *b = (const T *)s->lv[l].b;
-        CKH((mg_smooth<T, T>(g, x, b, 1, st)));
-        CKH((mg_smooth<T, T>(g, x, b, 0, st)));
-      }
-    }
+      return SIM_OK;
+    };
+    sim_status rc = l == 0 ? post(v) : post((const T *)s->lv[l].b);
+    if (rc) return rc;
   }
   return SIM_OK;
 }
@@ -601,8 +726,11 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
     S.rel_res = 0;
     return isfinite(bn2) ? SIM_OK : fail(s, SIM_ENONFINITE, "non-finite right-hand side");
   }
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), sig(m + 1);
-  Coef64 sig2{};  // sig_i^2, passed by value to the update kernel
+  // Hessenberg matrix, Givens rotations and scales on the host stack (no
+  // allocation inside a solve)
+  double H[(MAX_RESTART + 1) * MAX_RESTART], cs[MAX_RESTART], sn[MAX_RESTART], gv[MAX_RESTART + 1],
+      y[MAX_RESTART], sig[MAX_RESTART + 1];
+  KCoef sig2{};  // sig_i^2, passed by value to the update kernel
   auto Hij = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
   double beta = bnorm;
   const double *rvec = b;
@@ -614,7 +742,7 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
     CKH(scale_cast<T>(V, rvec, N, 1.0 / beta, st));
     sig[0] = 1.0;
     sig2.v[0] = 1.0;
-    std::fill(gv.begin(), gv.end(), 0.0);
+    std::fill(gv, gv + m + 1, 0.0);
     gv[0] = beta;
     int jd = 0;
     for (int j = 0; j < m; ++j) {
@@ -622,8 +750,13 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
       T *vj = V + (long long)j * N, *vnext = V + (long long)(j + 1) * N;
       double *w = sep_w ? s->TMPC : (double *)vnext;
       if (s->fastdiag) {
-        ProbeScope pr(PR_VCYCLE, st);
+        ProbeScope pr(PR_VCYCLE, st, fd_bytes(s, sizeof(T), sizeof(T)));
         CKH((fd_precond<T, T>(s->g, vj, zj, s->FDW1, s->FDW2, s->FDQ, (float)sig[j], st)));
+      } else if (s->fdx) {
+        if constexpr (std::is_same<T, double>::value) {
+          ProbeScope pr(PR_VCYCLE, st, fdx_bytes(s));
+          CKH(fdx_precond(s->g, vj, zj, s->FDX1, s->FDX2, s->FDXQ, st));
+        }
       } else if ((rc = vcycle<T, T>(s, vj, zj))) {
         return rc;
       }
@@ -633,12 +766,13 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
       // in one pass; with w' = S~ z'_j = S~ z_j / sig_j the Hessenberg column
       // is h_ij = sig_j sig_i g_i, h_{j+1,j} = sig_j |V'_{j+1}|.
       {
-        ProbeScope pr(PR_MULTIDOT, st);
+        ProbeScope pr(PR_MULTIDOT, st, (double)N * (sizeof(double) + (j + 1) * sizeof(T)));  // w, V_0..V_j
         CKH(multidot<T>(w, V, N, j + 1, N, s->PART, st));
       }
       CKH(finalize(s->PART, red_blocks(), j + 1, s->RED, st, s->hpin_dev));
       {
-        ProbeScope pr(PR_UPDATE_NORM, st);
+        // w, V_0..V_j read, V_{j+1} written
+        ProbeScope pr(PR_UPDATE_NORM, st, (double)N * (sizeof(double) + (j + 2) * sizeof(T)));
         CKH(update_cast_norm<T>(vnext, w, V, N, j + 1, s->RED, sig2, N,
                                 s->PART + (long long)(MAX_RESTART + 1) * red_blocks(), st));
       }
@@ -682,7 +816,7 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
       for (int k = i + 1; k < jd; ++k) v -= Hij(i, k) * y[k];
       y[i] = v / Hij(i, i);
     }
-    Coef64 yc{};
+    KCoef yc{};
     for (int i = 0; i < jd; ++i) yc.v[i] = y[i] * sig[i];  // z_i = sig_i z'_i
     CKH(sol_update<T>(x, Z, N, jd, yc, N, st));
     // true residual r = b - S~ x (in TMPC)
@@ -722,8 +856,15 @@ sim_status bicgstab(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
   sim_status rc;
   auto precond = [&](const double *in, T *out) -> sim_status {
     if (s->fastdiag) {
-      ProbeScope pr(PR_VCYCLE, st);
+      ProbeScope pr(PR_VCYCLE, st, fd_bytes(s, sizeof(double), sizeof(T)));
       CKH((fd_precond<double, T>(s->g, in, out, s->FDW1, s->FDW2, s->FDQ, 1.0f, st)));
+      return SIM_OK;
+    }
+    if (s->fdx) {
+      if constexpr (std::is_same<T, double>::value) {
+        ProbeScope pr(PR_VCYCLE, st, fdx_bytes(s));
+        CKH(fdx_precond(s->g, in, out, s->FDX1, s->FDX2, s->FDXQ, st));
+      }
       return SIM_OK;
     }
     return vcycle<T, double>(s, in, out);
@@ -785,7 +926,7 @@ sim_status bicgstab(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
       ++since;
       if (sqrt(ss) / bnorm <= c.krylov_rtol || !(tt > 0.0)) {
         // converged (or t = 0) at the half step: x += alpha p^, r = s
-        Coef64 y1{};
+        KCoef y1{};
         y1.v[0] = alpha;
         CKH(sol_update<T>(x, PH, N, 1, y1, N, st));
         CKH(scale_copy(R, Sv, N, 1.0, st));
@@ -796,7 +937,7 @@ sim_status bicgstab(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
       }
       omega = ts / tt;
       // x += alpha p^ + omega s^ (p^, s^ adjacent in Z); r = s - omega t with |r|^2, (r, r^)
-      Coef64 y2{};
+      KCoef y2{};
       y2.v[0] = alpha;
       y2.v[1] = omega;
       CKH(sol_update<T>(x, PH, N, 2, y2, N, st));
@@ -846,9 +987,7 @@ sim_status schur_rhs(sim_t s) {
 // Pressure-force correction on the current RHSP / RF: PP = p', PHIP = Phi'.
 sim_status schur_solve_core(sim_t s, sim_solve_stats *stt) {
   sim_status rc;
-  hipEvent_t e0, e1;
-  CKH(hipEventCreate(&e0));
-  CKH(hipEventCreate(&e1));
+  hipEvent_t e0 = s->ev_solve[0], e1 = s->ev_solve[1];
   CKH(hipEventRecord(e0, s->st));
   if ((rc = schur_rhs(s))) return rc;
   sim_status solve_rc = fgmres_any(s, s->BVEC, s->PP, stt);
@@ -860,8 +999,6 @@ sim_status schur_solve_core(sim_t s, sim_solve_stats *stt) {
   float ms = 0;
   CKH(hipEventElapsedTime(&ms, e0, e1));
   if (stt) stt->seconds = ms * 1e-3;
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   return solve_rc;
 }
 
@@ -908,7 +1045,7 @@ sim_status helm_solve(sim_t s, const double *rhs, double *u, sim_solve_stats *st
   int nb = 0;
   for (;; ++it) {
     {
-      ProbeScope pr(PR_HELM_RESID, st);
+      ProbeScope pr(PR_HELM_RESID, st, 3.0 * s->N * (2 * sizeof(double) + sizeof(T)));  // x, b read, r written
       CKH(helm_resid<T>(g, a0, c.nu, u, rhs, R, s->PART, &nb, st));
     }
     CKH(finalize(s->PART, nb, 1, s->RED, st, s->hpin_dev));
@@ -920,12 +1057,13 @@ sim_status helm_solve(sim_t s, const double *rhs, double *u, sim_solve_stats *st
     if (rel <= c.helm_rtol || it >= c.helm_maxit) break;
     const int kin = sweeps_for(rel);
     {
-      ProbeScope pr(PR_HELM_FIRST, st);
+      ProbeScope pr(PR_HELM_FIRST, st, 3.0 * s->N * 2 * sizeof(T));  // r read, both colours of e written
       CKH((helm_sor_first<T>(g, a0, c.nu, omega, E, R, st)));
     }
     for (int k = 1; k < kin; ++k) {
       for (int color = 0; color < 2; ++color) {
-        ProbeScope pr(PR_HELM_SWEEP, st);
+        // other-colour e, own-colour r and e read, own-colour e written
+        ProbeScope pr(PR_HELM_SWEEP, st, 3.0 * s->N * 2 * sizeof(T));
         CKH((helm_sor<T, T>(g, a0, c.nu, omega, E, R, color, st)));
       }
     }
@@ -951,7 +1089,8 @@ sim_status predictor(sim_t s, sim_step_stats &S, sim_status &hrc) {
   const sim_config &c = s->cfg;
   CKH(gather3(s->K, s->PERM, s->PHIN, s->PHIS, st));
   {
-    ProbeScope pr(PR_MOM_RHS, st);
+    // u^n, u^{n-1} (three components each) and p^n read; rhs and the guess written
+    ProbeScope pr(PR_MOM_RHS, st, 13.0 * s->N * sizeof(double));
     CKH(mom_rhs(s->g, c.dt, s->U, s->UM, s->P, s->RHSU, s->USTAR, st));
   }
   CKH(band_apply(s->ker, false, s->g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, s->PHIS, 1.0,
@@ -1280,8 +1419,37 @@ sim_status step_two_way(sim_t s, sim_step_stats *out) {
 
 }  // namespace
 
+// Frees what sim_create took besides the caller's workspace: the pinned
+// reduction mirror, the probe events and the handle itself.
+void release_handle(sim_t s) {
+  if (s->hpin) hipHostFree(s->hpin);
+  probe_free(s->probes);
+  for (hipEvent_t e : s->ev_solve)
+    if (e) hipEventDestroy(e);
+  delete s;
+}
+
+// sim_solve_schur on whatever solve scratch the handle currently points to
+sim_status solve_schur_entry(sim_t s, const double *d_rhs_p, const double *d_rhs_f, double *d_p, double *d_phi,
+                             sim_solve_stats *stats) {
+  s->adj_ready = false;
+  s->adj2_ready = false;
+  if (!s->have_bodies) return fail(s, SIM_ESTATE, "no bodies set");
+  if (!d_rhs_p || !d_p || (s->K > 0 && (!d_rhs_f || !d_phi))) return fail(s, SIM_EINVAL, "null argument");
+  hipStream_t st = s->st;
+  CKH(to_split(s->g, 1, d_rhs_p, s->RHSP, st));
+  if (s->K > 0) CKH(gather3(s->K, s->PERM, d_rhs_f, s->RF, st));
+  sim_status rc = schur_solve_core(s, stats);
+  if (rc != SIM_OK && rc != SIM_ENOTCONV) return rc;
+  CKH(to_natural(s->g, 1, s->PP, d_p, st));
+  if (s->K > 0) CKH(scatter3(s->K, s->PERM, s->PHIP, d_phi, st));
+  sim_status r2 = sync(s);
+  return r2 ? r2 : rc;
+}
+
 // ===========================================================================
 // C ABI
+
 extern "C" {
 
 sim_status sim_config_check(const sim_config *cfg, int64_t max_points, char *msg, int32_t msg_len) {
@@ -1331,9 +1499,14 @@ sim_status sim_create(const sim_config *cfg, void *d_workspace, size_t bytes, in
     delete s;
     return SIM_EDEVICE;
   }
+  s->probes = probe_new();
+  s->dims = dims;
+  if (hipEventCreate(&s->ev_solve[0]) != hipSuccess || hipEventCreate(&s->ev_solve[1]) != hipSuccess) {
+    release_handle(s);
+    return SIM_EDEVICE;
+  }
   if (hipHostGetDevicePointer((void **)&s->hpin_dev, s->hpin, 0) != hipSuccess) {
-    hipHostFree(s->hpin);
-    delete s;
+    release_handle(s);
     return SIM_EDEVICE;
   }
   {
@@ -1343,9 +1516,18 @@ sim_status sim_create(const sim_config *cfg, void *d_workspace, size_t bytes, in
     std::vector<double> fd((size_t)coarse_fd_size(cn));
     coarse_fd_build(cn, cbc, gcoarse.h, fd.data());
     if (hipMemcpy(s->COARSEFD, fd.data(), sizeof(double) * fd.size(), hipMemcpyHostToDevice) != hipSuccess) {
-      hipHostFree(s->hpin);
-      delete s;
+      release_handle(s);
       return SIM_EDEVICE;
+    }
+    if (s->fdx) {
+      const int fn[3] = {cfg->n[0], cfg->n[1], cfg->n[2]};
+      std::vector<double> qd((size_t)coarse_fd_size(fn)), blob(fdx_blob_doubles(fn));
+      coarse_fd_build(fn, cbc, s->g.h, qd.data());
+      fdx_blob_pack(fn, qd.data(), blob.data());
+      if (hipMemcpy(s->FDXQ, blob.data(), sizeof(double) * blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        release_handle(s);
+        return SIM_EDEVICE;
+      }
     }
     if (s->fastdiag || s->coarse_mfma) {
       const Geo &gq = s->fastdiag ? s->lv[0].g : gcoarse;
@@ -1355,8 +1537,7 @@ sim_status sim_create(const sim_config *cfg, void *d_workspace, size_t bytes, in
       std::vector<unsigned char> blob(fd_blob_bytes(fn));
       fd_blob_pack(fn, qd.data(), blob.data());
       if (hipMemcpy(s->FDQ, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
-        hipHostFree(s->hpin);
-        delete s;
+        release_handle(s);
         return SIM_EDEVICE;
       }
     }
@@ -1366,8 +1547,7 @@ sim_status sim_create(const sim_config *cfg, void *d_workspace, size_t bytes, in
             fill(s->P, s->N, 0.0, st) == hipSuccess && fill(s->USTAR, 3 * s->N, 0.0, st) == hipSuccess &&
             hipStreamSynchronize(st) == hipSuccess;
   if (!ok) {
-    hipHostFree(s->hpin);
-    delete s;
+    release_handle(s);
     return SIM_EDEVICE;
   }
   *out = s;
@@ -1377,8 +1557,7 @@ sim_status sim_create(const sim_config *cfg, void *d_workspace, size_t bytes, in
 sim_status sim_destroy(sim_t s) {
   if (!s) return SIM_EINVAL;
   hipStreamSynchronize(s->st);
-  if (s->hpin) hipHostFree(s->hpin);
-  delete s;
+  release_handle(s);
   return SIM_OK;
 }
 
@@ -1552,23 +1731,14 @@ sim_status sim_get_forces(sim_t s, double *d_f, double *body_ft) {
 sim_status sim_solve_schur(sim_t s, const double *d_rhs_p, const double *d_rhs_f, double *d_p, double *d_phi,
                            sim_solve_stats *stats) {
   if (!s) return SIM_EINVAL;
-  s->adj_ready = false;
-  s->adj2_ready = false;
-  if (!s->have_bodies) return fail(s, SIM_ESTATE, "no bodies set");
-  if (!d_rhs_p || !d_p || (s->K > 0 && (!d_rhs_f || !d_phi))) return fail(s, SIM_EINVAL, "null argument");
-  hipStream_t st = s->st;
-  CKH(to_split(s->g, 1, d_rhs_p, s->RHSP, st));
-  if (s->K > 0) CKH(gather3(s->K, s->PERM, d_rhs_f, s->RF, st));
-  sim_status rc = schur_solve_core(s, stats);
-  if (rc != SIM_OK && rc != SIM_ENOTCONV) return rc;
-  CKH(to_natural(s->g, 1, s->PP, d_p, st));
-  if (s->K > 0) CKH(scatter3(s->K, s->PERM, s->PHIP, d_phi, st));
-  sim_status r2 = sync(s);
-  return r2 ? r2 : rc;
+  ProbeBind probe_bind_(s->probes);
+  return solve_schur_entry(s, d_rhs_p, d_rhs_f, d_p, d_phi, stats);
 }
+
 
 sim_status sim_step(sim_t s, int32_t nsteps, sim_step_stats *stats) {
   if (!s) return SIM_EINVAL;
+  ProbeBind probe_bind_(s->probes);
   s->adj_ready = false;
   s->adj2_ready = false;
   if (!s->have_bodies) return fail(s, SIM_ESTATE, "no bodies set");
@@ -1585,6 +1755,7 @@ sim_status sim_step_adjoint(sim_t s, const double *d_gu, const double *d_gv, con
                             const double *d_gphi, double *d_gX, double *gU, double *d_gu_in, double *d_gum_in,
                             double *d_gp_in, double *d_gphi_in) {
   if (!s) return SIM_EINVAL;
+  ProbeBind probe_bind_(s->probes);
   if (!s->have_bodies || !s->adj_ready)
     return fail(s, SIM_ESTATE, "no recorded one-way step with one correction to transpose");
   hipStream_t st = s->st;
@@ -1717,6 +1888,7 @@ sim_status sim_step_adjoint_two_way(sim_t s, const double *d_gu, const double *d
                                     double *d_gu_in, double *d_gum_in, double *d_gp_in, double *d_gphi_in,
                                     double *gbody_in) {
   if (!s) return SIM_EINVAL;
+  ProbeBind probe_bind_(s->probes);
   if (!s->have_bodies || !s->adj2_ready)
     return fail(s, SIM_ESTATE, "no recorded two-way step (record_two_way, outer_tol = 0) to transpose");
   hipStream_t st = s->st;
@@ -1939,18 +2111,19 @@ sim_status sim_step_adjoint_two_way(sim_t s, const double *d_gu, const double *d
 sim_status sim_probe_enable(sim_t s, int32_t probe, int32_t on) {
   if (!s) return SIM_EINVAL;
   if (probe < 0 || probe >= PR_COUNT) return fail(s, SIM_EINVAL, "unknown probe");
-  probe_enable(probe, on != 0);
+  probe_enable(s->probes, probe, on != 0);
   return SIM_OK;
 }
 
-sim_status sim_probe_read(sim_t s, int32_t probe, int64_t *launches, double *ms, int32_t reset) {
+sim_status sim_probe_read(sim_t s, int32_t probe, int64_t *launches, double *ms, double *bytes, int32_t reset) {
   if (!s || !launches || !ms) return SIM_EINVAL;
   if (probe < 0 || probe >= PR_COUNT) return fail(s, SIM_EINVAL, "unknown probe");
   long long c = 0;
-  double t = 0.0;
-  CKH(probe_read(probe, &c, &t, reset != 0));
+  double t = 0.0, b = 0.0;
+  CKH(probe_read(s->probes, probe, &c, &t, &b, reset != 0));
   *launches = c;
   *ms = t;
+  if (bytes) *bytes = b;
   return SIM_OK;
 }
 
@@ -2039,6 +2212,8 @@ sim_status lap_solve(sim_t s, const double *b, double *x, double rtol, int maxit
   auto precond = [&](const double *in, double *out) -> sim_status {
     if (s->fastdiag) {
       CKH((fd_precond<double, double>(g, in, out, s->FDW1, s->FDW2, s->FDQ, 1.0f, st)));
+    } else if (s->fdx) {
+      CKH(fdx_precond(g, in, out, s->FDX1, s->FDX2, s->FDXQ, st));
     } else if (s->fp32) {
       if ((rc = vcycle<float, double>(s, in, (float *)s->Z))) return rc;
       CKH(fill(out, N, 0.0, st));
@@ -2133,6 +2308,7 @@ double tridiag_eig(const double *a, const double *b, int m, int idx) {
 
 sim_status sim_apply(sim_t s, int32_t op, const double *in, const double *in2, double *out) {
   if (!s) return SIM_EINVAL;
+  ProbeBind probe_bind_(s->probes);
   s->adj_ready = false;
   s->adj2_ready = false;
   if (!in || !out) return fail(s, SIM_EINVAL, "null argument");
@@ -2158,6 +2334,8 @@ sim_status sim_apply(sim_t s, int32_t op, const double *in, const double *in2, d
       CKH(to_split(g, 1, in, s->TMPC, st));
       if (s->fastdiag) {
         CKH((fd_precond<double, double>(g, s->TMPC, s->PP, s->FDW1, s->FDW2, s->FDQ, 1.0f, st)));
+      } else if (s->fdx) {
+        CKH(fdx_precond(g, s->TMPC, s->PP, s->FDX1, s->FDX2, s->FDXQ, st));
       } else if (s->fp32) {
         if ((rc = vcycle<float, double>(s, s->TMPC, (float *)s->Z))) return rc;
         CKH(fill(s->PP, N, 0.0, st));
@@ -2234,6 +2412,7 @@ sim_status sim_apply(sim_t s, int32_t op, const double *in, const double *in2, d
 sim_status sim_schur_spectrum(sim_t s, int32_t exact, const double *v0, int32_t steps, double lap_rtol,
                               double *alpha, double *beta, int32_t *steps_done, double *lmin, double *lmax) {
   if (!s) return SIM_EINVAL;
+  ProbeBind probe_bind_(s->probes);
   s->adj_ready = false;
   s->adj2_ready = false;
   if (!v0) return fail(s, SIM_EINVAL, "null start vector");

@@ -11,18 +11,36 @@ namespace ibs {
 
 // ---- kernel timing probes (probe.hip) --------------------------------------
 enum ProbeId {
-  PR_SMOOTH_FINE = 0, PR_SMOOTH_FIRST_FINE, PR_RESTRICT_FINE, PR_PROLONG_FINE, PR_LAP, PR_BAND_DIV,
+  PR_SMOOTH = 0, PR_SMOOTH_FIRST, PR_RESTRICT, PR_PROLONG, PR_LAP, PR_BAND_DIV,
   PR_BAND_FACE, PR_INTERP_GRAD, PR_INTERP_FACE, PR_MULTIDOT, PR_UPDATE_NORM, PR_COARSE, PR_HELM_SWEEP,
   PR_HELM_RESID, PR_VCYCLE, PR_MOM_RHS, PR_HELM_FIRST, PR_COUNT
 };
-int probe_begin(int id, hipStream_t s);
+struct ProbeState;  // per handle
+ProbeState *probe_new();
+void probe_free(ProbeState *ps);
+ProbeState *probe_bind(ProbeState *ps);  // binds ps to the calling thread, returns the previous binding
+struct ProbeBind {
+  ProbeState *prev;
+  explicit ProbeBind(ProbeState *ps) : prev(probe_bind(ps)) {}
+  ~ProbeBind() { probe_bind(prev); }
+};
+// Launches made while a handle's state is bound are timed if their probe is
+// on; each probed launch also records its algorithmic bytes (every operand
+// read once, every result written once), given by the launch site.
+int probe_begin(int id, hipStream_t s, double bytes);
 void probe_end(int id, int slot, hipStream_t s);
-void probe_enable(int id, bool on);
-hipError_t probe_read(int id, long long *count, double *ms, bool reset);
+void probe_enable(ProbeState *ps, int id, bool on);
+hipError_t probe_read(ProbeState *ps, int id, long long *count, double *ms, double *bytes, bool reset);
+// Lagrangian point count and active (support-reached) 4^3-cell tile count of
+// the bound handle, for the byte models of the spreading and interpolation
+// launches; set by the handle whenever it bins its points.
+void probe_set_points(ProbeState *ps, long long K, long long active_tiles);
+long long probe_points();
+long long probe_active_tiles();
 struct ProbeScope {
   int id, slot;
   hipStream_t s;
-  ProbeScope(int id_, hipStream_t s_) : id(id_), slot(probe_begin(id_, s_)), s(s_) {}
+  ProbeScope(int id_, hipStream_t s_, double bytes = 0.0) : id(id_), slot(probe_begin(id_, s_, bytes)), s(s_) {}
   ~ProbeScope() { probe_end(id, slot, s); }
 };
 
@@ -71,8 +89,10 @@ template <typename T>
 hipError_t cast_copy(T *y, const double *x, long long n, hipStream_t s);
 
 // ---- multigrid (kernels_mg.hip) --------------------------------------------
+// first sweep from x = 0 (red from b, then black); the red values are
+// stored only with store_red (else a following half sweep overwrites them)
 template <typename T, typename TB>
-hipError_t mg_smooth_first(const Geo &g, T *x, const TB *b, hipStream_t s);
+hipError_t mg_smooth_first(const Geo &g, T *x, const TB *b, bool store_red, hipStream_t s);
 template <typename T, typename TB>
 hipError_t mg_smooth(const Geo &g, T *x, const TB *b, int color, hipStream_t s);
 template <typename T, typename TB>
@@ -86,6 +106,13 @@ int coarse_max_cells();
 template <typename T, typename TB>
 hipError_t mg_coarse_fd(const Geo &gc, const TB *b, T *x, const double *fd, hipStream_t s);
 int coarse_fd_size(const int n[3]);  // doubles
+// the last two levels (fine grid gf of at most 4096 cells and its coarsest
+// grid gc, solved exactly with fd from coarse_fd_build) in one LDS workgroup:
+// x = the V-cycle of those two levels applied to b, from x = 0
+bool subcycle_fits(const Geo &gf, const Geo &gc);
+template <typename T, typename TB>
+hipError_t mg_subcycle(const Geo &gf, const Geo &gc, const TB *b, T *x, const double *fd, int pre, int post,
+                       hipStream_t s);
 // z = L^+ v on a grid by fast diagonalisation (bfloat16 matrix-core
 // transforms); w1, w2: bfloat16 scratch grids; blob: eigenbases packed by
 // fd_blob_pack from coarse_fd_build's output (device copy)
@@ -93,6 +120,13 @@ template <typename TI, typename T>
 hipError_t fd_precond(const Geo &g, const TI *v, T *z, unsigned short *w1, unsigned short *w2, const void *blob,
                       float vscale, hipStream_t s);
 size_t fd_blob_bytes(const int n[3]);
+// z = L^+ v exactly by fast diagonalisation in float64 (split layout in and
+// out); w1, w2: natural-layout float64 scratch grids; blob: fdx_blob_pack of
+// coarse_fd_build's eigen-decomposition of the grid (device copy)
+hipError_t fdx_precond(const Geo &g, const double *v, double *z, double *w1, double *w2, const double *blob,
+                       hipStream_t s);
+size_t fdx_blob_doubles(const int n[3]);
+void fdx_blob_pack(const int n[3], const double *q, double *blob);
 void fd_blob_pack(const int n[3], const double *qd, unsigned char *out);
 
 void coarse_fd_build(const int n[3], const int bc[3], double h, double *out);
@@ -171,7 +205,10 @@ hipError_t touch_tiles(int ker, const Geo &g, int nt0, int nt1, int nt2, int ntl
                        int *list, hipStream_t s);
 // flags[t] = 1 for the tiles within one tile of the n tiles nz[0..n)
 hipError_t mark_near(const Geo &g, int nt0, int nt1, int nt2, int n, const int *nz, int *flags, hipStream_t s);
+// launch order of the n tiles of a list (XCD-chunked, longest lists first in
+// each chunk): order_launch_count(n) entries, -1 in the holes
 hipError_t order_active(int n, const int *active, const int *lstart, int *out, hipStream_t s);
+int order_launch_count(int n);
 hipError_t positive_flags(int n, const int *counts, int *flags, hipStream_t s);
 // band: for the active tiles, out += alpha D (W q)   (div = true, cell field)
 //                          or out += alpha W q       (div = false, face field)
@@ -192,14 +229,16 @@ hipError_t update_norm(double *w, const TV *V, long long stride, int nv, const d
                        long long n, double *part, hipStream_t s);
 template <typename TV>
 hipError_t scale_cast(TV *y, const double *x, long long n, double alpha, hipStream_t s);  // y = alpha x
-// up to 64 coefficients passed by value to a kernel
-struct Coef64 {
-  double v[64];
+// Krylov coefficients passed by value to a kernel: one per basis vector of
+// a restart cycle of up to 64 iterations, plus the new vector's (65)
+constexpr int KCOEF_MAX = 65;
+struct KCoef {
+  double v[KCOEF_MAX];
 };
 // vout = (TV)(w - sum_i sig2_i g_i V_i), partial |vout|^2 per block (g on the device)
 template <typename TV>
 hipError_t update_cast_norm(TV *vout, const double *w, const TV *V, long long stride, int nv, const double *g,
-                            const Coef64 &sig2, long long n, double *part, hipStream_t s);  // w -= sum h_i V_i ; |w|^2
+                            const KCoef &sig2, long long n, double *part, hipStream_t s);  // w -= sum h_i V_i ; |w|^2
 hipError_t scale_inplace(double *x, long long n, double alpha, hipStream_t s);
 // ---- reverse-mode step (kernels_adj.hip) ------------------------------------
 // out[k][e] += scale * d/dX_{k,e} (a^T W(X) b), a a face field, b [K][3]
@@ -210,7 +249,7 @@ hipError_t convection_adjoint(const Geo &g, const double *u3, const double *r3, 
 
 hipError_t scale_copy(double *y, const double *x, long long n, double alpha, hipStream_t s);
 template <typename T>
-hipError_t sol_update(double *x, const T *Z, long long stride, int nz, const Coef64 &y, long long n,
+hipError_t sol_update(double *x, const T *Z, long long stride, int nz, const KCoef &y, long long n,
                       hipStream_t s);  // x += sum y_j Z_j  // x += sum y_j Z_j
 hipError_t axpby(double *y, const double *x, long long n, double a, double b,
                  hipStream_t s);  // y = a x + b y

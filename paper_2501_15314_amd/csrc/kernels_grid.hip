@@ -19,6 +19,7 @@ Geo make_geo(int n0, int n1, int n2, int bc0, int bc1, int bc2, double h) {
   g.n0 = n0; g.n1 = n1; g.n2 = n2; g.hn2 = n2 / 2;
   g.half = (long long)n0 * n1 * (n2 / 2);
   g.bc0 = bc0; g.bc1 = bc1; g.bc2 = bc2;
+  g.march_min_blocks = MARCH_MIN_BLOCKS_DEFAULT;
   g.h = h; g.h2 = h * h;
   return g;
 }

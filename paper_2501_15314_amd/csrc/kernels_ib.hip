@@ -215,6 +215,7 @@ __global__ void __launch_bounds__(256) k_interp(Geo g, int nt1, int nt2, const i
   __shared__ double pw[IPTS][3][2][4];   // [point][axis][face/centre][node]
   __shared__ int pb[IPTS][3][2];         // local start of the support
   const int tile = tiles[blockIdx.x];
+  if (tile < 0) return;  // a hole of the launch order
   const int T2 = tile % nt2, r = tile / nt2, T1 = r % nt1, T0 = r / nt1;
   const int o0 = 4 * T0 - 2, o1 = 4 * T1 - 2, o2 = 4 * T2 - 2;  // region origin
   const long long N = 2 * g.half;
@@ -290,7 +291,9 @@ template <typename T>
 hipError_t interp_grad(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, const int *tiles, const int *tstart,
                        const double *X, const T *z, double alpha, const double *y, double beta, double *out,
                        hipStream_t s) {
-  ProbeScope probe_(PR_INTERP_GRAD, s);
+  // positions read, results written (and y read), the cells of the support band (T each)
+  ProbeScope probe_(PR_INTERP_GRAD, s,
+                    (double)probe_points() * (beta != 0.0 ? 72 : 48) + (double)probe_active_tiles() * 64 * sizeof(T));
   if (ntiles_nz == 0) return hipSuccess;
   dim3 gr(ntiles_nz), bl(256);
   if (ker == KER_PESKIN4)
@@ -309,7 +312,9 @@ template hipError_t interp_grad<double>(int, const Geo &, int, int, int, const i
 hipError_t interp_face(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, const int *tiles, const int *tstart,
                        const double *X, const double *u3, double alpha, const double *y, double beta, double *out,
                        hipStream_t s) {
-  ProbeScope probe_(PR_INTERP_FACE, s);
+  // positions read, results written (and y read), three face components of the support band
+  ProbeScope probe_(PR_INTERP_FACE, s,
+                    (double)probe_points() * (beta != 0.0 ? 72 : 48) + (double)probe_active_tiles() * 64 * 3 * 8);
   if (ntiles_nz == 0) return hipSuccess;
   dim3 gr(ntiles_nz), bl(256);
   if (ker == KER_PESKIN4)
@@ -460,32 +465,42 @@ hipError_t mark_near(const Geo &g, int nt0, int nt1, int nt2, int n, const int *
   return hipGetLastError();
 }
 
-// Active tiles in order of decreasing touch-list length (one workgroup,
-// bucket sort on min(length, 1023)): the spreading workgroups with the most
-// work start first, which shortens the tail of the launch.  Each tile's
-// result does not depend on the order, which within a bucket is arbitrary.
-constexpr int ORD_T = 1024, ORD_B = 1024;
+// Launch order of a tile list (one workgroup, counting sort).  The
+// dispatcher deals consecutive workgroups round-robin to the 8 XCDs, each
+// with its own L2: the list (in tile-index order, i.e. spatially sorted) is
+// cut into ORD_X contiguous chunks and chunk c is dealt to the workgroups
+// c, c + 8, c + 16, ..., so the neighbouring tiles that share points and
+// halo cells run on one XCD and find them in its L2.  Within a chunk the
+// tiles go in order of decreasing list length (the workgroups with the most
+// work start first, which shortens the tail).  out has ORD_X * ceil(n /
+// ORD_X) entries; -1 marks the holes of a short last chunk (those
+// workgroups exit).  Each tile's result does not depend on the order, which
+// within a length bucket is arbitrary.
+constexpr int ORD_T = 1024, ORD_B = 256, ORD_X = 8;
 __global__ void __launch_bounds__(ORD_T) k_order_active(int n, const int *active, const int *lstart, int *out) {
-  __shared__ int cnt[ORD_B], base[ORD_B];
+  __shared__ int cnt[ORD_X * ORD_B], base[ORD_X * ORD_B];
   const int t = threadIdx.x;
-  cnt[t] = 0;
+  const int cs = (n + ORD_X - 1) / ORD_X;
+  for (int b = t; b < ORD_X * ORD_B; b += ORD_T) cnt[b] = 0;
+  for (int i = t; i < ORD_X * cs; i += ORD_T) out[i] = -1;
   __syncthreads();
   auto key = [&](int i) {
     const int a = active[i];
-    return ORD_B - 1 - min(lstart[a + 1] - lstart[a], ORD_B - 1);
+    return (i / cs) * ORD_B + ORD_B - 1 - min(lstart[a + 1] - lstart[a], ORD_B - 1);
   };
   for (int i = t; i < n; i += ORD_T) atomicAdd(&cnt[key(i)], 1);
   __syncthreads();
-  if (t == 0) {
-    int acc = 0;
+  if (t < ORD_X) {
+    int acc = 0;  // position within chunk t
     for (int b = 0; b < ORD_B; ++b) {
-      base[b] = acc;
-      acc += cnt[b];
+      base[t * ORD_B + b] = acc;
+      acc += cnt[t * ORD_B + b];
     }
   }
   __syncthreads();
-  for (int i = t; i < n; i += ORD_T) out[atomicAdd(&base[key(i)], 1)] = active[i];
+  for (int i = t; i < n; i += ORD_T) out[atomicAdd(&base[key(i)], 1) * ORD_X + i / cs] = active[i];
 }
+int order_launch_count(int n) { return ORD_X * ((n + ORD_X - 1) / ORD_X); }
 hipError_t order_active(int n, const int *active, const int *lstart, int *out, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_order_active, dim3(1), dim3(ORD_T), 0, s, n, active, lstart, out);
@@ -537,6 +552,7 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
   __shared__ double wts[BAND_CH][BAND_WS];
   double(*part)[3][80] = reinterpret_cast<double(*)[3][80]>(&wts[0][0]);
   const int tile = active[blockIdx.x];
+  if (tile < 0) return;  // a hole of the launch order
   const int T2 = tile % nt2, r = tile / nt2, T1 = r % nt1, T0 = r / nt1;
   const int tid = threadIdx.x;
   const int s0 = lstart[tile], s1 = lstart[tile + 1];
@@ -653,7 +669,9 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
 hipError_t band_apply(int ker, bool div, const Geo &g, int nt1, int nt2, int nactive, const int *active,
                       const int *lstart, const int *list, const double *X, const double *q, double alpha,
                       double *out, hipStream_t s) {
-  ProbeScope probe_(div ? PR_BAND_DIV : PR_BAND_FACE, s);
+  // positions and values read, the active tiles' cells (div) or faces read and written
+  ProbeScope probe_(div ? PR_BAND_DIV : PR_BAND_FACE, s,
+                    (double)probe_points() * 48 + (double)probe_active_tiles() * 64 * (div ? 1 : 3) * 16);
   if (nactive == 0) return hipSuccess;
   dim3 gr(nactive), bl(256);
   if (ker == KER_PESKIN4) {

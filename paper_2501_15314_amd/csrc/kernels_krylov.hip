@@ -89,7 +89,7 @@ hipError_t multidot(const double *w, const TV *V, long long stride, int nv, long
 // w when TV is double): the next unnormalised basis vector in one pass
 template <typename TV>
 __global__ void __launch_bounds__(RED_T) k_update_cast_norm(TV *vout, const double *w, const TV *V, long long stride,
-                                                            int nv, const double *g, Coef64 sig2, long long n,
+                                                            int nv, const double *g, KCoef sig2, long long n,
                                                             double *part) {
   __shared__ double hs[64];
   __shared__ double sh[4];
@@ -119,16 +119,16 @@ __global__ void __launch_bounds__(RED_T) k_update_cast_norm(TV *vout, const doub
 }
 template <typename TV>
 hipError_t update_cast_norm(TV *vout, const double *w, const TV *V, long long stride, int nv, const double *g,
-                            const Coef64 &sig2, long long n, double *part, hipStream_t s) {
+                            const KCoef &sig2, long long n, double *part, hipStream_t s) {
   if (nv > 64 || (n & 1) || (stride & 1)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_update_cast_norm<TV>, dim3(RED_BLOCKS), dim3(RED_T), 0, s, vout, w, V, stride, nv, g, sig2, n,
                      part);
   return hipGetLastError();
 }
 template hipError_t update_cast_norm<float>(float *, const double *, const float *, long long, int, const double *,
-                                            const Coef64 &, long long, double *, hipStream_t);
+                                            const KCoef &, long long, double *, hipStream_t);
 template hipError_t update_cast_norm<double>(double *, const double *, const double *, long long, int,
-                                             const double *, const Coef64 &, long long, double *, hipStream_t);
+                                             const double *, const KCoef &, long long, double *, hipStream_t);
 template hipError_t multidot<float>(const double *, const float *, long long, int, long long, double *,
                                     hipStream_t);
 template hipError_t multidot<double>(const double *, const double *, long long, int, long long, double *,
@@ -225,7 +225,7 @@ hipError_t scale_copy(double *y, const double *x, long long n, double alpha, hip
 }
 
 template <typename T>
-__global__ void k_sol_update(double *x, const T *Z, long long stride, int nz, Coef64 y, long long n) {
+__global__ void k_sol_update(double *x, const T *Z, long long stride, int nz, KCoef y, long long n) {
   __shared__ double ys[64];
   for (int i = threadIdx.x; i < nz; i += RED_T) ys[i] = y.v[i];
   __syncthreads();
@@ -236,15 +236,15 @@ __global__ void k_sol_update(double *x, const T *Z, long long stride, int nz, Co
   }
 }
 template <typename T>
-hipError_t sol_update(double *x, const T *Z, long long stride, int nz, const Coef64 &y, long long n,
+hipError_t sol_update(double *x, const T *Z, long long stride, int nz, const KCoef &y, long long n,
                       hipStream_t s) {
   if (nz > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_sol_update<T>, dim3(RED_BLOCKS * 4), dim3(RED_T), 0, s, x, Z, stride, nz, y, n);
   return hipGetLastError();
 }
-template hipError_t sol_update<float>(double *, const float *, long long, int, const Coef64 &, long long,
+template hipError_t sol_update<float>(double *, const float *, long long, int, const KCoef &, long long,
                                       hipStream_t);
-template hipError_t sol_update<double>(double *, const double *, long long, int, const Coef64 &, long long,
+template hipError_t sol_update<double>(double *, const double *, long long, int, const KCoef &, long long,
                                        hipStream_t);
 
 __global__ void k_axpby(double *y, const double *x, long long n, double a, double b) {

@@ -206,9 +206,12 @@ __global__ void __launch_bounds__(256) k_prolong(Geo gf, T *xf, Geo gc, const T 
 }
 
 template <typename T, typename TB>
-hipError_t mg_smooth_first(const Geo &g, T *x, const TB *b, hipStream_t s) {
+hipError_t mg_smooth_first(const Geo &g, T *x, const TB *b, bool store_red, hipStream_t s) {
   MarchShape M = march_shape(g, 1);
-  hipLaunchKernelGGL((k_sweep<T, TB, SW_FIRST>), M.grid, M.block, 0, s, g, x, b, 1, g.h2, 0.0, 0.0, 1.0);
+  if (store_red)
+    hipLaunchKernelGGL((k_sweep<T, TB, SW_FIRST>), M.grid, M.block, 0, s, g, x, b, 1, g.h2, 0.0, 0.0, 1.0);
+  else
+    hipLaunchKernelGGL((k_sweep<T, TB, SW_FIRST1>), M.grid, M.block, 0, s, g, x, b, 1, g.h2, 0.0, 0.0, 1.0);
   return hipGetLastError();
 }
 template <typename T, typename TB>
@@ -577,6 +580,145 @@ hipError_t mg_coarse_fd(const Geo &gc, const TB *b, T *x, const double *fd, hipS
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// The last two levels of the V-cycle in one workgroup: a fine grid of at most
+// SUB_FINE cells (natural layout in LDS) and its coarsest grid, solved exactly
+// by fast diagonalisation.  The same cycle as the grid-wide levels: from
+// x = 0, `pre` red-black pairs (the first one is the sweep from zero), the
+// residual averaged over the eight children, the exact coarse solve (constant
+// mode dropped), trilinear prolongation, `post` black-red pairs.  One launch
+// replaces the eight of the two levels, which are bound by latency.
+constexpr int SUB_FINE = 4096;
+constexpr int SUB_COARSE = SUB_FINE / 8;
+
+template <typename T, typename TB>
+__global__ void __launch_bounds__(COARSE_THREADS) k_subcycle(Geo gf, Geo gc, const TB *bin, T *xout,
+                                                             const double *fd, int pre, int post) {
+  __shared__ T sx[SUB_FINE + SUB_COARSE];
+  __shared__ T sb[SUB_FINE + SUB_COARSE];
+  __shared__ T fa[SUB_COARSE], fb[SUB_COARSE];
+  __shared__ T Q[3][FD_MAXN * FD_MAXN];
+  __shared__ T lam[3][FD_MAXN];
+  const int tid = threadIdx.x;
+  const int nf = gf.n0 * gf.n1 * gf.n2, nc = gc.n0 * gc.n1 * gc.n2;
+  auto dimsof = [](const Geo &g, int off) {
+    LvlDim d;
+    d.n0 = g.n0; d.n1 = g.n1; d.n2 = g.n2; d.off = off;
+    d.pow2 = !(g.n0 & (g.n0 - 1)) && !(g.n1 & (g.n1 - 1)) && !(g.n2 & (g.n2 - 1));
+    d.l1 = 31 - __clz(g.n1);
+    d.l2 = 31 - __clz(g.n2);
+    return d;
+  };
+  const LvlDim f = dimsof(gf, 0), c = dimsof(gc, nf);
+  const int bc0 = gf.bc0, bc1 = gf.bc1, bc2 = gf.bc2;
+  {
+    const int n[3] = {gc.n0, gc.n1, gc.n2};
+    const double *p = fd;
+    for (int a = 0; a < 3; ++a) {
+      for (int q = tid; q < n[a] * n[a]; q += COARSE_THREADS) Q[a][q] = (T)p[q];
+      p += n[a] * n[a];
+    }
+    for (int a = 0; a < 3; ++a) {
+      for (int q = tid; q < n[a]; q += COARSE_THREADS) lam[a][q] = (T)p[q];
+      p += n[a];
+    }
+  }
+  for (int e = tid; e < nf; e += COARSE_THREADS) {
+    int k = e % gf.n2, r = e / gf.n2, j = r % gf.n1, i = r / gf.n1;
+    sb[e] = (T)bin[sidx(gf, i, j, k)];
+    sx[e] = T(0);
+  }
+  __syncthreads();
+  const T h2 = (T)(gf.h * gf.h), ih2 = T(1) / h2;
+  for (int q = 0; q < pre; ++q) {
+    lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 0, COARSE_THREADS);
+    __syncthreads();
+    lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 1, COARSE_THREADS);
+    __syncthreads();
+  }
+  for (int e = tid; e < nc; e += COARSE_THREADS) {
+    int i, j, k;
+    lds_decode(c, e, i, j, k);
+    T acc = T(0);
+    for (int q = 0; q < 8; ++q)
+      acc += lds_resid(sx, sb, f, bc0, bc1, bc2, ih2, 2 * i + (q >> 2), 2 * j + ((q >> 1) & 1), 2 * k + (q & 1));
+    fa[e] = acc * (T)0.125;
+  }
+  __syncthreads();
+  // exact coarse solve: the six 1-D eigenbasis transforms and the division
+  const int n[3] = {gc.n0, gc.n1, gc.n2};
+  auto pass = [&](const T *in, T *out, int a, bool fwd) {
+    const int na = n[a];
+    const int stride = a == 2 ? 1 : (a == 1 ? gc.n2 : gc.n1 * gc.n2);
+    const T *M = Q[a];
+    for (int e = tid; e < nc; e += COARSE_THREADS) {
+      const int ia = (e / stride) % na;
+      const int base = e - ia * stride;
+      T acc = T(0);
+      for (int t = 0; t < na; ++t) acc += (fwd ? M[t * na + ia] : M[ia * na + t]) * in[base + t * stride];
+      out[e] = acc;
+    }
+    __syncthreads();
+  };
+  pass(fa, fb, 2, true);
+  pass(fb, fa, 1, true);
+  pass(fa, fb, 0, true);
+  for (int e = tid; e < nc; e += COARSE_THREADS) {
+    int k = e % gc.n2, r = e / gc.n2, j = r % gc.n1, i = r / gc.n1;
+    T d = lam[0][i] + lam[1][j] + lam[2][k];
+    fb[e] = d > T(0) ? fb[e] / d : T(0);
+  }
+  __syncthreads();
+  pass(fb, fa, 0, false);
+  pass(fa, fb, 1, false);
+  pass(fb, fa, 2, false);
+  for (int e = tid; e < nc; e += COARSE_THREADS) sx[nf + e] = fa[e];
+  __syncthreads();
+  // trilinear prolongation of the coarse solution onto every fine cell
+  for (int e = tid; e < nf; e += COARSE_THREADS) {
+    int i, j, k;
+    lds_decode(f, e, i, j, k);
+    const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
+    const int I1 = coarse_partner(I0, i & 1, c.n0, bc0);
+    const int J1 = coarse_partner(J0, j & 1, c.n1, bc1);
+    const int K1 = coarse_partner(K0, k & 1, c.n2, bc2);
+    const T *xc = sx + nf;
+    auto X = [&](int a, int b, int cc) { return xc[(a * c.n1 + b) * c.n2 + cc]; };
+    const T v0 = (T)0.75 * X(I0, J0, K0) + (T)0.25 * X(I1, J0, K0);
+    const T v1 = (T)0.75 * X(I0, J1, K0) + (T)0.25 * X(I1, J1, K0);
+    const T v2 = (T)0.75 * X(I0, J0, K1) + (T)0.25 * X(I1, J0, K1);
+    const T v3 = (T)0.75 * X(I0, J1, K1) + (T)0.25 * X(I1, J1, K1);
+    const T w0 = (T)0.75 * v0 + (T)0.25 * v1;
+    const T w1 = (T)0.75 * v2 + (T)0.25 * v3;
+    sx[e] += (T)0.75 * w0 + (T)0.25 * w1;
+  }
+  __syncthreads();
+  for (int q = 0; q < post; ++q) {
+    lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 1, COARSE_THREADS);
+    __syncthreads();
+    lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 0, COARSE_THREADS);
+    __syncthreads();
+  }
+  for (int e = tid; e < nf; e += COARSE_THREADS) {
+    int k = e % gf.n2, r = e / gf.n2, j = r % gf.n1, i = r / gf.n1;
+    xout[sidx(gf, i, j, k)] = sx[e];
+  }
+}
+
+bool subcycle_fits(const Geo &gf, const Geo &gc) {
+  const long long nf = (long long)gf.n0 * gf.n1 * gf.n2;
+  return nf <= SUB_FINE && gc.n0 <= FD_MAXN && gc.n1 <= FD_MAXN && gc.n2 <= FD_MAXN && gc.n0 * 2 == gf.n0 &&
+         gc.n1 * 2 == gf.n1 && gc.n2 * 2 == gf.n2;
+}
+
+template <typename T, typename TB>
+hipError_t mg_subcycle(const Geo &gf, const Geo &gc, const TB *b, T *x, const double *fd, int pre, int post,
+                       hipStream_t s) {
+  if (!subcycle_fits(gf, gc)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_subcycle<T, TB>), dim3(1), dim3(COARSE_THREADS), 0, s, gf, gc, b, x, fd, pre, post);
+  return hipGetLastError();
+}
+
 // Packed eigen-decompositions of the three 1-D Laplacians of a coarse grid
 // (host): Q0 (n0 x n0), Q1, Q2 row-major with the eigenvectors as columns,
 // then lam0, lam1, lam2.  No-slip axes: cell-centred Neumann operator,
@@ -629,12 +771,14 @@ void coarse_fd_build(const int n[3], const int bc[3], double h, double *out) {
 }
 
 #define INST(T, TB)                                                                                    \
-  template hipError_t mg_smooth_first<T, TB>(const Geo &, T *, const TB *, hipStream_t);              \
+  template hipError_t mg_smooth_first<T, TB>(const Geo &, T *, const TB *, bool, hipStream_t);        \
   template hipError_t mg_smooth<T, TB>(const Geo &, T *, const TB *, int, hipStream_t);               \
   template hipError_t mg_restrict<T, TB>(const Geo &, const T *, const TB *, const Geo &, T *,         \
                                          hipStream_t);                                                 \
   template hipError_t mg_coarse<T, TB>(const Geo &, const TB *, T *, int, int, hipStream_t);                   \
-  template hipError_t mg_coarse_fd<T, TB>(const Geo &, const TB *, T *, const double *, hipStream_t);
+  template hipError_t mg_coarse_fd<T, TB>(const Geo &, const TB *, T *, const double *, hipStream_t);   \
+  template hipError_t mg_subcycle<T, TB>(const Geo &, const Geo &, const TB *, T *, const double *, int, int, \
+                                         hipStream_t);
 INST(float, float)
 INST(float, double)
 INST(double, double)

@@ -13,7 +13,6 @@ namespace ibs {
 
 constexpr int MARCH_CH = 8;       // most planes per workgroup
 constexpr int MARCH_TILE = 1104;  // >= max (BY+2)(2BX+2) over BX*BY <= 256
-constexpr int MARCH_MIN_BLOCKS = 2048;
 
 struct MarchShape {
   int bx, by;
@@ -27,7 +26,7 @@ __host__ __device__ inline int pow2_divisor(int n, int cap) {
 }
 
 // Planes per workgroup: MARCH_CH on large grids (long register-window
-// chains, few halo re-reads), halved until the grid has MARCH_MIN_BLOCKS
+// chains, few halo re-reads), halved until the grid has g.march_min_blocks
 // workgroups on coarse multigrid levels, where latency rather than bytes
 // bounds a sweep.
 __host__ __device__ inline int march_chunk(const Geo &g) {
@@ -35,7 +34,7 @@ __host__ __device__ inline int march_chunk(const Geo &g) {
   const int by = pow2_divisor(g.n1, 256 / bx);
   const long long xy = (long long)(g.hn2 / (2 * bx)) * (g.n1 / by);
   int ch = MARCH_CH;
-  while (ch > 1 && xy * ((g.n0 + ch - 1) / ch) < MARCH_MIN_BLOCKS) ch >>= 1;
+  while (ch > 1 && xy * ((g.n0 + ch - 1) / ch) < g.march_min_blocks) ch >>= 1;
   return ch;
 }
 
@@ -351,7 +350,11 @@ __device__ __forceinline__ int diag_i(const Geo &g, int i, bool helm, int d) {
 //               colour-0 values omega b / (a0 + nu/h^2 diag) are formed on
 //               the fly from b (and stored), then the colour-1 update; one
 //               pass replaces clearing x and two half sweeps.
-enum { SW_POISSON = 0, SW_FIRST = 1, SW_HELM = 2, SW_HFIRST = 3 };
+//   SW_FIRST1:  SW_FIRST without storing the colour-0 values, for a cycle
+//               whose next half sweep recomputes colour 0 from colour 1
+//               (a Gauss-Seidel update never reads the old value of its
+//               own colour).
+enum { SW_POISSON = 0, SW_FIRST = 1, SW_HELM = 2, SW_HFIRST = 3, SW_FIRST1 = 4 };
 
 template <typename T, typename TB, int MODE>
 __global__ void __launch_bounds__(256) k_sweep(Geo g, T *x, const TB *b, int color, double h2, double a0,
@@ -373,7 +376,7 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, T *x, const TB *b, int col
   const long long P = (long long)g.n1 * g.hn2;  // one plane of one colour
   const int rw = p.j * g.hn2 + p.m0;            // this thread's two cells within a plane
   const T th2 = (T)h2, ta0 = (T)a0, tnu = (T)nuh2, tom = (T)omega;
-  constexpr bool FIRSTM = MODE == SW_FIRST || MODE == SW_HFIRST;
+  constexpr bool FIRSTM = MODE == SW_FIRST || MODE == SW_HFIRST || MODE == SW_FIRST1;
   constexpr bool HELMM = MODE == SW_HELM || MODE == SW_HFIRST;
   // momentum stencil at face (i, jj, kk) of component d: the diagonal count
   // (2 per axis plus the tangential wall ghosts) and whether it is a wall face
@@ -395,7 +398,7 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, T *x, const TB *b, int col
   // into the colour-0 value once the current plane has been computed.
   auto oxf = [&](int i, int jj, int mm, T bv) -> T {
     const int kk = 2 * mm + ((i + jj) & 1);  // colour-0 cell of row (i, jj) at index mm
-    if (MODE == SW_FIRST) return th2 * bv / (T)cell_nnb(g, i, jj, kk);
+    if (MODE == SW_FIRST || MODE == SW_FIRST1) return th2 * bv / (T)cell_nnb(g, i, jj, kk);
     bool wall;
     const int dg = helm_cell(i, jj, kk, wall);
     return wall ? T(0) : tom * (bv / (ta0 + tnu * (T)dg));
@@ -497,7 +500,7 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, T *x, const TB *b, int col
     }
     const long long r = i * P + rw;
     st2(own + r, out[0], out[1]);
-    if (FIRSTM) st2(oth + r, cur.x, cur.y);
+    if (MODE == SW_FIRST || MODE == SW_HFIRST) st2(oth + r, cur.x, cur.y);
     __syncthreads();
     prev = cur;
     cur = next;

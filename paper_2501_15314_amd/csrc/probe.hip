@@ -1,53 +1,95 @@
-// Kernel timing probes: when a probe is enabled, every launch of its kernel
-// class is bracketed by a pair of HIP events on the launch stream, and the
-// summed elapsed device time can be read back.  Used to measure the achieved
-// bandwidth of individual kernels inside a running workload.
+// Kernel timing probes: when a probe is enabled on a handle, every launch of
+// its kernel class made by that handle is bracketed by a pair of HIP events
+// on the launch stream, and the summed elapsed device time can be read back.
+// Used to measure the achieved bandwidth of individual kernels inside a
+// running workload.  Each handle owns its probe state; the entry points of
+// the C ABI bind it to the calling thread for the duration of the call, so
+// handles on different threads never share probe state.
 #include <vector>
 
 #include "internal.h"
 
 namespace ibs {
 
-namespace {
 struct ProbeState {
   bool on[PR_COUNT] = {};
+  long long points = 0, active_tiles = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[PR_COUNT];
+  std::vector<double> bytes[PR_COUNT];
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
 };
-ProbeState g_probe;
+
+namespace {
+thread_local ProbeState *t_probe = nullptr;
 }  // namespace
 
-int probe_begin(int id, hipStream_t s) {
-  if (id < 0 || id >= PR_COUNT || !g_probe.on[id]) return -1;
+ProbeState *probe_new() { return new ProbeState(); }
+
+void probe_free(ProbeState *ps) {
+  if (!ps) return;
+  for (int id = 0; id < PR_COUNT; ++id)
+    for (auto &e : ps->ev[id]) ps->pool.push_back(e);
+  for (auto &e : ps->pool) {
+    hipEventDestroy(e.first);
+    hipEventDestroy(e.second);
+  }
+  delete ps;
+}
+
+ProbeState *probe_bind(ProbeState *ps) {
+  ProbeState *prev = t_probe;
+  t_probe = ps;
+  return prev;
+}
+
+void probe_set_points(ProbeState *ps, long long K, long long active_tiles) {
+  if (ps) {
+    ps->points = K;
+    ps->active_tiles = active_tiles;
+  }
+}
+
+long long probe_points() { return t_probe ? t_probe->points : 0; }
+long long probe_active_tiles() { return t_probe ? t_probe->active_tiles : 0; }
+
+int probe_begin(int id, hipStream_t s, double bytes) {
+  ProbeState *ps = t_probe;
+  if (!ps || id < 0 || id >= PR_COUNT || !ps->on[id]) return -1;
   std::pair<hipEvent_t, hipEvent_t> e;
-  if (!g_probe.pool.empty()) {
-    e = g_probe.pool.back();
-    g_probe.pool.pop_back();
+  if (!ps->pool.empty()) {
+    e = ps->pool.back();
+    ps->pool.pop_back();
   } else {
     if (hipEventCreate(&e.first) != hipSuccess) return -1;
-    if (hipEventCreate(&e.second) != hipSuccess) return -1;
+    if (hipEventCreate(&e.second) != hipSuccess) {
+      hipEventDestroy(e.first);
+      return -1;
+    }
   }
   hipEventRecord(e.first, s);
-  g_probe.ev[id].push_back(e);
-  return (int)g_probe.ev[id].size() - 1;
+  ps->ev[id].push_back(e);
+  ps->bytes[id].push_back(bytes);
+  return (int)ps->ev[id].size() - 1;
 }
 
 void probe_end(int id, int slot, hipStream_t s) {
-  if (slot < 0) return;
-  hipEventRecord(g_probe.ev[id][slot].second, s);
+  ProbeState *ps = t_probe;
+  if (slot < 0 || !ps) return;
+  hipEventRecord(ps->ev[id][slot].second, s);
 }
 
-void probe_enable(int id, bool on) {
-  if (id >= 0 && id < PR_COUNT) g_probe.on[id] = on;
+void probe_enable(ProbeState *ps, int id, bool on) {
+  if (ps && id >= 0 && id < PR_COUNT) ps->on[id] = on;
 }
 
 // Sum of the recorded launch durations (ms); waits for the events.
-hipError_t probe_read(int id, long long *count, double *ms, bool reset) {
+hipError_t probe_read(ProbeState *ps, int id, long long *count, double *ms, double *bytes, bool reset) {
   *count = 0;
   *ms = 0.0;
-  if (id < 0 || id >= PR_COUNT) return hipErrorInvalidValue;
+  *bytes = 0.0;
+  if (!ps || id < 0 || id >= PR_COUNT) return hipErrorInvalidValue;
   double tot = 0.0;
-  for (auto &e : g_probe.ev[id]) {
+  for (auto &e : ps->ev[id]) {
     hipError_t r = hipEventSynchronize(e.second);
     if (r != hipSuccess) return r;
     float t = 0.f;
@@ -55,11 +97,13 @@ hipError_t probe_read(int id, long long *count, double *ms, bool reset) {
     if (r != hipSuccess) return r;
     tot += t;
   }
-  *count = (long long)g_probe.ev[id].size();
+  *count = (long long)ps->ev[id].size();
   *ms = tot;
+  for (double b : ps->bytes[id]) *bytes += b;
   if (reset) {
-    for (auto &e : g_probe.ev[id]) g_probe.pool.push_back(e);
-    g_probe.ev[id].clear();
+    for (auto &e : ps->ev[id]) ps->pool.push_back(e);
+    ps->ev[id].clear();
+    ps->bytes[id].clear();
   }
   return hipSuccess;
 }

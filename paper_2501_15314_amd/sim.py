@@ -220,10 +220,13 @@ class Sim:
         self._check(self.lib.sim_probe_enable(self.h, _lib.PROBES[name], int(on)))
 
     def probe_read(self, name, reset=True):
+        """(launches, milliseconds, algorithmic bytes) of a probe's kernel class."""
         n = C.c_int64()
         ms = C.c_double()
-        self._check(self.lib.sim_probe_read(self.h, _lib.PROBES[name], C.byref(n), C.byref(ms), int(reset)))
-        return int(n.value), float(ms.value)
+        nb = C.c_double()
+        self._check(self.lib.sim_probe_read(self.h, _lib.PROBES[name], C.byref(n), C.byref(ms), C.byref(nb),
+                                            int(reset)))
+        return int(n.value), float(ms.value), float(nb.value)
 
     BODY_OUT = ("xc", "us", "w", "I", "J")
     BODY_IN = ("xc", "xc_m", "us", "us_m", "w", "w_m", "I_n", "I_m", "J_n", "J_m")

@@ -38,6 +38,7 @@ MOTION_PRESCRIBED = 0
 MOTION_FREE = 1
 PRECOND_VCYCLE = 0
 PRECOND_FASTDIAG = 1
+PRECOND_FASTDIAG_EXACT = 2
 KRYLOV_FGMRES = 0
 KRYLOV_BICGSTAB = 1
 
@@ -304,6 +305,27 @@ def make_porous(n_sub: int = 7, cells_per_d: int = 32, re: float = 100.0, amp: f
     u0 = np.zeros((3,) + n)
     return Workload(f"porous{n_sub}_{n[0]}x{n[1]}x{n[2]}", cfg, bodies, offsets, u0, steps=1, seed=0)
 
+
+
+def make_oscillating_sphere(cells_per_d: int = 16, re: float = 100.0, amp: float = 1.0,
+                            precision: int = PREC_FP64) -> Workload:
+    """The oscillating sphere of Sec. 6.1.1: a solid sphere of diameter D = 1
+    at the centre of a 4D x 4D x 6D no-slip box moving with
+    z(t) = -A cos(t / A) (u_z = sin(t / A), U_max = 1), nu = 1/Re, Roma
+    3-point kernel, markers at spacing ~h on the sphere retracted by h/2,
+    time step at CFL 0.1."""
+    n = (4 * cells_per_d, 4 * cells_per_d, 6 * cells_per_d)
+    h = 1.0 / cells_per_d
+    radius = 0.5 - 0.5 * h
+    n_points = max(8, int(round(4.0 * math.pi * radius * radius / (h * h))))
+    cfg = Config(n=n, length=(4.0, 4.0, 6.0), bc=(BC_NOSLIP,) * 3, nu=1.0 / re, dt=0.1 * h,
+                 delta=DELTA_ROMA3, lump_c=lump_constant(DELTA_ROMA3, h, n_points, radius),
+                 precision=precision, krylov_rtol=1e-8)
+    body = Body(center=np.array([2.0, 2.0, 3.0]), vel=np.zeros(3), omega=np.zeros(3), radius=radius,
+                n_points=n_points, osc_amp=np.array([0.0, 0.0, amp]), osc_omega=1.0 / amp)
+    u0 = np.zeros((3,) + n)
+    return Workload(f"oscillating_sphere_{n[0]}x{n[1]}x{n[2]}", cfg, [body],
+                    fibonacci_offsets(n_points, radius), u0, steps=1, seed=0)
 
 # Settling sphere in a quiescent fluid (Sec. 6.1.3): density ratio,
 # particle Reynolds number Re_p = U D / nu and Froude number Fr = U / sqrt(g D)

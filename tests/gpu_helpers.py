@@ -1,5 +1,8 @@
 """Shared set-up for the GPU parity tests: the same seeded workload goes to the
 HIP library (through the C ABI) and to the CPU oracle."""
+import contextlib
+import os
+
 import numpy as np
 
 from oracle import bodies as obd
@@ -118,3 +121,34 @@ def prescribed_points(w: wl.Workload, t: float):
         Us.append(obd.point_velocities(obd.prescribed_velocity(b.vel, b.osc_amp, b.osc_omega, t), b.omega, lever))
         k0 += b.n_points
     return np.concatenate(Xs), np.concatenate(Us)
+
+
+# The plane-marching kernels run shorter chunks of planes per workgroup on
+# small grids; the library reads IBSCHUR_MARCH_FULL_CHUNKS when a handle is
+# created, and "1" gives every grid the full 8-plane chunks of the
+# benchmark-size grids.  Parity tests run both launch shapes.
+CHUNKS = ["auto", "full"]
+
+
+@contextlib.contextmanager
+def march_chunks(mode: str):
+    """Environment for sim_create: mode "full" forces 8-plane chunks."""
+    old = os.environ.get("IBSCHUR_MARCH_FULL_CHUNKS")
+    if mode == "full":
+        os.environ["IBSCHUR_MARCH_FULL_CHUNKS"] = "1"
+    else:
+        os.environ.pop("IBSCHUR_MARCH_FULL_CHUNKS", None)
+    try:
+        yield
+    finally:
+        if old is None:
+            os.environ.pop("IBSCHUR_MARCH_FULL_CHUNKS", None)
+        else:
+            os.environ["IBSCHUR_MARCH_FULL_CHUNKS"] = old
+
+
+def make_sim(cfg, max_points, chunks: str = "auto"):
+    """A Sim created under the given plane-march chunking."""
+    from paper_2501_15314_amd.sim import Sim
+    with march_chunks(chunks):
+        return Sim(cfg, max_points)

@@ -10,7 +10,7 @@ from oracle import step as ostep
 from paper_2501_15314_amd import workloads as wl
 
 from .conftest import gpu_available
-from .gpu_helpers import freeslip_workload, prescribed_points, rel, walls_workload
+from .gpu_helpers import CHUNKS, freeslip_workload, make_sim, prescribed_points, rel, walls_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -45,8 +45,8 @@ def _case(name, prec):
     return w, g, ostep.State(u0, um, p0, phi0), ybar
 
 
-def _gpu(w, state, ybar):
-    sim = Sim(w.cfg, w.n_points)
+def _gpu(w, state, ybar, chunks="auto"):
+    sim = make_sim(w.cfg, w.n_points, chunks)
     sim.set_bodies(w.bodies, w.offsets)
     sim.set_fields(0, state.u, state.p, state.phi)
     sim.set_fields(1, state.um)
@@ -55,17 +55,18 @@ def _gpu(w, state, ybar):
     return sim, res
 
 
+@pytest.mark.parametrize("chunks", CHUNKS)
 @pytest.mark.parametrize("name", ["c4_32", "walls", "freeslip"])
 @pytest.mark.parametrize("prec", [wl.PREC_FP64, wl.PREC_FP32MG])
-def test_step_adjoint_matches_oracle(name, prec):
+def test_step_adjoint_matches_oracle(name, prec, chunks):
     w, g, state, ybar = _case(name, prec)
     cfg = w.cfg
-    print(f"adjoint {name} prec {prec} n={cfg.n} K={w.n_points}", flush=True)
-    sim, res = _gpu(w, state, ybar)
+    print(f"adjoint {name} prec {prec} chunks {chunks} n={cfg.n} K={w.n_points}", flush=True)
+    sim, res = _gpu(w, state, ybar, chunks)
     X, U = prescribed_points(w, cfg.dt)
     ref, new, info = oadj.one_way_step_vjp(g, cfg.nu, cfg.dt, state, X, U, cfg.delta, cfg.lump_c, cfg.xi,
                                            ybar[0], ybar[1], ybar[2])
-    tol = 1e-8 if prec == wl.PREC_FP64 else 1e-6
+    tol = 1e-10 if prec == wl.PREC_FP64 else 1e-8
     errs = dict(X=rel(res["gX"].cpu().numpy(), ref["X"]),
                 u=rel(res["gu"].cpu().numpy(), ref["u"]),
                 um=rel(res["gum"].cpu().numpy(), ref["um"]),

@@ -11,7 +11,7 @@ from oracle import step as ostep
 from paper_2501_15314_amd import workloads as wl
 
 from .conftest import gpu_available
-from .gpu_helpers import free_workload, oracle_free_bodies, rel
+from .gpu_helpers import CHUNKS, free_workload, make_sim, oracle_free_bodies, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -19,13 +19,14 @@ if gpu_available():
     from paper_2501_15314_amd.sim import Sim, SimError
 
 
+@pytest.mark.parametrize("chunks", CHUNKS)
 @pytest.mark.parametrize("bc", [wl.BC_PERIODIC, wl.BC_NOSLIP, wl.BC_FREESLIP])
 @pytest.mark.parametrize("prec", [wl.PREC_FP64, wl.PREC_FP32MG])
-def test_two_way_adjoint_matches_oracle(bc, prec):
+def test_two_way_adjoint_matches_oracle(bc, prec, chunks):
     w = free_workload(32, bc, precision=prec)
     cfg = w.cfg
     cfg.record_two_way = 1
-    print(f"two-way adjoint bc {bc} prec {prec} n={cfg.n} K={w.n_points}", flush=True)
+    print(f"two-way adjoint bc {bc} prec {prec} chunks {chunks} n={cfg.n} K={w.n_points}", flush=True)
     g = omac.Grid(cfg.n, cfg.h, cfg.bc)
     mask = g.face_dof_mask()
     rng = np.random.default_rng(23)
@@ -35,7 +36,7 @@ def test_two_way_adjoint_matches_oracle(bc, prec):
     gphi = rng.standard_normal((K, 3))
     gbod = [dict(xc=rng.standard_normal(3), us=rng.standard_normal(3), w=rng.standard_normal(3),
                  I=rng.standard_normal(3), J=rng.standard_normal(3)) for _ in w.bodies]
-    sim = Sim(cfg, K)
+    sim = make_sim(cfg, K, chunks)
     sim.set_workload(w)
     sim.step(1)
     res = sim.step_adjoint_two_way(gu, gp, gphi, gbod)
@@ -44,7 +45,7 @@ def test_two_way_adjoint_matches_oracle(bc, prec):
     ostep.init_volume_history(g, state.u, fb)
     ref, _, _, _ = oadj.two_way_step_vjp(g, cfg.nu, cfg.dt, np.array(cfg.g), state, fb, cfg.delta, cfg.lump_c,
                                          cfg.xi, cfg.outer_iters, gu, gp, gphi, gbod)
-    tol = 1e-8 if prec == wl.PREC_FP64 else 1e-6
+    tol = 1e-10 if prec == wl.PREC_FP64 else 1e-8
     errs = dict(u=rel(res["gu"].cpu().numpy(), ref["u"]), um=rel(res["gum"].cpu().numpy(), ref["um"]),
                 p=rel(res["gp"].cpu().numpy(), ref["p"]), phi=rel(res["gphi"].cpu().numpy(), ref["phi"]))
     for i in range(len(w.bodies)):

@@ -7,7 +7,7 @@ from oracle import mac as omac
 from paper_2501_15314_amd import workloads as wl
 
 from .conftest import gpu_available
-from .gpu_helpers import freeslip_workload, mixed_workload, oracle_for, rel, walls_workload
+from .gpu_helpers import CHUNKS, freeslip_workload, make_sim, mixed_workload, oracle_for, rel, walls_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -24,15 +24,17 @@ def _cases():
     }
 
 
-@pytest.fixture(scope="module", params=["c1_periodic", "walls", "mixed", "freeslip"])
+@pytest.fixture(scope="module", params=[(c, m) for c in ["c1_periodic", "walls", "mixed", "freeslip"]
+                                        for m in CHUNKS], ids=lambda p: f"{p[0]}-{p[1]}")
 def setup(request):
-    w = _cases()[request.param]()
+    case, chunks = request.param
+    w = _cases()[case]()
     w.cfg.precision = wl.PREC_FP64
-    print(f"case {request.param} n={w.cfg.n} K={w.n_points}", flush=True)
-    sim = Sim(w.cfg, w.n_points)
+    print(f"case {case} chunks {chunks} n={w.cfg.n} K={w.n_points}", flush=True)
+    sim = make_sim(w.cfg, w.n_points, chunks)
     sim.set_bodies(w.bodies, w.offsets)
     g, X, W, S = oracle_for(w)
-    yield request.param, w, sim, g, X, W, S
+    yield case, w, sim, g, X, W, S
     sim.close()
 
 
@@ -97,6 +99,60 @@ def test_schur_operator_and_rhs(setup):
     assert rel(sim.apply("schur", p).cpu().numpy(), S.matvec(p)) < 1e-13
     rp, rf = wl.random_schur_rhs(9, g.n, w.n_points)
     assert rel(sim.apply("schur_rhs", rp, rf).cpu().numpy(), S.rhs(rp, rf)) < 1e-13
+
+
+@pytest.mark.parametrize("chunks", CHUNKS)
+@pytest.mark.parametrize("prec", [wl.PREC_FP64, wl.PREC_FP32MG])
+@pytest.mark.parametrize("case", ["c1_periodic", "walls", "mixed", "freeslip"])
+def test_helm_solve_matches_oracle(case, prec, chunks):
+    """The momentum (A-block) solve alone, A u* = rhs with
+    A = 3/(2 dt) - nu Delta_h (Sec. 3.1, eq. ustar), against the oracle's
+    conjugate-gradient solve on its sparse A: FP64 defect correction whose
+    red-black SOR relaxations run in the precision form's type."""
+    from oracle import step as ostep
+    w = _cases()[case]()
+    cfg = w.cfg
+    cfg.precision = prec
+    cfg.helm_rtol = 1e-12 if prec == wl.PREC_FP64 else 1e-11
+    g = omac.Grid(cfg.n, cfg.h, cfg.bc)
+    rhs = _rand(16, (3,) + g.n, g.face_dof_mask())
+    ref, _ = ostep.helmholtz_solve(g, cfg.nu, cfg.dt, rhs, rtol=1e-14)
+    sim = make_sim(cfg, w.n_points, chunks)
+    out = sim.apply("helm_solve", rhs).cpu().numpy()
+    err = rel(out, ref)
+    print(f"  {case} prec {prec} chunks {chunks}: helm_solve err {err:.2e}", flush=True)
+    assert err < (1e-11 if prec == wl.PREC_FP64 else 1e-10)
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", [wl.PREC_FP64, wl.PREC_FP32MG])
+@pytest.mark.parametrize("case", ["c1_periodic", "walls", "mixed", "freeslip"])
+def test_full_chunks_give_the_same_operators(case, prec):
+    """The 8-plane chunks of the large grids and the shorter chunks of the
+    small ones compute the same values: every red-black half sweep, residual,
+    restriction and prolongation updates a cell from the other colour only,
+    so the V-cycle, the Laplacian, the momentum operator, the momentum solve
+    and the Schur operator agree to the last bit between the two launch
+    shapes."""
+    w = _cases()[case]()
+    w.cfg.precision = prec
+    g = omac.Grid(w.cfg.n, w.cfg.h, w.cfg.bc)
+    mask = g.face_dof_mask()
+    b = _rand(17, g.n)
+    b -= b.mean()
+    u = _rand(18, (3,) + g.n, mask)
+    outs = {}
+    for mode in CHUNKS:
+        sim = make_sim(w.cfg, w.n_points, mode)
+        sim.set_bodies(w.bodies, w.offsets)
+        outs[mode] = [sim.apply("precond", b).cpu().numpy(), sim.apply("laplacian", b).cpu().numpy(),
+                      sim.apply("helmholtz", u).cpu().numpy(), sim.apply("helm_solve", u).cpu().numpy(),
+                      sim.apply("schur", b).cpu().numpy()]
+        sim.close()
+    for name, a, c in zip(["precond", "laplacian", "helmholtz", "helm_solve", "schur"], outs["auto"],
+                          outs["full"]):
+        print(f"  {case} prec {prec} {name}: max |auto - full| = {np.abs(a - c).max():.1e}", flush=True)
+        assert np.array_equal(a, c), name
 
 
 def test_vcycle_contracts(setup):
@@ -199,3 +255,31 @@ def test_fastdiag_long_axis(n, bc):
     print(f"n {n} bc {bc}: fast-diagonalisation rel err {err:.2e}", flush=True)
     assert err < 2e-2
     sim.close()
+
+
+@pytest.mark.parametrize("n,bc", [((32, 32, 32), (0, 0, 0)), ((32, 32, 32), (1, 1, 1)), ((16, 24, 40), (1, 0, 2)),
+                                  ((20, 28, 36), (0, 1, 0)), ((64, 48, 96), (1, 1, 1))])
+def test_exact_fastdiag_is_pseudo_inverse(n, bc):
+    """The float64 fast-diagonalisation preconditioner is the exact L^+ of
+    the direct solve of Sec. 4.2 (the oracle's FFT/DCT pseudo-inverse) to
+    rounding, on any axis sizes (multiples of 4 that are not multiples of
+    the 64-wide transform tiles included) and every boundary kind."""
+    from oracle import poisson as opoisson
+    cfg = wl.Config(n=n, length=tuple(x / 32.0 for x in n), bc=bc, precision=wl.PREC_FP64,
+                    precond=wl.PRECOND_FASTDIAG_EXACT)
+    sim = Sim(cfg, 1)
+    g = omac.Grid(cfg.n, cfg.h, cfg.bc)
+    b = _rand(19, g.n)
+    z = sim.apply("precond", b).cpu().numpy()
+    ref = opoisson.solve_laplacian(g, b)
+    err = rel(z, ref)
+    print(f"n {n} bc {bc}: exact fast-diagonalisation rel err {err:.2e}, mean {z.mean():.1e}", flush=True)
+    assert err < 1e-12 and abs(z.mean()) < 1e-12 * np.abs(ref).max()
+    sim.close()
+
+
+def test_exact_fastdiag_needs_fp64():
+    cfg = wl.Config(n=(32, 32, 32), precision=wl.PREC_FP32MG, precond=wl.PRECOND_FASTDIAG_EXACT)
+    with pytest.raises(Exception) as e:
+        Sim(cfg, 1)
+    assert "EINVAL" in str(e.value)

@@ -9,7 +9,7 @@ from oracle import step as ostep
 from paper_2501_15314_amd import workloads as wl
 
 from .conftest import gpu_available
-from .gpu_helpers import freeslip_workload, mixed_workload, oracle_for, rel, walls_workload
+from .gpu_helpers import CHUNKS, freeslip_workload, make_sim, mixed_workload, oracle_for, rel, walls_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -32,16 +32,17 @@ def _roma(w):
     return w
 
 
+@pytest.mark.parametrize("chunks", CHUNKS)
 @pytest.mark.parametrize("case", list(CASES))
 @pytest.mark.parametrize("prec", [wl.PREC_FP64, wl.PREC_FP32MG])
 @pytest.mark.parametrize("precond", [wl.PRECOND_VCYCLE, wl.PRECOND_FASTDIAG])
-def test_schur_solve_matches_oracle(case, prec, precond):
+def test_schur_solve_matches_oracle(case, prec, precond, chunks):
     w = CASES[case]()
     w.cfg.precision = prec
     w.cfg.precond = precond
     w.cfg.krylov_rtol = 1e-12 if prec == wl.PREC_FP64 else 1e-11
-    print(f"case {case} prec {prec} precond {precond} n={w.cfg.n} K={w.n_points}", flush=True)
-    sim = Sim(w.cfg, w.n_points)
+    print(f"case {case} prec {prec} precond {precond} chunks {chunks} n={w.cfg.n} K={w.n_points}", flush=True)
+    sim = make_sim(w.cfg, w.n_points, chunks)
     sim.set_bodies(w.bodies, w.offsets)
     g, X, W, S = oracle_for(w)
     rp, rf = wl.random_schur_rhs(21, g.n, w.n_points)
@@ -110,6 +111,28 @@ def test_notconv_reports_best_iterate():
     assert "ENOTCONV" in str(e.value)
     p, phi, st = sim.solve_schur(rp, rf, allow_notconv=True)
     assert st.iters == 1 and 0 < st.rel_res < 1
+    sim.close()
+
+
+def test_restart_at_its_maximum_runs_a_full_cycle():
+    """krylov_restart = 64, the largest the header allows: with a tolerance
+    out of reach the iteration cap ends the first cycle after all 64 Arnoldi
+    steps (the last one forms the 65th basis scale), and the iterate still
+    matches the oracle's solution."""
+    w = wl.make_c1(n=32, n_points=300)
+    w.cfg.krylov_restart = 64
+    w.cfg.krylov_maxit = 64
+    w.cfg.krylov_rtol = 1e-300
+    sim = Sim(w.cfg, w.n_points)
+    sim.set_bodies(w.bodies, w.offsets)
+    g, X, W, S = oracle_for(w)
+    rp, rf = wl.random_schur_rhs(26, g.n, w.n_points)
+    p, phi, st = sim.solve_schur(rp, rf, allow_notconv=True)
+    p_ref, phi_ref, _, _ = S.solve(rp, rf, rtol=1e-13)
+    ep, ef = rel(p.cpu().numpy(), p_ref), rel(phi.cpu().numpy(), phi_ref)
+    print(f"  iters {st.iters} rel_res {st.rel_res:.2e} err p={ep:.2e} phi={ef:.2e}")
+    assert st.iters == 64 and st.nhist == 64
+    assert st.rel_res < 1e-12 and ep < 1e-10 and ef < 1e-10
     sim.close()
 
 
@@ -192,9 +215,10 @@ def _oracle_step(w, state, t1):
     return ostep.one_way_step(g, cfg.nu, cfg.dt, state, X, U, cfg.delta, cfg.lump_c, cfg.xi)
 
 
+@pytest.mark.parametrize("chunks", CHUNKS)
 @pytest.mark.parametrize("case", ["c1_periodic", "walls", "mixed", "freeslip"])
 @pytest.mark.parametrize("prec", [wl.PREC_FP64, wl.PREC_FP32MG])
-def test_one_way_steps_match_oracle(case, prec):
+def test_one_way_steps_match_oracle(case, prec, chunks):
     w = CASES[case]()
     cfg = w.cfg
     cfg.precision = prec
@@ -204,13 +228,13 @@ def test_one_way_steps_match_oracle(case, prec):
         rng = np.random.default_rng(5)
         mask = omac.Grid(cfg.n, cfg.h, cfg.bc).face_dof_mask()
         w.u0 = rng.standard_normal(w.u0.shape) * 1e-2 * mask
-    print(f"case {case} prec {prec}", flush=True)
-    sim = Sim(cfg, w.n_points)
+    print(f"case {case} prec {prec} chunks {chunks}", flush=True)
+    sim = make_sim(cfg, w.n_points, chunks)
     sim.set_workload(w)
     g = omac.Grid(cfg.n, cfg.h, cfg.bc)
     mask = g.face_dof_mask()
     state = ostep.State(w.u0 * mask, w.u0 * mask, np.zeros(g.n), np.zeros((w.n_points, 3)))
-    tol = 1e-9 if prec == wl.PREC_FP64 else 1e-7
+    tol = 1e-10 if prec == wl.PREC_FP64 else 1e-8
     for n in range(2):
         st, _ = sim.step(1)
         t1 = (n + 1) * cfg.dt

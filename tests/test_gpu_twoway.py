@@ -9,7 +9,7 @@ from oracle import step as ostep
 from paper_2501_15314_amd import workloads as wl
 
 from .conftest import gpu_available
-from .gpu_helpers import free_workload, oracle_free_bodies, rel
+from .gpu_helpers import CHUNKS, free_workload, make_sim, oracle_free_bodies, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -25,20 +25,21 @@ def _body_err(gpu_state, bodies):
     return e
 
 
+@pytest.mark.parametrize("chunks", CHUNKS)
 @pytest.mark.parametrize("bc", [wl.BC_PERIODIC, wl.BC_NOSLIP, wl.BC_FREESLIP])
 @pytest.mark.parametrize("prec", [wl.PREC_FP64, wl.PREC_FP32MG])
-def test_two_way_steps_match_oracle(bc, prec):
+def test_two_way_steps_match_oracle(bc, prec, chunks):
     w = free_workload(32, bc, precision=prec)
     cfg = w.cfg
-    print(f"two-way bc {bc} prec {prec} n={cfg.n} K={w.n_points}", flush=True)
-    sim = Sim(cfg, w.n_points)
+    print(f"two-way bc {bc} prec {prec} chunks {chunks} n={cfg.n} K={w.n_points}", flush=True)
+    sim = make_sim(cfg, w.n_points, chunks)
     sim.set_workload(w)
     g = omac.Grid(cfg.n, cfg.h, cfg.bc)
     mask = g.face_dof_mask()
     state = ostep.State(w.u0 * mask, w.u0 * mask, np.zeros(g.n), np.zeros((w.n_points, 3)))
     fb = oracle_free_bodies(w)
     ostep.init_volume_history(g, state.u, fb)
-    tol = 1e-9 if prec == wl.PREC_FP64 else 1e-7
+    tol = 1e-10 if prec == wl.PREC_FP64 else 1e-8
     for n in range(2):
         st, _ = sim.step(1)
         state, fb, info = ostep.two_way_step(g, cfg.nu, cfg.dt, np.array(cfg.g), state, fb, cfg.delta,
