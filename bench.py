@@ -10,7 +10,8 @@ and 18,000 Lagrangian points each (144,000 points), nu = 0.005, dt = 0.002,
 fluid at rest.  From rest the momentum predictor gives u* = 0, so the
 first step's system is RHS_p = -D u*/tau = 0 and RHS_F = (W^T u* - U)/tau =
 -U/tau with the points at t = dt.  Inputs are resident in HBM before the
-timed region; value = Schur solves per second at rtol 1e-8.
+timed region; value = Schur solves per second at the Krylov tolerance that
+keeps the solution within 1e-8 of the oracle's (METRIC_RTOL).
 
 Printed: one JSON line with the solve rate of the FP32-MG form (value) and
 of the FP64 form, both forms' relative L2 error against the FP64 CPU
@@ -33,6 +34,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+# Krylov tolerance of the metric's solves: the largest relative residual at
+# which both forms' p' and Phi' stay within 1e-8 of the oracle's solution
+# (the relative error runs about twice the relative residual here), and the
+# tolerance of the FP64 row held to the 1e-10 accuracy of the FP64 form
+METRIC_RTOL = 3e-9
+FP64_ACCURATE_RTOL = 3e-11
+PROBED_SOLVES = 2       # timed solves (the last ones) whose dominant-kernel launches carry HIP events
 SINGLE_KERNEL_CLASSES = ("smooth", "smooth_first", "restrict", "prolong", "coarse", "laplacian",
                          "spread_div", "interp_grad", "multidot", "update_norm")
 
@@ -195,7 +203,7 @@ def main():
     rpt = torch.as_tensor(rp, device="cuda")
     rft = torch.as_tensor(rf, device="cuda")
 
-    def make_sim(prec, precond=wl.PRECOND_VCYCLE, krylov=wl.KRYLOV_FGMRES, rtol=1e-8):
+    def make_sim(prec, precond=wl.PRECOND_VCYCLE, krylov=wl.KRYLOV_FGMRES, rtol=METRIC_RTOL):
         cfg = wl.make_c3(n=n, points_per_sphere=pps).cfg
         cfg.precision, cfg.precond, cfg.krylov, cfg.krylov_rtol = prec, precond, krylov, rtol
         s = Sim(cfg, K)
@@ -222,15 +230,20 @@ def main():
             kern[p] = (cnt, ms, nb)
     singles = {k: v for k, v in kern.items() if k in SINGLE_KERNEL_CLASSES}
     dom = max(singles, key=lambda k: singles[k][1]) if singles else None
-    for p in ([dom] if dom else []) + ["vcycle"]:
-        sim.probe(p, True)
+    probed = ([dom] if dom else []) + ["vcycle"]
+    for p in probed:
         sim.probe_read(p, reset=True)
-    # timed region: K solves, the dominant kernel's and the preconditioner's
-    # launches bracketed by events on the solver's stream
+    # timed region: K solves; in the last PROBED_SOLVES of them the launches
+    # of the dominant kernel and every preconditioner application are
+    # bracketed by HIP events on the solver's stream (the events cost about
+    # a microsecond per launch, so the other solves run without them)
     its = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
+        if k == max(args.steps - PROBED_SOLVES, 0):
+            for p in probed:
+                sim.probe(p, True)
         p32, phi32, st = sim.solve_schur(rpt, rft)
         its.append(st.iters)
     torch.cuda.synchronize()
@@ -253,24 +266,30 @@ def main():
         for _ in range(reps):
             p, phi, st2 = s.solve_schur(rpt, rft)
         torch.cuda.synchronize()
-        return p.cpu().numpy(), phi.cpu().numpy(), (time.perf_counter() - a) / reps, st2
+        t = (time.perf_counter() - a) / reps  # before the copies to the host below
+        return p.cpu().numpy(), phi.cpu().numpy(), t, st2
 
     forms = {}
     gp, gphi = {"fp32mg": p32, }, {"fp32mg": phi32}
     forms["fp32mg"] = {"solves_per_s": round(args.steps / elapsed, 2), "ms": round(1e3 * elapsed / args.steps, 3),
-                       "iters": its[-1], "rel_res": res32,
+                       "iters": its[-1], "krylov_rtol": METRIC_RTOL, "rel_res": res32,
                        "cell_updates_per_s": round(N * its[-1] * args.steps / elapsed, 1)}
-    variants = [("fp64", wl.PREC_FP64, wl.PRECOND_VCYCLE, wl.KRYLOV_FGMRES)] if not args.no_fp64 else []
+    variants = [("fp64", wl.PREC_FP64, wl.PRECOND_VCYCLE, wl.KRYLOV_FGMRES, METRIC_RTOL),
+                ("fp64_rtol_3e-11", wl.PREC_FP64, wl.PRECOND_VCYCLE, wl.KRYLOV_FGMRES, FP64_ACCURATE_RTOL)] \
+        if not args.no_fp64 else []
     if not args.no_variants:
-        variants += [("fp32mg_fgmres_fastdiag", wl.PREC_FP32MG, wl.PRECOND_FASTDIAG, wl.KRYLOV_FGMRES),
-                     ("fp32mg_bicgstab_vcycle", wl.PREC_FP32MG, wl.PRECOND_VCYCLE, wl.KRYLOV_BICGSTAB),
-                     ("fp64_bicgstab_vcycle", wl.PREC_FP64, wl.PRECOND_VCYCLE, wl.KRYLOV_BICGSTAB),
-                     ("fp64_bicgstab_fastdiag", wl.PREC_FP64, wl.PRECOND_FASTDIAG, wl.KRYLOV_BICGSTAB)]
-    for form, prec, precond, krylov in variants:
-        s2 = make_sim(prec, precond, krylov)
+        variants += [("fp32mg_fgmres_fastdiag", wl.PREC_FP32MG, wl.PRECOND_FASTDIAG, wl.KRYLOV_FGMRES, METRIC_RTOL),
+                     ("fp32mg_bicgstab_vcycle", wl.PREC_FP32MG, wl.PRECOND_VCYCLE, wl.KRYLOV_BICGSTAB, METRIC_RTOL),
+                     ("fp64_bicgstab_vcycle", wl.PREC_FP64, wl.PRECOND_VCYCLE, wl.KRYLOV_BICGSTAB, METRIC_RTOL),
+                     # the paper's own solver: BiCGStab with the exact L^-1 (float64 fast diagonalisation)
+                     ("fp64_bicgstab_exact_fastdiag_rtol_1e-12", wl.PREC_FP64, wl.PRECOND_FASTDIAG_EXACT,
+                      wl.KRYLOV_BICGSTAB, 1e-12)]
+    for form, prec, precond, krylov, rtol in variants:
+        s2 = make_sim(prec, precond, krylov, rtol)
         gp[form], gphi[form], tsol, st2 = solve_rate(s2)
         forms[form] = {"solves_per_s": round(1.0 / tsol, 2), "ms": round(1e3 * tsol, 3), "iters": st2.iters,
-                       "rel_res": st2.rel_res, "cell_updates_per_s": round(N * st2.iters / tsol, 1)}
+                       "krylov_rtol": rtol, "rel_res": st2.rel_res,
+                       "cell_updates_per_s": round(N * st2.iters / tsol, 1)}
         log(f"{form}: {1e3 * tsol:.2f} ms, {st2.iters} iterations")
         s2.close()
         del s2
@@ -389,7 +408,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"c3 first-step Schur system, {n}^3 no-slip box, 8 spheres, {K} points",
                    "grid": list(w1.cfg.n), "bodies": len(w1.bodies), "points": K, "form": "fp32mg",
-                   "krylov": "fgmres(20)", "precond": "vcycle", "krylov_rtol": 1e-8, "nu": w1.cfg.nu,
+                   "krylov": "fgmres(20)", "precond": "vcycle", "krylov_rtol": METRIC_RTOL, "nu": w1.cfg.nu,
                    "dt": w1.cfg.dt},
         "solves": forms,
         "random_rhs": rand_rhs,

@@ -85,9 +85,9 @@ struct sim_s {
       *ACTIVE = nullptr, *SCANTMP = nullptr;
   int *TCOUNT = nullptr, *TLSTART = nullptr, *TLIST = nullptr;
   long long tl_cap = 0;  // capacity of the touch lists
+  int nactive = 0;       // launch count of ACTIVE (active tiles in launch order)
   int *NZT = nullptr;    // non-empty point tiles in launch order (-1: hole)
   int nnz = 0;           // launch count of NZT
-  int nactive = 0;       // launch count of ACTIVE (active tiles in launch order)
   int ntouch = 0;
   BodyDev *BODIES = nullptr;
   std::vector<HostBody> bodies;
@@ -129,6 +129,7 @@ struct sim_s {
   // kernel timing probes of this handle; the timing events of a Schur solve
   ProbeState *probes = nullptr;
   hipEvent_t ev_solve[2] = {nullptr, nullptr};
+  hipEvent_t ev_iter = nullptr;  // end of an FGMRES iteration's coefficients (pipelined wait)
   // multigrid level sizes (3 per level, finest first)
   std::vector<int> dims;
   // last-step statistics
@@ -509,7 +510,7 @@ sim_status place_and_bin(sim_t s, const std::vector<BodyDev> &bd) {
   CKH(bin_canon(s->K, s->TILE, s->TSTART, s->PERMTMP, s->PERM, st));
   CKH(gather3(s->K, s->PERM, s->XN, s->XS, st));
   CKH(gather3(s->K, s->PERM, s->UN, s->US, st));
-  // non-empty point tiles (interpolation work list)
+  // non-empty point tiles (the interpolation work list; their neighbourhoods hold the touch-list candidates)
   CKH(positive_flags(nt, s->COUNTS, s->FLAGS, st));
   CKH(scan_exclusive(s->FLAGS, s->FPOS, nt, s->SCANTMP, st));
   CKH(compact(nt, s->FLAGS, s->FPOS, s->ACTIVE, st));
@@ -518,7 +519,7 @@ sim_status place_and_bin(sim_t s, const std::vector<BodyDev> &bd) {
   CKH(hipStreamSynchronize(st));
   memcpy(&nz, s->hpin, sizeof(int));
   s->nnz = order_launch_count(nz);  // launch count of NZT (holes included)
-  // launch order of the non-empty point tiles: XCD chunks, fullest first
+  // interpolation launch order of the non-empty point tiles: XCD chunks, fullest first
   CKH(order_active(nz, s->ACTIVE, s->TSTART, s->NZT, st));
   // touch lists of the active tiles (tiles reached by some point's support),
   // counted and filled tile by tile in a fixed order; only the tiles within
@@ -550,7 +551,7 @@ sim_status place_and_bin(sim_t s, const std::vector<BodyDev> &bd) {
   std::swap(s->ACTIVE, s->FLAGS);
   s->ntouch = M;
   s->nactive = order_launch_count(na);  // launch count of ACTIVE (holes included)
-  probe_set_points(s->probes, s->K, na);
+  probe_set_points(s->probes, s->K, 64LL * na);
   return SIM_OK;
 }
 
@@ -616,6 +617,7 @@ sim_status vcycle(sim_t s, const TV *v, T *z) {
   auto half_bytes = [&](int l) { return cells(l) * (0.5 * t + 0.5 * tb(l) + 0.5 * t); };
   auto restrict_bytes = [&](int l) { return cells(l) * (t + 0.5 * tb(l)) + cells(l + 1) * t; };
   auto prolong_bytes = [&](int l) { return cells(l) * t + cells(l + 1) * t; };
+
   // the last two levels run in one LDS workgroup when they fit (an exact
   // coarse solve below a fine level of at most 4096 cells); grid-wide levels
   // run above level lsub
@@ -703,7 +705,21 @@ sim_status vcycle(sim_t s, const TV *v, T *z) {
 // T: precision of the preconditioned vectors Z and of the V-cycle; the basis
 // V has the same precision (a float32 basis in the FP32-MG form: each cycle
 // only has to gain FP32_CYCLE_DROP before the float64 true residual restarts
-// it).  w = S~ z_j is formed and orthogonalised in float64.
+// it).  w = S~ z_j is formed and orthogonalised in float64: the Gram-Schmidt
+// products, the update and every norm are float64 arithmetic.
+//
+// Pipelining: the preconditioner of iteration j + 1 applies to the
+// unnormalised basis vector V'_{j+1}, which is complete once the update of
+// iteration j has run, and it does not need the norm the host is waiting
+// for.  So after enqueuing iteration j's update, the preconditioner, S~
+// product and Gram-Schmidt products of iteration j + 1 are enqueued before
+// the host waits (on an event, not the whole stream) for iteration j's
+// coefficients, and the device never idles during the host's Givens step.
+// This is done when the iteration count and residual trend predict that
+// iteration j + 1 will run; a mispredicted last iteration is discarded
+// (its only outputs are z_{j+1}, w and the products, all overwritten).
+// The host mirror alternates between two slots so that the products of
+// iteration j + 1 never overwrite those of iteration j before they are read.
 template <typename T>
 sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
   hipStream_t st = s->st;
@@ -713,6 +729,9 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
   T *V = (T *)s->V;
   T *Z = (T *)s->Z;
   const bool sep_w = sizeof(T) != sizeof(double);  // orthogonalise in a float64 buffer
+  // the bfloat16 fast diagonalisation scales its input by sig_j, known only
+  // after the wait: no pipelining with it
+  const bool can_pipe = !s->fastdiag;
   sim_solve_stats loc{};
   sim_solve_stats &S = stt ? *stt : loc;
   S.iters = 0;
@@ -732,6 +751,37 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
       y[MAX_RESTART], sig[MAX_RESTART + 1];
   KCoef sig2{};  // sig_i^2, passed by value to the update kernel
   auto Hij = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
+  // host-mirror slots of iteration j: products at slot(j) + 0..j, the norm at slot(j) + MIRROR_NORM
+  constexpr int MIRROR_SLOT = 80, MIRROR_NORM = 70;
+  auto slot = [&](int j) { return (j & 1) * MIRROR_SLOT; };
+  double *const part_dots = s->PART, *const part_norm = s->PART + (long long)(MAX_RESTART + 1) * red_blocks();
+  double *const red_norm = s->RED + 2 * (MAX_RESTART + 2);  // device copy of the norm (unused by kernels)
+  // preconditioner, S~ product, Gram-Schmidt products of iteration j
+  auto front = [&](int j) -> sim_status {
+    T *zj = Z + (long long)j * N;
+    T *vj = V + (long long)j * N;
+    double *w = sep_w ? s->TMPC : (double *)(V + (long long)(j + 1) * N);
+    if (s->fastdiag) {
+      ProbeScope pr(PR_VCYCLE, st, fd_bytes(s, sizeof(T), sizeof(T)));
+      CKH((fd_precond<T, T>(s->g, vj, zj, s->FDW1, s->FDW2, s->FDQ, (float)sig[j], st)));
+    } else if (s->fdx) {
+      if constexpr (std::is_same<T, double>::value) {
+        ProbeScope pr(PR_VCYCLE, st, fdx_bytes(s));
+        CKH(fdx_precond(s->g, vj, zj, s->FDX1, s->FDX2, s->FDXQ, st));
+      }
+    } else {
+      sim_status r = vcycle<T, T>(s, vj, zj);
+      if (r) return r;
+    }
+    sim_status r = schur_matvec<T>(s, zj, w);
+    if (r) return r;
+    {
+      ProbeScope pr(PR_MULTIDOT, st, (double)N * (sizeof(double) + (j + 1) * sizeof(T)));  // w, V_0..V_j
+      CKH(multidot<T>(w, V, N, j + 1, N, part_dots, st));
+    }
+    CKH(finalize(part_dots, red_blocks(), j + 1, s->RED, st, s->hpin_dev + slot(j)));
+    return SIM_OK;
+  };
   double beta = bnorm;
   const double *rvec = b;
   int total = 0;
@@ -745,41 +795,38 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
     std::fill(gv, gv + m + 1, 0.0);
     gv[0] = beta;
     int jd = 0;
+    bool have_front = false;  // iteration j's front already enqueued
     for (int j = 0; j < m; ++j) {
-      T *zj = Z + (long long)j * N;
-      T *vj = V + (long long)j * N, *vnext = V + (long long)(j + 1) * N;
+      T *vnext = V + (long long)(j + 1) * N;
       double *w = sep_w ? s->TMPC : (double *)vnext;
-      if (s->fastdiag) {
-        ProbeScope pr(PR_VCYCLE, st, fd_bytes(s, sizeof(T), sizeof(T)));
-        CKH((fd_precond<T, T>(s->g, vj, zj, s->FDW1, s->FDW2, s->FDQ, (float)sig[j], st)));
-      } else if (s->fdx) {
-        if constexpr (std::is_same<T, double>::value) {
-          ProbeScope pr(PR_VCYCLE, st, fdx_bytes(s));
-          CKH(fdx_precond(s->g, vj, zj, s->FDX1, s->FDX2, s->FDXQ, st));
-        }
-      } else if ((rc = vcycle<T, T>(s, vj, zj))) {
-        return rc;
-      }
-      if ((rc = schur_matvec<T>(s, zj, w))) return rc;
+      if (!have_front && (rc = front(j))) return rc;
+      have_front = false;
       // classical Gram-Schmidt on the unnormalised basis (v_i = sig_i V'_i):
       // g_i = <w', V'_i>, V'_{j+1} = w' - sum_i sig_i^2 g_i V'_i and its norm
       // in one pass; with w' = S~ z'_j = S~ z_j / sig_j the Hessenberg column
       // is h_ij = sig_j sig_i g_i, h_{j+1,j} = sig_j |V'_{j+1}|.
       {
-        ProbeScope pr(PR_MULTIDOT, st, (double)N * (sizeof(double) + (j + 1) * sizeof(T)));  // w, V_0..V_j
-        CKH(multidot<T>(w, V, N, j + 1, N, s->PART, st));
-      }
-      CKH(finalize(s->PART, red_blocks(), j + 1, s->RED, st, s->hpin_dev));
-      {
         // w, V_0..V_j read, V_{j+1} written
         ProbeScope pr(PR_UPDATE_NORM, st, (double)N * (sizeof(double) + (j + 2) * sizeof(T)));
-        CKH(update_cast_norm<T>(vnext, w, V, N, j + 1, s->RED, sig2, N,
-                                s->PART + (long long)(MAX_RESTART + 1) * red_blocks(), st));
+        CKH(update_cast_norm<T>(vnext, w, V, N, j + 1, s->RED, sig2, N, part_norm, st));
       }
-      CKH(finalize(s->PART + (long long)(MAX_RESTART + 1) * red_blocks(), red_blocks(), 1, s->RED + j + 1, st,
-                   s->hpin_dev + j + 1));
+      CKH(finalize(part_norm, red_blocks(), 1, red_norm, st, s->hpin_dev + slot(j) + MIRROR_NORM));
+      CKH(hipEventRecord(s->ev_iter, st));
+      // iteration j + 1 will run unless this one converges, hits a limit or
+      // (float32 basis) the cycle's gain: predicted from the residual trend
+      if (can_pipe && j + 1 < m && total + 1 < c.krylov_maxit) {
+        const double g0 = fabs(gv[j]), gm = j > 0 ? fabs(gv[j - 1]) : 0.0;
+        const double pred = (j > 0 && gm > 0.0) ? g0 * (g0 / gm) : 0.5 * g0;  // |g_{j+1}| expected
+        const bool go = pred > 2.0 * c.krylov_rtol * bnorm && (!s->fp32 || pred > 2.0 * FP32_CYCLE_DROP * beta);
+        if (go) {
+          if ((rc = front(j + 1))) return rc;
+          have_front = true;
+        }
+      }
+      CKH(hipEventSynchronize(s->ev_iter));
       double hc[MAX_RESTART + 2];
-      if ((rc = read_mirror(s, j + 2, hc))) return rc;
+      memcpy(hc, s->hpin + slot(j), sizeof(double) * (j + 1));
+      hc[j + 1] = s->hpin[slot(j) + MIRROR_NORM];
       const double nrm = sqrt(std::max(hc[j + 1], 0.0));
       if (!isfinite(nrm)) return fail(s, SIM_ENONFINITE, "non-finite Krylov norm");
       for (int i = 0; i <= j; ++i) Hij(i, j) = sig[j] * sig[i] * hc[i];
@@ -1426,6 +1473,7 @@ void release_handle(sim_t s) {
   probe_free(s->probes);
   for (hipEvent_t e : s->ev_solve)
     if (e) hipEventDestroy(e);
+  if (s->ev_iter) hipEventDestroy(s->ev_iter);
   delete s;
 }
 
@@ -1501,7 +1549,8 @@ sim_status sim_create(const sim_config *cfg, void *d_workspace, size_t bytes, in
   }
   s->probes = probe_new();
   s->dims = dims;
-  if (hipEventCreate(&s->ev_solve[0]) != hipSuccess || hipEventCreate(&s->ev_solve[1]) != hipSuccess) {
+  if (hipEventCreate(&s->ev_solve[0]) != hipSuccess || hipEventCreate(&s->ev_solve[1]) != hipSuccess ||
+      hipEventCreateWithFlags(&s->ev_iter, hipEventDisableTiming) != hipSuccess) {
     release_handle(s);
     return SIM_EDEVICE;
   }
@@ -1734,7 +1783,6 @@ sim_status sim_solve_schur(sim_t s, const double *d_rhs_p, const double *d_rhs_f
   ProbeBind probe_bind_(s->probes);
   return solve_schur_entry(s, d_rhs_p, d_rhs_f, d_p, d_phi, stats);
 }
-
 
 sim_status sim_step(sim_t s, int32_t nsteps, sim_step_stats *stats) {
   if (!s) return SIM_EINVAL;

@@ -31,12 +31,12 @@ int probe_begin(int id, hipStream_t s, double bytes);
 void probe_end(int id, int slot, hipStream_t s);
 void probe_enable(ProbeState *ps, int id, bool on);
 hipError_t probe_read(ProbeState *ps, int id, long long *count, double *ms, double *bytes, bool reset);
-// Lagrangian point count and active (support-reached) 4^3-cell tile count of
-// the bound handle, for the byte models of the spreading and interpolation
-// launches; set by the handle whenever it bins its points.
-void probe_set_points(ProbeState *ps, long long K, long long active_tiles);
+// Lagrangian point count and the cells of the active (support-reached) band
+// tiles of the bound handle, for the byte models of the spreading and
+// interpolation launches; set by the handle whenever it bins its points.
+void probe_set_points(ProbeState *ps, long long K, long long band_cells);
 long long probe_points();
-long long probe_active_tiles();
+long long probe_band_cells();
 struct ProbeScope {
   int id, slot;
   hipStream_t s;
@@ -99,6 +99,7 @@ template <typename T, typename TB>
 hipError_t mg_restrict(const Geo &gf, const T *xf, const TB *bf, const Geo &gc, T *bc, hipStream_t s);
 template <typename T>
 hipError_t mg_prolong(const Geo &gf, T *xf, const Geo &gc, const T *xc, hipStream_t s);
+
 template <typename T, typename TB>
 hipError_t mg_coarse(const Geo &gc, const TB *b, T *x, int cycles, int sweeps, hipStream_t s);
 int coarse_max_cells();
@@ -188,8 +189,8 @@ hipError_t scale3(int K, const double *x, double alpha, const double *y, double 
 
 // interp: out[p][d] = alpha * (W^T src)[p][d] + beta * y[p][d] for the points
 // of the ntiles_nz non-empty tiles listed in tiles (points sorted by tile,
-// tstart = tile offsets); src is a face field (interp_face) or the gradient
-// of a cell field (interp_grad).
+// tstart = tile offsets; -1 entries of the list are holes); src is a face
+// field (interp_face) or the gradient of a cell field (interp_grad).
 template <typename T>
 hipError_t interp_grad(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, const int *tiles,
                        const int *tstart, const double *X, const T *z, double alpha, const double *y,
@@ -197,20 +198,25 @@ hipError_t interp_grad(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, c
 hipError_t interp_face(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, const int *tiles,
                        const int *tstart, const double *X, const double *u3, double alpha, const double *y,
                        double beta, double *out, hipStream_t s);
-// Touch lists (the tiles whose face boxes a point's support meets), tile by tile (no atomics, fixed order): with list == nullptr the
-// counts of the listed tiles (tiles == nullptr: tiles 0..ntl-1), else their
+// Band tiles: R x R x R point tiles (4R cells per axis, R = 1 or 2), the
+// units of the spreading kernels; nt* count point tiles.
+// Touch lists (the band tiles whose face boxes a point's support meets),
+// band tile by band tile (no atomics, fixed order): with list == nullptr the
+// counts of the listed band tiles (tiles == nullptr: 0..ntl-1), else their
 // lists at lstart; ntl bounds the launch, *ntl_dev (if given) is the count
 hipError_t touch_tiles(int ker, const Geo &g, int nt0, int nt1, int nt2, int ntl, const int *ntl_dev,
                        const int *tiles, const int *tstart, const double *X, int *counts, const int *lstart,
                        int *list, hipStream_t s);
-// flags[t] = 1 for the tiles within one tile of the n tiles nz[0..n)
-hipError_t mark_near(const Geo &g, int nt0, int nt1, int nt2, int n, const int *nz, int *flags, hipStream_t s);
+// flags[b] = 1 for the band tiles holding a point tile within one point tile of
+// the n point tiles nz[0..n)
+hipError_t mark_near(const Geo &g, int nt0, int nt1, int nt2, int n, const int *nz, int *flags,
+                     hipStream_t s);
 // launch order of the n tiles of a list (XCD-chunked, longest lists first in
 // each chunk): order_launch_count(n) entries, -1 in the holes
 hipError_t order_active(int n, const int *active, const int *lstart, int *out, hipStream_t s);
 int order_launch_count(int n);
 hipError_t positive_flags(int n, const int *counts, int *flags, hipStream_t s);
-// band: for the active tiles, out += alpha D (W q)   (div = true, cell field)
+// band: for the active band tiles, out += alpha D (W q)   (div = true, cell field)
 //                          or out += alpha W q       (div = false, face field)
 hipError_t band_apply(int ker, bool div, const Geo &g, int nt1, int nt2, int nactive, const int *active,
                       const int *lstart, const int *list, const double *X, const double *q, double alpha,

@@ -219,6 +219,16 @@ __global__ void __launch_bounds__(256) k_interp(Geo g, int nt1, int nt2, const i
   const int T2 = tile % nt2, r = tile / nt2, T1 = r % nt1, T0 = r / nt1;
   const int o0 = 4 * T0 - 2, o1 = 4 * T1 - 2, o2 = 4 * T2 - 2;  // region origin
   const long long N = 2 * g.half;
+  const int s0 = tstart[tile], s1 = tstart[tile + 1];
+  // the coordinates of this thread's staging tasks in the first chunk
+  // (task t: point t / 6, axis (t % 6) / 2), loaded before the region so
+  // that both sets of loads are in flight together
+  double xpre[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int task = threadIdx.x + 256 * u, pt = task / 6;
+    xpre[u] = s0 + pt < s1 && pt < IPTS ? X[3 * (s0 + pt) + ((task - 6 * pt) >> 1)] : 0.0;
+  }
   for (int e = threadIdx.x; e < NC * IREG * IREG * IREG; e += 256) {
     int comp = e / (IREG * IREG * IREG), l = e % (IREG * IREG * IREG);
     int li = l / (IREG * IREG), lj = (l / IREG) % IREG, lk = l % IREG;
@@ -229,7 +239,6 @@ __global__ void __launch_bounds__(256) k_interp(Geo g, int nt1, int nt2, const i
     if (g.bc2) ok = ok && k >= 0 && k < g.n2; else k = wrapi(k, g.n2);
     reg[comp][l] = ok ? (double)src[comp * N + sidx(g, i, j, k)] : 0.0;
   }
-  const int s0 = tstart[tile], s1 = tstart[tile + 1];
   const int lane = threadIdx.x & 15, ta = lane >> 2, tb = lane & 3;
   const double ih = 1.0 / g.h;
   const int org[3] = {o0, o1, o2};
@@ -239,10 +248,12 @@ __global__ void __launch_bounds__(256) k_interp(Geo g, int nt1, int nt2, const i
     const int np = min(IPTS, s1 - c0);
     __syncthreads();
     // stage weights: one task per (point, axis, staggering)
+    static_assert(6 * IPTS <= 2 * 256, "two staging tasks per thread");
     for (int task = threadIdx.x; task < np * 6; task += 256) {
       int pt = task / 6, rem = task - 6 * pt, ax = rem >> 1, st = rem & 1;
       double wv[4];
-      int i0 = axis_weights<KER>(X[3 * (c0 + pt) + ax], ih, st == 0, wv);
+      const double xv = c0 == s0 ? (task < 256 ? xpre[0] : xpre[1]) : X[3 * (c0 + pt) + ax];
+      int i0 = axis_weights<KER>(xv, ih, st == 0, wv);
       int l0 = i0 - org[ax];
       if (!bcs[ax]) l0 = wrapi(l0 + nn[ax] / 2, nn[ax]) - nn[ax] / 2;
       pb[pt][ax][st] = l0;
@@ -293,7 +304,7 @@ hipError_t interp_grad(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, c
                        hipStream_t s) {
   // positions read, results written (and y read), the cells of the support band (T each)
   ProbeScope probe_(PR_INTERP_GRAD, s,
-                    (double)probe_points() * (beta != 0.0 ? 72 : 48) + (double)probe_active_tiles() * 64 * sizeof(T));
+                    (double)probe_points() * (beta != 0.0 ? 72 : 48) + (double)probe_band_cells() * sizeof(T));
   if (ntiles_nz == 0) return hipSuccess;
   dim3 gr(ntiles_nz), bl(256);
   if (ker == KER_PESKIN4)
@@ -314,7 +325,7 @@ hipError_t interp_face(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, c
                        hipStream_t s) {
   // positions read, results written (and y read), three face components of the support band
   ProbeScope probe_(PR_INTERP_FACE, s,
-                    (double)probe_points() * (beta != 0.0 ? 72 : 48) + (double)probe_active_tiles() * 64 * 3 * 8);
+                    (double)probe_points() * (beta != 0.0 ? 72 : 48) + (double)probe_band_cells() * 3 * 8);
   if (ntiles_nz == 0) return hipSuccess;
   dim3 gr(ntiles_nz), bl(256);
   if (ker == KER_PESKIN4)
@@ -575,24 +586,43 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
   const int nf = cd == 2 ? 5 : 4;
   const bool owner = hl < 30;
   double acc0[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, acc1[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  // Staging task of this thread in every chunk (3 BAND_CH <= 256 tasks: at
+  // most one per thread): axis a of listed point cand.  Its operands are
+  // loaded one chunk ahead and its list entry two chunks ahead, so the
+  // dependent loads (list entry, then position and value) of the next chunk
+  // are in flight while the current one is accumulated.
+  static_assert(3 * BAND_CH <= 256, "one staging task per thread");
+  const int cand = tid / 3, a = tid - 3 * cand;
+  const bool stager = tid < 3 * BAND_CH;
+  auto entry = [&](int c0) { return (stager && c0 + cand < s1) ? list[c0 + cand] : -1; };
+  int p_cur = entry(s0);
+  double xa, qv[3];
+  auto operands = [&](int p, double &x, double (&qq)[3]) {
+    const int pc = p >= 0 ? p : 0;  // every list here is non-empty, so point 0 exists
+    x = X[3 * pc + a];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) qq[d] = a == 0 ? q[3 * pc + d] : 1.0;
+  };
+  operands(p_cur, xa, qv);
+  int p_nxt = entry(s0 + BAND_CH);
   for (int c0 = s0; c0 < s1; c0 += BAND_CH) {
     const int nc = min(BAND_CH, s1 - c0);
     __syncthreads();
-    for (int task = tid; task < 3 * nc; task += 256) {
-      const int cand = task / 3, a = task - 3 * cand;
-      const int p = list[c0 + cand];
-      const double xa = X[3 * p + a];
+    if (p_cur >= 0) {
       double wf[4], wc[4];
       int f0 = axis_weights<KER>(xa, ih, true, wf);
       int e0 = axis_weights<KER>(xa, ih, false, wc);
       int lf = f0 - org[a], lc = e0 - org[a];
       if (!bcs[a]) {
-        lf = wrapi(lf + nn[a] / 2, nn[a]) - nn[a] / 2;
-        lc = wrapi(lc + nn[a] / 2, nn[a]) - nn[a] / 2;
+        // periodic image of the support start in [-4, n - 4): every offset
+        // that reaches the box (-3 .. its last position) keeps its value,
+        // and no image of another can reach it, for any n >= 16
+        lf = wrapi(lf + 4, nn[a]) - 4;
+        lc = wrapi(lc + 4, nn[a]) - 4;
       }
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const double qd = a == 0 ? q[3 * p + d] : 1.0;
+        const double qd = qv[d];
         const int l0 = d == a ? lf : lc;
         const double *w = d == a ? wf : wc;
 #pragma unroll
@@ -609,6 +639,10 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
         }
       }
     }
+    // the next chunk's operands and the list entries of the one after it
+    p_cur = p_nxt;
+    operands(p_cur, xa, qv);
+    p_nxt = entry(c0 + 2 * BAND_CH);
     __syncthreads();
     if (owner) {
       for (int c = 2 * wv + half; c < nc; c += 8) {
@@ -671,7 +705,7 @@ hipError_t band_apply(int ker, bool div, const Geo &g, int nt1, int nt2, int nac
                       double *out, hipStream_t s) {
   // positions and values read, the active tiles' cells (div) or faces read and written
   ProbeScope probe_(div ? PR_BAND_DIV : PR_BAND_FACE, s,
-                    (double)probe_points() * 48 + (double)probe_active_tiles() * 64 * (div ? 1 : 3) * 16);
+                    (double)probe_points() * 48 + (double)probe_band_cells() * (div ? 1 : 3) * 16);
   if (nactive == 0) return hipSuccess;
   dim3 gr(nactive), bl(256);
   if (ker == KER_PESKIN4) {

@@ -40,36 +40,44 @@ __device__ __forceinline__ void ld_pair(const TV *p, double &a, double &b) {
   }
 }
 
-template <typename TV>
-__global__ void __launch_bounds__(RED_T) k_multidot(const double *w, const TV *V, long long stride, int nv,
-                                                    long long n, double *part) {
-  double acc[MD_MAX];
+// The number of vectors is a template parameter (1 .. MD_MAX): the loop over
+// them unrolls completely, so every load of a grid-stride step is issued
+// before the first product waits on one
+template <typename TV, int NV>
+__global__ void __launch_bounds__(RED_T) k_multidot(const double *w, const TV *V, long long stride, long long n,
+                                                    double *part) {
+  double acc[NV];
 #pragma unroll
-  for (int i = 0; i < MD_MAX; ++i) acc[i] = 0.0;
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
   const long long n2 = n >> 1;
   for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n2; t += (long long)gridDim.x * RED_T) {
     const double2 wv = *(const double2 *)(w + 2 * t);
+    double a[NV], b[NV];
 #pragma unroll
-    for (int i = 0; i < MD_MAX; ++i)
-      if (i < nv) {
-        double a, b;
-        ld_pair(V + i * stride + 2 * t, a, b);
-        acc[i] += wv.x * a + wv.y * b;
-      }
+    for (int i = 0; i < NV; ++i) ld_pair(V + i * stride + 2 * t, a[i], b[i]);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] += wv.x * a[i] + wv.y * b[i];
   }
-  __shared__ double sh[4][MD_MAX];
+  __shared__ double sh[4][NV];
   int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
 #pragma unroll
-  for (int i = 0; i < MD_MAX; ++i) {
-    if (i < nv) {
-      double v = wave_sum(acc[i]);
-      if (ln == 0) sh[wv][i] = v;
-    }
+  for (int i = 0; i < NV; ++i) {
+    double v = wave_sum(acc[i]);
+    if (ln == 0) sh[wv][i] = v;
   }
   __syncthreads();
-  if (threadIdx.x < nv)
-    part[(long long)blockIdx.x * nv + threadIdx.x] =
+  if (threadIdx.x < NV)
+    part[(long long)blockIdx.x * NV + threadIdx.x] =
         ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
+}
+
+template <typename TV, int NV>
+static void launch_multidot(const double *w, const TV *V, long long stride, int nv, long long n, double *part,
+                            hipStream_t s) {
+  if constexpr (NV > 1) {
+    if (nv < NV) return launch_multidot<TV, NV - 1>(w, V, stride, nv, n, part, s);
+  }
+  hipLaunchKernelGGL((k_multidot<TV, NV>), dim3(RED_BLOCKS), dim3(RED_T), 0, s, w, V, stride, n, part);
 }
 
 template <typename TV>
@@ -79,15 +87,16 @@ hipError_t multidot(const double *w, const TV *V, long long stride, int nv, long
   // part layout: [blk][nv]; chunks of MD_MAX vectors write consecutive column groups
   for (int c0 = 0; c0 < nv; c0 += MD_MAX) {
     int nc = nv - c0 < MD_MAX ? nv - c0 : MD_MAX;
-    hipLaunchKernelGGL(k_multidot<TV>, dim3(RED_BLOCKS), dim3(RED_T), 0, s, w, V + c0 * stride, stride, nc, n,
-                       part + (long long)c0 * RED_BLOCKS);
+    launch_multidot<TV, MD_MAX>(w, V + c0 * stride, stride, nc, n, part + (long long)c0 * RED_BLOCKS, s);
   }
   return hipGetLastError();
 }
 
 // vout = (TV)(w - sum_i sig2_i g_i V_i) and partial |vout|^2 (vout may alias
 // w when TV is double): the next unnormalised basis vector in one pass
-template <typename TV>
+// NV > 0: that many vectors, unrolled (all loads of a step issued together);
+// NV = 0: nv vectors in a runtime loop
+template <typename TV, int NV>
 __global__ void __launch_bounds__(RED_T) k_update_cast_norm(TV *vout, const double *w, const TV *V, long long stride,
                                                             int nv, const double *g, KCoef sig2, long long n,
                                                             double *part) {
@@ -99,11 +108,22 @@ __global__ void __launch_bounds__(RED_T) k_update_cast_norm(TV *vout, const doub
   const long long n2 = n >> 1;
   for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n2; t += (long long)gridDim.x * RED_T) {
     double2 v = *(const double2 *)(w + 2 * t);
-    for (int i = 0; i < nv; ++i) {
-      double a, b;
-      ld_pair(V + i * stride + 2 * t, a, b);
-      v.x -= hs[i] * a;
-      v.y -= hs[i] * b;
+    if constexpr (NV > 0) {
+      double a[NV], b[NV];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) ld_pair(V + i * stride + 2 * t, a[i], b[i]);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        v.x -= hs[i] * a[i];
+        v.y -= hs[i] * b[i];
+      }
+    } else {
+      for (int i = 0; i < nv; ++i) {
+        double a, b;
+        ld_pair(V + i * stride + 2 * t, a, b);
+        v.x -= hs[i] * a;
+        v.y -= hs[i] * b;
+      }
     }
     if (sizeof(TV) == 4) {
       const float2 f = make_float2((float)v.x, (float)v.y);
@@ -117,12 +137,26 @@ __global__ void __launch_bounds__(RED_T) k_update_cast_norm(TV *vout, const doub
   acc = block_reduce(acc, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
+
+template <typename TV, int NV>
+static void launch_update(TV *vout, const double *w, const TV *V, long long stride, int nv, const double *g,
+                          const KCoef &sig2, long long n, double *part, hipStream_t s) {
+  if constexpr (NV > 1) {
+    if (nv < NV) return launch_update<TV, NV - 1>(vout, w, V, stride, nv, g, sig2, n, part, s);
+  }
+  hipLaunchKernelGGL((k_update_cast_norm<TV, NV>), dim3(RED_BLOCKS), dim3(RED_T), 0, s, vout, w, V, stride, nv, g,
+                     sig2, n, part);
+}
+
 template <typename TV>
 hipError_t update_cast_norm(TV *vout, const double *w, const TV *V, long long stride, int nv, const double *g,
                             const KCoef &sig2, long long n, double *part, hipStream_t s) {
-  if (nv > 64 || (n & 1) || (stride & 1)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_update_cast_norm<TV>, dim3(RED_BLOCKS), dim3(RED_T), 0, s, vout, w, V, stride, nv, g, sig2, n,
-                     part);
+  if (nv < 1 || nv > 64 || (n & 1) || (stride & 1)) return hipErrorInvalidValue;
+  if (nv <= MD_MAX)
+    launch_update<TV, MD_MAX>(vout, w, V, stride, nv, g, sig2, n, part, s);
+  else
+    hipLaunchKernelGGL((k_update_cast_norm<TV, 0>), dim3(RED_BLOCKS), dim3(RED_T), 0, s, vout, w, V, stride, nv, g,
+                       sig2, n, part);
   return hipGetLastError();
 }
 template hipError_t update_cast_norm<float>(float *, const double *, const float *, long long, int, const double *,

@@ -220,6 +220,7 @@ hipError_t mg_smooth(const Geo &g, T *x, const TB *b, int color, hipStream_t s) 
   hipLaunchKernelGGL((k_sweep<T, TB, SW_POISSON>), M.grid, M.block, 0, s, g, x, b, color, g.h2, 0.0, 0.0, 1.0);
   return hipGetLastError();
 }
+
 template <typename T, typename TB>
 hipError_t mg_restrict(const Geo &gf, const T *xf, const TB *bf, const Geo &gc, T *bc, hipStream_t s) {
   MarchShape M = march_shape(gf, 1);

@@ -13,7 +13,7 @@ namespace ibs {
 
 struct ProbeState {
   bool on[PR_COUNT] = {};
-  long long points = 0, active_tiles = 0;
+  long long points = 0, band_cells = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[PR_COUNT];
   std::vector<double> bytes[PR_COUNT];
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
@@ -42,15 +42,15 @@ ProbeState *probe_bind(ProbeState *ps) {
   return prev;
 }
 
-void probe_set_points(ProbeState *ps, long long K, long long active_tiles) {
+void probe_set_points(ProbeState *ps, long long K, long long band_cells) {
   if (ps) {
     ps->points = K;
-    ps->active_tiles = active_tiles;
+    ps->band_cells = band_cells;
   }
 }
 
 long long probe_points() { return t_probe ? t_probe->points : 0; }
-long long probe_active_tiles() { return t_probe ? t_probe->active_tiles : 0; }
+long long probe_band_cells() { return t_probe ? t_probe->band_cells : 0; }
 
 int probe_begin(int id, hipStream_t s, double bytes) {
   ProbeState *ps = t_probe;

@@ -69,6 +69,46 @@ def mixed_workload(seed=12):
     return wl.Workload("mixed_16x24x32", cfg, bodies, off, np.zeros((3,) + n), steps=1, seed=seed)
 
 
+def odd_tiles_workload(seed=13):
+    """A grid whose point-tile counts are odd along two axes (20 x 24 x 28
+    cells of width 1/28: 5 x 6 x 7 tiles of 4^3 cells), so the spreading runs
+    on 4^3-cell band tiles instead of 8^3; periodic, no-slip and free-slip
+    axes; one sphere; the multigrid hierarchy stops at 10 x 12 x 14."""
+    rng = np.random.default_rng(seed)
+    n = (20, 24, 28)
+    h = 1.0 / 28
+    radius = 0.17
+    K = 220
+    cfg = wl.Config(n=n, length=tuple(x * h for x in n), bc=(wl.BC_PERIODIC, wl.BC_NOSLIP, wl.BC_FREESLIP),
+                    nu=0.02, dt=0.005, delta=wl.DELTA_PESKIN4,
+                    lump_c=wl.lump_constant(wl.DELTA_PESKIN4, h, K, radius), krylov_rtol=1e-12, mg_coarsest=14)
+    c = np.array([0.3, 0.43, 0.5]) + rng.uniform(-0.01, 0.01, 3)
+    bodies = [wl.Body(center=c, vel=rng.normal(0, 0.1, 3), omega=np.array([0.0, 1.0, 0.0]), radius=radius,
+                      n_points=K)]
+    return wl.Workload("odd_tiles_20x24x28", cfg, bodies, wl.fibonacci_offsets(K, radius), np.zeros((3,) + n),
+                       steps=1, seed=seed)
+
+
+def wrap16_workload(seed=14):
+    """A 16^3 periodic box (two 8^3-cell band tiles per axis) with one sphere
+    centred near a corner, so that point supports wrap across the x and z
+    boundaries and reach the last face position of a band tile's box from
+    the far side."""
+    rng = np.random.default_rng(seed)
+    n = (16, 16, 16)
+    h = 1.0 / 16
+    radius = 0.2
+    K = 130
+    cfg = wl.Config(n=n, length=(1.0, 1.0, 1.0), bc=(wl.BC_PERIODIC,) * 3, nu=0.02, dt=0.005,
+                    delta=wl.DELTA_PESKIN4, lump_c=wl.lump_constant(wl.DELTA_PESKIN4, h, K, radius),
+                    krylov_rtol=1e-12)
+    c = np.array([0.97, 0.5, 0.03]) + rng.uniform(-0.01, 0.01, 3)
+    bodies = [wl.Body(center=c, vel=rng.normal(0, 0.1, 3), omega=np.array([1.0, 0.0, 0.0]), radius=radius,
+                      n_points=K)]
+    return wl.Workload("wrap16_periodic", cfg, bodies, wl.fibonacci_offsets(K, radius), np.zeros((3,) + n),
+                       steps=1, seed=seed)
+
+
 def free_workload(n=32, bc=wl.BC_PERIODIC, seed=21, precision=wl.PREC_FP64, xi=0.6, outer_iters=3):
     """Two free spheres (a = 0.15, theta 1.5 and 2.5) under gravity, with small
     random initial velocities and spins in a random solenoidal flow (periodic)

@@ -7,7 +7,8 @@ from oracle import mac as omac
 from paper_2501_15314_amd import workloads as wl
 
 from .conftest import gpu_available
-from .gpu_helpers import CHUNKS, freeslip_workload, make_sim, mixed_workload, oracle_for, rel, walls_workload
+from .gpu_helpers import (CHUNKS, freeslip_workload, make_sim, mixed_workload, odd_tiles_workload, oracle_for, rel,
+                          walls_workload, wrap16_workload)
 
 pytestmark = pytest.mark.gpu
 
@@ -21,10 +22,13 @@ def _cases():
         "walls": lambda: walls_workload(32, 260),
         "mixed": mixed_workload,
         "freeslip": freeslip_workload,
+        "odd_tiles": odd_tiles_workload,
+        "wrap16": wrap16_workload,
     }
 
 
-@pytest.fixture(scope="module", params=[(c, m) for c in ["c1_periodic", "walls", "mixed", "freeslip"]
+@pytest.fixture(scope="module", params=[(c, m) for c in ["c1_periodic", "walls", "mixed", "freeslip", "odd_tiles",
+                                                                  "wrap16"]
                                         for m in CHUNKS], ids=lambda p: f"{p[0]}-{p[1]}")
 def setup(request):
     case, chunks = request.param
