@@ -225,6 +225,26 @@ sim_status sim_step(sim_t sim, int32_t nsteps, sim_step_stats *stats);
 sim_status sim_solve_schur(sim_t sim, const double *d_rhs_p, const double *d_rhs_f,
                            double *d_p, double *d_phi, sim_solve_stats *stats);
 
+/* sim_solve_schur for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same solve, arguments, results and errors, bit for bit, but the
+ * solve's work arrays (staged right-hand sides, Krylov basis and
+ * preconditioned vectors, BiCGStab vectors, multigrid levels below the
+ * finest, fast-diagonalisation work grids, reduction partials) live in a
+ * static device array of 64 MiB that the library holds on each device for
+ * the life of the process, instead of in the handle's workspace.  The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ * The handle's state (points, tiles, touch lists, eigenbases) still comes
+ * from its workspace.  64 MiB covers e.g. a 64^3 grid in the FP32MG form or
+ * a 48^3 grid in FP64 with krylov_restart 20; a configuration whose solve
+ * needs more returns SIM_EINVAL with the byte count in sim_last_error.
+ * Every call on a device shares that device's array: calls that overlap in
+ * time on one device (from any handle, thread or stream) race and must be
+ * serialised by the caller.  Nothing in the array needs to be zero at the
+ * start of a call. */
+sim_status sim_solve_schur_noalloc(sim_t sim, const double *d_rhs_p, const double *d_rhs_f,
+                                   double *d_p, double *d_phi, sim_solve_stats *stats);
+
 /* Forces of the last step: d_f [K][3] = h^3 Phi_k (may be NULL) and, per
  * body, body_ft [nb][6] = (h^3 sum Phi, h^3 sum L~ x Phi) on the host. */
 sim_status sim_get_forces(sim_t sim, double *d_f, double *body_ft);

@@ -21,7 +21,7 @@ OPS = dict(laplacian=0, schur=1, precond=2, grad=3, div=4, interp=5, spread=6, h
            convection=8, helm_solve=9, schur_rhs=10, schur_exact=11)
 
 EXPORTS = ["sim_config_check", "sim_workspace_bytes", "sim_create", "sim_destroy", "sim_set_bodies", "sim_set_fields",
-           "sim_get_fields", "sim_step", "sim_solve_schur", "sim_get_forces",
+           "sim_get_fields", "sim_step", "sim_solve_schur", "sim_solve_schur_noalloc", "sim_get_forces",
            "sim_get_points",
            "sim_get_body_state", "sim_set_time",
            "sim_step_adjoint", "sim_step_adjoint_two_way", "sim_apply", "sim_schur_spectrum", "sim_probe_enable", "sim_probe_read", "sim_last_error"]
@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH):
     lib.sim_get_fields.argtypes = [sim_t, VP, VP, VP, VP]
     lib.sim_step.argtypes = [sim_t, I32, P(StepStats)]
     lib.sim_solve_schur.argtypes = [sim_t, VP, VP, VP, VP, P(SolveStats)]
+    lib.sim_solve_schur_noalloc.argtypes = [sim_t, VP, VP, VP, VP, P(SolveStats)]
     lib.sim_get_forces.argtypes = [sim_t, VP, P(D)]
     lib.sim_get_points.argtypes = [sim_t, VP, VP]
     lib.sim_get_body_state.argtypes = [sim_t, P(D)]

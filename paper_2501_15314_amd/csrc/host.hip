@@ -19,6 +19,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -27,6 +28,13 @@
 #include "internal.h"
 
 using namespace ibs;
+
+// Static scratch of sim_solve_schur_noalloc (callers that cannot allocate):
+// the work arrays of one Schur solve, one copy per device for the life of
+// the process.  In host code `scratch` only names the symbol; its device
+// address comes from hipGetSymbolAddress (noalloc_scratch_setup).
+constexpr size_t NOALLOC_SCRATCH_BYTES = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -132,6 +140,8 @@ struct sim_s {
   hipEvent_t ev_iter = nullptr;  // end of an FGMRES iteration's coefficients (pipelined wait)
   // multigrid level sizes (3 per level, finest first)
   std::vector<int> dims;
+  // the device address of this device's static scratch (sim_solve_schur_noalloc)
+  void *noalloc_scratch = nullptr;
   // last-step statistics
   sim_step_stats last{};
   bool have_bodies = false;
@@ -1466,6 +1476,26 @@ sim_status step_two_way(sim_t s, sim_step_stats *out) {
 
 }  // namespace
 
+// The device address of the static scratch on `device`, which must be the
+// current device: taken once per device and kept (each device holds its own
+// copy of the array).
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+hipError_t noalloc_scratch_setup(int device, void **out) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_noalloc_ptr[device] = p;
+  }
+  *out = g_noalloc_ptr[device];
+  return hipSuccess;
+}
+
 // Frees what sim_create took besides the caller's workspace: the pinned
 // reduction mirror, the probe events and the handle itself.
 void release_handle(sim_t s) {
@@ -1550,7 +1580,8 @@ sim_status sim_create(const sim_config *cfg, void *d_workspace, size_t bytes, in
   s->probes = probe_new();
   s->dims = dims;
   if (hipEventCreate(&s->ev_solve[0]) != hipSuccess || hipEventCreate(&s->ev_solve[1]) != hipSuccess ||
-      hipEventCreateWithFlags(&s->ev_iter, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&s->ev_iter, hipEventDisableTiming) != hipSuccess ||
+      noalloc_scratch_setup(cfg->device, &s->noalloc_scratch) != hipSuccess) {
     release_handle(s);
     return SIM_EDEVICE;
   }
@@ -1782,6 +1813,29 @@ sim_status sim_solve_schur(sim_t s, const double *d_rhs_p, const double *d_rhs_f
   if (!s) return SIM_EINVAL;
   ProbeBind probe_bind_(s->probes);
   return solve_schur_entry(s, d_rhs_p, d_rhs_f, d_p, d_phi, stats);
+}
+
+sim_status sim_solve_schur_noalloc(sim_t s, const double *d_rhs_p, const double *d_rhs_f, double *d_p,
+                                   double *d_phi, sim_solve_stats *stats) {
+  if (!s) return SIM_EINVAL;
+  ProbeBind probe_bind_(s->probes);
+  if (!s->noalloc_scratch) return fail(s, SIM_ESTATE, "static scratch not set up");
+  const long long K = s->Kmax > 0 ? s->Kmax : 1;
+  Carver sizing(nullptr);
+  carve_solve(sizing, &s->cfg, K, 0, s->dims);
+  if (sizing.off > NOALLOC_SCRATCH_BYTES) {
+    char msg[160];
+    snprintf(msg, sizeof msg, "this solve needs %zu bytes of static scratch, more than its %zu", sizing.off,
+             (size_t)NOALLOC_SCRATCH_BYTES);
+    return fail(s, SIM_EINVAL, msg);
+  }
+  Carver cv(s->noalloc_scratch);
+  const SolveScratch mine = carve_solve(cv, &s->cfg, K, 0, s->dims);
+  const SolveScratch own = get_solve_scratch(s);
+  put_solve_scratch(s, mine);
+  const sim_status rc = solve_schur_entry(s, d_rhs_p, d_rhs_f, d_p, d_phi, stats);
+  put_solve_scratch(s, own);
+  return rc;
 }
 
 sim_status sim_step(sim_t s, int32_t nsteps, sim_step_stats *stats) {

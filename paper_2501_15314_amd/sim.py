@@ -189,6 +189,18 @@ class Sim:
                                                   C.byref(st)), allow_notconv)
         return p, phi[:self.K], st
 
+    def solve_schur_noalloc(self, rhs_p, rhs_f, allow_notconv=False):
+        """sim_solve_schur_noalloc: the solve with its work arrays in the
+        library's static device scratch (the output tensors are allocated
+        here, by the caller, as the C ABI expects)."""
+        rp, rf = self._t(rhs_p), self._t(rhs_f)
+        p = torch.empty(self.n, dtype=torch.float64, device=self.dev)
+        phi = torch.empty((max(self.K, 1), 3), dtype=torch.float64, device=self.dev)
+        st = _lib.SolveStats()
+        rc = self._check(self.lib.sim_solve_schur_noalloc(self.h, _ptr(rp), _ptr(rf), _ptr(p), _ptr(phi),
+                                                          C.byref(st)), allow_notconv)
+        return p, phi[:self.K], st
+
     def apply(self, op, x, x2=None):
         opid = _lib.OPS[op]
         x = self._t(x)
