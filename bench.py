@@ -166,6 +166,9 @@ def main():
                     help="skip the solver variants (fast-diagonalisation preconditioner, BiCGStab)")
     ap.add_argument("--no-steps", action="store_true",
                     help="skip the whole-time-step timings (128^3, 256^3, 384^3 two-way)")
+    ap.add_argument("--step-workloads", default="c3,c2,c5",
+                    help="comma-separated whole-time-step timings to run (c3: 256^3, c2: 128^3 oscillating "
+                         "sphere, c5: 384^3 two-way)")
     ap.add_argument("--c5-steps", type=int, default=100, help="timed two-way steps at 384^3")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the reference "
@@ -324,6 +327,8 @@ def main():
                                            (wl.PREC_FP64, wl.PREC_FP32MG)),
                                           ("c5_384cube_27free_spheres", wl.make_c5, args.c5_steps,
                                            (wl.PREC_FP32MG,))):
+            if tag.split("_")[0] not in args.step_workloads.split(","):
+                continue
             for prec in forms_:
                 wt = make()
                 wt.cfg.precision = prec
