@@ -75,6 +75,19 @@ __device__ __forceinline__ bool row_pos(const Geo &g, RowPos &p) {
   return true;
 }
 
+// 1 / (number of neighbours), rounded once: the pressure relaxations
+// multiply by it instead of dividing.  Selects among constants (no division,
+// no branch); a cell has 1..6 neighbours.
+template <typename T>
+__device__ __forceinline__ T inv_nn(int nn) {
+  T r = nn >= 6 ? T(1) / T(6) : T(1) / T(5);
+  r = nn == 4 ? T(0.25) : r;
+  r = nn == 3 ? T(1) / T(3) : r;
+  r = nn == 2 ? T(0.5) : r;
+  r = nn <= 1 ? T(1) : r;
+  return r;
+}
+
 // Number of neighbours of a cell that exist (walls remove one per side); the
 // diagonal of L = G^T G is nnb / h^2.
 __device__ __forceinline__ int cell_nnb(const Geo &g, int i, int j, int k) {

@@ -278,12 +278,6 @@ __device__ __forceinline__ T lds_nb(const T *x, LvlDim d, int bc0, int bc1, int 
   return s;
 }
 
-// 1 / (number of neighbours) for 0..6 neighbours
-template <typename T>
-__device__ __forceinline__ T inv_nn(int nn) {
-  return nn == 6 ? T(1) / T(6) : nn == 5 ? T(1) / T(5) : nn == 4 ? T(0.25) : nn == 3 ? T(1) / T(3) : T(1) / T(nn);
-}
-
 // Sync of the threads that take part in a coarse-kernel phase: the whole
 // workgroup, or only wavefront 0 for levels small enough for one wavefront
 // (its LDS operations complete in program order, so a compiler-level fence
