@@ -188,7 +188,8 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 // Sum over groups of 16 lanes (lanes 16q .. 16q+15), fixed order.
-__device__ __forceinline__ double sum16(double v) {
+template <typename TA>
+__device__ __forceinline__ TA sum16(TA v) {
 #pragma unroll
   for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;

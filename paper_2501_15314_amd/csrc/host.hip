@@ -597,15 +597,20 @@ double fd_bytes(const sim_s *s, size_t ti, size_t to) { return (double)s->N * (t
 double fdx_bytes(const sim_s *s) { return (double)s->N * 16 * 8; }
 
 // w = S~ z = L z + c^-1 G^T W W^T G z  (= L z - c^-1 D W (W^T G z))
+// f32: the coupling term in float32 arithmetic (float32 z only), for the
+// products of the float32 FGMRES cycle, whose restarts from the float64
+// true residual absorb its rounding; every other product is float64.
 template <typename T>
-sim_status schur_matvec(sim_t s, const T *z, double *w) {
+sim_status schur_matvec(sim_t s, const T *z, double *w, bool f32 = false) {
   {
     ProbeScope pr(PR_LAP, s->st, (double)s->N * (sizeof(T) + sizeof(double)));  // z read, w written
     CKH(lap_apply<T>(s->g, z, w, s->st));
   }
-  CKH(interp_grad<T>(s->ker, s->g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, z, 1.0, nullptr, 0.0, s->Q, s->st));
+  const bool c32 = f32 && sizeof(T) == sizeof(float);
+  CKH(interp_grad<T>(s->ker, s->g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, z, 1.0, nullptr, 0.0, s->Q,
+                     s->st, c32));
   CKH(band_apply(s->ker, true, s->g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, s->Q,
-                 -1.0 / s->c, w, s->st));
+                 -1.0 / s->c, w, s->st, c32));
   return SIM_OK;
 }
 
@@ -783,7 +788,7 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
       sim_status r = vcycle<T, T>(s, vj, zj);
       if (r) return r;
     }
-    sim_status r = schur_matvec<T>(s, zj, w);
+    sim_status r = schur_matvec<T>(s, zj, w, true);
     if (r) return r;
     {
       ProbeScope pr(PR_MULTIDOT, st, (double)N * (sizeof(double) + (j + 1) * sizeof(T)));  // w, V_0..V_j

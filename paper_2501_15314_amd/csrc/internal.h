@@ -194,7 +194,7 @@ hipError_t scale3(int K, const double *x, double alpha, const double *y, double 
 template <typename T>
 hipError_t interp_grad(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, const int *tiles,
                        const int *tstart, const double *X, const T *z, double alpha, const double *y,
-                       double beta, double *out, hipStream_t s);
+                       double beta, double *out, hipStream_t s, bool f32 = false);
 hipError_t interp_face(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, const int *tiles,
                        const int *tstart, const double *X, const double *u3, double alpha, const double *y,
                        double beta, double *out, hipStream_t s);
@@ -220,7 +220,7 @@ hipError_t positive_flags(int n, const int *counts, int *flags, hipStream_t s);
 //                          or out += alpha W q       (div = false, face field)
 hipError_t band_apply(int ker, bool div, const Geo &g, int nt1, int nt2, int nactive, const int *active,
                       const int *lstart, const int *list, const double *X, const double *q, double alpha,
-                      double *out, hipStream_t s);
+                      double *out, hipStream_t s, bool f32 = false);
 
 // ---- reductions / Krylov vector kernels (kernels_krylov.hip) ---------------
 int red_blocks();

@@ -205,14 +205,16 @@ hipError_t scale3(int K, const double *x, double alpha, const double *y, double 
 constexpr int IREG = 8;   // region width per axis
 constexpr int IPTS = 64;  // points staged per pass
 
-template <int KER, int MODE, typename T>
+template <int KER, int MODE, typename T, typename TA>
 __global__ void __launch_bounds__(256) k_interp(Geo g, int nt1, int nt2, const int *tiles, const int *tstart,
                                                 const double *X, const T *src, double alpha, const double *y,
                                                 double beta, double *out) {
   constexpr int W = KerWidth<KER>::W;
   constexpr int NC = MODE == 0 ? 3 : 1;
-  __shared__ double reg[NC][IREG * IREG * IREG];
-  __shared__ double pw[IPTS][3][2][4];   // [point][axis][face/centre][node]
+  // TA: the arithmetic type (float64, or float32 for the gradient of a
+  // float32 cell field in the float32 Krylov cycle, weights rounded to it)
+  __shared__ TA reg[NC][IREG * IREG * IREG];
+  __shared__ TA pw[IPTS][3][2][4];   // [point][axis][face/centre][node]
   __shared__ int pb[IPTS][3][2];         // local start of the support
   const int tile = tiles[blockIdx.x];
   if (tile < 0) return;  // a hole of the launch order
@@ -237,7 +239,7 @@ __global__ void __launch_bounds__(256) k_interp(Geo g, int nt1, int nt2, const i
     if (g.bc0) ok = ok && i >= 0 && i < g.n0; else i = wrapi(i, g.n0);
     if (g.bc1) ok = ok && j >= 0 && j < g.n1; else j = wrapi(j, g.n1);
     if (g.bc2) ok = ok && k >= 0 && k < g.n2; else k = wrapi(k, g.n2);
-    reg[comp][l] = ok ? (double)src[comp * N + sidx(g, i, j, k)] : 0.0;
+    reg[comp][l] = ok ? (TA)src[comp * N + sidx(g, i, j, k)] : TA(0);
   }
   const int lane = threadIdx.x & 15, ta = lane >> 2, tb = lane & 3;
   const double ih = 1.0 / g.h;
@@ -260,7 +262,7 @@ __global__ void __launch_bounds__(256) k_interp(Geo g, int nt1, int nt2, const i
       // a wall face (index 0 along a wall axis) carries no gradient: zero its weight
 #pragma unroll
       for (int t = 0; t < 4; ++t)
-        pw[pt][ax][st][t] = (MODE == 1 && st == 0 && bcs[ax] && i0 + t == 0) ? 0.0 : wv[t];
+        pw[pt][ax][st][t] = (MODE == 1 && st == 0 && bcs[ax] && i0 + t == 0) ? TA(0) : (TA)wv[t];
     }
     __syncthreads();
     for (int pb0 = 0; pb0 < np; pb0 += 16) {
@@ -268,22 +270,22 @@ __global__ void __launch_bounds__(256) k_interp(Geo g, int nt1, int nt2, const i
       bool active = pt < np;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        double acc = 0.0;
+        TA acc = TA(0);
         if (active && ta < W && tb < W) {
           const int sx = d == 0 ? 0 : 1, sy = d == 1 ? 0 : 1, sz = d == 2 ? 0 : 1;
           int li = pb[pt][0][sx] + ta, lj = pb[pt][1][sy] + tb, lk0 = pb[pt][2][sz];
-          double wab = pw[pt][0][sx][ta] * pw[pt][1][sy][tb];
+          TA wab = pw[pt][0][sx][ta] * pw[pt][1][sy][tb];
 #pragma unroll
           for (int c = 0; c < W; ++c) {
             int lk = lk0 + c;
-            double v = 0.0;
+            TA v = TA(0);
             bool in = (unsigned)li < IREG && (unsigned)lj < IREG && (unsigned)lk < IREG;
             if (MODE == 0) {
               if (in) v = reg[d][(li * IREG + lj) * IREG + lk];
             } else {
               int mi = li - (d == 0), mj = lj - (d == 1), mk = lk - (d == 2);
               bool inm = (unsigned)mi < IREG && (unsigned)mj < IREG && (unsigned)mk < IREG;
-              if (in && inm) v = (reg[0][(li * IREG + lj) * IREG + lk] - reg[0][(mi * IREG + mj) * IREG + mk]) * ih;
+              if (in && inm) v = (reg[0][(li * IREG + lj) * IREG + lk] - reg[0][(mi * IREG + mj) * IREG + mk]) * (TA)ih;
             }
             acc += (wab * pw[pt][2][sz][c]) * v;
           }
@@ -291,7 +293,7 @@ __global__ void __launch_bounds__(256) k_interp(Geo g, int nt1, int nt2, const i
         acc = sum16(acc);
         if (active && lane == 0) {
           long long o = 3LL * (c0 + pt) + d;
-          out[o] = alpha * acc + (y ? beta * y[o] : 0.0);
+          out[o] = alpha * (double)acc + (y ? beta * y[o] : 0.0);
         }
       }
     }
@@ -301,24 +303,29 @@ __global__ void __launch_bounds__(256) k_interp(Geo g, int nt1, int nt2, const i
 template <typename T>
 hipError_t interp_grad(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, const int *tiles, const int *tstart,
                        const double *X, const T *z, double alpha, const double *y, double beta, double *out,
-                       hipStream_t s) {
+                       hipStream_t s, bool f32) {
   // positions read, results written (and y read), the cells of the support band (T each)
   ProbeScope probe_(PR_INTERP_GRAD, s,
                     (double)probe_points() * (beta != 0.0 ? 72 : 48) + (double)probe_band_cells() * sizeof(T));
   if (ntiles_nz == 0) return hipSuccess;
+  if (f32 && sizeof(T) != sizeof(float)) return hipErrorInvalidValue;
   dim3 gr(ntiles_nz), bl(256);
-  if (ker == KER_PESKIN4)
-    hipLaunchKernelGGL((k_interp<KER_PESKIN4, 1, T>), gr, bl, 0, s, g, nt1, nt2, tiles, tstart, X, z, alpha, y,
-                       beta, out);
-  else
-    hipLaunchKernelGGL((k_interp<KER_ROMA3, 1, T>), gr, bl, 0, s, g, nt1, nt2, tiles, tstart, X, z, alpha, y,
-                       beta, out);
+#define INTERP(K_, A_) \
+  hipLaunchKernelGGL((k_interp<K_, 1, T, A_>), gr, bl, 0, s, g, nt1, nt2, tiles, tstart, X, z, alpha, y, beta, out)
+  if (ker == KER_PESKIN4) {
+    if (f32) INTERP(KER_PESKIN4, float);
+    else INTERP(KER_PESKIN4, double);
+  } else {
+    if (f32) INTERP(KER_ROMA3, float);
+    else INTERP(KER_ROMA3, double);
+  }
+#undef INTERP
   return hipGetLastError();
 }
 template hipError_t interp_grad<float>(int, const Geo &, int, int, int, const int *, const int *, const double *,
-                                       const float *, double, const double *, double, double *, hipStream_t);
+                                       const float *, double, const double *, double, double *, hipStream_t, bool);
 template hipError_t interp_grad<double>(int, const Geo &, int, int, int, const int *, const int *, const double *,
-                                        const double *, double, const double *, double, double *, hipStream_t);
+                                        const double *, double, const double *, double, double *, hipStream_t, bool);
 
 hipError_t interp_face(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, const int *tiles, const int *tstart,
                        const double *X, const double *u3, double alpha, const double *y, double beta, double *out,
@@ -329,10 +336,10 @@ hipError_t interp_face(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, c
   if (ntiles_nz == 0) return hipSuccess;
   dim3 gr(ntiles_nz), bl(256);
   if (ker == KER_PESKIN4)
-    hipLaunchKernelGGL((k_interp<KER_PESKIN4, 0, double>), gr, bl, 0, s, g, nt1, nt2, tiles, tstart, X, u3, alpha,
+    hipLaunchKernelGGL((k_interp<KER_PESKIN4, 0, double, double>), gr, bl, 0, s, g, nt1, nt2, tiles, tstart, X, u3, alpha,
                        y, beta, out);
   else
-    hipLaunchKernelGGL((k_interp<KER_ROMA3, 0, double>), gr, bl, 0, s, g, nt1, nt2, tiles, tstart, X, u3, alpha, y,
+    hipLaunchKernelGGL((k_interp<KER_ROMA3, 0, double, double>), gr, bl, 0, s, g, nt1, nt2, tiles, tstart, X, u3, alpha, y,
                        beta, out);
   return hipGetLastError();
 }
@@ -553,15 +560,17 @@ constexpr int BAND_CH = 64;
 // fall on distinct banks for the accumulation reads.
 constexpr int BAND_WS = 45;
 
-template <int KER, bool DIV>
+template <int KER, bool DIV, typename TA>
 __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int *active, const int *lstart,
                                               const int *list, const double *X, const double *q, double alpha,
                                               double *out) {
   // [cand][axis a * 15 + comp * 5 + position]; after the last chunk the same
   // LDS holds the per-half-wavefront face sums part[8][3][80]
   static_assert(8 * 3 * 80 <= BAND_CH * BAND_WS, "face sums must fit the weight buffer");
-  __shared__ double wts[BAND_CH][BAND_WS];
-  double(*part)[3][80] = reinterpret_cast<double(*)[3][80]>(&wts[0][0]);
+  // TA: the weights' and sums' type (float64, or float32 for the S~ products
+  // of the float32 Krylov cycle)
+  __shared__ TA wts[BAND_CH][BAND_WS];
+  TA(*part)[3][80] = reinterpret_cast<TA(*)[3][80]>(&wts[0][0]);
   const int tile = active[blockIdx.x];
   if (tile < 0) return;  // a hole of the launch order
   const int T2 = tile % nt2, r = tile / nt2, T1 = r % nt1, T0 = r / nt1;
@@ -585,7 +594,7 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
   const bool has1 = cj0 + 1 < cby;
   const int nf = cd == 2 ? 5 : 4;
   const bool owner = hl < 30;
-  double acc0[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, acc1[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  TA acc0[5] = {TA(0), TA(0), TA(0), TA(0), TA(0)}, acc1[5] = {TA(0), TA(0), TA(0), TA(0), TA(0)};
   // Staging task of this thread in every chunk (3 BAND_CH <= 256 tasks: at
   // most one per thread): axis a of listed point cand.  Its operands are
   // loaded one chunk ahead and its list entry two chunks ahead, so the
@@ -635,7 +644,7 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
           v = idx == 2 ? w[2] : v;
           v = idx == 3 ? w[3] : v;
           v *= (t < 4 || d == a) ? qd : 0.0;
-          wts[cand][15 * a + 5 * d + t] = v;
+          wts[cand][15 * a + 5 * d + t] = (TA)v;
         }
       }
     }
@@ -646,13 +655,13 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
     __syncthreads();
     if (owner) {
       for (int c = 2 * wv + half; c < nc; c += 8) {
-        const double *W = wts[c] + 5 * cd;
-        const double wx = W[ci];
-        const double wab0 = wx * W[15 + cj0];
-        const double wab1 = has1 ? wx * W[16 + cj0] : 0.0;
+        const TA *W = wts[c] + 5 * cd;
+        const TA wx = W[ci];
+        const TA wab0 = wx * W[15 + cj0];
+        const TA wab1 = has1 ? wx * W[16 + cj0] : TA(0);
 #pragma unroll
         for (int fk = 0; fk < 5; ++fk) {
-          const double wz = W[30 + fk];
+          const TA wz = W[30 + fk];
           acc0[fk] += wab0 * wz;
           acc1[fk] += wab1 * wz;
         }
@@ -674,7 +683,7 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
   __syncthreads();
   long long N = 2 * g.half;
   auto face = [&](int d, int idx) {
-    double f = part[0][d][idx];
+    TA f = part[0][d][idx];
 #pragma unroll
     for (int q = 1; q < 8; ++q) f += part[q][d][idx];
     return f;
@@ -682,12 +691,12 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
   if (DIV) {
     if (tid < 64) {
       int ci2 = tid >> 4, cj2 = (tid >> 2) & 3, ck = tid & 3;
-      double dv = 0.0;
+      TA dv = TA(0);
       dv += face(0, ((ci2 + 1) * 4 + cj2) * 4 + ck) - face(0, (ci2 * 4 + cj2) * 4 + ck);
       dv += face(1, (ci2 * 5 + cj2 + 1) * 4 + ck) - face(1, (ci2 * 5 + cj2) * 4 + ck);
       dv += face(2, (ci2 * 4 + cj2) * 5 + ck + 1) - face(2, (ci2 * 4 + cj2) * 5 + ck);
       int gi = 4 * T0 + ci2, gj = 4 * T1 + cj2, gk = 4 * T2 + ck;
-      out[sidx(g, gi, gj, gk)] += alpha * dv * ih;
+      out[sidx(g, gi, gj, gk)] += alpha * (double)dv * ih;
     }
   } else {
     if (tid < 192) {
@@ -695,30 +704,33 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
       int fi = t >> 4, fj = (t >> 2) & 3, fk = t & 3;
       int by = 4 + (d == 1), bz = 4 + (d == 2);
       int gi = 4 * T0 + fi, gj = 4 * T1 + fj, gk = 4 * T2 + fk;
-      out[d * N + sidx(g, gi, gj, gk)] += alpha * face(d, (fi * by + fj) * bz + fk);
+      out[d * N + sidx(g, gi, gj, gk)] += alpha * (double)face(d, (fi * by + fj) * bz + fk);
     }
   }
 }
 
 hipError_t band_apply(int ker, bool div, const Geo &g, int nt1, int nt2, int nactive, const int *active,
                       const int *lstart, const int *list, const double *X, const double *q, double alpha,
-                      double *out, hipStream_t s) {
+                      double *out, hipStream_t s, bool f32) {
   // positions and values read, the active tiles' cells (div) or faces read and written
   ProbeScope probe_(div ? PR_BAND_DIV : PR_BAND_FACE, s,
                     (double)probe_points() * 48 + (double)probe_band_cells() * (div ? 1 : 3) * 16);
   if (nactive == 0) return hipSuccess;
   dim3 gr(nactive), bl(256);
-  if (ker == KER_PESKIN4) {
-    if (div)
-      hipLaunchKernelGGL((k_band<KER_PESKIN4, true>), gr, bl, 0, s, g, nt1, nt2, active, lstart, list, X, q, alpha, out);
-    else
-      hipLaunchKernelGGL((k_band<KER_PESKIN4, false>), gr, bl, 0, s, g, nt1, nt2, active, lstart, list, X, q, alpha, out);
+#define BAND(K_, D_, A_) \
+  hipLaunchKernelGGL((k_band<K_, D_, A_>), gr, bl, 0, s, g, nt1, nt2, active, lstart, list, X, q, alpha, out)
+  if (f32) {
+    if (!div) return hipErrorInvalidValue;  // float32 sums serve the S~ products only
+    if (ker == KER_PESKIN4) BAND(KER_PESKIN4, true, float);
+    else BAND(KER_ROMA3, true, float);
+  } else if (ker == KER_PESKIN4) {
+    if (div) BAND(KER_PESKIN4, true, double);
+    else BAND(KER_PESKIN4, false, double);
   } else {
-    if (div)
-      hipLaunchKernelGGL((k_band<KER_ROMA3, true>), gr, bl, 0, s, g, nt1, nt2, active, lstart, list, X, q, alpha, out);
-    else
-      hipLaunchKernelGGL((k_band<KER_ROMA3, false>), gr, bl, 0, s, g, nt1, nt2, active, lstart, list, X, q, alpha, out);
+    if (div) BAND(KER_ROMA3, true, double);
+    else BAND(KER_ROMA3, false, double);
   }
+#undef BAND
   return hipGetLastError();
 }
 
