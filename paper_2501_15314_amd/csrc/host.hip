@@ -596,21 +596,23 @@ double fd_bytes(const sim_s *s, size_t ti, size_t to) { return (double)s->N * (t
 // written in split order (16 passes of 8 bytes per cell).
 double fdx_bytes(const sim_s *s) { return (double)s->N * 16 * 8; }
 
-// w = S~ z = L z + c^-1 G^T W W^T G z  (= L z - c^-1 D W (W^T G z))
-// f32: the coupling term in float32 arithmetic (float32 z only), for the
-// products of the float32 FGMRES cycle, whose restarts from the float64
-// true residual absorb its rounding; every other product is float64.
-template <typename T>
-sim_status schur_matvec(sim_t s, const T *z, double *w, bool f32 = false) {
+// w = S~ z = L z + c^-1 G^T W W^T G z  (= L z - c^-1 D W (W^T G z)), in
+// float64.  With TW = float (the products of the float32 FGMRES cycle, z in
+// float32 too) w is stored in float32 and its coupling term is formed in
+// float32 arithmetic; the cycle's restarts from the float64 true residual
+// absorb their rounding.  Every other product is float64.
+template <typename T, typename TW = double>
+sim_status schur_matvec(sim_t s, const T *z, TW *w) {
+  constexpr bool f32 = std::is_same<TW, float>::value;
+  static_assert(!f32 || std::is_same<T, float>::value, "a float32 product takes a float32 z");
   {
-    ProbeScope pr(PR_LAP, s->st, (double)s->N * (sizeof(T) + sizeof(double)));  // z read, w written
-    CKH(lap_apply<T>(s->g, z, w, s->st));
+    ProbeScope pr(PR_LAP, s->st, (double)s->N * (sizeof(T) + sizeof(TW)));  // z read, w written
+    CKH((lap_apply<T, TW>(s->g, z, w, s->st)));
   }
-  const bool c32 = f32 && sizeof(T) == sizeof(float);
   CKH(interp_grad<T>(s->ker, s->g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, z, 1.0, nullptr, 0.0, s->Q,
-                     s->st, c32));
+                     s->st, f32));
   CKH(band_apply(s->ker, true, s->g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, s->Q,
-                 -1.0 / s->c, w, s->st, c32));
+                 -1.0 / s->c, w, s->st, f32));
   return SIM_OK;
 }
 
@@ -743,7 +745,10 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
   const int m = c.krylov_restart;
   T *V = (T *)s->V;
   T *Z = (T *)s->Z;
-  const bool sep_w = sizeof(T) != sizeof(double);  // orthogonalise in a float64 buffer
+  // w = S~ z_j: in the basis vector V_{j+1} itself (float64 basis), or in a
+  // float32 scratch vector (float32 basis) that the products and the update read
+  using TW = T;
+  TW *const wsep = sizeof(T) != sizeof(double) ? (TW *)s->TMPC : nullptr;
   // the bfloat16 fast diagonalisation scales its input by sig_j, known only
   // after the wait: no pipelining with it
   const bool can_pipe = !s->fastdiag;
@@ -775,7 +780,7 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
   auto front = [&](int j) -> sim_status {
     T *zj = Z + (long long)j * N;
     T *vj = V + (long long)j * N;
-    double *w = sep_w ? s->TMPC : (double *)(V + (long long)(j + 1) * N);
+    TW *w = wsep ? wsep : V + (long long)(j + 1) * N;
     if (s->fastdiag) {
       ProbeScope pr(PR_VCYCLE, st, fd_bytes(s, sizeof(T), sizeof(T)));
       CKH((fd_precond<T, T>(s->g, vj, zj, s->FDW1, s->FDW2, s->FDQ, (float)sig[j], st)));
@@ -788,11 +793,11 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
       sim_status r = vcycle<T, T>(s, vj, zj);
       if (r) return r;
     }
-    sim_status r = schur_matvec<T>(s, zj, w, true);
+    sim_status r = schur_matvec<T, TW>(s, zj, w);
     if (r) return r;
     {
-      ProbeScope pr(PR_MULTIDOT, st, (double)N * (sizeof(double) + (j + 1) * sizeof(T)));  // w, V_0..V_j
-      CKH(multidot<T>(w, V, N, j + 1, N, part_dots, st));
+      ProbeScope pr(PR_MULTIDOT, st, (double)N * (sizeof(TW) + (j + 1) * sizeof(T)));  // w, V_0..V_j
+      CKH((multidot<T, TW>(w, V, N, j + 1, N, part_dots, st)));
     }
     CKH(finalize(part_dots, red_blocks(), j + 1, s->RED, st, s->hpin_dev + slot(j)));
     return SIM_OK;
@@ -813,7 +818,7 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
     bool have_front = false;  // iteration j's front already enqueued
     for (int j = 0; j < m; ++j) {
       T *vnext = V + (long long)(j + 1) * N;
-      double *w = sep_w ? s->TMPC : (double *)vnext;
+      TW *w = wsep ? wsep : vnext;
       if (!have_front && (rc = front(j))) return rc;
       have_front = false;
       // classical Gram-Schmidt on the unnormalised basis (v_i = sig_i V'_i):
@@ -822,8 +827,8 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
       // is h_ij = sig_j sig_i g_i, h_{j+1,j} = sig_j |V'_{j+1}|.
       {
         // w, V_0..V_j read, V_{j+1} written
-        ProbeScope pr(PR_UPDATE_NORM, st, (double)N * (sizeof(double) + (j + 2) * sizeof(T)));
-        CKH(update_cast_norm<T>(vnext, w, V, N, j + 1, s->RED, sig2, N, part_norm, st));
+        ProbeScope pr(PR_UPDATE_NORM, st, (double)N * (sizeof(TW) + (j + 2) * sizeof(T)));
+        CKH((update_cast_norm<T, TW>(vnext, w, V, N, j + 1, s->RED, sig2, N, part_norm, st)));
       }
       CKH(finalize(part_norm, red_blocks(), 1, red_norm, st, s->hpin_dev + slot(j) + MIRROR_NORM));
       CKH(hipEventRecord(s->ev_iter, st));

@@ -56,8 +56,8 @@ inline long long geo_cells(const Geo &g) { return 2 * g.half; }
 // ---- grid kernels (kernels_grid.hip) ---------------------------------------
 hipError_t to_split(const Geo &g, int ncomp, const double *nat, double *spl, hipStream_t s);
 hipError_t to_natural(const Geo &g, int ncomp, const double *spl, double *nat, hipStream_t s);
-template <typename T>
-hipError_t lap_apply(const Geo &g, const T *x, double *y, hipStream_t s);  // y = L x
+template <typename T, typename TY = double>
+hipError_t lap_apply(const Geo &g, const T *x, TY *y, hipStream_t s);  // y = L x
 hipError_t grad_apply(const Geo &g, const double *p, double *f3, double alpha, const double *add3,
                       hipStream_t s);  // f3 = add3 + alpha G p   (add3 may be null)
 hipError_t div_apply(const Geo &g, const double *u3, double *y, double alpha,
@@ -221,12 +221,15 @@ hipError_t positive_flags(int n, const int *counts, int *flags, hipStream_t s);
 hipError_t band_apply(int ker, bool div, const Geo &g, int nt1, int nt2, int nactive, const int *active,
                       const int *lstart, const int *list, const double *X, const double *q, double alpha,
                       double *out, hipStream_t s, bool f32 = false);
+hipError_t band_apply(int ker, bool div, const Geo &g, int nt1, int nt2, int nactive, const int *active,
+                      const int *lstart, const int *list, const double *X, const double *q, double alpha,
+                      float *out, hipStream_t s, bool f32 = true);
 
 // ---- reductions / Krylov vector kernels (kernels_krylov.hip) ---------------
 int red_blocks();
 // basis V of type TV (float32 in the FP32-MG form, float64 otherwise); n, stride even
-template <typename TV>
-hipError_t multidot(const double *w, const TV *V, long long stride, int nv, long long n,
+template <typename TV, typename TW = double>  // w in TW (float64, or float32 in the float32 FGMRES cycle)
+hipError_t multidot(const TW *w, const TV *V, long long stride, int nv, long long n,
                     double *part, hipStream_t s);  // part[blk*nv + i]
 hipError_t finalize(const double *part, int nblk, int nv, double *out, hipStream_t s,
                     double *host = nullptr);  // host: optional pinned mirror of out
@@ -242,8 +245,8 @@ struct KCoef {
   double v[KCOEF_MAX];
 };
 // vout = (TV)(w - sum_i sig2_i g_i V_i), partial |vout|^2 per block (g on the device)
-template <typename TV>
-hipError_t update_cast_norm(TV *vout, const double *w, const TV *V, long long stride, int nv, const double *g,
+template <typename TV, typename TW = double>
+hipError_t update_cast_norm(TV *vout, const TW *w, const TV *V, long long stride, int nv, const double *g,
                             const KCoef &sig2, long long n, double *part, hipStream_t s);  // w -= sum h_i V_i ; |w|^2
 hipError_t scale_inplace(double *x, long long n, double alpha, hipStream_t s);
 // ---- reverse-mode step (kernels_adj.hip) ------------------------------------

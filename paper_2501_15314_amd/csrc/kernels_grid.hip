@@ -90,14 +90,16 @@ hipError_t to_natural(const Geo &g, int ncomp, const double *spl, double *nat, h
 
 // ---------------------------------------------------------------------------
 // y = L x, L = G^T G: (L x)_c = sum over existing neighbours (x_c - x_nb) / h^2
-template <typename T>
-hipError_t lap_apply(const Geo &g, const T *x, double *y, hipStream_t s) {
+// (formed in float64, stored as TY)
+template <typename T, typename TY>
+hipError_t lap_apply(const Geo &g, const T *x, TY *y, hipStream_t s) {
   MarchShape M = march_shape(g, 1);
-  hipLaunchKernelGGL((k_apply2<T, double, AP_LAP>), M.grid, M.block, 0, s, g, x, nullptr, y, 0.0, 0.0, nullptr);
+  hipLaunchKernelGGL((k_apply2<T, TY, AP_LAP>), M.grid, M.block, 0, s, g, x, nullptr, y, 0.0, 0.0, nullptr);
   return hipGetLastError();
 }
-template hipError_t lap_apply<float>(const Geo &, const float *, double *, hipStream_t);
-template hipError_t lap_apply<double>(const Geo &, const double *, double *, hipStream_t);
+template hipError_t lap_apply<float, double>(const Geo &, const float *, double *, hipStream_t);
+template hipError_t lap_apply<double, double>(const Geo &, const double *, double *, hipStream_t);
+template hipError_t lap_apply<float, float>(const Geo &, const float *, float *, hipStream_t);
 
 // f3 = add3 + alpha G p ; (G p)_d(idx) = (p(idx) - p(idx - e_d)) / h, zero on wall faces
 __global__ void k_grad(Geo g, const double *p_, double *f3, double alpha, const double *add3) {

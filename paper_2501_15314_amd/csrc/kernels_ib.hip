@@ -560,10 +560,10 @@ constexpr int BAND_CH = 64;
 // fall on distinct banks for the accumulation reads.
 constexpr int BAND_WS = 45;
 
-template <int KER, bool DIV, typename TA>
+template <int KER, bool DIV, typename TA, typename TO>
 __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int *active, const int *lstart,
                                               const int *list, const double *X, const double *q, double alpha,
-                                              double *out) {
+                                              TO *out) {
   // [cand][axis a * 15 + comp * 5 + position]; after the last chunk the same
   // LDS holds the per-half-wavefront face sums part[8][3][80]
   static_assert(8 * 3 * 80 <= BAND_CH * BAND_WS, "face sums must fit the weight buffer");
@@ -696,7 +696,8 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
       dv += face(1, (ci2 * 5 + cj2 + 1) * 4 + ck) - face(1, (ci2 * 5 + cj2) * 4 + ck);
       dv += face(2, (ci2 * 4 + cj2) * 5 + ck + 1) - face(2, (ci2 * 4 + cj2) * 5 + ck);
       int gi = 4 * T0 + ci2, gj = 4 * T1 + cj2, gk = 4 * T2 + ck;
-      out[sidx(g, gi, gj, gk)] += alpha * (double)dv * ih;
+      const long long o = sidx(g, gi, gj, gk);
+      out[o] = (TO)((double)out[o] + alpha * (double)dv * ih);
     }
   } else {
     if (tid < 192) {
@@ -704,34 +705,50 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
       int fi = t >> 4, fj = (t >> 2) & 3, fk = t & 3;
       int by = 4 + (d == 1), bz = 4 + (d == 2);
       int gi = 4 * T0 + fi, gj = 4 * T1 + fj, gk = 4 * T2 + fk;
-      out[d * N + sidx(g, gi, gj, gk)] += alpha * (double)face(d, (fi * by + fj) * bz + fk);
+      const long long o = d * N + sidx(g, gi, gj, gk);
+      out[o] = (TO)((double)out[o] + alpha * (double)face(d, (fi * by + fj) * bz + fk));
     }
   }
 }
 
-hipError_t band_apply(int ker, bool div, const Geo &g, int nt1, int nt2, int nactive, const int *active,
-                      const int *lstart, const int *list, const double *X, const double *q, double alpha,
-                      double *out, hipStream_t s, bool f32) {
+template <typename TO>
+static hipError_t band_launch(int ker, bool div, const Geo &g, int nt1, int nt2, int nactive, const int *active,
+                              const int *lstart, const int *list, const double *X, const double *q, double alpha,
+                              TO *out, hipStream_t s, bool f32) {
   // positions and values read, the active tiles' cells (div) or faces read and written
   ProbeScope probe_(div ? PR_BAND_DIV : PR_BAND_FACE, s,
-                    (double)probe_points() * 48 + (double)probe_band_cells() * (div ? 1 : 3) * 16);
+                    (double)probe_points() * 48 + (double)probe_band_cells() * (div ? 1 : 3) * 2 * sizeof(TO));
   if (nactive == 0) return hipSuccess;
   dim3 gr(nactive), bl(256);
 #define BAND(K_, D_, A_) \
-  hipLaunchKernelGGL((k_band<K_, D_, A_>), gr, bl, 0, s, g, nt1, nt2, active, lstart, list, X, q, alpha, out)
+  hipLaunchKernelGGL((k_band<K_, D_, A_, TO>), gr, bl, 0, s, g, nt1, nt2, active, lstart, list, X, q, alpha, out)
   if (f32) {
     if (!div) return hipErrorInvalidValue;  // float32 sums serve the S~ products only
     if (ker == KER_PESKIN4) BAND(KER_PESKIN4, true, float);
     else BAND(KER_ROMA3, true, float);
-  } else if (ker == KER_PESKIN4) {
-    if (div) BAND(KER_PESKIN4, true, double);
-    else BAND(KER_PESKIN4, false, double);
+  } else if constexpr (sizeof(TO) == sizeof(double)) {
+    if (ker == KER_PESKIN4) {
+      if (div) BAND(KER_PESKIN4, true, double);
+      else BAND(KER_PESKIN4, false, double);
+    } else {
+      if (div) BAND(KER_ROMA3, true, double);
+      else BAND(KER_ROMA3, false, double);
+    }
   } else {
-    if (div) BAND(KER_ROMA3, true, double);
-    else BAND(KER_ROMA3, false, double);
+    return hipErrorInvalidValue;  // a float32 output takes float32 sums
   }
 #undef BAND
   return hipGetLastError();
+}
+hipError_t band_apply(int ker, bool div, const Geo &g, int nt1, int nt2, int nactive, const int *active,
+                      const int *lstart, const int *list, const double *X, const double *q, double alpha,
+                      double *out, hipStream_t s, bool f32) {
+  return band_launch(ker, div, g, nt1, nt2, nactive, active, lstart, list, X, q, alpha, out, s, f32);
+}
+hipError_t band_apply(int ker, bool div, const Geo &g, int nt1, int nt2, int nactive, const int *active,
+                      const int *lstart, const int *list, const double *X, const double *q, double alpha,
+                      float *out, hipStream_t s, bool f32) {
+  return band_launch(ker, div, g, nt1, nt2, nactive, active, lstart, list, X, q, alpha, out, s, f32);
 }
 
 }  // namespace ibs

@@ -43,15 +43,16 @@ __device__ __forceinline__ void ld_pair(const TV *p, double &a, double &b) {
 // The number of vectors is a template parameter (1 .. MD_MAX): the loop over
 // them unrolls completely, so every load of a grid-stride step is issued
 // before the first product waits on one
-template <typename TV, int NV>
-__global__ void __launch_bounds__(RED_T) k_multidot(const double *w, const TV *V, long long stride, long long n,
+template <typename TV, typename TW, int NV>
+__global__ void __launch_bounds__(RED_T) k_multidot(const TW *w, const TV *V, long long stride, long long n,
                                                     double *part) {
   double acc[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;
   const long long n2 = n >> 1;
   for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n2; t += (long long)gridDim.x * RED_T) {
-    const double2 wv = *(const double2 *)(w + 2 * t);
+    double2 wv;
+    ld_pair(w + 2 * t, wv.x, wv.y);
     double a[NV], b[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) ld_pair(V + i * stride + 2 * t, a[i], b[i]);
@@ -71,23 +72,23 @@ __global__ void __launch_bounds__(RED_T) k_multidot(const double *w, const TV *V
         ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
 }
 
-template <typename TV, int NV>
-static void launch_multidot(const double *w, const TV *V, long long stride, int nv, long long n, double *part,
+template <typename TV, typename TW, int NV>
+static void launch_multidot(const TW *w, const TV *V, long long stride, int nv, long long n, double *part,
                             hipStream_t s) {
   if constexpr (NV > 1) {
-    if (nv < NV) return launch_multidot<TV, NV - 1>(w, V, stride, nv, n, part, s);
+    if (nv < NV) return launch_multidot<TV, TW, NV - 1>(w, V, stride, nv, n, part, s);
   }
-  hipLaunchKernelGGL((k_multidot<TV, NV>), dim3(RED_BLOCKS), dim3(RED_T), 0, s, w, V, stride, n, part);
+  hipLaunchKernelGGL((k_multidot<TV, TW, NV>), dim3(RED_BLOCKS), dim3(RED_T), 0, s, w, V, stride, n, part);
 }
 
-template <typename TV>
-hipError_t multidot(const double *w, const TV *V, long long stride, int nv, long long n, double *part,
+template <typename TV, typename TW>
+hipError_t multidot(const TW *w, const TV *V, long long stride, int nv, long long n, double *part,
                     hipStream_t s) {
   if ((n & 1) || (stride & 1)) return hipErrorInvalidValue;
   // part layout: [blk][nv]; chunks of MD_MAX vectors write consecutive column groups
   for (int c0 = 0; c0 < nv; c0 += MD_MAX) {
     int nc = nv - c0 < MD_MAX ? nv - c0 : MD_MAX;
-    launch_multidot<TV, MD_MAX>(w, V + c0 * stride, stride, nc, n, part + (long long)c0 * RED_BLOCKS, s);
+    launch_multidot<TV, TW, MD_MAX>(w, V + c0 * stride, stride, nc, n, part + (long long)c0 * RED_BLOCKS, s);
   }
   return hipGetLastError();
 }
@@ -96,8 +97,8 @@ hipError_t multidot(const double *w, const TV *V, long long stride, int nv, long
 // w when TV is double): the next unnormalised basis vector in one pass
 // NV > 0: that many vectors, unrolled (all loads of a step issued together);
 // NV = 0: nv vectors in a runtime loop
-template <typename TV, int NV>
-__global__ void __launch_bounds__(RED_T) k_update_cast_norm(TV *vout, const double *w, const TV *V, long long stride,
+template <typename TV, typename TW, int NV>
+__global__ void __launch_bounds__(RED_T) k_update_cast_norm(TV *vout, const TW *w, const TV *V, long long stride,
                                                             int nv, const double *g, KCoef sig2, long long n,
                                                             double *part) {
   __shared__ double hs[64];
@@ -107,7 +108,8 @@ __global__ void __launch_bounds__(RED_T) k_update_cast_norm(TV *vout, const doub
   double acc = 0.0;
   const long long n2 = n >> 1;
   for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n2; t += (long long)gridDim.x * RED_T) {
-    double2 v = *(const double2 *)(w + 2 * t);
+    double2 v;
+    ld_pair(w + 2 * t, v.x, v.y);
     if constexpr (NV > 0) {
       double a[NV], b[NV];
 #pragma unroll
@@ -138,35 +140,39 @@ __global__ void __launch_bounds__(RED_T) k_update_cast_norm(TV *vout, const doub
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
-template <typename TV, int NV>
-static void launch_update(TV *vout, const double *w, const TV *V, long long stride, int nv, const double *g,
+template <typename TV, typename TW, int NV>
+static void launch_update(TV *vout, const TW *w, const TV *V, long long stride, int nv, const double *g,
                           const KCoef &sig2, long long n, double *part, hipStream_t s) {
   if constexpr (NV > 1) {
-    if (nv < NV) return launch_update<TV, NV - 1>(vout, w, V, stride, nv, g, sig2, n, part, s);
+    if (nv < NV) return launch_update<TV, TW, NV - 1>(vout, w, V, stride, nv, g, sig2, n, part, s);
   }
-  hipLaunchKernelGGL((k_update_cast_norm<TV, NV>), dim3(RED_BLOCKS), dim3(RED_T), 0, s, vout, w, V, stride, nv, g,
-                     sig2, n, part);
+  hipLaunchKernelGGL((k_update_cast_norm<TV, TW, NV>), dim3(RED_BLOCKS), dim3(RED_T), 0, s, vout, w, V, stride,
+                     nv, g, sig2, n, part);
 }
 
-template <typename TV>
-hipError_t update_cast_norm(TV *vout, const double *w, const TV *V, long long stride, int nv, const double *g,
+template <typename TV, typename TW>
+hipError_t update_cast_norm(TV *vout, const TW *w, const TV *V, long long stride, int nv, const double *g,
                             const KCoef &sig2, long long n, double *part, hipStream_t s) {
   if (nv < 1 || nv > 64 || (n & 1) || (stride & 1)) return hipErrorInvalidValue;
   if (nv <= MD_MAX)
-    launch_update<TV, MD_MAX>(vout, w, V, stride, nv, g, sig2, n, part, s);
+    launch_update<TV, TW, MD_MAX>(vout, w, V, stride, nv, g, sig2, n, part, s);
   else
-    hipLaunchKernelGGL((k_update_cast_norm<TV, 0>), dim3(RED_BLOCKS), dim3(RED_T), 0, s, vout, w, V, stride, nv, g,
-                       sig2, n, part);
+    hipLaunchKernelGGL((k_update_cast_norm<TV, TW, 0>), dim3(RED_BLOCKS), dim3(RED_T), 0, s, vout, w, V, stride,
+                       nv, g, sig2, n, part);
   return hipGetLastError();
 }
-template hipError_t update_cast_norm<float>(float *, const double *, const float *, long long, int, const double *,
-                                            const KCoef &, long long, double *, hipStream_t);
-template hipError_t update_cast_norm<double>(double *, const double *, const double *, long long, int,
-                                             const double *, const KCoef &, long long, double *, hipStream_t);
-template hipError_t multidot<float>(const double *, const float *, long long, int, long long, double *,
-                                    hipStream_t);
-template hipError_t multidot<double>(const double *, const double *, long long, int, long long, double *,
-                                     hipStream_t);
+template hipError_t update_cast_norm<float, double>(float *, const double *, const float *, long long, int,
+                                                    const double *, const KCoef &, long long, double *, hipStream_t);
+template hipError_t update_cast_norm<float, float>(float *, const float *, const float *, long long, int,
+                                                   const double *, const KCoef &, long long, double *, hipStream_t);
+template hipError_t update_cast_norm<double, double>(double *, const double *, const double *, long long, int,
+                                                     const double *, const KCoef &, long long, double *, hipStream_t);
+template hipError_t multidot<float, double>(const double *, const float *, long long, int, long long, double *,
+                                            hipStream_t);
+template hipError_t multidot<float, float>(const float *, const float *, long long, int, long long, double *,
+                                           hipStream_t);
+template hipError_t multidot<double, double>(const double *, const double *, long long, int, long long, double *,
+                                             hipStream_t);
 
 // out[i] = sum_b part[b][i] over nblk blocks (chunked layout of multidot);
 // with host != null the sums are also written to that pinned host buffer
