@@ -158,24 +158,30 @@ template <int KER> __device__ __forceinline__ int support_start(double x, double
 //            w = ((3-2f-q)/8, (3-2f+q)/8, (1+2f+q)/8, (1+2f-q)/8);
 //   3-point: nodes round(s)-1 .. round(s)+1, f = s - round(s),
 //            q = sqrt(1 - 3f^2), w = ((2-3f-q)/6, (1+q)/3, (2+3f-q)/6, 0).
-template <int KER>
-__device__ __forceinline__ int axis_weights(double x, double inv_h, bool face, double w[4]) {
+// The node index and f come from s in float64 (positions reach n h); the
+// weights are formed in TA: float64, or float32 where they are rounded to
+// float32 anyway (the products of the float32 Krylov cycle), which spares
+// the float64 square root and its refinement.
+template <int KER, typename TA = double>
+__device__ __forceinline__ int axis_weights(double x, double inv_h, bool face, TA w[4]) {
   double s = x * inv_h - (face ? 0.0 : 0.5);
   if (KER == KER_PESKIN4) {
-    double fl = floor(s), f = s - fl;
-    double q = sqrt(fmax(0.0, 1.0 + 4.0 * f - 4.0 * f * f));
-    w[0] = (3.0 - 2.0 * f - q) * 0.125;
-    w[1] = (3.0 - 2.0 * f + q) * 0.125;
-    w[2] = (1.0 + 2.0 * f + q) * 0.125;
-    w[3] = (1.0 + 2.0 * f - q) * 0.125;
+    double fl = floor(s);
+    TA f = (TA)(s - fl);
+    TA q = sqrt(fmax(TA(0), TA(1) + TA(4) * f - TA(4) * f * f));
+    w[0] = (TA(3) - TA(2) * f - q) * TA(0.125);
+    w[1] = (TA(3) - TA(2) * f + q) * TA(0.125);
+    w[2] = (TA(1) + TA(2) * f + q) * TA(0.125);
+    w[3] = (TA(1) + TA(2) * f - q) * TA(0.125);
     return (int)fl - 1;
   } else {
-    double rd = floor(s + 0.5), f = s - rd;
-    double q = sqrt(fmax(0.0, 1.0 - 3.0 * f * f));
-    w[0] = (2.0 - 3.0 * f - q) * (1.0 / 6.0);
-    w[1] = (1.0 + q) * (1.0 / 3.0);
-    w[2] = (2.0 + 3.0 * f - q) * (1.0 / 6.0);
-    w[3] = 0.0;
+    double rd = floor(s + 0.5);
+    TA f = (TA)(s - rd);
+    TA q = sqrt(fmax(TA(0), TA(1) - TA(3) * f * f));
+    w[0] = (TA(2) - TA(3) * f - q) * TA(1.0 / 6.0);
+    w[1] = (TA(1) + q) * TA(1.0 / 3.0);
+    w[2] = (TA(2) + TA(3) * f - q) * TA(1.0 / 6.0);
+    w[3] = TA(0);
     return (int)rd - 1;
   }
 }

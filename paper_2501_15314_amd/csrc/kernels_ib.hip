@@ -203,6 +203,9 @@ hipError_t scale3(int K, const double *x, double alpha, const double *y, double 
 // point (node offsets (a, b)), z nodes summed in order, the 16 partial sums
 // reduced by a fixed butterfly.
 constexpr int IREG = 8;   // region width per axis
+// region stride between x planes: 2 more than IREG^2, so the 16 lanes of a
+// point (x offsets a, y offsets b) fall on 16 distinct LDS banks
+constexpr int IRS = IREG * IREG + 2;
 constexpr int IPTS = 64;  // points staged per pass
 
 template <int KER, int MODE, typename T, typename TA>
@@ -213,7 +216,7 @@ __global__ void __launch_bounds__(256) k_interp(Geo g, int nt1, int nt2, const i
   constexpr int NC = MODE == 0 ? 3 : 1;
   // TA: the arithmetic type (float64, or float32 for the gradient of a
   // float32 cell field in the float32 Krylov cycle, weights rounded to it)
-  __shared__ TA reg[NC][IREG * IREG * IREG];
+  __shared__ TA reg[NC][IREG * IRS];
   __shared__ TA pw[IPTS][3][2][4];   // [point][axis][face/centre][node]
   __shared__ int pb[IPTS][3][2];         // local start of the support
   const int tile = tiles[blockIdx.x];
@@ -239,7 +242,7 @@ __global__ void __launch_bounds__(256) k_interp(Geo g, int nt1, int nt2, const i
     if (g.bc0) ok = ok && i >= 0 && i < g.n0; else i = wrapi(i, g.n0);
     if (g.bc1) ok = ok && j >= 0 && j < g.n1; else j = wrapi(j, g.n1);
     if (g.bc2) ok = ok && k >= 0 && k < g.n2; else k = wrapi(k, g.n2);
-    reg[comp][l] = ok ? (TA)src[comp * N + sidx(g, i, j, k)] : TA(0);
+    reg[comp][li * IRS + lj * IREG + lk] = ok ? (TA)src[comp * N + sidx(g, i, j, k)] : TA(0);
   }
   const int lane = threadIdx.x & 15, ta = lane >> 2, tb = lane & 3;
   const double ih = 1.0 / g.h;
@@ -253,16 +256,16 @@ __global__ void __launch_bounds__(256) k_interp(Geo g, int nt1, int nt2, const i
     static_assert(6 * IPTS <= 2 * 256, "two staging tasks per thread");
     for (int task = threadIdx.x; task < np * 6; task += 256) {
       int pt = task / 6, rem = task - 6 * pt, ax = rem >> 1, st = rem & 1;
-      double wv[4];
+      TA wv[4];
       const double xv = c0 == s0 ? (task < 256 ? xpre[0] : xpre[1]) : X[3 * (c0 + pt) + ax];
-      int i0 = axis_weights<KER>(xv, ih, st == 0, wv);
+      int i0 = axis_weights<KER, TA>(xv, ih, st == 0, wv);
       int l0 = i0 - org[ax];
       if (!bcs[ax]) l0 = wrapi(l0 + nn[ax] / 2, nn[ax]) - nn[ax] / 2;
       pb[pt][ax][st] = l0;
       // a wall face (index 0 along a wall axis) carries no gradient: zero its weight
 #pragma unroll
       for (int t = 0; t < 4; ++t)
-        pw[pt][ax][st][t] = (MODE == 1 && st == 0 && bcs[ax] && i0 + t == 0) ? TA(0) : (TA)wv[t];
+        pw[pt][ax][st][t] = (MODE == 1 && st == 0 && bcs[ax] && i0 + t == 0) ? TA(0) : wv[t];
     }
     __syncthreads();
     for (int pb0 = 0; pb0 < np; pb0 += 16) {
@@ -281,11 +284,11 @@ __global__ void __launch_bounds__(256) k_interp(Geo g, int nt1, int nt2, const i
             TA v = TA(0);
             bool in = (unsigned)li < IREG && (unsigned)lj < IREG && (unsigned)lk < IREG;
             if (MODE == 0) {
-              if (in) v = reg[d][(li * IREG + lj) * IREG + lk];
+              if (in) v = reg[d][li * IRS + lj * IREG + lk];
             } else {
               int mi = li - (d == 0), mj = lj - (d == 1), mk = lk - (d == 2);
               bool inm = (unsigned)mi < IREG && (unsigned)mj < IREG && (unsigned)mk < IREG;
-              if (in && inm) v = (reg[0][(li * IREG + lj) * IREG + lk] - reg[0][(mi * IREG + mj) * IREG + mk]) * (TA)ih;
+              if (in && inm) v = (reg[0][li * IRS + lj * IREG + lk] - reg[0][mi * IRS + mj * IREG + mk]) * (TA)ih;
             }
             acc += (wab * pw[pt][2][sz][c]) * v;
           }
@@ -618,9 +621,9 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
     const int nc = min(BAND_CH, s1 - c0);
     __syncthreads();
     if (p_cur >= 0) {
-      double wf[4], wc[4];
-      int f0 = axis_weights<KER>(xa, ih, true, wf);
-      int e0 = axis_weights<KER>(xa, ih, false, wc);
+      TA wf[4], wc[4];
+      int f0 = axis_weights<KER, TA>(xa, ih, true, wf);
+      int e0 = axis_weights<KER, TA>(xa, ih, false, wc);
       int lf = f0 - org[a], lc = e0 - org[a];
       if (!bcs[a]) {
         // periodic image of the support start in [-4, n - 4): every offset
@@ -629,22 +632,34 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
         lf = wrapi(lf + 4, nn[a]) - 4;
         lc = wrapi(lc + 4, nn[a]) - 4;
       }
+      // the weights over the box positions along this axis: faces (5) and
+      // centres (4), zero outside the support (select chains: no dynamic
+      // index into a register array, no branch)
+      TA F[5], C[4];
+#pragma unroll
+      for (int t = 0; t < 5; ++t) {
+        const int i_f = t - lf, i_c = t - lc;
+        TA v = i_f == 0 ? wf[0] : TA(0);
+        v = i_f == 1 ? wf[1] : v;
+        v = i_f == 2 ? wf[2] : v;
+        v = i_f == 3 ? wf[3] : v;
+        F[t] = v;
+        if (t < 4) {
+          TA u = i_c == 0 ? wc[0] : TA(0);
+          u = i_c == 1 ? wc[1] : u;
+          u = i_c == 2 ? wc[2] : u;
+          u = i_c == 3 ? wc[3] : u;
+          C[t] = u;
+        }
+      }
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const double qd = qv[d];
-        const int l0 = d == a ? lf : lc;
-        const double *w = d == a ? wf : wc;
+        const TA qd = (TA)qv[d];
 #pragma unroll
         for (int t = 0; t < 5; ++t) {
-          const int idx = t - l0;
           // position t exists for the faces of axis d (5) and the cells of the others (4)
-          // select chain (no dynamic index into w, no branch)
-          double v = idx == 0 ? w[0] : 0.0;
-          v = idx == 1 ? w[1] : v;
-          v = idx == 2 ? w[2] : v;
-          v = idx == 3 ? w[3] : v;
-          v *= (t < 4 || d == a) ? qd : 0.0;
-          wts[cand][15 * a + 5 * d + t] = (TA)v;
+          const TA v = d == a ? F[t] : (t < 4 ? C[t] : TA(0));
+          wts[cand][15 * a + 5 * d + t] = v * qd;
         }
       }
     }
@@ -654,11 +669,15 @@ __global__ void __launch_bounds__(256) k_band(Geo g, int nt1, int nt2, const int
     p_nxt = entry(c0 + 2 * BAND_CH);
     __syncthreads();
     if (owner) {
+#pragma unroll 2
       for (int c = 2 * wv + half; c < nc; c += 8) {
         const TA *W = wts[c] + 5 * cd;
         const TA wx = W[ci];
         const TA wab0 = wx * W[15 + cj0];
-        const TA wab1 = has1 ? wx * W[16 + cj0] : TA(0);
+        // without a second column (has1 false) the lane reads the next
+        // block's first y weight, inside the point's row, and acc1 is
+        // never stored
+        const TA wab1 = wx * W[16 + cj0];
 #pragma unroll
         for (int fk = 0; fk < 5; ++fk) {
           const TA wz = W[30 + fk];
