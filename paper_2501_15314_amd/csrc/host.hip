@@ -722,8 +722,9 @@ sim_status vcycle(sim_t s, const TV *v, T *z) {
 // T: precision of the preconditioned vectors Z and of the V-cycle; the basis
 // V has the same precision (a float32 basis in the FP32-MG form: each cycle
 // only has to gain FP32_CYCLE_DROP before the float64 true residual restarts
-// it).  w = S~ z_j is formed and orthogonalised in float64: the Gram-Schmidt
-// products, the update and every norm are float64 arithmetic.
+// it).  w = S~ z_j is stored in T too (in the float32 form its coupling term
+// is float32 arithmetic); the Gram-Schmidt products, the update and every
+// norm are float64 arithmetic.
 //
 // Pipelining: the preconditioner of iteration j + 1 applies to the
 // unnormalised basis vector V'_{j+1}, which is complete once the update of
@@ -757,14 +758,6 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
   S.iters = 0;
   S.nhist = 0;
   sim_status rc;
-  double bn2;
-  if ((rc = dev_norm2(s, b, N, &bn2))) return rc;
-  double bnorm = sqrt(bn2);
-  CKH(fill(x, N, 0.0, st));
-  if (!(bnorm > 0)) {
-    S.rel_res = 0;
-    return isfinite(bn2) ? SIM_OK : fail(s, SIM_ENONFINITE, "non-finite right-hand side");
-  }
   // Hessenberg matrix, Givens rotations and scales on the host stack (no
   // allocation inside a solve)
   double H[(MAX_RESTART + 1) * MAX_RESTART], cs[MAX_RESTART], sn[MAX_RESTART], gv[MAX_RESTART + 1],
@@ -802,20 +795,50 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
     CKH(finalize(part_dots, red_blocks(), j + 1, s->RED, st, s->hpin_dev + slot(j)));
     return SIM_OK;
   };
+  // A cycle starts from V'_0 = r, the residual itself (sig_0 = 1 / |r|):
+  // the pass that casts r into the basis also forms |r|^2, and since the
+  // front of iteration 0 needs no norm, it is enqueued before the host waits
+  // for that norm whenever the cycle is expected to run.  The host mirror
+  // slot of these norms is apart from the products' slots.
+  double *const mirror_res = s->hpin + 2 * MIRROR_SLOT;
+  auto cycle_start = [&](const double *ax, bool speculate, double &r2) -> sim_status {
+    CKH(sub_cast_norm<T>(V, b, ax, N, s->PART, st));
+    CKH(finalize(s->PART, red_blocks(), 1, s->RED, st, s->hpin_dev + 2 * MIRROR_SLOT));
+    CKH(hipEventRecord(s->ev_iter, st));
+    if (speculate && can_pipe) {
+      sim_status r = front(0);
+      if (r) return r;
+    }
+    CKH(hipEventSynchronize(s->ev_iter));
+    r2 = mirror_res[0];
+    return SIM_OK;
+  };
+  double bn2;
+  if ((rc = cycle_start(nullptr, c.krylov_maxit > 0, bn2))) return rc;
+  bool front0 = c.krylov_maxit > 0 && can_pipe;  // the next cycle's front(0) already enqueued
+  const double bnorm = sqrt(bn2);
+  if (!(bnorm > 0)) {
+    CKH(fill(x, N, 0.0, st));
+    S.rel_res = 0;
+    return isfinite(bn2) ? SIM_OK : fail(s, SIM_ENONFINITE, "non-finite right-hand side");
+  }
+  // the solution: written by the first cycle's update (x = Z y), accumulated
+  // by the later ones; the update's per-block sums of x give its mean
+  bool xset = false;
+  double *const part_x = s->PART + red_blocks();
   double beta = bnorm;
-  const double *rvec = b;
   int total = 0;
   double rel = 1.0;
   while (true) {
     rel = beta / bnorm;
     if (rel <= c.krylov_rtol || total >= c.krylov_maxit) break;
-    CKH(scale_cast<T>(V, rvec, N, 1.0 / beta, st));
-    sig[0] = 1.0;
-    sig2.v[0] = 1.0;
+    sig[0] = 1.0 / beta;
+    sig2.v[0] = sig[0] * sig[0];
     std::fill(gv, gv + m + 1, 0.0);
     gv[0] = beta;
     int jd = 0;
-    bool have_front = false;  // iteration j's front already enqueued
+    bool have_front = front0;  // iteration j's front already enqueued
+    front0 = false;
     for (int j = 0; j < m; ++j) {
       T *vnext = V + (long long)(j + 1) * N;
       TW *w = wsep ? wsep : vnext;
@@ -885,20 +908,28 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
     }
     KCoef yc{};
     for (int i = 0; i < jd; ++i) yc.v[i] = y[i] * sig[i];  // z_i = sig_i z'_i
-    CKH(sol_update<T>(x, Z, N, jd, yc, N, st));
-    // true residual r = b - S~ x (in TMPC)
+    CKH(sol_update<T>(x, Z, N, jd, yc, N, st, !xset, part_x));
+    xset = true;
+    // true residual r = b - S~ x (S~ x in TMPC), cast into V'_0 of the next
+    // cycle; its front is enqueued ahead of the norm when the cycle's
+    // residual estimate says another cycle follows
     if ((rc = schur_matvec<double>(s, x, s->TMPC))) return rc;
-    CKH(sub_mul(s->TMPC, b, s->TMPC, N, s->PART, st));
-    CKH(finalize(s->PART, red_blocks(), 1, s->RED, st, s->hpin_dev));
+    const bool more = fabs(gv[jd]) > 10.0 * c.krylov_rtol * bnorm && total < c.krylov_maxit;
     double r2;
-    if ((rc = read_mirror(s, 1, &r2))) return rc;
+    if ((rc = cycle_start(s->TMPC, more, r2))) return rc;
+    front0 = more && can_pipe;
     if (!isfinite(r2)) return fail(s, SIM_ENONFINITE, "non-finite residual");
     beta = sqrt(r2);
-    rvec = s->TMPC;
   }
   S.iters = total;
   S.rel_res = rel;
-  if ((rc = project_mean(s, x))) return rc;
+  if (xset) {
+    // subtract the mean of x (its sum from the last update's block sums)
+    CKH(finalize(part_x, sol_blocks(), 1, s->RED, st));
+    CKH(add_scalar_dev(x, N, s->RED, -1.0 / (double)N, st));
+  } else {
+    CKH(fill(x, N, 0.0, st));
+  }
   if (rel > c.krylov_rtol) return fail(s, SIM_ENOTCONV, "Krylov iteration limit reached");
   return SIM_OK;
 }

@@ -236,8 +236,6 @@ hipError_t finalize(const double *part, int nblk, int nv, double *out, hipStream
 template <typename TV>
 hipError_t update_norm(double *w, const TV *V, long long stride, int nv, const double *hcoef,
                        long long n, double *part, hipStream_t s);
-template <typename TV>
-hipError_t scale_cast(TV *y, const double *x, long long n, double alpha, hipStream_t s);  // y = alpha x
 // Krylov coefficients passed by value to a kernel: one per basis vector of
 // a restart cycle of up to 64 iterations, plus the new vector's (65)
 constexpr int KCOEF_MAX = 65;
@@ -257,15 +255,20 @@ hipError_t interp_dx(int ker, const Geo &g, int K, const double *X, const double
 hipError_t convection_adjoint(const Geo &g, const double *u3, const double *r3, double *out3, hipStream_t s);
 
 hipError_t scale_copy(double *y, const double *x, long long n, double alpha, hipStream_t s);
+// x = (first ? 0 : x) + sum_j y_j Z_j; part (optional): sol_blocks() partial
+// sums of the new x
+int sol_blocks();
 template <typename T>
 hipError_t sol_update(double *x, const T *Z, long long stride, int nz, const KCoef &y, long long n,
-                      hipStream_t s);  // x += sum y_j Z_j  // x += sum y_j Z_j
+                      hipStream_t s, bool first = false, double *part = nullptr);
 hipError_t axpby(double *y, const double *x, long long n, double a, double b,
                  hipStream_t s);  // y = a x + b y
 hipError_t add_scalar_dev(double *x, long long n, const double *dscalar, double mult,
                           hipStream_t s);  // x += mult * (*dscalar)
 hipError_t sub_mul(double *r, const double *b, const double *ax, long long n, double *part,
                    hipStream_t s);  // r = b - ax, partial |r|^2
+template <typename TV>  // y = (TV)(b - ax) (ax null: (TV)b), partial |b - ax|^2
+hipError_t sub_cast_norm(TV *y, const double *b, const double *ax, long long n, double *part, hipStream_t s);
 hipError_t dot2(const double *a, const double *b, long long n, double *part,
                 hipStream_t s);
 hipError_t lincomb(double *y, const double *a, double ca, const double *b, double cb, const double *c, double cc,

@@ -237,20 +237,6 @@ template hipError_t update_norm<float>(double *, const float *, long long, int, 
 template hipError_t update_norm<double>(double *, const double *, long long, int, const double *, long long,
                                         double *, hipStream_t);
 
-// y = (TV)(a x): a basis vector from a float64 residual or orthogonalised vector
-template <typename TV>
-__global__ void k_scale_cast(TV *y, const double *x, long long n, double a) {
-  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T)
-    y[t] = (TV)(a * x[t]);
-}
-template <typename TV>
-hipError_t scale_cast(TV *y, const double *x, long long n, double alpha, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_cast<TV>, dim3(RED_BLOCKS * 4), dim3(RED_T), 0, s, y, x, n, alpha);
-  return hipGetLastError();
-}
-template hipError_t scale_cast<float>(float *, const double *, long long, double, hipStream_t);
-template hipError_t scale_cast<double>(double *, const double *, long long, double, hipStream_t);
-
 __global__ void k_scale_copy(double *y, const double *x, long long n, double a) {
   for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T)
     y[t] = a * x[t];
@@ -264,28 +250,41 @@ hipError_t scale_copy(double *y, const double *x, long long n, double alpha, hip
   return hipGetLastError();
 }
 
+// x = (first ? 0 : x) + sum_j y_j Z_j; with part != null also the per-block
+// partial sums of the new x (part[blockIdx.x], SOL_BLOCKS blocks), from
+// which the mean of the final solution is formed without another pass
+constexpr int SOL_BLOCKS = RED_BLOCKS * 4;
+int sol_blocks() { return SOL_BLOCKS; }
 template <typename T>
-__global__ void k_sol_update(double *x, const T *Z, long long stride, int nz, KCoef y, long long n) {
+__global__ void __launch_bounds__(RED_T) k_sol_update(double *x, const T *Z, long long stride, int nz, KCoef y,
+                                                      long long n, bool first, double *part) {
   __shared__ double ys[64];
+  __shared__ double sh[4];
   for (int i = threadIdx.x; i < nz; i += RED_T) ys[i] = y.v[i];
   __syncthreads();
+  double acc = 0.0;
   for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T) {
-    double v = x[t];
+    double v = first ? 0.0 : x[t];
     for (int j = 0; j < nz; ++j) v += ys[j] * (double)Z[j * stride + t];
     x[t] = v;
+    acc += v;
+  }
+  if (part) {
+    acc = block_reduce(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
   }
 }
 template <typename T>
 hipError_t sol_update(double *x, const T *Z, long long stride, int nz, const KCoef &y, long long n,
-                      hipStream_t s) {
+                      hipStream_t s, bool first, double *part) {
   if (nz > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_sol_update<T>, dim3(RED_BLOCKS * 4), dim3(RED_T), 0, s, x, Z, stride, nz, y, n);
+  hipLaunchKernelGGL(k_sol_update<T>, dim3(SOL_BLOCKS), dim3(RED_T), 0, s, x, Z, stride, nz, y, n, first, part);
   return hipGetLastError();
 }
 template hipError_t sol_update<float>(double *, const float *, long long, int, const KCoef &, long long,
-                                      hipStream_t);
+                                      hipStream_t, bool, double *);
 template hipError_t sol_update<double>(double *, const double *, long long, int, const KCoef &, long long,
-                                       hipStream_t);
+                                       hipStream_t, bool, double *);
 
 __global__ void k_axpby(double *y, const double *x, long long n, double a, double b) {
   for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T)
@@ -323,6 +322,31 @@ hipError_t sub_mul(double *r, const double *b, const double *ax, long long n, do
   hipLaunchKernelGGL(k_sub_norm, dim3(RED_BLOCKS), dim3(RED_T), 0, s, r, b, ax, n, part);
   return hipGetLastError();
 }
+
+// y = (TV)(b - ax) (ax null: y = (TV)b) ; partial |b - ax|^2 of the float64
+// difference: a Krylov cycle's first (unnormalised) basis vector together
+// with the norm of the residual it stands for
+template <typename TV>
+__global__ void __launch_bounds__(RED_T) k_sub_cast_norm(TV *y, const double *b, const double *ax, long long n,
+                                                         double *part) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T) {
+    double v = ax ? b[t] - ax[t] : b[t];
+    y[t] = (TV)v;
+    acc += v * v;
+  }
+  acc = block_reduce(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+template <typename TV>
+hipError_t sub_cast_norm(TV *y, const double *b, const double *ax, long long n, double *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_cast_norm<TV>, dim3(RED_BLOCKS), dim3(RED_T), 0, s, y, b, ax, n, part);
+  return hipGetLastError();
+}
+template hipError_t sub_cast_norm<float>(float *, const double *, const double *, long long, double *, hipStream_t);
+template hipError_t sub_cast_norm<double>(double *, const double *, const double *, long long, double *,
+                                          hipStream_t);
 
 __global__ void __launch_bounds__(RED_T) k_dot2(const double *a, const double *b, long long n, double *part) {
   __shared__ double sh[4];
