@@ -73,11 +73,11 @@ enum { SIM_BC_PERIODIC = 0, SIM_BC_NOSLIP = 1, SIM_BC_FREESLIP = 2 };
 enum { SIM_DELTA_PESKIN4 = 0, SIM_DELTA_ROMA3 = 1 };
 /* FP64: every kernel in float64.  FP32MG: the V-cycle and the momentum
  * relaxations run in float32 inside float64 outer iterations; with FGMRES the
- * Krylov basis V and the preconditioned vectors Z are also stored in float32
- * (the Gram-Schmidt products, updates and norms are float64 arithmetic on
- * them, w = S~ z is float64 with its coupling term c^-1 G^T W W^T G z formed
- * in float32), and each cycle restarts from the float64 true residual once it
- * has gained a factor 1e-6.  The result is checked in float64: at the
+ * Krylov basis V, the preconditioned vectors Z and the products w = S~ z are
+ * also stored in float32 (the Gram-Schmidt products, updates and norms are
+ * float64 arithmetic on them; the coupling term c^-1 G^T W W^T G z of w is
+ * float32 arithmetic), and each cycle restarts from the float64 true residual
+ * once it has gained a factor 1e-6.  The result is checked in float64: at the
  * 256^3 benchmark size and krylov_rtol 3e-9 p' and Phi' are within 3e-9 of
  * an exact solution.  With BiCGStab the Krylov vectors and S~ products are
  * float64 in both precisions. */
