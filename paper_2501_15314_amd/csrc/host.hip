@@ -738,8 +738,14 @@ sim_status vcycle(sim_t s, const TV *v, T *z) {
 // (its only outputs are z_{j+1}, w and the products, all overwritten).
 // The host mirror alternates between two slots so that the products of
 // iteration j + 1 never overwrite those of iteration j before they are read.
+//
+// bsum (optional, on the device): the sum of b, whose mean the solver then
+// removes on the fly (b itself is left as it is).  xsum (optional): the
+// solver leaves the sum of x there instead of subtracting x's mean; the
+// caller removes it.
 template <typename T>
-sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
+sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt, const double *bsum = nullptr,
+                  double *xsum = nullptr) {
   hipStream_t st = s->st;
   const sim_config &c = s->cfg;
   const long long N = s->N;
@@ -802,7 +808,7 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
   // slot of these norms is apart from the products' slots.
   double *const mirror_res = s->hpin + 2 * MIRROR_SLOT;
   auto cycle_start = [&](const double *ax, bool speculate, double &r2) -> sim_status {
-    CKH(sub_cast_norm<T>(V, b, ax, N, s->PART, st));
+    CKH(sub_cast_norm<T>(V, b, ax, N, s->PART, st, bsum, 1.0 / (double)N));
     CKH(finalize(s->PART, red_blocks(), 1, s->RED, st, s->hpin_dev + 2 * MIRROR_SLOT));
     CKH(hipEventRecord(s->ev_iter, st));
     if (speculate && can_pipe) {
@@ -819,6 +825,7 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
   const double bnorm = sqrt(bn2);
   if (!(bnorm > 0)) {
     CKH(fill(x, N, 0.0, st));
+    if (xsum) CKH(fill(xsum, 1, 0.0, st));
     S.rel_res = 0;
     return isfinite(bn2) ? SIM_OK : fail(s, SIM_ENONFINITE, "non-finite right-hand side");
   }
@@ -924,11 +931,13 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt) {
   S.iters = total;
   S.rel_res = rel;
   if (xset) {
-    // subtract the mean of x (its sum from the last update's block sums)
-    CKH(finalize(part_x, sol_blocks(), 1, s->RED, st));
-    CKH(add_scalar_dev(x, N, s->RED, -1.0 / (double)N, st));
+    // the mean of x (its sum from the last update's block sums): subtracted
+    // here, or left to the caller in xsum
+    CKH(finalize(part_x, sol_blocks(), 1, xsum ? xsum : s->RED, st));
+    if (!xsum) CKH(add_scalar_dev(x, N, s->RED, -1.0 / (double)N, st));
   } else {
     CKH(fill(x, N, 0.0, st));
+    if (xsum) CKH(fill(xsum, 1, 0.0, st));
   }
   if (rel > c.krylov_rtol) return fail(s, SIM_ENOTCONV, "Krylov iteration limit reached");
   return SIM_OK;
@@ -1074,21 +1083,41 @@ sim_status fgmres_any(sim_t s, const double *b, double *x, sim_solve_stats *stt)
   return s->fp32 ? fgmres<float>(s, b, x, stt) : fgmres<double>(s, b, x, stt);
 }
 
-// b = RHSP + c^-1 D W RF, projected to mean zero (into BVEC)
-sim_status schur_rhs(sim_t s) {
-  CKH(scale_copy(s->BVEC, s->RHSP, s->N, 1.0, s->st));
+// b = RHSP + c^-1 D W RF (into BVEC; in_bvec: RHSP is already there),
+// projected to mean zero, or with its sum left in bsum for a solver that
+// removes the mean on the fly
+sim_status schur_rhs(sim_t s, bool in_bvec = false, double *bsum = nullptr) {
+  if (!in_bvec) CKH(scale_copy(s->BVEC, s->RHSP, s->N, 1.0, s->st));
   CKH(band_apply(s->ker, true, s->g, s->nt1, s->nt2, s->nactive, s->ACTIVE, s->TLSTART, s->TLIST, s->XS, s->RF,
                  1.0 / s->c, s->BVEC, s->st));
+  if (bsum) {
+    CKH(dot2(s->BVEC, nullptr, s->N, s->PART, s->st));
+    CKH(finalize(s->PART, red_blocks(), 1, bsum, s->st));
+    return SIM_OK;
+  }
   return project_mean(s, s->BVEC);
 }
 
+// Device slots of the isolated solve's deferred means: the sum of b and the
+// sum of p' (after the reduction slots of the Krylov solvers)
+double *mean_slots(sim_t s) { return s->RED + 3 * (MAX_RESTART + 2); }
+
 // Pressure-force correction on the current RHSP / RF: PP = p', PHIP = Phi'.
-sim_status schur_solve_core(sim_t s, sim_solve_stats *stt) {
+// isolated (the Schur solve entry): the pressure right-hand side is already
+// in BVEC, and with FGMRES the means of b and p' are not subtracted in passes
+// of their own: the solver removes b's on the fly and leaves the sum of p'
+// in mean_slots(s)[1] for the entry's output conversion (PP keeps it; a
+// constant has no gradient, so Phi' is the same).
+sim_status schur_solve_core(sim_t s, sim_solve_stats *stt, bool isolated = false) {
   sim_status rc;
   hipEvent_t e0 = s->ev_solve[0], e1 = s->ev_solve[1];
   CKH(hipEventRecord(e0, s->st));
-  if ((rc = schur_rhs(s))) return rc;
-  sim_status solve_rc = fgmres_any(s, s->BVEC, s->PP, stt);
+  const bool defer = isolated && s->cfg.krylov == SIM_KRYLOV_FGMRES;
+  double *const bsum = defer ? mean_slots(s) : nullptr, *const xsum = defer ? mean_slots(s) + 1 : nullptr;
+  if ((rc = schur_rhs(s, isolated, bsum))) return rc;
+  sim_status solve_rc = !defer  ? fgmres_any(s, s->BVEC, s->PP, stt)
+                        : s->fp32 ? fgmres<float>(s, s->BVEC, s->PP, stt, bsum, xsum)
+                                  : fgmres<double>(s, s->BVEC, s->PP, stt, bsum, xsum);
   if (solve_rc != SIM_OK && solve_rc != SIM_ENOTCONV) return solve_rc;
   // Phi' = c^-1 (B p' - RHS_F) = -c^-1 (W^T G p' + RHS_F)
   CKH(interp_grad<double>(s->ker, s->g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, s->PP, -1.0 / s->c, s->RF, -1.0 / s->c, s->PHIP, s->st));
@@ -1556,11 +1585,12 @@ sim_status solve_schur_entry(sim_t s, const double *d_rhs_p, const double *d_rhs
   if (!s->have_bodies) return fail(s, SIM_ESTATE, "no bodies set");
   if (!d_rhs_p || !d_p || (s->K > 0 && (!d_rhs_f || !d_phi))) return fail(s, SIM_EINVAL, "null argument");
   hipStream_t st = s->st;
-  CKH(to_split(s->g, 1, d_rhs_p, s->RHSP, st));
+  CKH(to_split(s->g, 1, d_rhs_p, s->BVEC, st));
   if (s->K > 0) CKH(gather3(s->K, s->PERM, d_rhs_f, s->RF, st));
-  sim_status rc = schur_solve_core(s, stats);
+  sim_status rc = schur_solve_core(s, stats, true);
   if (rc != SIM_OK && rc != SIM_ENOTCONV) return rc;
-  CKH(to_natural(s->g, 1, s->PP, d_p, st));
+  const bool deferred = s->cfg.krylov == SIM_KRYLOV_FGMRES;
+  CKH(to_natural(s->g, 1, s->PP, d_p, st, deferred ? mean_slots(s) + 1 : nullptr, 1.0 / (double)s->N));
   if (s->K > 0) CKH(scatter3(s->K, s->PERM, s->PHIP, d_phi, st));
   sim_status r2 = sync(s);
   return r2 ? r2 : rc;

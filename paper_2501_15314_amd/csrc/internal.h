@@ -55,7 +55,9 @@ inline long long geo_cells(const Geo &g) { return 2 * g.half; }
 
 // ---- grid kernels (kernels_grid.hip) ---------------------------------------
 hipError_t to_split(const Geo &g, int ncomp, const double *nat, double *spl, hipStream_t s);
-hipError_t to_natural(const Geo &g, int ncomp, const double *spl, double *nat, hipStream_t s);
+// nat = spl - mult * sum[0] with sum on the device (null: a plain copy)
+hipError_t to_natural(const Geo &g, int ncomp, const double *spl, double *nat, hipStream_t s,
+                      const double *sum = nullptr, double mult = 0.0);
 template <typename T, typename TY = double>
 hipError_t lap_apply(const Geo &g, const T *x, TY *y, hipStream_t s);  // y = L x
 hipError_t grad_apply(const Geo &g, const double *p, double *f3, double alpha, const double *add3,
@@ -267,8 +269,10 @@ hipError_t add_scalar_dev(double *x, long long n, const double *dscalar, double 
                           hipStream_t s);  // x += mult * (*dscalar)
 hipError_t sub_mul(double *r, const double *b, const double *ax, long long n, double *part,
                    hipStream_t s);  // r = b - ax, partial |r|^2
-template <typename TV>  // y = (TV)(b - ax) (ax null: (TV)b), partial |b - ax|^2
-hipError_t sub_cast_norm(TV *y, const double *b, const double *ax, long long n, double *part, hipStream_t s);
+// y = (TV)(b - mult * bsum[0] - ax) (ax, bsum optional), partial |.|^2 of the float64 value
+template <typename TV>
+hipError_t sub_cast_norm(TV *y, const double *b, const double *ax, long long n, double *part, hipStream_t s,
+                         const double *bsum = nullptr, double mult = 0.0);
 hipError_t dot2(const double *a, const double *b, long long n, double *part,
                 hipStream_t s);
 hipError_t lincomb(double *y, const double *a, double ca, const double *b, double cb, const double *c, double cc,

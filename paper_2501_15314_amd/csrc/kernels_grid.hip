@@ -69,12 +69,14 @@ __global__ void k_to_split(Geo g, const double *nat, double *spl) {
   long long ni = ((long long)p.i * g.n1 + p.j) * g.n2 + p.k;
   spl[p.comp * N + p.e] = nat[p.comp * N + ni];
 }
-__global__ void k_to_natural(Geo g, const double *spl, double *nat) {
+// nat = spl - mult * sum[0] (sum null: a plain copy)
+__global__ void k_to_natural(Geo g, const double *spl, double *nat, const double *sum, double mult) {
   RowPos p;
   if (!row_pos(g, p)) return;
   long long N = 2 * g.half;
   long long ni = ((long long)p.i * g.n1 + p.j) * g.n2 + p.k;
-  nat[p.comp * N + ni] = spl[p.comp * N + p.e];
+  const double v = spl[p.comp * N + p.e];
+  nat[p.comp * N + ni] = sum ? v - mult * sum[0] : v;
 }
 
 hipError_t to_split(const Geo &g, int ncomp, const double *nat, double *spl, hipStream_t s) {
@@ -82,9 +84,10 @@ hipError_t to_split(const Geo &g, int ncomp, const double *nat, double *spl, hip
   hipLaunchKernelGGL(k_to_split, L.grid, L.block, 0, s, g, nat, spl);
   return hipGetLastError();
 }
-hipError_t to_natural(const Geo &g, int ncomp, const double *spl, double *nat, hipStream_t s) {
+hipError_t to_natural(const Geo &g, int ncomp, const double *spl, double *nat, hipStream_t s, const double *sum,
+                      double mult) {
   RowLaunch L = row_launch(g, 2 * g.n0 * ncomp);
-  hipLaunchKernelGGL(k_to_natural, L.grid, L.block, 0, s, g, spl, nat);
+  hipLaunchKernelGGL(k_to_natural, L.grid, L.block, 0, s, g, spl, nat, sum, mult);
   return hipGetLastError();
 }
 

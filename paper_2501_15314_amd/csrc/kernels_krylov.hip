@@ -323,16 +323,19 @@ hipError_t sub_mul(double *r, const double *b, const double *ax, long long n, do
   return hipGetLastError();
 }
 
-// y = (TV)(b - ax) (ax null: y = (TV)b) ; partial |b - ax|^2 of the float64
-// difference: a Krylov cycle's first (unnormalised) basis vector together
-// with the norm of the residual it stands for
+// y = (TV)(b - mult bsum[0] - ax) (ax or bsum null: that term absent) ;
+// partial |.|^2 of the float64 value: a Krylov cycle's first (unnormalised)
+// basis vector together with the norm of the residual it stands for (bsum:
+// the sum of a right-hand side whose mean is removed on the fly)
 template <typename TV>
 __global__ void __launch_bounds__(RED_T) k_sub_cast_norm(TV *y, const double *b, const double *ax, long long n,
-                                                         double *part) {
+                                                         double *part, const double *bsum, double mult) {
   __shared__ double sh[4];
+  const double shift = bsum ? mult * bsum[0] : 0.0;
   double acc = 0.0;
   for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T) {
-    double v = ax ? b[t] - ax[t] : b[t];
+    double v = b[t] - shift;
+    if (ax) v -= ax[t];
     y[t] = (TV)v;
     acc += v * v;
   }
@@ -340,13 +343,15 @@ __global__ void __launch_bounds__(RED_T) k_sub_cast_norm(TV *y, const double *b,
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 template <typename TV>
-hipError_t sub_cast_norm(TV *y, const double *b, const double *ax, long long n, double *part, hipStream_t s) {
-  hipLaunchKernelGGL(k_sub_cast_norm<TV>, dim3(RED_BLOCKS), dim3(RED_T), 0, s, y, b, ax, n, part);
+hipError_t sub_cast_norm(TV *y, const double *b, const double *ax, long long n, double *part, hipStream_t s,
+                         const double *bsum, double mult) {
+  hipLaunchKernelGGL(k_sub_cast_norm<TV>, dim3(RED_BLOCKS), dim3(RED_T), 0, s, y, b, ax, n, part, bsum, mult);
   return hipGetLastError();
 }
-template hipError_t sub_cast_norm<float>(float *, const double *, const double *, long long, double *, hipStream_t);
+template hipError_t sub_cast_norm<float>(float *, const double *, const double *, long long, double *, hipStream_t,
+                                         const double *, double);
 template hipError_t sub_cast_norm<double>(double *, const double *, const double *, long long, double *,
-                                          hipStream_t);
+                                          hipStream_t, const double *, double);
 
 __global__ void __launch_bounds__(RED_T) k_dot2(const double *a, const double *b, long long n, double *part) {
   __shared__ double sh[4];
