@@ -104,26 +104,31 @@ template hipError_t lap_apply<float, double>(const Geo &, const float *, double 
 template hipError_t lap_apply<double, double>(const Geo &, const double *, double *, hipStream_t);
 template hipError_t lap_apply<float, float>(const Geo &, const float *, float *, hipStream_t);
 
-// f3 = add3 + alpha G p ; (G p)_d(idx) = (p(idx) - p(idx - e_d)) / h, zero on wall faces
+// f3 = add3 + alpha G p ; (G p)_d(idx) = (p(idx) - p(idx - e_d)) / h, zero on wall faces.
+// One thread per cell writes the cell's lower face along every axis, so p is
+// read once for the three components.
 __global__ void k_grad(Geo g, const double *p_, double *f3, double alpha, const double *add3) {
   RowPos p;
   if (!row_pos(g, p)) return;
   long long N = 2 * g.half;
-  int d = p.comp;
-  int bcd = geo_bc(g, d);
-  int xd = d == 0 ? p.i : (d == 1 ? p.j : p.k);
-  double v = 0.0;
-  if (!(bcd && xd == 0)) {
-    int i = p.i - (d == 0), j = p.j - (d == 1), k = p.k - (d == 2);
-    double lo = fetch(p_, g, i, j, k);
-    v = alpha * (p_[p.e] - lo) / g.h;
-    if (add3) v += add3[d * N + p.e];
+  const double pc = p_[p.e];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int bcd = geo_bc(g, d);
+    int xd = d == 0 ? p.i : (d == 1 ? p.j : p.k);
+    double v = 0.0;
+    if (!(bcd && xd == 0)) {
+      int i = p.i - (d == 0), j = p.j - (d == 1), k = p.k - (d == 2);
+      double lo = fetch(p_, g, i, j, k);
+      v = alpha * (pc - lo) / g.h;
+      if (add3) v += add3[d * N + p.e];
+    }
+    f3[d * N + p.e] = v;
   }
-  f3[d * N + p.e] = v;
 }
 hipError_t grad_apply(const Geo &g, const double *p, double *f3, double alpha, const double *add3,
                       hipStream_t s) {
-  RowLaunch L = row_launch(g, 2 * g.n0 * 3);
+  RowLaunch L = row_launch(g, 2 * g.n0);
   hipLaunchKernelGGL(k_grad, L.grid, L.block, 0, s, g, p, f3, alpha, add3);
   return hipGetLastError();
 }

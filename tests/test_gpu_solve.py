@@ -89,6 +89,28 @@ def test_schur_bicgstab_matches_oracle(case, prec, precond):
     sim.close()
 
 
+@pytest.mark.parametrize("prec", [wl.PREC_FP64, wl.PREC_FP32MG])
+def test_constant_in_pressure_rhs_is_projected_out(prec):
+    """S~ annihilates the constants (L and B^T B both do: Sec. 4.1), so the
+    solve takes RHS_p to mean zero (inside the pass that starts each Krylov
+    cycle) and returns a mean-free p': a large constant added to RHS_p must
+    leave p' and Phi' as they are."""
+    w = walls_workload(32, 260)
+    w.cfg.precision = prec
+    w.cfg.krylov_rtol = 1e-12 if prec == wl.PREC_FP64 else 1e-11
+    sim = Sim(w.cfg, w.n_points)
+    sim.set_bodies(w.bodies, w.offsets)
+    rp, rf = wl.random_schur_rhs(23, w.cfg.n, w.n_points)
+    p1, f1, _ = sim.solve_schur(rp, rf)
+    p2, f2, _ = sim.solve_schur(rp + 7.0, rf)
+    p1, p2, f1, f2 = (t.cpu().numpy() for t in (p1, p2, f1, f2))
+    tol = 1e-10 if prec == wl.PREC_FP64 else 1e-8
+    print(f"  prec {prec}: shift changes p' by {rel(p2, p1):.1e}, Phi' by {rel(f2, f1):.1e}", flush=True)
+    assert rel(p2, p1) < tol and rel(f2, f1) < tol
+    assert abs(p2.mean()) < 1e-12 * np.abs(p1).max()
+    sim.close()
+
+
 def test_schur_solve_bitwise_repeatable():
     w = walls_workload(32, 260)
     w.cfg.precision = wl.PREC_FP32MG
