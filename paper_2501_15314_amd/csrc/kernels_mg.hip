@@ -585,12 +585,72 @@ hipError_t mg_coarse_fd(const Geo &gc, const TB *b, T *x, const double *fd, hipS
 // replaces the eight of the two levels, which are bound by latency.
 constexpr int SUB_FINE = 4096;
 constexpr int SUB_COARSE = SUB_FINE / 8;
+constexpr int SUB_ZERO = SUB_FINE + SUB_COARSE;  // an LDS slot that always holds 0
+constexpr int SUB_SLOTS = SUB_FINE / 2 / COARSE_THREADS;  // fine cells of one colour per thread
+
+// A fine cell of the subcycle with everything its relaxation and residual
+// need that does not change during the kernel: its LDS index q, its
+// neighbour count nn (meta = q | nn << 16, -1 for an absent slot) and the LDS
+// indices of its neighbours in the order -x, +x, -y, +y, -z, +z, two per word
+// (a missing neighbour past a wall points at the zero slot, so it adds 0).
+// Built once per thread, so a half sweep costs six LDS reads and a few adds
+// per cell instead of the index decoding and boundary logic of lds_nb, which
+// bound the single workgroup's four SIMDs.
+struct SubCell {
+  int meta;
+  unsigned nb[3];
+};
+__device__ __forceinline__ SubCell sub_cell(const LvlDim &f, int bc0, int bc1, int bc2, int color, int ec) {
+  SubCell r;
+  const int hn2 = f.n2 >> 1;
+  r.meta = -1;
+  r.nb[0] = r.nb[1] = r.nb[2] = 0;
+  if (ec >= f.n0 * f.n1 * hn2) return r;
+  int kh, rr, i, j;
+  if (f.pow2) {
+    kh = ec & (hn2 - 1);
+    rr = ec >> (f.l2 - 1);
+    j = rr & (f.n1 - 1);
+    i = rr >> f.l1;
+  } else {
+    kh = ec % hn2;
+    rr = ec / hn2;
+    j = rr % f.n1;
+    i = rr / f.n1;
+  }
+  const int k = 2 * kh + ((i + j + color) & 1);
+  auto at = [&](int ii, int jj, int kk) { return f.off + (ii * f.n1 + jj) * f.n2 + kk; };
+  const int t[6] = {nbr(i, -1, f.n0, bc0), nbr(i, 1, f.n0, bc0), nbr(j, -1, f.n1, bc1),
+                    nbr(j, 1, f.n1, bc1),  nbr(k, -1, f.n2, bc2), nbr(k, 1, f.n2, bc2)};
+  int id[6], nn = 0;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    const int a = d >> 1;
+    id[d] = t[d] < 0 ? SUB_ZERO : (a == 0 ? at(t[d], j, k) : (a == 1 ? at(i, t[d], k) : at(i, j, t[d])));
+    nn += t[d] >= 0;
+  }
+#pragma unroll
+  for (int w = 0; w < 3; ++w) r.nb[w] = (unsigned)id[2 * w] | ((unsigned)id[2 * w + 1] << 16);
+  r.meta = at(i, j, k) | (nn << 16);
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ T sub_nbsum(const T *x, const SubCell &c) {
+  T s = T(0);
+#pragma unroll
+  for (int w = 0; w < 3; ++w) {
+    s += x[c.nb[w] & 0xffffu];
+    s += x[c.nb[w] >> 16];
+  }
+  return s;
+}
 
 template <typename T, typename TB>
 __global__ void __launch_bounds__(COARSE_THREADS) k_subcycle(Geo gf, Geo gc, const TB *bin, T *xout,
                                                              const double *fd, int pre, int post) {
-  __shared__ T sx[SUB_FINE + SUB_COARSE];
+  __shared__ T sx[SUB_FINE + SUB_COARSE + 1];
   __shared__ T sb[SUB_FINE + SUB_COARSE];
+  __shared__ T rf[SUB_FINE];  // fine residuals for the restriction
   __shared__ T fa[SUB_COARSE], fb[SUB_COARSE];
   __shared__ T Q[3][FD_MAXN * FD_MAXN];
   __shared__ T lam[3][FD_MAXN];
@@ -623,20 +683,52 @@ __global__ void __launch_bounds__(COARSE_THREADS) k_subcycle(Geo gf, Geo gc, con
     sb[e] = (T)bin[sidx(gf, i, j, k)];
     sx[e] = T(0);
   }
+  if (tid == 0) sx[SUB_ZERO] = T(0);
+  SubCell cell[2][SUB_SLOTS];
+#pragma unroll
+  for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+    for (int u = 0; u < SUB_SLOTS; ++u) cell[cc][u] = sub_cell(f, bc0, bc1, bc2, cc, tid + u * COARSE_THREADS);
   __syncthreads();
   const T h2 = (T)(gf.h * gf.h), ih2 = T(1) / h2;
+  // one half sweep over colour cc (the same operations as lds_smooth)
+  auto smooth = [&](int cc) {
+#pragma unroll
+    for (int u = 0; u < SUB_SLOTS; ++u) {
+      const SubCell &cl = cell[cc][u];
+      if (cl.meta >= 0) {
+        const int q = cl.meta & 0xffff, nn = cl.meta >> 16;
+        const T sum = sub_nbsum(sx, cl);
+        sx[q] = (h2 * sb[q] + sum) * inv_nn<T>(nn);
+      }
+    }
+  };
   for (int q = 0; q < pre; ++q) {
-    lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 0, COARSE_THREADS);
+    smooth(0);
     __syncthreads();
-    lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 1, COARSE_THREADS);
+    smooth(1);
     __syncthreads();
   }
+  // residual of every fine cell (as lds_resid), then the average over the
+  // eight children of each coarse cell
+#pragma unroll
+  for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+    for (int u = 0; u < SUB_SLOTS; ++u) {
+      const SubCell &cl = cell[cc][u];
+      if (cl.meta >= 0) {
+        const int q = cl.meta & 0xffff, nn = cl.meta >> 16;
+        const T sum = sub_nbsum(sx, cl);
+        rf[q] = sb[q] - ((T)nn * sx[q] - sum) * ih2;
+      }
+    }
+  __syncthreads();
   for (int e = tid; e < nc; e += COARSE_THREADS) {
     int i, j, k;
     lds_decode(c, e, i, j, k);
     T acc = T(0);
     for (int q = 0; q < 8; ++q)
-      acc += lds_resid(sx, sb, f, bc0, bc1, bc2, ih2, 2 * i + (q >> 2), 2 * j + ((q >> 1) & 1), 2 * k + (q & 1));
+      acc += rf[((2 * i + (q >> 2)) * gf.n1 + 2 * j + ((q >> 1) & 1)) * gf.n2 + 2 * k + (q & 1)];
     fa[e] = acc * (T)0.125;
   }
   __syncthreads();
@@ -689,9 +781,9 @@ __global__ void __launch_bounds__(COARSE_THREADS) k_subcycle(Geo gf, Geo gc, con
   }
   __syncthreads();
   for (int q = 0; q < post; ++q) {
-    lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 1, COARSE_THREADS);
+    smooth(1);
     __syncthreads();
-    lds_smooth(sx, sb, f, bc0, bc1, bc2, h2, 0, COARSE_THREADS);
+    smooth(0);
     __syncthreads();
   }
   for (int e = tid; e < nf; e += COARSE_THREADS) {
