@@ -678,17 +678,22 @@ __global__ void __launch_bounds__(COARSE_THREADS) k_subcycle(Geo gf, Geo gc, con
       p += n[a];
     }
   }
-  for (int e = tid; e < nf; e += COARSE_THREADS) {
-    int k = e % gf.n2, r = e / gf.n2, j = r % gf.n1, i = r / gf.n1;
-    sb[e] = (T)bin[sidx(gf, i, j, k)];
-    sx[e] = T(0);
-  }
   if (tid == 0) sx[SUB_ZERO] = T(0);
+  // the cell tables; slot (cc, u) is the colour-cc cell with split-layout
+  // index cc half + tid + u COARSE_THREADS, so the right-hand side is read
+  // and the result written with coalesced accesses and no index arithmetic
   SubCell cell[2][SUB_SLOTS];
 #pragma unroll
   for (int cc = 0; cc < 2; ++cc)
 #pragma unroll
-    for (int u = 0; u < SUB_SLOTS; ++u) cell[cc][u] = sub_cell(f, bc0, bc1, bc2, cc, tid + u * COARSE_THREADS);
+    for (int u = 0; u < SUB_SLOTS; ++u) {
+      cell[cc][u] = sub_cell(f, bc0, bc1, bc2, cc, tid + u * COARSE_THREADS);
+      if (cell[cc][u].meta >= 0) {
+        const int q = cell[cc][u].meta & 0xffff;
+        sb[q] = (T)bin[(long long)cc * gf.half + tid + u * COARSE_THREADS];
+        sx[q] = T(0);
+      }
+    }
   __syncthreads();
   const T h2 = (T)(gf.h * gf.h), ih2 = T(1) / h2;
   // one half sweep over colour cc (the same operations as lds_smooth)
@@ -732,35 +737,40 @@ __global__ void __launch_bounds__(COARSE_THREADS) k_subcycle(Geo gf, Geo gc, con
     fa[e] = acc * (T)0.125;
   }
   __syncthreads();
-  // exact coarse solve: the six 1-D eigenbasis transforms and the division
+  // exact coarse solve: the six 1-D eigenbasis transforms and the division;
+  // thread tid owns coarse element tid (nc <= SUB_COARSE <= COARSE_THREADS),
+  // whose index along each axis and line base are formed once
+  static_assert(SUB_COARSE <= COARSE_THREADS, "one coarse element per thread");
   const int n[3] = {gc.n0, gc.n1, gc.n2};
+  const int cstride[3] = {gc.n1 * gc.n2, gc.n2, 1};
+  int cia[3], cbase[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cia[a] = (tid / cstride[a]) % n[a];
+    cbase[a] = tid - cia[a] * cstride[a];
+  }
   auto pass = [&](const T *in, T *out, int a, bool fwd) {
-    const int na = n[a];
-    const int stride = a == 2 ? 1 : (a == 1 ? gc.n2 : gc.n1 * gc.n2);
-    const T *M = Q[a];
-    for (int e = tid; e < nc; e += COARSE_THREADS) {
-      const int ia = (e / stride) % na;
-      const int base = e - ia * stride;
+    if (tid < nc) {
+      const int na = n[a], stride = cstride[a], ia = cia[a], base = cbase[a];
+      const T *M = Q[a];
       T acc = T(0);
+#pragma unroll 8
       for (int t = 0; t < na; ++t) acc += (fwd ? M[t * na + ia] : M[ia * na + t]) * in[base + t * stride];
-      out[e] = acc;
+      out[tid] = acc;
     }
     __syncthreads();
   };
   pass(fa, fb, 2, true);
   pass(fb, fa, 1, true);
   pass(fa, fb, 0, true);
-  for (int e = tid; e < nc; e += COARSE_THREADS) {
-    int k = e % gc.n2, r = e / gc.n2, j = r % gc.n1, i = r / gc.n1;
-    T d = lam[0][i] + lam[1][j] + lam[2][k];
-    fb[e] = d > T(0) ? fb[e] / d : T(0);
+  if (tid < nc) {
+    T d = lam[0][cia[0]] + lam[1][cia[1]] + lam[2][cia[2]];
+    fb[tid] = d > T(0) ? fb[tid] / d : T(0);
   }
   __syncthreads();
   pass(fb, fa, 0, false);
   pass(fa, fb, 1, false);
-  pass(fb, fa, 2, false);
-  for (int e = tid; e < nc; e += COARSE_THREADS) sx[nf + e] = fa[e];
-  __syncthreads();
+  pass(fb, sx + nf, 2, false);  // the coarse solution, after the fine cells
   // trilinear prolongation of the coarse solution onto every fine cell
   for (int e = tid; e < nf; e += COARSE_THREADS) {
     int i, j, k;
@@ -786,10 +796,12 @@ __global__ void __launch_bounds__(COARSE_THREADS) k_subcycle(Geo gf, Geo gc, con
     smooth(0);
     __syncthreads();
   }
-  for (int e = tid; e < nf; e += COARSE_THREADS) {
-    int k = e % gf.n2, r = e / gf.n2, j = r % gf.n1, i = r / gf.n1;
-    xout[sidx(gf, i, j, k)] = sx[e];
-  }
+#pragma unroll
+  for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+    for (int u = 0; u < SUB_SLOTS; ++u)
+      if (cell[cc][u].meta >= 0)
+        xout[(long long)cc * gf.half + tid + u * COARSE_THREADS] = sx[cell[cc][u].meta & 0xffff];
 }
 
 bool subcycle_fits(const Geo &gf, const Geo &gc) {
