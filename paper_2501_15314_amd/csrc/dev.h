@@ -19,8 +19,9 @@ namespace ibs {
 
 // Plane-marching kernels shorten their chunks of planes until a grid has at
 // least this many workgroups (coarse multigrid levels); 0 keeps full chunks
-// on every grid.
-constexpr int MARCH_MIN_BLOCKS_DEFAULT = 2048;
+// on every grid.  1024 gives the 128^3 level of a 256^3 grid 2-plane chunks
+// (2048 gave it 1-plane chunks, 512 4-plane ones: both slower).
+constexpr int MARCH_MIN_BLOCKS_DEFAULT = 1024;
 
 struct Geo {
   int n0, n1, n2, hn2;
