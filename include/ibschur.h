@@ -77,7 +77,7 @@ enum { SIM_DELTA_PESKIN4 = 0, SIM_DELTA_ROMA3 = 1 };
  * also stored in float32 (the Gram-Schmidt products, updates and norms are
  * float64 arithmetic on them; the coupling term c^-1 G^T W W^T G z of w is
  * float32 arithmetic), and each cycle restarts from the float64 true residual
- * once it has gained a factor 1e-6.  The result is checked in float64: at the
+ * once it has gained a factor 3e-6.  The result is checked in float64: at the
  * 256^3 benchmark size and krylov_rtol 3e-9 p' and Phi' are within 3e-9 of
  * an exact solution.  With BiCGStab the Krylov vectors and S~ products are
  * float64 in both precisions. */
