@@ -333,10 +333,29 @@ __global__ void __launch_bounds__(RED_T) k_sub_cast_norm(TV *y, const double *b,
   __shared__ double sh[4];
   const double shift = bsum ? mult * bsum[0] : 0.0;
   double acc = 0.0;
-  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n; t += (long long)gridDim.x * RED_T) {
-    double v = b[t] - shift;
-    if (ax) v -= ax[t];
-    y[t] = (TV)v;
+  // two consecutive entries per thread and step (16-byte loads), as in the
+  // Gram-Schmidt kernels; an odd last entry is taken by thread 0 of block 0
+  const long long n2 = n >> 1;
+  for (long long t = (long long)blockIdx.x * RED_T + threadIdx.x; t < n2; t += (long long)gridDim.x * RED_T) {
+    const double2 bv = *(const double2 *)(b + 2 * t);
+    double v0 = bv.x - shift, v1 = bv.y - shift;
+    if (ax) {
+      const double2 av = *(const double2 *)(ax + 2 * t);
+      v0 -= av.x;
+      v1 -= av.y;
+    }
+    if (sizeof(TV) == 4) {
+      *(float2 *)(y + 2 * t) = make_float2((float)v0, (float)v1);
+    } else {
+      *(double2 *)(y + 2 * t) = make_double2(v0, v1);
+    }
+    acc += v0 * v0;
+    acc += v1 * v1;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    double v = b[n - 1] - shift;
+    if (ax) v -= ax[n - 1];
+    y[n - 1] = (TV)v;
     acc += v * v;
   }
   acc = block_reduce(acc, sh);
@@ -345,6 +364,8 @@ __global__ void __launch_bounds__(RED_T) k_sub_cast_norm(TV *y, const double *b,
 template <typename TV>
 hipError_t sub_cast_norm(TV *y, const double *b, const double *ax, long long n, double *part, hipStream_t s,
                          const double *bsum, double mult) {
+  // the paired accesses need 16-byte aligned vectors (8-byte for a float32 y)
+  if (((uintptr_t)b | (uintptr_t)ax) % 16 || (uintptr_t)y % (2 * sizeof(TV))) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_sub_cast_norm<TV>, dim3(RED_BLOCKS), dim3(RED_T), 0, s, y, b, ax, n, part, bsum, mult);
   return hipGetLastError();
 }
