@@ -79,15 +79,59 @@ __global__ void k_to_natural(Geo g, const double *spl, double *nat, const double
   nat[p.comp * N + ni] = sum ? v - mult * sum[0] : v;
 }
 
+// The same conversions a cell pair per thread: cells k = 2m and 2m + 1 of
+// row (i, j) are adjacent in natural order (one 16-byte access) and sit at
+// in-row index m of the two colours (grid.z = plane x component).
+__device__ __forceinline__ bool pair_pos(const Geo &g, long long &ni, long long &e0, long long &e1, int &comp) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y;
+  comp = blockIdx.z / g.n0;
+  const int i = blockIdx.z - comp * g.n0;
+  if (m >= g.hn2 || j >= g.n1) return false;
+  const long long row = (long long)i * g.n1 + j;
+  const int c0 = (i + j) & 1;  // colour of cell k = 2m
+  ni = row * g.n2 + 2 * m;
+  e0 = (long long)c0 * g.half + row * g.hn2 + m;
+  e1 = (long long)(1 - c0) * g.half + row * g.hn2 + m;
+  return true;
+}
+__global__ void k_to_split2(Geo g, const double *nat, double *spl) {
+  long long ni, e0, e1;
+  int comp;
+  if (!pair_pos(g, ni, e0, e1, comp)) return;
+  const long long N = 2 * g.half;
+  const double2 v = *(const double2 *)(nat + comp * N + ni);
+  spl[comp * N + e0] = v.x;
+  spl[comp * N + e1] = v.y;
+}
+__global__ void k_to_natural2(Geo g, const double *spl, double *nat, const double *sum, double mult) {
+  long long ni, e0, e1;
+  int comp;
+  if (!pair_pos(g, ni, e0, e1, comp)) return;
+  const long long N = 2 * g.half;
+  const double sh = sum ? mult * sum[0] : 0.0;
+  const double a = spl[comp * N + e0], b = spl[comp * N + e1];
+  *(double2 *)(nat + comp * N + ni) = sum ? make_double2(a - sh, b - sh) : make_double2(a, b);
+}
+
 hipError_t to_split(const Geo &g, int ncomp, const double *nat, double *spl, hipStream_t s) {
-  RowLaunch L = row_launch(g, 2 * g.n0 * ncomp);
-  hipLaunchKernelGGL(k_to_split, L.grid, L.block, 0, s, g, nat, spl);
+  if ((uintptr_t)nat % 16 == 0) {
+    RowLaunch L = row_launch(g, g.n0 * ncomp);
+    hipLaunchKernelGGL(k_to_split2, L.grid, L.block, 0, s, g, nat, spl);
+  } else {
+    RowLaunch L = row_launch(g, 2 * g.n0 * ncomp);
+    hipLaunchKernelGGL(k_to_split, L.grid, L.block, 0, s, g, nat, spl);
+  }
   return hipGetLastError();
 }
 hipError_t to_natural(const Geo &g, int ncomp, const double *spl, double *nat, hipStream_t s, const double *sum,
                       double mult) {
-  RowLaunch L = row_launch(g, 2 * g.n0 * ncomp);
-  hipLaunchKernelGGL(k_to_natural, L.grid, L.block, 0, s, g, spl, nat, sum, mult);
+  if ((uintptr_t)nat % 16 == 0) {
+    RowLaunch L = row_launch(g, g.n0 * ncomp);
+    hipLaunchKernelGGL(k_to_natural2, L.grid, L.block, 0, s, g, spl, nat, sum, mult);
+  } else {
+    RowLaunch L = row_launch(g, 2 * g.n0 * ncomp);
+    hipLaunchKernelGGL(k_to_natural, L.grid, L.block, 0, s, g, spl, nat, sum, mult);
+  }
   return hipGetLastError();
 }
 
