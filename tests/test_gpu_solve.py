@@ -125,6 +125,28 @@ def test_schur_solve_bitwise_repeatable():
     sim.close()
 
 
+@pytest.mark.parametrize("prec", [wl.PREC_FP64, wl.PREC_FP32MG])
+def test_zero_and_constant_rhs_give_zero_solution(prec):
+    """b = 0 (or a constant RHS_p, whose projection is 0) has the solution
+    p' = 0 and, with RHS_F = 0, Phi' = 0; the solve returns it without an
+    iteration.  Run twice on one handle, after a nonzero solve, so nothing
+    of the earlier solution survives in the outputs."""
+    w = walls_workload(32, 260)
+    w.cfg.precision = prec
+    sim = Sim(w.cfg, w.n_points)
+    sim.set_bodies(w.bodies, w.offsets)
+    rp, rf = wl.random_schur_rhs(24, w.cfg.n, w.n_points)
+    sim.solve_schur(rp, rf)
+    for const in (0.0, 3.0):
+        p, phi, st = sim.solve_schur(np.full(w.cfg.n, const), np.zeros((w.n_points, 3)))
+        p, phi = p.cpu().numpy(), phi.cpu().numpy()
+        print(f"  prec {prec} RHS_p = {const}: iters {st.iters}, max |p'| {np.abs(p).max():.1e}, "
+              f"max |Phi'| {np.abs(phi).max():.1e}", flush=True)
+        assert st.iters == 0
+        assert np.abs(p).max() <= 1e-12 * max(const, 1.0) and np.abs(phi).max() <= 1e-12 * max(const, 1.0)
+    sim.close()
+
+
 def test_notconv_reports_best_iterate():
     w = wl.make_c1(n=32, n_points=300)
     w.cfg.krylov_maxit = 1
