@@ -679,16 +679,16 @@ sim_status vcycle(sim_t s, const TV *v, T *z) {
     auto pre = [&](auto *b) -> sim_status {
       using TBl = std::remove_const_t<std::remove_pointer_t<decltype(b)>>;
       {
-        ProbeScope pr(PR_SMOOTH_FIRST, st, first_bytes(l, store_red));
+        ProbeExt pr(PR_SMOOTH_FIRST, st, first_bytes(l, store_red));
         CKH((mg_smooth_first<T, TBl>(g, x, b, store_red, st)));
       }
       for (int q = 1; q < c.mg_pre; ++q)
         for (int color = 0; color < 2; ++color) {
-          ProbeScope pr(PR_SMOOTH, st, half_bytes(l));
+          ProbeExt pr(PR_SMOOTH, st, half_bytes(l));
           CKH((mg_smooth<T, TBl>(g, x, b, color, st)));
         }
       T *bnext = (T *)s->lv[l + 1].b;
-      ProbeScope pr(PR_RESTRICT, st, restrict_bytes(l));
+      ProbeExt pr(PR_RESTRICT, st, restrict_bytes(l));
       CKH((mg_restrict<T, TBl>(g, x, b, s->lv[l + 1].g, bnext, st)));
       return SIM_OK;
     };
@@ -705,14 +705,14 @@ sim_status vcycle(sim_t s, const TV *v, T *z) {
     const Geo &g = s->lv[l].g;
     T *x = l == 0 ? z : (T *)s->lv[l].x;
     {
-      ProbeScope pr(PR_PROLONG, st, prolong_bytes(l));
+      ProbeExt pr(PR_PROLONG, st, prolong_bytes(l));
       CKH(mg_prolong<T>(g, x, s->lv[l + 1].g, (const T *)s->lv[l + 1].x, st));
     }
     auto post = [&](auto *b) -> sim_status {
       using TBl = std::remove_const_t<std::remove_pointer_t<decltype(b)>>;
       for (int q = 0; q < c.mg_post; ++q)
         for (int color = 1; color >= 0; --color) {
-          ProbeScope pr(PR_SMOOTH, st, half_bytes(l));
+          ProbeExt pr(PR_SMOOTH, st, half_bytes(l));
           CKH((mg_smooth<T, TBl>(g, x, b, color, st)));
         }
       return SIM_OK;

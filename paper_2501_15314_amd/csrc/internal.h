@@ -43,6 +43,18 @@ struct ProbeScope {
   ProbeScope(int id_, hipStream_t s_, double bytes = 0.0) : id(id_), slot(probe_begin(id_, s_, bytes)), s(s_) {}
   ~ProbeScope() { probe_end(id, slot, s); }
 };
+// A probe stamped by the kernel itself: the one launch inside the scope must
+// be made with hipExtLaunchKernelGGL and the events of probe_ext_take (null
+// when the probe is off).
+int probe_ext_begin(int id, double bytes);
+void probe_ext_take(hipEvent_t *start, hipEvent_t *stop);
+void probe_ext_end(int id, int slot, hipStream_t s);
+struct ProbeExt {
+  int id, slot;
+  hipStream_t s;
+  ProbeExt(int id_, hipStream_t s_, double bytes = 0.0) : id(id_), slot(probe_ext_begin(id_, bytes)), s(s_) {}
+  ~ProbeExt() { probe_ext_end(id, slot, s); }
+};
 
 // ---- launch shapes ---------------------------------------------------------
 struct RowLaunch {

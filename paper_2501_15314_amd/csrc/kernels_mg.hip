@@ -9,6 +9,8 @@
 // rediscretised on 2h, and a single-workgroup kernel that runs V-cycles on
 // the coarsest grids entirely in LDS.  Kernels are templated on the working
 // precision T (float or double) and on the right-hand-side type TB.
+#include <hip/hip_ext.h>
+
 #include "internal.h"
 #include "march.h"
 
@@ -208,16 +210,24 @@ __global__ void __launch_bounds__(256) k_prolong(Geo gf, T *xf, Geo gc, const T 
 template <typename T, typename TB>
 hipError_t mg_smooth_first(const Geo &g, T *x, const TB *b, bool store_red, hipStream_t s) {
   MarchShape M = march_shape(g, 1);
+  // launched with the events of an enclosing ProbeExt, if any (as the three below)
+  hipEvent_t e0, e1;
+  probe_ext_take(&e0, &e1);
   if (store_red)
-    hipLaunchKernelGGL((k_sweep<T, TB, SW_FIRST>), M.grid, M.block, 0, s, g, x, b, 1, g.h2, 0.0, 0.0, 1.0);
+    hipExtLaunchKernelGGL((k_sweep<T, TB, SW_FIRST>), M.grid, M.block, 0, s, e0, e1, 0, g, x, b, 1, g.h2, 0.0, 0.0,
+                          1.0);
   else
-    hipLaunchKernelGGL((k_sweep<T, TB, SW_FIRST1>), M.grid, M.block, 0, s, g, x, b, 1, g.h2, 0.0, 0.0, 1.0);
+    hipExtLaunchKernelGGL((k_sweep<T, TB, SW_FIRST1>), M.grid, M.block, 0, s, e0, e1, 0, g, x, b, 1, g.h2, 0.0, 0.0,
+                          1.0);
   return hipGetLastError();
 }
 template <typename T, typename TB>
 hipError_t mg_smooth(const Geo &g, T *x, const TB *b, int color, hipStream_t s) {
   MarchShape M = march_shape(g, 1);
-  hipLaunchKernelGGL((k_sweep<T, TB, SW_POISSON>), M.grid, M.block, 0, s, g, x, b, color, g.h2, 0.0, 0.0, 1.0);
+  hipEvent_t e0, e1;
+  probe_ext_take(&e0, &e1);
+  hipExtLaunchKernelGGL((k_sweep<T, TB, SW_POISSON>), M.grid, M.block, 0, s, e0, e1, 0, g, x, b, color, g.h2, 0.0,
+                        0.0, 1.0);
   return hipGetLastError();
 }
 
@@ -228,13 +238,17 @@ hipError_t mg_restrict(const Geo &gf, const T *xf, const TB *bf, const Geo &gc, 
   M.grid.z = (gf.n0 + len - 1) / len;
   // pairs of planes and rows stay inside one workgroup
   if (gf.n0 % 2 || M.block.y % 2 || len % 2) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_restrict<T, TB>), M.grid, M.block, 0, s, gf, xf, bf, gc, bc);
+  hipEvent_t e0, e1;
+  probe_ext_take(&e0, &e1);
+  hipExtLaunchKernelGGL((k_restrict<T, TB>), M.grid, M.block, 0, s, e0, e1, 0, gf, xf, bf, gc, bc);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t mg_prolong(const Geo &gf, T *xf, const Geo &gc, const T *xc, hipStream_t s) {
   MarchShape M = march_shape(gf, 1);
-  hipLaunchKernelGGL(k_prolong<T>, M.grid, M.block, 0, s, gf, xf, gc, xc);
+  hipEvent_t e0, e1;
+  probe_ext_take(&e0, &e1);
+  hipExtLaunchKernelGGL(k_prolong<T>, M.grid, M.block, 0, s, e0, e1, 0, gf, xf, gc, xc);
   return hipGetLastError();
 }
 

@@ -21,6 +21,9 @@ struct ProbeState {
 
 namespace {
 thread_local ProbeState *t_probe = nullptr;
+// the event pair of a probed launch made through hipExtLaunchKernel, between
+// ProbeExt's constructor and the launch that takes it
+thread_local std::pair<hipEvent_t, hipEvent_t> t_ext = {nullptr, nullptr};
 }  // namespace
 
 ProbeState *probe_new() { return new ProbeState(); }
@@ -52,9 +55,7 @@ void probe_set_points(ProbeState *ps, long long K, long long band_cells) {
 long long probe_points() { return t_probe ? t_probe->points : 0; }
 long long probe_band_cells() { return t_probe ? t_probe->band_cells : 0; }
 
-int probe_begin(int id, hipStream_t s, double bytes) {
-  ProbeState *ps = t_probe;
-  if (!ps || id < 0 || id >= PR_COUNT || !ps->on[id]) return -1;
+static int probe_slot(ProbeState *ps, int id, double bytes) {
   std::pair<hipEvent_t, hipEvent_t> e;
   if (!ps->pool.empty()) {
     e = ps->pool.back();
@@ -66,10 +67,45 @@ int probe_begin(int id, hipStream_t s, double bytes) {
       return -1;
     }
   }
-  hipEventRecord(e.first, s);
   ps->ev[id].push_back(e);
   ps->bytes[id].push_back(bytes);
   return (int)ps->ev[id].size() - 1;
+}
+
+int probe_begin(int id, hipStream_t s, double bytes) {
+  ProbeState *ps = t_probe;
+  if (!ps || id < 0 || id >= PR_COUNT || !ps->on[id]) return -1;
+  const int slot = probe_slot(ps, id, bytes);
+  if (slot >= 0) hipEventRecord(ps->ev[id][slot].first, s);
+  return slot;
+}
+
+// A probe whose events the runtime stamps with the kernel's own start and
+// end: the launch inside the scope is made with hipExtLaunchKernel and takes
+// the pair through probe_ext_take, so short kernels are timed without the
+// dispatch latency that events recorded around the launch add.
+int probe_ext_begin(int id, double bytes) {
+  ProbeState *ps = t_probe;
+  t_ext = {nullptr, nullptr};
+  if (!ps || id < 0 || id >= PR_COUNT || !ps->on[id]) return -1;
+  const int slot = probe_slot(ps, id, bytes);
+  if (slot >= 0) t_ext = ps->ev[id][slot];
+  return slot;
+}
+void probe_ext_take(hipEvent_t *start, hipEvent_t *stop) {
+  *start = t_ext.first;
+  *stop = t_ext.second;
+  t_ext = {nullptr, nullptr};
+}
+void probe_ext_end(int id, int slot, hipStream_t s) {
+  ProbeState *ps = t_probe;
+  if (slot < 0 || !ps) return;
+  if (t_ext.first) {
+    // no launch took the pair: record it here (an empty interval)
+    hipEventRecord(t_ext.first, s);
+    hipEventRecord(t_ext.second, s);
+    t_ext = {nullptr, nullptr};
+  }
 }
 
 void probe_end(int id, int slot, hipStream_t s) {
