@@ -611,7 +611,7 @@ sim_status schur_matvec(sim_t s, const T *z, TW *w) {
   constexpr bool f32 = std::is_same<TW, float>::value;
   static_assert(!f32 || std::is_same<T, float>::value, "a float32 product takes a float32 z");
   {
-    ProbeScope pr(PR_LAP, s->st, (double)s->N * (sizeof(T) + sizeof(TW)));  // z read, w written
+    ProbeExt pr(PR_LAP, s->st, (double)s->N * (sizeof(T) + sizeof(TW)));  // z read, w written
     CKH((lap_apply<T, TW>(s->g, z, w, s->st)));
   }
   CKH(interp_grad<T>(s->ker, s->g, s->nt1, s->nt2, s->nnz, s->NZT, s->TSTART, s->XS, z, 1.0, nullptr, 0.0, s->Q,
@@ -665,7 +665,7 @@ sim_status vcycle(sim_t s, const TV *v, T *z) {
   auto subcycle = [&](auto *b, T *x) -> sim_status {
     using TBs = std::remove_const_t<std::remove_pointer_t<decltype(b)>>;
     const Geo &gf = s->lv[nl - 2].g;
-    ProbeScope pr(PR_COARSE, st, (double)geo_cells(gf) * (sizeof(TBs) + t));
+    ProbeExt pr(PR_COARSE, st, (double)geo_cells(gf) * (sizeof(TBs) + t));
     CKH((mg_subcycle<T, TBs>(gf, s->lv[nl - 1].g, b, x, s->COARSEFD, c.mg_pre, c.mg_post, st)));
     return SIM_OK;
   };
@@ -800,7 +800,7 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt, con
     sim_status r = schur_matvec<T, TW>(s, zj, w);
     if (r) return r;
     {
-      ProbeScope pr(PR_MULTIDOT, st, (double)N * (sizeof(TW) + (j + 1) * sizeof(T)));  // w, V_0..V_j
+      ProbeExt pr(PR_MULTIDOT, st, (double)N * (sizeof(TW) + (j + 1) * sizeof(T)));  // w, V_0..V_j
       CKH((multidot<T, TW>(w, V, N, j + 1, N, part_dots, st)));
     }
     CKH(finalize(part_dots, red_blocks(), j + 1, s->RED, st, s->hpin_dev + slot(j)));
@@ -862,7 +862,7 @@ sim_status fgmres(sim_t s, const double *b, double *x, sim_solve_stats *stt, con
       // is h_ij = sig_j sig_i g_i, h_{j+1,j} = sig_j |V'_{j+1}|.
       {
         // w, V_0..V_j read, V_{j+1} written
-        ProbeScope pr(PR_UPDATE_NORM, st, (double)N * (sizeof(TW) + (j + 2) * sizeof(T)));
+        ProbeExt pr(PR_UPDATE_NORM, st, (double)N * (sizeof(TW) + (j + 2) * sizeof(T)));
         CKH((update_cast_norm<T, TW>(vnext, w, V, N, j + 1, s->RED, sig2, N, part_norm, st)));
       }
       CKH(finalize(part_norm, red_blocks(), 1, red_norm, st, s->hpin_dev + slot(j) + MIRROR_NORM));

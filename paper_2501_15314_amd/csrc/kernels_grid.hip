@@ -9,6 +9,8 @@
 // pressure Laplacian is Neumann there; a tangential velocity's neighbour
 // beyond a wall is the ghost value -u on a no-slip wall and +u on a
 // free-slip wall.
+#include <hip/hip_ext.h>
+
 #include "internal.h"
 #include "march.h"
 
@@ -141,7 +143,10 @@ hipError_t to_natural(const Geo &g, int ncomp, const double *spl, double *nat, h
 template <typename T, typename TY>
 hipError_t lap_apply(const Geo &g, const T *x, TY *y, hipStream_t s) {
   MarchShape M = march_shape(g, 1);
-  hipLaunchKernelGGL((k_apply2<T, TY, AP_LAP>), M.grid, M.block, 0, s, g, x, nullptr, y, 0.0, 0.0, nullptr);
+  hipEvent_t e0, e1;
+  probe_ext_take(&e0, &e1);  // the events of an enclosing ProbeExt, if any
+  hipExtLaunchKernelGGL((k_apply2<T, TY, AP_LAP>), M.grid, M.block, 0, s, e0, e1, 0, g, x, nullptr, y, 0.0, 0.0,
+                        (double *)nullptr);
   return hipGetLastError();
 }
 template hipError_t lap_apply<float, double>(const Geo &, const float *, double *, hipStream_t);

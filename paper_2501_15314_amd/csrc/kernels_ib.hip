@@ -10,6 +10,8 @@
 // candidate points of the 27 neighbouring tiles in a fixed order, and for
 // each point its 64 stencil nodes are 64 distinct lanes adding into distinct
 // LDS cells, so every grid value is summed in the same order on every run.
+#include <hip/hip_ext.h>
+
 #include "internal.h"
 
 namespace ibs {
@@ -308,13 +310,16 @@ hipError_t interp_grad(int ker, const Geo &g, int nt1, int nt2, int ntiles_nz, c
                        const double *X, const T *z, double alpha, const double *y, double beta, double *out,
                        hipStream_t s, bool f32) {
   // positions read, results written (and y read), the cells of the support band (T each)
-  ProbeScope probe_(PR_INTERP_GRAD, s,
+  ProbeExt probe_(PR_INTERP_GRAD, s,
                     (double)probe_points() * (beta != 0.0 ? 72 : 48) + (double)probe_band_cells() * sizeof(T));
   if (ntiles_nz == 0) return hipSuccess;
   if (f32 && sizeof(T) != sizeof(float)) return hipErrorInvalidValue;
   dim3 gr(ntiles_nz), bl(256);
-#define INTERP(K_, A_) \
-  hipLaunchKernelGGL((k_interp<K_, 1, T, A_>), gr, bl, 0, s, g, nt1, nt2, tiles, tstart, X, z, alpha, y, beta, out)
+  hipEvent_t e0, e1;
+  probe_ext_take(&e0, &e1);
+#define INTERP(K_, A_)                                                                                             \
+  hipExtLaunchKernelGGL((k_interp<K_, 1, T, A_>), gr, bl, 0, s, e0, e1, 0, g, nt1, nt2, tiles, tstart, X, z, alpha, y, \
+                        beta, out)
   if (ker == KER_PESKIN4) {
     if (f32) INTERP(KER_PESKIN4, float);
     else INTERP(KER_PESKIN4, double);
@@ -735,12 +740,15 @@ static hipError_t band_launch(int ker, bool div, const Geo &g, int nt1, int nt2,
                               const int *lstart, const int *list, const double *X, const double *q, double alpha,
                               TO *out, hipStream_t s, bool f32) {
   // positions and values read, the active tiles' cells (div) or faces read and written
-  ProbeScope probe_(div ? PR_BAND_DIV : PR_BAND_FACE, s,
+  ProbeExt probe_(div ? PR_BAND_DIV : PR_BAND_FACE, s,
                     (double)probe_points() * 48 + (double)probe_band_cells() * (div ? 1 : 3) * 2 * sizeof(TO));
   if (nactive == 0) return hipSuccess;
   dim3 gr(nactive), bl(256);
-#define BAND(K_, D_, A_) \
-  hipLaunchKernelGGL((k_band<K_, D_, A_, TO>), gr, bl, 0, s, g, nt1, nt2, active, lstart, list, X, q, alpha, out)
+  hipEvent_t e0, e1;
+  probe_ext_take(&e0, &e1);
+#define BAND(K_, D_, A_)                                                                                           \
+  hipExtLaunchKernelGGL((k_band<K_, D_, A_, TO>), gr, bl, 0, s, e0, e1, 0, g, nt1, nt2, active, lstart, list, X, q, \
+                        alpha, out)
   if (f32) {
     if (!div) return hipErrorInvalidValue;  // float32 sums serve the S~ products only
     if (ker == KER_PESKIN4) BAND(KER_PESKIN4, true, float);

@@ -5,6 +5,8 @@
 // order, fixed butterfly inside the wavefront, fixed order across the
 // wavefronts of a block, then a second kernel that sums the per-block
 // partials in a fixed order.
+#include <hip/hip_ext.h>
+
 #include "internal.h"
 
 namespace ibs {
@@ -74,22 +76,31 @@ __global__ void __launch_bounds__(RED_T) k_multidot(const TW *w, const TV *V, lo
 
 template <typename TV, typename TW, int NV>
 static void launch_multidot(const TW *w, const TV *V, long long stride, int nv, long long n, double *part,
-                            hipStream_t s) {
+                            hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if constexpr (NV > 1) {
-    if (nv < NV) return launch_multidot<TV, TW, NV - 1>(w, V, stride, nv, n, part, s);
+    if (nv < NV) return launch_multidot<TV, TW, NV - 1>(w, V, stride, nv, n, part, s, e0, e1);
   }
-  hipLaunchKernelGGL((k_multidot<TV, TW, NV>), dim3(RED_BLOCKS), dim3(RED_T), 0, s, w, V, stride, n, part);
+  hipExtLaunchKernelGGL((k_multidot<TV, TW, NV>), dim3(RED_BLOCKS), dim3(RED_T), 0, s, e0, e1, 0, w, V, stride, n,
+                        part);
 }
 
 template <typename TV, typename TW>
 hipError_t multidot(const TW *w, const TV *V, long long stride, int nv, long long n, double *part,
                     hipStream_t s) {
+  // the events of an enclosing ProbeExt, if any: stamped by the one launch,
+  // or recorded around the launches when there are several
+  hipEvent_t e0, e1;
+  probe_ext_take(&e0, &e1);
   if ((n & 1) || (stride & 1)) return hipErrorInvalidValue;
+  const bool one = nv <= MD_MAX;
+  if (!one && e0) hipEventRecord(e0, s);
   // part layout: [blk][nv]; chunks of MD_MAX vectors write consecutive column groups
   for (int c0 = 0; c0 < nv; c0 += MD_MAX) {
     int nc = nv - c0 < MD_MAX ? nv - c0 : MD_MAX;
-    launch_multidot<TV, TW, MD_MAX>(w, V + c0 * stride, stride, nc, n, part + (long long)c0 * RED_BLOCKS, s);
+    launch_multidot<TV, TW, MD_MAX>(w, V + c0 * stride, stride, nc, n, part + (long long)c0 * RED_BLOCKS, s,
+                                    one ? e0 : nullptr, one ? e1 : nullptr);
   }
+  if (!one && e1) hipEventRecord(e1, s);
   return hipGetLastError();
 }
 
@@ -142,23 +153,25 @@ __global__ void __launch_bounds__(RED_T) k_update_cast_norm(TV *vout, const TW *
 
 template <typename TV, typename TW, int NV>
 static void launch_update(TV *vout, const TW *w, const TV *V, long long stride, int nv, const double *g,
-                          const KCoef &sig2, long long n, double *part, hipStream_t s) {
+                          const KCoef &sig2, long long n, double *part, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if constexpr (NV > 1) {
-    if (nv < NV) return launch_update<TV, TW, NV - 1>(vout, w, V, stride, nv, g, sig2, n, part, s);
+    if (nv < NV) return launch_update<TV, TW, NV - 1>(vout, w, V, stride, nv, g, sig2, n, part, s, e0, e1);
   }
-  hipLaunchKernelGGL((k_update_cast_norm<TV, TW, NV>), dim3(RED_BLOCKS), dim3(RED_T), 0, s, vout, w, V, stride,
-                     nv, g, sig2, n, part);
+  hipExtLaunchKernelGGL((k_update_cast_norm<TV, TW, NV>), dim3(RED_BLOCKS), dim3(RED_T), 0, s, e0, e1, 0, vout, w,
+                        V, stride, nv, g, sig2, n, part);
 }
 
 template <typename TV, typename TW>
 hipError_t update_cast_norm(TV *vout, const TW *w, const TV *V, long long stride, int nv, const double *g,
                             const KCoef &sig2, long long n, double *part, hipStream_t s) {
+  hipEvent_t e0, e1;
+  probe_ext_take(&e0, &e1);  // the events of an enclosing ProbeExt, if any
   if (nv < 1 || nv > 64 || (n & 1) || (stride & 1)) return hipErrorInvalidValue;
   if (nv <= MD_MAX)
-    launch_update<TV, TW, MD_MAX>(vout, w, V, stride, nv, g, sig2, n, part, s);
+    launch_update<TV, TW, MD_MAX>(vout, w, V, stride, nv, g, sig2, n, part, s, e0, e1);
   else
-    hipLaunchKernelGGL((k_update_cast_norm<TV, TW, 0>), dim3(RED_BLOCKS), dim3(RED_T), 0, s, vout, w, V, stride,
-                       nv, g, sig2, n, part);
+    hipExtLaunchKernelGGL((k_update_cast_norm<TV, TW, 0>), dim3(RED_BLOCKS), dim3(RED_T), 0, s, e0, e1, 0, vout, w, V,
+                          stride, nv, g, sig2, n, part);
   return hipGetLastError();
 }
 template hipError_t update_cast_norm<float, double>(float *, const double *, const float *, long long, int,

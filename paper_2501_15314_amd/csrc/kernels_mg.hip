@@ -828,7 +828,10 @@ template <typename T, typename TB>
 hipError_t mg_subcycle(const Geo &gf, const Geo &gc, const TB *b, T *x, const double *fd, int pre, int post,
                        hipStream_t s) {
   if (!subcycle_fits(gf, gc)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_subcycle<T, TB>), dim3(1), dim3(COARSE_THREADS), 0, s, gf, gc, b, x, fd, pre, post);
+  hipEvent_t e0, e1;
+  probe_ext_take(&e0, &e1);
+  hipExtLaunchKernelGGL((k_subcycle<T, TB>), dim3(1), dim3(COARSE_THREADS), 0, s, e0, e1, 0, gf, gc, b, x, fd, pre,
+                        post);
   return hipGetLastError();
 }
 
