@@ -78,7 +78,9 @@ __global__ void k_to_natural(Geo g, const double *spl, double *nat, const double
   long long N = 2 * g.half;
   long long ni = ((long long)p.i * g.n1 + p.j) * g.n2 + p.k;
   const double v = spl[p.comp * N + p.e];
-  nat[p.comp * N + ni] = sum ? v - mult * sum[0] : v;
+  // separately rounded product and difference (no fused multiply-add), as
+  // in the paired form below, so both give the same bits
+  nat[p.comp * N + ni] = sum ? __dsub_rn(v, __dmul_rn(mult, sum[0])) : v;
 }
 
 // The same conversions a cell pair per thread: cells k = 2m and 2m + 1 of
@@ -110,9 +112,9 @@ __global__ void k_to_natural2(Geo g, const double *spl, double *nat, const doubl
   int comp;
   if (!pair_pos(g, ni, e0, e1, comp)) return;
   const long long N = 2 * g.half;
-  const double sh = sum ? mult * sum[0] : 0.0;
+  const double sh = sum ? __dmul_rn(mult, sum[0]) : 0.0;
   const double a = spl[comp * N + e0], b = spl[comp * N + e1];
-  *(double2 *)(nat + comp * N + ni) = sum ? make_double2(a - sh, b - sh) : make_double2(a, b);
+  *(double2 *)(nat + comp * N + ni) = sum ? make_double2(__dsub_rn(a, sh), __dsub_rn(b, sh)) : make_double2(a, b);
 }
 
 hipError_t to_split(const Geo &g, int ncomp, const double *nat, double *spl, hipStream_t s) {

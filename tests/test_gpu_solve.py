@@ -147,6 +147,36 @@ def test_zero_and_constant_rhs_give_zero_solution(prec):
     sim.close()
 
 
+def test_unaligned_caller_buffers_give_the_same_solve():
+    """The boundary takes any 8-byte aligned device pointers: RHS_p and p'
+    one double past a 16-byte boundary take the per-cell layout conversions
+    instead of the paired ones, with the same values bit for bit."""
+    import ctypes as C
+    import torch
+    from paper_2501_15314_amd import _lib
+    w = walls_workload(32, 260)
+    w.cfg.precision = wl.PREC_FP32MG
+    sim = Sim(w.cfg, w.n_points)
+    sim.set_bodies(w.bodies, w.offsets)
+    rp, rf = wl.random_schur_rhs(25, w.cfg.n, w.n_points)
+    p1, f1, _ = sim.solve_schur(rp, rf)
+    n = int(np.prod(w.cfg.n))
+    rbuf = torch.zeros(n + 1, dtype=torch.float64, device=sim.dev)
+    rbuf[1:] = torch.as_tensor(rp.ravel(), device=sim.dev)
+    pbuf = torch.zeros(n + 1, dtype=torch.float64, device=sim.dev)
+    rft = torch.as_tensor(rf, dtype=torch.float64, device=sim.dev).contiguous()
+    phi = torch.empty((w.n_points, 3), dtype=torch.float64, device=sim.dev)
+    assert (rbuf[1:].data_ptr() % 16, pbuf[1:].data_ptr() % 16) == (8, 8)
+    st = _lib.SolveStats()
+    rc = sim.lib.sim_solve_schur(sim.h, C.c_void_p(rbuf[1:].data_ptr()), C.c_void_p(rft.data_ptr()),
+                                 C.c_void_p(pbuf[1:].data_ptr()), C.c_void_p(phi.data_ptr()), C.byref(st))
+    torch.cuda.synchronize()
+    assert rc == 0
+    assert np.array_equal(pbuf[1:].cpu().numpy(), p1.cpu().numpy().ravel())
+    assert np.array_equal(phi.cpu().numpy(), f1.cpu().numpy())
+    sim.close()
+
+
 def test_notconv_reports_best_iterate():
     w = wl.make_c1(n=32, n_points=300)
     w.cfg.krylov_maxit = 1
