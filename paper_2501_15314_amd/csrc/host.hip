@@ -1164,9 +1164,11 @@ sim_status helm_solve(sim_t s, const double *rhs, double *u, sim_solve_stats *st
   double bnorm = sqrt(bn2);
   // sweeps per correction: enough for rho^k to reach the remaining factor
   // to helm_rtol (half of it, for margin), but no more than a safe gain for
-  // the correction's precision (1e-4 in float32; 1e-10 in float64, where one
-  // correction usually suffices)
-  const double floor_gain = sizeof(T) == 4 ? 1e-4 : 1e-10;
+  // the correction's precision (1e-5 in float32, two orders above its
+  // rounding; 1e-10 in float64, where one correction usually suffices).
+  // In float32, 1e-5 against 1e-4 saves a correction per solve at 1e-10:
+  // 256^3 steps 11.47 -> 11.08 ms (1e-6: 11.12 ms).
+  const double floor_gain = sizeof(T) == 4 ? 1e-5 : 1e-10;
   auto sweeps_for = [&](double rel_now) {
     const double gain = std::min(1.0, std::max(0.5 * c.helm_rtol / std::max(rel_now, 1e-300), floor_gain));
     int k = rho > 1e-12 ? (int)ceil(log(gain) / log(rho)) : 1;
