@@ -395,7 +395,9 @@ enum {
   SIM_PROBE_VCYCLE = 14,            /* one whole preconditioner application (all its kernels) */
   SIM_PROBE_MOM_RHS = 15,           /* momentum right-hand side with convection */
   SIM_PROBE_HELM_FIRST = 16,        /* momentum SOR sweep from zero (both colours) */
-  SIM_PROBE_COUNT = 17
+  SIM_PROBE_TILE_DOWN = 17,         /* tile level: pre-smoothing + residual + restriction */
+  SIM_PROBE_TILE_UP = 18,           /* tile level: prolongation + post-smoothing */
+  SIM_PROBE_COUNT = 19
 };
 sim_status sim_probe_enable(sim_t sim, int32_t probe, int32_t on);
 sim_status sim_probe_read(sim_t sim, int32_t probe, int64_t *launches, double *ms, double *bytes,

@@ -29,7 +29,7 @@ EXPORTS = ["sim_config_check", "sim_workspace_bytes", "sim_create", "sim_destroy
 PROBES = dict(smooth=0, smooth_first=1, restrict=2, prolong=3, laplacian=4,
               spread_div=5, spread_face=6, interp_grad=7, interp_face=8, multidot=9,
               update_norm=10, coarse=11, helm_sweep=12, helm_resid=13, vcycle=14, mom_rhs=15,
-              helm_first=16)
+              helm_first=16, tile_down=17, tile_up=18)
 
 
 class SimConfig(C.Structure):

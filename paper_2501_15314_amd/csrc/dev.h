@@ -99,6 +99,35 @@ __device__ __forceinline__ int cell_nnb(const Geo &g, int i, int j, int k) {
   return n;
 }
 
+// Pressure-cell arithmetic of the multigrid cycle, with its fused
+// multiply-adds written out so that the plane-march kernels and the
+// tile-level kernels round every cell the same way:
+//   pc_first:  the Gauss-Seidel value h^2 b / nn of a first sweep from
+//              x = 0 (products rounded one at a time, never fused into a
+//              later sum);
+//   pc_relax:  Gauss-Seidel value (h^2 b + sum of neighbours) / nn;
+//   pc_resid:  residual b - (nn x - sum of neighbours) / h^2;
+//   blend34:   3/4 near + 1/4 far, one axis of cell-centred trilinear
+//              interpolation.
+__device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
+__device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
+template <typename T>
+__device__ __forceinline__ T pc_first(T h2, T b, int nn) {
+  return mul_rn(mul_rn(h2, b), inv_nn<T>(nn));
+}
+template <typename T>
+__device__ __forceinline__ T pc_relax(T h2, T b, T sum, int nn) {
+  return fma(h2, b, sum) * inv_nn<T>(nn);
+}
+template <typename T>
+__device__ __forceinline__ T pc_resid(T b, T x, T sum, int nn, T ih2) {
+  return fma(-fma((T)nn, x, -sum), ih2, b);
+}
+template <typename T>
+__device__ __forceinline__ T blend34(T near, T far) {
+  return fma((T)0.75, near, (T)0.25 * far);
+}
+
 // ---------------------------------------------------------------------------
 // Discrete delta kernels (argument in cell widths).  ROMA3 is the 3-point
 // kernel of the paper (Sec. 2.3, eq. delta); PESKIN4 the standard 4-point one.

@@ -62,6 +62,7 @@ struct Level {
   Geo g;
   void *x = nullptr;
   void *b = nullptr;
+  void *xs = nullptr;  // a tile level's pre-smoothed x (null: the level runs the march kernels)
 };
 
 }  // namespace
@@ -194,6 +195,39 @@ int march_min_blocks_setting() {
   return (e && e[0] == '1' && e[1] == '\0') ? 0 : MARCH_MIN_BLOCKS_DEFAULT;
 }
 
+// Multigrid levels of at most this many cells run as tile levels (two
+// launches per level instead of seven: k_tile_down, k_tile_up).  On a 256^3
+// grid that is the 64^3 and 32^3 levels, about 8.9 + 6.8 us per level
+// against seven launches of about 4.5 us (142.5 -> 148.3 solves/s); with the
+// 128^3 level too, the tiles' redundant halo work (an 8^3 tile loads 16^3
+// cells) outweighs the launches saved there (141.3 solves/s), and the finest
+// levels stream through the march kernels near the bandwidth bound.
+// IBSCHUR_MG_TILE_CELLS in the environment at sim_create overrides it
+// (0: no tile levels).
+constexpr long long MG_TILE_CELLS_DEFAULT = 64LL * 64 * 64;
+long long mg_tile_cells_setting() {
+  const char *e = getenv("IBSCHUR_MG_TILE_CELLS");
+  if (!e || !e[0]) return MG_TILE_CELLS_DEFAULT;
+  char *end = nullptr;
+  const long long v = strtoll(e, &end, 10);
+  return (end && *end == '\0' && v >= 0) ? v : MG_TILE_CELLS_DEFAULT;
+}
+// Whether level l of the hierarchy dims (3 entries per level) runs as a tile
+// level: a V-cycle preconditioner, a next level of half the edges, edges that
+// are multiples of the 8-cell tile, 1 or 2 pre- and post-sweeps, and at most
+// mg_tile_cells_setting() cells.
+bool tile_level(const sim_config *c, const std::vector<int> &dims, size_t l) {
+  if (c->precond != SIM_PRECOND_VCYCLE || 3 * l + 5 >= dims.size()) return false;
+  if (c->mg_pre < 1 || c->mg_pre > 2 || c->mg_post < 1 || c->mg_post > 2) return false;
+  long long cells = 1;
+  for (int a = 0; a < 3; ++a) {
+    const int n = dims[3 * l + a];
+    if (n % 8 != 0 || dims[3 * l + 3 + a] * 2 != n) return false;
+    cells *= n;
+  }
+  return cells <= mg_tile_cells_setting();
+}
+
 // Validate the configuration; fills the level dimensions. Returns "" if ok.
 std::string validate(const sim_config *c, std::vector<int> *dims) {
   if (!c) return "null config";
@@ -264,6 +298,7 @@ struct SolveScratch {
   static constexpr int MAX_LEVELS = 24;
   int nlv = 0;                       // levels below the finest
   void *lvx[MAX_LEVELS] = {}, *lvb[MAX_LEVELS] = {};
+  void *lvs[MAX_LEVELS + 1] = {};    // pre-smoothed x of the tile levels, from the finest
   double *Q = nullptr, *RF = nullptr, *PHIP = nullptr, *PART = nullptr, *RED = nullptr;
   unsigned short *FDW1 = nullptr, *FDW2 = nullptr;
   double *FDX1 = nullptr, *FDX2 = nullptr;
@@ -276,6 +311,7 @@ void put_solve_scratch(sim_s *s, const SolveScratch &q) {
     s->lv[l + 1].x = q.lvx[l];
     s->lv[l + 1].b = q.lvb[l];
   }
+  for (size_t l = 0; l < s->lv.size() && l <= (size_t)SolveScratch::MAX_LEVELS; ++l) s->lv[l].xs = q.lvs[l];
   s->Q = q.Q; s->RF = q.RF; s->PHIP = q.PHIP; s->PART = q.PART; s->RED = q.RED;
   s->FDW1 = q.FDW1; s->FDW2 = q.FDW2;
   s->FDX1 = q.FDX1; s->FDX2 = q.FDX2;
@@ -290,6 +326,7 @@ SolveScratch get_solve_scratch(const sim_s *s) {
     q.lvb[q.nlv] = s->lv[l].b;
     ++q.nlv;
   }
+  for (size_t l = 0; l < s->lv.size() && l <= (size_t)SolveScratch::MAX_LEVELS; ++l) q.lvs[l] = s->lv[l].xs;
   q.Q = s->Q; q.RF = s->RF; q.PHIP = s->PHIP; q.PART = s->PART; q.RED = s->RED;
   q.FDW1 = s->FDW1; q.FDW2 = s->FDW2;
   q.FDX1 = s->FDX1; q.FDX2 = s->FDX2;
@@ -325,6 +362,9 @@ SolveScratch carve_solve(Carver &cv, const sim_config *c, long long K, long long
     q.lvb[q.nlv] = cv.take(ts * nl);
     ++q.nlv;
   }
+  for (size_t l = 0; 3 * l < dims.size() && l <= (size_t)SolveScratch::MAX_LEVELS; ++l)
+    if (tile_level(c, dims, l))
+      q.lvs[l] = cv.take(ts * (size_t)dims[3 * l] * dims[3 * l + 1] * dims[3 * l + 2]);
   q.Q = cv.arr<double>(3 * K);
   q.RF = cv.arr<double>(3 * K);
   q.PHIP = cv.arr<double>(3 * K);
@@ -639,18 +679,24 @@ sim_status vcycle(sim_t s, const TV *v, T *z) {
   auto half_bytes = [&](int l) { return cells(l) * (0.5 * t + 0.5 * tb(l) + 0.5 * t); };
   auto restrict_bytes = [&](int l) { return cells(l) * (t + 0.5 * tb(l)) + cells(l + 1) * t; };
   auto prolong_bytes = [&](int l) { return cells(l) * t + cells(l + 1) * t; };
+  // tile levels: b read, x written, the coarse b written; the red half of x,
+  // b and the coarse x read, x written
+  auto tile_down_bytes = [&](int l) { return cells(l) * (tb(l) + t) + cells(l + 1) * t; };
+  auto tile_up_bytes = [&](int l) { return cells(l) * (0.5 * t + tb(l) + t) + cells(l + 1) * t; };
 
   // the last two levels run in one LDS workgroup when they fit (an exact
   // coarse solve below a fine level of at most 4096 cells); grid-wide levels
   // run above level lsub
   const bool sub = nl >= 2 && cyc == 0 && !s->coarse_mfma && subcycle_fits(s->lv[nl - 2].g, s->lv[nl - 1].g);
   const int lsub = sub ? nl - 2 : nl - 1;
+  auto tiled = [&](int l) { return l < lsub && s->lv[l].xs != nullptr; };
   // the whole cycle: the sum of the per-launch models below
   ProbeScope whole(PR_VCYCLE, st, [&] {
     double b = nl == 1 ? coarse_bytes(0) : coarse_bytes(lsub);
     for (int l = 0; l < lsub; ++l)
-      b += first_bytes(l, c.mg_pre == 1) + 2.0 * (c.mg_pre - 1) * half_bytes(l) + restrict_bytes(l) +
-           prolong_bytes(l) + 2.0 * c.mg_post * half_bytes(l);
+      b += tiled(l) ? tile_down_bytes(l) + tile_up_bytes(l)
+                    : first_bytes(l, c.mg_pre == 1) + 2.0 * (c.mg_pre - 1) * half_bytes(l) + restrict_bytes(l) +
+                          prolong_bytes(l) + 2.0 * c.mg_post * half_bytes(l);
     return b;
   }());
   auto coarse_solve = [&](const Geo &g, auto *b, T *x) -> sim_status {
@@ -671,13 +717,21 @@ sim_status vcycle(sim_t s, const TV *v, T *z) {
   };
   if (sub && lsub == 0) return subcycle(v, z);
   // descend: pre-smoothing red then black, the first sweep from zero (which
-  // stores the red values only when no further half sweep overwrites them)
+  // stores the red values only when no further half sweep overwrites them);
+  // a tile level runs its sweeps, residual and restriction in one launch and
+  // keeps its pre-smoothed x apart (xs), since its ascent reads the old
+  // values of neighbouring tiles while writing x
   const bool store_red = c.mg_pre == 1;
   for (int l = 0; l < lsub; ++l) {
     const Geo &g = s->lv[l].g;
     T *x = l == 0 ? z : (T *)s->lv[l].x;
     auto pre = [&](auto *b) -> sim_status {
       using TBl = std::remove_const_t<std::remove_pointer_t<decltype(b)>>;
+      if (tiled(l)) {
+        ProbeExt pr(PR_TILE_DOWN, st, tile_down_bytes(l));
+        CKH((mg_tile_down<T, TBl>(g, (T *)s->lv[l].xs, b, s->lv[l + 1].g, (T *)s->lv[l + 1].b, c.mg_pre, st)));
+        return SIM_OK;
+      }
       {
         ProbeExt pr(PR_SMOOTH_FIRST, st, first_bytes(l, store_red));
         CKH((mg_smooth_first<T, TBl>(g, x, b, store_red, st)));
@@ -701,15 +755,22 @@ sim_status vcycle(sim_t s, const TV *v, T *z) {
     if (rc) return rc;
   }
   // ascend: prolongation onto the red cells, post-smoothing black then red
+  // (a tile level: both in one launch, from its pre-smoothed x)
   for (int l = lsub - 1; l >= 0; --l) {
     const Geo &g = s->lv[l].g;
     T *x = l == 0 ? z : (T *)s->lv[l].x;
-    {
-      ProbeExt pr(PR_PROLONG, st, prolong_bytes(l));
-      CKH(mg_prolong<T>(g, x, s->lv[l + 1].g, (const T *)s->lv[l + 1].x, st));
-    }
     auto post = [&](auto *b) -> sim_status {
       using TBl = std::remove_const_t<std::remove_pointer_t<decltype(b)>>;
+      if (tiled(l)) {
+        ProbeExt pr(PR_TILE_UP, st, tile_up_bytes(l));
+        CKH((mg_tile_up<T, TBl>(g, (const T *)s->lv[l].xs, x, b, s->lv[l + 1].g, (const T *)s->lv[l + 1].x,
+                                c.mg_post, st)));
+        return SIM_OK;
+      }
+      {
+        ProbeExt pr(PR_PROLONG, st, prolong_bytes(l));
+        CKH(mg_prolong<T>(g, x, s->lv[l + 1].g, (const T *)s->lv[l + 1].x, st));
+      }
       for (int q = 0; q < c.mg_post; ++q)
         for (int color = 1; color >= 0; --color) {
           ProbeExt pr(PR_SMOOTH, st, half_bytes(l));

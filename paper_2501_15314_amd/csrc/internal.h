@@ -13,7 +13,7 @@ namespace ibs {
 enum ProbeId {
   PR_SMOOTH = 0, PR_SMOOTH_FIRST, PR_RESTRICT, PR_PROLONG, PR_LAP, PR_BAND_DIV,
   PR_BAND_FACE, PR_INTERP_GRAD, PR_INTERP_FACE, PR_MULTIDOT, PR_UPDATE_NORM, PR_COARSE, PR_HELM_SWEEP,
-  PR_HELM_RESID, PR_VCYCLE, PR_MOM_RHS, PR_HELM_FIRST, PR_COUNT
+  PR_HELM_RESID, PR_VCYCLE, PR_MOM_RHS, PR_HELM_FIRST, PR_TILE_DOWN, PR_TILE_UP, PR_COUNT
 };
 struct ProbeState;  // per handle
 ProbeState *probe_new();
@@ -113,6 +113,16 @@ template <typename T, typename TB>
 hipError_t mg_restrict(const Geo &gf, const T *xf, const TB *bf, const Geo &gc, T *bc, hipStream_t s);
 template <typename T>
 hipError_t mg_prolong(const Geo &gf, T *xf, const Geo &gc, const T *xc, hipStream_t s);
+// tile levels: the descent of a level (pre sweeps from x = 0, x written, the
+// coarse right-hand side bc) and its ascent (xout = xin + P xc, then post
+// sweeps) in one launch each, for 8^3-divisible grids with gc = g / 2 and
+// 1 or 2 pre / post sweeps (tile_level_fits)
+bool tile_level_fits(const Geo &g, const Geo &gc, int pre, int post);
+template <typename T, typename TB>
+hipError_t mg_tile_down(const Geo &g, T *x, const TB *b, const Geo &gc, T *bc, int pre, hipStream_t s);
+template <typename T, typename TB>
+hipError_t mg_tile_up(const Geo &g, const T *xin, T *xout, const TB *b, const Geo &gc, const T *xc, int post,
+                      hipStream_t s);
 
 template <typename T, typename TB>
 hipError_t mg_coarse(const Geo &gc, const TB *b, T *x, int cycles, int sweeps, hipStream_t s);

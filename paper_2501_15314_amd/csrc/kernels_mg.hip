@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(256) k_restrict(Geo gf, const T *xf, const TB 
       const T sum = (u ? prev.y : prev.x) + (u ? next.y : next.x) + tile[ty * W2 + col] + tile[(ty + 2) * W2 + col] +
                     trow[col - 1 + s] + trow[col + s];
       const T xv = u ? xr.y : xr.x, bv = u ? br.y : br.x;
-      acc[u] += bv - ((T)cell_nnb(gf, i, j, k) * xv - sum) * ih2;
+      acc[u] += pc_resid(bv, xv, sum, cell_nnb(gf, i, j, k), ih2);
     }
     if (i & 1) {
       // plane pair done: add the partner row and write the coarse values
@@ -196,9 +196,9 @@ __global__ void __launch_bounds__(256) k_prolong(Geo gf, T *xf, Geo gc, const T 
 #pragma unroll
       for (int pl = 0; pl < 2; ++pl) {
         const T(*v)[4] = pl ? vhi : vlo;
-        const T zJ = (T)0.75 * v[0][qc] + (T)0.25 * v[0][qo];
-        const T zO = (T)0.75 * v[1][qc] + (T)0.25 * v[1][qo];
-        acc += (pl ? whi : wlo) * ((T)0.75 * zJ + (T)0.25 * zO);
+        const T zJ = blend34(v[0][qc], v[0][qo]);
+        const T zO = blend34(v[1][qc], v[1][qo]);
+        acc = fma(pl ? whi : wlo, blend34(zJ, zO), acc);
       }
       out[u] = acc;
     }
@@ -249,6 +249,330 @@ hipError_t mg_prolong(const Geo &gf, T *xf, const Geo &gc, const T *xc, hipStrea
   hipEvent_t e0, e1;
   probe_ext_take(&e0, &e1);
   hipExtLaunchKernelGGL(k_prolong<T>, M.grid, M.block, 0, s, e0, e1, 0, gf, xf, gc, xc);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Tile levels.  On the small levels of the cycle a launch costs more than the
+// work it carries (a few microseconds whatever the grid), and the march
+// kernels above spend seven launches per level.  A tile level takes two: one
+// workgroup per 8^3 tile loads its tile with a halo into LDS and runs the
+// tile's whole descent (pre-smoothing, residual, restriction: k_tile_down) or
+// whole ascent (prolongation, post-smoothing: k_tile_up), recomputing the
+// halo cells that neighbouring tiles own.  A half sweep is exact on a box one
+// cell smaller on every side than the box whose values it reads, so the box
+// shrinks by one cell per half sweep and a halo of two cells per sweep
+// suffices.  Every cell takes the operations of k_sweep, k_restrict and
+// k_prolong in the same order (pc_first, pc_relax, pc_resid, blend34), so a
+// tile level gives the bits of the march kernels.
+//
+// Region coordinates r in [0, R) of a tile at grid origin o with halo H stand
+// for the unwrapped grid coordinate u = o - H + r.  A wall axis has no cells
+// outside [0, n) (their LDS slots hold 0, which a neighbour sum then adds as
+// the missing neighbour); a periodic axis wraps.  Origins and halos are even
+// and n is even, so the colour of a cell is the parity of r0 + r1 + r2.
+constexpr int TL_TS = 8;  // tile edge in cells
+constexpr int TL_THREADS = 512;
+
+struct TileAxes {
+  int o[3], n[3], bc[3];
+  __device__ __forceinline__ bool inside(int a, int u) const { return !bc[a] || (u >= 0 && u < n[a]); }
+  // u within one period of the grid: [-n, 2n) (halos of at most n cells)
+  __device__ __forceinline__ int wrap(int a, int u) const {
+    return bc[a] ? u : (u < 0 ? u + n[a] : (u >= n[a] ? u - n[a] : u));
+  }
+  // neighbours that a wall removes along axis a
+  __device__ __forceinline__ int walls(int a, int u) const { return bc[a] ? (u == 0) + (u == n[a] - 1) : 0; }
+};
+// the tile of this workgroup on grid g (or the matching block of the coarse
+// grid gc, whose origin is half the fine one)
+__device__ __forceinline__ TileAxes tile_axes(const Geo &g, int scale) {
+  TileAxes t;
+  const int t1 = g.n1 / TL_TS, t2 = g.n2 / TL_TS, b = blockIdx.x;
+  const int tile[3] = {b / (t1 * t2), (b / t2) % t1, b % t2};
+  t.n[0] = g.n0 / scale; t.n[1] = g.n1 / scale; t.n[2] = g.n2 / scale;
+  t.bc[0] = g.bc0; t.bc[1] = g.bc1; t.bc[2] = g.bc2;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) t.o[a] = tile[a] * TL_TS / scale;
+  return t;
+}
+
+// A thread's share of the sweeps over an LDS region of edge R: half a row,
+// (r0, r1) = the row, cells r2 in [s0, s0 + R/2) (2 R^2 <= TL_THREADS threads
+// take part), with what the row's cells share: whether the row lies in the
+// grid, the neighbours its axes 0 and 1 leave (nn01) and its LDS base.  LDS
+// rows are R + 1 entries apart, so the rows that the lanes of a wavefront
+// work on fall in different banks.
+template <int R>
+struct TileRow {
+  static constexpr int SEG = R / 2;  // even: a segment starts on an even r2
+  int r0, r1, s0, u0, u1, nn01, qrow;
+  bool live;
+};
+template <int R>
+__device__ __forceinline__ TileRow<R> tile_row(const TileAxes &ax, int H) {
+  static_assert(2 * R * R <= TL_THREADS && (R / 2) % 2 == 0, "two threads per row, even segments");
+  TileRow<R> w;
+  const int tid = threadIdx.x, row = tid >> 1;
+  w.r0 = row / R;
+  w.r1 = row % R;
+  w.s0 = (tid & 1) * TileRow<R>::SEG;
+  w.u0 = ax.o[0] - H + w.r0;
+  w.u1 = ax.o[1] - H + w.r1;
+  w.live = row < R * R && ax.inside(0, w.u0) && ax.inside(1, w.u1);
+  w.nn01 = 6 - ax.walls(0, w.u0) - ax.walls(1, w.u1);
+  w.qrow = (w.r0 * R + w.r1) * (R + 1);
+  return w;
+}
+
+// one red-black half sweep of colour c over the cells of the box [LO, R-LO)^3
+// of an LDS region of edge R (x, b by region index)
+template <typename T, int R, int LO>
+__device__ __forceinline__ void tile_sweep(T *sx, const T *sb, const TileAxes &ax, const TileRow<R> &w, int H, int c,
+                                           T th2) {
+  if (w.live && w.r0 >= LO && w.r0 < R - LO && w.r1 >= LO && w.r1 < R - LO) {
+    const int p = (c + w.r0 + w.r1) & 1;
+#pragma unroll
+    for (int m = 0; m < R / 4; ++m) {
+      const int r2 = w.s0 + 2 * m + p, u2 = ax.o[2] - H + r2;
+      if (r2 < LO || r2 >= R - LO || !ax.inside(2, u2)) continue;
+      const int q = w.qrow + r2;
+      constexpr int DJ = R + 1, DI = R * (R + 1);
+      const T sum = sx[q - DI] + sx[q + DI] + sx[q - DJ] + sx[q + DJ] + sx[q - 1] + sx[q + 1];
+      sx[q] = pc_relax(th2, sb[q], sum, w.nn01 - ax.walls(2, u2));
+    }
+  }
+  __syncthreads();
+}
+
+// Descent of one tile: PRE red-black sweeps from x = 0 (red then black), x of
+// the tile's cells written, and the coarse right-hand side of the tile's
+// coarse cells: the average of the residuals of the four red children (the
+// black ones were relaxed last and have none).  The halo is 2 PRE: the first
+// red values need only their own b, every later half sweep shrinks the box.
+template <typename T, typename TB, int PRE>
+__global__ void __launch_bounds__(TL_THREADS) k_tile_down(Geo g, T *x, const TB *b, Geo gc, T *bc) {
+  constexpr int H = 2 * PRE, R = TL_TS + 2 * H, R3 = R * R * (R + 1);
+  constexpr int DJ = R + 1, DI = R * (R + 1);
+  constexpr int TC = TL_TS / 2;
+  __shared__ T sx[R3];
+  __shared__ T sb[R3];
+  const TileAxes ax = tile_axes(g, 1);
+  const TileRow<R> w = tile_row<R>(ax, H);
+  const int tid = threadIdx.x;
+  const T th2 = (T)g.h2, ih2 = (T)(1.0 / g.h2);
+  // b over the region in natural order (consecutive threads, consecutive
+  // cells of a row), every load of a thread issued before the first is used
+  // (a cell outside the grid loads element 0 and keeps 0); the red cells
+  // take their first-sweep values on the way
+  constexpr int NL = (R * R * R + TL_THREADS - 1) / TL_THREADS;
+  static_assert(NL <= 32, "one bit per slot");
+  TB bl[NL];
+  unsigned ok = 0;
+#pragma unroll
+  for (int t = 0; t < NL; ++t) {
+    const int e = tid + t * TL_THREADS;
+    const int r2 = e % R, r1 = (e / R) % R, r0 = e / (R * R);
+    const int u0 = ax.o[0] - H + r0, u1 = ax.o[1] - H + r1, u2 = ax.o[2] - H + r2;
+    const bool in = e < R * R * R && ax.inside(0, u0) && ax.inside(1, u1) && ax.inside(2, u2);
+    ok |= (unsigned)in << t;
+    bl[t] = b[in ? sidx(g, ax.wrap(0, u0), ax.wrap(1, u1), ax.wrap(2, u2)) : 0];
+  }
+#pragma unroll
+  for (int t = 0; t < NL; ++t) {
+    const int e = tid + t * TL_THREADS;
+    if (e < R * R * R) {
+      const int r2 = e % R, r1 = (e / R) % R, r0 = e / (R * R), q = (r0 * R + r1) * DJ + r2;
+      const bool in = (ok >> t) & 1u;
+      const T bv = in ? (T)bl[t] : T(0);
+      sb[q] = bv;
+      sx[q] = (in && !((r0 + r1 + r2) & 1))
+                  ? pc_first(th2, bv,
+                             6 - ax.walls(0, ax.o[0] - H + r0) - ax.walls(1, ax.o[1] - H + r1) -
+                                 ax.walls(2, ax.o[2] - H + r2))
+                  : T(0);
+    }
+  }
+  __syncthreads();
+  tile_sweep<T, R, 1>(sx, sb, ax, w, H, 1, th2);
+  if (PRE == 2) {
+    tile_sweep<T, R, 2>(sx, sb, ax, w, H, 0, th2);
+    tile_sweep<T, R, 3>(sx, sb, ax, w, H, 1, th2);
+  }
+  // the tile's cells, both colours
+  for (int e = tid; e < TL_TS * TL_TS * TL_TS; e += TL_THREADS) {
+    const int r2 = H + e % TL_TS, r1 = H + (e / TL_TS) % TL_TS, r0 = H + e / (TL_TS * TL_TS);
+    x[sidx(g, ax.o[0] - H + r0, ax.o[1] - H + r1, ax.o[2] - H + r2)] = sx[(r0 * R + r1) * (R + 1) + r2];
+  }
+  // coarse cell (C0, C1, C2) of the tile: the red child of fine row
+  // (2 C0 + di, 2 C1 + dj) sits at 2 C2 + ((di + dj) & 1); the residuals are
+  // added plane by plane per row, then the two rows, as k_restrict does
+  if (tid < TC * TC * TC) {
+    const int C2 = tid % TC, C1 = (tid / TC) % TC, C0 = tid / (TC * TC);
+    T acc[2];
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj) {
+      T a = T(0);
+#pragma unroll
+      for (int di = 0; di < 2; ++di) {
+        const int r0 = H + 2 * C0 + di, r1 = H + 2 * C1 + dj, r2 = H + 2 * C2 + ((di + dj) & 1);
+        const int q = (r0 * R + r1) * (R + 1) + r2;
+        const T sum = sx[q - DI] + sx[q + DI] + sx[q - DJ] + sx[q + DJ] + sx[q - 1] + sx[q + 1];
+        const int nn = 6 - ax.walls(0, ax.o[0] - H + r0) - ax.walls(1, ax.o[1] - H + r1) -
+                       ax.walls(2, ax.o[2] - H + r2);
+        a += pc_resid(sb[q], sx[q], sum, nn, ih2);
+      }
+      acc[dj] = a;
+    }
+    bc[sidx(gc, ax.o[0] / 2 + C0, ax.o[1] / 2 + C1, ax.o[2] / 2 + C2)] = (acc[0] + acc[1]) * (T)0.125;
+  }
+}
+
+// Ascent of one tile: x = xin + P x_c on the red cells (trilinear
+// cell-centred, as k_prolong: per axis 3/4 on the parent, 1/4 on the
+// parent's neighbour on the child's side, the parent itself past a wall),
+// then POST sweeps black then red, and the tile's cells written to xout.
+// xout is not xin: neighbouring tiles still read the halo's old values.  The
+// halo is 2 POST; the coarse block spans the parents and their neighbours of
+// the whole region.
+template <typename T, typename TB, int POST>
+__global__ void __launch_bounds__(TL_THREADS) k_tile_up(Geo g, const T *xin, T *xout, const TB *b, Geo gc,
+                                                            const T *xc) {
+  constexpr int H = 2 * POST, R = TL_TS + 2 * H, R3 = R * R * (R + 1), DJ = R + 1;
+  constexpr int HC = H / 2 + 1, RC = TL_TS / 2 + 2 * HC, RC3 = RC * RC * RC;
+  __shared__ T sx[R3];
+  __shared__ T sb[R3];
+  __shared__ T sc[RC3];
+  const TileAxes ax = tile_axes(g, 1), cx = tile_axes(g, 2);
+  const TileRow<R> w = tile_row<R>(ax, H);
+  const int tid = threadIdx.x;
+  const T th2 = (T)g.h2;
+  // the coarse block, then b and the red x of the region in natural order,
+  // every load of a thread issued before the first is used (slots outside
+  // the grid load element 0 and keep 0; black x values are overwritten
+  // unread)
+  constexpr int NC = (RC3 + TL_THREADS - 1) / TL_THREADS, NL = (R * R * R + TL_THREADS - 1) / TL_THREADS;
+  static_assert(NC <= 32 && NL <= 32, "one bit per slot");
+  T cl[NC];
+  TB bl[NL];
+  T xl[NL];
+  unsigned okc = 0, ok = 0;
+#pragma unroll
+  for (int t = 0; t < NC; ++t) {
+    const int e = tid + t * TL_THREADS;
+    const int c2 = e % RC, c1 = (e / RC) % RC, c0 = e / (RC * RC);
+    const int U0 = cx.o[0] - HC + c0, U1 = cx.o[1] - HC + c1, U2 = cx.o[2] - HC + c2;
+    const bool in = e < RC3 && cx.inside(0, U0) && cx.inside(1, U1) && cx.inside(2, U2);
+    okc |= (unsigned)in << t;
+    cl[t] = xc[in ? sidx(gc, cx.wrap(0, U0), cx.wrap(1, U1), cx.wrap(2, U2)) : 0];
+  }
+#pragma unroll
+  for (int t = 0; t < NL; ++t) {
+    const int e = tid + t * TL_THREADS;
+    const int r2 = e % R, r1 = (e / R) % R, r0 = e / (R * R);
+    const int u0 = ax.o[0] - H + r0, u1 = ax.o[1] - H + r1, u2 = ax.o[2] - H + r2;
+    const bool in = e < R * R * R && ax.inside(0, u0) && ax.inside(1, u1) && ax.inside(2, u2);
+    ok |= (unsigned)in << t;
+    const long long q = in ? sidx(g, ax.wrap(0, u0), ax.wrap(1, u1), ax.wrap(2, u2)) : 0;
+    bl[t] = b[q];
+    xl[t] = xin[(in && !((r0 + r1 + r2) & 1)) ? q : 0];
+  }
+#pragma unroll
+  for (int t = 0; t < NC; ++t) {
+    const int e = tid + t * TL_THREADS;
+    if (e < RC3) sc[e] = ((okc >> t) & 1u) ? cl[t] : T(0);
+  }
+#pragma unroll
+  for (int t = 0; t < NL; ++t) {
+    const int e = tid + t * TL_THREADS;
+    if (e < R * R * R) {
+      const int r2 = e % R, r1 = (e / R) % R, r0 = e / (R * R), q = (r0 * R + r1) * DJ + r2;
+      const bool in = (ok >> t) & 1u;
+      sb[q] = in ? (T)bl[t] : T(0);
+      sx[q] = (in && !((r0 + r1 + r2) & 1)) ? xl[t] : T(0);
+    }
+  }
+  __syncthreads();
+  // prolongation onto the red cells of the thread's half row: the planes
+  // (u0 - 1) >> 1 and the next with weights by the parity of u0, and the
+  // coarse rows J, Jo are the row's; per cell the coarse K and Ko
+  if (w.live) {
+    auto other = [&](int a, int P, int odd) {
+      const int O = P + (odd ? 1 : -1);
+      return (cx.bc[a] && (O < 0 || O >= cx.n[a])) ? P : O;
+    };
+    int lo = (w.u0 - 1) >> 1, hi = lo + 1;
+    if (cx.bc[0]) {
+      lo = lo < 0 ? 0 : lo;
+      hi = hi >= cx.n[0] ? cx.n[0] - 1 : hi;
+    }
+    const int J = w.u1 >> 1, Jo = other(1, J, w.u1 & 1);
+    const int b0 = cx.o[0] - HC, b1 = cx.o[1] - HC, b2 = cx.o[2] - HC;
+    const T wlo = (w.u0 & 1) ? (T)0.75 : (T)0.25, whi = (T)1 - wlo;
+    const int plo = ((lo - b0) * RC + (J - b1)) * RC - b2, plo_o = ((lo - b0) * RC + (Jo - b1)) * RC - b2;
+    const int phi = ((hi - b0) * RC + (J - b1)) * RC - b2, phi_o = ((hi - b0) * RC + (Jo - b1)) * RC - b2;
+    const int p = (w.r0 + w.r1) & 1;
+#pragma unroll
+    for (int m = 0; m < R / 4; ++m) {
+      const int r2 = w.s0 + 2 * m + p, u2 = ax.o[2] - H + r2;
+      if (!ax.inside(2, u2)) continue;
+      const int K = u2 >> 1, Ko = other(2, K, u2 & 1);
+      T acc = T(0);
+#pragma unroll
+      for (int pl = 0; pl < 2; ++pl) {
+        const int pJ = pl ? phi : plo, pO = pl ? phi_o : plo_o;
+        const T zJ = blend34(sc[pJ + K], sc[pJ + Ko]);
+        const T zO = blend34(sc[pO + K], sc[pO + Ko]);
+        acc = fma(pl ? whi : wlo, blend34(zJ, zO), acc);
+      }
+      const int q = w.qrow + r2;
+      sx[q] = sx[q] + acc;
+    }
+  }
+  __syncthreads();
+  tile_sweep<T, R, 1>(sx, sb, ax, w, H, 1, th2);
+  tile_sweep<T, R, 2>(sx, sb, ax, w, H, 0, th2);
+  if (POST == 2) {
+    tile_sweep<T, R, 3>(sx, sb, ax, w, H, 1, th2);
+    tile_sweep<T, R, 4>(sx, sb, ax, w, H, 0, th2);
+  }
+  for (int e = tid; e < TL_TS * TL_TS * TL_TS; e += TL_THREADS) {
+    const int r2 = H + e % TL_TS, r1 = H + (e / TL_TS) % TL_TS, r0 = H + e / (TL_TS * TL_TS);
+    xout[sidx(g, ax.o[0] - H + r0, ax.o[1] - H + r1, ax.o[2] - H + r2)] = sx[(r0 * R + r1) * (R + 1) + r2];
+  }
+}
+
+bool tile_level_fits(const Geo &g, const Geo &gc, int pre, int post) {
+  return g.n0 % TL_TS == 0 && g.n1 % TL_TS == 0 && g.n2 % TL_TS == 0 && gc.n0 * 2 == g.n0 &&
+         gc.n1 * 2 == g.n1 && gc.n2 * 2 == g.n2 && (pre == 1 || pre == 2) && (post == 1 || post == 2);
+}
+static unsigned tile_count(const Geo &g) { return (unsigned)((g.n0 / TL_TS) * (g.n1 / TL_TS) * (g.n2 / TL_TS)); }
+
+template <typename T, typename TB>
+hipError_t mg_tile_down(const Geo &g, T *x, const TB *b, const Geo &gc, T *bc, int pre, hipStream_t s) {
+  if (!tile_level_fits(g, gc, pre, 1)) return hipErrorInvalidValue;
+  hipEvent_t e0, e1;
+  probe_ext_take(&e0, &e1);
+  if (pre == 2)
+    hipExtLaunchKernelGGL((k_tile_down<T, TB, 2>), dim3(tile_count(g)), dim3(TL_THREADS), 0, s, e0, e1, 0, g, x, b,
+                          gc, bc);
+  else
+    hipExtLaunchKernelGGL((k_tile_down<T, TB, 1>), dim3(tile_count(g)), dim3(TL_THREADS), 0, s, e0, e1, 0, g, x, b,
+                          gc, bc);
+  return hipGetLastError();
+}
+template <typename T, typename TB>
+hipError_t mg_tile_up(const Geo &g, const T *xin, T *xout, const TB *b, const Geo &gc, const T *xc, int post,
+                      hipStream_t s) {
+  if (!tile_level_fits(g, gc, 1, post) || xin == xout) return hipErrorInvalidValue;
+  hipEvent_t e0, e1;
+  probe_ext_take(&e0, &e1);
+  if (post == 2)
+    hipExtLaunchKernelGGL((k_tile_up<T, TB, 2>), dim3(tile_count(g)), dim3(TL_THREADS), 0, s, e0, e1, 0, g, xin, xout,
+                          b, gc, xc);
+  else
+    hipExtLaunchKernelGGL((k_tile_up<T, TB, 1>), dim3(tile_count(g)), dim3(TL_THREADS), 0, s, e0, e1, 0, g, xin, xout,
+                          b, gc, xc);
   return hipGetLastError();
 }
 
@@ -894,7 +1218,10 @@ void coarse_fd_build(const int n[3], const int bc[3], double h, double *out) {
   template hipError_t mg_coarse<T, TB>(const Geo &, const TB *, T *, int, int, hipStream_t);                   \
   template hipError_t mg_coarse_fd<T, TB>(const Geo &, const TB *, T *, const double *, hipStream_t);   \
   template hipError_t mg_subcycle<T, TB>(const Geo &, const Geo &, const TB *, T *, const double *, int, int, \
-                                         hipStream_t);
+                                         hipStream_t);  \
+  template hipError_t mg_tile_down<T, TB>(const Geo &, T *, const TB *, const Geo &, T *, int, hipStream_t);   \
+  template hipError_t mg_tile_up<T, TB>(const Geo &, const T *, T *, const TB *, const Geo &, const T *, int, \
+                                        hipStream_t);
 INST(float, float)
 INST(float, double)
 INST(double, double)

@@ -399,7 +399,7 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, T *x, const TB *b, int col
   // into the colour-0 value once the current plane has been computed.
   auto oxf = [&](int i, int jj, int mm, T bv) -> T {
     const int kk = 2 * mm + ((i + jj) & 1);  // colour-0 cell of row (i, jj) at index mm
-    if (MODE == SW_FIRST || MODE == SW_FIRST1) return th2 * bv * inv_nn<T>(cell_nnb(g, i, jj, kk));
+    if (MODE == SW_FIRST || MODE == SW_FIRST1) return pc_first(th2, bv, cell_nnb(g, i, jj, kk));
     bool wall;
     const int dg = helm_cell(i, jj, kk, wall);
     return wall ? T(0) : tom * (bv / (ta0 + tnu * (T)dg));
@@ -490,7 +490,7 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, T *x, const TB *b, int col
               trow[col - 1 + s] + trow[col + s];
       T bv = u ? bb.y : bb.x;
       if (!HELMM) {
-        out[u] = (th2 * bv + sum) * inv_nn<T>(6 - di - djk.dg(s, u));
+        out[u] = pc_relax(th2, bv, sum, 6 - di - djk.dg(s, u));
       } else {
         const int diag = di + djk.dg(s, u);
         const bool wall = d == 0 ? (g.bc0 && i == 0) : djk.wl(s, u);

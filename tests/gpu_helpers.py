@@ -187,6 +187,24 @@ def march_chunks(mode: str):
             os.environ["IBSCHUR_MARCH_FULL_CHUNKS"] = old
 
 
+@contextlib.contextmanager
+def mg_tile_cells(cells):
+    """Environment for sim_create: multigrid levels of at most `cells` cells
+    run as tile levels (0: none; None: the library's default)."""
+    old = os.environ.get("IBSCHUR_MG_TILE_CELLS")
+    if cells is None:
+        os.environ.pop("IBSCHUR_MG_TILE_CELLS", None)
+    else:
+        os.environ["IBSCHUR_MG_TILE_CELLS"] = str(int(cells))
+    try:
+        yield
+    finally:
+        if old is None:
+            os.environ.pop("IBSCHUR_MG_TILE_CELLS", None)
+        else:
+            os.environ["IBSCHUR_MG_TILE_CELLS"] = old
+
+
 def make_sim(cfg, max_points, chunks: str = "auto"):
     """A Sim created under the given plane-march chunking."""
     from paper_2501_15314_amd.sim import Sim

@@ -7,8 +7,8 @@ from oracle import mac as omac
 from paper_2501_15314_amd import workloads as wl
 
 from .conftest import gpu_available
-from .gpu_helpers import (CHUNKS, freeslip_workload, make_sim, mixed_workload, odd_tiles_workload, oracle_for, rel,
-                          walls_workload, wrap16_workload)
+from .gpu_helpers import (CHUNKS, freeslip_workload, make_sim, mg_tile_cells, mixed_workload, odd_tiles_workload,
+                          oracle_for, rel, walls_workload, wrap16_workload)
 
 pytestmark = pytest.mark.gpu
 
@@ -157,6 +157,51 @@ def test_full_chunks_give_the_same_operators(case, prec):
                           outs["full"]):
         print(f"  {case} prec {prec} {name}: max |auto - full| = {np.abs(a - c).max():.1e}", flush=True)
         assert np.array_equal(a, c), name
+
+
+@pytest.mark.parametrize("prec", [wl.PREC_FP64, wl.PREC_FP32MG])
+@pytest.mark.parametrize("case", ["c1_periodic", "walls", "mixed", "freeslip", "walls64", "periodic64_v22",
+                                  "freeslip64_v11"])
+def test_tile_levels_give_the_same_bits(case, prec):
+    """Tile levels (a level's pre-smoothing, residual and restriction in one
+    launch, its prolongation and post-smoothing in another, each 8^3 tile
+    recomputing its halo) give every cell the operations of the march
+    kernels in the same order: the V-cycle and a whole Schur solve agree to
+    the last bit with the tile levels switched off.  The 64^3 cases tile two
+    levels (64^3 and 32^3 above the 16^3 + 8^3 subcycle); V(2,2) and V(1,1)
+    take the other halo widths."""
+    cases = dict(_cases())
+    cases["walls64"] = lambda: walls_workload(64, 260)
+    cases["periodic64_v22"] = lambda: wl.make_c1(n=64, n_points=300)
+    cases["freeslip64_v11"] = lambda: freeslip_workload(64, 260)
+    w = cases[case]()
+    w.cfg.precision = prec
+    w.cfg.krylov_rtol = 1e-10
+    if case == "periodic64_v22":
+        w.cfg.mg_pre, w.cfg.mg_post = 2, 2
+    if case == "freeslip64_v11":
+        w.cfg.mg_pre, w.cfg.mg_post = 1, 1
+    g = omac.Grid(w.cfg.n, w.cfg.h, w.cfg.bc)
+    b = _rand(31, g.n)
+    b -= b.mean()
+    rp, rf = wl.random_schur_rhs(32, w.cfg.n, w.n_points)
+    outs = {}
+    for cells in (0, 1 << 40):
+        with mg_tile_cells(cells):
+            sim = Sim(w.cfg, w.n_points)
+        sim.set_bodies(w.bodies, w.offsets)
+        sim.probe("tile_down")
+        z = sim.apply("precond", b).cpu().numpy()
+        p, f, st = sim.solve_schur(rp, rf)
+        ntile = sim.probe_read("tile_down")[0]
+        outs[cells] = (z, p.cpu().numpy(), f.cpu().numpy(), st.iters, ntile)
+        sim.close()
+    (z0, p0, f0, it0, n0), (z1, p1, f1, it1, n1) = outs[0], outs[1 << 40]
+    print(f"  {case} prec {prec}: tile launches {n0} / {n1}, iterations {it0} / {it1}, "
+          f"max |dz| {np.abs(z1 - z0).max():.1e}, |dp| {np.abs(p1 - p0).max():.1e}", flush=True)
+    assert n0 == 0 and n1 > 0
+    assert np.array_equal(z0, z1)
+    assert it0 == it1 and np.array_equal(p0, p1) and np.array_equal(f0, f1)
 
 
 def test_vcycle_contracts(setup):
