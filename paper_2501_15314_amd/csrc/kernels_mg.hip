@@ -276,13 +276,16 @@ constexpr int TL_THREADS = 512;
 
 struct TileAxes {
   int o[3], n[3], bc[3];
-  __device__ __forceinline__ bool inside(int a, int u) const { return !bc[a] || (u >= 0 && u < n[a]); }
-  // u within one period of the grid: [-n, 2n) (halos of at most n cells)
+  __device__ __forceinline__ bool inside(int a, int u) const { return (unsigned)u < (unsigned)n[a] || !bc[a]; }
+  // the grid coordinate of u within one period of it, [-n, 2n) (halos of at
+  // most n cells); a coordinate inside a wall box is its own
   __device__ __forceinline__ int wrap(int a, int u) const {
-    return bc[a] ? u : (u < 0 ? u + n[a] : (u >= n[a] ? u - n[a] : u));
+    return u + (u < 0 ? n[a] : 0) - (u >= n[a] ? n[a] : 0);
   }
   // neighbours that a wall removes along axis a
-  __device__ __forceinline__ int walls(int a, int u) const { return bc[a] ? (u == 0) + (u == n[a] - 1) : 0; }
+  __device__ __forceinline__ int walls(int a, int u) const {
+    return (bc[a] != 0) * ((u == 0) + (u == n[a] - 1));
+  }
 };
 // the tile of this workgroup on grid g (or the matching block of the coarse
 // grid gc, whose origin is half the fine one)
@@ -325,6 +328,47 @@ __device__ __forceinline__ TileRow<R> tile_row(const TileAxes &ax, int H) {
   return w;
 }
 
+// The loads of a region of edge R: a tile kernel runs KP = TL_THREADS / R^2
+// threads per column (r1, r2) of the region, thread tid taking planes
+// r0 = tid / R^2 + KP m, so that everything but the plane is fixed per
+// thread and consecutive threads read consecutive cells of a row.
+template <int R>
+struct TileCols {
+  static constexpr int KP = TL_THREADS / (R * R);
+  static constexpr int NT = KP * R * R;  // threads of the launch
+  static constexpr int NL = R / KP;      // planes per thread
+  static_assert(KP >= 2 && R % KP == 0 && NL <= 32, "whole columns, two threads per sweep row, one bit per plane");
+};
+__host__ __device__ constexpr int tile_threads(int R) { return (TL_THREADS / (R * R)) * R * R; }
+// a thread's column: its region and grid coordinates along axes 1 and 2
+struct TileCol {
+  int r1, r2, rb, u1, u2, par, w12, plane;
+  bool in12;
+  long long base0, base1;  // split-layout offset of the column in plane 0, per colour of its cell there
+};
+template <int R>
+__device__ __forceinline__ TileCol tile_col(const Geo &g, const TileAxes &ax, int H) {
+  TileCol c;
+  const int tid = threadIdx.x;
+  c.r2 = tid % R;
+  c.r1 = (tid / R) % R;
+  c.rb = tid / (R * R);
+  c.u1 = ax.o[1] - H + c.r1;
+  c.u2 = ax.o[2] - H + c.r2;
+  c.in12 = ax.inside(1, c.u1) && ax.inside(2, c.u2);
+  const int gj = ax.wrap(1, c.u1), gk = ax.wrap(2, c.u2);
+  c.par = (gj + gk) & 1;
+  c.w12 = ax.walls(1, c.u1) + ax.walls(2, c.u2);
+  c.plane = g.n1 * g.hn2;
+  c.base0 = gj * g.hn2 + (gk >> 1);
+  c.base1 = c.base0 + g.half;
+  return c;
+}
+// split-layout index of the cell of column c in grid plane gi
+__device__ __forceinline__ long long tile_cidx(const TileCol &c, int gi) {
+  return (((gi + c.par) & 1) ? c.base1 : c.base0) + gi * c.plane;
+}
+
 // one red-black half sweep of colour c over the cells of the box [LO, R-LO)^3
 // of an LDS region of edge R (x, b by region index)
 template <typename T, int R, int LO>
@@ -361,36 +405,29 @@ __global__ void __launch_bounds__(TL_THREADS) k_tile_down(Geo g, T *x, const TB 
   const TileRow<R> w = tile_row<R>(ax, H);
   const int tid = threadIdx.x;
   const T th2 = (T)g.h2, ih2 = (T)(1.0 / g.h2);
-  // b over the region in natural order (consecutive threads, consecutive
-  // cells of a row), every load of a thread issued before the first is used
-  // (a cell outside the grid loads element 0 and keeps 0); the red cells
-  // take their first-sweep values on the way
-  constexpr int NL = (R * R * R + TL_THREADS - 1) / TL_THREADS;
-  static_assert(NL <= 32, "one bit per slot");
-  TB bl[NL];
-  unsigned ok = 0;
+  // b over the region, column by column (every load of a thread issued
+  // before the first is used; a cell outside the grid loads element 0 and
+  // keeps 0); the red cells take their first-sweep values on the way
+  using CL = TileCols<R>;
+  {
+    const TileCol c = tile_col<R>(g, ax, H);
+    TB bl[CL::NL];
+    unsigned ok = 0;
 #pragma unroll
-  for (int t = 0; t < NL; ++t) {
-    const int e = tid + t * TL_THREADS;
-    const int r2 = e % R, r1 = (e / R) % R, r0 = e / (R * R);
-    const int u0 = ax.o[0] - H + r0, u1 = ax.o[1] - H + r1, u2 = ax.o[2] - H + r2;
-    const bool in = e < R * R * R && ax.inside(0, u0) && ax.inside(1, u1) && ax.inside(2, u2);
-    ok |= (unsigned)in << t;
-    bl[t] = b[in ? sidx(g, ax.wrap(0, u0), ax.wrap(1, u1), ax.wrap(2, u2)) : 0];
-  }
+    for (int m = 0; m < CL::NL; ++m) {
+      const int u0 = ax.o[0] - H + c.rb + CL::KP * m;
+      const bool in = c.in12 && ax.inside(0, u0);
+      ok |= (unsigned)in << m;
+      bl[m] = b[in ? tile_cidx(c, ax.wrap(0, u0)) : 0];
+    }
 #pragma unroll
-  for (int t = 0; t < NL; ++t) {
-    const int e = tid + t * TL_THREADS;
-    if (e < R * R * R) {
-      const int r2 = e % R, r1 = (e / R) % R, r0 = e / (R * R), q = (r0 * R + r1) * DJ + r2;
-      const bool in = (ok >> t) & 1u;
-      const T bv = in ? (T)bl[t] : T(0);
+    for (int m = 0; m < CL::NL; ++m) {
+      const int r0 = c.rb + CL::KP * m, q = (r0 * R + c.r1) * DJ + c.r2;
+      const bool in = (ok >> m) & 1u;
+      const T bv = in ? (T)bl[m] : T(0);
       sb[q] = bv;
-      sx[q] = (in && !((r0 + r1 + r2) & 1))
-                  ? pc_first(th2, bv,
-                             6 - ax.walls(0, ax.o[0] - H + r0) - ax.walls(1, ax.o[1] - H + r1) -
-                                 ax.walls(2, ax.o[2] - H + r2))
-                  : T(0);
+      sx[q] = (in && !((r0 + c.r1 + c.r2) & 1)) ? pc_first(th2, bv, 6 - ax.walls(0, ax.o[0] - H + r0) - c.w12)
+                                                : T(0);
     }
   }
   __syncthreads();
@@ -400,7 +437,7 @@ __global__ void __launch_bounds__(TL_THREADS) k_tile_down(Geo g, T *x, const TB 
     tile_sweep<T, R, 3>(sx, sb, ax, w, H, 1, th2);
   }
   // the tile's cells, both colours
-  for (int e = tid; e < TL_TS * TL_TS * TL_TS; e += TL_THREADS) {
+  for (int e = tid; e < TL_TS * TL_TS * TL_TS; e += CL::NT) {
     const int r2 = H + e % TL_TS, r1 = H + (e / TL_TS) % TL_TS, r0 = H + e / (TL_TS * TL_TS);
     x[sidx(g, ax.o[0] - H + r0, ax.o[1] - H + r1, ax.o[2] - H + r2)] = sx[(r0 * R + r1) * (R + 1) + r2];
   }
@@ -447,49 +484,49 @@ __global__ void __launch_bounds__(TL_THREADS) k_tile_up(Geo g, const T *xin, T *
   const TileRow<R> w = tile_row<R>(ax, H);
   const int tid = threadIdx.x;
   const T th2 = (T)g.h2;
-  // the coarse block, then b and the red x of the region in natural order,
+  // the coarse block, then b and the red x of the region column by column,
   // every load of a thread issued before the first is used (slots outside
   // the grid load element 0 and keep 0; black x values are overwritten
   // unread)
-  constexpr int NC = (RC3 + TL_THREADS - 1) / TL_THREADS, NL = (R * R * R + TL_THREADS - 1) / TL_THREADS;
-  static_assert(NC <= 32 && NL <= 32, "one bit per slot");
-  T cl[NC];
-  TB bl[NL];
-  T xl[NL];
-  unsigned okc = 0, ok = 0;
+  using CL = TileCols<R>;
+  constexpr int NC = (RC3 + CL::NT - 1) / CL::NT;
+  static_assert(NC <= 32, "one bit per slot");
+  {
+    T cl[NC];
+    unsigned okc = 0;
 #pragma unroll
-  for (int t = 0; t < NC; ++t) {
-    const int e = tid + t * TL_THREADS;
-    const int c2 = e % RC, c1 = (e / RC) % RC, c0 = e / (RC * RC);
-    const int U0 = cx.o[0] - HC + c0, U1 = cx.o[1] - HC + c1, U2 = cx.o[2] - HC + c2;
-    const bool in = e < RC3 && cx.inside(0, U0) && cx.inside(1, U1) && cx.inside(2, U2);
-    okc |= (unsigned)in << t;
-    cl[t] = xc[in ? sidx(gc, cx.wrap(0, U0), cx.wrap(1, U1), cx.wrap(2, U2)) : 0];
-  }
+    for (int t = 0; t < NC; ++t) {
+      const int e = tid + t * CL::NT;
+      const int c2 = e % RC, c1 = (e / RC) % RC, c0 = e / (RC * RC);
+      const int U0 = cx.o[0] - HC + c0, U1 = cx.o[1] - HC + c1, U2 = cx.o[2] - HC + c2;
+      const bool in = e < RC3 && cx.inside(0, U0) && cx.inside(1, U1) && cx.inside(2, U2);
+      okc |= (unsigned)in << t;
+      cl[t] = xc[in ? sidx(gc, cx.wrap(0, U0), cx.wrap(1, U1), cx.wrap(2, U2)) : 0];
+    }
+    const TileCol c = tile_col<R>(g, ax, H);
+    TB bl[CL::NL];
+    T xl[CL::NL];
+    unsigned ok = 0;
 #pragma unroll
-  for (int t = 0; t < NL; ++t) {
-    const int e = tid + t * TL_THREADS;
-    const int r2 = e % R, r1 = (e / R) % R, r0 = e / (R * R);
-    const int u0 = ax.o[0] - H + r0, u1 = ax.o[1] - H + r1, u2 = ax.o[2] - H + r2;
-    const bool in = e < R * R * R && ax.inside(0, u0) && ax.inside(1, u1) && ax.inside(2, u2);
-    ok |= (unsigned)in << t;
-    const long long q = in ? sidx(g, ax.wrap(0, u0), ax.wrap(1, u1), ax.wrap(2, u2)) : 0;
-    bl[t] = b[q];
-    xl[t] = xin[(in && !((r0 + r1 + r2) & 1)) ? q : 0];
-  }
+    for (int m = 0; m < CL::NL; ++m) {
+      const int r0 = c.rb + CL::KP * m, u0 = ax.o[0] - H + r0;
+      const bool in = c.in12 && ax.inside(0, u0);
+      ok |= (unsigned)in << m;
+      const long long q = in ? tile_cidx(c, ax.wrap(0, u0)) : 0;
+      bl[m] = b[q];
+      xl[m] = xin[(in && !((r0 + c.r1 + c.r2) & 1)) ? q : 0];
+    }
 #pragma unroll
-  for (int t = 0; t < NC; ++t) {
-    const int e = tid + t * TL_THREADS;
-    if (e < RC3) sc[e] = ((okc >> t) & 1u) ? cl[t] : T(0);
-  }
+    for (int t = 0; t < NC; ++t) {
+      const int e = tid + t * CL::NT;
+      if (e < RC3) sc[e] = ((okc >> t) & 1u) ? cl[t] : T(0);
+    }
 #pragma unroll
-  for (int t = 0; t < NL; ++t) {
-    const int e = tid + t * TL_THREADS;
-    if (e < R * R * R) {
-      const int r2 = e % R, r1 = (e / R) % R, r0 = e / (R * R), q = (r0 * R + r1) * DJ + r2;
-      const bool in = (ok >> t) & 1u;
-      sb[q] = in ? (T)bl[t] : T(0);
-      sx[q] = (in && !((r0 + r1 + r2) & 1)) ? xl[t] : T(0);
+    for (int m = 0; m < CL::NL; ++m) {
+      const int r0 = c.rb + CL::KP * m, q = (r0 * R + c.r1) * DJ + c.r2;
+      const bool in = (ok >> m) & 1u;
+      sb[q] = in ? (T)bl[m] : T(0);
+      sx[q] = (in && !((r0 + c.r1 + c.r2) & 1)) ? xl[m] : T(0);
     }
   }
   __syncthreads();
@@ -536,7 +573,7 @@ __global__ void __launch_bounds__(TL_THREADS) k_tile_up(Geo g, const T *xin, T *
     tile_sweep<T, R, 3>(sx, sb, ax, w, H, 1, th2);
     tile_sweep<T, R, 4>(sx, sb, ax, w, H, 0, th2);
   }
-  for (int e = tid; e < TL_TS * TL_TS * TL_TS; e += TL_THREADS) {
+  for (int e = tid; e < TL_TS * TL_TS * TL_TS; e += CL::NT) {
     const int r2 = H + e % TL_TS, r1 = H + (e / TL_TS) % TL_TS, r0 = H + e / (TL_TS * TL_TS);
     xout[sidx(g, ax.o[0] - H + r0, ax.o[1] - H + r1, ax.o[2] - H + r2)] = sx[(r0 * R + r1) * (R + 1) + r2];
   }
@@ -554,11 +591,11 @@ hipError_t mg_tile_down(const Geo &g, T *x, const TB *b, const Geo &gc, T *bc, i
   hipEvent_t e0, e1;
   probe_ext_take(&e0, &e1);
   if (pre == 2)
-    hipExtLaunchKernelGGL((k_tile_down<T, TB, 2>), dim3(tile_count(g)), dim3(TL_THREADS), 0, s, e0, e1, 0, g, x, b,
-                          gc, bc);
+    hipExtLaunchKernelGGL((k_tile_down<T, TB, 2>), dim3(tile_count(g)), dim3(tile_threads(TL_TS + 8)), 0, s, e0,
+                          e1, 0, g, x, b, gc, bc);
   else
-    hipExtLaunchKernelGGL((k_tile_down<T, TB, 1>), dim3(tile_count(g)), dim3(TL_THREADS), 0, s, e0, e1, 0, g, x, b,
-                          gc, bc);
+    hipExtLaunchKernelGGL((k_tile_down<T, TB, 1>), dim3(tile_count(g)), dim3(tile_threads(TL_TS + 4)), 0, s, e0,
+                          e1, 0, g, x, b, gc, bc);
   return hipGetLastError();
 }
 template <typename T, typename TB>
@@ -568,11 +605,11 @@ hipError_t mg_tile_up(const Geo &g, const T *xin, T *xout, const TB *b, const Ge
   hipEvent_t e0, e1;
   probe_ext_take(&e0, &e1);
   if (post == 2)
-    hipExtLaunchKernelGGL((k_tile_up<T, TB, 2>), dim3(tile_count(g)), dim3(TL_THREADS), 0, s, e0, e1, 0, g, xin, xout,
-                          b, gc, xc);
+    hipExtLaunchKernelGGL((k_tile_up<T, TB, 2>), dim3(tile_count(g)), dim3(tile_threads(TL_TS + 8)), 0, s, e0,
+                          e1, 0, g, xin, xout, b, gc, xc);
   else
-    hipExtLaunchKernelGGL((k_tile_up<T, TB, 1>), dim3(tile_count(g)), dim3(TL_THREADS), 0, s, e0, e1, 0, g, xin, xout,
-                          b, gc, xc);
+    hipExtLaunchKernelGGL((k_tile_up<T, TB, 1>), dim3(tile_count(g)), dim3(tile_threads(TL_TS + 4)), 0, s, e0,
+                          e1, 0, g, xin, xout, b, gc, xc);
   return hipGetLastError();
 }
 
