@@ -375,13 +375,16 @@ sim_status sim_schur_spectrum(sim_t sim, int32_t exact, const double *d_v0, int3
  * kernels are launched).  sim_probe_read returns the number of probed
  * launches, their summed device time in milliseconds (waiting for the
  * events) and, if bytes is not NULL, their summed algorithmic bytes; with
- * reset != 0 it clears them.  Probe state belongs to the handle.  The
- * multigrid classes cover every level. */
+ * reset != 0 it clears them.  Probe state belongs to the handle.  A
+ * multigrid level runs either the plane-march kernels (the first five
+ * classes) or, at most 64^3 cells by default, the two tile kernels
+ * (IBSCHUR_MG_TILE_CELLS in the environment at sim_create sets that bound;
+ * 0: no tile levels). */
 enum {
-  SIM_PROBE_SMOOTH = 0,             /* red-black Gauss-Seidel half sweep, all levels */
-  SIM_PROBE_SMOOTH_FIRST = 1,       /* first sweep from zero, all levels */
-  SIM_PROBE_RESTRICT = 2,           /* residual + restriction, all levels */
-  SIM_PROBE_PROLONG = 3,            /* prolongation + correction, all levels */
+  SIM_PROBE_SMOOTH = 0,             /* red-black Gauss-Seidel half sweep, plane-march levels */
+  SIM_PROBE_SMOOTH_FIRST = 1,       /* first sweep from zero, plane-march levels */
+  SIM_PROBE_RESTRICT = 2,           /* residual + restriction, plane-march levels */
+  SIM_PROBE_PROLONG = 3,            /* prolongation + correction, plane-march levels */
   SIM_PROBE_LAPLACIAN = 4,          /* L z inside the S~ product */
   SIM_PROBE_SPREAD_DIV = 5,         /* D W q on the active tiles */
   SIM_PROBE_SPREAD_FACE = 6,        /* W q on the active tiles */
