@@ -197,11 +197,11 @@ int march_min_blocks_setting() {
 
 // Multigrid levels of at most this many cells run as tile levels (two
 // launches per level instead of seven: k_tile_down, k_tile_up).  On a 256^3
-// grid that is the 64^3 and 32^3 levels, about 8.9 + 6.8 us per level
-// against seven launches of about 4.5 us (142.5 -> 148.3 solves/s); with the
-// 128^3 level too, the tiles' redundant halo work (an 8^3 tile loads 16^3
-// cells) outweighs the launches saved there (141.3 solves/s), and the finest
-// levels stream through the march kernels near the bandwidth bound.
+// grid that is the 64^3 and 32^3 levels: 10.0 + 7.5 us and 6.8 + 6.2 us per
+// level against seven launches of about 4.5 us (142.5 -> 149.0 solves/s);
+// with the 128^3 level too, the tiles' redundant halo work (an 8^3 tile loads
+// 16^3 cells) outweighs the launches saved there (143.5 solves/s), and the
+// finest levels stream through the march kernels near the bandwidth bound.
 // IBSCHUR_MG_TILE_CELLS in the environment at sim_create overrides it
 // (0: no tile levels).
 constexpr long long MG_TILE_CELLS_DEFAULT = 64LL * 64 * 64;
