@@ -128,6 +128,7 @@ struct sim_s {
   // reductions
   double *PART = nullptr, *RED = nullptr;
   double *COARSEFD = nullptr;  // eigen-decomposition of the coarsest grid (exact coarse solve)
+  int *SUBTAB = nullptr;       // the subcycle's per-thread cell tables (built at sim_create)
   // whole-grid fast-diagonalisation preconditioner: eigenbases (float) and two
   // bfloat16 scratch grids
   bool fastdiag = false;
@@ -434,6 +435,7 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
   double *VPART = cv.arr<double>(9LL * VOL_CHUNKS * MAX_BODIES);
   const int cdims[3] = {dims[dims.size() - 3], dims[dims.size() - 2], dims[dims.size() - 1]};
   double *COARSEFD = cv.arr<double>(coarse_fd_size(cdims));
+  int *SUBTAB = cv.arr<int>(subcycle_table_ints());
   // matrix-core fast diagonalisation: of the whole grid (FASTDIAG
   // preconditioner) or of a coarsest grid too large for the LDS solver
   bool fdg, fdc;
@@ -459,6 +461,7 @@ size_t layout(sim_s *s, const sim_config *c, int64_t kmax, void *base, const std
     s->TCOUNT = TCOUNT; s->TLSTART = TLSTART; s->TLIST = TLIST;
     s->tl_cap = tl_cap; s->NZT = NZT;
     s->COARSEFD = COARSEFD;
+    s->SUBTAB = SUBTAB;
     s->fastdiag = fdg;
     s->coarse_mfma = fdc;
     s->FDQ = FDQ;
@@ -712,7 +715,7 @@ sim_status vcycle(sim_t s, const TV *v, T *z) {
     using TBs = std::remove_const_t<std::remove_pointer_t<decltype(b)>>;
     const Geo &gf = s->lv[nl - 2].g;
     ProbeExt pr(PR_COARSE, st, (double)geo_cells(gf) * (sizeof(TBs) + t));
-    CKH((mg_subcycle<T, TBs>(gf, s->lv[nl - 1].g, b, x, s->COARSEFD, c.mg_pre, c.mg_post, st)));
+    CKH((mg_subcycle<T, TBs>(gf, s->lv[nl - 1].g, b, x, s->COARSEFD, s->SUBTAB, c.mg_pre, c.mg_post, st)));
     return SIM_OK;
   };
   if (sub && lsub == 0) return subcycle(v, z);
@@ -1735,6 +1738,13 @@ sim_status sim_create(const sim_config *cfg, void *d_workspace, size_t bytes, in
     std::vector<double> fd((size_t)coarse_fd_size(cn));
     coarse_fd_build(cn, cbc, gcoarse.h, fd.data());
     if (hipMemcpy(s->COARSEFD, fd.data(), sizeof(double) * fd.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      release_handle(s);
+      return SIM_EDEVICE;
+    }
+    const size_t nl = s->lv.size();
+    if (nl >= 2 && subcycle_fits(s->lv[nl - 2].g, s->lv[nl - 1].g) &&
+        (mg_subcycle_tables(s->lv[nl - 2].g, s->lv[nl - 1].g, s->SUBTAB, s->st) != hipSuccess ||
+         hipStreamSynchronize(s->st) != hipSuccess)) {
       release_handle(s);
       return SIM_EDEVICE;
     }

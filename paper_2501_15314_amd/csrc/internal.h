@@ -134,10 +134,14 @@ int coarse_fd_size(const int n[3]);  // doubles
 // the last two levels (fine grid gf of at most 4096 cells and its coarsest
 // grid gc, solved exactly with fd from coarse_fd_build) in one LDS workgroup:
 // x = the V-cycle of those two levels applied to b, from x = 0
+// (tab: the per-thread tables from mg_subcycle_tables, subcycle_table_ints()
+// ints, built once per grid pair)
 bool subcycle_fits(const Geo &gf, const Geo &gc);
+int subcycle_table_ints();
+hipError_t mg_subcycle_tables(const Geo &gf, const Geo &gc, int *tab, hipStream_t s);
 template <typename T, typename TB>
-hipError_t mg_subcycle(const Geo &gf, const Geo &gc, const TB *b, T *x, const double *fd, int pre, int post,
-                       hipStream_t s);
+hipError_t mg_subcycle(const Geo &gf, const Geo &gc, const TB *b, T *x, const double *fd, const int *tab, int pre,
+                       int post, hipStream_t s);
 // z = L^+ v on a grid by fast diagonalisation (bfloat16 matrix-core
 // transforms); w1, w2: bfloat16 scratch grids; blob: eigenbases packed by
 // fd_blob_pack from coarse_fd_build's output (device copy)

@@ -272,13 +272,14 @@ hipError_t mg_prolong(const Geo &gf, T *xf, const Geo &gc, const T *xc, hipStrea
 // the missing neighbour); a periodic axis wraps.  Origins and halos are even
 // and n is even, so the colour of a cell is the parity of r0 + r1 + r2.
 constexpr int TL_TS = 8;  // tile edge in cells
-constexpr int TL_THREADS = 512;
+constexpr int TL_THREADS = 512;  // at most, per tile workgroup (tile_threads: whole region columns)
 
 struct TileAxes {
   int o[3], n[3], bc[3];
   __device__ __forceinline__ bool inside(int a, int u) const { return (unsigned)u < (unsigned)n[a] || !bc[a]; }
-  // the grid coordinate of u within one period of it, [-n, 2n) (halos of at
-  // most n cells); a coordinate inside a wall box is its own
+  // the grid coordinate of an unwrapped u in [-n, 2n) (a halo is at most n
+  // cells: n is a multiple of 8 on the fine grid and of 4 on the coarse one);
+  // inside a wall box u is its own
   __device__ __forceinline__ int wrap(int a, int u) const {
     return u + (u < 0 ? n[a] : 0) - (u >= n[a] ? n[a] : 0);
   }
@@ -1020,9 +1021,58 @@ __device__ __forceinline__ T sub_nbsum(const T *x, const SubCell &c) {
   return s;
 }
 
+// The subcycle's per-thread tables, built once per grid (k_subcycle_tables)
+// so that a launch reads them instead of forming them: int4 slot s of thread
+// tid at tab[s * COARSE_THREADS + tid]; slots 0-3 the SubCell of cell (cc,
+// u) = (s >> 1, s & 1), slots 4-7 the prolongation of natural-order fine
+// cell e = tid + (s - 4) COARSE_THREADS: the coarse offsets of the parent and
+// of its neighbour on the child's side along each axis, two 16-bit offsets
+// per word (axis 0 in x, 1 in y, 2 in z; w = 1 for a cell of the grid).
+constexpr int SUB_TAB_SLOTS = 8;
+int subcycle_table_ints() { return 4 * SUB_TAB_SLOTS * COARSE_THREADS; }
+__device__ __forceinline__ int4 sub_prolong_entry(const LvlDim &f, const LvlDim &c, int bc0, int bc1, int bc2, int e) {
+  int4 r = make_int4(0, 0, 0, 0);
+  if (e >= f.n0 * f.n1 * f.n2) return r;
+  int i, j, k;
+  lds_decode(f, e, i, j, k);
+  const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
+  const int I1 = coarse_partner(I0, i & 1, c.n0, bc0);
+  const int J1 = coarse_partner(J0, j & 1, c.n1, bc1);
+  const int K1 = coarse_partner(K0, k & 1, c.n2, bc2);
+  const int s0 = c.n1 * c.n2, s1 = c.n2;
+  r.x = (I0 * s0) | ((I1 * s0) << 16);
+  r.y = (J0 * s1) | ((J1 * s1) << 16);
+  r.z = K0 | (K1 << 16);
+  r.w = 1;
+  return r;
+}
+__device__ __forceinline__ LvlDim sub_dims(const Geo &g, int off) {
+  LvlDim d;
+  d.n0 = g.n0; d.n1 = g.n1; d.n2 = g.n2; d.off = off;
+  d.pow2 = !(g.n0 & (g.n0 - 1)) && !(g.n1 & (g.n1 - 1)) && !(g.n2 & (g.n2 - 1));
+  d.l1 = 31 - __clz(g.n1);
+  d.l2 = 31 - __clz(g.n2);
+  return d;
+}
+__global__ void __launch_bounds__(COARSE_THREADS) k_subcycle_tables(Geo gf, Geo gc, int4 *tab) {
+  const int tid = threadIdx.x, nf = gf.n0 * gf.n1 * gf.n2;
+  const LvlDim f = sub_dims(gf, 0), c = sub_dims(gc, nf);
+#pragma unroll
+  for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+    for (int u = 0; u < SUB_SLOTS; ++u) {
+      const SubCell sc = sub_cell(f, gf.bc0, gf.bc1, gf.bc2, cc, tid + u * COARSE_THREADS);
+      tab[(cc * SUB_SLOTS + u) * COARSE_THREADS + tid] = make_int4(sc.meta, (int)sc.nb[0], (int)sc.nb[1], (int)sc.nb[2]);
+    }
+#pragma unroll
+  for (int r = 0; r < SUB_FINE / COARSE_THREADS; ++r)
+    tab[(2 * SUB_SLOTS + r) * COARSE_THREADS + tid] =
+        sub_prolong_entry(f, c, gf.bc0, gf.bc1, gf.bc2, tid + r * COARSE_THREADS);
+}
+
 template <typename T, typename TB>
 __global__ void __launch_bounds__(COARSE_THREADS) k_subcycle(Geo gf, Geo gc, const TB *bin, T *xout,
-                                                             const double *fd, int pre, int post) {
+                                                             const double *fd, const int4 *tab, int pre, int post) {
   __shared__ T sx[SUB_FINE + SUB_COARSE + 1];
   __shared__ T sb[SUB_FINE + SUB_COARSE];
   __shared__ T rf[SUB_FINE];  // fine residuals for the restriction
@@ -1031,16 +1081,29 @@ __global__ void __launch_bounds__(COARSE_THREADS) k_subcycle(Geo gf, Geo gc, con
   __shared__ T lam[3][FD_MAXN];
   const int tid = threadIdx.x;
   const int nf = gf.n0 * gf.n1 * gf.n2, nc = gc.n0 * gc.n1 * gc.n2;
-  auto dimsof = [](const Geo &g, int off) {
-    LvlDim d;
-    d.n0 = g.n0; d.n1 = g.n1; d.n2 = g.n2; d.off = off;
-    d.pow2 = !(g.n0 & (g.n0 - 1)) && !(g.n1 & (g.n1 - 1)) && !(g.n2 & (g.n2 - 1));
-    d.l1 = 31 - __clz(g.n1);
-    d.l2 = 31 - __clz(g.n2);
-    return d;
-  };
-  const LvlDim f = dimsof(gf, 0), c = dimsof(gc, nf);
-  const int bc0 = gf.bc0, bc1 = gf.bc1, bc2 = gf.bc2;
+  const LvlDim c = sub_dims(gc, nf);
+  // the right-hand side of the thread's cells and its tables, every load
+  // issued before any is used; slot (cc, u) is the colour-cc cell with
+  // split-layout index cc half + tid + u COARSE_THREADS, so the right-hand
+  // side is read and the result written with coalesced accesses and no
+  // index arithmetic
+  TB bl[2][SUB_SLOTS];
+  SubCell cell[2][SUB_SLOTS];
+  int4 pe[SUB_FINE / COARSE_THREADS];
+#pragma unroll
+  for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+    for (int u = 0; u < SUB_SLOTS; ++u) {
+      const long long ec = tid + u * COARSE_THREADS;
+      bl[cc][u] = ec < gf.half ? bin[(long long)cc * gf.half + ec] : TB(0);
+      const int4 t = tab[(cc * SUB_SLOTS + u) * COARSE_THREADS + tid];
+      cell[cc][u].meta = t.x;
+      cell[cc][u].nb[0] = (unsigned)t.y;
+      cell[cc][u].nb[1] = (unsigned)t.z;
+      cell[cc][u].nb[2] = (unsigned)t.w;
+    }
+#pragma unroll
+  for (int r = 0; r < SUB_FINE / COARSE_THREADS; ++r) pe[r] = tab[(2 * SUB_SLOTS + r) * COARSE_THREADS + tid];
   {
     const int n[3] = {gc.n0, gc.n1, gc.n2};
     const double *p = fd;
@@ -1054,21 +1117,15 @@ __global__ void __launch_bounds__(COARSE_THREADS) k_subcycle(Geo gf, Geo gc, con
     }
   }
   if (tid == 0) sx[SUB_ZERO] = T(0);
-  // the cell tables; slot (cc, u) is the colour-cc cell with split-layout
-  // index cc half + tid + u COARSE_THREADS, so the right-hand side is read
-  // and the result written with coalesced accesses and no index arithmetic
-  SubCell cell[2][SUB_SLOTS];
 #pragma unroll
   for (int cc = 0; cc < 2; ++cc)
 #pragma unroll
-    for (int u = 0; u < SUB_SLOTS; ++u) {
-      cell[cc][u] = sub_cell(f, bc0, bc1, bc2, cc, tid + u * COARSE_THREADS);
+    for (int u = 0; u < SUB_SLOTS; ++u)
       if (cell[cc][u].meta >= 0) {
         const int q = cell[cc][u].meta & 0xffff;
-        sb[q] = (T)bin[(long long)cc * gf.half + tid + u * COARSE_THREADS];
+        sb[q] = (T)bl[cc][u];
         sx[q] = T(0);
       }
-    }
   __syncthreads();
   const T h2 = (T)(gf.h * gf.h), ih2 = T(1) / h2;
   // one half sweep over colour cc (the same operations as lds_smooth)
@@ -1146,16 +1203,16 @@ __global__ void __launch_bounds__(COARSE_THREADS) k_subcycle(Geo gf, Geo gc, con
   pass(fb, fa, 0, false);
   pass(fa, fb, 1, false);
   pass(fb, sx + nf, 2, false);  // the coarse solution, after the fine cells
-  // trilinear prolongation of the coarse solution onto every fine cell
-  for (int e = tid; e < nf; e += COARSE_THREADS) {
-    int i, j, k;
-    lds_decode(f, e, i, j, k);
-    const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
-    const int I1 = coarse_partner(I0, i & 1, c.n0, bc0);
-    const int J1 = coarse_partner(J0, j & 1, c.n1, bc1);
-    const int K1 = coarse_partner(K0, k & 1, c.n2, bc2);
+  // trilinear prolongation of the coarse solution onto every fine cell (the
+  // coarse offsets of each cell's parents from the tables)
+#pragma unroll
+  for (int r = 0; r < SUB_FINE / COARSE_THREADS; ++r) {
+    const int e = tid + r * COARSE_THREADS;
+    if (!pe[r].w) continue;
+    const int I0 = pe[r].x & 0xffff, I1 = pe[r].x >> 16, J0 = pe[r].y & 0xffff, J1 = pe[r].y >> 16;
+    const int K0 = pe[r].z & 0xffff, K1 = pe[r].z >> 16;
     const T *xc = sx + nf;
-    auto X = [&](int a, int b, int cc) { return xc[(a * c.n1 + b) * c.n2 + cc]; };
+    auto X = [&](int a, int b, int cc) { return xc[a + b + cc]; };
     const T v0 = (T)0.75 * X(I0, J0, K0) + (T)0.25 * X(I1, J0, K0);
     const T v1 = (T)0.75 * X(I0, J1, K0) + (T)0.25 * X(I1, J1, K0);
     const T v2 = (T)0.75 * X(I0, J0, K1) + (T)0.25 * X(I1, J0, K1);
@@ -1186,13 +1243,18 @@ bool subcycle_fits(const Geo &gf, const Geo &gc) {
 }
 
 template <typename T, typename TB>
-hipError_t mg_subcycle(const Geo &gf, const Geo &gc, const TB *b, T *x, const double *fd, int pre, int post,
-                       hipStream_t s) {
-  if (!subcycle_fits(gf, gc)) return hipErrorInvalidValue;
+hipError_t mg_subcycle(const Geo &gf, const Geo &gc, const TB *b, T *x, const double *fd, const int *tab, int pre,
+                       int post, hipStream_t s) {
+  if (!subcycle_fits(gf, gc) || !tab) return hipErrorInvalidValue;
   hipEvent_t e0, e1;
   probe_ext_take(&e0, &e1);
-  hipExtLaunchKernelGGL((k_subcycle<T, TB>), dim3(1), dim3(COARSE_THREADS), 0, s, e0, e1, 0, gf, gc, b, x, fd, pre,
-                        post);
+  hipExtLaunchKernelGGL((k_subcycle<T, TB>), dim3(1), dim3(COARSE_THREADS), 0, s, e0, e1, 0, gf, gc, b, x, fd,
+                        (const int4 *)tab, pre, post);
+  return hipGetLastError();
+}
+hipError_t mg_subcycle_tables(const Geo &gf, const Geo &gc, int *tab, hipStream_t s) {
+  if (!subcycle_fits(gf, gc) || !tab) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_subcycle_tables, dim3(1), dim3(COARSE_THREADS), 0, s, gf, gc, (int4 *)tab);
   return hipGetLastError();
 }
 
@@ -1254,8 +1316,8 @@ void coarse_fd_build(const int n[3], const int bc[3], double h, double *out) {
                                          hipStream_t);                                                 \
   template hipError_t mg_coarse<T, TB>(const Geo &, const TB *, T *, int, int, hipStream_t);                   \
   template hipError_t mg_coarse_fd<T, TB>(const Geo &, const TB *, T *, const double *, hipStream_t);   \
-  template hipError_t mg_subcycle<T, TB>(const Geo &, const Geo &, const TB *, T *, const double *, int, int, \
-                                         hipStream_t);  \
+  template hipError_t mg_subcycle<T, TB>(const Geo &, const Geo &, const TB *, T *, const double *, const int *, \
+                                         int, int, hipStream_t);                                               \
   template hipError_t mg_tile_down<T, TB>(const Geo &, T *, const TB *, const Geo &, T *, int, hipStream_t);   \
   template hipError_t mg_tile_up<T, TB>(const Geo &, const T *, T *, const TB *, const Geo &, const T *, int, \
                                         hipStream_t);
