@@ -161,7 +161,7 @@ def test_full_chunks_give_the_same_operators(case, prec):
 
 @pytest.mark.parametrize("prec", [wl.PREC_FP64, wl.PREC_FP32MG])
 @pytest.mark.parametrize("case", ["c1_periodic", "walls", "mixed", "freeslip", "walls64", "periodic64_v22",
-                                  "freeslip64_v11"])
+                                  "freeslip64_v11", "thin64x64x16"])
 def test_tile_levels_give_the_same_bits(case, prec):
     """Tile levels (a level's pre-smoothing, residual and restriction in one
     launch, its prolongation and post-smoothing in another, each 8^3 tile
@@ -169,8 +169,11 @@ def test_tile_levels_give_the_same_bits(case, prec):
     kernels in the same order: the V-cycle and a whole Schur solve agree to
     the last bit with the tile levels switched off.  The 64^3 cases tile two
     levels (64^3 and 32^3 above the 16^3 + 8^3 subcycle); V(2,2) and V(1,1)
-    take the other halo widths."""
+    take the other halo widths.  The thin 64 x 64 x 16 box tiles two levels
+    whose coarse grids are 4 cells deep along the periodic axis, so a tile's
+    coarse block wraps across most of that axis."""
     cases = dict(_cases())
+    cases["thin64x64x16"] = thin_workload
     cases["walls64"] = lambda: walls_workload(64, 260)
     cases["periodic64_v22"] = lambda: wl.make_c1(n=64, n_points=300)
     cases["freeslip64_v11"] = lambda: freeslip_workload(64, 260)
@@ -202,6 +205,23 @@ def test_tile_levels_give_the_same_bits(case, prec):
     assert n0 == 0 and n1 > 0
     assert np.array_equal(z0, z1)
     assert it0 == it1 and np.array_equal(p0, p1) and np.array_equal(f0, f1)
+
+
+def thin_workload(seed=15):
+    """A 64 x 64 x 16 box of cells of width 1/64, no-slip along x and y,
+    periodic along z, one sphere."""
+    rng = np.random.default_rng(seed)
+    n = (64, 64, 16)
+    h = 1.0 / 64
+    radius = 0.07
+    K = 200
+    cfg = wl.Config(n=n, length=tuple(x * h for x in n), bc=(wl.BC_NOSLIP, wl.BC_NOSLIP, wl.BC_PERIODIC),
+                    nu=0.02, dt=0.005, delta=wl.DELTA_PESKIN4,
+                    lump_c=wl.lump_constant(wl.DELTA_PESKIN4, h, K, radius), krylov_rtol=1e-12)
+    c = np.array([0.5, 0.45, 0.125]) + rng.uniform(-0.01, 0.01, 3)
+    bodies = [wl.Body(center=c, vel=rng.normal(0, 0.1, 3), omega=np.zeros(3), radius=radius, n_points=K)]
+    return wl.Workload("thin_64x64x16", cfg, bodies, wl.fibonacci_offsets(K, radius), np.zeros((3,) + n),
+                       steps=1, seed=seed)
 
 
 def test_vcycle_contracts(setup):
